@@ -1,0 +1,162 @@
+"""Time propagation (oracle): adaptive Lanczos exponential and Magnus-2 step.
+
+* Sec. 2.6, eq. (AdaptiveKrylov): exp(-i tau Hbar) psi ~ ||psi|| Q_k exp(-i tau T_k) e_1,
+  with Q_k the Lanczos vectors of Hbar started from psi and T_k tridiagonal.
+  Full reorthogonalisation: two classical Gram-Schmidt passes against all
+  previous Lanczos vectors.  exp(-i tau T_k) e_1 by eigendecomposition of T_k.
+* eq. (AdaptiveKrylovErr): the error estimate of the k-dimensional
+  approximation is |tau| beta_k ||psi|| |[exp(-i tau T_k)]_{k,1}|, where beta_k is
+  the next off-diagonal entry (the factor |tau| converts the Lanczos data of Hbar
+  into those of -i tau Hbar).  The iteration stops at the first k whose estimate
+  is at most tol ||psi||, or at an invariant subspace (beta_k <= 1e-14 ||T_k||).
+* Sec. 2.5, eq. (ApproxMagnus): psi(t+dt) = exp(-i dt Hbar[rho(t+dt/2)]) psi(t),
+  with the midpoint Hamiltonian from a second-order predictor-corrector: a
+  predictor step with Hbar[rho(t), t], rho_mid = (rho(t) + rho_pred)/2, field at
+  t + dt/2, one corrector step.
+* delta kick: psi <- exp(i kappa Zbar_d) psi with the Loewdin position operator.
+"""
+from __future__ import annotations
+
+import math
+from typing import Optional, Sequence
+
+import numpy as np
+import scipy.linalg as sla
+
+
+class NoConvergence(RuntimeError):
+    pass
+
+
+def tridiag_exp_e1(alpha, beta, tau):
+    """u = exp(-i tau T) e_1 for the symmetric tridiagonal T(alpha, beta)."""
+    alpha = np.asarray(alpha, dtype=np.float64)
+    if len(alpha) == 1:
+        return np.array([np.exp(-1j * tau * alpha[0])])
+    lam, V = sla.eigh_tridiagonal(alpha, np.asarray(beta, dtype=np.float64))
+    return V @ (np.exp(-1j * tau * lam) * V[0, :])
+
+
+def lanczos_expm_column(Aop, tau, v, tol, kmax, k_force: Optional[int] = None):
+    """One column: returns (exp(-i tau A) v approximation, k, error estimate)."""
+    beta0 = float(np.linalg.norm(v))
+    if beta0 == 0.0:
+        return np.zeros_like(v), 0, 0.0
+    Q = [v / beta0]
+    alpha, beta = [], []
+    for j in range(1, kmax + 1):
+        q = Q[-1]
+        w = Aop(q)
+        a = float(np.real(np.vdot(q, w)))
+        alpha.append(a)
+        w = w - a * q
+        if j > 1:
+            w = w - beta[-1] * Q[-2]
+        Qm = np.stack(Q, axis=1)
+        for _ in range(2):                       # two CGS passes
+            h = Qm.conj().T @ w
+            w = w - Qm @ h
+        b = float(np.linalg.norm(w))
+        u = tridiag_exp_e1(alpha, beta, tau)
+        err = abs(tau) * b * beta0 * abs(u[-1])
+        tnorm = max(abs(alpha[i]) + (beta[i - 1] if i > 0 else 0.0) + (beta[i] if i < len(beta) else 0.0)
+                    for i in range(len(alpha))) + b
+        if k_force is not None:
+            done = j >= k_force
+        else:
+            done = err <= tol * beta0 or b <= 1e-14 * tnorm
+        if done:
+            return beta0 * (Qm @ u), j, err
+        beta.append(b)
+        Q.append(w / b)
+    raise NoConvergence(f"Lanczos did not reach tol {tol} within {kmax} vectors")
+
+
+def lanczos_expm(A, tau, X, tol=1e-10, kmax=64, k_force: Optional[Sequence[int]] = None):
+    """exp(-i tau A) X column by column.  A: matrix (sparse/dense) or callable."""
+    Aop = A if callable(A) else (lambda q: A @ q)
+    X = np.asarray(X, dtype=np.complex128)
+    Y = np.empty_like(X)
+    ks = np.zeros(X.shape[1], dtype=np.int32)
+    errs = np.zeros(X.shape[1])
+    for a in range(X.shape[1]):
+        kf = None if k_force is None else int(k_force[a])
+        Y[:, a], ks[a], errs[a] = lanczos_expm_column(Aop, tau, X[:, a], tol, kmax, kf)
+    return Y, ks, errs
+
+
+class Propagator:
+    """Magnus-2 predictor-corrector propagation of the orbital block (eq. ApproxMagnus)."""
+
+    def __init__(self, model, X, t=0.0, field=None, tol=None, kmax=None):
+        self.model = model
+        self.X = np.asarray(X, dtype=np.complex128).copy()
+        self.t = float(t)
+        self.field = field
+        self.tol = model.spec.krylov_tol if tol is None else tol
+        self.kmax = model.spec.kmax if kmax is None else kmax
+        self.refresh()
+
+    def refresh(self):
+        """(Re)build rho and Hbar for the current orbitals and time."""
+        self.rho = self.model.density(self.X)
+        self.H = self.model.hamiltonian_from_density(self.rho, self.t, self.field)
+
+    def kick(self, kappa, direction=2):
+        """psi <- exp(i kappa Zbar_d) psi, then refresh the Hamiltonian."""
+        Z = self.model.position_operator(direction)
+        self.X, k, _ = lanczos_expm(Z, -kappa, self.X, self.tol, self.kmax)
+        self.refresh()
+        return k
+
+    def step(self, dt, k_force=None):
+        """One Magnus-2 step; returns (mu, k_pred, k_corr)."""
+        m = self.model
+        kp_f = None if k_force is None else k_force[0]
+        kc_f = None if k_force is None else k_force[1]
+        Xp, kp, _ = lanczos_expm(self.H, dt, self.X, self.tol, self.kmax, kp_f)
+        rho_mid = 0.5 * (self.rho + m.density(Xp))
+        Hmid = m.hamiltonian_from_density(rho_mid, self.t + 0.5 * dt, self.field)
+        self.X, kc, _ = lanczos_expm(Hmid, dt, self.X, self.tol, self.kmax, kc_f)
+        self.t += dt
+        self.refresh()
+        return m.dipole(self.rho), kp, kc
+
+    def run(self, dt, nsteps, k_force=None):
+        mus, ks = [], []
+        for n in range(nsteps):
+            mu, kp, kc = self.step(dt, None if k_force is None else k_force[n])
+            mus.append(mu)
+            ks.append((kp, kc))
+        return np.array(mus), np.array(ks)
+
+
+def scf_ground_state(model, tol=1e-11, mix=0.5, maxit=200, verbose=False):
+    """Self-consistent ground state by dense diagonalisation of Hbar.
+
+    Start from the Hamiltonian without Hartree and xc terms, take the lowest
+    norb eigenvectors, mix densities linearly, stop when max |rho_out - rho_in| < tol.
+    Returns (X, eigenvalues, iterations).
+    """
+    norb = model.spec.norb
+    active = np.concatenate([model.interior, model.mesh.n_nodes + np.arange(model.nk)])
+    v0 = model.v_nuc + model.v_trap
+    H = model.hamiltonian(v0)
+    rho_in = None
+    for it in range(1, maxit + 1):
+        Ha = H[active][:, active].toarray()
+        lam, V = sla.eigh(Ha, subset_by_index=[0, norb - 1])
+        X = np.zeros((model.n_rows, norb), dtype=np.complex128)
+        X[active] = V
+        rho_out = model.density(X)
+        if rho_in is not None:
+            dmax = float(np.max(np.abs(rho_out - rho_in)))
+            if verbose:
+                print(f"scf {it}: max|drho| = {dmax:.3e}  eps = {lam}")
+            if dmax < tol:
+                return X, lam, it
+            rho_in = (1.0 - mix) * rho_in + mix * rho_out
+        else:
+            rho_in = rho_out
+        H = model.hamiltonian_from_density(rho_in)
+    raise NoConvergence("SCF did not converge")

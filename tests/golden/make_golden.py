@@ -1,0 +1,65 @@
+"""Write the stored expected values under tests/golden/ (calls only the oracle).
+
+Usage: python tests/golden/make_golden.py [tiny_gs] [trap_gs] [tiny_traj] [na8]
+
+Every file written here is produced by the FP64 oracle from the seeded inputs of
+``workloads``; nothing comes from the GPU library.
+"""
+from __future__ import annotations
+
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from workloads import tiny, trap  # noqa: E402
+from oracle.model import EFEModel  # noqa: E402
+from oracle.propagate import scf_ground_state, Propagator  # noqa: E402
+
+TRAP_ARGS = dict(omega=1.0, ncell=4, half=6.0, degree=4)
+
+
+def tiny_gs():
+    m = EFEModel(tiny())
+    X, eps, it = scf_ground_state(m, tol=1e-11, mix=0.5)
+    np.savez_compressed(os.path.join(HERE, "tiny_ground_state.npz"), X=X, eps=eps, iterations=it)
+    print("tiny ground state:", eps, it)
+
+
+def trap_gs():
+    m = EFEModel(trap(**TRAP_ARGS))
+    X, eps, it = scf_ground_state(m, tol=1e-11, mix=0.5)
+    np.savez_compressed(os.path.join(HERE, "trap_ground_state.npz"), X=X, eps=eps, iterations=it)
+    print("trap ground state:", eps, it)
+
+
+def tiny_traj():
+    """Kick 1e-3 along z, then 200 Magnus-2 steps of 0.05 au at tol 1e-10."""
+    spec = tiny()
+    m = EFEModel(spec)
+    X0 = np.load(os.path.join(HERE, "tiny_ground_state.npz"))["X"]
+    P = Propagator(m, X0, tol=spec.krylov_tol, kmax=spec.kmax)
+    mu0 = m.dipole(P.rho)
+    k_kick = P.kick(spec.kick, spec.kick_dir)
+    mus = [m.dipole(P.rho)]
+    ks = []
+    t0 = time.time()
+    for n in range(spec.nsteps):
+        mu, kp, kc = P.step(spec.dt)
+        mus.append(mu)
+        ks.append(np.stack([kp, kc]))
+        if n % 20 == 0:
+            print(f"step {n} mu_z={mu[2]:.6e} k={kp},{kc} ({time.time() - t0:.0f}s)", flush=True)
+    np.savez_compressed(os.path.join(HERE, "tiny_traj.npz"), mu_ground=mu0, mu=np.array(mus),
+                        k=np.array(ks, dtype=np.int32), k_kick=k_kick, X_final=P.X,
+                        rho_final=P.rho, dt=spec.dt, kick=spec.kick)
+
+
+if __name__ == "__main__":
+    jobs = sys.argv[1:] or ["tiny_gs", "trap_gs", "tiny_traj"]
+    for j in jobs:
+        globals()[j]()

@@ -1,0 +1,11 @@
+"""Seeded synthetic inputs shared by the CPU oracle and the GPU path.
+
+This package holds no arithmetic of the method: only atom positions, enrichment
+lists, occupations, propagation parameters and the random numbers that the
+initial-state recipe draws.  Both sides build everything else themselves.
+"""
+from .systems import (SystemSpec, tiny, na_cluster, na8, trap, gaussian_box,
+                      cluster_positions, noise_coefficients, NOISE_MODES)
+
+__all__ = ["SystemSpec", "tiny", "na_cluster", "na8", "trap", "gaussian_box",
+           "cluster_positions", "noise_coefficients", "NOISE_MODES"]
