@@ -1,0 +1,215 @@
+/*
+ * efe.h -- C ABI of the MI355X (gfx950) library for one second-order Magnus
+ * step of all-electron real-time TDDFT in an enriched finite-element basis
+ * (Kanungo, Rufus, Gavini, arXiv:2210.14421).
+ *
+ * Problem statement followed by the calls:
+ *   TDKS equations and density ........... Sec. 2.1, eq. (TDKS)
+ *   EFE basis, H and M, Loewdin form ..... Sec. 2.2, eqs. (PsiEFE)-(TDKSDiscrete2)
+ *   spectral FE / GLL, (M^ee)^-1/2 ........ Sec. 2.3, eq. (MSquareRoot)
+ *   Hartree potential by FE Poisson ...... Sec. 2.1 eq. (Hartree_possion), Sec. 2.2 eq. (DiscretePoisson)
+ *   Magnus-2 midpoint step ............... Sec. 2.5, eq. (ApproxMagnus)
+ *   adaptive Lanczos exponential ......... Sec. 2.6, eqs. (AdaptiveKrylov), (AdaptiveKrylovErr)
+ *   dipole moment ........................ Sec. 3.1
+ *
+ * Conventions (all calls)
+ *   - Orbital blocks (Psi, X, Y) are caller-owned DEVICE pointers to complex128
+ *     values, row-major ("node-major"): row r holds the ncol orbitals of basis
+ *     function r as interleaved (re, im) doubles, rows r and r+1 are ld complex
+ *     values apart (ld >= ncol).  Rows 0 .. n_nodes-1 are the classical FE nodes
+ *     in the order gx + Nx (gy + Ny gz); the rows of boundary nodes must hold
+ *     zeros (homogeneous Dirichlet condition) and are returned as zeros.  Rows
+ *     n_nodes .. n_nodes+n_enr-1 are the Loewdin-orthonormalised enrichment
+ *     directions.  The coefficients are those of the Loewdin form
+ *     psibar = M^1/2 psi of eq. (TDKSDiscrete2).
+ *   - Quadrature arrays (rho_q) are DEVICE arrays of doubles, one per
+ *     quadrature point, cell-major (cell ex + nx (ey + ny ez)), then point
+ *     i + n (j + n k) of the cell's Gauss rule.
+ *   - Calls are ordered on the HIP stream given in efe_options.hip_stream (0 =
+ *     the null stream) and return after the stream has drained, except where
+ *     noted.  A context is not thread-safe; separate contexts are independent.
+ *   - Nothing aborts or throws across the ABI.  Every call returns an
+ *     efe_status; on error the caller's output arrays are left unchanged and
+ *     efe_last_error() describes the failure.
+ */
+#ifndef EFE_H
+#define EFE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct efe_ctx efe_ctx;
+typedef struct efe_plan efe_plan;
+typedef int32_t efe_status;
+
+enum {
+  EFE_OK = 0,
+  EFE_ERR_ARG = -1,        /* invalid argument or inconsistent sizes            */
+  EFE_ERR_ALLOC = -2,      /* device or host allocation failed                  */
+  EFE_ERR_HIP = -3,        /* a HIP runtime call failed                         */
+  EFE_ERR_NOCONV = -4,     /* Lanczos reached kmax / Poisson CG reached maxit   */
+  EFE_ERR_SINGULAR = -5,   /* enrichment overlap has no direction above the drop threshold */
+  EFE_ERR_NONFINITE = -6,  /* NaN or Inf met in an input or a result           */
+  EFE_ERR_STATE = -7       /* call out of order (e.g. magnus_step before any Hamiltonian) */
+};
+
+/* product dtype of the cell-block and enrichment-coupling products */
+enum { EFE_F64 = 0, EFE_F32 = 1, EFE_BF16 = 2 };
+/* adiabatic LDA (Sec. 2.1): none, Slater exchange, Slater + PW92 correlation */
+enum { EFE_XC_NONE = 0, EFE_XC_SLATER = 1, EFE_XC_SLATER_PW92 = 2 };
+/* operator exponentiated by lanczos_expm: Hbar, or the Loewdin position operator */
+enum { EFE_OP_H = 0, EFE_OP_X = 1, EFE_OP_Y = 2, EFE_OP_Z = 3 };
+
+/* Physical system and discretisation.  Host memory, read during the call only. */
+typedef struct {
+  int32_t ncell[3];        /* uniform hex cells per axis                          */
+  double lo[3], hi[3];     /* box [lo, hi] in bohr                                */
+  int32_t degree;          /* FE degree p (2..6): (p+1)^3 GLL nodes per cell      */
+  int32_t natom;
+  const double *R;         /* natom x 3 positions (bohr)                          */
+  const double *Z;         /* natom charges                                       */
+  double nuc_sigma;        /* nuclear charge Z (pi s^2)^-3/2 exp(-r^2/s^2), s = nuc_sigma */
+  int32_t nenr;            /* enrichment functions (Sec. 2.2, eq. (EFEAtomic))    */
+  const int32_t *enr_atom; /* owning atom                                         */
+  const int32_t *enr_l;    /* 0 or 1                                              */
+  const int32_t *enr_m;    /* l = 1: -1 -> y, 0 -> z, +1 -> x                     */
+  const double *enr_zeta;  /* r^l exp(-zeta r) Y_lm (1-(r/r_cut)^2)^3, unit norm   */
+  double r_cut;
+  int32_t norb;            /* occupied orbitals                                   */
+  const double *occ;       /* occupations f_a (density = sum f_a |psi_a|^2)       */
+  int32_t xc;              /* EFE_XC_*                                            */
+  double trap_omega;       /* > 0 adds 1/2 w^2 |x|^2 (test systems)               */
+  int32_t quad_cell;       /* Gauss points per axis on ordinary cells; 0 -> p+1   */
+  int32_t quad_enr;        /* ... on cells within r_cut of an atom; 0 -> 2p+2     */
+  double enr_drop_tol;     /* drop M^ee eigenvalues below tol * max (canonical orthogonalisation) */
+} efe_system;
+
+typedef struct {
+  int32_t prod_dtype;      /* EFE_F64 / EFE_F32 / EFE_BF16                        */
+  int32_t kmax;            /* maximum Krylov dimension (1..128)                   */
+  double krylov_tol;       /* stop when the estimate of eq. (AdaptiveKrylovErr) <= tol * ||psi|| */
+  double cg_tol;           /* Poisson: relative residual                          */
+  int32_t cg_maxit;
+  void *hip_stream;        /* hipStream_t, or 0                                   */
+} efe_options;
+
+/* External field E(t) = dir * sum_k A_k sin(w_k t + phi_k) exp(-(t-t0)^2/s^2),
+ * potential -E(t) . x (eq. (VField)).  kind 0: no field. */
+typedef struct {
+  int32_t kind;
+  int32_t direction;       /* 0 x, 1 y, 2 z                                       */
+  int32_t ncomp;
+  const double *A, *w, *phi;  /* host arrays of ncomp                             */
+  double t0, s;
+} efe_field;
+
+/* Per-call statistics (host memory, may be NULL). */
+typedef struct {
+  int32_t k_pred[128];     /* Krylov dimension per orbital, predictor            */
+  int32_t k_corr[128];     /* ... corrector                                      */
+  double err_pred_max, err_corr_max;   /* largest a-posteriori estimates         */
+  int32_t cg_iters[2];     /* Poisson PCG iterations (midpoint, end of step)      */
+  double mu[3];            /* dipole at the end of the step                       */
+} efe_step_stats;
+
+/* ---- host-only planning (no GPU needed) --------------------------------- */
+
+/* Builds every static quantity of the discretisation on the host: tables,
+ * mesh classes, enrichment normalisation, orthogonalising coefficients
+ * c = D^-1 b (Sec. 2.2, eq. (EFEOrtho) with the GLL-lumped classical mass),
+ * M^ee and S = (M^ee)^-1/2 (Sec. 2.3, eq. (MSquareRoot); canonical when a
+ * direction is dropped), enrichment values at quadrature points, static kinetic
+ * couplings, and the fast-diagonalisation data of the Poisson operator.
+ * Errors: EFE_ERR_ARG, EFE_ERR_SINGULAR, EFE_ERR_ALLOC. */
+efe_status efe_plan_create(const efe_system *sys, efe_plan **out);
+efe_status efe_plan_free(efe_plan *plan);
+/* Sizes: n_nodes, n_cells, n_quad, n_enr_kept, n_union_rows, n_tcells. */
+efe_status efe_plan_sizes(const efe_plan *plan, int64_t sizes[6]);
+/* Copies a named static array into host memory `out` of `count` doubles
+ * (EFE_ERR_ARG if the name is unknown or count differs).  Names: "D" (n_nodes
+ * lumped mass), "S" (n_enr x n_kept), "Mee" (n_enr^2), "c" (n_nodes x n_enr,
+ * zero outside the support), "enr_scale" (n_enr), "Kce" (n_nodes x n_enr static
+ * kinetic part of H^ce, unscaled), "Kee" (n_enr^2), "vstatic" (n_quad),
+ * "lift" (n_nodes: K_IB g), "is_enr" (n_cells as doubles). */
+efe_status efe_plan_get(const efe_plan *plan, const char *name, double *out, int64_t count);
+const char *efe_plan_error(const efe_plan *plan);
+
+/* ---- GPU context ----------------------------------------------------------- */
+
+/* Plans the system on the host, uploads the static data, and allocates the
+ * Krylov workspace (kmax+1 orbital blocks), the cell blocks of Hbar in the
+ * product dtype, the enrichment coupling and the quadrature arrays.
+ * Errors: EFE_ERR_ARG, EFE_ERR_SINGULAR, EFE_ERR_ALLOC, EFE_ERR_HIP. */
+efe_status efe_setup(const efe_system *sys, const efe_options *opt, efe_ctx **out);
+efe_status efe_free(efe_ctx *ctx);
+/* n_rows (= n_nodes + n_enr_kept), n_nodes, n_enr_kept, n_quad. */
+efe_status efe_dims(const efe_ctx *ctx, int64_t dims[4]);
+/* Changes stream / Krylov settings of a live context (kmax only downwards). */
+efe_status efe_set_options(efe_ctx *ctx, const efe_options *opt);
+
+/* Initial orbitals for cluster workloads: orbital a = the enrichment direction
+ * enr_index[a] (its Loewdin coordinates S^+ e_nu) plus classical-block noise
+ * D^1/2 * amp * n/||n||_M with n = sum_m g[a][m] prod_d sin(m_d pi (x_d-lo_d)/(hi_d-lo_d)),
+ * m over {1,2,3}^3 (m_x slowest), then X <- X (X^T X)^-1/2.  Psi: device,
+ * n_rows x norb, ld = norb.  Host inputs: enr_index[norb], g[norb*27]. */
+efe_status efe_initial_state(efe_ctx *ctx, const int32_t *enr_index, const double *g,
+                             double amp, void *Psi);
+
+/* Rebuilds Hbar[rho(Psi), t] (Sec. 2.2 eq. (Hmn) with v_KS of Sec. 2.1) and
+ * keeps rho(Psi) as the density of the current time level; required before
+ * the first magnus_step and after any change of Psi outside magnus_step. */
+efe_status efe_set_hamiltonian(efe_ctx *ctx, const void *Psi, double t, const efe_field *field);
+
+/* Y = Hbar X for the Hamiltonian last built (ncol <= norb columns). */
+efe_status efe_apply_H(efe_ctx *ctx, const void *X, void *Y, int32_t ncol, int64_t ld);
+
+/* X <- exp(-i tau A) X, A = Hbar (op EFE_OP_H, Hamiltonian last built) or the
+ * Loewdin position operator along x/y/z (no kinetic term, v = x_d), by the
+ * adaptive Lanczos method of Sec. 2.6 with full reorthogonalisation, one Krylov
+ * space per orbital.  k_force (host, ncol, may be NULL) fixes the Krylov
+ * dimension of each column; otherwise each column stops at the first k whose
+ * estimate |tau| beta_k ||x|| |[exp(-i tau T_k)]_{k,1}| <= tol ||x||, or at an
+ * invariant subspace.  k_used, err_est: host outputs (ncol, may be NULL).
+ * A position operator replaces the stored Hamiltonian: call
+ * efe_set_hamiltonian before the next magnus_step.  EFE_ERR_NOCONV if a column
+ * needs more than kmax vectors (X unchanged). */
+efe_status lanczos_expm(efe_ctx *ctx, int32_t op, double tau, void *X, int32_t ncol, int64_t ld,
+                        const int32_t *k_force, int32_t *k_used, double *err_est);
+
+/* One Magnus-2 step, eq. (ApproxMagnus), with the predictor-corrector midpoint
+ * Hamiltonian: Psi_p = exp(-i dt Hbar[rho_n, t]) Psi;
+ * rho_mid = (rho_n + rho(Psi_p))/2; Psi <- exp(-i dt Hbar[rho_mid, t+dt/2]) Psi;
+ * then rho_{n+1}, Hbar[rho_{n+1}, t+dt] and the dipole.  Psi: device, n_rows x
+ * norb, ld >= norb.  k_force: host [2][norb] (predictor, corrector) or NULL.
+ * stats: host, may be NULL. */
+efe_status magnus_step(efe_ctx *ctx, void *Psi, int64_t ld, double t, double dt,
+                       const efe_field *field, const int32_t *k_force, efe_step_stats *stats);
+
+/* rho(q) = sum_a f_a |psi_a(q)|^2 at every quadrature point (device output,
+ * n_quad doubles), psi = M^-1/2 Psi evaluated through the EFE basis. */
+efe_status density(efe_ctx *ctx, const void *Psi, int64_t ld, double *rho_q);
+
+/* Nodal Hartree potential (device output, n_nodes) of a quadrature density
+ * (device input): (1/4 pi) K phi = d, phi = g on the boundary, by PCG with a
+ * fast-diagonalisation preconditioner; iters (host, may be NULL). */
+efe_status efe_hartree(efe_ctx *ctx, const double *rho_q, double *phi, int32_t *iters);
+
+/* Electronic dipole mu_d = sum_q W_q x_d(q) rho(q) of Psi (host output mu[3]). */
+efe_status dipole(efe_ctx *ctx, const void *Psi, int64_t ld, double mu[3]);
+
+/* Device time of the last call's stages in ms: [0] Hbar X cell products,
+ * [1] enrichment coupling, [2] Lanczos vector work, [3] tridiagonal
+ * exponentials, [4] density, [5] Poisson, [6] rebuild, [7] total; and the
+ * number of Hbar X products.  Filled only when timing is enabled. */
+efe_status efe_enable_timing(efe_ctx *ctx, int32_t on);
+efe_status efe_get_timing(const efe_ctx *ctx, double ms[8], int64_t *n_hx);
+
+const char *efe_last_error(const efe_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EFE_H */

@@ -1,0 +1,855 @@
+// C ABI of the library (declared in include/efe.h): context set-up, the
+// Lanczos exponential driver, the Hartree solve, and the Magnus-2 step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "device.h"
+#include "efe.h"
+#include "plan.h"
+
+struct efe_plan {
+  efe::Plan p;
+};
+
+namespace {
+
+constexpr int kStages = 8;   // timing slots, see efe_get_timing
+
+struct Timer {
+  bool on = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> stage;
+  double ms[kStages] = {0};
+  int64_t n_hx = 0;
+};
+
+}  // namespace
+
+struct efe_ctx {
+  efe::Plan plan;
+  efe::DevData d;
+  efe_options opt{};
+  hipStream_t stream = nullptr;
+  std::string err;
+  int dtype = 0;
+  int norb = 0, ncolr = 0;
+  int kmax = 0;
+  int64_t n_rows = 0, blk = 0;     // blk = doubles per orbital block
+  // device buffers
+  std::vector<void *> allocs;
+  void *cells = nullptr;
+  double *Q = nullptr, *W = nullptr, *X0 = nullptr, *X1 = nullptr;
+  double *rho_prev = nullptr, *rho_tmp = nullptr, *vq = nullptr;
+  double *phi = nullptr, *dvec = nullptr, *rhs = nullptr;
+  double *cg[7] = {nullptr};
+  double *part = nullptr, *hee_part = nullptr, *G = nullptr, *Hee_raw = nullptr, *Hbar_ee = nullptr;
+  double *psiE = nullptr, *red = nullptr, *small = nullptr, *couple_scr = nullptr;
+  int64_t red_len = 0;
+  double *alpha = nullptr, *beta = nullptr, *beta0 = nullptr, *errv = nullptr, *ubuf = nullptr;
+  int *active = nullptr, *kused = nullptr, *kforce = nullptr;
+  // state
+  int cells_mode = -1;      // -1 nothing built, 0 Hamiltonian, 1..3 position operator
+  bool ham_valid = false;   // rho_prev and the Hamiltonian belong to the current orbitals
+  Timer timer;
+};
+
+namespace {
+
+using efe::DevData;
+
+const char *hip_err(hipError_t e) { return hipGetErrorString(e); }
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) {                                                                  \
+      ctx->err = std::string(#expr) + ": " + hip_err(e_);                                    \
+      return EFE_ERR_HIP;                                                                    \
+    }                                                                                        \
+  } while (0)
+
+#define EFE_TRY(expr)                 \
+  do {                                \
+    efe_status s_ = (expr);           \
+    if (s_ != EFE_OK) return s_;      \
+  } while (0)
+
+template <typename T>
+efe_status dalloc(efe_ctx *ctx, T **p, int64_t count) {
+  *p = nullptr;
+  if (count <= 0) count = 1;
+  void *q = nullptr;
+  hipError_t e = hipMalloc(&q, (size_t)count * sizeof(T));
+  if (e != hipSuccess) {
+    ctx->err = "hipMalloc of " + std::to_string((size_t)count * sizeof(T)) + " bytes failed: " + hip_err(e);
+    return EFE_ERR_ALLOC;
+  }
+  ctx->allocs.push_back(q);
+  *p = (T *)q;
+  return EFE_OK;
+}
+
+template <typename T>
+efe_status upload(efe_ctx *ctx, T **p, const std::vector<T> &v) {
+  EFE_TRY(dalloc(ctx, p, (int64_t)v.size()));
+  if (!v.empty()) HIP_TRY(hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return EFE_OK;
+}
+
+void tstart(efe_ctx *ctx, int stage) {
+  if (!ctx->timer.on) return;
+  hipEvent_t e;
+  hipEventCreate(&e);
+  hipEventRecord(e, ctx->stream);
+  ctx->timer.ev.push_back(e);
+  ctx->timer.stage.push_back(stage);
+}
+void tstop(efe_ctx *ctx, int stage) { tstart(ctx, -1 - stage); }
+
+void timer_reset(efe_ctx *ctx) {
+  for (auto e : ctx->timer.ev) hipEventDestroy(e);
+  ctx->timer.ev.clear();
+  ctx->timer.stage.clear();
+  for (double &m : ctx->timer.ms) m = 0.0;
+  ctx->timer.n_hx = 0;
+}
+
+void timer_collect(efe_ctx *ctx) {
+  if (!ctx->timer.on) return;
+  hipStreamSynchronize(ctx->stream);
+  std::vector<int> open(kStages, -1);
+  for (size_t i = 0; i < ctx->timer.ev.size(); ++i) {
+    int s = ctx->timer.stage[i];
+    if (s >= 0) {
+      open[s] = (int)i;
+    } else {
+      int st = -1 - s;
+      if (open[st] >= 0) {
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, ctx->timer.ev[open[st]], ctx->timer.ev[i]);
+        ctx->timer.ms[st] += ms;
+        open[st] = -1;
+      }
+    }
+  }
+  for (auto e : ctx->timer.ev) hipEventDestroy(e);
+  ctx->timer.ev.clear();
+  ctx->timer.stage.clear();
+}
+
+efe_status check_launch(efe_ctx *ctx, const char *what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    ctx->err = std::string(what) + ": " + hip_err(e);
+    return EFE_ERR_HIP;
+  }
+  return EFE_OK;
+}
+
+efe_status sync(efe_ctx *ctx, const char *what) {
+  EFE_TRY(check_launch(ctx, what));
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    ctx->err = std::string(what) + ": " + hip_err(e);
+    return EFE_ERR_HIP;
+  }
+  return EFE_OK;
+}
+
+// --------------------------------------------------------------------------- setup
+efe_status build_device(efe_ctx *ctx) {
+  const efe::Plan &pl = ctx->plan;
+  DevData &d = ctx->d;
+  efe::Geom &g = d.g;
+  for (int i = 0; i < 3; ++i) {
+    g.nc[i] = pl.nc[i];
+    g.nn[i] = pl.nn[i];
+    g.lo[i] = pl.lo[i];
+    g.h[i] = pl.h[i];
+  }
+  g.p = pl.p; g.P = pl.P; g.nloc = pl.nloc; g.qc = pl.qc; g.qe = pl.qe; g.n_nodes = pl.n_nodes;
+  const int P = pl.P, NP = P * (P + 1) / 2;
+  // 1-D tables
+  std::vector<double> tab;
+  auto put = [&](const std::vector<double> &v) { int o = (int)tab.size(); tab.insert(tab.end(), v.begin(), v.end()); return o; };
+  d.to.Bc = put(pl.Bc); d.to.dBc = put(pl.dBc); d.to.Be = put(pl.Be); d.to.dBe = put(pl.dBe);
+  d.to.xqc = put(pl.xqc); d.to.wqc = put(pl.wqc); d.to.xqe = put(pl.xqe); d.to.wqe = put(pl.wqe);
+  std::vector<int> pair(P * P);
+  {
+    int idx = 0;
+    for (int a = 0; a < P; ++a)
+      for (int b = a; b < P; ++b) { pair[a * P + b] = pair[b * P + a] = idx++; }
+  }
+  for (int cls = 0; cls < 2; ++cls) {
+    const std::vector<double> &B = cls ? pl.Be : pl.Bc;
+    int n = cls ? pl.qe : pl.qc;
+    std::vector<double> G1((size_t)n * NP);
+    for (int i = 0; i < n; ++i)
+      for (int a = 0; a < P; ++a)
+        for (int b = a; b < P; ++b) G1[(size_t)i * NP + pair[a * P + b]] = B[i * P + a] * B[i * P + b];
+    if (cls) d.to.G1e = put(G1); else d.to.G1c = put(G1);
+  }
+  {
+    std::vector<double> K, M;
+    for (int dd = 0; dd < 3; ++dd) {
+      K.insert(K.end(), pl.Kel[dd].begin(), pl.Kel[dd].end());
+      M.insert(M.end(), pl.Mel[dd].begin(), pl.Mel[dd].end());
+    }
+    d.to.Kel = put(K);
+    d.to.Mel = put(M);
+    std::vector<double> pd(pair.begin(), pair.end());
+    d.to.pair = put(pd);
+  }
+  d.to.total = (int)tab.size();
+  EFE_TRY(upload(ctx, &d.tab, tab));
+  EFE_TRY(upload(ctx, &d.is_enr, pl.is_enr));
+  EFE_TRY(upload(ctx, &d.q_off, pl.q_off));
+  std::vector<int> ord, enr, col[8];
+  for (int64_t c = 0; c < pl.n_cells; ++c) {
+    (pl.is_enr[c] ? enr : ord).push_back((int)c);
+    int e[3];
+    pl.cell_ijk(c, e);
+    col[(e[0] & 1) | ((e[1] & 1) << 1) | ((e[2] & 1) << 2)].push_back((int)c);
+  }
+  d.n_ord = (int)ord.size(); d.n_enr = (int)enr.size();
+  EFE_TRY(upload(ctx, &d.cells_ord, ord));
+  EFE_TRY(upload(ctx, &d.cells_enr, enr));
+  std::vector<int> colour;
+  d.colour_off[0] = 0;
+  for (int c = 0; c < 8; ++c) {
+    colour.insert(colour.end(), col[c].begin(), col[c].end());
+    d.colour_off[c + 1] = (int)colour.size();
+  }
+  EFE_TRY(upload(ctx, &d.colour_cells, colour));
+  std::vector<double> Dm12(pl.n_nodes);
+  for (int64_t i = 0; i < pl.n_nodes; ++i) Dm12[i] = pl.is_boundary(i) ? 0.0 : 1.0 / std::sqrt(pl.D[i]);
+  EFE_TRY(upload(ctx, &d.D, pl.D));
+  EFE_TRY(upload(ctx, &d.Dm12, Dm12));
+  EFE_TRY(upload(ctx, &d.vstatic, pl.vstatic));
+  EFE_TRY(upload(ctx, &d.occ, pl.occ));
+  // enrichment
+  d.ne = pl.nenr; d.nk = pl.nk; d.nt = (int)pl.tcell.size(); d.nr = pl.n_urows();
+  EFE_TRY(upload(ctx, &d.tcell, pl.tcell));
+  EFE_TRY(upload(ctx, &d.tnu_off, pl.tnu_off));
+  EFE_TRY(upload(ctx, &d.tnu, pl.tnu));
+  EFE_TRY(upload(ctx, &d.tslot_of_cell, pl.tslot_of_cell));
+  EFE_TRY(upload(ctx, &d.tne_off, pl.tne_off));
+  EFE_TRY(upload(ctx, &d.NE, pl.NE));
+  std::vector<int64_t> tpart(d.nt + 1, 0), thee(d.nt + 1, 0);
+  std::vector<int16_t> tpos((size_t)d.nt * std::max(1, d.ne), -1);
+  for (int t = 0; t < d.nt; ++t) {
+    int nnu = pl.tnu_off[t + 1] - pl.tnu_off[t];
+    tpart[t + 1] = tpart[t] + (int64_t)pl.nloc * nnu;
+    thee[t + 1] = thee[t] + (int64_t)nnu * nnu;
+    for (int k = 0; k < nnu; ++k) tpos[(size_t)t * d.ne + pl.tnu[pl.tnu_off[t] + k]] = (int16_t)k;
+  }
+  EFE_TRY(upload(ctx, &d.tpart_off, tpart));
+  EFE_TRY(upload(ctx, &d.thee_off, thee));
+  EFE_TRY(upload(ctx, &d.tpos, tpos));
+  EFE_TRY(upload(ctx, &d.urow_node, pl.urow_node));
+  EFE_TRY(upload(ctx, &d.urow_cnt, pl.urow_cnt));
+  EFE_TRY(upload(ctx, &d.urow_pair, pl.urow_pair));
+  EFE_TRY(upload(ctx, &d.S, pl.S));
+  EFE_TRY(upload(ctx, &d.Kce, pl.Kce));
+  EFE_TRY(upload(ctx, &d.Kee, pl.Kee));
+  for (int dd = 0; dd < 3; ++dd) {
+    EFE_TRY(upload(ctx, &d.K1[dd], pl.K1[dd]));
+    EFE_TRY(upload(ctx, &d.M1[dd], pl.M1[dd]));
+    EFE_TRY(upload(ctx, &d.fdmV[dd], pl.fdmV[dd]));
+    EFE_TRY(upload(ctx, &d.fdmL[dd], pl.fdmL[dd]));
+  }
+  EFE_TRY(upload(ctx, &d.gbnd, pl.gbnd));
+  EFE_TRY(upload(ctx, &d.lift, pl.lift));
+  // work buffers
+  ctx->norb = pl.norb;
+  ctx->ncolr = 2 * pl.norb;
+  ctx->n_rows = pl.n_nodes + pl.nk;
+  ctx->blk = ctx->n_rows * ctx->ncolr;
+  const size_t esz = ctx->dtype == 0 ? 8 : (ctx->dtype == 1 ? 4 : 2);
+  void *cells = nullptr;
+  size_t cbytes = (size_t)pl.n_cells * pl.nloc * pl.nloc * esz;
+  hipError_t e = hipMalloc(&cells, cbytes);
+  if (e != hipSuccess) { ctx->err = "cell blocks: " + std::string(hip_err(e)); return EFE_ERR_ALLOC; }
+  ctx->allocs.push_back(cells);
+  ctx->cells = cells;
+  EFE_TRY(dalloc(ctx, &ctx->Q, ctx->blk * ctx->kmax));
+  EFE_TRY(dalloc(ctx, &ctx->W, ctx->blk));
+  EFE_TRY(dalloc(ctx, &ctx->X0, ctx->blk));
+  EFE_TRY(dalloc(ctx, &ctx->X1, ctx->blk));
+  EFE_TRY(dalloc(ctx, &ctx->rho_prev, pl.n_quad));
+  EFE_TRY(dalloc(ctx, &ctx->rho_tmp, pl.n_quad));
+  EFE_TRY(dalloc(ctx, &ctx->vq, pl.n_quad));
+  EFE_TRY(dalloc(ctx, &ctx->phi, pl.n_nodes));
+  EFE_TRY(dalloc(ctx, &ctx->dvec, pl.n_nodes));
+  EFE_TRY(dalloc(ctx, &ctx->rhs, pl.n_nodes));
+  for (int i = 0; i < 7; ++i) EFE_TRY(dalloc(ctx, &ctx->cg[i], pl.n_nodes));
+  EFE_TRY(dalloc(ctx, &ctx->part, tpart[d.nt]));
+  EFE_TRY(dalloc(ctx, &ctx->hee_part, thee[d.nt]));
+  EFE_TRY(dalloc(ctx, &ctx->G, d.nr * std::max(1, d.nk)));
+  EFE_TRY(dalloc(ctx, &ctx->Hee_raw, (int64_t)d.ne * d.ne));
+  EFE_TRY(dalloc(ctx, &ctx->Hbar_ee, (int64_t)d.nk * d.nk));
+  EFE_TRY(dalloc(ctx, &ctx->psiE, (int64_t)d.ne * ctx->ncolr));
+  ctx->red_len = std::max<int64_t>({(int64_t)512 * ctx->kmax * ctx->ncolr, pl.n_cells * 3, 4096});
+  EFE_TRY(dalloc(ctx, &ctx->red, ctx->red_len));
+  EFE_TRY(dalloc(ctx, &ctx->small, (int64_t)ctx->kmax * ctx->ncolr + 64));
+  EFE_TRY(dalloc(ctx, &ctx->couple_scr, (int64_t)512 * std::max(1, d.nk) * ctx->ncolr));
+  EFE_TRY(dalloc(ctx, &ctx->alpha, (int64_t)ctx->kmax * pl.norb));
+  EFE_TRY(dalloc(ctx, &ctx->beta, (int64_t)ctx->kmax * pl.norb));
+  EFE_TRY(dalloc(ctx, &ctx->beta0, pl.norb));
+  EFE_TRY(dalloc(ctx, &ctx->errv, pl.norb));
+  EFE_TRY(dalloc(ctx, &ctx->ubuf, (int64_t)pl.norb * ctx->kmax * 2));
+  EFE_TRY(dalloc(ctx, &ctx->active, pl.norb));
+  EFE_TRY(dalloc(ctx, &ctx->kused, pl.norb));
+  EFE_TRY(dalloc(ctx, &ctx->kforce, pl.norb));
+  return sync(ctx, "setup");
+}
+
+// --------------------------------------------------------------------------- building blocks
+// Y = A X with the operator currently held in the cell blocks (rows with stride ldr doubles)
+efe_status apply_op(efe_ctx *ctx, const double *X, double *Y, int ncolr, int64_t ldr) {
+  const DevData &d = ctx->d;
+  hipStream_t s = ctx->stream;
+  if (ldr != ncolr) {
+    ctx->err = "internal: apply_op expects packed blocks";
+    return EFE_ERR_ARG;
+  }
+  efe::k::zero(Y, d.g.n_nodes * ncolr, s);
+  tstart(ctx, 0);
+  efe::k::cell_apply(d, ctx->cells, ctx->dtype, X, Y, ncolr, ldr, s);
+  tstop(ctx, 0);
+  tstart(ctx, 1);
+  efe::k::couple_apply(d, ctx->G, ctx->Hbar_ee, X, Y, ncolr, ldr, ctx->couple_scr, s);
+  tstop(ctx, 1);
+  ctx->timer.n_hx++;
+  return check_launch(ctx, "apply");
+}
+
+// sums of partials -> host
+efe_status reduce_to(efe_ctx *ctx, double *part, int nblk, int nval, double *dev_out) {
+  efe::k::reduce_partials(part, nblk, nval, dev_out, ctx->stream);
+  return EFE_OK;
+}
+
+// Hartree: (1/4pi) K phi = d with phi = g on the boundary; PCG with the FDM inverse.
+efe_status hartree(efe_ctx *ctx, const double *rho, double *phi, int *iters) {
+  const DevData &d = ctx->d;
+  hipStream_t s = ctx->stream;
+  const int64_t N = d.g.n_nodes;
+  double *x = ctx->cg[0], *r = ctx->cg[1], *z = ctx->cg[2], *p = ctx->cg[3], *q = ctx->cg[4], *t1 = ctx->cg[5],
+         *t2 = ctx->cg[6];
+  tstart(ctx, 5);
+  efe::k::poisson_rhs(d, rho, ctx->dvec, ctx->rhs, s);
+  efe::k::fdm_apply(d, ctx->rhs, x, t1, t2, s);
+  efe::k::stiffness_apply(d, x, q, t1, t2, s);
+  efe::k::axpby(ctx->rhs, q, 1.0, -1.0, r, N, s);
+  auto dot = [&](const double *a, const double *b, double &out) -> efe_status {
+    int nb = efe::k::dot_partials(a, b, N, ctx->red, s);
+    efe::k::reduce_partials(ctx->red, nb, 1, ctx->small, s);
+    HIP_TRY(hipMemcpyAsync(&out, ctx->small, sizeof(double), hipMemcpyDeviceToHost, s));
+    return sync(ctx, "hartree dot");
+  };
+  double bb = 0.0, rr = 0.0, rz = 0.0, rz_old = 0.0;
+  EFE_TRY(dot(ctx->rhs, ctx->rhs, bb));
+  EFE_TRY(dot(r, r, rr));
+  int it = 0;
+  const double tol = ctx->opt.cg_tol > 0 ? ctx->opt.cg_tol : 1e-12;
+  const int maxit = ctx->opt.cg_maxit > 0 ? ctx->opt.cg_maxit : 50;
+  while (rr > tol * tol * bb && bb > 0.0) {
+    if (it >= maxit) {
+      ctx->err = "Poisson PCG did not reach the tolerance";
+      return EFE_ERR_NOCONV;
+    }
+    efe::k::fdm_apply(d, r, z, t1, t2, s);
+    EFE_TRY(dot(r, z, rz));
+    if (it == 0) HIP_TRY(hipMemcpyAsync(p, z, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+    else efe::k::axpby(z, p, 1.0, rz / rz_old, p, N, s);
+    efe::k::stiffness_apply(d, p, q, t1, t2, s);
+    double pq = 0.0;
+    EFE_TRY(dot(p, q, pq));
+    const double a = rz / pq;
+    efe::k::axpby(x, p, 1.0, a, x, N, s);
+    efe::k::axpby(r, q, 1.0, -a, r, N, s);
+    rz_old = rz;
+    EFE_TRY(dot(r, r, rr));
+    ++it;
+  }
+  HIP_TRY(hipMemcpyAsync(phi, x, N * sizeof(double), hipMemcpyDeviceToDevice, s));
+  efe::k::set_boundary(d, phi, s);
+  tstop(ctx, 5);
+  if (iters) *iters = it;
+  return check_launch(ctx, "hartree");
+}
+
+double field_value(const efe_field *f, double t) {
+  if (!f || f->kind == 0 || f->ncomp <= 0) return 0.0;
+  double s = 0.0;
+  for (int k = 0; k < f->ncomp; ++k) s += f->A[k] * std::sin(f->w[k] * t + f->phi[k]);
+  double x = (t - f->t0) / f->s;
+  return s * std::exp(-x * x);
+}
+
+efe_status validate_field(efe_ctx *ctx, const efe_field *f) {
+  if (!f || f->kind == 0) return EFE_OK;
+  if (f->kind != 1 || f->ncomp < 0 || f->direction < 0 || f->direction > 2 ||
+      (f->ncomp > 0 && (!f->A || !f->w || !f->phi)) || !(f->s > 0.0)) {
+    ctx->err = "invalid field";
+    return EFE_ERR_ARG;
+  }
+  return EFE_OK;
+}
+
+// mode 0: Hamiltonian at density rho (device) and time t; mode 1..3: position operator
+efe_status rebuild(efe_ctx *ctx, int mode, const double *rho, double t, const efe_field *field, int *cg_iters) {
+  const DevData &d = ctx->d;
+  hipStream_t s = ctx->stream;
+  double efield = 0.0;
+  int fdir = 2;
+  if (mode == 0) {
+    EFE_TRY(hartree(ctx, rho, ctx->phi, cg_iters));
+    efield = field_value(field, t);
+    if (field && field->kind) fdir = field->direction;
+  }
+  tstart(ctx, 6);
+  efe::k::rebuild_cells(d, mode, rho, ctx->phi, efield, fdir, ctx->plan.xc, ctx->cells, ctx->dtype, ctx->vq, s);
+  efe::k::coupling_partials(d, ctx->vq, ctx->part, ctx->hee_part, s);
+  efe::k::coupling_gather(d, ctx->part, mode == 0 ? 1 : 0, ctx->G, s);
+  efe::k::hee_reduce(d, ctx->hee_part, mode == 0 ? 1 : 0, ctx->Hee_raw, ctx->Hbar_ee, s);
+  tstop(ctx, 6);
+  ctx->cells_mode = mode;
+  return check_launch(ctx, "rebuild");
+}
+
+efe_status density_packed(efe_ctx *ctx, const double *X, double *rho) {
+  const DevData &d = ctx->d;
+  tstart(ctx, 4);
+  efe::k::psiE(d, X, ctx->ncolr, ctx->ncolr, ctx->psiE, ctx->stream);
+  efe::k::density(d, X, ctx->norb, ctx->ncolr, ctx->psiE, rho, ctx->stream);
+  tstop(ctx, 4);
+  return check_launch(ctx, "density");
+}
+
+efe_status dipole_of(efe_ctx *ctx, const double *rho, double mu[3]) {
+  int nb = 0;
+  efe::k::dipole_partials(ctx->d, rho, ctx->red, &nb, ctx->stream);
+  efe::k::reduce_partials(ctx->red, nb, 3, ctx->small, ctx->stream);
+  HIP_TRY(hipMemcpyAsync(mu, ctx->small, 3 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+  return sync(ctx, "dipole");
+}
+
+// X (packed, n_rows x ncol complex) -> out = exp(-i tau A) X for the operator in the cell blocks.
+efe_status run_lanczos(efe_ctx *ctx, double tau, const double *X, double *out, int ncol, const int32_t *kforce_host,
+                       int32_t *kused_host, double *err_host) {
+  hipStream_t s = ctx->stream;
+  const int64_t nrows = ctx->n_rows;
+  const int ncolr = 2 * ncol;
+  const int64_t bs = nrows * ncolr;     // doubles per block (packed for ncol)
+  const int kmax = ctx->kmax;
+  const double tol = ctx->opt.krylov_tol > 0 ? ctx->opt.krylov_tol : 1e-10;
+  if (kforce_host) {
+    for (int c = 0; c < ncol; ++c)
+      if (kforce_host[c] < 1 || kforce_host[c] > kmax) {
+        ctx->err = "k_force entries must be 1..kmax";
+        return EFE_ERR_ARG;
+      }
+    HIP_TRY(hipMemcpyAsync(ctx->kforce, kforce_host, ncol * sizeof(int), hipMemcpyHostToDevice, s));
+  }
+  const int *kf = kforce_host ? ctx->kforce : nullptr;
+  double *tmp = ctx->small;
+  tstart(ctx, 2);
+  int nb = efe::k::multidot_partials(X, 0, 1, X, nrows, ncol, nullptr, ctx->red, s);
+  efe::k::reduce_partials(ctx->red, nb, ncolr, tmp, s);
+  efe::k::store_re(tmp, ctx->beta0, ncol, 1, nullptr, s);
+  efe::k::init_active(ctx->beta0, ctx->active, ctx->kused, ncol, s);
+  efe::k::scale_cols(X, ctx->Q, ctx->beta0, nrows, ncol, ctx->active, s);
+  tstop(ctx, 2);
+  std::vector<int> act(ncol);
+  HIP_TRY(hipMemcpyAsync(act.data(), ctx->active, ncol * sizeof(int), hipMemcpyDeviceToHost, s));
+  EFE_TRY(sync(ctx, "lanczos start"));
+  bool any = false;
+  for (int c = 0; c < ncol; ++c) any |= act[c] != 0;
+  std::vector<double> b0h(ncol);
+  HIP_TRY(hipMemcpy(b0h.data(), ctx->beta0, ncol * sizeof(double), hipMemcpyDeviceToHost));
+  for (int c = 0; c < ncol; ++c)
+    if (!std::isfinite(b0h[c])) { ctx->err = "non-finite input orbital"; return EFE_ERR_NONFINITE; }
+  int j = 0;
+  while (any) {
+    ++j;
+    double *q = ctx->Q + (int64_t)(j - 1) * bs;
+    EFE_TRY(apply_op(ctx, q, ctx->W, ncolr, ncolr));
+    tstart(ctx, 2);
+    double *a_j = ctx->alpha + (int64_t)(j - 1) * ncol;
+    nb = efe::k::multidot_partials(q, 0, 1, ctx->W, nrows, ncol, ctx->active, ctx->red, s);
+    efe::k::reduce_partials(ctx->red, nb, ncolr, tmp, s);
+    efe::k::store_re(tmp, a_j, ncol, 0, ctx->active, s);
+    efe::k::three_term(ctx->W, q, j > 1 ? q - bs : nullptr, a_j, j > 1 ? ctx->beta + (int64_t)(j - 2) * ncol : nullptr,
+                       nrows, ncol, ctx->active, s);
+    for (int pass = 0; pass < 2; ++pass) {
+      nb = efe::k::multidot_partials(ctx->Q, bs, j, ctx->W, nrows, ncol, ctx->active, ctx->red, s);
+      efe::k::reduce_partials(ctx->red, nb, j * ncolr, tmp, s);
+      efe::k::multi_update(ctx->Q, bs, j, tmp, ctx->W, nrows, ncol, ctx->active, s);
+    }
+    double *b_j = ctx->beta + (int64_t)(j - 1) * ncol;
+    nb = efe::k::multidot_partials(ctx->W, 0, 1, ctx->W, nrows, ncol, ctx->active, ctx->red, s);
+    efe::k::reduce_partials(ctx->red, nb, ncolr, tmp, s);
+    efe::k::store_re(tmp, b_j, ncol, 1, ctx->active, s);
+    tstop(ctx, 2);
+    tstart(ctx, 3);
+    efe::k::tridiag_exp(ctx->alpha, ctx->beta, j, ncol, kmax, tau, ctx->beta0, kf, tol, ctx->active, ctx->kused,
+                        ctx->errv, ctx->ubuf, s);
+    tstop(ctx, 3);
+    HIP_TRY(hipMemcpyAsync(act.data(), ctx->active, ncol * sizeof(int), hipMemcpyDeviceToHost, s));
+    EFE_TRY(sync(ctx, "lanczos iteration"));
+    any = false;
+    for (int c = 0; c < ncol; ++c) any |= act[c] != 0;
+    if (!any) break;
+    if (j == kmax) {
+      ctx->err = "Lanczos did not reach the tolerance within kmax vectors";
+      return EFE_ERR_NOCONV;
+    }
+    tstart(ctx, 2);
+    efe::k::scale_cols(ctx->W, ctx->Q + (int64_t)j * bs, b_j, nrows, ncol, ctx->active, s);
+    tstop(ctx, 2);
+  }
+  tstart(ctx, 2);
+  efe::k::combine(ctx->Q, bs, ctx->ubuf, kmax, ctx->kused, ctx->beta0, out, nrows, ncol, s);
+  tstop(ctx, 2);
+  std::vector<int> ku(ncol);
+  std::vector<double> ev(ncol);
+  HIP_TRY(hipMemcpyAsync(ku.data(), ctx->kused, ncol * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(ev.data(), ctx->errv, ncol * sizeof(double), hipMemcpyDeviceToHost, s));
+  EFE_TRY(sync(ctx, "lanczos end"));
+  for (int c = 0; c < ncol; ++c) {
+    if (kused_host) kused_host[c] = ku[c];
+    if (err_host) err_host[c] = b0h[c] > 0 ? ev[c] : 0.0;
+  }
+  return EFE_OK;
+}
+
+efe_status check_ctx(efe_ctx *ctx) {
+  if (!ctx) return EFE_ERR_ARG;
+  return EFE_OK;
+}
+
+// copy a user block (ld complex per row) into packed X0 (ncol complex per row)
+efe_status pack_in(efe_ctx *ctx, const void *src, int64_t ld, int ncol, double *dst) {
+  if (ld == ncol) {
+    HIP_TRY(hipMemcpyAsync(dst, src, ctx->n_rows * 2 * ncol * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  } else {
+    efe::k::copy_rows((const double *)src, 2 * ld, dst, 2 * ncol, ctx->n_rows, 2 * ncol, ctx->stream);
+  }
+  return check_launch(ctx, "pack");
+}
+
+efe_status pack_out(efe_ctx *ctx, const double *src, int ncol, void *dst, int64_t ld) {
+  if (ld == ncol) {
+    HIP_TRY(hipMemcpyAsync(dst, src, ctx->n_rows * 2 * ncol * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  } else {
+    efe::k::copy_rows(src, 2 * ncol, (double *)dst, 2 * ld, ctx->n_rows, 2 * ncol, ctx->stream);
+  }
+  return check_launch(ctx, "unpack");
+}
+
+}  // namespace
+
+// ============================================================================ C ABI
+extern "C" {
+
+efe_status efe_plan_create(const efe_system *sys, efe_plan **out) {
+  if (!sys || !out) return EFE_ERR_ARG;
+  *out = nullptr;
+  efe_plan *p = new (std::nothrow) efe_plan();
+  if (!p) return EFE_ERR_ALLOC;
+  efe_status st;
+  try {
+    st = efe::build_plan(*sys, p->p);
+  } catch (const std::bad_alloc &) {
+    st = EFE_ERR_ALLOC;
+    p->p.error = "host allocation failed";
+  }
+  *out = p;   // returned even on error so that efe_plan_error can report
+  return st;
+}
+
+efe_status efe_plan_free(efe_plan *plan) {
+  delete plan;
+  return EFE_OK;
+}
+
+const char *efe_plan_error(const efe_plan *plan) { return plan ? plan->p.error.c_str() : "null plan"; }
+
+efe_status efe_plan_sizes(const efe_plan *plan, int64_t sizes[6]) {
+  if (!plan || !sizes) return EFE_ERR_ARG;
+  const efe::Plan &p = plan->p;
+  sizes[0] = p.n_nodes; sizes[1] = p.n_cells; sizes[2] = p.n_quad; sizes[3] = p.nk;
+  sizes[4] = p.n_urows(); sizes[5] = (int64_t)p.tcell.size();
+  return EFE_OK;
+}
+
+efe_status efe_plan_get(const efe_plan *plan, const char *name, double *out, int64_t count) {
+  if (!plan || !name || !out) return EFE_ERR_ARG;
+  const efe::Plan &p = plan->p;
+  const int ne = p.nenr;
+  std::string n(name);
+  auto give = [&](const std::vector<double> &v) -> efe_status {
+    if ((int64_t)v.size() != count) return EFE_ERR_ARG;
+    std::copy(v.begin(), v.end(), out);
+    return EFE_OK;
+  };
+  auto expand = [&](const std::vector<double> &v) -> efe_status {   // union rows -> all nodes
+    if (count != p.n_nodes * ne) return EFE_ERR_ARG;
+    std::fill(out, out + count, 0.0);
+    for (int64_t r = 0; r < p.n_urows(); ++r)
+      for (int k = 0; k < ne; ++k) out[p.urow_node[r] * ne + k] = v[(size_t)r * ne + k];
+    return EFE_OK;
+  };
+  if (n == "D") return give(p.D);
+  if (n == "S") return give(p.S);
+  if (n == "Mee") return give(p.Mee);
+  if (n == "MAA") return give(p.MAA);
+  if (n == "enr_scale") return give(p.enr_scale);
+  if (n == "Kee") return give(p.Kee);
+  if (n == "vstatic") return give(p.vstatic);
+  if (n == "lift") return give(p.lift);
+  if (n == "gbnd") return give(p.gbnd);
+  if (n == "c") return expand(p.c);
+  if (n == "b") return expand(p.b);
+  if (n == "Kce") return expand(p.Kce);
+  if (n == "is_enr") {
+    std::vector<double> v(p.is_enr.begin(), p.is_enr.end());
+    return give(v);
+  }
+  return EFE_ERR_ARG;
+}
+
+efe_status efe_setup(const efe_system *sys, const efe_options *opt, efe_ctx **out) {
+  if (!sys || !opt || !out) return EFE_ERR_ARG;
+  *out = nullptr;
+  if (opt->prod_dtype < 0 || opt->prod_dtype > 2 || opt->kmax < 1 || opt->kmax > 64) return EFE_ERR_ARG;
+  efe_ctx *ctx = new (std::nothrow) efe_ctx();
+  if (!ctx) return EFE_ERR_ALLOC;
+  ctx->opt = *opt;
+  ctx->dtype = opt->prod_dtype;
+  ctx->kmax = opt->kmax;
+  ctx->stream = (hipStream_t)opt->hip_stream;
+  efe_status st;
+  try {
+    st = efe::build_plan(*sys, ctx->plan);
+    if (st != EFE_OK) ctx->err = ctx->plan.error;
+    else st = build_device(ctx);
+  } catch (const std::bad_alloc &) {
+    st = EFE_ERR_ALLOC;
+    ctx->err = "host allocation failed";
+  }
+  *out = ctx;   // returned even on error (efe_last_error); caller frees
+  return st;
+}
+
+efe_status efe_free(efe_ctx *ctx) {
+  if (!ctx) return EFE_OK;
+  if (ctx->stream) hipStreamSynchronize(ctx->stream);
+  else hipDeviceSynchronize();
+  timer_reset(ctx);
+  for (void *p : ctx->allocs) hipFree(p);
+  delete ctx;
+  return EFE_OK;
+}
+
+efe_status efe_dims(const efe_ctx *ctx, int64_t dims[4]) {
+  if (!ctx || !dims) return EFE_ERR_ARG;
+  dims[0] = ctx->n_rows;
+  dims[1] = ctx->plan.n_nodes;
+  dims[2] = ctx->plan.nk;
+  dims[3] = ctx->plan.n_quad;
+  return EFE_OK;
+}
+
+efe_status efe_set_options(efe_ctx *ctx, const efe_options *opt) {
+  if (!ctx || !opt) return EFE_ERR_ARG;
+  if (opt->kmax < 1 || opt->kmax > ctx->kmax || opt->prod_dtype != ctx->dtype) {
+    ctx->err = "kmax may only decrease and the product dtype is fixed at setup";
+    return EFE_ERR_ARG;
+  }
+  ctx->opt = *opt;
+  ctx->kmax = opt->kmax;
+  ctx->stream = (hipStream_t)opt->hip_stream;
+  return EFE_OK;
+}
+
+efe_status efe_initial_state(efe_ctx *ctx, const int32_t *enr_index, const double *g, double amp, void *Psi) {
+  if (!ctx || !enr_index || !g || !Psi) return EFE_ERR_ARG;
+  std::vector<double> X;
+  efe_status st = efe::initial_state(ctx->plan, enr_index, g, amp, X);
+  if (st != EFE_OK) {
+    ctx->err = "initial state: invalid enrichment index or degenerate orbitals";
+    return st;
+  }
+  // real -> complex interleaved
+  const int no = ctx->norb;
+  std::vector<double> Z((size_t)ctx->n_rows * 2 * no, 0.0);
+  for (int64_t r = 0; r < ctx->n_rows; ++r)
+    for (int a = 0; a < no; ++a) Z[((size_t)r * no + a) * 2] = X[(size_t)r * no + a];
+  HIP_TRY(hipMemcpy(Psi, Z.data(), Z.size() * sizeof(double), hipMemcpyHostToDevice));
+  ctx->ham_valid = false;
+  return EFE_OK;
+}
+
+efe_status efe_set_hamiltonian(efe_ctx *ctx, const void *Psi, double t, const efe_field *field) {
+  if (!ctx || !Psi) return EFE_ERR_ARG;
+  EFE_TRY(validate_field(ctx, field));
+  timer_reset(ctx);
+  ctx->ham_valid = false;
+  EFE_TRY(pack_in(ctx, Psi, ctx->norb, ctx->norb, ctx->X0));
+  EFE_TRY(density_packed(ctx, ctx->X0, ctx->rho_prev));
+  EFE_TRY(rebuild(ctx, 0, ctx->rho_prev, t, field, nullptr));
+  EFE_TRY(sync(ctx, "set_hamiltonian"));
+  timer_collect(ctx);
+  ctx->ham_valid = true;
+  return EFE_OK;
+}
+
+efe_status efe_apply_H(efe_ctx *ctx, const void *X, void *Y, int32_t ncol, int64_t ld) {
+  if (!ctx || !X || !Y || ncol < 1 || ncol > ctx->norb || ld < ncol) return EFE_ERR_ARG;
+  if (ctx->cells_mode != 0) {
+    ctx->err = "no Hamiltonian built (call efe_set_hamiltonian)";
+    return EFE_ERR_STATE;
+  }
+  timer_reset(ctx);
+  EFE_TRY(pack_in(ctx, X, ld, ncol, ctx->X0));
+  EFE_TRY(apply_op(ctx, ctx->X0, ctx->X1, 2 * ncol, 2 * ncol));
+  EFE_TRY(pack_out(ctx, ctx->X1, ncol, Y, ld));
+  EFE_TRY(sync(ctx, "apply_H"));
+  timer_collect(ctx);
+  return EFE_OK;
+}
+
+efe_status lanczos_expm(efe_ctx *ctx, int32_t op, double tau, void *X, int32_t ncol, int64_t ld,
+                        const int32_t *k_force, int32_t *k_used, double *err_est) {
+  if (!ctx || !X || ncol < 1 || ncol > ctx->norb || ld < ncol || op < 0 || op > 3 || !std::isfinite(tau))
+    return EFE_ERR_ARG;
+  timer_reset(ctx);
+  if (op == EFE_OP_H) {
+    if (ctx->cells_mode != 0) {
+      ctx->err = "no Hamiltonian built (call efe_set_hamiltonian)";
+      return EFE_ERR_STATE;
+    }
+  } else {
+    ctx->ham_valid = false;
+    EFE_TRY(rebuild(ctx, op, nullptr, 0.0, nullptr, nullptr));
+  }
+  EFE_TRY(pack_in(ctx, X, ld, ncol, ctx->X0));
+  EFE_TRY(run_lanczos(ctx, tau, ctx->X0, ctx->X1, ncol, k_force, k_used, err_est));
+  EFE_TRY(pack_out(ctx, ctx->X1, ncol, X, ld));
+  EFE_TRY(sync(ctx, "lanczos_expm"));
+  timer_collect(ctx);
+  return EFE_OK;
+}
+
+efe_status magnus_step(efe_ctx *ctx, void *Psi, int64_t ld, double t, double dt, const efe_field *field,
+                       const int32_t *k_force, efe_step_stats *stats) {
+  if (!ctx || !Psi || ld < ctx->norb || !std::isfinite(t) || !std::isfinite(dt)) return EFE_ERR_ARG;
+  EFE_TRY(validate_field(ctx, field));
+  if (!ctx->ham_valid || ctx->cells_mode != 0) {
+    ctx->err = "magnus_step needs the Hamiltonian of the current orbitals (call efe_set_hamiltonian)";
+    return EFE_ERR_STATE;
+  }
+  timer_reset(ctx);
+  tstart(ctx, 7);
+  const int no = ctx->norb;
+  const int64_t n = ctx->plan.n_quad;
+  double *Xp = ctx->X1;
+  std::vector<int32_t> kp(no), kc(no);
+  std::vector<double> ep(no), ec(no);
+  int cg[2] = {0, 0};
+  ctx->ham_valid = false;   // restored on success
+  EFE_TRY(pack_in(ctx, Psi, ld, no, ctx->X0));
+  // predictor with Hbar[rho_n, t]
+  EFE_TRY(run_lanczos(ctx, dt, ctx->X0, Xp, no, k_force ? k_force : nullptr, kp.data(), ep.data()));
+  // midpoint Hamiltonian from rho_mid = (rho_n + rho_p)/2 at t + dt/2
+  EFE_TRY(density_packed(ctx, Xp, ctx->rho_tmp));
+  efe::k::axpby(ctx->rho_prev, ctx->rho_tmp, 0.5, 0.5, ctx->rho_tmp, n, ctx->stream);
+  EFE_TRY(rebuild(ctx, 0, ctx->rho_tmp, t + 0.5 * dt, field, &cg[0]));
+  // corrector from Psi_n
+  EFE_TRY(run_lanczos(ctx, dt, ctx->X0, Xp, no, k_force ? k_force + no : nullptr, kc.data(), ec.data()));
+  // end of step: rho_{n+1}, Hbar[rho_{n+1}, t + dt], dipole
+  EFE_TRY(density_packed(ctx, Xp, ctx->rho_prev));
+  EFE_TRY(rebuild(ctx, 0, ctx->rho_prev, t + dt, field, &cg[1]));
+  double mu[3];
+  EFE_TRY(dipole_of(ctx, ctx->rho_prev, mu));
+  if (!std::isfinite(mu[0]) || !std::isfinite(mu[1]) || !std::isfinite(mu[2])) {
+    ctx->err = "non-finite dipole after the step";
+    return EFE_ERR_NONFINITE;
+  }
+  EFE_TRY(pack_out(ctx, Xp, no, Psi, ld));
+  tstop(ctx, 7);
+  EFE_TRY(sync(ctx, "magnus_step"));
+  timer_collect(ctx);
+  ctx->ham_valid = true;
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    for (int c = 0; c < no && c < 128; ++c) {
+      stats->k_pred[c] = kp[c];
+      stats->k_corr[c] = kc[c];
+      stats->err_pred_max = std::max(stats->err_pred_max, ep[c]);
+      stats->err_corr_max = std::max(stats->err_corr_max, ec[c]);
+    }
+    stats->cg_iters[0] = cg[0];
+    stats->cg_iters[1] = cg[1];
+    for (int k = 0; k < 3; ++k) stats->mu[k] = mu[k];
+  }
+  return EFE_OK;
+}
+
+efe_status density(efe_ctx *ctx, const void *Psi, int64_t ld, double *rho_q) {
+  if (!ctx || !Psi || !rho_q || ld < ctx->norb) return EFE_ERR_ARG;
+  timer_reset(ctx);
+  EFE_TRY(pack_in(ctx, Psi, ld, ctx->norb, ctx->X0));
+  EFE_TRY(density_packed(ctx, ctx->X0, rho_q));
+  EFE_TRY(sync(ctx, "density"));
+  timer_collect(ctx);
+  return EFE_OK;
+}
+
+efe_status efe_hartree(efe_ctx *ctx, const double *rho_q, double *phi, int32_t *iters) {
+  if (!ctx || !rho_q || !phi) return EFE_ERR_ARG;
+  timer_reset(ctx);
+  int it = 0;
+  EFE_TRY(hartree(ctx, rho_q, phi, &it));
+  EFE_TRY(sync(ctx, "hartree"));
+  timer_collect(ctx);
+  if (iters) *iters = it;
+  return EFE_OK;
+}
+
+efe_status dipole(efe_ctx *ctx, const void *Psi, int64_t ld, double mu[3]) {
+  if (!ctx || !Psi || !mu || ld < ctx->norb) return EFE_ERR_ARG;
+  EFE_TRY(pack_in(ctx, Psi, ld, ctx->norb, ctx->X0));
+  EFE_TRY(density_packed(ctx, ctx->X0, ctx->rho_tmp));
+  return dipole_of(ctx, ctx->rho_tmp, mu);
+}
+
+efe_status efe_enable_timing(efe_ctx *ctx, int32_t on) {
+  if (!ctx) return EFE_ERR_ARG;
+  timer_reset(ctx);
+  ctx->timer.on = on != 0;
+  return EFE_OK;
+}
+
+efe_status efe_get_timing(const efe_ctx *ctx, double ms[8], int64_t *n_hx) {
+  if (!ctx || !ms) return EFE_ERR_ARG;
+  for (int i = 0; i < kStages; ++i) ms[i] = ctx->timer.ms[i];
+  if (n_hx) *n_hx = ctx->timer.n_hx;
+  return EFE_OK;
+}
+
+const char *efe_last_error(const efe_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+}  // extern "C"

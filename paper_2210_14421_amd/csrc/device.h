@@ -1,0 +1,117 @@
+// Device-side data of a context and the launchers of the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace efe {
+
+// Geometry and 1-D tables needed by most kernels (passed by value).
+struct Geom {
+  int nc[3];
+  int64_t nn[3];
+  int p, P, nloc;
+  int qc, qe;
+  double lo[3], h[3];
+  int64_t n_nodes;
+};
+
+// Offsets of the 1-D tables inside the device table buffer (doubles).
+struct TabOff {
+  int Bc, dBc, Be, dBe;     // [n][P]
+  int xqc, wqc, xqe, wqe;   // [n]
+  int G1c, G1e;             // [n][NP]: B[i][a] B[i][a'] per unordered pair
+  int Kel, Mel;             // [3][P][P]
+  int pair;                 // [P][P] pair index (as doubles)
+  int total;
+};
+
+struct DevData {
+  Geom g;
+  TabOff to;
+  double *tab = nullptr;          // 1-D tables
+  uint8_t *is_enr = nullptr;      // n_cells
+  int64_t *q_off = nullptr;       // n_cells + 1
+  int *cells_ord = nullptr, *cells_enr = nullptr;   // ordinary / enrichment cell ids
+  int n_ord = 0, n_enr = 0;
+  int *colour_cells = nullptr;    // cells grouped by colour
+  int colour_off[9] = {0};
+  double *D = nullptr, *Dm12 = nullptr;   // lumped mass, D^-1/2 (0 on boundary)
+  double *vstatic = nullptr;      // n_quad
+  double *occ = nullptr;          // norb
+  // enrichment
+  int ne = 0, nk = 0, nt = 0;     // enrichment functions, kept directions, T-cells
+  int64_t nr = 0;                 // union rows
+  int *tcell = nullptr, *tnu_off = nullptr, *tnu = nullptr;
+  int *tslot_of_cell = nullptr;   // n_cells, -1 if not a T-cell
+  int64_t *tne_off = nullptr;     // per slot, N^E values
+  double *NE = nullptr;
+  int64_t *tpart_off = nullptr;   // per slot: offset into the coupling partials (nloc * nnu)
+  int64_t *thee_off = nullptr;    // per slot: offset into H^ee partials (nnu^2)
+  int16_t *tpos = nullptr;        // [slot][ne]: local index of nu in the slot's list, -1
+  int64_t *urow_node = nullptr;
+  int *urow_cnt = nullptr, *urow_pair = nullptr;
+  double *S = nullptr;            // ne x nk
+  double *Kce = nullptr;          // nr x ne
+  double *Kee = nullptr;          // ne x ne
+  // Poisson
+  double *K1[3] = {nullptr, nullptr, nullptr}, *M1[3] = {nullptr, nullptr, nullptr};
+  double *fdmV[3] = {nullptr, nullptr, nullptr}, *fdmL[3] = {nullptr, nullptr, nullptr};
+  double *gbnd = nullptr, *lift = nullptr;
+};
+
+// Kernel launchers (stream-ordered, no synchronisation).
+namespace k {
+
+void zero(double *p, int64_t n, hipStream_t s);
+void copy_rows(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t nrows, int ncolr, hipStream_t s);
+void axpby(const double *x, const double *y, double a, double b, double *out, int64_t n, hipStream_t s);
+
+// rebuild of the cell blocks: mode 0 = Hamiltonian, 1..3 = position operator x/y/z
+void rebuild_cells(const DevData &d, int mode, const double *rho, const double *phi, double efield,
+                   int fdir, int xc, void *cells, int dtype, double *vq, hipStream_t s);
+void coupling_partials(const DevData &d, const double *vq, double *part, double *hee_part, hipStream_t s);
+void coupling_gather(const DevData &d, const double *part, int kinetic, double *G, hipStream_t s);
+void hee_reduce(const DevData &d, const double *hee_part, int kinetic, double *Hee_raw, double *Hbar_ee,
+                hipStream_t s);
+
+// Hbar X
+void cell_apply(const DevData &d, const void *cells, int dtype, const double *X, double *Y, int ncolr,
+                int64_t ldr, hipStream_t s);
+void couple_apply(const DevData &d, const double *G, const double *Hee, const double *X, double *Y,
+                  int ncolr, int64_t ldr, double *scratch, hipStream_t s);
+
+// density and Poisson
+void psiE(const DevData &d, const double *X, int ncolr, int64_t ldr, double *psiE, hipStream_t s);
+void density(const DevData &d, const double *X, int ncol, int64_t ldr, const double *psiE, double *rho,
+             hipStream_t s);
+void poisson_rhs(const DevData &d, const double *rho, double *dvec, double *rhs, hipStream_t s);
+void stiffness_apply(const DevData &d, const double *x, double *y, double *t1, double *t2, hipStream_t s);
+void fdm_apply(const DevData &d, const double *r, double *z, double *t1, double *t2, hipStream_t s);
+void set_boundary(const DevData &d, double *phi, hipStream_t s);
+// partial dot products: out[blk] partials; returns number of blocks used
+int dot_partials(const double *x, const double *y, int64_t n, double *part, hipStream_t s);
+void reduce_partials(const double *part, int nblk, int nval, double *out, hipStream_t s);
+void dipole_partials(const DevData &d, const double *rho, double *part, int *nblk, hipStream_t s);
+
+// Lanczos
+int coldot_partials(const double *A, const double *B, int64_t nrows, int ncol, double *part, hipStream_t s);
+int multidot_partials(const double *Q, int64_t qstride, int nq, const double *w, int64_t nrows, int ncol,
+                      const int *active, double *part, hipStream_t s);
+void multi_update(const double *Q, int64_t qstride, int nq, const double *h, double *w, int64_t nrows,
+                  int ncol, const int *active, hipStream_t s);
+void three_term(double *w, const double *q, const double *qm1, const double *alpha, const double *beta,
+                int64_t nrows, int ncol, const int *active, hipStream_t s);
+void scale_cols(const double *w, double *q, const double *inv, int64_t nrows, int ncol, const int *active,
+                hipStream_t s);
+void tridiag_exp(const double *alpha, const double *beta, int j, int ncol, int kmax, double tau,
+                 const double *beta0, const int *kforce, double tol, int *active, int *kused, double *err,
+                 double *u, hipStream_t s);
+void store_re(const double *tmp, double *dst, int ncol, int sqrt_mode, const int *active, hipStream_t s);
+void init_active(const double *beta0, int *active, int *kused, int ncol, hipStream_t s);
+void combine(const double *Q, int64_t qstride, const double *u, int kmax, const int *kused, const double *beta0,
+             double *out, int64_t nrows, int ncol, hipStream_t s);
+
+}  // namespace k
+}  // namespace efe

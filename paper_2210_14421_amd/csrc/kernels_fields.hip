@@ -1,0 +1,680 @@
+// HIP kernels for the time-dependent fields of the Magnus step:
+//   rebuild of the Loewdin cell blocks  Hbar_c = D_c^-1/2 (1/2 K_c + B^T diag(W v) B) D_c^-1/2
+//   enrichment coupling  H^ce_{i nu} = int 1/2 grad N_i . grad N^E + v N_i N^E  (and H^ee)
+//   density at quadrature points, Poisson right-hand side, stiffness and
+//   fast-diagonalisation operators, dipole.
+// Sec. 2.1-2.3 of the paper (eqs. (Hmn), (TDKSDiscrete2), (DiscretePoisson)).
+#include <hip/hip_runtime.h>
+
+#include "common.cuh"
+
+namespace efe {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);   // round to nearest even
+  return (uint16_t)(u >> 16);
+}
+
+template <typename T> __device__ __forceinline__ T cast_out(double v);
+template <> __device__ __forceinline__ double cast_out<double>(double v) { return v; }
+template <> __device__ __forceinline__ float cast_out<float>(double v) { return (float)v; }
+template <> __device__ __forceinline__ uint16_t cast_out<uint16_t>(double v) { return f32_to_bf16((float)v); }
+
+// ---------------------------------------------------------------------------
+// Cell-block rebuild.  One workgroup per cell of one class (all cells of a
+// launch share the Gauss rule size n).  The potential part
+//   V[(a,b,c),(a',b',c')] = sum_ijk W v(i,j,k) B_i(a)B_i(a') B_j(b)B_j(b') B_k(c)B_k(c')
+// depends on the unordered pairs {a,a'}, {b,b'}, {c,c'} only, and is built by
+// three contractions over the pair tables G1[i][pair] = B_i(a) B_i(a').
+// mode 0: Hamiltonian (kinetic + v_static + v_H + v_xc - E x_dir); mode 1..3:
+// position operator along x/y/z (v = x_d, no kinetic term).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kThreads)
+k_rebuild(const DevData d, const int *__restrict__ cell_list, int n, int mode, const double *__restrict__ rho,
+          const double *__restrict__ phi, double efield, int fdir, int xc, T *__restrict__ cells,
+          double *__restrict__ vq) {
+  extern __shared__ double sm[];
+  const Geom &g = d.g;
+  const int P = g.P, P2 = P * P, nloc = g.nloc, NP = P * (P + 1) / 2;
+  const int n3 = n * n * n;
+  const bool enr = n == g.qe && g.qe != g.qc ? true : (n == g.qe);
+  const double *tab = d.tab;
+  double *Bt = sm;                       // n*P
+  double *G1 = Bt + n * P;               // n*NP
+  double *Kel = G1 + n * NP;             // 3*P2
+  double *Mel = Kel + 3 * P2;            // 3*P2
+  double *dm = Mel + 3 * P2;             // nloc
+  double *wv = dm + nloc;                // n3
+  double *U = wv + n3;                   // n*n*NP
+  double *W2 = U + n * n * NP;           // n*NP*NP
+  double *Vc = W2 + n * NP * NP;         // NP*NP
+  int *pair = (int *)(Vc + NP * NP);     // P2 ints
+  // scratch for the Hartree interpolation aliases U / W2
+  double *u0 = U, *t1 = U + nloc, *t2 = W2;
+
+  const int64_t cell = cell_list[blockIdx.x];
+  int e[3];
+  cell_ijk(g, cell, e);
+  const int toB = enr ? d.to.Be : d.to.Bc, toG = enr ? d.to.G1e : d.to.G1c;
+  const int tox = enr ? d.to.xqe : d.to.xqc, tow = enr ? d.to.wqe : d.to.wqc;
+  for (int t = threadIdx.x; t < n * P; t += blockDim.x) Bt[t] = tab[toB + t];
+  for (int t = threadIdx.x; t < n * NP; t += blockDim.x) G1[t] = tab[toG + t];
+  for (int t = threadIdx.x; t < 3 * P2; t += blockDim.x) {
+    Kel[t] = tab[d.to.Kel + t];
+    Mel[t] = tab[d.to.Mel + t];
+  }
+  for (int t = threadIdx.x; t < P2; t += blockDim.x) pair[t] = (int)tab[d.to.pair + t];
+  for (int t = threadIdx.x; t < nloc; t += blockDim.x) {
+    int64_t node = local_node(g, e, t);
+    dm[t] = d.Dm12[node];
+    if (mode == 0) u0[t] = phi[node];
+  }
+  __syncthreads();
+  const int64_t q0 = d.q_off[cell];
+  if (mode == 0) {
+    apply_axis(u0, t1, Bt, P, false, P, P, P, 0, n, 1);      // [c][b][i]
+    __syncthreads();
+    apply_axis(t1, t2, Bt, P, false, n, P, P, 1, n, 1);      // [c][j][i]
+    __syncthreads();
+    apply_axis(t2, wv, Bt, P, false, n, n, P, 2, n, 1);      // [k][j][i] = v_H
+    __syncthreads();
+  }
+  const double jac = 0.125 * g.h[0] * g.h[1] * g.h[2];
+  for (int q = threadIdx.x; q < n3; q += blockDim.x) {
+    int i = q % n, j = (q / n) % n, k = q / (n * n);
+    double x[3] = {g.lo[0] + e[0] * g.h[0] + (tab[tox + i] + 1.0) * 0.5 * g.h[0],
+                   g.lo[1] + e[1] * g.h[1] + (tab[tox + j] + 1.0) * 0.5 * g.h[1],
+                   g.lo[2] + e[2] * g.h[2] + (tab[tox + k] + 1.0) * 0.5 * g.h[2]};
+    double w = jac * tab[tow + i] * tab[tow + j] * tab[tow + k];
+    double v;
+    if (mode == 0) {
+      v = d.vstatic[q0 + q] + wv[q] + vxc_lda(rho[q0 + q], xc) - efield * x[fdir];
+    } else {
+      v = x[mode - 1];
+    }
+    vq[q0 + q] = v;
+    wv[q] = w * v;
+  }
+  __syncthreads();
+  // U[k][j][pa] = sum_i wv[k][j][i] G1[i][pa]
+  for (int t = threadIdx.x; t < n * n * NP; t += blockDim.x) {
+    int pa = t % NP, kj = t / NP;
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += wv[kj * n + i] * G1[i * NP + pa];
+    U[t] = s;
+  }
+  __syncthreads();
+  // W2[k][pb][pa] = sum_j G1[j][pb] U[k][j][pa]
+  for (int t = threadIdx.x; t < n * NP * NP; t += blockDim.x) {
+    int pa = t % NP, pb = (t / NP) % NP, k = t / (NP * NP);
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) s += G1[j * NP + pb] * U[(k * n + j) * NP + pa];
+    W2[t] = s;
+  }
+  __syncthreads();
+  T *out = cells + (int64_t)blockIdx.x * 0 + cell * (int64_t)nloc * nloc;
+  for (int c = 0; c < P; ++c)
+    for (int c2 = c; c2 < P; ++c2) {
+      const int pc = pair[c * P + c2];
+      for (int t = threadIdx.x; t < NP * NP; t += blockDim.x) {
+        double s = 0.0;
+        for (int k = 0; k < n; ++k) s += G1[k * NP + pc] * W2[k * NP * NP + t];
+        Vc[t] = s;
+      }
+      __syncthreads();
+      for (int t = threadIdx.x; t < P2 * P2; t += blockDim.x) {
+        int rp = t / P2, cp = t % P2;
+        int a = rp % P, b = rp / P, a2 = cp % P, b2 = cp / P;
+        double val = Vc[pair[b * P + b2] * NP + pair[a * P + a2]];
+        if (mode == 0) {
+          val += 0.5 * (Kel[0 * P2 + a * P + a2] * Mel[1 * P2 + b * P + b2] * Mel[2 * P2 + c * P + c2] +
+                        Mel[0 * P2 + a * P + a2] * Kel[1 * P2 + b * P + b2] * Mel[2 * P2 + c * P + c2] +
+                        Mel[0 * P2 + a * P + a2] * Mel[1 * P2 + b * P + b2] * Kel[2 * P2 + c * P + c2]);
+        }
+        int row = rp + P2 * c, col = cp + P2 * c2;
+        out[(int64_t)row * nloc + col] = cast_out<T>(dm[row] * val * dm[col]);
+        if (c2 != c) {
+          int row2 = rp + P2 * c2, col2 = cp + P2 * c;
+          out[(int64_t)row2 * nloc + col2] = cast_out<T>(dm[row2] * val * dm[col2]);
+        }
+      }
+      __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Enrichment coupling, per T-cell (a cell where some N^E is nonzero):
+//   part[slot][l][nu_local] = sum_q W v N_l(q) N^E_nu(q)
+//   hee_part[slot][mu_local][nu_local] = sum_q W v N^E_mu N^E_nu
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads)
+k_coupling_partials(const DevData d, const double *__restrict__ vq, double *__restrict__ part,
+                    double *__restrict__ hee_part) {
+  extern __shared__ double sm[];
+  const Geom &g = d.g;
+  const int slot = blockIdx.x;
+  const int64_t cell = d.tcell[slot];
+  const bool enr = d.is_enr[cell] != 0;
+  const int n = enr ? g.qe : g.qc, n3 = n * n * n, P = g.P, nloc = g.nloc;
+  const double *tab = d.tab;
+  const int toB = enr ? d.to.Be : d.to.Bc, tow = enr ? d.to.wqe : d.to.wqc;
+  double *Bt = sm;             // n*P
+  double *wv = Bt + n * P;     // n3
+  double *f = wv + n3;         // n3
+  double *t1 = f + n3;         // n*n*P
+  double *t2 = t1 + n * n * P; // n*P*P
+  double *nod = t2 + n * P * P;  // nloc
+  for (int t = threadIdx.x; t < n * P; t += blockDim.x) Bt[t] = tab[toB + t];
+  const int64_t q0 = d.q_off[cell];
+  const double jac = 0.125 * g.h[0] * g.h[1] * g.h[2];
+  for (int q = threadIdx.x; q < n3; q += blockDim.x) {
+    int i = q % n, j = (q / n) % n, k = q / (n * n);
+    wv[q] = jac * tab[tow + i] * tab[tow + j] * tab[tow + k] * vq[q0 + q];
+  }
+  __syncthreads();
+  const int k0 = d.tnu_off[slot], k1 = d.tnu_off[slot + 1], nnu = k1 - k0;
+  const double *NEs = d.NE + d.tne_off[slot];
+  double *ps = part + d.tpart_off[slot];
+  double *hs = hee_part + d.thee_off[slot];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int kk = 0; kk < nnu; ++kk) {
+    const double *ne = NEs + (int64_t)kk * n3;
+    for (int q = threadIdx.x; q < n3; q += blockDim.x) f[q] = wv[q] * ne[q];
+    __syncthreads();
+    apply_axis(f, t1, Bt, P, true, n, n, n, 0, P, 1);     // [k][j][a]
+    __syncthreads();
+    apply_axis(t1, t2, Bt, P, true, P, n, n, 1, P, 1);    // [k][b][a]
+    __syncthreads();
+    apply_axis(t2, nod, Bt, P, true, P, P, n, 2, P, 1);   // [c][b][a]
+    // H^ee partial row kk: one wave per mu
+    for (int mm = wid; mm < nnu; mm += nw) {
+      const double *nm = NEs + (int64_t)mm * n3;
+      double s = 0.0;
+      for (int q = lane; q < n3; q += 64) s += f[q] * nm[q];
+      s = wave_sum(s);
+      if (lane == 0) hs[kk * nnu + mm] = s;
+    }
+    __syncthreads();
+    for (int l = threadIdx.x; l < nloc; l += blockDim.x) ps[(int64_t)l * nnu + kk] = nod[l];
+    __syncthreads();
+  }
+}
+
+// G[r][kappa] = D^-1/2_r sum_nu (Kce[r][nu] + sum_cells part) S[nu][kappa]  (Hbar^ce rows)
+__global__ void __launch_bounds__(64)
+k_coupling_gather(const DevData d, const double *__restrict__ part, int kinetic, double *__restrict__ G) {
+  extern __shared__ double sm[];
+  const int ne = d.ne, nk = d.nk;
+  double *Ss = sm;                          // ne*nk
+  double *acc = Ss + ne * nk;               // 64*ne
+  for (int t = threadIdx.x; t < ne * nk; t += blockDim.x) Ss[t] = d.S[t];
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (r >= d.nr) return;
+  double *a = acc + threadIdx.x * ne;
+  for (int v = 0; v < ne; ++v) a[v] = kinetic ? d.Kce[r * ne + v] : 0.0;
+  const int cnt = d.urow_cnt[r];
+  for (int k = 0; k < cnt; ++k) {
+    int pr = d.urow_pair[r * 8 + k];
+    int slot = pr >> 8, l = pr & 255;
+    int k0 = d.tnu_off[slot], nnu = d.tnu_off[slot + 1] - k0;
+    const double *ps = part + d.tpart_off[slot] + (int64_t)l * nnu;
+    for (int kk = 0; kk < nnu; ++kk) a[d.tnu[k0 + kk]] += ps[kk];
+  }
+  const double dm = d.Dm12[d.urow_node[r]];
+  for (int kp = 0; kp < nk; ++kp) {
+    double s = 0.0;
+    for (int v = 0; v < ne; ++v) s += a[v] * Ss[v * nk + kp];
+    G[r * nk + kp] = dm * s;
+  }
+}
+
+// H^ee = Kee + sum over T-cells of the partials (fixed slot order)
+__global__ void k_hee_sum(const DevData d, const double *__restrict__ hee_part, int kinetic, double *__restrict__ Hraw) {
+  const int ne = d.ne;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ne * ne) return;
+  const int mu = t / ne, nu = t % ne;
+  double s = kinetic ? d.Kee[t] : 0.0;
+  for (int slot = 0; slot < d.nt; ++slot) {
+    int i = d.tpos[(int64_t)slot * ne + mu], j = d.tpos[(int64_t)slot * ne + nu];
+    if (i >= 0 && j >= 0) {
+      int nnu = d.tnu_off[slot + 1] - d.tnu_off[slot];
+      s += hee_part[d.thee_off[slot] + i * nnu + j];
+    }
+  }
+  Hraw[t] = s;
+}
+
+// Hbar^ee = S^T H^ee S
+__global__ void k_hee_loewdin(const DevData d, const double *__restrict__ Hraw, double *__restrict__ Hbar) {
+  const int ne = d.ne, nk = d.nk;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nk * nk) return;
+  const int a = t / nk, b = t % nk;
+  double s = 0.0;
+  for (int mu = 0; mu < ne; ++mu) {
+    double sm = d.S[mu * nk + a];
+    if (sm == 0.0) continue;
+    double inner = 0.0;
+    for (int nu = 0; nu < ne; ++nu) inner += Hraw[mu * ne + nu] * d.S[nu * nk + b];
+    s += sm * inner;
+  }
+  Hbar[t] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Density rho(q) = sum_a f_a |psi_a(q)|^2, psi = sum_i D_i^-1/2 X_i N_i + sum_nu psiE_nu N^E_nu.
+// One workgroup per cell of one class; columns in passes of NCC complex orbitals.
+// ---------------------------------------------------------------------------
+template <int NCC, int MAXS>
+__global__ void __launch_bounds__(kThreads)
+k_density(const DevData d, const int *__restrict__ cell_list, int n, const double *__restrict__ X, int ncol,
+          int64_t ldr, const double *__restrict__ psiE, double *__restrict__ rho) {
+  extern __shared__ double sm[];
+  constexpr int F = 2 * NCC;
+  const Geom &g = d.g;
+  const int P = g.P, nloc = g.nloc, n3 = n * n * n;
+  const bool enr = (n == g.qe);
+  const double *tab = d.tab;
+  double *Bt = sm;                    // n*P
+  double *dm = Bt + n * P;            // nloc
+  double *u = dm + nloc;              // nloc*F
+  double *t1 = u + nloc * F;          // P*P*n*F
+  double *t2 = t1 + P * P * n * F;    // P*n*n*F
+  double *occ = t2 + P * n * n * F;   // ncol
+  const int64_t cell = cell_list[blockIdx.x];
+  int e[3];
+  cell_ijk(g, cell, e);
+  const int toB = enr ? d.to.Be : d.to.Bc;
+  for (int t = threadIdx.x; t < n * P; t += blockDim.x) Bt[t] = tab[toB + t];
+  for (int t = threadIdx.x; t < nloc; t += blockDim.x) dm[t] = d.Dm12[local_node(g, e, t)];
+  for (int t = threadIdx.x; t < ncol; t += blockDim.x) occ[t] = d.occ[t];
+  const int slot = d.tslot_of_cell[cell];
+  const int k0 = slot >= 0 ? d.tnu_off[slot] : 0, nnu = slot >= 0 ? d.tnu_off[slot + 1] - k0 : 0;
+  const double *NEs = slot >= 0 ? d.NE + d.tne_off[slot] : nullptr;
+  double acc[MAXS];
+#pragma unroll
+  for (int s = 0; s < MAXS; ++s) acc[s] = 0.0;
+  const int ncolr = 2 * ncol;
+  __syncthreads();
+  for (int c0 = 0; c0 < ncol; c0 += NCC) {
+    for (int t = threadIdx.x; t < nloc * F; t += blockDim.x) {
+      int l = t / F, f = t % F;
+      int col = 2 * c0 + f;
+      u[t] = col < ncolr ? dm[l] * X[local_node(g, e, l) * ldr + col] : 0.0;
+    }
+    __syncthreads();
+    apply_axis(u, t1, Bt, P, false, P, P, P, 0, n, F);      // [c][b][i][f]
+    __syncthreads();
+    apply_axis(t1, t2, Bt, P, false, n, P, P, 1, n, F);     // [c][j][i][f]
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < MAXS; ++s) {
+      int q = threadIdx.x + s * kThreads;
+      if (q < n3) {
+        int ji = q % (n * n), k = q / (n * n);
+        double val[F];
+#pragma unroll
+        for (int f = 0; f < F; ++f) val[f] = 0.0;
+        for (int c = 0; c < P; ++c) {
+          double bk = Bt[k * P + c];
+#pragma unroll
+          for (int f = 0; f < F; ++f) val[f] += bk * t2[(c * n * n + ji) * F + f];
+        }
+        for (int kk = 0; kk < nnu; ++kk) {
+          double nev = NEs[(int64_t)kk * n3 + q];
+          const double *pe = psiE + (int64_t)d.tnu[k0 + kk] * ncolr + 2 * c0;
+#pragma unroll
+          for (int f = 0; f < F; ++f)
+            if (2 * c0 + f < ncolr) val[f] += nev * pe[f];
+        }
+#pragma unroll
+        for (int cc = 0; cc < NCC; ++cc)
+          if (c0 + cc < ncol) acc[s] += occ[c0 + cc] * (val[2 * cc] * val[2 * cc] + val[2 * cc + 1] * val[2 * cc + 1]);
+      }
+    }
+    __syncthreads();
+  }
+  const int64_t q0 = d.q_off[cell];
+#pragma unroll
+  for (int s = 0; s < MAXS; ++s) {
+    int q = threadIdx.x + s * kThreads;
+    if (q < n3) rho[q0 + q] = acc[s];
+  }
+}
+
+// psiE[nu][col] = sum_kappa S[nu][kappa] X[n_nodes + kappa][col]
+__global__ void k_psiE(const DevData d, const double *__restrict__ X, int ncolr, int64_t ldr, double *__restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= d.ne * ncolr) return;
+  const int nu = t / ncolr, col = t % ncolr;
+  double s = 0.0;
+  for (int k = 0; k < d.nk; ++k) s += d.S[nu * d.nk + k] * X[(d.g.n_nodes + k) * ldr + col];
+  out[t] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Poisson right-hand side d_i = int rho N_i, one colour of cells per launch
+// (cells of one colour share no node, so the scatter needs no atomics).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kThreads)
+k_poisson_rhs(const DevData d, const int *__restrict__ cell_list, const double *__restrict__ rho, double *__restrict__ dvec) {
+  extern __shared__ double sm[];
+  const Geom &g = d.g;
+  const int64_t cell = cell_list[blockIdx.x];
+  const bool enr = d.is_enr[cell] != 0;
+  const int n = enr ? g.qe : g.qc, n3 = n * n * n, P = g.P, nloc = g.nloc;
+  const double *tab = d.tab;
+  const int toB = enr ? d.to.Be : d.to.Bc, tow = enr ? d.to.wqe : d.to.wqc;
+  double *Bt = sm, *f = Bt + n * P, *t1 = f + n3, *t2 = t1 + n * n * P, *nod = t2 + n * P * P;
+  for (int t = threadIdx.x; t < n * P; t += blockDim.x) Bt[t] = tab[toB + t];
+  const int64_t q0 = d.q_off[cell];
+  const double jac = 0.125 * g.h[0] * g.h[1] * g.h[2];
+  for (int q = threadIdx.x; q < n3; q += blockDim.x) {
+    int i = q % n, j = (q / n) % n, k = q / (n * n);
+    f[q] = jac * tab[tow + i] * tab[tow + j] * tab[tow + k] * rho[q0 + q];
+  }
+  __syncthreads();
+  apply_axis(f, t1, Bt, P, true, n, n, n, 0, P, 1);
+  __syncthreads();
+  apply_axis(t1, t2, Bt, P, true, P, n, n, 1, P, 1);
+  __syncthreads();
+  apply_axis(t2, nod, Bt, P, true, P, P, n, 2, P, 1);
+  __syncthreads();
+  int e[3];
+  cell_ijk(g, cell, e);
+  for (int l = threadIdx.x; l < nloc; l += blockDim.x) dvec[local_node(g, e, l)] += nod[l];
+}
+
+// rhs = 4 pi d - lift on interior nodes, 0 on the boundary
+__global__ void k_rhs_finish(const DevData d, const double *__restrict__ dvec, double *__restrict__ rhs) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.g.n_nodes) return;
+  rhs[i] = d.Dm12[i] != 0.0 ? 4.0 * 3.14159265358979323846 * dvec[i] - d.lift[i] : 0.0;
+}
+
+// out = A_axis in (banded 1-D operator, bandwidth p), over all nodes
+__global__ void k_axis_band(const DevData d, const double *__restrict__ A, int axis, const double *__restrict__ in,
+                            double *__restrict__ out) {
+  const Geom &g = d.g;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.n_nodes) return;
+  int64_t gg[3] = {i % g.nn[0], (i / g.nn[0]) % g.nn[1], i / (g.nn[0] * g.nn[1])};
+  const int64_t n = g.nn[axis], gi = gg[axis];
+  const int64_t stride = axis == 0 ? 1 : (axis == 1 ? g.nn[0] : g.nn[0] * g.nn[1]);
+  const int64_t lo = gi - g.p < 0 ? 0 : gi - g.p, hi = gi + g.p > n - 1 ? n - 1 : gi + g.p;
+  double s = 0.0;
+  for (int64_t k = lo; k <= hi; ++k) s += A[gi * n + k] * in[i + (k - gi) * stride];
+  out[i] = s;
+}
+
+// y (+)= x on interior nodes; boundary of y zeroed
+__global__ void k_interior_acc(const DevData d, const double *__restrict__ x, double *__restrict__ y, int accumulate) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.g.n_nodes) return;
+  double v = d.Dm12[i] != 0.0 ? x[i] : 0.0;
+  y[i] = accumulate ? y[i] + v : v;
+}
+
+// fast diagonalisation transform along one axis on interior nodes:
+// fwd: out_i = sum_a V[a][i] in_a ; back: out_a = sum_i V[a][i] in_i (V: m x m, m = nn - 2)
+__global__ void k_fdm_axis(const DevData d, const double *__restrict__ V, int axis, int back,
+                           const double *__restrict__ in, double *__restrict__ out) {
+  const Geom &g = d.g;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.n_nodes) return;
+  int64_t gg[3] = {i % g.nn[0], (i / g.nn[0]) % g.nn[1], i / (g.nn[0] * g.nn[1])};
+  if (d.Dm12[i] == 0.0) { out[i] = 0.0; return; }
+  const int64_t m = g.nn[axis] - 2, o = gg[axis] - 1;
+  const int64_t stride = axis == 0 ? 1 : (axis == 1 ? g.nn[0] : g.nn[0] * g.nn[1]);
+  const double *base = in + i - gg[axis] * stride;   // node with coordinate 0 along axis
+  double s = 0.0;
+  if (back) {
+    for (int64_t k = 0; k < m; ++k) s += V[o * m + k] * base[(k + 1) * stride];
+  } else {
+    for (int64_t k = 0; k < m; ++k) s += V[k * m + o] * base[(k + 1) * stride];
+  }
+  out[i] = s;
+}
+
+__global__ void k_fdm_scale(const DevData d, double *__restrict__ t) {
+  const Geom &g = d.g;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.n_nodes) return;
+  if (d.Dm12[i] == 0.0) { t[i] = 0.0; return; }
+  int64_t gg[3] = {i % g.nn[0], (i / g.nn[0]) % g.nn[1], i / (g.nn[0] * g.nn[1])};
+  t[i] /= d.fdmL[0][gg[0] - 1] + d.fdmL[1][gg[1] - 1] + d.fdmL[2][gg[2] - 1];
+}
+
+__global__ void k_add_boundary(const DevData d, double *__restrict__ phi) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.g.n_nodes) return;
+  if (d.Dm12[i] == 0.0) phi[i] = d.gbnd[i];
+}
+
+// deterministic partial dot products
+__global__ void __launch_bounds__(kThreads)
+k_dot(const double *__restrict__ x, const double *__restrict__ y, int64_t n, double *__restrict__ part) {
+  __shared__ double red[16];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    s += x[i] * y[i];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// out[v] = sum_b part[b * nval + v] in block order
+__global__ void k_reduce(const double *__restrict__ part, int nblk, int nval, double *__restrict__ out) {
+  __shared__ double red[16];
+  const int v = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += blockDim.x) s += part[(int64_t)b * nval + v];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) out[v] = s;
+}
+
+// dipole partials: one block per cell, part[cell][3]
+__global__ void __launch_bounds__(kThreads)
+k_dipole(const DevData d, const double *__restrict__ rho, double *__restrict__ part) {
+  __shared__ double red[16];
+  const Geom &g = d.g;
+  const int64_t cell = blockIdx.x;
+  const bool enr = d.is_enr[cell] != 0;
+  const int n = enr ? g.qe : g.qc, n3 = n * n * n;
+  const double *tab = d.tab;
+  const int tox = enr ? d.to.xqe : d.to.xqc, tow = enr ? d.to.wqe : d.to.wqc;
+  int e[3];
+  cell_ijk(g, cell, e);
+  const int64_t q0 = d.q_off[cell];
+  const double jac = 0.125 * g.h[0] * g.h[1] * g.h[2];
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int q = threadIdx.x; q < n3; q += blockDim.x) {
+    int i = q % n, j = (q / n) % n, k = q / (n * n);
+    double w = jac * tab[tow + i] * tab[tow + j] * tab[tow + k] * rho[q0 + q];
+    s[0] += w * (g.lo[0] + e[0] * g.h[0] + (tab[tox + i] + 1.0) * 0.5 * g.h[0]);
+    s[1] += w * (g.lo[1] + e[1] * g.h[1] + (tab[tox + j] + 1.0) * 0.5 * g.h[1]);
+    s[2] += w * (g.lo[2] + e[2] * g.h[2] + (tab[tox + k] + 1.0) * 0.5 * g.h[2]);
+  }
+  for (int dd = 0; dd < 3; ++dd) {
+    double t = block_sum(s[dd], red);
+    if (threadIdx.x == 0) part[cell * 3 + dd] = t;
+  }
+}
+
+__global__ void k_zero(double *p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+__global__ void k_axpby(const double *x, const double *y, double a, double b, double *out, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a * x[i] + b * y[i];
+}
+
+__global__ void k_copy_rows(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t nrows, int ncolr) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nrows * ncolr) return;
+  int64_t r = t / ncolr;
+  int c = (int)(t % ncolr);
+  dst[r * ldd + c] = src[r * lds + c];
+}
+
+inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+namespace k {
+
+void zero(double *p, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_zero, dim3(nblocks(n, 256)), dim3(256), 0, s, p, n);
+}
+
+void axpby(const double *x, const double *y, double a, double b, double *out, int64_t n, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_axpby, dim3(nblocks(n, 256)), dim3(256), 0, s, x, y, a, b, out, n);
+}
+
+void copy_rows(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t nrows, int ncolr, hipStream_t s) {
+  if (nrows * ncolr > 0)
+    hipLaunchKernelGGL(k_copy_rows, dim3(nblocks(nrows * ncolr, 256)), dim3(256), 0, s, src, lds, dst, ldd, nrows, ncolr);
+}
+
+static size_t rebuild_lds(const Geom &g, int n) {
+  const int P = g.P, NP = P * (P + 1) / 2;
+  size_t dbl = (size_t)n * P + n * NP + 6 * P * P + g.nloc + n * n * n + n * n * NP + n * NP * NP + NP * NP;
+  size_t need_interp = (size_t)g.nloc + P * P * n;   // u0 + t1 inside U
+  if (need_interp > (size_t)n * n * NP) dbl += need_interp - (size_t)n * n * NP;
+  return dbl * sizeof(double) + P * P * sizeof(int) + 64;
+}
+
+void rebuild_cells(const DevData &d, int mode, const double *rho, const double *phi, double efield, int fdir, int xc,
+                   void *cells, int dtype, double *vq, hipStream_t s) {
+  for (int cls = 0; cls < 2; ++cls) {
+    int nc = cls ? d.n_enr : d.n_ord;
+    if (nc == 0) continue;
+    int n = cls ? d.g.qe : d.g.qc;
+    const int *list = cls ? d.cells_enr : d.cells_ord;
+    size_t lds = rebuild_lds(d.g, n);
+    if (dtype == 0)
+      hipLaunchKernelGGL(k_rebuild<double>, dim3(nc), dim3(kThreads), lds, s, d, list, n, mode, rho, phi, efield, fdir,
+                         xc, (double *)cells, vq);
+    else if (dtype == 1)
+      hipLaunchKernelGGL(k_rebuild<float>, dim3(nc), dim3(kThreads), lds, s, d, list, n, mode, rho, phi, efield, fdir,
+                         xc, (float *)cells, vq);
+    else
+      hipLaunchKernelGGL(k_rebuild<uint16_t>, dim3(nc), dim3(kThreads), lds, s, d, list, n, mode, rho, phi, efield,
+                         fdir, xc, (uint16_t *)cells, vq);
+  }
+}
+
+void coupling_partials(const DevData &d, const double *vq, double *part, double *hee_part, hipStream_t s) {
+  if (d.nt == 0) return;
+  const int n = d.g.qe > d.g.qc ? d.g.qe : d.g.qc, P = d.g.P;
+  size_t lds = ((size_t)n * P + 2 * n * n * n + n * n * P + n * P * P + d.g.nloc) * sizeof(double);
+  hipLaunchKernelGGL(k_coupling_partials, dim3(d.nt), dim3(kThreads), lds, s, d, vq, part, hee_part);
+}
+
+void coupling_gather(const DevData &d, const double *part, int kinetic, double *G, hipStream_t s) {
+  if (d.nr == 0 || d.nk == 0) return;
+  size_t lds = ((size_t)d.ne * d.nk + 64 * d.ne) * sizeof(double);
+  hipLaunchKernelGGL(k_coupling_gather, dim3(nblocks(d.nr, 64)), dim3(64), lds, s, d, part, kinetic, G);
+}
+
+void hee_reduce(const DevData &d, const double *hee_part, int kinetic, double *Hraw, double *Hbar, hipStream_t s) {
+  if (d.ne == 0) return;
+  hipLaunchKernelGGL(k_hee_sum, dim3(nblocks(d.ne * d.ne, 64)), dim3(64), 0, s, d, hee_part, kinetic, Hraw);
+  hipLaunchKernelGGL(k_hee_loewdin, dim3(nblocks(d.nk * d.nk, 64)), dim3(64), 0, s, d, Hraw, Hbar);
+}
+
+void psiE(const DevData &d, const double *X, int ncolr, int64_t ldr, double *out, hipStream_t s) {
+  if (d.ne == 0) return;
+  hipLaunchKernelGGL(k_psiE, dim3(nblocks((int64_t)d.ne * ncolr, 128)), dim3(128), 0, s, d, X, ncolr, ldr, out);
+}
+
+void density(const DevData &d, const double *X, int ncol, int64_t ldr, const double *psiE, double *rho, hipStream_t s) {
+  constexpr int NCC = 4, F = 2 * NCC;
+  for (int cls = 0; cls < 2; ++cls) {
+    int nc = cls ? d.n_enr : d.n_ord;
+    if (nc == 0) continue;
+    int n = cls ? d.g.qe : d.g.qc, P = d.g.P;
+    const int *list = cls ? d.cells_enr : d.cells_ord;
+    size_t lds = ((size_t)n * P + d.g.nloc + (size_t)d.g.nloc * F + (size_t)P * P * n * F + (size_t)P * n * n * F + ncol) *
+                 sizeof(double);
+    int n3 = n * n * n;
+    if (n3 <= 256)
+      hipLaunchKernelGGL((k_density<NCC, 1>), dim3(nc), dim3(kThreads), lds, s, d, list, n, X, ncol, ldr, psiE, rho);
+    else if (n3 <= 512)
+      hipLaunchKernelGGL((k_density<NCC, 2>), dim3(nc), dim3(kThreads), lds, s, d, list, n, X, ncol, ldr, psiE, rho);
+    else if (n3 <= 1024)
+      hipLaunchKernelGGL((k_density<NCC, 4>), dim3(nc), dim3(kThreads), lds, s, d, list, n, X, ncol, ldr, psiE, rho);
+    else if (n3 <= 2048)
+      hipLaunchKernelGGL((k_density<NCC, 8>), dim3(nc), dim3(kThreads), lds, s, d, list, n, X, ncol, ldr, psiE, rho);
+    else
+      hipLaunchKernelGGL((k_density<NCC, 16>), dim3(nc), dim3(kThreads), lds, s, d, list, n, X, ncol, ldr, psiE, rho);
+  }
+}
+
+void poisson_rhs(const DevData &d, const double *rho, double *dvec, double *rhs, hipStream_t s) {
+  zero(dvec, d.g.n_nodes, s);
+  const int n = d.g.qe > d.g.qc ? d.g.qe : d.g.qc, P = d.g.P;
+  size_t lds = ((size_t)n * P + (size_t)n * n * n + (size_t)n * n * P + (size_t)n * P * P + d.g.nloc) * sizeof(double);
+  for (int c = 0; c < 8; ++c) {
+    int cnt = d.colour_off[c + 1] - d.colour_off[c];
+    if (cnt == 0) continue;
+    hipLaunchKernelGGL(k_poisson_rhs, dim3(cnt), dim3(kThreads), lds, s, d, d.colour_cells + d.colour_off[c], rho, dvec);
+  }
+  hipLaunchKernelGGL(k_rhs_finish, dim3(nblocks(d.g.n_nodes, 256)), dim3(256), 0, s, d, dvec, rhs);
+}
+
+// y = K_II x for x with zero boundary: K = K1 x M1 x M1 + M1 x K1 x M1 + M1 x M1 x K1
+void stiffness_apply(const DevData &d, const double *x, double *y, double *t1, double *t2, hipStream_t s) {
+  const unsigned nb = nblocks(d.g.n_nodes, 256);
+  for (int term = 0; term < 3; ++term) {
+    hipLaunchKernelGGL(k_axis_band, dim3(nb), dim3(256), 0, s, d, term == 0 ? d.K1[0] : d.M1[0], 0, x, t1);
+    hipLaunchKernelGGL(k_axis_band, dim3(nb), dim3(256), 0, s, d, term == 1 ? d.K1[1] : d.M1[1], 1, t1, t2);
+    hipLaunchKernelGGL(k_axis_band, dim3(nb), dim3(256), 0, s, d, term == 2 ? d.K1[2] : d.M1[2], 2, t2, t1);
+    hipLaunchKernelGGL(k_interior_acc, dim3(nb), dim3(256), 0, s, d, t1, y, term > 0 ? 1 : 0);
+  }
+}
+
+// z = K_II^-1 r on interior nodes by fast diagonalisation
+void fdm_apply(const DevData &d, const double *r, double *z, double *t1, double *t2, hipStream_t s) {
+  const unsigned nb = nblocks(d.g.n_nodes, 256);
+  hipLaunchKernelGGL(k_fdm_axis, dim3(nb), dim3(256), 0, s, d, d.fdmV[0], 0, 0, r, t1);
+  hipLaunchKernelGGL(k_fdm_axis, dim3(nb), dim3(256), 0, s, d, d.fdmV[1], 1, 0, t1, t2);
+  hipLaunchKernelGGL(k_fdm_axis, dim3(nb), dim3(256), 0, s, d, d.fdmV[2], 2, 0, t2, t1);
+  hipLaunchKernelGGL(k_fdm_scale, dim3(nb), dim3(256), 0, s, d, t1);
+  hipLaunchKernelGGL(k_fdm_axis, dim3(nb), dim3(256), 0, s, d, d.fdmV[2], 2, 1, t1, t2);
+  hipLaunchKernelGGL(k_fdm_axis, dim3(nb), dim3(256), 0, s, d, d.fdmV[1], 1, 1, t2, t1);
+  hipLaunchKernelGGL(k_fdm_axis, dim3(nb), dim3(256), 0, s, d, d.fdmV[0], 0, 1, t1, z);
+}
+
+void set_boundary(const DevData &d, double *phi, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_boundary, dim3(nblocks(d.g.n_nodes, 256)), dim3(256), 0, s, d, phi);
+}
+
+int dot_partials(const double *x, const double *y, int64_t n, double *part, hipStream_t s) {
+  int nb = (int)std::min<int64_t>(1024, (n + 255) / 256);
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(k_dot, dim3(nb), dim3(kThreads), 0, s, x, y, n, part);
+  return nb;
+}
+
+void reduce_partials(const double *part, int nblk, int nval, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3(nval), dim3(256), 0, s, part, nblk, nval, out);
+}
+
+void dipole_partials(const DevData &d, const double *rho, double *part, int *nblk, hipStream_t s) {
+  int64_t nc = (int64_t)d.g.nc[0] * d.g.nc[1] * d.g.nc[2];
+  hipLaunchKernelGGL(k_dipole, dim3((unsigned)nc), dim3(kThreads), 0, s, d, rho, part);
+  *nblk = (int)nc;
+}
+
+}  // namespace k
+}  // namespace efe

@@ -1,0 +1,608 @@
+// HIP kernels of the Krylov part of the Magnus step:
+//   Hbar X  = sum_c P_c^T Hbar_c P_c X  (cell blocks on MFMA) + enrichment coupling
+//   Lanczos recurrence with full reorthogonalisation (Sec. 2.6, eq. (AdaptiveKrylov))
+//   exp(-i tau T_k) e_1 and the a-posteriori estimate (eq. (AdaptiveKrylovErr))
+//   Krylov combination beta0 Q_k u.
+// Orbital blocks are node-major with ncol interleaved complex columns.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+
+#include "common.cuh"
+
+namespace efe {
+
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Cell products Y[nodes_c] += Hbar_c X[nodes_c] for the cells of one colour
+// (no two cells of a colour share a node).  One workgroup (4 waves in a 2 x 2
+// grid) per (cell, column chunk); the nloc x nloc block is streamed through LDS
+// in K-chunks of 8 rows (Hbar_c is symmetric, so rows k of the row-major block
+// are the A-operand columns), the gathered X chunk is staged beside it, and the
+// 16x16x4 MFMA accumulates in registers.  Double-buffered LDS, one barrier per
+// chunk.
+// ---------------------------------------------------------------------------
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  typedef double C;
+  typedef v4d Acc;
+  static __device__ __forceinline__ Acc mma(C a, C b, Acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+  // output register r of a lane holds row lane/16 + 4 r, column lane%16
+  static __device__ __forceinline__ int row(int kr, int r) { return kr + 4 * r; }
+};
+template <> struct Mfma<float> {
+  typedef float C;
+  typedef v4f Acc;
+  static __device__ __forceinline__ Acc mma(C a, C b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  // output register r of a lane holds row 4 (lane/16) + r, column lane%16
+  static __device__ __forceinline__ int row(int kr, int r) { return 4 * kr + r; }
+};
+
+template <typename T, int MTW, int NTW>
+__global__ void __launch_bounds__(256)
+k_cell_apply(const DevData d, const int *__restrict__ cell_list, const T *__restrict__ cells,
+             const double *__restrict__ X, double *__restrict__ Y, int ncolr, int64_t ldr) {
+  typedef typename Mfma<T>::C C;
+  typedef typename Mfma<T>::Acc Acc;
+  constexpr int KC = 8;
+  constexpr int MS = MTW * 32 + 4;      // LDS row stride of the A chunk
+  constexpr int NCH = NTW * 32;         // columns per workgroup
+  constexpr int NS = NCH + 4;
+  constexpr int LA = (KC * MTW * 32 + 255) / 256;
+  constexpr int LB = (KC * NCH + 255) / 256;
+  __shared__ C As[2][KC][MS];
+  __shared__ C Bs[2][KC][NS];
+  __shared__ int64_t rowoff[MTW * 32];
+
+  const Geom &g = d.g;
+  const int nloc = g.nloc;
+  const int64_t cell = cell_list[blockIdx.x];
+  const int col0 = blockIdx.y * NCH;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  int e[3];
+  cell_ijk(g, cell, e);
+  for (int l = tid; l < MTW * 32; l += 256) rowoff[l] = l < nloc ? local_node(g, e, l) * ldr : 0;
+  // zero the padded rows of both A buffers once (loaders only write m < nloc)
+  for (int t = tid; t < 2 * KC * MS; t += 256) (&As[0][0][0])[t] = (C)0;
+  __syncthreads();
+
+  const T *A = cells + cell * (int64_t)nloc * nloc;
+  const int nkc = (nloc + KC - 1) / KC;
+  C ra[LA], rb[LB];
+  auto load_chunk = [&](int kc) {
+#pragma unroll
+    for (int s = 0; s < LA; ++s) {
+      int t = tid + s * 256;
+      int kk = t / nloc, m = t - kk * nloc;
+      int k = kc * KC + kk;
+      ra[s] = (kk < KC && k < nloc) ? (C)A[(int64_t)k * nloc + m] : (C)0;
+    }
+#pragma unroll
+    for (int s = 0; s < LB; ++s) {
+      int t = tid + s * 256;
+      int kk = t / NCH, n = t - kk * NCH;
+      int k = kc * KC + kk;
+      rb[s] = (kk < KC && k < nloc && col0 + n < ncolr) ? (C)X[rowoff[k] + col0 + n] : (C)0;
+    }
+  };
+  auto store_chunk = [&](int buf) {
+#pragma unroll
+    for (int s = 0; s < LA; ++s) {
+      int t = tid + s * 256;
+      int kk = t / nloc, m = t - kk * nloc;
+      if (kk < KC) As[buf][kk][m] = ra[s];
+    }
+#pragma unroll
+    for (int s = 0; s < LB; ++s) {
+      int t = tid + s * 256;
+      int kk = t / NCH, n = t - kk * NCH;
+      if (kk < KC) Bs[buf][kk][n] = rb[s];
+    }
+  };
+
+  Acc acc[MTW][NTW];
+#pragma unroll
+  for (int i = 0; i < MTW; ++i)
+#pragma unroll
+    for (int j = 0; j < NTW; ++j) acc[i][j] = Acc{0, 0, 0, 0};
+
+  load_chunk(0);
+  store_chunk(0);
+  __syncthreads();
+  const int kr = lane >> 4, cl = lane & 15;
+  for (int kc = 0; kc < nkc; ++kc) {
+    const int buf = kc & 1;
+    if (kc + 1 < nkc) load_chunk(kc + 1);
+#pragma unroll
+    for (int ks = 0; ks < KC / 4; ++ks) {
+      C a[MTW], b[NTW];
+#pragma unroll
+      for (int mt = 0; mt < MTW; ++mt) a[mt] = As[buf][ks * 4 + kr][(wm * MTW + mt) * 16 + cl];
+#pragma unroll
+      for (int nt = 0; nt < NTW; ++nt) b[nt] = Bs[buf][ks * 4 + kr][(wn * NTW + nt) * 16 + cl];
+#pragma unroll
+      for (int mt = 0; mt < MTW; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NTW; ++nt) acc[mt][nt] = Mfma<T>::mma(a[mt], b[nt], acc[mt][nt]);
+    }
+    if (kc + 1 < nkc) store_chunk(buf ^ 1);
+    __syncthreads();
+  }
+  // D layout of the 16x16 MFMA (differs between the f64 and f32 forms)
+#pragma unroll
+  for (int mt = 0; mt < MTW; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NTW; ++nt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int row = (wm * MTW + mt) * 16 + Mfma<T>::row(kr, r);
+        int col = col0 + (wn * NTW + nt) * 16 + cl;
+        if (row < nloc && col < ncolr) Y[rowoff[row] + col] += (double)acc[mt][nt][r];
+      }
+}
+
+// ---------------------------------------------------------------------------
+// Enrichment coupling: Y_C[r] += G[r] X_E ;  Y_E = G^T X_C[R] + Hbar^ee X_E
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_couple_c(const DevData d, const double *__restrict__ G, const double *__restrict__ X, double *__restrict__ Y,
+           int ncolr, int64_t ldr) {
+  extern __shared__ double xe[];     // nk * ncolr
+  const int nk = d.nk;
+  for (int t = threadIdx.x; t < nk * ncolr; t += blockDim.x) {
+    int k = t / ncolr, c = t % ncolr;
+    xe[t] = X[(d.g.n_nodes + k) * ldr + c];
+  }
+  __syncthreads();
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= d.nr * ncolr) return;
+  const int64_t r = t / ncolr;
+  const int c = (int)(t % ncolr);
+  const double *gr = G + r * nk;
+  double s = 0.0;
+  for (int k = 0; k < nk; ++k) s += gr[k] * xe[k * ncolr + c];
+  Y[d.urow_node[r] * ldr + c] += s;
+}
+
+constexpr int kRowChunk = 32;
+__global__ void __launch_bounds__(256)
+k_couple_e_partial(const DevData d, const double *__restrict__ G, const double *__restrict__ X, int ncolr,
+                   int64_t ldr, int64_t rows_per_blk, double *__restrict__ part) {
+  extern __shared__ double sm[];
+  const int nk = d.nk;
+  double *gs = sm;                       // kRowChunk * nk
+  double *xs = gs + kRowChunk * nk;      // kRowChunk * ncolr
+  const int nout = nk * ncolr;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
+  const int64_t r1 = r0 + rows_per_blk < d.nr ? r0 + rows_per_blk : d.nr;
+  for (int o0 = 0; o0 < nout; o0 += 256 * 4) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t rc = r0; rc < r1; rc += kRowChunk) {
+      const int nrow = (int)(r1 - rc < kRowChunk ? r1 - rc : kRowChunk);
+      __syncthreads();
+      for (int t = threadIdx.x; t < nrow * nk; t += blockDim.x) gs[t] = G[rc * nk + t];
+      for (int t = threadIdx.x; t < nrow * ncolr; t += blockDim.x) {
+        int rr = t / ncolr, c = t % ncolr;
+        xs[t] = X[d.urow_node[rc + rr] * ldr + c];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        int o = o0 + threadIdx.x + s * 256;
+        if (o < nout) {
+          int k = o / ncolr, c = o % ncolr;
+          double a = 0.0;
+          for (int rr = 0; rr < nrow; ++rr) a += gs[rr * nk + k] * xs[rr * ncolr + c];
+          acc[s] += a;
+        }
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      int o = o0 + threadIdx.x + s * 256;
+      if (o < nout) part[(int64_t)blockIdx.x * nout + o] = acc[s];
+    }
+  }
+}
+
+__global__ void k_couple_e_final(const DevData d, const double *__restrict__ part, int nblk,
+                                 const double *__restrict__ Hee, const double *__restrict__ X, double *__restrict__ Y,
+                                 int ncolr, int64_t ldr) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nk = d.nk, nout = nk * ncolr;
+  if (o >= nout) return;
+  const int k = o / ncolr, c = o % ncolr;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * nout + o];
+  for (int kp = 0; kp < nk; ++kp) s += Hee[k * nk + kp] * X[(d.g.n_nodes + kp) * ldr + c];
+  Y[(d.g.n_nodes + k) * ldr + c] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Lanczos vector kernels.  Blocks are n_rows x ncol complex, packed (ld = ncol).
+// ---------------------------------------------------------------------------
+constexpr int LCH = 8;
+
+// part[blk][l][c][re, im] = sum_r conj(Q_l[r][c]) w[r][c], l < nq
+__global__ void __launch_bounds__(256)
+k_multidot(const double *__restrict__ Q, int64_t qstride, int nq, const double *__restrict__ w, int64_t nrows,
+           int ncol, const int *__restrict__ active, double *__restrict__ part) {
+  extern __shared__ double red[];    // R * LCH * ncol * 2
+  const int R = blockDim.x / ncol;
+  const int c = threadIdx.x % ncol, r0 = threadIdx.x / ncol;
+  const bool on = r0 < R && (active == nullptr || active[c] != 0);
+  for (int l0 = 0; l0 < nq; l0 += LCH) {
+    double are[LCH], aim[LCH];
+#pragma unroll
+    for (int l = 0; l < LCH; ++l) are[l] = aim[l] = 0.0;
+    if (on) {
+      for (int64_t r = (int64_t)blockIdx.x * R + r0; r < nrows; r += (int64_t)gridDim.x * R) {
+        const int64_t o = (r * ncol + c) * 2;
+        const double wr = w[o], wi = w[o + 1];
+#pragma unroll
+        for (int l = 0; l < LCH; ++l)
+          if (l0 + l < nq) {
+            const double *q = Q + (int64_t)(l0 + l) * qstride + o;
+            const double qr = q[0], qi = q[1];
+            are[l] += qr * wr + qi * wi;
+            aim[l] += qr * wi - qi * wr;
+          }
+      }
+    }
+    __syncthreads();
+    if (r0 < R) {
+#pragma unroll
+      for (int l = 0; l < LCH; ++l) {
+        red[((r0 * LCH + l) * ncol + c) * 2] = are[l];
+        red[((r0 * LCH + l) * ncol + c) * 2 + 1] = aim[l];
+      }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < LCH * ncol * 2; t += blockDim.x) {
+      int l = t / (ncol * 2);
+      if (l0 + l >= nq) continue;
+      double s = 0.0;
+      for (int rr = 0; rr < R; ++rr) s += red[rr * LCH * ncol * 2 + t];
+      part[((int64_t)blockIdx.x * nq + l0) * ncol * 2 + t] = s;
+    }
+  }
+}
+
+// w[r][c] -= sum_l h[l][c] Q_l[r][c]   (complex), active columns only
+__global__ void __launch_bounds__(256)
+k_multi_update(const double *__restrict__ Q, int64_t qstride, int nq, const double *__restrict__ h,
+               double *__restrict__ w, int64_t nrows, int ncol, const int *__restrict__ active) {
+  extern __shared__ double hs[];     // nq * ncol * 2
+  for (int t = threadIdx.x; t < nq * ncol * 2; t += blockDim.x) hs[t] = h[t];
+  __syncthreads();
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nrows * ncol) return;
+  const int c = (int)(t % ncol);
+  if (active && !active[c]) return;
+  double wr = w[2 * t], wi = w[2 * t + 1];
+  for (int l = 0; l < nq; ++l) {
+    const double qr = Q[(int64_t)l * qstride + 2 * t], qi = Q[(int64_t)l * qstride + 2 * t + 1];
+    const double hr = hs[(l * ncol + c) * 2], hi = hs[(l * ncol + c) * 2 + 1];
+    wr -= hr * qr - hi * qi;
+    wi -= hr * qi + hi * qr;
+  }
+  w[2 * t] = wr;
+  w[2 * t + 1] = wi;
+}
+
+// w -= alpha q + beta qm1 (real coefficients per column)
+__global__ void k_three_term(double *__restrict__ w, const double *__restrict__ q, const double *__restrict__ qm1,
+                             const double *__restrict__ alpha, const double *__restrict__ beta, int64_t nrows,
+                             int ncol, const int *__restrict__ active) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nrows * ncol) return;
+  const int c = (int)(t % ncol);
+  if (!active[c]) return;
+  const double a = alpha[c];
+  double wr = w[2 * t] - a * q[2 * t], wi = w[2 * t + 1] - a * q[2 * t + 1];
+  if (qm1) {
+    const double b = beta[c];
+    wr -= b * qm1[2 * t];
+    wi -= b * qm1[2 * t + 1];
+  }
+  w[2 * t] = wr;
+  w[2 * t + 1] = wi;
+}
+
+// q = w * inv[c]
+__global__ void k_scale_cols(const double *__restrict__ w, double *__restrict__ q, const double *__restrict__ nrm,
+                             int64_t nrows, int ncol, const int *__restrict__ active) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nrows * ncol) return;
+  const int c = (int)(t % ncol);
+  if (active && !active[c]) return;
+  const double s = nrm[c] > 0.0 ? 1.0 / nrm[c] : 0.0;
+  q[2 * t] = w[2 * t] * s;
+  q[2 * t + 1] = w[2 * t + 1] * s;
+}
+
+// ---------------------------------------------------------------------------
+// Per column: eigendecomposition of the j x j symmetric tridiagonal T_j by the
+// implicit QL method with Wilkinson-type shifts (Bowdler, Martin, Reinsch and
+// Wilkinson, 1968), u = V exp(-i tau Lambda) V^T e_1, the estimate
+// |tau| beta_j beta0 |u_j| and the stopping decision.  One wavefront per
+// column; lane k owns row k of V (j <= 64).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64)
+k_tridiag_exp(const double *__restrict__ alpha, const double *__restrict__ beta, int j, int ncol, int kmax,
+              double tau, const double *__restrict__ beta0, const int *__restrict__ kforce, double tol,
+              int *__restrict__ active, int *__restrict__ kused, double *__restrict__ err, double *__restrict__ ubuf) {
+  __shared__ double Z[64][65];
+  __shared__ double dd[64], ee[64];
+  const int c = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (!active[c]) return;
+  const int n = j;
+  for (int k = 0; k < n; ++k) Z[lane][k] = (lane == k) ? 1.0 : 0.0;
+  if (lane < n) {
+    dd[lane] = alpha[(int64_t)lane * ncol + c];
+    ee[lane] = lane < n - 1 ? beta[(int64_t)lane * ncol + c] : 0.0;
+  }
+  __syncthreads();
+  bool fail = false;
+  for (int l = 0; l < n && !fail; ++l) {
+    int iter = 0;
+    for (;;) {
+      int m = l;
+      for (; m < n - 1; ++m) {
+        double s = fabs(dd[m]) + fabs(dd[m + 1]);
+        if (fabs(ee[m]) <= DBL_EPSILON * s) break;
+      }
+      if (m == l) break;
+      if (++iter > 60) { fail = true; break; }
+      double g = (dd[l + 1] - dd[l]) / (2.0 * ee[l]);
+      double r = hypot(g, 1.0);
+      g = dd[m] - dd[l] + ee[l] / (g + (g >= 0.0 ? fabs(r) : -fabs(r)));
+      double s = 1.0, co = 1.0, p = 0.0;
+      bool early = false;
+      for (int i = m - 1; i >= l; --i) {
+        double f = s * ee[i], b = co * ee[i];
+        r = hypot(f, g);
+        __syncthreads();
+        if (lane == 0) ee[i + 1] = r;
+        __syncthreads();
+        if (r == 0.0) {
+          __syncthreads();
+          if (lane == 0) { dd[i + 1] -= p; ee[m] = 0.0; }
+          __syncthreads();
+          early = true;
+          break;
+        }
+        s = f / r;
+        co = g / r;
+        g = dd[i + 1] - p;
+        r = (dd[i] - g) * s + 2.0 * co * b;
+        p = s * r;
+        __syncthreads();
+        if (lane == 0) dd[i + 1] = g + p;
+        __syncthreads();
+        g = co * r - b;
+        if (lane < n) {
+          double zf = Z[lane][i + 1], zi = Z[lane][i];
+          Z[lane][i + 1] = s * zi + co * zf;
+          Z[lane][i] = co * zi - s * zf;
+        }
+      }
+      if (early) continue;
+      __syncthreads();
+      if (lane == 0) { dd[l] -= p; ee[l] = g; ee[m] = 0.0; }
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  // u_k = sum_m Z[k][m] exp(-i tau lam_m) Z[0][m]
+  double ur = 0.0, ui = 0.0;
+  if (lane < n) {
+    for (int m = 0; m < n; ++m) {
+      double z0 = Z[0][m], ph = -tau * dd[m];
+      double sn, cs;
+      sincos(ph, &sn, &cs);
+      ur += Z[lane][m] * z0 * cs;
+      ui += Z[lane][m] * z0 * sn;
+    }
+  }
+  // broadcast u_{n-1}
+  double un_r = __shfl(ur, n - 1, 64), un_i = __shfl(ui, n - 1, 64);
+  double bj = beta[(int64_t)(j - 1) * ncol + c];
+  double tn = 0.0;
+  for (int i = 0; i < n; ++i) {
+    double v = fabs(alpha[(int64_t)i * ncol + c]) + (i > 0 ? beta[(int64_t)(i - 1) * ncol + c] : 0.0) +
+               beta[(int64_t)i * ncol + c];
+    tn = v > tn ? v : tn;
+  }
+  const double b0 = beta0[c];
+  const double est = fabs(tau) * bj * b0 * hypot(un_r, un_i);
+  bool done;
+  if (kforce) done = j >= kforce[c] || bj == 0.0;
+  else done = est <= tol * b0 || bj <= 1e-14 * tn;
+  if (fail) done = false;
+  if (lane == 0) err[c] = fail ? -1.0 : est;
+  if (done) {
+    if (lane < n) {
+      ubuf[((int64_t)c * kmax + lane) * 2] = ur;
+      ubuf[((int64_t)c * kmax + lane) * 2 + 1] = ui;
+    }
+    if (lane == 0) {
+      kused[c] = j;
+      active[c] = 0;
+    }
+  }
+}
+
+// out[r][c] = beta0[c] sum_{l < k_c} u[c][l] Q_l[r][c]
+__global__ void __launch_bounds__(256)
+k_combine(const double *__restrict__ Q, int64_t qstride, const double *__restrict__ u, int kmax,
+          const int *__restrict__ kused, const double *__restrict__ beta0, double *__restrict__ out, int64_t nrows,
+          int ncol) {
+  extern __shared__ double us[];   // ncol * kmax * 2
+  for (int t = threadIdx.x; t < ncol * kmax * 2; t += blockDim.x) us[t] = u[t];
+  __syncthreads();
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nrows * ncol) return;
+  const int c = (int)(t % ncol);
+  const int kc = kused[c];
+  double sr = 0.0, si = 0.0;
+  for (int l = 0; l < kc; ++l) {
+    const double qr = Q[(int64_t)l * qstride + 2 * t], qi = Q[(int64_t)l * qstride + 2 * t + 1];
+    const double ur = us[(c * kmax + l) * 2], ui = us[(c * kmax + l) * 2 + 1];
+    sr += ur * qr - ui * qi;
+    si += ur * qi + ui * qr;
+  }
+  const double b = beta0[c];
+  out[2 * t] = b * sr;
+  out[2 * t + 1] = b * si;
+}
+
+inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+template <typename T, int MTW>
+void launch_apply_m(const DevData &d, const T *cells, const double *X, double *Y, int ncolr, int64_t ldr, hipStream_t s) {
+  for (int c = 0; c < 8; ++c) {
+    int cnt = d.colour_off[c + 1] - d.colour_off[c];
+    if (cnt == 0) continue;
+    const int *list = d.colour_cells + d.colour_off[c];
+    if (ncolr <= 32) {
+      hipLaunchKernelGGL((k_cell_apply<T, MTW, 1>), dim3(cnt, 1), dim3(256), 0, s, d, list, cells, X, Y, ncolr, ldr);
+    } else if (ncolr <= 64) {
+      hipLaunchKernelGGL((k_cell_apply<T, MTW, 2>), dim3(cnt, 1), dim3(256), 0, s, d, list, cells, X, Y, ncolr, ldr);
+    } else {
+      unsigned nch = (unsigned)((ncolr + 95) / 96);
+      hipLaunchKernelGGL((k_cell_apply<T, MTW, 3>), dim3(cnt, nch), dim3(256), 0, s, d, list, cells, X, Y, ncolr, ldr);
+    }
+  }
+}
+
+template <typename T>
+void launch_apply(const DevData &d, const T *cells, const double *X, double *Y, int ncolr, int64_t ldr, hipStream_t s) {
+  const int mt = (d.g.nloc + 15) / 16;
+  const int mtw = (mt + 1) / 2;
+  if (mtw <= 1) launch_apply_m<T, 1>(d, cells, X, Y, ncolr, ldr, s);
+  else if (mtw <= 2) launch_apply_m<T, 2>(d, cells, X, Y, ncolr, ldr, s);
+  else if (mtw <= 4) launch_apply_m<T, 4>(d, cells, X, Y, ncolr, ldr, s);
+  else if (mtw <= 7) launch_apply_m<T, 7>(d, cells, X, Y, ncolr, ldr, s);
+  else launch_apply_m<T, 11>(d, cells, X, Y, ncolr, ldr, s);
+}
+
+}  // namespace
+
+namespace k {
+
+void cell_apply(const DevData &d, const void *cells, int dtype, const double *X, double *Y, int ncolr, int64_t ldr,
+                hipStream_t s) {
+  if (dtype == 0) launch_apply<double>(d, (const double *)cells, X, Y, ncolr, ldr, s);
+  else launch_apply<float>(d, (const float *)cells, X, Y, ncolr, ldr, s);
+}
+
+void couple_apply(const DevData &d, const double *G, const double *Hee, const double *X, double *Y, int ncolr,
+                  int64_t ldr, double *scratch, hipStream_t s) {
+  if (d.nk == 0) return;
+  size_t lds = (size_t)d.nk * ncolr * sizeof(double);
+  if (d.nr > 0)
+    hipLaunchKernelGGL(k_couple_c, dim3(nblocks(d.nr * ncolr, 256)), dim3(256), lds, s, d, G, X, Y, ncolr, ldr);
+  int nblk = 1;
+  int64_t rpb = d.nr;
+  if (d.nr > 0) {
+    nblk = (int)std::min<int64_t>(512, (d.nr + 255) / 256);
+    rpb = (d.nr + nblk - 1) / nblk;
+    size_t lds2 = (size_t)kRowChunk * (d.nk + ncolr) * sizeof(double);
+    hipLaunchKernelGGL(k_couple_e_partial, dim3(nblk), dim3(256), lds2, s, d, G, X, ncolr, ldr, rpb, scratch);
+  } else {
+    k::zero(scratch, (int64_t)d.nk * ncolr, s);
+  }
+  hipLaunchKernelGGL(k_couple_e_final, dim3(nblocks((int64_t)d.nk * ncolr, 128)), dim3(128), 0, s, d, scratch, nblk, Hee,
+                     X, Y, ncolr, ldr);
+}
+
+int multidot_partials(const double *Q, int64_t qstride, int nq, const double *w, int64_t nrows, int ncol,
+                      const int *active, double *part, hipStream_t s) {
+  int R = 256 / ncol;
+  int nb = (int)std::min<int64_t>(512, (nrows + R - 1) / R);
+  if (nb < 1) nb = 1;
+  size_t lds = (size_t)R * LCH * ncol * 2 * sizeof(double);
+  hipLaunchKernelGGL(k_multidot, dim3(nb), dim3(256), lds, s, Q, qstride, nq, w, nrows, ncol, active, part);
+  return nb;
+}
+
+int coldot_partials(const double *A, const double *B, int64_t nrows, int ncol, double *part, hipStream_t s) {
+  return multidot_partials(A, 0, 1, B, nrows, ncol, nullptr, part, s);
+}
+
+void multi_update(const double *Q, int64_t qstride, int nq, const double *h, double *w, int64_t nrows, int ncol,
+                  const int *active, hipStream_t s) {
+  size_t lds = (size_t)nq * ncol * 2 * sizeof(double);
+  hipLaunchKernelGGL(k_multi_update, dim3(nblocks(nrows * ncol, 256)), dim3(256), lds, s, Q, qstride, nq, h, w, nrows,
+                     ncol, active);
+}
+
+void three_term(double *w, const double *q, const double *qm1, const double *alpha, const double *beta, int64_t nrows,
+                int ncol, const int *active, hipStream_t s) {
+  hipLaunchKernelGGL(k_three_term, dim3(nblocks(nrows * ncol, 256)), dim3(256), 0, s, w, q, qm1, alpha, beta, nrows,
+                     ncol, active);
+}
+
+void scale_cols(const double *w, double *q, const double *nrm, int64_t nrows, int ncol, const int *active,
+                hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_cols, dim3(nblocks(nrows * ncol, 256)), dim3(256), 0, s, w, q, nrm, nrows, ncol, active);
+}
+
+void tridiag_exp(const double *alpha, const double *beta, int j, int ncol, int kmax, double tau, const double *beta0,
+                 const int *kforce, double tol, int *active, int *kused, double *err, double *u, hipStream_t s) {
+  hipLaunchKernelGGL(k_tridiag_exp, dim3(ncol), dim3(64), 0, s, alpha, beta, j, ncol, kmax, tau, beta0, kforce, tol,
+                     active, kused, err, u);
+}
+
+void combine(const double *Q, int64_t qstride, const double *u, int kmax, const int *kused, const double *beta0,
+             double *out, int64_t nrows, int ncol, hipStream_t s) {
+  size_t lds = (size_t)ncol * kmax * 2 * sizeof(double);
+  hipLaunchKernelGGL(k_combine, dim3(nblocks(nrows * ncol, 256)), dim3(256), lds, s, Q, qstride, u, kmax, kused, beta0,
+                     out, nrows, ncol);
+}
+
+}  // namespace k
+}  // namespace efe
+
+namespace efe {
+namespace {
+
+// dst[c] = Re(tmp[c]) or sqrt(max(Re(tmp[c]), 0)) for active columns
+__global__ void k_store_re(const double *__restrict__ tmp, double *__restrict__ dst, int ncol, int sqrt_mode,
+                           const int *__restrict__ active) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncol) return;
+  if (active && !active[c]) return;
+  const double v = tmp[2 * c];
+  dst[c] = sqrt_mode ? sqrt(v > 0.0 ? v : 0.0) : v;
+}
+
+__global__ void k_init_active(const double *__restrict__ beta0, int *__restrict__ active, int *__restrict__ kused,
+                              int ncol) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncol) return;
+  active[c] = beta0[c] > 0.0 ? 1 : 0;
+  kused[c] = 0;
+}
+
+}  // namespace
+
+namespace k {
+
+void store_re(const double *tmp, double *dst, int ncol, int sqrt_mode, const int *active, hipStream_t s) {
+  hipLaunchKernelGGL(k_store_re, dim3((ncol + 63) / 64), dim3(64), 0, s, tmp, dst, ncol, sqrt_mode, active);
+}
+
+void init_active(const double *beta0, int *active, int *kused, int ncol, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_active, dim3((ncol + 63) / 64), dim3(64), 0, s, beta0, active, kused, ncol);
+}
+
+}  // namespace k
+}  // namespace efe

@@ -1,0 +1,314 @@
+"""Thin ctypes binding of libefe.so (C ABI in include/efe.h).
+
+Argument marshalling only: every step of the Magnus propagation runs in the
+library's HIP kernels.  Device arrays are torch tensors (complex128 orbital
+blocks, float64 quadrature/nodal arrays); the library works on the current
+torch HIP stream.  If the library is missing, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libefe.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2210_14421_amd.build`")
+
+_lib = C.CDLL(LIB_PATH)
+
+EFE_OK, EFE_ERR_ARG, EFE_ERR_ALLOC, EFE_ERR_HIP = 0, -1, -2, -3
+EFE_ERR_NOCONV, EFE_ERR_SINGULAR, EFE_ERR_NONFINITE, EFE_ERR_STATE = -4, -5, -6, -7
+DTYPES = {"f64": 0, "f32": 1, "bf16": 2}
+XC = {"none": 0, "slater": 1, "slater_pw92": 2}
+OPS = {"H": 0, "x": 1, "y": 2, "z": 3}
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+
+class EfeSystem(C.Structure):
+    _fields_ = [("ncell", C.c_int32 * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+                ("degree", C.c_int32), ("natom", C.c_int32), ("R", _dp), ("Z", _dp),
+                ("nuc_sigma", C.c_double), ("nenr", C.c_int32), ("enr_atom", _ip), ("enr_l", _ip),
+                ("enr_m", _ip), ("enr_zeta", _dp), ("r_cut", C.c_double), ("norb", C.c_int32),
+                ("occ", _dp), ("xc", C.c_int32), ("trap_omega", C.c_double), ("quad_cell", C.c_int32),
+                ("quad_enr", C.c_int32), ("enr_drop_tol", C.c_double)]
+
+
+class EfeOptions(C.Structure):
+    _fields_ = [("prod_dtype", C.c_int32), ("kmax", C.c_int32), ("krylov_tol", C.c_double),
+                ("cg_tol", C.c_double), ("cg_maxit", C.c_int32), ("hip_stream", C.c_void_p)]
+
+
+class EfeField(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("direction", C.c_int32), ("ncomp", C.c_int32),
+                ("A", _dp), ("w", _dp), ("phi", _dp), ("t0", C.c_double), ("s", C.c_double)]
+
+
+class EfeStepStats(C.Structure):
+    _fields_ = [("k_pred", C.c_int32 * 128), ("k_corr", C.c_int32 * 128), ("err_pred_max", C.c_double),
+                ("err_corr_max", C.c_double), ("cg_iters", C.c_int32 * 2), ("mu", C.c_double * 3)]
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_plan_create = _sig("efe_plan_create", C.c_int32, [C.POINTER(EfeSystem), C.POINTER(C.c_void_p)])
+_plan_free = _sig("efe_plan_free", C.c_int32, [C.c_void_p])
+_plan_sizes = _sig("efe_plan_sizes", C.c_int32, [C.c_void_p, C.POINTER(C.c_int64)])
+_plan_get = _sig("efe_plan_get", C.c_int32, [C.c_void_p, C.c_char_p, _dp, C.c_int64])
+_plan_error = _sig("efe_plan_error", C.c_char_p, [C.c_void_p])
+_setup = _sig("efe_setup", C.c_int32, [C.POINTER(EfeSystem), C.POINTER(EfeOptions), C.POINTER(C.c_void_p)])
+_free = _sig("efe_free", C.c_int32, [C.c_void_p])
+_dims = _sig("efe_dims", C.c_int32, [C.c_void_p, C.POINTER(C.c_int64)])
+_set_options = _sig("efe_set_options", C.c_int32, [C.c_void_p, C.POINTER(EfeOptions)])
+_initial_state = _sig("efe_initial_state", C.c_int32, [C.c_void_p, _ip, _dp, C.c_double, C.c_void_p])
+_set_ham = _sig("efe_set_hamiltonian", C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.POINTER(EfeField)])
+_apply_H = _sig("efe_apply_H", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int64])
+_lanczos = _sig("lanczos_expm", C.c_int32, [C.c_void_p, C.c_int32, C.c_double, C.c_void_p, C.c_int32, C.c_int64,
+                                            _ip, _ip, _dp])
+_magnus = _sig("magnus_step", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_double,
+                                          C.POINTER(EfeField), _ip, C.POINTER(EfeStepStats)])
+_density = _sig("density", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p])
+_hartree = _sig("efe_hartree", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, _ip])
+_dipole = _sig("dipole", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, _dp])
+_timing_on = _sig("efe_enable_timing", C.c_int32, [C.c_void_p, C.c_int32])
+_timing_get = _sig("efe_get_timing", C.c_int32, [C.c_void_p, _dp, C.POINTER(C.c_int64)])
+_last_error = _sig("efe_last_error", C.c_char_p, [C.c_void_p])
+
+EXPORTED = ["efe_plan_create", "efe_plan_free", "efe_plan_sizes", "efe_plan_get", "efe_plan_error",
+            "efe_setup", "efe_free", "efe_dims", "efe_set_options", "efe_initial_state",
+            "efe_set_hamiltonian", "efe_apply_H", "lanczos_expm", "magnus_step", "density",
+            "efe_hartree", "dipole", "efe_enable_timing", "efe_get_timing", "efe_last_error"]
+
+
+class EfeError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"efe status {status}: {msg}")
+        self.status = status
+
+
+def _arr(a, dtype):
+    return np.ascontiguousarray(np.asarray(a, dtype=dtype))
+
+
+class _SystemHolder:
+    """Keeps the numpy arrays referenced by an EfeSystem alive."""
+
+    def __init__(self, spec):
+        self.R = _arr(spec.R, np.float64).reshape(-1)
+        self.Z = _arr(spec.Z, np.float64)
+        self.ea = _arr(spec.enr_atom, np.int32)
+        self.el = _arr(spec.enr_l, np.int32)
+        self.em = _arr(spec.enr_m, np.int32)
+        self.ez = _arr(spec.enr_zeta, np.float64)
+        self.occ = _arr(spec.occ, np.float64)
+        s = EfeSystem()
+        for d in range(3):
+            s.ncell[d] = int(spec.ncell[d])
+            s.lo[d] = float(spec.lo[d])
+            s.hi[d] = float(spec.hi[d])
+        s.degree = int(spec.degree)
+        s.natom = int(len(self.Z))
+        s.R = self.R.ctypes.data_as(_dp)
+        s.Z = self.Z.ctypes.data_as(_dp)
+        s.nuc_sigma = float(spec.nuc_sigma)
+        s.nenr = int(len(self.ez))
+        s.enr_atom = self.ea.ctypes.data_as(_ip)
+        s.enr_l = self.el.ctypes.data_as(_ip)
+        s.enr_m = self.em.ctypes.data_as(_ip)
+        s.enr_zeta = self.ez.ctypes.data_as(_dp)
+        s.r_cut = float(spec.r_cut)
+        s.norb = int(len(self.occ))
+        s.occ = self.occ.ctypes.data_as(_dp)
+        s.xc = XC[spec.xc]
+        s.trap_omega = float(spec.trap_omega)
+        s.quad_cell = int(spec.quad_cell)
+        s.quad_enr = int(spec.quad_enr)
+        s.enr_drop_tol = float(spec.enr_drop_tol)
+        self.sys = s
+
+
+class Plan:
+    """Host-only static data of the discretisation (no GPU needed)."""
+
+    def __init__(self, spec):
+        self._h = _SystemHolder(spec)
+        self._p = C.c_void_p()
+        st = _plan_create(C.byref(self._h.sys), C.byref(self._p))
+        if st != EFE_OK:
+            msg = _plan_error(self._p).decode() if self._p else ""
+            _plan_free(self._p)
+            self._p = None
+            raise EfeError(st, msg)
+        sz = (C.c_int64 * 6)()
+        _plan_sizes(self._p, sz)
+        (self.n_nodes, self.n_cells, self.n_quad, self.n_kept, self.n_union_rows, self.n_tcells) = list(sz)
+        self.nenr = int(len(spec.enr_zeta))
+
+    def get(self, name, count):
+        out = np.empty(int(count), dtype=np.float64)
+        st = _plan_get(self._p, name.encode(), out.ctypes.data_as(_dp), int(count))
+        if st != EFE_OK:
+            raise EfeError(st, f"plan array {name!r} of {count}")
+        return out
+
+    def __del__(self):
+        if getattr(self, "_p", None):
+            _plan_free(self._p)
+            self._p = None
+
+
+def make_field(direction=2, A=(), w=(), phi=(), t0=0.0, s=1.0):
+    """E(t) = dir * sum A_k sin(w_k t + phi_k) exp(-(t-t0)^2/s^2); returns (EfeField, keepalive)."""
+    A, w, phi = _arr(A, np.float64), _arr(w, np.float64), _arr(phi, np.float64)
+    f = EfeField()
+    f.kind = 1 if len(A) else 0
+    f.direction = int(direction)
+    f.ncomp = int(len(A))
+    f.A, f.w, f.phi = A.ctypes.data_as(_dp), w.ctypes.data_as(_dp), phi.ctypes.data_as(_dp)
+    f.t0, f.s = float(t0), float(s)
+    return f, (A, w, phi)
+
+
+class Context:
+    """A GPU context: static data uploaded, workspace allocated."""
+
+    def __init__(self, spec, dtype="f64", kmax=None, tol=None, cg_tol=1e-12, cg_maxit=50, stream=None):
+        import torch
+        self.torch = torch
+        self.spec = spec
+        self._h = _SystemHolder(spec)
+        o = EfeOptions()
+        o.prod_dtype = DTYPES[dtype]
+        o.kmax = int(kmax if kmax is not None else min(spec.kmax, 64))
+        o.krylov_tol = float(tol if tol is not None else spec.krylov_tol)
+        o.cg_tol = float(cg_tol)
+        o.cg_maxit = int(cg_maxit)
+        s = stream if stream is not None else torch.cuda.current_stream()
+        o.hip_stream = C.c_void_p(s.cuda_stream)
+        self._opt = o
+        self._c = C.c_void_p()
+        st = _setup(C.byref(self._h.sys), C.byref(o), C.byref(self._c))
+        if st != EFE_OK:
+            msg = _last_error(self._c).decode() if self._c else ""
+            _free(self._c)
+            self._c = None
+            raise EfeError(st, msg)
+        d = (C.c_int64 * 4)()
+        _dims(self._c, d)
+        self.n_rows, self.n_nodes, self.n_kept, self.n_quad = [int(x) for x in d]
+        self.norb = spec.norb
+        self.kmax = o.kmax
+
+    # -- helpers ---------------------------------------------------------------
+    def _check(self, st):
+        if st != EFE_OK:
+            raise EfeError(st, _last_error(self._c).decode())
+
+    def _ptr(self, t, dtype=None, rows=None):
+        torch = self.torch
+        if not t.is_cuda:
+            raise ValueError("device tensor expected")
+        if not t.is_contiguous():
+            raise ValueError("contiguous tensor expected")
+        if dtype is not None and t.dtype != dtype:
+            raise ValueError(f"{dtype} expected, got {t.dtype}")
+        if rows is not None and t.shape[0] != rows:
+            raise ValueError(f"{rows} rows expected, got {t.shape[0]}")
+        return C.c_void_p(t.data_ptr())
+
+    def empty_block(self, ncol=None):
+        torch = self.torch
+        return torch.zeros((self.n_rows, ncol or self.norb), dtype=torch.complex128, device="cuda")
+
+    # -- API ---------------------------------------------------------------------
+    def initial_state(self, Psi=None):
+        """Enrichment directions plus seeded FE noise, Loewdin-orthonormalised."""
+        spec = self.spec
+        Psi = self.empty_block() if Psi is None else Psi
+        idx = _arr(spec.init_enr, np.int32)
+        g = _arr(spec.noise(), np.float64).reshape(-1)
+        self._check(_initial_state(self._c, idx.ctypes.data_as(_ip), g.ctypes.data_as(_dp),
+                                   float(spec.noise_amp), self._ptr(Psi, self.torch.complex128, self.n_rows)))
+        return Psi
+
+    def set_hamiltonian(self, Psi, t=0.0, field=None):
+        f = C.byref(field) if field is not None else None
+        self._check(_set_ham(self._c, self._ptr(Psi, self.torch.complex128, self.n_rows), float(t), f))
+
+    def apply_H(self, X, Y=None):
+        ncol = X.shape[1]
+        Y = self.torch.empty_like(X) if Y is None else Y
+        self._check(_apply_H(self._c, self._ptr(X, self.torch.complex128, self.n_rows),
+                             self._ptr(Y, self.torch.complex128, self.n_rows), ncol, ncol))
+        return Y
+
+    def lanczos_expm(self, X, tau, op="H", k_force: Optional[Sequence[int]] = None):
+        ncol = X.shape[1]
+        ku = np.zeros(ncol, dtype=np.int32)
+        er = np.zeros(ncol, dtype=np.float64)
+        kf = None if k_force is None else _arr(k_force, np.int32)
+        self._check(_lanczos(self._c, OPS[op], float(tau), self._ptr(X, self.torch.complex128, self.n_rows), ncol, ncol,
+                             None if kf is None else kf.ctypes.data_as(_ip), ku.ctypes.data_as(_ip),
+                             er.ctypes.data_as(_dp)))
+        return ku, er
+
+    def magnus_step(self, Psi, t, dt, field=None, k_force=None):
+        st = EfeStepStats()
+        kf = None if k_force is None else _arr(k_force, np.int32).reshape(-1)
+        f = C.byref(field) if field is not None else None
+        self._check(_magnus(self._c, self._ptr(Psi, self.torch.complex128, self.n_rows), Psi.shape[1], float(t),
+                            float(dt), f, None if kf is None else kf.ctypes.data_as(_ip), C.byref(st)))
+        n = self.norb
+        return dict(k_pred=np.array(st.k_pred[:n]), k_corr=np.array(st.k_corr[:n]),
+                    err_pred_max=st.err_pred_max, err_corr_max=st.err_corr_max,
+                    cg_iters=tuple(st.cg_iters), mu=np.array(st.mu[:3]))
+
+    def density(self, Psi, rho=None):
+        torch = self.torch
+        rho = torch.empty(self.n_quad, dtype=torch.float64, device="cuda") if rho is None else rho
+        self._check(_density(self._c, self._ptr(Psi, torch.complex128, self.n_rows), Psi.shape[1],
+                             self._ptr(rho, torch.float64)))
+        return rho
+
+    def hartree(self, rho, phi=None):
+        torch = self.torch
+        phi = torch.empty(self.n_nodes, dtype=torch.float64, device="cuda") if phi is None else phi
+        it = C.c_int32(0)
+        self._check(_hartree(self._c, self._ptr(rho, torch.float64), self._ptr(phi, torch.float64), C.byref(it)))
+        return phi, int(it.value)
+
+    def dipole(self, Psi):
+        mu = (C.c_double * 3)()
+        self._check(_dipole(self._c, self._ptr(Psi, self.torch.complex128, self.n_rows), Psi.shape[1], mu))
+        return np.array(mu[:3])
+
+    def enable_timing(self, on=True):
+        self._check(_timing_on(self._c, 1 if on else 0))
+
+    def timing(self):
+        ms = (C.c_double * 8)()
+        n = C.c_int64(0)
+        self._check(_timing_get(self._c, ms, C.byref(n)))
+        keys = ["cell_hx", "coupling", "lanczos_vec", "tridiag_exp", "density", "poisson", "rebuild", "total"]
+        out = dict(zip(keys, list(ms)))
+        out["n_hx"] = int(n.value)
+        return out
+
+    def close(self):
+        if getattr(self, "_c", None):
+            _free(self._c)
+            self._c = None
+
+    def __del__(self):
+        self.close()
