@@ -1,0 +1,177 @@
+"""Benchmark: Magnus-2 steps/s on the Na8 workload on one MI355X.
+
+Workload (one GPU): 8 Na atoms at seeded positions in a ball of radius 6 bohr,
+box [-20, 20]^3 with 24^3 cells of degree 5 (1,771,561 nodes), 48 enrichment
+functions, 44 doubly occupied orbitals from enrichment directions plus seeded
+low-frequency noise, ALDA (Slater + PW92), z kick 1e-3, dt = 0.02 au, Lanczos
+tolerance 1e-10.  A step is one full predictor-corrector Magnus-2 step (two
+adaptive Lanczos exponentials, two densities, two Poisson solves, two
+Hamiltonian rebuilds, one dipole), orbitals resident in HBM.
+
+Prints one JSON line.  Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Magnus steps/s at Na8 (44 orbitals) + H.X roofline fraction, mixed vs plain FP64"
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
+HBM_GBS = 8000.0
+
+
+def run_gpu(spec, dtype, steps, warmup, kmax):
+    import numpy as np
+    import torch
+    from paper_2210_14421_amd.efe import Context
+    t0 = time.time()
+    ctx = Context(spec, dtype=dtype, kmax=kmax)
+    Psi = ctx.initial_state()
+    ctx.lanczos_expm(Psi, -spec.kick, op="z")
+    ctx.set_hamiltonian(Psi, 0.0)
+    torch.cuda.synchronize()
+    setup_s = time.time() - t0
+    print(f"[bench] {dtype}: setup + initial state + kick {setup_s:.1f} s", file=sys.stderr, flush=True)
+    t = 0.0
+    for i in range(warmup):
+        ctx.magnus_step(Psi, t, spec.dt)
+        t += spec.dt
+    ctx.enable_timing(True)
+    stage = {}
+    ks = []
+    mus = []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(steps):
+        st = ctx.magnus_step(Psi, t, spec.dt)
+        t += spec.dt
+        tm = ctx.timing()
+        for k, v in tm.items():
+            stage[k] = stage.get(k, 0) + v
+        ks.append((float(np.mean(st["k_pred"])), float(np.mean(st["k_corr"]))))
+        mus.append(st["mu"].tolist())
+        print(f"[bench] {dtype} step {i}: mu_z={st['mu'][2]:.9e} k={ks[-1]} total {tm['total']:.1f} ms",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    G = Psi.conj().T @ Psi
+    orth = float((G - torch.eye(spec.norb, dtype=G.dtype, device=G.device)).abs().max())
+    ctx.close()
+    return dict(wall=wall, stage=stage, k=ks, mu=mus, orth=orth, setup_s=setup_s)
+
+
+def roofline(spec, res, dtype):
+    """Achieved FLOP/s of the cell-product kernel (all colour launches of every Hbar X)."""
+    P = spec.degree + 1
+    nloc = P ** 3
+    ncells = spec.ncell[0] * spec.ncell[1] * spec.ncell[2]
+    ncolr = 2 * spec.norb
+    flop_per_hx = 2.0 * nloc * nloc * ncolr * ncells
+    n_hx = res["stage"]["n_hx"]
+    ms = res["stage"]["cell_hx"]
+    achieved = flop_per_hx * n_hx / (ms * 1e-3) / 1e12
+    return {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s",
+            "frac": achieved / PEAK_TFLOPS[dtype], "traffic": None,
+            "kernel": "k_cell_apply", "flop_per_hx": flop_per_hx, "hx_per_step": n_hx / max(1, len(res["k"])),
+            "ms_per_hx": ms / max(1, n_hx)}
+
+
+def cpu_baseline(spec, hx_per_step, ncells_sample=96):
+    """Time the FP64 oracle's Hbar X (cell route) on a sample of cells and scale to steps/s.
+
+    The sample is the oracle's cell-block construction and product on
+    `ncells_sample` cells (ordinary and enrichment cells in the mesh's
+    proportion), scaled to all cells and to the Hbar X count per step measured on
+    the GPU.  Vector work, densities and Poisson solves are not included, so the
+    figure is an upper bound of the oracle's steps/s.
+    """
+    import numpy as np
+    from oracle.fe import Mesh
+    m = Mesh(spec.ncell, spec.lo, spec.hi, spec.degree, spec.r_cut, spec.R, spec.qcell, spec.qenr)
+    rng = np.random.default_rng(0)
+    X = rng.standard_normal((m.n_nodes, 2 * spec.norb))
+    ids = np.concatenate([np.nonzero(~m.is_enr)[0][:ncells_sample - ncells_sample * int(m.is_enr.sum()) // m.n_cells],
+                          np.nonzero(m.is_enr)[0][:max(1, ncells_sample * int(m.is_enr.sum()) // m.n_cells)]])
+    shapes = {}
+    t0 = time.perf_counter()
+    Y = np.zeros_like(X)
+    for c in ids:
+        key = bool(m.is_enr[c])
+        if key not in shapes:
+            _, _, B, G = m.cell_shape(c)
+            shapes[key] = (B, G)
+        B, G = shapes[key]
+        pts, w, _ = m.cell_rule(c)
+        v = np.sum(pts * pts, axis=1)
+        Hc = B.T @ ((w * v)[:, None] * B) + 0.5 * sum(G[d].T @ (w[:, None] * G[d]) for d in range(3))
+        nodes = m.cell_nodes(c)
+        Y[nodes] += Hc @ X[nodes]
+    dt = time.perf_counter() - t0
+    t_hx = dt * m.n_cells / len(ids)
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    return {"value": 1.0 / (t_hx * hx_per_step), "unit": "steps/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"oracle Hbar X on {len(ids)} of {m.n_cells} cells ({dt:.1f} s), scaled to all cells "
+                      f"and {hx_per_step:.0f} Hbar X per step; vector work, density and Poisson excluded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--kmax", type=int, default=40)
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", default="na8", choices=["na8", "tiny", "na2"])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the orbital-sharded design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from workloads import na8, tiny, na_cluster
+    spec = {"na8": na8, "tiny": tiny, "na2": lambda: na_cluster(2, seed=2)}[args.workload]()
+    torch.cuda.set_device(0)
+    res = run_gpu(spec, "f64", args.steps, args.warmup, args.kmax)
+    value = args.steps / res["wall"]
+    roof = roofline(spec, res, "f64")
+    out = {
+        "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * res["wall"] / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{spec.name}: {spec.natom} atoms, {spec.ncell[0]}^3 cells degree {spec.degree}, "
+                               f"{(spec.ncell[0] * spec.degree + 1) ** 3} nodes, {spec.norb} orbitals, "
+                               f"dt {spec.dt}, Krylov tol {spec.krylov_tol}, z kick {spec.kick}",
+                   "precision": "FP64 products, FP64 Lanczos"},
+        "roofline": roof,
+        "stage_ms_per_step": {k: v / args.steps for k, v in res["stage"].items() if k != "n_hx"},
+        "krylov_k_mean": res["k"], "orthonormality_error": res["orth"],
+    }
+    if not args.no_mixed:
+        mres = run_gpu(spec, "f32", args.steps, args.warmup, args.kmax)
+        mroof = roofline(spec, mres, "f32")
+        mv = args.steps / mres["wall"]
+        import numpy as np
+        dmu = np.max(np.linalg.norm(np.array(mres["mu"]) - np.array(res["mu"]), axis=1)) / \
+            np.max(np.linalg.norm(np.array(res["mu"]), axis=1))
+        out["mixed"] = {"dtype": "f32 products, FP64 Lanczos", "value": mv, "unit": "steps/s",
+                        "ms_per_step": 1e3 * mres["wall"] / args.steps, "speedup_vs_f64": mv / value,
+                        "roofline": mroof, "dipole_rel_diff_vs_f64": float(dmu),
+                        "stage_ms_per_step": {k: v / args.steps for k, v in mres["stage"].items() if k != "n_hx"}}
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(spec, roof["hx_per_step"])
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

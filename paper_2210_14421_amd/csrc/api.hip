@@ -55,7 +55,9 @@ struct efe_ctx {
   double *psiE = nullptr, *red = nullptr, *small = nullptr, *couple_scr = nullptr;
   int64_t red_len = 0;
   double *alpha = nullptr, *beta = nullptr, *beta0 = nullptr, *errv = nullptr, *ubuf = nullptr;
-  int *active = nullptr, *kused = nullptr, *kforce = nullptr;
+  int *active = nullptr, *kused = nullptr, *kforce = nullptr, *need = nullptr, *anyflag = nullptr;
+  double *h1 = nullptr, *h2n = nullptr, *nrm1 = nullptr, *nrm2 = nullptr;
+  int *one = nullptr;
   // state
   int cells_mode = -1;      // -1 nothing built, 0 Hamiltonian, 1..3 position operator
   bool ham_valid = false;   // rho_prev and the Hamiltonian belong to the current orbitals
@@ -298,10 +300,10 @@ efe_status build_device(efe_ctx *ctx) {
   EFE_TRY(dalloc(ctx, &ctx->Hee_raw, (int64_t)d.ne * d.ne));
   EFE_TRY(dalloc(ctx, &ctx->Hbar_ee, (int64_t)d.nk * d.nk));
   EFE_TRY(dalloc(ctx, &ctx->psiE, (int64_t)d.ne * ctx->ncolr));
-  ctx->red_len = std::max<int64_t>({(int64_t)512 * ctx->kmax * ctx->ncolr, pl.n_cells * 3, 4096});
+  ctx->red_len = std::max<int64_t>({(int64_t)efe::k::kDotBlocksMax * (ctx->kmax + 1) * ctx->ncolr, pl.n_cells * 3, 4096});
   EFE_TRY(dalloc(ctx, &ctx->red, ctx->red_len));
   EFE_TRY(dalloc(ctx, &ctx->small, (int64_t)ctx->kmax * ctx->ncolr + 64));
-  EFE_TRY(dalloc(ctx, &ctx->couple_scr, (int64_t)512 * std::max(1, d.nk) * ctx->ncolr));
+  EFE_TRY(dalloc(ctx, &ctx->couple_scr, (int64_t)1024 * std::max(1, d.nk) * ctx->ncolr));
   EFE_TRY(dalloc(ctx, &ctx->alpha, (int64_t)ctx->kmax * pl.norb));
   EFE_TRY(dalloc(ctx, &ctx->beta, (int64_t)ctx->kmax * pl.norb));
   EFE_TRY(dalloc(ctx, &ctx->beta0, pl.norb));
@@ -310,6 +312,16 @@ efe_status build_device(efe_ctx *ctx) {
   EFE_TRY(dalloc(ctx, &ctx->active, pl.norb));
   EFE_TRY(dalloc(ctx, &ctx->kused, pl.norb));
   EFE_TRY(dalloc(ctx, &ctx->kforce, pl.norb));
+  EFE_TRY(dalloc(ctx, &ctx->need, pl.norb));
+  EFE_TRY(dalloc(ctx, &ctx->anyflag, 1));
+  EFE_TRY(dalloc(ctx, &ctx->h1, (int64_t)(ctx->kmax + 1) * ctx->ncolr));
+  {
+    std::vector<int> one(1, 1);
+    EFE_TRY(upload(ctx, &ctx->one, one));
+  }
+  EFE_TRY(dalloc(ctx, &ctx->h2n, (int64_t)(ctx->kmax + 1) * ctx->ncolr));
+  EFE_TRY(dalloc(ctx, &ctx->nrm1, pl.norb));
+  EFE_TRY(dalloc(ctx, &ctx->nrm2, ctx->ncolr));
   return sync(ctx, "setup");
 }
 
@@ -465,7 +477,7 @@ efe_status run_lanczos(efe_ctx *ctx, double tau, const double *X, double *out, i
   const int *kf = kforce_host ? ctx->kforce : nullptr;
   double *tmp = ctx->small;
   tstart(ctx, 2);
-  int nb = efe::k::multidot_partials(X, 0, 1, X, nrows, ncol, nullptr, ctx->red, s);
+  int nb = efe::k::norm_partials(X, nrows, ncol, nullptr, ctx->red, s);
   efe::k::reduce_partials(ctx->red, nb, ncolr, tmp, s);
   efe::k::store_re(tmp, ctx->beta0, ncol, 1, nullptr, s);
   efe::k::init_active(ctx->beta0, ctx->active, ctx->kused, ncol, s);
@@ -480,6 +492,10 @@ efe_status run_lanczos(efe_ctx *ctx, double tau, const double *X, double *out, i
   HIP_TRY(hipMemcpy(b0h.data(), ctx->beta0, ncol * sizeof(double), hipMemcpyDeviceToHost));
   for (int c = 0; c < ncol; ++c)
     if (!std::isfinite(b0h[c])) { ctx->err = "non-finite input orbital"; return EFE_ERR_NONFINITE; }
+  // Each iteration: w = A q_j; classical Gram-Schmidt of w against q_1..q_j
+  // (this pass contains the three-term recurrence: its q_j coefficient is
+  // alpha_j); a second pass for the columns where the first one cancelled
+  // most of w; beta_j = ||w||; tridiagonal exponential and stopping test.
   int j = 0;
   while (any) {
     ++j;
@@ -487,20 +503,17 @@ efe_status run_lanczos(efe_ctx *ctx, double tau, const double *X, double *out, i
     EFE_TRY(apply_op(ctx, q, ctx->W, ncolr, ncolr));
     tstart(ctx, 2);
     double *a_j = ctx->alpha + (int64_t)(j - 1) * ncol;
-    nb = efe::k::multidot_partials(q, 0, 1, ctx->W, nrows, ncol, ctx->active, ctx->red, s);
-    efe::k::reduce_partials(ctx->red, nb, ncolr, tmp, s);
-    efe::k::store_re(tmp, a_j, ncol, 0, ctx->active, s);
-    efe::k::three_term(ctx->W, q, j > 1 ? q - bs : nullptr, a_j, j > 1 ? ctx->beta + (int64_t)(j - 2) * ncol : nullptr,
-                       nrows, ncol, ctx->active, s);
-    for (int pass = 0; pass < 2; ++pass) {
-      nb = efe::k::multidot_partials(ctx->Q, bs, j, ctx->W, nrows, ncol, ctx->active, ctx->red, s);
-      efe::k::reduce_partials(ctx->red, nb, j * ncolr, tmp, s);
-      efe::k::multi_update(ctx->Q, bs, j, tmp, ctx->W, nrows, ncol, ctx->active, s);
-    }
     double *b_j = ctx->beta + (int64_t)(j - 1) * ncol;
-    nb = efe::k::multidot_partials(ctx->W, 0, 1, ctx->W, nrows, ncol, ctx->active, ctx->red, s);
-    efe::k::reduce_partials(ctx->red, nb, ncolr, tmp, s);
-    efe::k::store_re(tmp, b_j, ncol, 1, ctx->active, s);
+    nb = efe::k::dots_partials(ctx->Q, bs, j, ctx->W, nrows, ncol, ctx->active, 1, nullptr, ctx->red, s);
+    efe::k::reduce_partials(ctx->red, nb, (j + 1) * ncolr, ctx->h1, s);
+    nb = efe::k::update_norm_partials(ctx->Q, bs, j, ctx->h1, ctx->W, nrows, ncol, ctx->active, ctx->one, ctx->red, s);
+    efe::k::reduce_partials(ctx->red, nb, ncolr, ctx->nrm2, s);
+    efe::k::cgs_decide(ctx->h1, ctx->nrm2, j, ncol, ctx->active, a_j, ctx->nrm1, ctx->need, ctx->anyflag, s);
+    nb = efe::k::dots_partials(ctx->Q, bs, j, ctx->W, nrows, ncol, ctx->need, 0, ctx->anyflag, ctx->red, s);
+    efe::k::reduce_partials(ctx->red, nb, j * ncolr, ctx->h2n, s);
+    nb = efe::k::update_norm_partials(ctx->Q, bs, j, ctx->h2n, ctx->W, nrows, ncol, ctx->need, ctx->anyflag, ctx->red, s);
+    efe::k::reduce_partials(ctx->red, nb, ncolr, ctx->nrm2, s);
+    efe::k::cgs_beta(ctx->nrm1, ctx->nrm2, ctx->need, ctx->active, ncol, b_j, s);
     tstop(ctx, 2);
     tstart(ctx, 3);
     efe::k::tridiag_exp(ctx->alpha, ctx->beta, j, ncol, kmax, tau, ctx->beta0, kf, tol, ctx->active, ctx->kused,

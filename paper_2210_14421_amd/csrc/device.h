@@ -64,6 +64,8 @@ struct DevData {
 // Kernel launchers (stream-ordered, no synchronisation).
 namespace k {
 
+constexpr int kDotBlocksMax = 1024;   // partial blocks of the column reductions
+
 void zero(double *p, int64_t n, hipStream_t s);
 void copy_rows(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t nrows, int ncolr, hipStream_t s);
 void axpby(const double *x, const double *y, double a, double b, double *out, int64_t n, hipStream_t s);
@@ -96,9 +98,17 @@ void reduce_partials(const double *part, int nblk, int nval, double *out, hipStr
 void dipole_partials(const DevData &d, const double *rho, double *part, int *nblk, hipStream_t s);
 
 // Lanczos
-int coldot_partials(const double *A, const double *B, int64_t nrows, int ncol, double *part, hipStream_t s);
 int multidot_partials(const double *Q, int64_t qstride, int nq, const double *w, int64_t nrows, int ncol,
                       const int *active, double *part, hipStream_t s);
+int norm_partials(const double *w, int64_t nrows, int ncol, const int *active, double *part, hipStream_t s);
+int dots_partials(const double *Q, int64_t qstride, int nq, const double *w, int64_t nrows, int ncol,
+                  const int *active, int with_norm, const int *any, double *part, hipStream_t s);
+int update_norm_partials(const double *Q, int64_t qstride, int nq, const double *h, double *w, int64_t nrows, int ncol,
+                         const int *need, const int *any, double *part, hipStream_t s);
+void cgs_decide(const double *h1n, const double *nrm1_sum, int j, int ncol, const int *active, double *alpha_j,
+                double *nrm1, int *need, int *any, hipStream_t s);
+void cgs_beta(const double *nrm1, const double *nrm2, const int *need, const int *active, int ncol, double *beta_j,
+              hipStream_t s);
 void multi_update(const double *Q, int64_t qstride, int nq, const double *h, double *w, int64_t nrows,
                   int ncol, const int *active, hipStream_t s);
 void three_term(double *w, const double *q, const double *qm1, const double *alpha, const double *beta,

@@ -43,63 +43,65 @@ template <> struct Mfma<float> {
 };
 
 template <typename T, int MTW, int NTW>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 k_cell_apply(const DevData d, const int *__restrict__ cell_list, const T *__restrict__ cells,
              const double *__restrict__ X, double *__restrict__ Y, int ncolr, int64_t ldr) {
   typedef typename Mfma<T>::C C;
   typedef typename Mfma<T>::Acc Acc;
-  constexpr int KC = 8;
-  constexpr int MS = MTW * 32 + 4;      // LDS row stride of the A chunk
+  constexpr int NT = 512;               // 8 waves: 4 along M x 2 along N
+  constexpr int KC = 8;                 // K rows per chunk
+  constexpr int MROWS = MTW * 64;       // M rows covered by the workgroup
+  constexpr int MS = MROWS + 4;         // LDS row stride of the A chunk
   constexpr int NCH = NTW * 32;         // columns per workgroup
   constexpr int NS = NCH + 4;
-  constexpr int LA = (KC * MTW * 32 + 255) / 256;
-  constexpr int LB = (KC * NCH + 255) / 256;
+  constexpr int LA = (KC * MROWS + NT - 1) / NT;
+  constexpr int LB = (KC * NCH + NT - 1) / NT;
   __shared__ C As[2][KC][MS];
   __shared__ C Bs[2][KC][NS];
-  __shared__ int64_t rowoff[MTW * 32];
+  __shared__ int64_t rowoff[MROWS];
 
   const Geom &g = d.g;
   const int nloc = g.nloc;
+  const int mt_total = (nloc + 15) / 16;
   const int64_t cell = cell_list[blockIdx.x];
   const int col0 = blockIdx.y * NCH;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   int e[3];
   cell_ijk(g, cell, e);
-  for (int l = tid; l < MTW * 32; l += 256) rowoff[l] = l < nloc ? local_node(g, e, l) * ldr : 0;
-  // zero the padded rows of both A buffers once (loaders only write m < nloc)
-  for (int t = tid; t < 2 * KC * MS; t += 256) (&As[0][0][0])[t] = (C)0;
+  for (int l = tid; l < MROWS; l += NT) rowoff[l] = l < nloc ? local_node(g, e, l) * ldr : 0;
+  for (int t = tid; t < 2 * KC * MS; t += NT) (&As[0][0][0])[t] = (C)0;   // padded rows stay zero
   __syncthreads();
 
   const T *A = cells + cell * (int64_t)nloc * nloc;
   const int nkc = (nloc + KC - 1) / KC;
-  C ra[LA], rb[LB];
-  auto load_chunk = [&](int kc) {
+  C ra0[LA], rb0[LB], ra1[LA], rb1[LB];
+  auto load_chunk = [&](int kc, C (&ra)[LA], C (&rb)[LB]) {
 #pragma unroll
     for (int s = 0; s < LA; ++s) {
-      int t = tid + s * 256;
+      int t = tid + s * NT;
       int kk = t / nloc, m = t - kk * nloc;
       int k = kc * KC + kk;
       ra[s] = (kk < KC && k < nloc) ? (C)A[(int64_t)k * nloc + m] : (C)0;
     }
 #pragma unroll
     for (int s = 0; s < LB; ++s) {
-      int t = tid + s * 256;
+      int t = tid + s * NT;
       int kk = t / NCH, n = t - kk * NCH;
       int k = kc * KC + kk;
       rb[s] = (kk < KC && k < nloc && col0 + n < ncolr) ? (C)X[rowoff[k] + col0 + n] : (C)0;
     }
   };
-  auto store_chunk = [&](int buf) {
+  auto store_chunk = [&](int buf, const C (&ra)[LA], const C (&rb)[LB]) {
 #pragma unroll
     for (int s = 0; s < LA; ++s) {
-      int t = tid + s * 256;
+      int t = tid + s * NT;
       int kk = t / nloc, m = t - kk * nloc;
       if (kk < KC) As[buf][kk][m] = ra[s];
     }
 #pragma unroll
     for (int s = 0; s < LB; ++s) {
-      int t = tid + s * 256;
+      int t = tid + s * NT;
       int kk = t / NCH, n = t - kk * NCH;
       if (kk < KC) Bs[buf][kk][n] = rb[s];
     }
@@ -110,14 +112,8 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, const T *__rest
   for (int i = 0; i < MTW; ++i)
 #pragma unroll
     for (int j = 0; j < NTW; ++j) acc[i][j] = Acc{0, 0, 0, 0};
-
-  load_chunk(0);
-  store_chunk(0);
-  __syncthreads();
   const int kr = lane >> 4, cl = lane & 15;
-  for (int kc = 0; kc < nkc; ++kc) {
-    const int buf = kc & 1;
-    if (kc + 1 < nkc) load_chunk(kc + 1);
+  auto compute = [&](int buf) {
 #pragma unroll
     for (int ks = 0; ks < KC / 4; ++ks) {
       C a[MTW], b[NTW];
@@ -127,10 +123,29 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, const T *__rest
       for (int nt = 0; nt < NTW; ++nt) b[nt] = Bs[buf][ks * 4 + kr][(wn * NTW + nt) * 16 + cl];
 #pragma unroll
       for (int mt = 0; mt < MTW; ++mt)
+        if (wm * MTW + mt < mt_total) {
 #pragma unroll
-        for (int nt = 0; nt < NTW; ++nt) acc[mt][nt] = Mfma<T>::mma(a[mt], b[nt], acc[mt][nt]);
+          for (int nt = 0; nt < NTW; ++nt) acc[mt][nt] = Mfma<T>::mma(a[mt], b[nt], acc[mt][nt]);
+        }
     }
-    if (kc + 1 < nkc) store_chunk(buf ^ 1);
+  };
+
+  // Pipeline: chunk kc is computed from LDS buffer kc&1 while chunk kc+1 sits in
+  // registers waiting to be stored and chunk kc+2 is being loaded.
+  load_chunk(0, ra0, rb0);
+  store_chunk(0, ra0, rb0);
+  if (1 < nkc) load_chunk(1, ra1, rb1);
+  if (2 < nkc) load_chunk(2, ra0, rb0);
+  __syncthreads();
+  for (int kc = 0; kc < nkc; kc += 2) {
+    compute(0);
+    if (kc + 1 < nkc) store_chunk(1, ra1, rb1);
+    if (kc + 3 < nkc) load_chunk(kc + 3, ra1, rb1);
+    __syncthreads();
+    if (kc + 1 >= nkc) break;
+    compute(1);
+    if (kc + 2 < nkc) store_chunk(0, ra0, rb0);
+    if (kc + 4 < nkc) load_chunk(kc + 4, ra0, rb0);
     __syncthreads();
   }
   // D layout of the 16x16 MFMA (differs between the f64 and f32 forms)
@@ -149,27 +164,51 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, const T *__rest
 // ---------------------------------------------------------------------------
 // Enrichment coupling: Y_C[r] += G[r] X_E ;  Y_E = G^T X_C[R] + Hbar^ee X_E
 // ---------------------------------------------------------------------------
+// Y_C[rows] += G X_E: a block stages 32 rows of G and all of X_E in LDS; a
+// thread owns one row and a group of 4 columns.
+constexpr int kRowChunk = 32;
+constexpr int kCoupleBlocks = 1024;
 __global__ void __launch_bounds__(256)
 k_couple_c(const DevData d, const double *__restrict__ G, const double *__restrict__ X, double *__restrict__ Y,
            int ncolr, int64_t ldr) {
-  extern __shared__ double xe[];     // nk * ncolr
+  extern __shared__ double sm[];
   const int nk = d.nk;
+  double *xe = sm;                       // nk * ncolr
+  double *gs = xe + nk * ncolr;          // kRowChunk * nk
   for (int t = threadIdx.x; t < nk * ncolr; t += blockDim.x) {
     int k = t / ncolr, c = t % ncolr;
     xe[t] = X[(d.g.n_nodes + k) * ldr + c];
   }
-  __syncthreads();
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= d.nr * ncolr) return;
-  const int64_t r = t / ncolr;
-  const int c = (int)(t % ncolr);
-  const double *gr = G + r * nk;
-  double s = 0.0;
-  for (int k = 0; k < nk; ++k) s += gr[k] * xe[k * ncolr + c];
-  Y[d.urow_node[r] * ldr + c] += s;
+  const int ng = (ncolr + 3) / 4;
+  for (int64_t rc = (int64_t)blockIdx.x * kRowChunk; rc < d.nr; rc += (int64_t)gridDim.x * kRowChunk) {
+    const int nrow = (int)(d.nr - rc < kRowChunk ? d.nr - rc : kRowChunk);
+    __syncthreads();
+    for (int t = threadIdx.x; t < nrow * nk; t += blockDim.x) gs[t] = G[rc * nk + t];
+    __syncthreads();
+    for (int t = threadIdx.x; t < nrow * ng; t += blockDim.x) {
+      const int rr = t / ng, c0 = (t % ng) * 4;
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      const double *gr = gs + rr * nk;
+      for (int k = 0; k < nk; ++k) {
+        const double gv = gr[k];
+        const double *xr = xe + k * ncolr + c0;
+        a0 += gv * xr[0];
+        if (c0 + 1 < ncolr) a1 += gv * xr[1];
+        if (c0 + 2 < ncolr) a2 += gv * xr[2];
+        if (c0 + 3 < ncolr) a3 += gv * xr[3];
+      }
+      double *y = Y + d.urow_node[rc + rr] * ldr + c0;
+      y[0] += a0;
+      if (c0 + 1 < ncolr) y[1] += a1;
+      if (c0 + 2 < ncolr) y[2] += a2;
+      if (c0 + 3 < ncolr) y[3] += a3;
+    }
+  }
 }
 
-constexpr int kRowChunk = 32;
+// Split-K partial of Y_E = G^T X_C[R]: part[blk][kappa][col] over the block's
+// rows; a thread owns a 4 x 4 tile of (kappa, col) outputs.
+template <int S>
 __global__ void __launch_bounds__(256)
 k_couple_e_partial(const DevData d, const double *__restrict__ G, const double *__restrict__ X, int ncolr,
                    int64_t ldr, int64_t rows_per_blk, double *__restrict__ part) {
@@ -178,34 +217,54 @@ k_couple_e_partial(const DevData d, const double *__restrict__ G, const double *
   double *gs = sm;                       // kRowChunk * nk
   double *xs = gs + kRowChunk * nk;      // kRowChunk * ncolr
   const int nout = nk * ncolr;
+  const int tk = (nk + 3) / 4, tc = (ncolr + 3) / 4, ntile = tk * tc;
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
   const int64_t r1 = r0 + rows_per_blk < d.nr ? r0 + rows_per_blk : d.nr;
-  for (int o0 = 0; o0 < nout; o0 += 256 * 4) {
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t rc = r0; rc < r1; rc += kRowChunk) {
-      const int nrow = (int)(r1 - rc < kRowChunk ? r1 - rc : kRowChunk);
-      __syncthreads();
-      for (int t = threadIdx.x; t < nrow * nk; t += blockDim.x) gs[t] = G[rc * nk + t];
-      for (int t = threadIdx.x; t < nrow * ncolr; t += blockDim.x) {
-        int rr = t / ncolr, c = t % ncolr;
-        xs[t] = X[d.urow_node[rc + rr] * ldr + c];
-      }
-      __syncthreads();
+  double acc[S][4][4];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        int o = o0 + threadIdx.x + s * 256;
-        if (o < nout) {
-          int k = o / ncolr, c = o % ncolr;
-          double a = 0.0;
-          for (int rr = 0; rr < nrow; ++rr) a += gs[rr * nk + k] * xs[rr * ncolr + c];
-          acc[s] += a;
+  for (int s = 0; s < S; ++s)
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[s][a][b] = 0.0;
+  for (int64_t rc = r0; rc < r1; rc += kRowChunk) {
+    const int nrow = (int)(r1 - rc < kRowChunk ? r1 - rc : kRowChunk);
+    __syncthreads();
+    for (int t = threadIdx.x; t < kRowChunk * nk; t += blockDim.x) gs[t] = t < nrow * nk ? G[rc * nk + t] : 0.0;
+    for (int t = threadIdx.x; t < kRowChunk * ncolr; t += blockDim.x) {
+      int rr = t / ncolr, c = t % ncolr;
+      xs[t] = rr < nrow ? X[d.urow_node[rc + rr] * ldr + c] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const int tile = threadIdx.x + s * 256;
+      if (tile < ntile) {
+        const int k0 = (tile / tc) * 4, c0 = (tile % tc) * 4;
+        for (int rr = 0; rr < nrow; ++rr) {
+          double gv[4], xv[4];
+#pragma unroll
+          for (int a = 0; a < 4; ++a) gv[a] = k0 + a < nk ? gs[rr * nk + k0 + a] : 0.0;
+#pragma unroll
+          for (int b = 0; b < 4; ++b) xv[b] = c0 + b < ncolr ? xs[rr * ncolr + c0 + b] : 0.0;
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[s][a][b] += gv[a] * xv[b];
         }
       }
     }
+  }
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      int o = o0 + threadIdx.x + s * 256;
-      if (o < nout) part[(int64_t)blockIdx.x * nout + o] = acc[s];
+  for (int s = 0; s < S; ++s) {
+    const int tile = threadIdx.x + s * 256;
+    if (tile < ntile) {
+      const int k0 = (tile / tc) * 4, c0 = (tile % tc) * 4;
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          if (k0 + a < nk && c0 + b < ncolr) part[(int64_t)blockIdx.x * nout + (k0 + a) * ncolr + c0 + b] = acc[s][a][b];
     }
   }
 }
@@ -226,51 +285,149 @@ __global__ void k_couple_e_final(const DevData d, const double *__restrict__ par
 // ---------------------------------------------------------------------------
 // Lanczos vector kernels.  Blocks are n_rows x ncol complex, packed (ld = ncol).
 // ---------------------------------------------------------------------------
-constexpr int LCH = 8;
+constexpr int LCH = 8;       // LDS reduction chunk (vectors)
+constexpr int kDotBlocks = k::kDotBlocksMax;
 
-// part[blk][l][c][re, im] = sum_r conj(Q_l[r][c]) w[r][c], l < nq
-__global__ void __launch_bounds__(256)
-k_multidot(const double *__restrict__ Q, int64_t qstride, int nq, const double *__restrict__ w, int64_t nrows,
-           int ncol, const int *__restrict__ active, double *__restrict__ part) {
-  extern __shared__ double red[];    // R * LCH * ncol * 2
-  const int R = blockDim.x / ncol;
-  const int c = threadIdx.x % ncol, r0 = threadIdx.x / ncol;
-  const bool on = r0 < R && (active == nullptr || active[c] != 0);
-  for (int l0 = 0; l0 < nq; l0 += LCH) {
-    double are[LCH], aim[LCH];
-#pragma unroll
-    for (int l = 0; l < LCH; ++l) are[l] = aim[l] = 0.0;
-    if (on) {
-      for (int64_t r = (int64_t)blockIdx.x * R + r0; r < nrows; r += (int64_t)gridDim.x * R) {
-        const int64_t o = (r * ncol + c) * 2;
-        const double wr = w[o], wi = w[o + 1];
-#pragma unroll
-        for (int l = 0; l < LCH; ++l)
-          if (l0 + l < nq) {
-            const double *q = Q + (int64_t)(l0 + l) * qstride + o;
-            const double qr = q[0], qi = q[1];
-            are[l] += qr * wr + qi * wi;
-            aim[l] += qr * wi - qi * wr;
-          }
-      }
-    }
+// Reduce per-thread accumulators acc[l][2] (l < nv) of the R row groups of a
+// block into part[blockIdx.x][l][c][2].  red: LDS of R * LCH * ncol * 2 doubles.
+template <int NV>
+__device__ __forceinline__ void block_reduce_cols(const double (&acc)[NV][2], int nv, int R, int r0, int c, int ncol,
+                                                  double *red, double *__restrict__ part) {
+  for (int l0 = 0; l0 < nv; l0 += LCH) {
     __syncthreads();
     if (r0 < R) {
 #pragma unroll
       for (int l = 0; l < LCH; ++l) {
-        red[((r0 * LCH + l) * ncol + c) * 2] = are[l];
-        red[((r0 * LCH + l) * ncol + c) * 2 + 1] = aim[l];
+        int ll = l0 + l;
+        double re = 0.0, im = 0.0;
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+          if (k == ll) { re = acc[k][0]; im = acc[k][1]; }
+        red[((r0 * LCH + l) * ncol + c) * 2] = re;
+        red[((r0 * LCH + l) * ncol + c) * 2 + 1] = im;
       }
     }
     __syncthreads();
     for (int t = threadIdx.x; t < LCH * ncol * 2; t += blockDim.x) {
       int l = t / (ncol * 2);
-      if (l0 + l >= nq) continue;
-      double s = 0.0;
-      for (int rr = 0; rr < R; ++rr) s += red[rr * LCH * ncol * 2 + t];
-      part[((int64_t)blockIdx.x * nq + l0) * ncol * 2 + t] = s;
+      if (l0 + l >= nv) continue;
+      double sum = 0.0;
+      for (int rr = 0; rr < R; ++rr) sum += red[rr * LCH * ncol * 2 + t];
+      part[((int64_t)blockIdx.x * nv + l0) * ncol * 2 + t] = sum;
     }
   }
+}
+
+// part[blk][l][c] = sum_r conj(Q_l[r][c]) w[r][c] for l < nq (one pass over the
+// rows, nq <= NL); with_norm adds entry nq = ||w||^2 per column.
+template <int NL>
+__global__ void __launch_bounds__(256)
+k_dots(const double *__restrict__ Q, int64_t qstride, int nq, const double *__restrict__ w, int64_t nrows, int ncol,
+       const int *__restrict__ active, int with_norm, const int *__restrict__ any, double *__restrict__ part) {
+  if (any && *any == 0) return;
+  extern __shared__ double red[];
+  const int R = blockDim.x / ncol;
+  const int c = threadIdx.x % ncol, r0 = threadIdx.x / ncol;
+  const bool on = r0 < R && (active == nullptr || active[c] != 0);
+  double acc[NL + 1][2];
+#pragma unroll
+  for (int l = 0; l <= NL; ++l) acc[l][0] = acc[l][1] = 0.0;
+  if (on) {
+    for (int64_t r = (int64_t)blockIdx.x * R + r0; r < nrows; r += (int64_t)gridDim.x * R) {
+      const int64_t o = (r * ncol + c) * 2;
+      const double wr = w[o], wi = w[o + 1];
+#pragma unroll
+      for (int l = 0; l < NL; ++l)
+        if (l < nq) {
+          const double *q = Q + (int64_t)l * qstride + o;
+          const double qr = q[0], qi = q[1];
+          acc[l][0] += qr * wr + qi * wi;
+          acc[l][1] += qr * wi - qi * wr;
+        }
+      acc[NL][0] += wr * wr + wi * wi;
+    }
+  }
+  if (with_norm) {
+    // move the norm to slot nq
+#pragma unroll
+    for (int l = 0; l < NL; ++l)
+      if (l == nq) { acc[l][0] = acc[NL][0]; acc[l][1] = 0.0; }
+  }
+  block_reduce_cols<NL + 1>(acc, nq + (with_norm ? 1 : 0), R, r0, c, ncol, red, part);
+}
+
+// Classical Gram-Schmidt update w -= sum_{l<nq} h[l][c] Q_l for the columns
+// with need[c] != 0, and the partial ||w||^2 of the updated vector.  If *any
+// is 0 the kernel returns at once.
+template <int NL>
+__global__ void __launch_bounds__(256)
+k_update_norm(const double *__restrict__ Q, int64_t qstride, int nq, const double *__restrict__ h,
+              double *__restrict__ w, int64_t nrows, int ncol, const int *__restrict__ need,
+              const int *__restrict__ any, double *__restrict__ part) {
+  if (*any == 0) return;
+  extern __shared__ double sm[];
+  const int R = blockDim.x / ncol;
+  double *hs = sm;
+  double *red = sm + NL * ncol * 2;
+  for (int t = threadIdx.x; t < nq * ncol * 2; t += blockDim.x) hs[t] = h[t];
+  __syncthreads();
+  const int c = threadIdx.x % ncol, r0 = threadIdx.x / ncol;
+  const bool on = r0 < R && need[c] != 0;
+  double acc[1][2] = {{0.0, 0.0}};
+  if (on) {
+    for (int64_t r = (int64_t)blockIdx.x * R + r0; r < nrows; r += (int64_t)gridDim.x * R) {
+      const int64_t o = (r * ncol + c) * 2;
+      double wr = w[o], wi = w[o + 1];
+#pragma unroll
+      for (int l = 0; l < NL; ++l)
+        if (l < nq) {
+          const double *q = Q + (int64_t)l * qstride + o;
+          const double qr = q[0], qi = q[1];
+          const double hr = hs[(l * ncol + c) * 2], hi = hs[(l * ncol + c) * 2 + 1];
+          wr -= hr * qr - hi * qi;
+          wi -= hr * qi + hi * qr;
+        }
+      w[o] = wr;
+      w[o + 1] = wi;
+      acc[0][0] += wr * wr + wi * wi;
+    }
+  }
+  block_reduce_cols<1>(acc, 1, R, r0, c, ncol, red, part);
+}
+
+// Daniel-Gragg-Kaufman-Stewart test after the first Gram-Schmidt pass: the
+// pass lost at most eps ||w|| / ||w'|| of orthogonality, so a second pass is
+// made only for columns with ||w'|| < kReorthEta ||w|| (heavy cancellation).
+// Sets alpha_j = Re h1_{j-1}, the first-pass norm, need[c] and any.
+constexpr double kReorthEta = 1e-3;
+__global__ void k_cgs_decide(const double *__restrict__ h1n, const double *__restrict__ nrm1_part, int j, int ncol,
+                             const int *__restrict__ active, double *__restrict__ alpha_j, double *__restrict__ nrm1,
+                             int *__restrict__ need, int *__restrict__ any) {
+  __shared__ int flag;
+  if (threadIdx.x == 0) flag = 0;
+  __syncthreads();
+  for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
+    int nd = 0;
+    if (active[c]) {
+      alpha_j[c] = h1n[((j - 1) * ncol + c) * 2];
+      const double w2 = h1n[(j * ncol + c) * 2];     // ||w||^2 before the pass
+      const double n2 = nrm1_part[2 * c];             // ||w'||^2 after it
+      nrm1[c] = n2;
+      nd = n2 < kReorthEta * kReorthEta * w2 ? 1 : 0;
+    }
+    need[c] = nd;
+    if (nd) atomicOr(&flag, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *any = flag;
+}
+
+__global__ void k_cgs_beta(const double *__restrict__ nrm1, const double *__restrict__ nrm2, const int *__restrict__ need,
+                           const int *__restrict__ active, int ncol, double *__restrict__ beta_j) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncol || !active[c]) return;
+  const double v = need[c] ? nrm2[2 * c] : nrm1[c];
+  beta_j[c] = sqrt(v > 0.0 ? v : 0.0);
 }
 
 // w[r][c] -= sum_l h[l][c] Q_l[r][c]   (complex), active columns only
@@ -472,12 +629,12 @@ void launch_apply_m(const DevData &d, const T *cells, const double *X, double *Y
     if (cnt == 0) continue;
     const int *list = d.colour_cells + d.colour_off[c];
     if (ncolr <= 32) {
-      hipLaunchKernelGGL((k_cell_apply<T, MTW, 1>), dim3(cnt, 1), dim3(256), 0, s, d, list, cells, X, Y, ncolr, ldr);
+      hipLaunchKernelGGL((k_cell_apply<T, MTW, 1>), dim3(cnt, 1), dim3(512), 0, s, d, list, cells, X, Y, ncolr, ldr);
     } else if (ncolr <= 64) {
-      hipLaunchKernelGGL((k_cell_apply<T, MTW, 2>), dim3(cnt, 1), dim3(256), 0, s, d, list, cells, X, Y, ncolr, ldr);
+      hipLaunchKernelGGL((k_cell_apply<T, MTW, 2>), dim3(cnt, 1), dim3(512), 0, s, d, list, cells, X, Y, ncolr, ldr);
     } else {
       unsigned nch = (unsigned)((ncolr + 95) / 96);
-      hipLaunchKernelGGL((k_cell_apply<T, MTW, 3>), dim3(cnt, nch), dim3(256), 0, s, d, list, cells, X, Y, ncolr, ldr);
+      hipLaunchKernelGGL((k_cell_apply<T, MTW, 3>), dim3(cnt, nch), dim3(512), 0, s, d, list, cells, X, Y, ncolr, ldr);
     }
   }
 }
@@ -485,12 +642,11 @@ void launch_apply_m(const DevData &d, const T *cells, const double *X, double *Y
 template <typename T>
 void launch_apply(const DevData &d, const T *cells, const double *X, double *Y, int ncolr, int64_t ldr, hipStream_t s) {
   const int mt = (d.g.nloc + 15) / 16;
-  const int mtw = (mt + 1) / 2;
+  const int mtw = (mt + 3) / 4;
   if (mtw <= 1) launch_apply_m<T, 1>(d, cells, X, Y, ncolr, ldr, s);
   else if (mtw <= 2) launch_apply_m<T, 2>(d, cells, X, Y, ncolr, ldr, s);
   else if (mtw <= 4) launch_apply_m<T, 4>(d, cells, X, Y, ncolr, ldr, s);
-  else if (mtw <= 7) launch_apply_m<T, 7>(d, cells, X, Y, ncolr, ldr, s);
-  else launch_apply_m<T, 11>(d, cells, X, Y, ncolr, ldr, s);
+  else launch_apply_m<T, 6>(d, cells, X, Y, ncolr, ldr, s);
 }
 
 }  // namespace
@@ -506,35 +662,88 @@ void cell_apply(const DevData &d, const void *cells, int dtype, const double *X,
 void couple_apply(const DevData &d, const double *G, const double *Hee, const double *X, double *Y, int ncolr,
                   int64_t ldr, double *scratch, hipStream_t s) {
   if (d.nk == 0) return;
-  size_t lds = (size_t)d.nk * ncolr * sizeof(double);
-  if (d.nr > 0)
-    hipLaunchKernelGGL(k_couple_c, dim3(nblocks(d.nr * ncolr, 256)), dim3(256), lds, s, d, G, X, Y, ncolr, ldr);
   int nblk = 1;
-  int64_t rpb = d.nr;
+  const int nout = d.nk * ncolr;
   if (d.nr > 0) {
-    nblk = (int)std::min<int64_t>(512, (d.nr + 255) / 256);
-    rpb = (d.nr + nblk - 1) / nblk;
+    size_t lds = ((size_t)d.nk * ncolr + (size_t)kRowChunk * d.nk) * sizeof(double);
+    unsigned nb = (unsigned)std::min<int64_t>(kCoupleBlocks, (d.nr + kRowChunk - 1) / kRowChunk);
+    hipLaunchKernelGGL(k_couple_c, dim3(nb), dim3(256), lds, s, d, G, X, Y, ncolr, ldr);
+    nblk = (int)std::min<int64_t>(kCoupleBlocks, (d.nr + 127) / 128);
+    int64_t rpb = (d.nr + nblk - 1) / nblk;
     size_t lds2 = (size_t)kRowChunk * (d.nk + ncolr) * sizeof(double);
-    hipLaunchKernelGGL(k_couple_e_partial, dim3(nblk), dim3(256), lds2, s, d, G, X, ncolr, ldr, rpb, scratch);
+    const int ntile = ((d.nk + 3) / 4) * ((ncolr + 3) / 4);
+    const int S = (ntile + 255) / 256;
+    if (S <= 1)
+      hipLaunchKernelGGL(k_couple_e_partial<1>, dim3(nblk), dim3(256), lds2, s, d, G, X, ncolr, ldr, rpb, scratch);
+    else if (S <= 2)
+      hipLaunchKernelGGL(k_couple_e_partial<2>, dim3(nblk), dim3(256), lds2, s, d, G, X, ncolr, ldr, rpb, scratch);
+    else
+      hipLaunchKernelGGL(k_couple_e_partial<4>, dim3(nblk), dim3(256), lds2, s, d, G, X, ncolr, ldr, rpb, scratch);
   } else {
-    k::zero(scratch, (int64_t)d.nk * ncolr, s);
+    k::zero(scratch, (int64_t)nout, s);
   }
-  hipLaunchKernelGGL(k_couple_e_final, dim3(nblocks((int64_t)d.nk * ncolr, 128)), dim3(128), 0, s, d, scratch, nblk, Hee,
-                     X, Y, ncolr, ldr);
+  hipLaunchKernelGGL(k_couple_e_final, dim3(nblocks((int64_t)nout, 128)), dim3(128), 0, s, d, scratch, nblk, Hee, X, Y,
+                     ncolr, ldr);
+}
+
+template <int NL>
+static int launch_dots(const double *Q, int64_t qstride, int nq, const double *w, int64_t nrows, int ncol,
+                       const int *active, int with_norm, const int *any, double *part, hipStream_t s) {
+  int R = 256 / ncol;
+  int nb = (int)std::min<int64_t>(kDotBlocks, (nrows + R - 1) / R);
+  if (nb < 1) nb = 1;
+  size_t lds = (size_t)R * LCH * ncol * 2 * sizeof(double);
+  hipLaunchKernelGGL(k_dots<NL>, dim3(nb), dim3(256), lds, s, Q, qstride, nq, w, nrows, ncol, active, with_norm, any, part);
+  return nb;
+}
+
+int dots_partials(const double *Q, int64_t qstride, int nq, const double *w, int64_t nrows, int ncol,
+                  const int *active, int with_norm, const int *any, double *part, hipStream_t s) {
+  if (nq <= 1) return launch_dots<1>(Q, qstride, nq, w, nrows, ncol, active, with_norm, any, part, s);
+  if (nq <= 8) return launch_dots<8>(Q, qstride, nq, w, nrows, ncol, active, with_norm, any, part, s);
+  if (nq <= 16) return launch_dots<16>(Q, qstride, nq, w, nrows, ncol, active, with_norm, any, part, s);
+  if (nq <= 24) return launch_dots<24>(Q, qstride, nq, w, nrows, ncol, active, with_norm, any, part, s);
+  if (nq <= 32) return launch_dots<32>(Q, qstride, nq, w, nrows, ncol, active, with_norm, any, part, s);
+  if (nq <= 48) return launch_dots<48>(Q, qstride, nq, w, nrows, ncol, active, with_norm, any, part, s);
+  return launch_dots<64>(Q, qstride, nq, w, nrows, ncol, active, with_norm, any, part, s);
 }
 
 int multidot_partials(const double *Q, int64_t qstride, int nq, const double *w, int64_t nrows, int ncol,
                       const int *active, double *part, hipStream_t s) {
+  return dots_partials(Q, qstride, nq, w, nrows, ncol, active, 0, nullptr, part, s);
+}
+
+int norm_partials(const double *w, int64_t nrows, int ncol, const int *active, double *part, hipStream_t s) {
+  return launch_dots<1>(w, 0, 0, w, nrows, ncol, active, 1, nullptr, part, s);
+}
+
+template <int NL>
+static int launch_update_norm(const double *Q, int64_t qstride, int nq, const double *h, double *w, int64_t nrows,
+                              int ncol, const int *need, const int *any, double *part, hipStream_t s) {
   int R = 256 / ncol;
-  int nb = (int)std::min<int64_t>(512, (nrows + R - 1) / R);
+  int nb = (int)std::min<int64_t>(kDotBlocks, (nrows + R - 1) / R);
   if (nb < 1) nb = 1;
-  size_t lds = (size_t)R * LCH * ncol * 2 * sizeof(double);
-  hipLaunchKernelGGL(k_multidot, dim3(nb), dim3(256), lds, s, Q, qstride, nq, w, nrows, ncol, active, part);
+  size_t lds = ((size_t)NL * ncol * 2 + (size_t)R * LCH * ncol * 2) * sizeof(double);
+  hipLaunchKernelGGL(k_update_norm<NL>, dim3(nb), dim3(256), lds, s, Q, qstride, nq, h, w, nrows, ncol, need, any, part);
   return nb;
 }
 
-int coldot_partials(const double *A, const double *B, int64_t nrows, int ncol, double *part, hipStream_t s) {
-  return multidot_partials(A, 0, 1, B, nrows, ncol, nullptr, part, s);
+int update_norm_partials(const double *Q, int64_t qstride, int nq, const double *h, double *w, int64_t nrows, int ncol,
+                         const int *need, const int *any, double *part, hipStream_t s) {
+  if (nq <= 8) return launch_update_norm<8>(Q, qstride, nq, h, w, nrows, ncol, need, any, part, s);
+  if (nq <= 16) return launch_update_norm<16>(Q, qstride, nq, h, w, nrows, ncol, need, any, part, s);
+  if (nq <= 32) return launch_update_norm<32>(Q, qstride, nq, h, w, nrows, ncol, need, any, part, s);
+  return launch_update_norm<64>(Q, qstride, nq, h, w, nrows, ncol, need, any, part, s);
+}
+
+void cgs_decide(const double *h1n, const double *nrm1_sum, int j, int ncol, const int *active, double *alpha_j,
+                double *nrm1, int *need, int *any, hipStream_t s) {
+  hipLaunchKernelGGL(k_cgs_decide, dim3(1), dim3(128), 0, s, h1n, nrm1_sum, j, ncol, active, alpha_j, nrm1, need, any);
+}
+
+void cgs_beta(const double *nrm1, const double *nrm2, const int *need, const int *active, int ncol, double *beta_j,
+              hipStream_t s) {
+  hipLaunchKernelGGL(k_cgs_beta, dim3((ncol + 63) / 64), dim3(64), 0, s, nrm1, nrm2, need, active, ncol, beta_j);
 }
 
 void multi_update(const double *Q, int64_t qstride, int nq, const double *h, double *w, int64_t nrows, int ncol,
