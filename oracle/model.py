@@ -212,44 +212,97 @@ class EFEModel:
         return v
 
     # ------------------------------------------------------------ Hamiltonian
+    def cell_block(self, c, v_q, kinetic=True):
+        """H_c = 1/2 int grad N . grad N + int v N N on cell c (unscaled, eq. (Hmn))."""
+        m = self.mesh
+        pts, w, B, G = self.shape(c)
+        v = v_q[m.q_off[c]:m.q_off[c + 1]]
+        Hc = B.T @ ((w * v)[:, None] * B)
+        if kinetic:
+            Hc += 0.5 * sum(G[d].T @ (w[:, None] * G[d]) for d in range(3))
+        return Hc
+
+    def coupling_on_cell(self, c, v_q, kinetic=True):
+        """Cell c's contributions to H^ce (nloc x ne) and H^ee (ne x ne), from N^E at its points."""
+        m = self.mesh
+        pts, w, B, G = self.shape(c)
+        v = v_q[m.q_off[c]:m.q_off[c + 1]]
+        NE, dNE = self.enrichment_on_cell(c, grad=kinetic)
+        part = B.T @ ((w * v)[:, None] * NE)
+        pee = NE.T @ ((w * v)[:, None] * NE)
+        if kinetic:
+            part += 0.5 * sum(G[d].T @ (w[:, None] * dNE[d]) for d in range(3))
+            pee += 0.5 * sum(dNE[d].T @ (w[:, None] * dNE[d]) for d in range(3))
+        return part, pee
+
+    def coupling(self, v_q, kinetic=True):
+        """H^ce (n_nodes x ne, boundary rows zero) and H^ee."""
+        m = self.mesh
+        ne = self.spec.nenr
+        Hce = np.zeros((m.n_nodes, ne))
+        Hee = np.zeros((ne, ne))
+        for c in self.tcells:
+            part, pee = self.coupling_on_cell(c, v_q, kinetic)
+            np.add.at(Hce, m.cell_nodes(c), part)
+            Hee += pee
+        Hce[self.bnd] = 0.0
+        return Hce, Hee
+
+    def dm12(self):
+        """D^-1/2 with the boundary rows removed."""
+        return (~self.bnd).astype(np.float64) / np.sqrt(self.D)
+
     def hamiltonian(self, v_q, kinetic=True):
         """Hbar as a sparse matrix on the full row layout, eq. (Hmn) + eq. (TDKSDiscrete2)."""
         m = self.mesh
-        ne = self.spec.nenr
         rows, cols, vals = [], [], []
-        Hce = np.zeros((m.n_nodes, ne))
-        Hee = np.zeros((ne, ne))
-        tset = set(self.tcells.tolist())
         for c in range(m.n_cells):
-            pts, w, B, G = self.shape(c)
-            v = v_q[m.q_off[c]:m.q_off[c + 1]]
-            Hc = B.T @ ((w * v)[:, None] * B)
-            if kinetic:
-                Hc += 0.5 * sum(G[d].T @ (w[:, None] * G[d]) for d in range(3))
+            Hc = self.cell_block(c, v_q, kinetic)
             nodes = m.cell_nodes(c)
             rows.append(np.repeat(nodes, len(nodes)))
             cols.append(np.tile(nodes, len(nodes)))
             vals.append(Hc.reshape(-1))
-            if ne > 0 and c in tset:
-                NE, dNE = self.enrichment_on_cell(c, grad=kinetic)
-                part = B.T @ ((w * v)[:, None] * NE)
-                pee = NE.T @ ((w * v)[:, None] * NE)
-                if kinetic:
-                    part += 0.5 * sum(G[d].T @ (w[:, None] * dNE[d]) for d in range(3))
-                    pee += 0.5 * sum(dNE[d].T @ (w[:, None] * dNE[d]) for d in range(3))
-                np.add.at(Hce, nodes, part)
-                Hee += pee
         N = m.n_nodes
         Hcc = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                             shape=(N, N)).tocsr()
-        keep = (~self.bnd).astype(np.float64)
-        dm = keep / np.sqrt(self.D)                  # D^-1/2 with boundary rows removed
+        dm = self.dm12()
         Hbar_cc = sp.diags(dm) @ Hcc @ sp.diags(dm)
+        if self.spec.nenr == 0:
+            return Hbar_cc.tocsr()
+        Hce, Hee = self.coupling(v_q, kinetic)
         Hbar_ce = (dm[:, None] * Hce) @ self.S
         Hbar_ee = self.S.T @ Hee @ self.S
         Hbar = sp.bmat([[Hbar_cc, sp.csr_matrix(Hbar_ce)],
                         [sp.csr_matrix(Hbar_ce.T), sp.csr_matrix(Hbar_ee)]], format="csr")
         return Hbar
+
+    def hamiltonian_rows(self, v_q, X, rows, kinetic=True):
+        """(Hbar X) at the given node rows and at every enrichment row, without assembling Hbar.
+
+        Same definitions as `hamiltonian`: cell blocks of the cells that hold each
+        requested node, and the full coupling H^ce, H^ee.  Returns (Y_rows, Y_E).
+        """
+        m = self.mesh
+        N = m.n_nodes
+        dm = self.dm12()
+        Xc = dm[:, None] * X[:N]
+        Yr = np.zeros((len(rows), X.shape[1]), dtype=np.result_type(X, np.float64))
+        for k, i in enumerate(rows):
+            if self.bnd[i]:
+                continue
+            acc = 0.0
+            for c in m.cells_of_node(int(i)):
+                nodes = m.cell_nodes(c)
+                li = int(np.nonzero(nodes == i)[0][0])
+                acc = acc + self.cell_block(c, v_q, kinetic)[li] @ Xc[nodes]
+            Yr[k] = dm[i] * acc
+        if self.spec.nenr == 0:
+            return Yr, np.zeros((0, X.shape[1]))
+        Hce, Hee = self.coupling(v_q, kinetic)
+        psiE = self.S @ X[N:]
+        Yr += dm[rows][:, None] * (Hce[rows] @ psiE)
+        YE = self.S.T @ (Hce.T @ Xc + Hee @ psiE)
+        return Yr, YE
 
     def position_operator(self, d):
         """Zbar_d: Loewdin position operator (no kinetic term, v = x_d)."""
@@ -310,8 +363,36 @@ class EFEModel:
             np.add.at(d, m.cell_nodes(c), B.T @ (w * rho[m.q_off[c]:m.q_off[c + 1]]))
         return d
 
+    def stiffness_tensor_apply(self, u):
+        """K u over all nodes, K = K1 x M1 x M1 + M1 x K1 x M1 + M1 x M1 x K1 (exact 1-D matrices)."""
+        m = self.mesh
+        K = [self.one_d_matrices(d) for d in range(3)]
+        U = u.reshape(m.nn[2], m.nn[1], m.nn[0])
+        out = np.zeros_like(U)
+        for term in range(3):
+            Ax = K[0][0] if term == 0 else K[0][1]
+            Ay = K[1][0] if term == 1 else K[1][1]
+            Az = K[2][0] if term == 2 else K[2][1]
+            out += np.einsum("zyx,ax,by,cz->cba", U, Ax, Ay, Az, optimize=True)
+        return out.reshape(-1)
+
     def hartree(self, rho, solver="direct", boundary=None):
-        """Nodal v_H: (1/4 pi) K phi = d in the interior, phi = g on the boundary."""
+        """Nodal v_H: (1/4 pi) K phi = d in the interior, phi = g on the boundary.
+
+        solver "fdm" uses the tensor structure of K for both the Dirichlet lift
+        and the interior solve (no assembled matrix; for large meshes)."""
+        m = self.mesh
+        Bn = np.nonzero(self.bnd)[0]
+        if solver == "fdm":
+            g = self.hartree_boundary(m.node_coords(Bn)) if boundary is None else boundary
+            gf = np.zeros(m.n_nodes)
+            gf[Bn] = g
+            d = self.poisson_rhs(rho)
+            rhs = 4.0 * math.pi * d[self.interior] - self.stiffness_tensor_apply(gf)[self.interior]
+            phi = np.zeros(m.n_nodes)
+            phi[self.interior] = self.fdm_solve(rhs)
+            phi[Bn] = g
+            return phi
         if self._poisson is None:
             self._poisson_setup()
         P = self._poisson
@@ -320,8 +401,6 @@ class EFEModel:
         rhs = 4.0 * math.pi * d[self.interior] - P["KIB"] @ g
         if solver == "direct":
             phiI = spla.spsolve(P["KII"], rhs)
-        elif solver == "fdm":
-            phiI = self.fdm_solve(rhs)
         elif solver == "cg":
             phiI, info = spla.cg(P["KII"], rhs, rtol=1e-14, atol=0.0, maxiter=20000)
             if info != 0:
@@ -344,10 +423,10 @@ class EFEModel:
             lams.append(lam)
         n = [len(l) for l in lams]
         r = rhs_interior.reshape(n[2], n[1], n[0])
-        t = np.einsum("zyx,xa,yb,zc->cba", r, Vs[0], Vs[1], Vs[2])
+        t = np.einsum("zyx,xa,yb,zc->cba", r, Vs[0], Vs[1], Vs[2], optimize=True)
         denom = lams[2][:, None, None] + lams[1][None, :, None] + lams[0][None, None, :]
         t = t / denom
-        out = np.einsum("cba,xa,yb,zc->zyx", t, Vs[0], Vs[1], Vs[2])
+        out = np.einsum("cba,xa,yb,zc->zyx", t, Vs[0], Vs[1], Vs[2], optimize=True)
         return out.reshape(-1)
 
     def one_d_matrices(self, d):

@@ -26,6 +26,8 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 // 16x16x4 MFMA accumulates in registers.  Double-buffered LDS, one barrier per
 // chunk.
 // ---------------------------------------------------------------------------
+constexpr int kApplyMaxLoc = 384;   // nloc of degree <= 6 is 343
+
 template <typename T> struct Mfma;
 template <> struct Mfma<double> {
   typedef double C;
@@ -42,111 +44,89 @@ template <> struct Mfma<float> {
   static __device__ __forceinline__ int row(int kr, int r) { return 4 * kr + r; }
 };
 
-template <typename T, int MTW, int NTW>
-__global__ void __launch_bounds__(512)
-k_cell_apply(const DevData d, const int *__restrict__ cell_list, const T *__restrict__ cells,
-             const double *__restrict__ X, double *__restrict__ Y, int ncolr, int64_t ldr) {
+// One wave per (cell, pair of 16-row M tiles, chunk of NTW 16-column N tiles).
+// No LDS staging of operands and no barriers: each lane loads its MFMA
+// operands straight from global memory with a PF-deep register pipeline.
+//   A operand (row i, k):  Hbar_c[k][i]  (symmetric block, row-major: 16 lanes
+//                          read 16 consecutive doubles)
+//   B operand (k, col j):  X[node(k)][col0 + j]  (16 consecutive doubles)
+// The waves of one cell get block ids congruent mod 8, so they run on the same
+// XCD (blocks are dealt to the 8 XCDs round-robin) and share its L2 copy of the
+// cell block and of the gathered rows.
+template <typename T, int NTW, int PF>
+__global__ void __launch_bounds__(64)
+k_cell_apply(const DevData d, const int *__restrict__ cell_list, int ncells, int npair, int nch,
+             const T *__restrict__ cells, const double *__restrict__ X, double *__restrict__ Y, int ncolr,
+             int64_t ldr) {
   typedef typename Mfma<T>::C C;
   typedef typename Mfma<T>::Acc Acc;
-  constexpr int NT = 512;               // 8 waves: 4 along M x 2 along N
-  constexpr int KC = 8;                 // K rows per chunk
-  constexpr int MROWS = MTW * 64;       // M rows covered by the workgroup
-  constexpr int MS = MROWS + 4;         // LDS row stride of the A chunk
-  constexpr int NCH = NTW * 32;         // columns per workgroup
-  constexpr int NS = NCH + 4;
-  constexpr int LA = (KC * MROWS + NT - 1) / NT;
-  constexpr int LB = (KC * NCH + NT - 1) / NT;
-  __shared__ C As[2][KC][MS];
-  __shared__ C Bs[2][KC][NS];
-  __shared__ int64_t rowoff[MROWS];
-
+  constexpr int MTW = 2;
+  __shared__ int64_t rowoff[kApplyMaxLoc];
   const Geom &g = d.g;
   const int nloc = g.nloc;
-  const int mt_total = (nloc + 15) / 16;
-  const int64_t cell = cell_list[blockIdx.x];
-  const int col0 = blockIdx.y * NCH;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int per_cell = npair * nch;
+  const int grp = blockIdx.x / (8 * per_cell), rem = blockIdx.x % (8 * per_cell);
+  const int ci = grp * 8 + rem % 8;
+  if (ci >= ncells) return;
+  const int sub = rem / 8;                  // 0 .. per_cell-1
+  const int pair = sub % npair, ch = sub / npair;
+  const int64_t cell = cell_list[ci];
+  const int lane = threadIdx.x;
+  const int kr = lane >> 4, cl = lane & 15;
   int e[3];
   cell_ijk(g, cell, e);
-  for (int l = tid; l < MROWS; l += NT) rowoff[l] = l < nloc ? local_node(g, e, l) * ldr : 0;
-  for (int t = tid; t < 2 * KC * MS; t += NT) (&As[0][0][0])[t] = (C)0;   // padded rows stay zero
+  for (int l = lane; l < nloc; l += 64) rowoff[l] = local_node(g, e, l) * ldr;
   __syncthreads();
-
   const T *A = cells + cell * (int64_t)nloc * nloc;
-  const int nkc = (nloc + KC - 1) / KC;
-  C ra0[LA], rb0[LB], ra1[LA], rb1[LB];
-  auto load_chunk = [&](int kc, C (&ra)[LA], C (&rb)[LB]) {
+  const int m0 = pair * MTW * 16;
+  const int col0 = ch * NTW * 16;
+  const int nks = (nloc + 3) / 4;           // k-steps of 4
+  // per-lane fixed parts of the operand addresses
+  int arow[MTW];
+  bool aok[MTW];
 #pragma unroll
-    for (int s = 0; s < LA; ++s) {
-      int t = tid + s * NT;
-      int kk = t / nloc, m = t - kk * nloc;
-      int k = kc * KC + kk;
-      ra[s] = (kk < KC && k < nloc) ? (C)A[(int64_t)k * nloc + m] : (C)0;
-    }
+  for (int mt = 0; mt < MTW; ++mt) {
+    arow[mt] = m0 + mt * 16 + cl;
+    aok[mt] = arow[mt] < nloc;
+  }
+  int bcol[NTW];
+  bool bok[NTW];
 #pragma unroll
-    for (int s = 0; s < LB; ++s) {
-      int t = tid + s * NT;
-      int kk = t / NCH, n = t - kk * NCH;
-      int k = kc * KC + kk;
-      rb[s] = (kk < KC && k < nloc && col0 + n < ncolr) ? (C)X[rowoff[k] + col0 + n] : (C)0;
-    }
+  for (int nt = 0; nt < NTW; ++nt) {
+    bcol[nt] = col0 + nt * 16 + cl;
+    bok[nt] = bcol[nt] < ncolr;
+  }
+  C a[PF][MTW], b[PF][NTW];
+  auto load = [&](int ks, C (&av)[MTW], C (&bv)[NTW]) {
+    const int k = ks * 4 + kr;
+    const bool kok = k < nloc;
+    const T *Ak = A + (int64_t)k * nloc;
+#pragma unroll
+    for (int mt = 0; mt < MTW; ++mt) av[mt] = (kok && aok[mt]) ? (C)Ak[arow[mt]] : (C)0;
+    const double *Xk = X + (kok ? rowoff[k] : 0);
+#pragma unroll
+    for (int nt = 0; nt < NTW; ++nt) bv[nt] = (kok && bok[nt]) ? (C)Xk[bcol[nt]] : (C)0;
   };
-  auto store_chunk = [&](int buf, const C (&ra)[LA], const C (&rb)[LB]) {
-#pragma unroll
-    for (int s = 0; s < LA; ++s) {
-      int t = tid + s * NT;
-      int kk = t / nloc, m = t - kk * nloc;
-      if (kk < KC) As[buf][kk][m] = ra[s];
-    }
-#pragma unroll
-    for (int s = 0; s < LB; ++s) {
-      int t = tid + s * NT;
-      int kk = t / NCH, n = t - kk * NCH;
-      if (kk < KC) Bs[buf][kk][n] = rb[s];
-    }
-  };
-
   Acc acc[MTW][NTW];
 #pragma unroll
   for (int i = 0; i < MTW; ++i)
 #pragma unroll
     for (int j = 0; j < NTW; ++j) acc[i][j] = Acc{0, 0, 0, 0};
-  const int kr = lane >> 4, cl = lane & 15;
-  auto compute = [&](int buf) {
+  const bool mt1 = m0 + 16 < nloc;          // second M tile of the pair in range
 #pragma unroll
-    for (int ks = 0; ks < KC / 4; ++ks) {
-      C a[MTW], b[NTW];
+  for (int p = 0; p < PF; ++p) load(p, a[p], b[p]);
+  for (int ks0 = 0; ks0 < nks; ks0 += PF) {
 #pragma unroll
-      for (int mt = 0; mt < MTW; ++mt) a[mt] = As[buf][ks * 4 + kr][(wm * MTW + mt) * 16 + cl];
+    for (int p = 0; p < PF; ++p) {
+      if (ks0 + p < nks) {
 #pragma unroll
-      for (int nt = 0; nt < NTW; ++nt) b[nt] = Bs[buf][ks * 4 + kr][(wn * NTW + nt) * 16 + cl];
-#pragma unroll
-      for (int mt = 0; mt < MTW; ++mt)
-        if (wm * MTW + mt < mt_total) {
-#pragma unroll
-          for (int nt = 0; nt < NTW; ++nt) acc[mt][nt] = Mfma<T>::mma(a[mt], b[nt], acc[mt][nt]);
+        for (int nt = 0; nt < NTW; ++nt) {
+          acc[0][nt] = Mfma<T>::mma(a[p][0], b[p][nt], acc[0][nt]);
+          if (mt1) acc[1][nt] = Mfma<T>::mma(a[p][1], b[p][nt], acc[1][nt]);
         }
+      }
+      if (ks0 + PF + p < nks) load(ks0 + PF + p, a[p], b[p]);
     }
-  };
-
-  // Pipeline: chunk kc is computed from LDS buffer kc&1 while chunk kc+1 sits in
-  // registers waiting to be stored and chunk kc+2 is being loaded.
-  load_chunk(0, ra0, rb0);
-  store_chunk(0, ra0, rb0);
-  if (1 < nkc) load_chunk(1, ra1, rb1);
-  if (2 < nkc) load_chunk(2, ra0, rb0);
-  __syncthreads();
-  for (int kc = 0; kc < nkc; kc += 2) {
-    compute(0);
-    if (kc + 1 < nkc) store_chunk(1, ra1, rb1);
-    if (kc + 3 < nkc) load_chunk(kc + 3, ra1, rb1);
-    __syncthreads();
-    if (kc + 1 >= nkc) break;
-    compute(1);
-    if (kc + 2 < nkc) store_chunk(0, ra0, rb0);
-    if (kc + 4 < nkc) load_chunk(kc + 4, ra0, rb0);
-    __syncthreads();
   }
   // D layout of the 16x16 MFMA (differs between the f64 and f32 forms)
 #pragma unroll
@@ -155,8 +135,8 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, const T *__rest
     for (int nt = 0; nt < NTW; ++nt)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        int row = (wm * MTW + mt) * 16 + Mfma<T>::row(kr, r);
-        int col = col0 + (wn * NTW + nt) * 16 + cl;
+        const int row = m0 + mt * 16 + Mfma<T>::row(kr, r);
+        const int col = col0 + nt * 16 + cl;
         if (row < nloc && col < ncolr) Y[rowoff[row] + col] += (double)acc[mt][nt][r];
       }
 }
@@ -622,31 +602,26 @@ k_combine(const double *__restrict__ Q, int64_t qstride, const double *__restric
 
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-template <typename T, int MTW>
-void launch_apply_m(const DevData &d, const T *cells, const double *X, double *Y, int ncolr, int64_t ldr, hipStream_t s) {
+template <typename T, int NTW>
+void launch_apply_n(const DevData &d, const T *cells, const double *X, double *Y, int ncolr, int64_t ldr, hipStream_t s) {
+  constexpr int PF = 4;
+  const int npair = ((d.g.nloc + 15) / 16 + 1) / 2;
+  const int nch = (ncolr + NTW * 16 - 1) / (NTW * 16);
   for (int c = 0; c < 8; ++c) {
     int cnt = d.colour_off[c + 1] - d.colour_off[c];
     if (cnt == 0) continue;
     const int *list = d.colour_cells + d.colour_off[c];
-    if (ncolr <= 32) {
-      hipLaunchKernelGGL((k_cell_apply<T, MTW, 1>), dim3(cnt, 1), dim3(512), 0, s, d, list, cells, X, Y, ncolr, ldr);
-    } else if (ncolr <= 64) {
-      hipLaunchKernelGGL((k_cell_apply<T, MTW, 2>), dim3(cnt, 1), dim3(512), 0, s, d, list, cells, X, Y, ncolr, ldr);
-    } else {
-      unsigned nch = (unsigned)((ncolr + 95) / 96);
-      hipLaunchKernelGGL((k_cell_apply<T, MTW, 3>), dim3(cnt, nch), dim3(512), 0, s, d, list, cells, X, Y, ncolr, ldr);
-    }
+    const unsigned nx = (unsigned)(((cnt + 7) / 8) * 8) * npair * nch;
+    hipLaunchKernelGGL((k_cell_apply<T, NTW, PF>), dim3(nx), dim3(64), 0, s, d, list, cnt, npair, nch, cells, X, Y,
+                       ncolr, ldr);
   }
 }
 
 template <typename T>
 void launch_apply(const DevData &d, const T *cells, const double *X, double *Y, int ncolr, int64_t ldr, hipStream_t s) {
-  const int mt = (d.g.nloc + 15) / 16;
-  const int mtw = (mt + 3) / 4;
-  if (mtw <= 1) launch_apply_m<T, 1>(d, cells, X, Y, ncolr, ldr, s);
-  else if (mtw <= 2) launch_apply_m<T, 2>(d, cells, X, Y, ncolr, ldr, s);
-  else if (mtw <= 4) launch_apply_m<T, 4>(d, cells, X, Y, ncolr, ldr, s);
-  else launch_apply_m<T, 6>(d, cells, X, Y, ncolr, ldr, s);
+  if (ncolr <= 16) launch_apply_n<T, 1>(d, cells, X, Y, ncolr, ldr, s);
+  else if (ncolr <= 32) launch_apply_n<T, 2>(d, cells, X, Y, ncolr, ldr, s);
+  else launch_apply_n<T, 3>(d, cells, X, Y, ncolr, ldr, s);
 }
 
 }  // namespace

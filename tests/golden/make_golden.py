@@ -16,7 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
-from workloads import tiny, trap  # noqa: E402
+from workloads import tiny, trap, na8 as na8_spec  # noqa: E402
 from oracle.model import EFEModel  # noqa: E402
 from oracle.propagate import scf_ground_state, Propagator  # noqa: E402
 
@@ -57,6 +57,40 @@ def tiny_traj():
     np.savez_compressed(os.path.join(HERE, "tiny_traj.npz"), mu_ground=mu0, mu=np.array(mus),
                         k=np.array(ks, dtype=np.int32), k_kick=k_kick, X_final=P.X,
                         rho_final=P.rho, dt=spec.dt, kick=spec.kick)
+
+
+def na8():
+    """Na8 reference values at sampled rows/points for the full-size GPU parity test.
+
+    Initial orbitals X0 (enrichment directions + seeded noise, Loewdin
+    orthonormalised), rho(X0) at sampled quadrature points, the dipole, the
+    Hartree potential at sampled nodes, and (Hbar[rho(X0), t=0] X0) at sampled
+    node rows and at every enrichment row.
+    """
+    spec = na8_spec()
+    t0 = time.time()
+    m = EFEModel(spec)
+    print(f"na8 model {time.time() - t0:.0f}s", flush=True)
+    X0 = m.enrichment_noise_state()
+    print(f"initial state {time.time() - t0:.0f}s", flush=True)
+    rho = m.density(X0)
+    mu = m.dipole(rho)
+    print(f"density {time.time() - t0:.0f}s  mu={mu}", flush=True)
+    phi = m.hartree(rho, solver="fdm")
+    v = m.ks_potential(rho, m.interpolate_nodal(phi), 0.0, None)
+    print(f"hartree {time.time() - t0:.0f}s", flush=True)
+    rng = np.random.default_rng(2024)
+    N = m.mesh.n_nodes
+    near = np.nonzero(np.any(m.c != 0.0, axis=1))[0]
+    rows = np.unique(np.concatenate([rng.choice(m.interior, 96, replace=False), rng.choice(near, 96, replace=False)]))
+    Yr, YE = m.hamiltonian_rows(v, X0, rows)
+    print(f"Hbar rows {time.time() - t0:.0f}s", flush=True)
+    q_idx = np.sort(rng.choice(m.mesh.n_quad, 8192, replace=False))
+    ph_idx = np.sort(rng.choice(N, 2048, replace=False))
+    np.savez_compressed(os.path.join(HERE, "na8_sampled.npz"), rows=rows, X0_rows=X0[rows], X0_E=X0[N:],
+                        Y_rows=Yr, Y_E=YE, q_idx=q_idx, rho_q=rho[q_idx], rho_sum=float(np.sum(m.qw * rho)),
+                        mu=mu, phi_idx=ph_idx, phi=phi[ph_idx], nk=m.nk)
+    print("na8 done", flush=True)
 
 
 if __name__ == "__main__":

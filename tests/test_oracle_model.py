@@ -174,3 +174,17 @@ def test_hamiltonian_symmetric_and_boundary_free():
     assert abs(H - H.T).max() < 1e-13
     bn = np.nonzero(m.bnd)[0]
     assert abs(H[bn]).max() == 0.0
+
+
+def test_hamiltonian_rows_match_full_matrix():
+    """The row-restricted route (used at full Na8 size) equals the assembled Hbar."""
+    m = EFEModel(tiny())
+    rng = np.random.default_rng(8)
+    v = m.v_nuc + 0.2 * np.cos(m.qpts[:, 1])
+    X = rng.standard_normal((m.n_rows, 2)) + 1j * rng.standard_normal((m.n_rows, 2))
+    X[:m.mesh.n_nodes][m.bnd] = 0.0
+    rows = rng.choice(m.mesh.n_nodes, size=40, replace=False)
+    Yr, YE = m.hamiltonian_rows(v, X, rows)
+    Y = m.hamiltonian(v) @ X
+    np.testing.assert_allclose(Yr, Y[rows], rtol=0, atol=1e-12 * np.abs(Y).max())
+    np.testing.assert_allclose(YE, Y[m.mesh.n_nodes:], rtol=0, atol=1e-12 * np.abs(Y).max())
