@@ -66,6 +66,46 @@ def run_gpu(spec, dtype, steps, warmup, kmax):
     return dict(wall=wall, stage=stage, k=ks, mu=mus, orth=orth, setup_s=setup_s)
 
 
+def traffic_summary(dtype):
+    """HBM traffic of one cell-product launch from the committed rocprofv3 summary.
+
+    The summary records FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by
+    the same counter's reading for a plain copy of known size, and the sha256 of
+    the kernel source it was taken with; it is used only while that source is
+    unchanged (otherwise traffic is reported as null)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "cell_apply_na8_traffic.json")
+    src = os.path.join(ROOT, "paper_2210_14421_amd", "csrc", "kernels_krylov.hip")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if rec.get("kernel_source_sha256") != sha or dtype not in rec.get("per_launch_bytes", {}):
+        return None
+    return rec["per_launch_bytes"][dtype]
+
+
+def run_apply_mode(spec, dtype, n_apply):
+    """Counter-collection workload: Na8 set-up, n_apply Hbar X, then a 1 GiB copy
+    (the calibration kernel of known size for FETCH_SIZE / WRITE_SIZE)."""
+    import torch
+    from paper_2210_14421_amd.efe import Context
+    ctx = Context(spec, dtype=dtype, kmax=4)
+    Psi = ctx.initial_state()
+    ctx.set_hamiltonian(Psi, 0.0)
+    Y = torch.empty_like(Psi)
+    for _ in range(n_apply):
+        ctx.apply_H(Psi, Y)
+    a = torch.full((1 << 27,), 1.0, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    ctx.close()
+    print(json.dumps({"mode": "apply", "dtype": dtype, "n_apply": n_apply, "calibration_copy_bytes": a.numel() * 8}))
+
+
 def roofline(spec, res, dtype):
     """Achieved FLOP/s of the cell-product kernel (all colour launches of every Hbar X)."""
     P = spec.degree + 1
@@ -76,13 +116,14 @@ def roofline(spec, res, dtype):
     n_hx = res["stage"]["n_hx"]
     ms = res["stage"]["cell_hx"]
     achieved = flop_per_hx * n_hx / (ms * 1e-3) / 1e12
+    tr = traffic_summary(dtype)
     return {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s",
-            "frac": achieved / PEAK_TFLOPS[dtype], "traffic": None,
+            "frac": achieved / PEAK_TFLOPS[dtype], "traffic": tr,
             "kernel": "k_cell_apply", "flop_per_hx": flop_per_hx, "hx_per_step": n_hx / max(1, len(res["k"])),
             "ms_per_hx": ms / max(1, n_hx)}
 
 
-def cpu_baseline(spec, hx_per_step, ncells_sample=96):
+def cpu_baseline(spec, hx_per_step, ncells_sample=1536):
     """Time the FP64 oracle's Hbar X (cell route) on a sample of cells and scale to steps/s.
 
     The sample is the oracle's cell-block construction and product on
@@ -133,6 +174,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", default="na8", choices=["na8", "tiny", "na2"])
+    ap.add_argument("--mode", default="step", choices=["step", "apply"])
+    ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -142,6 +185,9 @@ def main():
     from workloads import na8, tiny, na_cluster
     spec = {"na8": na8, "tiny": tiny, "na2": lambda: na_cluster(2, seed=2)}[args.workload]()
     torch.cuda.set_device(0)
+    if args.mode == "apply":
+        run_apply_mode(spec, args.dtype, max(1, args.steps))
+        return
     res = run_gpu(spec, "f64", args.steps, args.warmup, args.kmax)
     value = args.steps / res["wall"]
     roof = roofline(spec, res, "f64")

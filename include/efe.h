@@ -88,8 +88,10 @@ typedef struct {
 } efe_system;
 
 typedef struct {
-  int32_t prod_dtype;      /* EFE_F64 / EFE_F32 / EFE_BF16                        */
-  int32_t kmax;            /* maximum Krylov dimension (1..128)                   */
+  int32_t prod_dtype;      /* EFE_F64 or EFE_F32 (type of the stored cell blocks and of
+                              the cell products); EFE_BF16 is reserved and rejected
+                              with EFE_ERR_ARG                                     */
+  int32_t kmax;            /* maximum Krylov dimension (1..64)                    */
   double krylov_tol;       /* stop when the estimate of eq. (AdaptiveKrylovErr) <= tol * ||psi|| */
   double cg_tol;           /* Poisson: relative residual                          */
   int32_t cg_maxit;

@@ -232,6 +232,9 @@ efe_status build_device(efe_ctx *ctx) {
     d.colour_off[c + 1] = (int)colour.size();
   }
   EFE_TRY(upload(ctx, &d.colour_cells, colour));
+  std::vector<int> slot(pl.n_cells);
+  for (size_t i = 0; i < colour.size(); ++i) slot[colour[i]] = (int)i;
+  EFE_TRY(upload(ctx, &d.cell_slot, slot));
   std::vector<double> Dm12(pl.n_nodes);
   for (int64_t i = 0; i < pl.n_nodes; ++i) Dm12[i] = pl.is_boundary(i) ? 0.0 : 1.0 / std::sqrt(pl.D[i]);
   EFE_TRY(upload(ctx, &d.D, pl.D));
@@ -646,7 +649,7 @@ efe_status efe_plan_get(const efe_plan *plan, const char *name, double *out, int
 efe_status efe_setup(const efe_system *sys, const efe_options *opt, efe_ctx **out) {
   if (!sys || !opt || !out) return EFE_ERR_ARG;
   *out = nullptr;
-  if (opt->prod_dtype < 0 || opt->prod_dtype > 2 || opt->kmax < 1 || opt->kmax > 64) return EFE_ERR_ARG;
+  if (opt->prod_dtype < 0 || opt->prod_dtype > 1 || opt->kmax < 1 || opt->kmax > 64) return EFE_ERR_ARG;
   efe_ctx *ctx = new (std::nothrow) efe_ctx();
   if (!ctx) return EFE_ERR_ALLOC;
   ctx->opt = *opt;

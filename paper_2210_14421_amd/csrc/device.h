@@ -36,6 +36,7 @@ struct DevData {
   int *cells_ord = nullptr, *cells_enr = nullptr;   // ordinary / enrichment cell ids
   int n_ord = 0, n_enr = 0;
   int *colour_cells = nullptr;    // cells grouped by colour
+  int *cell_slot = nullptr;       // n_cells: storage slot of the cell block (colour-major order)
   int colour_off[9] = {0};
   double *D = nullptr, *Dm12 = nullptr;   // lumped mass, D^-1/2 (0 on boundary)
   double *vstatic = nullptr;      // n_quad

@@ -55,7 +55,7 @@ template <> struct Mfma<float> {
 // cell block and of the gathered rows.
 template <typename T, int NTW, int PF>
 __global__ void __launch_bounds__(64)
-k_cell_apply(const DevData d, const int *__restrict__ cell_list, int ncells, int npair, int nch,
+k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, int ncells, int npair, int nch,
              const T *__restrict__ cells, const double *__restrict__ X, double *__restrict__ Y, int ncolr,
              int64_t ldr) {
   typedef typename Mfma<T>::C C;
@@ -77,7 +77,8 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int ncells, int
   cell_ijk(g, cell, e);
   for (int l = lane; l < nloc; l += 64) rowoff[l] = local_node(g, e, l) * ldr;
   __syncthreads();
-  const T *A = cells + cell * (int64_t)nloc * nloc;
+  // blocks are stored in colour-major order: a colour launch streams them contiguously
+  const T *A = cells + (int64_t)(slot0 + ci) * nloc * nloc;
   const int m0 = pair * MTW * 16;
   const int col0 = ch * NTW * 16;
   const int nks = (nloc + 3) / 4;           // k-steps of 4
@@ -612,8 +613,8 @@ void launch_apply_n(const DevData &d, const T *cells, const double *X, double *Y
     if (cnt == 0) continue;
     const int *list = d.colour_cells + d.colour_off[c];
     const unsigned nx = (unsigned)(((cnt + 7) / 8) * 8) * npair * nch;
-    hipLaunchKernelGGL((k_cell_apply<T, NTW, PF>), dim3(nx), dim3(64), 0, s, d, list, cnt, npair, nch, cells, X, Y,
-                       ncolr, ldr);
+    hipLaunchKernelGGL((k_cell_apply<T, NTW, PF>), dim3(nx), dim3(64), 0, s, d, list, d.colour_off[c], cnt, npair, nch,
+                       cells, X, Y, ncolr, ldr);
   }
 }
 
