@@ -47,7 +47,7 @@ struct efe_ctx {
   // device buffers
   std::vector<void *> allocs;
   void *cells = nullptr;
-  double *Q = nullptr, *W = nullptr, *X0 = nullptr, *X1 = nullptr;
+  double *Q = nullptr, *X0 = nullptr, *X1 = nullptr;
   double *rho_prev = nullptr, *rho_tmp = nullptr, *vq = nullptr;
   double *phi = nullptr, *dvec = nullptr, *rhs = nullptr;
   double *cg[7] = {nullptr};
@@ -57,7 +57,8 @@ struct efe_ctx {
   double *alpha = nullptr, *beta = nullptr, *beta0 = nullptr, *errv = nullptr, *ubuf = nullptr;
   int *active = nullptr, *kused = nullptr, *kforce = nullptr, *need = nullptr, *anyflag = nullptr;
   double *h1 = nullptr, *h2n = nullptr, *nrm1 = nullptr, *nrm2 = nullptr;
-  int *one = nullptr;
+  double *sig = nullptr, *coef = nullptr, *gsc = nullptr, *msc = nullptr;
+  int *one_mask = nullptr;   // all-ones column mask
   // state
   int cells_mode = -1;      // -1 nothing built, 0 Hamiltonian, 1..3 position operator
   bool ham_valid = false;   // rho_prev and the Hamiltonian belong to the current orbitals
@@ -287,7 +288,6 @@ efe_status build_device(efe_ctx *ctx) {
   ctx->allocs.push_back(cells);
   ctx->cells = cells;
   EFE_TRY(dalloc(ctx, &ctx->Q, ctx->blk * ctx->kmax));
-  EFE_TRY(dalloc(ctx, &ctx->W, ctx->blk));
   EFE_TRY(dalloc(ctx, &ctx->X0, ctx->blk));
   EFE_TRY(dalloc(ctx, &ctx->X1, ctx->blk));
   EFE_TRY(dalloc(ctx, &ctx->rho_prev, pl.n_quad));
@@ -318,13 +318,17 @@ efe_status build_device(efe_ctx *ctx) {
   EFE_TRY(dalloc(ctx, &ctx->need, pl.norb));
   EFE_TRY(dalloc(ctx, &ctx->anyflag, 1));
   EFE_TRY(dalloc(ctx, &ctx->h1, (int64_t)(ctx->kmax + 1) * ctx->ncolr));
-  {
-    std::vector<int> one(1, 1);
-    EFE_TRY(upload(ctx, &ctx->one, one));
-  }
   EFE_TRY(dalloc(ctx, &ctx->h2n, (int64_t)(ctx->kmax + 1) * ctx->ncolr));
-  EFE_TRY(dalloc(ctx, &ctx->nrm1, pl.norb));
+  EFE_TRY(dalloc(ctx, &ctx->nrm1, ctx->ncolr));
   EFE_TRY(dalloc(ctx, &ctx->nrm2, ctx->ncolr));
+  EFE_TRY(dalloc(ctx, &ctx->sig, (int64_t)(ctx->kmax + 1) * pl.norb));
+  EFE_TRY(dalloc(ctx, &ctx->coef, (int64_t)ctx->kmax * ctx->ncolr));
+  EFE_TRY(dalloc(ctx, &ctx->gsc, pl.norb));
+  {
+    std::vector<int> ones(std::max(1, pl.norb), 1);
+    EFE_TRY(upload(ctx, &ctx->one_mask, ones));
+  }
+  EFE_TRY(dalloc(ctx, &ctx->msc, pl.norb));
   return sync(ctx, "setup");
 }
 
@@ -461,6 +465,8 @@ efe_status dipole_of(efe_ctx *ctx, const double *rho, double mu[3]) {
 }
 
 // X (packed, n_rows x ncol complex) -> out = exp(-i tau A) X for the operator in the cell blocks.
+// The Krylov basis is stored unnormalised: slot 0 is X itself, slot l >= 1 is
+// ctx->Q block l - 1, and sig[l][c] = 1 / ||slot l||; X and out must not overlap.
 efe_status run_lanczos(efe_ctx *ctx, double tau, const double *X, double *out, int ncol, const int32_t *kforce_host,
                        int32_t *kused_host, double *err_host) {
   hipStream_t s = ctx->stream;
@@ -469,6 +475,10 @@ efe_status run_lanczos(efe_ctx *ctx, double tau, const double *X, double *out, i
   const int64_t bs = nrows * ncolr;     // doubles per block (packed for ncol)
   const int kmax = ctx->kmax;
   const double tol = ctx->opt.krylov_tol > 0 ? ctx->opt.krylov_tol : 1e-10;
+  if (X == out) {
+    ctx->err = "lanczos: input and output blocks must differ";
+    return EFE_ERR_ARG;
+  }
   if (kforce_host) {
     for (int c = 0; c < ncol; ++c)
       if (kforce_host[c] < 1 || kforce_host[c] > kmax) {
@@ -478,45 +488,47 @@ efe_status run_lanczos(efe_ctx *ctx, double tau, const double *X, double *out, i
     HIP_TRY(hipMemcpyAsync(ctx->kforce, kforce_host, ncol * sizeof(int), hipMemcpyHostToDevice, s));
   }
   const int *kf = kforce_host ? ctx->kforce : nullptr;
-  double *tmp = ctx->small;
+  double *Qb = ctx->Q;
+  auto slot = [&](int l) -> const double * { return l == 0 ? X : Qb + (int64_t)(l - 1) * bs; };
   tstart(ctx, 2);
-  int nb = efe::k::norm_partials(X, nrows, ncol, nullptr, ctx->red, s);
-  efe::k::reduce_partials(ctx->red, nb, ncolr, tmp, s);
-  efe::k::store_re(tmp, ctx->beta0, ncol, 1, nullptr, s);
-  efe::k::init_active(ctx->beta0, ctx->active, ctx->kused, ncol, s);
-  efe::k::scale_cols(X, ctx->Q, ctx->beta0, nrows, ncol, ctx->active, s);
+  int nb = efe::k::lz_dots(X, Qb, bs, 0, X, nrows, ncol, ctx->one_mask, nullptr, 1, ctx->red, s);
+  efe::k::reduce_partials(ctx->red, nb, ncolr, ctx->small, s);
+  efe::k::lz_init(ctx->small, ncol, ctx->beta0, ctx->sig, ctx->active, ctx->kused, s);
   tstop(ctx, 2);
   std::vector<int> act(ncol);
   HIP_TRY(hipMemcpyAsync(act.data(), ctx->active, ncol * sizeof(int), hipMemcpyDeviceToHost, s));
+  std::vector<double> b0h(ncol);
+  HIP_TRY(hipMemcpyAsync(b0h.data(), ctx->beta0, ncol * sizeof(double), hipMemcpyDeviceToHost, s));
   EFE_TRY(sync(ctx, "lanczos start"));
   bool any = false;
   for (int c = 0; c < ncol; ++c) any |= act[c] != 0;
-  std::vector<double> b0h(ncol);
-  HIP_TRY(hipMemcpy(b0h.data(), ctx->beta0, ncol * sizeof(double), hipMemcpyDeviceToHost));
   for (int c = 0; c < ncol; ++c)
     if (!std::isfinite(b0h[c])) { ctx->err = "non-finite input orbital"; return EFE_ERR_NONFINITE; }
-  // Each iteration: w = A q_j; classical Gram-Schmidt of w against q_1..q_j
-  // (this pass contains the three-term recurrence: its q_j coefficient is
-  // alpha_j); a second pass for the columns where the first one cancelled
-  // most of w; beta_j = ||w||; tridiagonal exponential and stopping test.
+  // Iteration j: slot j = A slot_{j-1}; classical Gram-Schmidt of slot j
+  // against slots 0..j-1 (the pass contains the three-term recurrence: its
+  // slot_{j-1} coefficient gives alpha_j); a second pass for the columns where
+  // the first one cancelled most of the vector; beta_j; tridiagonal
+  // exponential and stopping test.
   int j = 0;
   while (any) {
     ++j;
-    double *q = ctx->Q + (int64_t)(j - 1) * bs;
-    EFE_TRY(apply_op(ctx, q, ctx->W, ncolr, ncolr));
+    double *w = Qb + (int64_t)(j - 1) * bs;   // slot j
+    EFE_TRY(apply_op(ctx, slot(j - 1), w, ncolr, ncolr));
     tstart(ctx, 2);
     double *a_j = ctx->alpha + (int64_t)(j - 1) * ncol;
     double *b_j = ctx->beta + (int64_t)(j - 1) * ncol;
-    nb = efe::k::dots_partials(ctx->Q, bs, j, ctx->W, nrows, ncol, ctx->active, 1, nullptr, ctx->red, s);
+    nb = efe::k::lz_dots(X, Qb, bs, j, w, nrows, ncol, ctx->active, nullptr, 1, ctx->red, s);
     efe::k::reduce_partials(ctx->red, nb, (j + 1) * ncolr, ctx->h1, s);
-    nb = efe::k::update_norm_partials(ctx->Q, bs, j, ctx->h1, ctx->W, nrows, ncol, ctx->active, ctx->one, ctx->red, s);
-    efe::k::reduce_partials(ctx->red, nb, ncolr, ctx->nrm2, s);
-    efe::k::cgs_decide(ctx->h1, ctx->nrm2, j, ncol, ctx->active, a_j, ctx->nrm1, ctx->need, ctx->anyflag, s);
-    nb = efe::k::dots_partials(ctx->Q, bs, j, ctx->W, nrows, ncol, ctx->need, 0, ctx->anyflag, ctx->red, s);
+    efe::k::lz_coef1(ctx->h1, ctx->sig, j, ncol, ctx->active, a_j, ctx->coef, ctx->gsc, ctx->msc, s);
+    nb = efe::k::lz_update(X, Qb, bs, j, ctx->coef, ctx->gsc, w, nrows, ncol, ctx->active, nullptr, ctx->red, s);
+    efe::k::reduce_partials(ctx->red, nb, ncolr, ctx->nrm1, s);
+    efe::k::lz_decide(ctx->nrm1, ncol, ctx->active, ctx->gsc, ctx->need, ctx->anyflag, s);
+    nb = efe::k::lz_dots(X, Qb, bs, j, w, nrows, ncol, ctx->need, ctx->anyflag, 0, ctx->red, s);
     efe::k::reduce_partials(ctx->red, nb, j * ncolr, ctx->h2n, s);
-    nb = efe::k::update_norm_partials(ctx->Q, bs, j, ctx->h2n, ctx->W, nrows, ncol, ctx->need, ctx->anyflag, ctx->red, s);
+    efe::k::lz_coef2(ctx->h2n, ctx->nrm1, ctx->sig, j, ncol, ctx->need, ctx->coef, ctx->gsc, ctx->msc, s);
+    nb = efe::k::lz_update(X, Qb, bs, j, ctx->coef, ctx->gsc, w, nrows, ncol, ctx->need, ctx->anyflag, ctx->red, s);
     efe::k::reduce_partials(ctx->red, nb, ncolr, ctx->nrm2, s);
-    efe::k::cgs_beta(ctx->nrm1, ctx->nrm2, ctx->need, ctx->active, ncol, b_j, s);
+    efe::k::lz_beta(ctx->nrm1, ctx->nrm2, ctx->need, ctx->active, ctx->msc, j, ncol, b_j, ctx->sig, s);
     tstop(ctx, 2);
     tstart(ctx, 3);
     efe::k::tridiag_exp(ctx->alpha, ctx->beta, j, ncol, kmax, tau, ctx->beta0, kf, tol, ctx->active, ctx->kused,
@@ -531,12 +543,10 @@ efe_status run_lanczos(efe_ctx *ctx, double tau, const double *X, double *out, i
       ctx->err = "Lanczos did not reach the tolerance within kmax vectors";
       return EFE_ERR_NOCONV;
     }
-    tstart(ctx, 2);
-    efe::k::scale_cols(ctx->W, ctx->Q + (int64_t)j * bs, b_j, nrows, ncol, ctx->active, s);
-    tstop(ctx, 2);
   }
   tstart(ctx, 2);
-  efe::k::combine(ctx->Q, bs, ctx->ubuf, kmax, ctx->kused, ctx->beta0, out, nrows, ncol, s);
+  efe::k::lz_comb_coef(ctx->ubuf, ctx->sig, ctx->beta0, ctx->kused, kmax, j, ncol, ctx->coef, s);
+  efe::k::lz_combine(X, Qb, bs, j, ctx->coef, out, nrows, ncol, s);
   tstop(ctx, 2);
   std::vector<int> ku(ncol);
   std::vector<double> ev(ncol);

@@ -98,31 +98,26 @@ int dot_partials(const double *x, const double *y, int64_t n, double *part, hipS
 void reduce_partials(const double *part, int nblk, int nval, double *out, hipStream_t s);
 void dipole_partials(const DevData &d, const double *rho, double *part, int *nblk, hipStream_t s);
 
-// Lanczos
-int multidot_partials(const double *Q, int64_t qstride, int nq, const double *w, int64_t nrows, int ncol,
-                      const int *active, double *part, hipStream_t s);
-int norm_partials(const double *w, int64_t nrows, int ncol, const int *active, double *part, hipStream_t s);
-int dots_partials(const double *Q, int64_t qstride, int nq, const double *w, int64_t nrows, int ncol,
-                  const int *active, int with_norm, const int *any, double *part, hipStream_t s);
-int update_norm_partials(const double *Q, int64_t qstride, int nq, const double *h, double *w, int64_t nrows, int ncol,
-                         const int *need, const int *any, double *part, hipStream_t s);
-void cgs_decide(const double *h1n, const double *nrm1_sum, int j, int ncol, const int *active, double *alpha_j,
-                double *nrm1, int *need, int *any, hipStream_t s);
-void cgs_beta(const double *nrm1, const double *nrm2, const int *need, const int *active, int ncol, double *beta_j,
-              hipStream_t s);
-void multi_update(const double *Q, int64_t qstride, int nq, const double *h, double *w, int64_t nrows,
-                  int ncol, const int *active, hipStream_t s);
-void three_term(double *w, const double *q, const double *qm1, const double *alpha, const double *beta,
-                int64_t nrows, int ncol, const int *active, hipStream_t s);
-void scale_cols(const double *w, double *q, const double *inv, int64_t nrows, int ncol, const int *active,
-                hipStream_t s);
+// Lanczos vectors (unnormalised basis: slot 0 = q0, slot l >= 1 = qb + (l - 1) * bs)
+int lz_dots(const double *q0, const double *qb, int64_t bs, int nq, const double *w, int64_t nrows, int ncol,
+            const int *mask, const int *any, int with_norm, double *part, hipStream_t s);
+int lz_update(const double *q0, const double *qb, int64_t bs, int nq, const double *coef, const double *gw, double *w,
+              int64_t nrows, int ncol, const int *mask, const int *any, double *part, hipStream_t s);
+void lz_combine(const double *q0, const double *qb, int64_t bs, int nq, const double *coef, double *out,
+                int64_t nrows, int ncol, hipStream_t s);
+void lz_init(const double *h0, int ncol, double *beta0, double *sig, int *active, int *kused, hipStream_t s);
+void lz_coef1(const double *h, const double *sig, int j, int ncol, const int *active, double *alpha_j, double *coef,
+              double *gsc, double *msc, hipStream_t s);
+void lz_decide(const double *nrm1, int ncol, const int *active, const double *gsc, int *need, int *any,
+               hipStream_t s);
+void lz_coef2(const double *h2, const double *nrm1, const double *sig, int j, int ncol, const int *need, double *coef,
+              double *gsc, double *msc, hipStream_t s);
+void lz_beta(const double *nrm1, const double *nrm2, const int *need, const int *active, const double *msc, int j,
+             int ncol, double *beta_j, double *sig, hipStream_t s);
+void lz_comb_coef(const double *u, const double *sig, const double *beta0, const int *kused, int kmax, int nl,
+                  int ncol, double *coef, hipStream_t s);
 void tridiag_exp(const double *alpha, const double *beta, int j, int ncol, int kmax, double tau,
                  const double *beta0, const int *kforce, double tol, int *active, int *kused, double *err,
                  double *u, hipStream_t s);
-void store_re(const double *tmp, double *dst, int ncol, int sqrt_mode, const int *active, hipStream_t s);
-void init_active(const double *beta0, int *active, int *kused, int ncol, hipStream_t s);
-void combine(const double *Q, int64_t qstride, const double *u, int kmax, const int *kused, const double *beta0,
-             double *out, int64_t nrows, int ncol, hipStream_t s);
-
 }  // namespace k
 }  // namespace efe

@@ -264,207 +264,6 @@ __global__ void k_couple_e_final(const DevData d, const double *__restrict__ par
 }
 
 // ---------------------------------------------------------------------------
-// Lanczos vector kernels.  Blocks are n_rows x ncol complex, packed (ld = ncol).
-// ---------------------------------------------------------------------------
-constexpr int LCH = 8;       // LDS reduction chunk (vectors)
-constexpr int kDotBlocks = k::kDotBlocksMax;
-
-// Reduce per-thread accumulators acc[l][2] (l < nv) of the R row groups of a
-// block into part[blockIdx.x][l][c][2].  red: LDS of R * LCH * ncol * 2 doubles.
-template <int NV>
-__device__ __forceinline__ void block_reduce_cols(const double (&acc)[NV][2], int nv, int R, int r0, int c, int ncol,
-                                                  double *red, double *__restrict__ part) {
-  for (int l0 = 0; l0 < nv; l0 += LCH) {
-    __syncthreads();
-    if (r0 < R) {
-#pragma unroll
-      for (int l = 0; l < LCH; ++l) {
-        int ll = l0 + l;
-        double re = 0.0, im = 0.0;
-#pragma unroll
-        for (int k = 0; k < NV; ++k)
-          if (k == ll) { re = acc[k][0]; im = acc[k][1]; }
-        red[((r0 * LCH + l) * ncol + c) * 2] = re;
-        red[((r0 * LCH + l) * ncol + c) * 2 + 1] = im;
-      }
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < LCH * ncol * 2; t += blockDim.x) {
-      int l = t / (ncol * 2);
-      if (l0 + l >= nv) continue;
-      double sum = 0.0;
-      for (int rr = 0; rr < R; ++rr) sum += red[rr * LCH * ncol * 2 + t];
-      part[((int64_t)blockIdx.x * nv + l0) * ncol * 2 + t] = sum;
-    }
-  }
-}
-
-// part[blk][l][c] = sum_r conj(Q_l[r][c]) w[r][c] for l < nq (one pass over the
-// rows, nq <= NL); with_norm adds entry nq = ||w||^2 per column.
-template <int NL>
-__global__ void __launch_bounds__(256)
-k_dots(const double *__restrict__ Q, int64_t qstride, int nq, const double *__restrict__ w, int64_t nrows, int ncol,
-       const int *__restrict__ active, int with_norm, const int *__restrict__ any, double *__restrict__ part) {
-  if (any && *any == 0) return;
-  extern __shared__ double red[];
-  const int R = blockDim.x / ncol;
-  const int c = threadIdx.x % ncol, r0 = threadIdx.x / ncol;
-  const bool on = r0 < R && (active == nullptr || active[c] != 0);
-  double acc[NL + 1][2];
-#pragma unroll
-  for (int l = 0; l <= NL; ++l) acc[l][0] = acc[l][1] = 0.0;
-  if (on) {
-    for (int64_t r = (int64_t)blockIdx.x * R + r0; r < nrows; r += (int64_t)gridDim.x * R) {
-      const int64_t o = (r * ncol + c) * 2;
-      const double wr = w[o], wi = w[o + 1];
-#pragma unroll
-      for (int l = 0; l < NL; ++l)
-        if (l < nq) {
-          const double *q = Q + (int64_t)l * qstride + o;
-          const double qr = q[0], qi = q[1];
-          acc[l][0] += qr * wr + qi * wi;
-          acc[l][1] += qr * wi - qi * wr;
-        }
-      acc[NL][0] += wr * wr + wi * wi;
-    }
-  }
-  if (with_norm) {
-    // move the norm to slot nq
-#pragma unroll
-    for (int l = 0; l < NL; ++l)
-      if (l == nq) { acc[l][0] = acc[NL][0]; acc[l][1] = 0.0; }
-  }
-  block_reduce_cols<NL + 1>(acc, nq + (with_norm ? 1 : 0), R, r0, c, ncol, red, part);
-}
-
-// Classical Gram-Schmidt update w -= sum_{l<nq} h[l][c] Q_l for the columns
-// with need[c] != 0, and the partial ||w||^2 of the updated vector.  If *any
-// is 0 the kernel returns at once.
-template <int NL>
-__global__ void __launch_bounds__(256)
-k_update_norm(const double *__restrict__ Q, int64_t qstride, int nq, const double *__restrict__ h,
-              double *__restrict__ w, int64_t nrows, int ncol, const int *__restrict__ need,
-              const int *__restrict__ any, double *__restrict__ part) {
-  if (*any == 0) return;
-  extern __shared__ double sm[];
-  const int R = blockDim.x / ncol;
-  double *hs = sm;
-  double *red = sm + NL * ncol * 2;
-  for (int t = threadIdx.x; t < nq * ncol * 2; t += blockDim.x) hs[t] = h[t];
-  __syncthreads();
-  const int c = threadIdx.x % ncol, r0 = threadIdx.x / ncol;
-  const bool on = r0 < R && need[c] != 0;
-  double acc[1][2] = {{0.0, 0.0}};
-  if (on) {
-    for (int64_t r = (int64_t)blockIdx.x * R + r0; r < nrows; r += (int64_t)gridDim.x * R) {
-      const int64_t o = (r * ncol + c) * 2;
-      double wr = w[o], wi = w[o + 1];
-#pragma unroll
-      for (int l = 0; l < NL; ++l)
-        if (l < nq) {
-          const double *q = Q + (int64_t)l * qstride + o;
-          const double qr = q[0], qi = q[1];
-          const double hr = hs[(l * ncol + c) * 2], hi = hs[(l * ncol + c) * 2 + 1];
-          wr -= hr * qr - hi * qi;
-          wi -= hr * qi + hi * qr;
-        }
-      w[o] = wr;
-      w[o + 1] = wi;
-      acc[0][0] += wr * wr + wi * wi;
-    }
-  }
-  block_reduce_cols<1>(acc, 1, R, r0, c, ncol, red, part);
-}
-
-// Daniel-Gragg-Kaufman-Stewart test after the first Gram-Schmidt pass: the
-// pass lost at most eps ||w|| / ||w'|| of orthogonality, so a second pass is
-// made only for columns with ||w'|| < kReorthEta ||w|| (heavy cancellation).
-// Sets alpha_j = Re h1_{j-1}, the first-pass norm, need[c] and any.
-constexpr double kReorthEta = 1e-3;
-__global__ void k_cgs_decide(const double *__restrict__ h1n, const double *__restrict__ nrm1_part, int j, int ncol,
-                             const int *__restrict__ active, double *__restrict__ alpha_j, double *__restrict__ nrm1,
-                             int *__restrict__ need, int *__restrict__ any) {
-  __shared__ int flag;
-  if (threadIdx.x == 0) flag = 0;
-  __syncthreads();
-  for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
-    int nd = 0;
-    if (active[c]) {
-      alpha_j[c] = h1n[((j - 1) * ncol + c) * 2];
-      const double w2 = h1n[(j * ncol + c) * 2];     // ||w||^2 before the pass
-      const double n2 = nrm1_part[2 * c];             // ||w'||^2 after it
-      nrm1[c] = n2;
-      nd = n2 < kReorthEta * kReorthEta * w2 ? 1 : 0;
-    }
-    need[c] = nd;
-    if (nd) atomicOr(&flag, 1);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) *any = flag;
-}
-
-__global__ void k_cgs_beta(const double *__restrict__ nrm1, const double *__restrict__ nrm2, const int *__restrict__ need,
-                           const int *__restrict__ active, int ncol, double *__restrict__ beta_j) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncol || !active[c]) return;
-  const double v = need[c] ? nrm2[2 * c] : nrm1[c];
-  beta_j[c] = sqrt(v > 0.0 ? v : 0.0);
-}
-
-// w[r][c] -= sum_l h[l][c] Q_l[r][c]   (complex), active columns only
-__global__ void __launch_bounds__(256)
-k_multi_update(const double *__restrict__ Q, int64_t qstride, int nq, const double *__restrict__ h,
-               double *__restrict__ w, int64_t nrows, int ncol, const int *__restrict__ active) {
-  extern __shared__ double hs[];     // nq * ncol * 2
-  for (int t = threadIdx.x; t < nq * ncol * 2; t += blockDim.x) hs[t] = h[t];
-  __syncthreads();
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nrows * ncol) return;
-  const int c = (int)(t % ncol);
-  if (active && !active[c]) return;
-  double wr = w[2 * t], wi = w[2 * t + 1];
-  for (int l = 0; l < nq; ++l) {
-    const double qr = Q[(int64_t)l * qstride + 2 * t], qi = Q[(int64_t)l * qstride + 2 * t + 1];
-    const double hr = hs[(l * ncol + c) * 2], hi = hs[(l * ncol + c) * 2 + 1];
-    wr -= hr * qr - hi * qi;
-    wi -= hr * qi + hi * qr;
-  }
-  w[2 * t] = wr;
-  w[2 * t + 1] = wi;
-}
-
-// w -= alpha q + beta qm1 (real coefficients per column)
-__global__ void k_three_term(double *__restrict__ w, const double *__restrict__ q, const double *__restrict__ qm1,
-                             const double *__restrict__ alpha, const double *__restrict__ beta, int64_t nrows,
-                             int ncol, const int *__restrict__ active) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nrows * ncol) return;
-  const int c = (int)(t % ncol);
-  if (!active[c]) return;
-  const double a = alpha[c];
-  double wr = w[2 * t] - a * q[2 * t], wi = w[2 * t + 1] - a * q[2 * t + 1];
-  if (qm1) {
-    const double b = beta[c];
-    wr -= b * qm1[2 * t];
-    wi -= b * qm1[2 * t + 1];
-  }
-  w[2 * t] = wr;
-  w[2 * t + 1] = wi;
-}
-
-// q = w * inv[c]
-__global__ void k_scale_cols(const double *__restrict__ w, double *__restrict__ q, const double *__restrict__ nrm,
-                             int64_t nrows, int ncol, const int *__restrict__ active) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nrows * ncol) return;
-  const int c = (int)(t % ncol);
-  if (active && !active[c]) return;
-  const double s = nrm[c] > 0.0 ? 1.0 / nrm[c] : 0.0;
-  q[2 * t] = w[2 * t] * s;
-  q[2 * t + 1] = w[2 * t + 1] * s;
-}
-
-// ---------------------------------------------------------------------------
 // Per column: eigendecomposition of the j x j symmetric tridiagonal T_j by the
 // implicit QL method with Wilkinson-type shifts (Bowdler, Martin, Reinsch and
 // Wilkinson, 1968), u = V exp(-i tau Lambda) V^T e_1, the estimate
@@ -577,30 +376,6 @@ k_tridiag_exp(const double *__restrict__ alpha, const double *__restrict__ beta,
   }
 }
 
-// out[r][c] = beta0[c] sum_{l < k_c} u[c][l] Q_l[r][c]
-__global__ void __launch_bounds__(256)
-k_combine(const double *__restrict__ Q, int64_t qstride, const double *__restrict__ u, int kmax,
-          const int *__restrict__ kused, const double *__restrict__ beta0, double *__restrict__ out, int64_t nrows,
-          int ncol) {
-  extern __shared__ double us[];   // ncol * kmax * 2
-  for (int t = threadIdx.x; t < ncol * kmax * 2; t += blockDim.x) us[t] = u[t];
-  __syncthreads();
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= nrows * ncol) return;
-  const int c = (int)(t % ncol);
-  const int kc = kused[c];
-  double sr = 0.0, si = 0.0;
-  for (int l = 0; l < kc; ++l) {
-    const double qr = Q[(int64_t)l * qstride + 2 * t], qi = Q[(int64_t)l * qstride + 2 * t + 1];
-    const double ur = us[(c * kmax + l) * 2], ui = us[(c * kmax + l) * 2 + 1];
-    sr += ur * qr - ui * qi;
-    si += ur * qi + ui * qr;
-  }
-  const double b = beta0[c];
-  out[2 * t] = b * sr;
-  out[2 * t + 1] = b * si;
-}
-
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 template <typename T, int NTW>
@@ -662,131 +437,10 @@ void couple_apply(const DevData &d, const double *G, const double *Hee, const do
                      ncolr, ldr);
 }
 
-template <int NL>
-static int launch_dots(const double *Q, int64_t qstride, int nq, const double *w, int64_t nrows, int ncol,
-                       const int *active, int with_norm, const int *any, double *part, hipStream_t s) {
-  int R = 256 / ncol;
-  int nb = (int)std::min<int64_t>(kDotBlocks, (nrows + R - 1) / R);
-  if (nb < 1) nb = 1;
-  size_t lds = (size_t)R * LCH * ncol * 2 * sizeof(double);
-  hipLaunchKernelGGL(k_dots<NL>, dim3(nb), dim3(256), lds, s, Q, qstride, nq, w, nrows, ncol, active, with_norm, any, part);
-  return nb;
-}
-
-int dots_partials(const double *Q, int64_t qstride, int nq, const double *w, int64_t nrows, int ncol,
-                  const int *active, int with_norm, const int *any, double *part, hipStream_t s) {
-  if (nq <= 1) return launch_dots<1>(Q, qstride, nq, w, nrows, ncol, active, with_norm, any, part, s);
-  if (nq <= 8) return launch_dots<8>(Q, qstride, nq, w, nrows, ncol, active, with_norm, any, part, s);
-  if (nq <= 16) return launch_dots<16>(Q, qstride, nq, w, nrows, ncol, active, with_norm, any, part, s);
-  if (nq <= 24) return launch_dots<24>(Q, qstride, nq, w, nrows, ncol, active, with_norm, any, part, s);
-  if (nq <= 32) return launch_dots<32>(Q, qstride, nq, w, nrows, ncol, active, with_norm, any, part, s);
-  if (nq <= 48) return launch_dots<48>(Q, qstride, nq, w, nrows, ncol, active, with_norm, any, part, s);
-  return launch_dots<64>(Q, qstride, nq, w, nrows, ncol, active, with_norm, any, part, s);
-}
-
-int multidot_partials(const double *Q, int64_t qstride, int nq, const double *w, int64_t nrows, int ncol,
-                      const int *active, double *part, hipStream_t s) {
-  return dots_partials(Q, qstride, nq, w, nrows, ncol, active, 0, nullptr, part, s);
-}
-
-int norm_partials(const double *w, int64_t nrows, int ncol, const int *active, double *part, hipStream_t s) {
-  return launch_dots<1>(w, 0, 0, w, nrows, ncol, active, 1, nullptr, part, s);
-}
-
-template <int NL>
-static int launch_update_norm(const double *Q, int64_t qstride, int nq, const double *h, double *w, int64_t nrows,
-                              int ncol, const int *need, const int *any, double *part, hipStream_t s) {
-  int R = 256 / ncol;
-  int nb = (int)std::min<int64_t>(kDotBlocks, (nrows + R - 1) / R);
-  if (nb < 1) nb = 1;
-  size_t lds = ((size_t)NL * ncol * 2 + (size_t)R * LCH * ncol * 2) * sizeof(double);
-  hipLaunchKernelGGL(k_update_norm<NL>, dim3(nb), dim3(256), lds, s, Q, qstride, nq, h, w, nrows, ncol, need, any, part);
-  return nb;
-}
-
-int update_norm_partials(const double *Q, int64_t qstride, int nq, const double *h, double *w, int64_t nrows, int ncol,
-                         const int *need, const int *any, double *part, hipStream_t s) {
-  if (nq <= 8) return launch_update_norm<8>(Q, qstride, nq, h, w, nrows, ncol, need, any, part, s);
-  if (nq <= 16) return launch_update_norm<16>(Q, qstride, nq, h, w, nrows, ncol, need, any, part, s);
-  if (nq <= 32) return launch_update_norm<32>(Q, qstride, nq, h, w, nrows, ncol, need, any, part, s);
-  return launch_update_norm<64>(Q, qstride, nq, h, w, nrows, ncol, need, any, part, s);
-}
-
-void cgs_decide(const double *h1n, const double *nrm1_sum, int j, int ncol, const int *active, double *alpha_j,
-                double *nrm1, int *need, int *any, hipStream_t s) {
-  hipLaunchKernelGGL(k_cgs_decide, dim3(1), dim3(128), 0, s, h1n, nrm1_sum, j, ncol, active, alpha_j, nrm1, need, any);
-}
-
-void cgs_beta(const double *nrm1, const double *nrm2, const int *need, const int *active, int ncol, double *beta_j,
-              hipStream_t s) {
-  hipLaunchKernelGGL(k_cgs_beta, dim3((ncol + 63) / 64), dim3(64), 0, s, nrm1, nrm2, need, active, ncol, beta_j);
-}
-
-void multi_update(const double *Q, int64_t qstride, int nq, const double *h, double *w, int64_t nrows, int ncol,
-                  const int *active, hipStream_t s) {
-  size_t lds = (size_t)nq * ncol * 2 * sizeof(double);
-  hipLaunchKernelGGL(k_multi_update, dim3(nblocks(nrows * ncol, 256)), dim3(256), lds, s, Q, qstride, nq, h, w, nrows,
-                     ncol, active);
-}
-
-void three_term(double *w, const double *q, const double *qm1, const double *alpha, const double *beta, int64_t nrows,
-                int ncol, const int *active, hipStream_t s) {
-  hipLaunchKernelGGL(k_three_term, dim3(nblocks(nrows * ncol, 256)), dim3(256), 0, s, w, q, qm1, alpha, beta, nrows,
-                     ncol, active);
-}
-
-void scale_cols(const double *w, double *q, const double *nrm, int64_t nrows, int ncol, const int *active,
-                hipStream_t s) {
-  hipLaunchKernelGGL(k_scale_cols, dim3(nblocks(nrows * ncol, 256)), dim3(256), 0, s, w, q, nrm, nrows, ncol, active);
-}
-
 void tridiag_exp(const double *alpha, const double *beta, int j, int ncol, int kmax, double tau, const double *beta0,
                  const int *kforce, double tol, int *active, int *kused, double *err, double *u, hipStream_t s) {
   hipLaunchKernelGGL(k_tridiag_exp, dim3(ncol), dim3(64), 0, s, alpha, beta, j, ncol, kmax, tau, beta0, kforce, tol,
                      active, kused, err, u);
-}
-
-void combine(const double *Q, int64_t qstride, const double *u, int kmax, const int *kused, const double *beta0,
-             double *out, int64_t nrows, int ncol, hipStream_t s) {
-  size_t lds = (size_t)ncol * kmax * 2 * sizeof(double);
-  hipLaunchKernelGGL(k_combine, dim3(nblocks(nrows * ncol, 256)), dim3(256), lds, s, Q, qstride, u, kmax, kused, beta0,
-                     out, nrows, ncol);
-}
-
-}  // namespace k
-}  // namespace efe
-
-namespace efe {
-namespace {
-
-// dst[c] = Re(tmp[c]) or sqrt(max(Re(tmp[c]), 0)) for active columns
-__global__ void k_store_re(const double *__restrict__ tmp, double *__restrict__ dst, int ncol, int sqrt_mode,
-                           const int *__restrict__ active) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncol) return;
-  if (active && !active[c]) return;
-  const double v = tmp[2 * c];
-  dst[c] = sqrt_mode ? sqrt(v > 0.0 ? v : 0.0) : v;
-}
-
-__global__ void k_init_active(const double *__restrict__ beta0, int *__restrict__ active, int *__restrict__ kused,
-                              int ncol) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncol) return;
-  active[c] = beta0[c] > 0.0 ? 1 : 0;
-  kused[c] = 0;
-}
-
-}  // namespace
-
-namespace k {
-
-void store_re(const double *tmp, double *dst, int ncol, int sqrt_mode, const int *active, hipStream_t s) {
-  hipLaunchKernelGGL(k_store_re, dim3((ncol + 63) / 64), dim3(64), 0, s, tmp, dst, ncol, sqrt_mode, active);
-}
-
-void init_active(const double *beta0, int *active, int *kused, int ncol, hipStream_t s) {
-  hipLaunchKernelGGL(k_init_active, dim3((ncol + 63) / 64), dim3(64), 0, s, beta0, active, kused, ncol);
 }
 
 }  // namespace k

@@ -93,7 +93,10 @@ def test_lanczos_parity(env):
     ku, er = ctx.lanczos_expm(Xd, 0.05)
     assert list(ku) == list(kref)
     assert _rel(Xd.cpu().numpy(), ref) < 1e-11
-    np.testing.assert_allclose(er, eref, rtol=1e-6, atol=1e-22)
+    # The estimate |tau| beta_k beta0 |u_k| takes u_k = [exp(-i tau T_k)]_{k,1}
+    # from a sum of O(1) terms that cancels down to ~1e-10, so two correct
+    # implementations agree in it only to ~k eps / |u_k| ~ 1e-5 relative.
+    np.testing.assert_allclose(er, eref, rtol=1e-5, atol=1e-22)
 
 
 def test_kick_parity(env):
