@@ -306,7 +306,7 @@ efe_status build_device(efe_ctx *ctx) {
   ctx->red_len = std::max<int64_t>({(int64_t)efe::k::kDotBlocksMax * (ctx->kmax + 1) * ctx->ncolr, pl.n_cells * 3, 4096});
   EFE_TRY(dalloc(ctx, &ctx->red, ctx->red_len));
   EFE_TRY(dalloc(ctx, &ctx->small, (int64_t)ctx->kmax * ctx->ncolr + 64));
-  EFE_TRY(dalloc(ctx, &ctx->couple_scr, (int64_t)1024 * std::max(1, d.nk) * ctx->ncolr));
+  EFE_TRY(dalloc(ctx, &ctx->couple_scr, (int64_t)efe::k::kCouplePartials * std::max(1, d.nk) * ctx->ncolr));
   EFE_TRY(dalloc(ctx, &ctx->alpha, (int64_t)ctx->kmax * pl.norb));
   EFE_TRY(dalloc(ctx, &ctx->beta, (int64_t)ctx->kmax * pl.norb));
   EFE_TRY(dalloc(ctx, &ctx->beta0, pl.norb));
@@ -341,7 +341,6 @@ efe_status apply_op(efe_ctx *ctx, const double *X, double *Y, int ncolr, int64_t
     ctx->err = "internal: apply_op expects packed blocks";
     return EFE_ERR_ARG;
   }
-  efe::k::zero(Y, d.g.n_nodes * ncolr, s);
   tstart(ctx, 0);
   efe::k::cell_apply(d, ctx->cells, ctx->dtype, X, Y, ncolr, ldr, s);
   tstop(ctx, 0);

@@ -66,6 +66,7 @@ struct DevData {
 namespace k {
 
 constexpr int kDotBlocksMax = 1024;   // partial blocks of the column reductions
+constexpr int kCouplePartials = 2048; // partial sums of the enrichment-row coupling product
 
 void zero(double *p, int64_t n, hipStream_t s);
 void copy_rows(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t nrows, int ncolr, hipStream_t s);

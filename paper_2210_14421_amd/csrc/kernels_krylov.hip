@@ -19,12 +19,11 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
 // Cell products Y[nodes_c] += Hbar_c X[nodes_c] for the cells of one colour
-// (no two cells of a colour share a node).  One workgroup (4 waves in a 2 x 2
-// grid) per (cell, column chunk); the nloc x nloc block is streamed through LDS
-// in K-chunks of 8 rows (Hbar_c is symmetric, so rows k of the row-major block
-// are the A-operand columns), the gathered X chunk is staged beside it, and the
-// 16x16x4 MFMA accumulates in registers.  Double-buffered LDS, one barrier per
-// chunk.
+// (no two cells of a colour share a node; the 8 colours are the parity
+// classes of the cell index and run one launch each, in order).  The first
+// colour to reach a node stores instead of adding, so Y needs no clearing
+// beforehand.  Hbar_c is symmetric, so row k of the row-major block is the
+// MFMA A-operand column k; the 16x16x4 MFMA accumulates in registers.
 // ---------------------------------------------------------------------------
 constexpr int kApplyMaxLoc = 384;   // nloc of degree <= 6 is 343
 
@@ -62,6 +61,7 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, int 
   typedef typename Mfma<T>::Acc Acc;
   constexpr int MTW = 2;
   __shared__ int64_t rowoff[kApplyMaxLoc];
+  __shared__ unsigned char first[kApplyMaxLoc];   // this cell's colour is the first to reach the node
   const Geom &g = d.g;
   const int nloc = g.nloc;
   const int per_cell = npair * nch;
@@ -75,7 +75,19 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, int 
   const int kr = lane >> 4, cl = lane & 15;
   int e[3];
   cell_ijk(g, cell, e);
-  for (int l = lane; l < nloc; l += 64) rowoff[l] = local_node(g, e, l) * ldr;
+  for (int l = lane; l < nloc; l += 64) {
+    rowoff[l] = local_node(g, e, l) * ldr;
+    // colours run in the order (e_x & 1) + 2 (e_y & 1) + 4 (e_z & 1); a node on a
+    // face shared along some axis is reached first by the even cell of that axis
+    const int li[3] = {l % g.P, (l / g.P) % g.P, l / (g.P * g.P)};
+    bool later = false;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const bool shared = (li[ax] == 0 && e[ax] > 0) || (li[ax] == g.p && e[ax] < g.nc[ax] - 1);
+      later |= shared && (e[ax] & 1);
+    }
+    first[l] = later ? 0 : 1;
+  }
   __syncthreads();
   // blocks are stored in colour-major order: a colour launch streams them contiguously
   const T *A = cells + (int64_t)(slot0 + ci) * nloc * nloc;
@@ -138,127 +150,150 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, int 
       for (int r = 0; r < 4; ++r) {
         const int row = m0 + mt * 16 + Mfma<T>::row(kr, r);
         const int col = col0 + nt * 16 + cl;
-        if (row < nloc && col < ncolr) Y[rowoff[row] + col] += (double)acc[mt][nt][r];
+        if (row < nloc && col < ncolr) {
+          double *y = Y + rowoff[row] + col;
+          *y = first[row] ? (double)acc[mt][nt][r] : *y + (double)acc[mt][nt][r];
+        }
       }
 }
 
 // ---------------------------------------------------------------------------
 // Enrichment coupling: Y_C[r] += G[r] X_E ;  Y_E = G^T X_C[R] + Hbar^ee X_E
-// ---------------------------------------------------------------------------
-// Y_C[rows] += G X_E: a block stages 32 rows of G and all of X_E in LDS; a
-// thread owns one row and a group of 4 columns.
-constexpr int kRowChunk = 32;
-constexpr int kCoupleBlocks = 1024;
-__global__ void __launch_bounds__(256)
+// (G = Hbar^ce on the union rows R of the cells where an enrichment function
+// is nonzero, row-major n_R x n_k).  One wave per block walks a contiguous
+// range of 16-row tiles of R on the FP64 16x16x4 MFMA; a block covers KNT
+// 16-column tiles (blockIdx.y).
+//   k_couple_c:  Y_C tile (16 x 16 N) += G tile (16 x n_k) . X_E (n_k x 16 N),
+//                added into Y.
+//   k_couple_e:  Y_E (16 M x 16 N) += G tile^T (16 M x 16 rows) . X[R tile],
+//                KMT M tiles per block (blockIdx.z), kept in registers over the
+//                range and written as the wave's partial sum; the partials are
+//                reduced in a fixed order (deterministic).
+constexpr int kCoupleCWaves = 4096;   // four per SIMD
+constexpr int KNT = 6;    // 16-column tiles per block (88 columns = 5.5 tiles)
+constexpr int KMT = 3;    // 16-row tiles of Y_E per block (48 functions)
+
+__global__ void __launch_bounds__(64)
 k_couple_c(const DevData d, const double *__restrict__ G, const double *__restrict__ X, double *__restrict__ Y,
-           int ncolr, int64_t ldr) {
-  extern __shared__ double sm[];
+           int ncolr, int64_t ldr, int64_t tiles_per_wave) {
   const int nk = d.nk;
-  double *xe = sm;                       // nk * ncolr
-  double *gs = xe + nk * ncolr;          // kRowChunk * nk
-  for (int t = threadIdx.x; t < nk * ncolr; t += blockDim.x) {
-    int k = t / ncolr, c = t % ncolr;
-    xe[t] = X[(d.g.n_nodes + k) * ldr + c];
+  const int64_t nr = d.nr;
+  const int lane = threadIdx.x, kr = lane >> 4, cl = lane & 15;
+  const int n0 = blockIdx.y * KNT * 16;
+  const int64_t ntiles = (nr + 15) / 16;
+  const int64_t t_begin = (int64_t)blockIdx.x * tiles_per_wave;
+  const int64_t t_end = t_begin + tiles_per_wave < ntiles ? t_begin + tiles_per_wave : ntiles;
+  const double *XE = X + (int64_t)d.g.n_nodes * ldr;
+  int col[KNT];
+  bool cok[KNT];
+#pragma unroll
+  for (int nt = 0; nt < KNT; ++nt) {
+    col[nt] = n0 + nt * 16 + cl;
+    cok[nt] = col[nt] < ncolr;
   }
-  const int ng = (ncolr + 3) / 4;
-  for (int64_t rc = (int64_t)blockIdx.x * kRowChunk; rc < d.nr; rc += (int64_t)gridDim.x * kRowChunk) {
-    const int nrow = (int)(d.nr - rc < kRowChunk ? d.nr - rc : kRowChunk);
-    __syncthreads();
-    for (int t = threadIdx.x; t < nrow * nk; t += blockDim.x) gs[t] = G[rc * nk + t];
-    __syncthreads();
-    for (int t = threadIdx.x; t < nrow * ng; t += blockDim.x) {
-      const int rr = t / ng, c0 = (t % ng) * 4;
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-      const double *gr = gs + rr * nk;
-      for (int k = 0; k < nk; ++k) {
-        const double gv = gr[k];
-        const double *xr = xe + k * ncolr + c0;
-        a0 += gv * xr[0];
-        if (c0 + 1 < ncolr) a1 += gv * xr[1];
-        if (c0 + 2 < ncolr) a2 += gv * xr[2];
-        if (c0 + 3 < ncolr) a3 += gv * xr[3];
+  const int nks = (nk + 3) / 4;
+  for (int64_t t = t_begin; t < t_end; ++t) {
+    const int64_t r0 = t * 16;
+    // A(i, k) = G[r0 + i][k], B(k, j) = X_E[k][j]
+    v4d acc[KNT];
+#pragma unroll
+    for (int nt = 0; nt < KNT; ++nt) acc[nt] = v4d{0, 0, 0, 0};
+    const int64_t ra = r0 + cl;
+    const bool rok = ra < nr;
+    for (int ks = 0; ks < nks; ++ks) {
+      const int k = ks * 4 + kr;
+      const bool kok = k < nk;
+      const double a = (rok && kok) ? G[ra * nk + k] : 0.0;
+#pragma unroll
+      for (int nt = 0; nt < KNT; ++nt) {
+        const double b = (kok && cok[nt]) ? XE[(int64_t)k * ldr + col[nt]] : 0.0;
+        acc[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[nt], 0, 0, 0);
       }
-      double *y = Y + d.urow_node[rc + rr] * ldr + c0;
-      y[0] += a0;
-      if (c0 + 1 < ncolr) y[1] += a1;
-      if (c0 + 2 < ncolr) y[2] += a2;
-      if (c0 + 3 < ncolr) y[3] += a3;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = r0 + kr + 4 * r;
+      if (row < nr) {
+        double *y = Y + (int64_t)d.urow_node[row] * ldr;
+#pragma unroll
+        for (int nt = 0; nt < KNT; ++nt)
+          if (cok[nt]) y[col[nt]] += acc[nt][r];
+      }
     }
   }
 }
 
-// Split-K partial of Y_E = G^T X_C[R]: part[blk][kappa][col] over the block's
-// rows; a thread owns a 4 x 4 tile of (kappa, col) outputs.
-template <int S>
+__global__ void __launch_bounds__(64)
+k_couple_e(const DevData d, const double *__restrict__ G, const double *__restrict__ X, int ncolr, int64_t ldr,
+           int64_t tiles_per_wave, double *__restrict__ part) {
+  const int nk = d.nk;
+  const int64_t nr = d.nr;
+  const int lane = threadIdx.x, kr = lane >> 4, cl = lane & 15;
+  const int n0 = blockIdx.y * KNT * 16, m0 = blockIdx.z * KMT * 16;
+  const int64_t ntiles = (nr + 15) / 16;
+  const int64_t t_begin = (int64_t)blockIdx.x * tiles_per_wave;
+  const int64_t t_end = t_begin + tiles_per_wave < ntiles ? t_begin + tiles_per_wave : ntiles;
+  int col[KNT];
+  bool cok[KNT];
+#pragma unroll
+  for (int nt = 0; nt < KNT; ++nt) {
+    col[nt] = n0 + nt * 16 + cl;
+    cok[nt] = col[nt] < ncolr;
+  }
+  v4d acc[KMT][KNT];
+#pragma unroll
+  for (int mt = 0; mt < KMT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < KNT; ++nt) acc[mt][nt] = v4d{0, 0, 0, 0};
+  // A(i, k) = G[r + k][m0 + i], B(k, j) = X[node(r + k)][j]; four k-steps per tile
+  for (int64_t r4 = t_begin * 4; r4 < t_end * 4; ++r4) {
+    const int64_t rk = r4 * 4 + kr;
+    const bool rok = rk < nr;
+    const double *xr = X + (rok ? (int64_t)d.urow_node[rk] * ldr : 0);
+    double b[KNT];
+#pragma unroll
+    for (int nt = 0; nt < KNT; ++nt) b[nt] = (rok && cok[nt]) ? xr[col[nt]] : 0.0;
+#pragma unroll
+    for (int mt = 0; mt < KMT; ++mt) {
+      const int m = m0 + mt * 16 + cl;
+      const double a = (rok && m < nk) ? G[rk * nk + m] : 0.0;
+#pragma unroll
+      for (int nt = 0; nt < KNT; ++nt) acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[nt], acc[mt][nt], 0, 0, 0);
+    }
+  }
+  // partial Y_E of this wave: part[blockIdx.x][m][col]
+  double *pw = part + (int64_t)blockIdx.x * nk * ncolr;
+#pragma unroll
+  for (int mt = 0; mt < KMT; ++mt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int m = m0 + mt * 16 + kr + 4 * r;
+      if (m < nk) {
+#pragma unroll
+        for (int nt = 0; nt < KNT; ++nt)
+          if (cok[nt]) pw[(int64_t)m * ncolr + col[nt]] = acc[mt][nt][r];
+      }
+    }
+}
+
+// Y_E[k][c] = sum_b part[b][k][c] + sum_k' Hbar^ee[k][k'] X_E[k'][c]; a block of
+// 4 x 64 threads reduces 64 consecutive outputs, each quarter over every
+// fourth partial, then combines the quarters in a fixed order.
 __global__ void __launch_bounds__(256)
-k_couple_e_partial(const DevData d, const double *__restrict__ G, const double *__restrict__ X, int ncolr,
-                   int64_t ldr, int64_t rows_per_blk, double *__restrict__ part) {
-  extern __shared__ double sm[];
-  const int nk = d.nk;
-  double *gs = sm;                       // kRowChunk * nk
-  double *xs = gs + kRowChunk * nk;      // kRowChunk * ncolr
-  const int nout = nk * ncolr;
-  const int tk = (nk + 3) / 4, tc = (ncolr + 3) / 4, ntile = tk * tc;
-  const int64_t r0 = (int64_t)blockIdx.x * rows_per_blk;
-  const int64_t r1 = r0 + rows_per_blk < d.nr ? r0 + rows_per_blk : d.nr;
-  double acc[S][4][4];
-#pragma unroll
-  for (int s = 0; s < S; ++s)
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) acc[s][a][b] = 0.0;
-  for (int64_t rc = r0; rc < r1; rc += kRowChunk) {
-    const int nrow = (int)(r1 - rc < kRowChunk ? r1 - rc : kRowChunk);
-    __syncthreads();
-    for (int t = threadIdx.x; t < kRowChunk * nk; t += blockDim.x) gs[t] = t < nrow * nk ? G[rc * nk + t] : 0.0;
-    for (int t = threadIdx.x; t < kRowChunk * ncolr; t += blockDim.x) {
-      int rr = t / ncolr, c = t % ncolr;
-      xs[t] = rr < nrow ? X[d.urow_node[rc + rr] * ldr + c] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const int tile = threadIdx.x + s * 256;
-      if (tile < ntile) {
-        const int k0 = (tile / tc) * 4, c0 = (tile % tc) * 4;
-        for (int rr = 0; rr < nrow; ++rr) {
-          double gv[4], xv[4];
-#pragma unroll
-          for (int a = 0; a < 4; ++a) gv[a] = k0 + a < nk ? gs[rr * nk + k0 + a] : 0.0;
-#pragma unroll
-          for (int b = 0; b < 4; ++b) xv[b] = c0 + b < ncolr ? xs[rr * ncolr + c0 + b] : 0.0;
-#pragma unroll
-          for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc[s][a][b] += gv[a] * xv[b];
-        }
-      }
-    }
-  }
-#pragma unroll
-  for (int s = 0; s < S; ++s) {
-    const int tile = threadIdx.x + s * 256;
-    if (tile < ntile) {
-      const int k0 = (tile / tc) * 4, c0 = (tile % tc) * 4;
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-          if (k0 + a < nk && c0 + b < ncolr) part[(int64_t)blockIdx.x * nout + (k0 + a) * ncolr + c0 + b] = acc[s][a][b];
-    }
-  }
-}
-
-__global__ void k_couple_e_final(const DevData d, const double *__restrict__ part, int nblk,
-                                 const double *__restrict__ Hee, const double *__restrict__ X, double *__restrict__ Y,
-                                 int ncolr, int64_t ldr) {
-  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+k_couple_final(const DevData d, const double *__restrict__ part, int nblk, const double *__restrict__ Hee,
+               const double *__restrict__ X, double *__restrict__ Y, int ncolr, int64_t ldr) {
+  __shared__ double red[4][64];
   const int nk = d.nk, nout = nk * ncolr;
-  if (o >= nout) return;
-  const int k = o / ncolr, c = o % ncolr;
+  const int o = blockIdx.x * 64 + (threadIdx.x & 63), q = threadIdx.x >> 6;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * nout + o];
+  if (o < nout)
+    for (int b = q; b < nblk; b += 4) s += part[(int64_t)b * nout + o];
+  red[q][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (q != 0 || o >= nout) return;
+  const int lo = threadIdx.x;
+  s = red[0][lo] + red[1][lo] + red[2][lo] + red[3][lo];
+  const int k = o / ncolr, c = o % ncolr;
   for (int kp = 0; kp < nk; ++kp) s += Hee[k * nk + kp] * X[(d.g.n_nodes + kp) * ldr + c];
   Y[(d.g.n_nodes + k) * ldr + c] = s;
 }
@@ -416,24 +451,19 @@ void couple_apply(const DevData &d, const double *G, const double *Hee, const do
   int nblk = 1;
   const int nout = d.nk * ncolr;
   if (d.nr > 0) {
-    size_t lds = ((size_t)d.nk * ncolr + (size_t)kRowChunk * d.nk) * sizeof(double);
-    unsigned nb = (unsigned)std::min<int64_t>(kCoupleBlocks, (d.nr + kRowChunk - 1) / kRowChunk);
-    hipLaunchKernelGGL(k_couple_c, dim3(nb), dim3(256), lds, s, d, G, X, Y, ncolr, ldr);
-    nblk = (int)std::min<int64_t>(kCoupleBlocks, (d.nr + 127) / 128);
-    int64_t rpb = (d.nr + nblk - 1) / nblk;
-    size_t lds2 = (size_t)kRowChunk * (d.nk + ncolr) * sizeof(double);
-    const int ntile = ((d.nk + 3) / 4) * ((ncolr + 3) / 4);
-    const int S = (ntile + 255) / 256;
-    if (S <= 1)
-      hipLaunchKernelGGL(k_couple_e_partial<1>, dim3(nblk), dim3(256), lds2, s, d, G, X, ncolr, ldr, rpb, scratch);
-    else if (S <= 2)
-      hipLaunchKernelGGL(k_couple_e_partial<2>, dim3(nblk), dim3(256), lds2, s, d, G, X, ncolr, ldr, rpb, scratch);
-    else
-      hipLaunchKernelGGL(k_couple_e_partial<4>, dim3(nblk), dim3(256), lds2, s, d, G, X, ncolr, ldr, rpb, scratch);
+    const int64_t ntiles = (d.nr + 15) / 16;
+    const unsigned ny = (unsigned)((ncolr + KNT * 16 - 1) / (KNT * 16));
+    const unsigned nz = (unsigned)((d.nk + KMT * 16 - 1) / (KMT * 16));
+    const int64_t tpc = (ntiles + kCoupleCWaves - 1) / kCoupleCWaves;
+    hipLaunchKernelGGL(k_couple_c, dim3((unsigned)((ntiles + tpc - 1) / tpc), ny), dim3(64), 0, s, d, G, X, Y, ncolr,
+                       ldr, tpc);
+    const int64_t tpe = (ntiles + kCouplePartials - 1) / kCouplePartials;
+    nblk = (int)((ntiles + tpe - 1) / tpe);
+    hipLaunchKernelGGL(k_couple_e, dim3((unsigned)nblk, ny, nz), dim3(64), 0, s, d, G, X, ncolr, ldr, tpe, scratch);
   } else {
     k::zero(scratch, (int64_t)nout, s);
   }
-  hipLaunchKernelGGL(k_couple_e_final, dim3(nblocks((int64_t)nout, 128)), dim3(128), 0, s, d, scratch, nblk, Hee, X, Y,
+  hipLaunchKernelGGL(k_couple_final, dim3(nblocks((int64_t)nout, 64)), dim3(256), 0, s, d, scratch, nblk, Hee, X, Y,
                      ncolr, ldr);
 }
 
