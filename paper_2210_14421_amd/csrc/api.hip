@@ -179,7 +179,7 @@ efe_status build_device(efe_ctx *ctx) {
     g.lo[i] = pl.lo[i];
     g.h[i] = pl.h[i];
   }
-  g.p = pl.p; g.P = pl.P; g.nloc = pl.nloc; g.qc = pl.qc; g.qe = pl.qe; g.n_nodes = pl.n_nodes;
+  g.p = pl.p; g.P = pl.P; g.nloc = pl.nloc; g.cstride = ((int64_t)pl.nloc * pl.nloc + 3) / 4 * 4; g.qc = pl.qc; g.qe = pl.qe; g.n_nodes = pl.n_nodes;
   const int P = pl.P, NP = P * (P + 1) / 2;
   // 1-D tables
   std::vector<double> tab;
@@ -282,7 +282,7 @@ efe_status build_device(efe_ctx *ctx) {
   ctx->blk = ctx->n_rows * ctx->ncolr;
   const size_t esz = ctx->dtype == 0 ? 8 : (ctx->dtype == 1 ? 4 : 2);
   void *cells = nullptr;
-  size_t cbytes = (size_t)pl.n_cells * pl.nloc * pl.nloc * esz;
+  size_t cbytes = (size_t)pl.n_cells * d.g.cstride * esz;
   hipError_t e = hipMalloc(&cells, cbytes);
   if (e != hipSuccess) { ctx->err = "cell blocks: " + std::string(hip_err(e)); return EFE_ERR_ALLOC; }
   ctx->allocs.push_back(cells);
@@ -329,6 +329,10 @@ efe_status build_device(efe_ctx *ctx) {
     EFE_TRY(upload(ctx, &ctx->one_mask, ones));
   }
   EFE_TRY(dalloc(ctx, &ctx->msc, pl.norb));
+  if (efe::k::cell_apply_init(pl.nloc) != 0) {
+    ctx->err = "cell-product kernels: dynamic LDS limit not accepted";
+    return EFE_ERR_HIP;
+  }
   return sync(ctx, "setup");
 }
 

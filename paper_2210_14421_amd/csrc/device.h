@@ -12,6 +12,7 @@ struct Geom {
   int nc[3];
   int64_t nn[3];
   int p, P, nloc;
+  int64_t cstride;   // elements between stored cell blocks: nloc^2 rounded up to 4 (16-byte aligned blocks)
   int qc, qe;
   double lo[3], h[3];
   int64_t n_nodes;
@@ -81,6 +82,8 @@ void hee_reduce(const DevData &d, const double *hee_part, int kinetic, double *H
                 hipStream_t s);
 
 // Hbar X
+// raises the dynamic LDS limit of the cell-product kernels for cells of nloc nodes; 0 on success
+int cell_apply_init(int nloc);
 void cell_apply(const DevData &d, const void *cells, int dtype, const double *X, double *Y, int ncolr,
                 int64_t ldr, hipStream_t s);
 void couple_apply(const DevData &d, const double *G, const double *Hee, const double *X, double *Y,

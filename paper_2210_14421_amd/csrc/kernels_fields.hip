@@ -118,7 +118,7 @@ k_rebuild(const DevData d, const int *__restrict__ cell_list, int n, int mode, c
     W2[t] = s;
   }
   __syncthreads();
-  T *out = cells + (int64_t)d.cell_slot[cell] * nloc * nloc;   // colour-major storage
+  T *out = cells + (int64_t)d.cell_slot[cell] * d.g.cstride;   // colour-major storage
   for (int c = 0; c < P; ++c)
     for (int c2 = c; c2 < P; ++c2) {
       const int pc = pair[c * P + c2];

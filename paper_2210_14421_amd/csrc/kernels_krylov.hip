@@ -43,39 +43,78 @@ template <> struct Mfma<float> {
   static __device__ __forceinline__ int row(int kr, int r) { return 4 * kr + r; }
 };
 
-// One wave per (cell, pair of 16-row M tiles, chunk of NTW 16-column N tiles).
-// No LDS staging of operands and no barriers: each lane loads its MFMA
-// operands straight from global memory with a PF-deep register pipeline.
-//   A operand (row i, k):  Hbar_c[k][i]  (symmetric block, row-major: 16 lanes
-//                          read 16 consecutive doubles)
-//   B operand (k, col j):  X[node(k)][col0 + j]  (16 consecutive doubles)
-// The waves of one cell get block ids congruent mod 8, so they run on the same
-// XCD (blocks are dealt to the 8 XCDs round-robin) and share its L2 copy of the
-// cell block and of the gathered rows.
-template <typename T, int NTW, int PF>
-__global__ void __launch_bounds__(64)
-k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, int ncells, int npair, int nch,
-             const T *__restrict__ cells, const double *__restrict__ X, double *__restrict__ Y, int ncolr,
-             int64_t ldr) {
+// One workgroup of 8 waves per (cell, chunk of 96 columns); two workgroups
+// share a CU.  Operands pass through LDS in chunks of 8 k-rows, three chunks in
+// flight: the chunk's rows of the symmetric cell block (contiguous in memory)
+// and the gathered rows of X are copied global -> LDS by the direct-to-LDS
+// loads (global_load_lds_dwordx4, 16 B per lane at LDS base + 16 * lane), so
+// no registers hold data in flight.  Every wave issues the same number of
+// copies per chunk (padding copies land in a scratch line), which lets a
+// fixed vmcnt wait certify that the chunk has arrived before the barrier.
+// Wave w takes the M tiles (w >> 1) + 4 i and the three 16-column N tiles of
+// half (w & 1): every SIMD then carries the same number of tiles.
+constexpr int kCellWaves = 8;
+constexpr int kCellNT = 3;                  // N tiles per wave
+constexpr int kCellCols = 2 * kCellNT * 16; // columns per workgroup
+constexpr int kCellKC = 8;                  // k-rows per chunk
+constexpr int kCellNS = 3;                  // chunks in flight
+constexpr int kCellLDX = 112;               // LDS row stride of X (doubles): the 4 rows of a B read hit disjoint banks
+constexpr int kCellXStage = kCellKC * kCellLDX * 8;
+
+// s_waitcnt with vmcnt = N and no wait on the other counters (gfx9 encoding)
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+typedef const void __attribute__((address_space(1))) *gptr_t;
+typedef void __attribute__((address_space(3))) *lptr_t;
+
+__device__ __forceinline__ void copy16_to_lds(const void *src, void *lds_base) {
+  __builtin_amdgcn_global_load_lds((gptr_t)src, (lptr_t)lds_base, 16, 0, 0);
+}
+
+template <typename T>
+struct CellChunk {
+  // A-chunk copies per wave per chunk, sized for the largest cell (nloc <= 384)
+  static constexpr int kAIns = (kCellKC * kApplyMaxLoc * (int)sizeof(T) + 1024 * kCellWaves - 1) / (1024 * kCellWaves);
+  static constexpr int kPer = kAIns + kCellKC / kCellWaves;   // copies per wave per chunk
+};
+
+inline size_t cell_lds_bytes(int nloc, size_t esz) {
+  const size_t aseg = (kCellKC * nloc * esz + 1023) / 1024;
+  return kCellNS * (aseg * 1024 + kCellXStage) + 1024;
+}
+
+template <typename T, int CMT>
+__global__ void __launch_bounds__(kCellWaves * 64)
+k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, const T *__restrict__ cells,
+             const double *__restrict__ X, double *__restrict__ Y, int ncolr, int64_t ldr) {
   typedef typename Mfma<T>::C C;
   typedef typename Mfma<T>::Acc Acc;
-  constexpr int MTW = 2;
+  constexpr int kAIns = CellChunk<T>::kAIns, kPer = CellChunk<T>::kPer;
   __shared__ int64_t rowoff[kApplyMaxLoc];
   __shared__ unsigned char first[kApplyMaxLoc];   // this cell's colour is the first to reach the node
+  extern __shared__ __attribute__((aligned(16))) unsigned char cell_sm[];
   const Geom &g = d.g;
   const int nloc = g.nloc;
-  const int per_cell = npair * nch;
-  const int grp = blockIdx.x / (8 * per_cell), rem = blockIdx.x % (8 * per_cell);
-  const int ci = grp * 8 + rem % 8;
-  if (ci >= ncells) return;
-  const int sub = rem / 8;                  // 0 .. per_cell-1
-  const int pair = sub % npair, ch = sub / npair;
+  const int abytes = kCellKC * nloc * (int)sizeof(T);
+  const int aseg = (abytes + 1023) / 1024;
+  unsigned char *As = cell_sm;                                   // kCellNS * aseg KB
+  unsigned char *Xs = cell_sm + kCellNS * aseg * 1024;           // kCellNS * kCellXStage
+  unsigned char *junk = Xs + kCellNS * kCellXStage;              // 1 KB target of padding copies
+  const int ci = blockIdx.x;
+  const int col0 = blockIdx.y * kCellCols;
+  const int wcol = ncolr - col0 < kCellCols ? ncolr - col0 : kCellCols;   // columns of this chunk (even)
   const int64_t cell = cell_list[ci];
-  const int lane = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int kr = lane >> 4, cl = lane & 15;
+  const int mg = wave >> 1, nh = wave & 1;
   int e[3];
   cell_ijk(g, cell, e);
-  for (int l = lane; l < nloc; l += 64) {
+  for (int l = tid; l < nloc; l += kCellWaves * 64) {
     rowoff[l] = local_node(g, e, l) * ldr;
     // colours run in the order (e_x & 1) + 2 (e_y & 1) + 4 (e_z & 1); a node on a
     // face shared along some axis is reached first by the even cell of that axis
@@ -88,73 +127,87 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, int 
     }
     first[l] = later ? 0 : 1;
   }
+  // X stages start zeroed: pad columns are never copied into
+  for (int i = tid; i < kCellNS * kCellXStage / 8; i += kCellWaves * 64) ((double *)Xs)[i] = 0.0;
   __syncthreads();
-  // blocks are stored in colour-major order: a colour launch streams them contiguously
-  const T *A = cells + (int64_t)(slot0 + ci) * nloc * nloc;
-  const int m0 = pair * MTW * 16;
-  const int col0 = ch * NTW * 16;
-  const int nks = (nloc + 3) / 4;           // k-steps of 4
-  // per-lane fixed parts of the operand addresses
-  int arow[MTW];
-  bool aok[MTW];
+  const unsigned char *Ag = (const unsigned char *)(cells + (int64_t)(slot0 + ci) * g.cstride);   // 16-byte aligned
+  const int64_t ablock = g.cstride * (int64_t)sizeof(T);   // padded block: copies never cross into the next one
+  const int nchunk = (nloc + kCellKC - 1) / kCellKC;
+  auto issue = [&](int kc) {
+    const int st = kc % kCellNS;
+    const int64_t abase = (int64_t)kc * abytes;
 #pragma unroll
-  for (int mt = 0; mt < MTW; ++mt) {
-    arow[mt] = m0 + mt * 16 + cl;
-    aok[mt] = arow[mt] < nloc;
-  }
-  int bcol[NTW];
-  bool bok[NTW];
+    for (int i = 0; i < kAIns; ++i) {
+      const int seg = wave + kCellWaves * i;
+      const int64_t off = abase + (int64_t)seg * 1024 + lane * 16;
+      const bool ok = seg < aseg && off + 16 <= ablock;
+      copy16_to_lds(Ag + (ok ? off : 0), seg < aseg ? As + (st * aseg + seg) * 1024 : junk);
+    }
 #pragma unroll
-  for (int nt = 0; nt < NTW; ++nt) {
-    bcol[nt] = col0 + nt * 16 + cl;
-    bok[nt] = bcol[nt] < ncolr;
-  }
-  C a[PF][MTW], b[PF][NTW];
-  auto load = [&](int ks, C (&av)[MTW], C (&bv)[NTW]) {
-    const int k = ks * 4 + kr;
-    const bool kok = k < nloc;
-    const T *Ak = A + (int64_t)k * nloc;
-#pragma unroll
-    for (int mt = 0; mt < MTW; ++mt) av[mt] = (kok && aok[mt]) ? (C)Ak[arow[mt]] : (C)0;
-    const double *Xk = X + (kok ? rowoff[k] : 0);
-#pragma unroll
-    for (int nt = 0; nt < NTW; ++nt) bv[nt] = (kok && bok[nt]) ? (C)Xk[bcol[nt]] : (C)0;
+    for (int i = 0; i < kCellKC / kCellWaves; ++i) {
+      const int r = wave + kCellWaves * i;
+      const int k = kc * kCellKC + r;
+      if (k < nloc) {
+        if (2 * lane < wcol) copy16_to_lds(X + rowoff[k] + col0 + 2 * lane, Xs + st * kCellXStage + r * kCellLDX * 8);
+      } else {
+        copy16_to_lds(X, junk);
+      }
+    }
   };
-  Acc acc[MTW][NTW];
+  const int nmt = (nloc + 15) / 16;
+  Acc acc[CMT][kCellNT];
 #pragma unroll
-  for (int i = 0; i < MTW; ++i)
+  for (int i = 0; i < CMT; ++i)
 #pragma unroll
-    for (int j = 0; j < NTW; ++j) acc[i][j] = Acc{0, 0, 0, 0};
-  const bool mt1 = m0 + 16 < nloc;          // second M tile of the pair in range
+    for (int j = 0; j < kCellNT; ++j) acc[i][j] = Acc{0, 0, 0, 0};
 #pragma unroll
-  for (int p = 0; p < PF; ++p) load(p, a[p], b[p]);
-  for (int ks0 = 0; ks0 < nks; ks0 += PF) {
+  for (int c = 0; c < kCellNS - 1; ++c)
+    if (c < nchunk) issue(c);
+  for (int kc = 0; kc < nchunk; ++kc) {
+    // this wave's copies of chunk kc are done once at most (chunks issued after it) * kPer remain
+    if (kc + 1 < nchunk) wait_vmcnt<kPer * (kCellNS - 2)>();
+    else wait_vmcnt<0>();
+    __builtin_amdgcn_s_barrier();
+    if (kc + kCellNS - 1 < nchunk) issue(kc + kCellNS - 1);
+    const int st = kc % kCellNS;
+    const T *Al = (const T *)(As + st * aseg * 1024);
+    const double *Xl = (const double *)(Xs + st * kCellXStage);
 #pragma unroll
-    for (int p = 0; p < PF; ++p) {
-      if (ks0 + p < nks) {
+    for (int s4 = 0; s4 < kCellKC / 4; ++s4) {
+      const int kl = s4 * 4 + kr;
+      const bool kok = kc * kCellKC + kl < nloc;
+      C b[kCellNT];
 #pragma unroll
-        for (int nt = 0; nt < NTW; ++nt) {
-          acc[0][nt] = Mfma<T>::mma(a[p][0], b[p][nt], acc[0][nt]);
-          if (mt1) acc[1][nt] = Mfma<T>::mma(a[p][1], b[p][nt], acc[1][nt]);
+      for (int j = 0; j < kCellNT; ++j) b[j] = (C)Xl[kl * kCellLDX + (nh * kCellNT + j) * 16 + cl];
+#pragma unroll
+      for (int i = 0; i < CMT; ++i) {
+        const int t = mg + 4 * i;
+        if (t < nmt) {
+          const int m = t * 16 + cl;
+          const C a = (kok && m < nloc) ? (C)Al[kl * nloc + m] : (C)0;
+#pragma unroll
+          for (int j = 0; j < kCellNT; ++j) acc[i][j] = Mfma<T>::mma(a, b[j], acc[i][j]);
         }
       }
-      if (ks0 + PF + p < nks) load(ks0 + PF + p, a[p], b[p]);
     }
   }
   // D layout of the 16x16 MFMA (differs between the f64 and f32 forms)
 #pragma unroll
-  for (int mt = 0; mt < MTW; ++mt)
+  for (int i = 0; i < CMT; ++i) {
+    if (mg + 4 * i >= nmt) continue;
 #pragma unroll
-    for (int nt = 0; nt < NTW; ++nt)
+    for (int r = 0; r < 4; ++r) {
+      const int row = (mg + 4 * i) * 16 + Mfma<T>::row(kr, r);
+      if (row >= nloc) continue;
+      double *yr = Y + rowoff[row];
+      const bool f = first[row] != 0;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + mt * 16 + Mfma<T>::row(kr, r);
-        const int col = col0 + nt * 16 + cl;
-        if (row < nloc && col < ncolr) {
-          double *y = Y + rowoff[row] + col;
-          *y = first[row] ? (double)acc[mt][nt][r] : *y + (double)acc[mt][nt][r];
-        }
+      for (int j = 0; j < kCellNT; ++j) {
+        const int col = col0 + (nh * kCellNT + j) * 16 + cl;
+        if (col < ncolr) yr[col] = f ? (double)acc[i][j][r] : yr[col] + (double)acc[i][j][r];
       }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -413,31 +466,43 @@ k_tridiag_exp(const double *__restrict__ alpha, const double *__restrict__ beta,
 
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-template <typename T, int NTW>
-void launch_apply_n(const DevData &d, const T *cells, const double *X, double *Y, int ncolr, int64_t ldr, hipStream_t s) {
-  constexpr int PF = 4;
-  const int npair = ((d.g.nloc + 15) / 16 + 1) / 2;
-  const int nch = (ncolr + NTW * 16 - 1) / (NTW * 16);
+template <typename T, int CMT>
+void launch_apply_m(const DevData &d, const T *cells, const double *X, double *Y, int ncolr, int64_t ldr,
+                    hipStream_t s) {
+  const unsigned ny = (unsigned)((ncolr + kCellCols - 1) / kCellCols);
+  const size_t lds = cell_lds_bytes(d.g.nloc, sizeof(T));
   for (int c = 0; c < 8; ++c) {
-    int cnt = d.colour_off[c + 1] - d.colour_off[c];
+    const int cnt = d.colour_off[c + 1] - d.colour_off[c];
     if (cnt == 0) continue;
     const int *list = d.colour_cells + d.colour_off[c];
-    const unsigned nx = (unsigned)(((cnt + 7) / 8) * 8) * npair * nch;
-    hipLaunchKernelGGL((k_cell_apply<T, NTW, PF>), dim3(nx), dim3(64), 0, s, d, list, d.colour_off[c], cnt, npair, nch,
-                       cells, X, Y, ncolr, ldr);
+    hipLaunchKernelGGL((k_cell_apply<T, CMT>), dim3((unsigned)cnt, ny), dim3(kCellWaves * 64), lds, s, d, list,
+                       d.colour_off[c], cells, X, Y, ncolr, ldr);
   }
 }
 
 template <typename T>
 void launch_apply(const DevData &d, const T *cells, const double *X, double *Y, int ncolr, int64_t ldr, hipStream_t s) {
-  if (ncolr <= 16) launch_apply_n<T, 1>(d, cells, X, Y, ncolr, ldr, s);
-  else if (ncolr <= 32) launch_apply_n<T, 2>(d, cells, X, Y, ncolr, ldr, s);
-  else launch_apply_n<T, 3>(d, cells, X, Y, ncolr, ldr, s);
+  const int nmt = (d.g.nloc + 15) / 16;     // M tiles per cell; wave group w >> 1 takes ceil(nmt / 4)
+  if (nmt <= 8) launch_apply_m<T, 2>(d, cells, X, Y, ncolr, ldr, s);
+  else if (nmt <= 16) launch_apply_m<T, 4>(d, cells, X, Y, ncolr, ldr, s);
+  else launch_apply_m<T, 6>(d, cells, X, Y, ncolr, ldr, s);
 }
 
 }  // namespace
 
 namespace k {
+
+int cell_apply_init(int nloc) {
+  const size_t l64 = cell_lds_bytes(nloc, 8), l32 = cell_lds_bytes(nloc, 4);
+  int st = 0;
+  st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<double, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l64);
+  st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<double, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l64);
+  st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<double, 6>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l64);
+  st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<float, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l32);
+  st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<float, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l32);
+  st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<float, 6>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l32);
+  return st;
+}
 
 void cell_apply(const DevData &d, const void *cells, int dtype, const double *X, double *Y, int ncolr, int64_t ldr,
                 hipStream_t s) {
