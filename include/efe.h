@@ -43,6 +43,7 @@ extern "C" {
 
 typedef struct efe_ctx efe_ctx;
 typedef struct efe_plan efe_plan;
+typedef struct efe_batch efe_batch;
 typedef int32_t efe_status;
 
 enum {
@@ -189,6 +190,36 @@ efe_status lanczos_expm(efe_ctx *ctx, int32_t op, double tau, void *X, int32_t n
  * stats: host, may be NULL. */
 efe_status magnus_step(efe_ctx *ctx, void *Psi, int64_t ld, double t, double dt,
                        const efe_field *field, const int32_t *k_force, efe_step_stats *stats);
+
+/* The same step as magnus_step, enqueued with no host round trip and replayed
+ * from a hipGraph captured on the first call (and again whenever Psi, ld, dt or
+ * the field's kind/direction change).  Every Lanczos runs kmax iterations whose
+ * kernels return at once after its last column has met the estimate of
+ * eq. (AdaptiveKrylovErr), and each Poisson solve runs a fixed budget of PCG
+ * iterations that likewise stop on the device, so the results equal
+ * magnus_step's (k per column identical).  The graph runs on a private stream
+ * ordered after and before the context's stream.  No k_force.  EFE_ERR_NOCONV
+ * if a Lanczos needed more than kmax vectors or a Poisson solve did not
+ * converge in the budget (Psi then holds the unconverged step; call
+ * efe_set_hamiltonian before stepping again). */
+efe_status magnus_step_graph(efe_ctx *ctx, void *Psi, int64_t ld, double t, double dt,
+                             const efe_field *field, efe_step_stats *stats);
+
+/* Batched propagation of independent systems (different meshes, orbital
+ * counts, kicks or fields): one step of every member is captured into a single
+ * hipGraph in which the members' device-driven steps (as magnus_step_graph)
+ * are concurrent branches, so small systems share the GPU.  The batch refers
+ * to the contexts (it does not own them; free the batch first).  All members
+ * need efe_set_hamiltonian of their current orbitals. */
+efe_status efe_batch_create(efe_ctx *const *ctxs, int32_t n, efe_batch **batch);
+efe_status efe_batch_free(efe_batch *batch);
+const char *efe_batch_error(const efe_batch *batch);
+/* Psi[i], ld[i]: member i's device block; fields: NULL or n pointers (each may
+ * be NULL); stats: NULL or n entries.  Re-captures when a pointer, ld, dt or a
+ * field's kind/direction changes.  Errors name the first failing member in
+ * efe_batch_error. */
+efe_status efe_batch_step(efe_batch *batch, void *const *Psi, const int64_t *ld, double t, double dt,
+                          const efe_field *const *fields, efe_step_stats *stats);
 
 /* rho(q) = sum_a f_a |psi_a(q)|^2 at every quadrature point (device output,
  * n_quad doubles), psi = M^-1/2 Psi evaluated through the EFE basis. */

@@ -58,11 +58,45 @@ struct efe_ctx {
   int *active = nullptr, *kused = nullptr, *kforce = nullptr, *need = nullptr, *anyflag = nullptr;
   double *h1 = nullptr, *h2n = nullptr, *nrm1 = nullptr, *nrm2 = nullptr;
   double *sig = nullptr, *coef = nullptr, *gsc = nullptr, *msc = nullptr;
+  // device-driven step (no host round trip; capturable in a hipGraph)
+  double *stepp = nullptr;      // [0] E(t + dt/2), [1] E(t + dt), [2] E of a host-driven rebuild
+  double *pcg_S = nullptr;      // PCG scalars
+  int *pcg_done = nullptr;
+  int *lz_anyf = nullptr;       // some column of the running Lanczos still active
+  int *lz_kmaxu = nullptr;      // largest k of the finished Lanczos
+  int *flags = nullptr;         // [0] predictor, [1] corrector Lanczos not converged; [2], [3] PCG not converged
+  double *mu_dev = nullptr;     // dipole of the step
+  int *kstat = nullptr;         // [2][norb] Krylov dimensions of predictor and corrector
+  double *estat = nullptr;      // [2][norb] error estimates
+  double *cgstat = nullptr;     // [2] PCG iterations
+  double *hpin = nullptr;       // pinned host staging: params and step statistics
+  hipStream_t gstream = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  void *gkey_psi = nullptr;
+  int64_t gkey_ld = 0;
+  double gkey_dt = 0.0;
+  int gkey_fkind = -1, gkey_fdir = -1;
   int *one_mask = nullptr;   // all-ones column mask
   // state
   int cells_mode = -1;      // -1 nothing built, 0 Hamiltonian, 1..3 position operator
   bool ham_valid = false;   // rho_prev and the Hamiltonian belong to the current orbitals
   Timer timer;
+};
+
+struct efe_batch {
+  std::vector<efe_ctx *> m;
+  hipStream_t bs = nullptr;
+  hipEvent_t e0 = nullptr;
+  std::vector<hipEvent_t> ev;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<void *> psi;
+  std::vector<int64_t> ld;
+  std::vector<int> fkind, fdir;
+  double dt = 0.0;
+  std::string err;
 };
 
 namespace {
@@ -329,6 +363,16 @@ efe_status build_device(efe_ctx *ctx) {
     EFE_TRY(upload(ctx, &ctx->one_mask, ones));
   }
   EFE_TRY(dalloc(ctx, &ctx->msc, pl.norb));
+  EFE_TRY(dalloc(ctx, &ctx->stepp, 8));
+  EFE_TRY(dalloc(ctx, &ctx->pcg_S, 8));
+  EFE_TRY(dalloc(ctx, &ctx->pcg_done, 1));
+  EFE_TRY(dalloc(ctx, &ctx->lz_anyf, 1));
+  EFE_TRY(dalloc(ctx, &ctx->lz_kmaxu, 1));
+  EFE_TRY(dalloc(ctx, &ctx->flags, 8));
+  EFE_TRY(dalloc(ctx, &ctx->mu_dev, 4));
+  EFE_TRY(dalloc(ctx, &ctx->kstat, 2 * std::max(1, pl.norb)));
+  EFE_TRY(dalloc(ctx, &ctx->estat, 2 * std::max(1, pl.norb)));
+  EFE_TRY(dalloc(ctx, &ctx->cgstat, 2));
   if (efe::k::cell_apply_init(pl.nloc) != 0) {
     ctx->err = "cell-product kernels: dynamic LDS limit not accepted";
     return EFE_ERR_HIP;
@@ -338,7 +382,7 @@ efe_status build_device(efe_ctx *ctx) {
 
 // --------------------------------------------------------------------------- building blocks
 // Y = A X with the operator currently held in the cell blocks (rows with stride ldr doubles)
-efe_status apply_op(efe_ctx *ctx, const double *X, double *Y, int ncolr, int64_t ldr) {
+efe_status apply_op(efe_ctx *ctx, const double *X, double *Y, int ncolr, int64_t ldr, const int *any = nullptr) {
   const DevData &d = ctx->d;
   hipStream_t s = ctx->stream;
   if (ldr != ncolr) {
@@ -346,10 +390,10 @@ efe_status apply_op(efe_ctx *ctx, const double *X, double *Y, int ncolr, int64_t
     return EFE_ERR_ARG;
   }
   tstart(ctx, 0);
-  efe::k::cell_apply(d, ctx->cells, ctx->dtype, X, Y, ncolr, ldr, s);
+  efe::k::cell_apply(d, ctx->cells, ctx->dtype, X, Y, ncolr, ldr, s, any);
   tstop(ctx, 0);
   tstart(ctx, 1);
-  efe::k::couple_apply(d, ctx->G, ctx->Hbar_ee, X, Y, ncolr, ldr, ctx->couple_scr, s);
+  efe::k::couple_apply(d, ctx->G, ctx->Hbar_ee, X, Y, ncolr, ldr, ctx->couple_scr, s, any);
   tstop(ctx, 1);
   ctx->timer.n_hx++;
   return check_launch(ctx, "apply");
@@ -441,7 +485,8 @@ efe_status rebuild(efe_ctx *ctx, int mode, const double *rho, double t, const ef
     if (field && field->kind) fdir = field->direction;
   }
   tstart(ctx, 6);
-  efe::k::rebuild_cells(d, mode, rho, ctx->phi, efield, fdir, ctx->plan.xc, ctx->cells, ctx->dtype, ctx->vq, s);
+  efe::k::set_scalar(ctx->stepp + 2, efield, s);
+  efe::k::rebuild_cells(d, mode, rho, ctx->phi, ctx->stepp + 2, fdir, ctx->plan.xc, ctx->cells, ctx->dtype, ctx->vq, s);
   efe::k::coupling_partials(d, ctx->vq, ctx->part, ctx->hee_part, s);
   efe::k::coupling_gather(d, ctx->part, mode == 0 ? 1 : 0, ctx->G, s);
   efe::k::hee_reduce(d, ctx->hee_part, mode == 0 ? 1 : 0, ctx->Hee_raw, ctx->Hbar_ee, s);
@@ -465,6 +510,44 @@ efe_status dipole_of(efe_ctx *ctx, const double *rho, double mu[3]) {
   efe::k::reduce_partials(ctx->red, nb, 3, ctx->small, ctx->stream);
   HIP_TRY(hipMemcpyAsync(mu, ctx->small, 3 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
   return sync(ctx, "dipole");
+}
+
+// One Lanczos iteration j (enqueue only): slot j = A slot_{j-1}, Gram-Schmidt
+// against slots 0..j-1 with the optional second pass, beta_j, tridiagonal
+// exponential and stopping test.  With any != nullptr every kernel returns at
+// once when no column is active (device-driven loops), and *any is refreshed.
+efe_status lz_iteration(efe_ctx *ctx, double tau, const double *X, int ncol, int j, const int *kf, double tol,
+                        int *any) {
+  hipStream_t s = ctx->stream;
+  const int64_t nrows = ctx->n_rows;
+  const int ncolr = 2 * ncol;
+  const int64_t bs = nrows * ncolr;
+  double *Qb = ctx->Q;
+  const double *prev = j == 1 ? X : Qb + (int64_t)(j - 2) * bs;
+  double *w = Qb + (int64_t)(j - 1) * bs;   // slot j
+  EFE_TRY(apply_op(ctx, prev, w, ncolr, ncolr, any));
+  tstart(ctx, 2);
+  double *a_j = ctx->alpha + (int64_t)(j - 1) * ncol;
+  double *b_j = ctx->beta + (int64_t)(j - 1) * ncol;
+  int nb = efe::k::lz_dots(X, Qb, bs, j, w, nrows, ncol, ctx->active, any, 1, ctx->red, s);
+  efe::k::reduce_partials(ctx->red, nb, (j + 1) * ncolr, ctx->h1, s);
+  efe::k::lz_coef1(ctx->h1, ctx->sig, j, ncol, ctx->active, a_j, ctx->coef, ctx->gsc, ctx->msc, s);
+  nb = efe::k::lz_update(X, Qb, bs, j, ctx->coef, ctx->gsc, w, nrows, ncol, ctx->active, any, ctx->red, s, 1);
+  efe::k::reduce_partials(ctx->red, nb, ncolr, ctx->nrm1, s);
+  efe::k::lz_decide(ctx->nrm1, ncol, ctx->active, ctx->gsc, ctx->need, ctx->anyflag, s);
+  nb = efe::k::lz_dots(X, Qb, bs, j, w, nrows, ncol, ctx->need, ctx->anyflag, 0, ctx->red, s);
+  efe::k::reduce_partials(ctx->red, nb, j * ncolr, ctx->h2n, s);
+  efe::k::lz_coef2(ctx->h2n, ctx->nrm1, ctx->sig, j, ncol, ctx->need, ctx->coef, ctx->gsc, ctx->msc, s);
+  nb = efe::k::lz_update(X, Qb, bs, j, ctx->coef, ctx->gsc, w, nrows, ncol, ctx->need, ctx->anyflag, ctx->red, s);
+  efe::k::reduce_partials(ctx->red, nb, ncolr, ctx->nrm2, s);
+  efe::k::lz_beta(ctx->nrm1, ctx->nrm2, ctx->need, ctx->active, ctx->msc, j, ncol, b_j, ctx->sig, s);
+  tstop(ctx, 2);
+  tstart(ctx, 3);
+  efe::k::tridiag_exp(ctx->alpha, ctx->beta, j, ncol, ctx->kmax, tau, ctx->beta0, kf, tol, ctx->active, ctx->kused,
+                      ctx->errv, ctx->ubuf, s);
+  tstop(ctx, 3);
+  if (any) efe::k::lz_any(ctx->active, ncol, any, s);
+  return check_launch(ctx, "lanczos iteration");
 }
 
 // X (packed, n_rows x ncol complex) -> out = exp(-i tau A) X for the operator in the cell blocks.
@@ -492,7 +575,6 @@ efe_status run_lanczos(efe_ctx *ctx, double tau, const double *X, double *out, i
   }
   const int *kf = kforce_host ? ctx->kforce : nullptr;
   double *Qb = ctx->Q;
-  auto slot = [&](int l) -> const double * { return l == 0 ? X : Qb + (int64_t)(l - 1) * bs; };
   tstart(ctx, 2);
   int nb = efe::k::lz_dots(X, Qb, bs, 0, X, nrows, ncol, ctx->one_mask, nullptr, 1, ctx->red, s);
   efe::k::reduce_partials(ctx->red, nb, ncolr, ctx->small, s);
@@ -515,28 +597,7 @@ efe_status run_lanczos(efe_ctx *ctx, double tau, const double *X, double *out, i
   int j = 0;
   while (any) {
     ++j;
-    double *w = Qb + (int64_t)(j - 1) * bs;   // slot j
-    EFE_TRY(apply_op(ctx, slot(j - 1), w, ncolr, ncolr));
-    tstart(ctx, 2);
-    double *a_j = ctx->alpha + (int64_t)(j - 1) * ncol;
-    double *b_j = ctx->beta + (int64_t)(j - 1) * ncol;
-    nb = efe::k::lz_dots(X, Qb, bs, j, w, nrows, ncol, ctx->active, nullptr, 1, ctx->red, s);
-    efe::k::reduce_partials(ctx->red, nb, (j + 1) * ncolr, ctx->h1, s);
-    efe::k::lz_coef1(ctx->h1, ctx->sig, j, ncol, ctx->active, a_j, ctx->coef, ctx->gsc, ctx->msc, s);
-    nb = efe::k::lz_update(X, Qb, bs, j, ctx->coef, ctx->gsc, w, nrows, ncol, ctx->active, nullptr, ctx->red, s);
-    efe::k::reduce_partials(ctx->red, nb, ncolr, ctx->nrm1, s);
-    efe::k::lz_decide(ctx->nrm1, ncol, ctx->active, ctx->gsc, ctx->need, ctx->anyflag, s);
-    nb = efe::k::lz_dots(X, Qb, bs, j, w, nrows, ncol, ctx->need, ctx->anyflag, 0, ctx->red, s);
-    efe::k::reduce_partials(ctx->red, nb, j * ncolr, ctx->h2n, s);
-    efe::k::lz_coef2(ctx->h2n, ctx->nrm1, ctx->sig, j, ncol, ctx->need, ctx->coef, ctx->gsc, ctx->msc, s);
-    nb = efe::k::lz_update(X, Qb, bs, j, ctx->coef, ctx->gsc, w, nrows, ncol, ctx->need, ctx->anyflag, ctx->red, s);
-    efe::k::reduce_partials(ctx->red, nb, ncolr, ctx->nrm2, s);
-    efe::k::lz_beta(ctx->nrm1, ctx->nrm2, ctx->need, ctx->active, ctx->msc, j, ncol, b_j, ctx->sig, s);
-    tstop(ctx, 2);
-    tstart(ctx, 3);
-    efe::k::tridiag_exp(ctx->alpha, ctx->beta, j, ncol, kmax, tau, ctx->beta0, kf, tol, ctx->active, ctx->kused,
-                        ctx->errv, ctx->ubuf, s);
-    tstop(ctx, 3);
+    EFE_TRY(lz_iteration(ctx, tau, X, ncol, j, kf, tol, nullptr));
     HIP_TRY(hipMemcpyAsync(act.data(), ctx->active, ncol * sizeof(int), hipMemcpyDeviceToHost, s));
     EFE_TRY(sync(ctx, "lanczos iteration"));
     any = false;
@@ -561,6 +622,232 @@ efe_status run_lanczos(efe_ctx *ctx, double tau, const double *X, double *out, i
     if (err_host) err_host[c] = b0h[c] > 0 ? ev[c] : 0.0;
   }
   return EFE_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Device-driven step: the same kernels in the same order, with every decision
+// (Lanczos stopping, PCG convergence) taken on the device, so that a whole
+// Magnus step is enqueued without a host round trip and can be captured in a
+// hipGraph.  Lanczos runs kmax iterations whose kernels return at once after
+// the last column has stopped; PCG runs kDevCgIters iterations likewise.
+// ---------------------------------------------------------------------------
+constexpr int kDevCgIters = 6;
+
+__global__ void k_lz_finish(const int *__restrict__ kused, const double *__restrict__ errv,
+                            const double *__restrict__ beta0, int ncol, const int *__restrict__ any,
+                            int *__restrict__ kstat, double *__restrict__ estat, int *__restrict__ flag) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c == 0) *flag = *any;
+  if (c >= ncol) return;
+  kstat[c] = kused[c];
+  estat[c] = beta0[c] > 0.0 ? errv[c] : 0.0;
+}
+
+__global__ void k_pcg_finish(const double *__restrict__ S, const int *__restrict__ done, double *__restrict__ iters,
+                             int *__restrict__ flag) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  *iters = S[7];
+  *flag = *done ? 0 : 1;
+}
+
+efe_status run_lanczos_dev(efe_ctx *ctx, double tau, const double *X, double *out, int ncol, int stat_slot) {
+  hipStream_t s = ctx->stream;
+  const int64_t nrows = ctx->n_rows;
+  const int ncolr = 2 * ncol;
+  const int64_t bs = nrows * ncolr;
+  const double tol = ctx->opt.krylov_tol > 0 ? ctx->opt.krylov_tol : 1e-10;
+  int nb = efe::k::lz_dots(X, ctx->Q, bs, 0, X, nrows, ncol, ctx->one_mask, nullptr, 1, ctx->red, s);
+  efe::k::reduce_partials(ctx->red, nb, ncolr, ctx->small, s);
+  efe::k::lz_init(ctx->small, ncol, ctx->beta0, ctx->sig, ctx->active, ctx->kused, s);
+  efe::k::lz_any(ctx->active, ncol, ctx->lz_anyf, s);
+  for (int j = 1; j <= ctx->kmax; ++j) EFE_TRY(lz_iteration(ctx, tau, X, ncol, j, nullptr, tol, ctx->lz_anyf));
+  efe::k::lz_comb_coef(ctx->ubuf, ctx->sig, ctx->beta0, ctx->kused, ctx->kmax, ctx->kmax, ncol, ctx->coef, s);
+  efe::k::lz_kmax(ctx->kused, ncol, ctx->lz_kmaxu, s);
+  efe::k::lz_combine(X, ctx->Q, bs, ctx->kmax, ctx->coef, out, nrows, ncol, s, ctx->lz_kmaxu);
+  hipLaunchKernelGGL(k_lz_finish, dim3((ncol + 63) / 64), dim3(64), 0, s, ctx->kused, ctx->errv, ctx->beta0, ncol,
+                     ctx->lz_anyf, ctx->kstat + stat_slot * ctx->norb, ctx->estat + stat_slot * ctx->norb,
+                     ctx->flags + stat_slot);
+  return check_launch(ctx, "device lanczos");
+}
+
+efe_status hartree_dev(efe_ctx *ctx, const double *rho, double *phi, int slot) {
+  const DevData &d = ctx->d;
+  hipStream_t s = ctx->stream;
+  const int64_t N = d.g.n_nodes;
+  double *x = ctx->cg[0], *r = ctx->cg[1], *z = ctx->cg[2], *p = ctx->cg[3], *q = ctx->cg[4], *t1 = ctx->cg[5],
+         *t2 = ctx->cg[6];
+  double *S = ctx->pcg_S;
+  int *done = ctx->pcg_done;
+  const double tol = ctx->opt.cg_tol > 0 ? ctx->opt.cg_tol : 1e-12;
+  auto dot = [&](const double *a, const double *b, double *out) {
+    int nb = efe::k::dot_partials(a, b, N, ctx->red, s);
+    efe::k::reduce_partials(ctx->red, nb, 1, out, s);
+  };
+  efe::k::poisson_rhs(d, rho, ctx->dvec, ctx->rhs, s);
+  efe::k::fdm_apply(d, ctx->rhs, x, t1, t2, s);
+  efe::k::stiffness_apply(d, x, q, t1, t2, s);
+  efe::k::axpby(ctx->rhs, q, 1.0, -1.0, r, N, s);
+  efe::k::zero(p, N, s);
+  dot(ctx->rhs, ctx->rhs, S + 4);
+  dot(r, r, S + 3);
+  efe::k::pcg_scalar(0, S, tol * tol, done, s);
+  for (int it = 0; it < kDevCgIters; ++it) {
+    efe::k::fdm_apply(d, r, z, t1, t2, s, done);
+    dot(r, z, S + 0);
+    efe::k::pcg_scalar(1, S, tol * tol, done, s);
+    efe::k::axpby_dev(z, p, 1.0, S + 6, p, N, done, s);
+    efe::k::stiffness_apply(d, p, q, t1, t2, s, done);
+    dot(p, q, S + 2);
+    efe::k::pcg_scalar(2, S, tol * tol, done, s);
+    efe::k::pcg_update(x, r, p, q, S + 5, N, done, s);
+    dot(r, r, S + 3);
+    efe::k::pcg_scalar(3, S, tol * tol, done, s);
+  }
+  efe::k::copy_rows(x, 1, phi, 1, N, 1, s);
+  efe::k::set_boundary(d, phi, s);
+  hipLaunchKernelGGL(k_pcg_finish, dim3(1), dim3(64), 0, s, S, done, ctx->cgstat + slot, ctx->flags + 2 + slot);
+  return check_launch(ctx, "device hartree");
+}
+
+// Hamiltonian at density rho with the field value read from the device scalar *efield
+efe_status rebuild_dev(efe_ctx *ctx, const double *rho, const double *efield, int fdir, int slot) {
+  const DevData &d = ctx->d;
+  hipStream_t s = ctx->stream;
+  EFE_TRY(hartree_dev(ctx, rho, ctx->phi, slot));
+  efe::k::rebuild_cells(d, 0, rho, ctx->phi, efield, fdir, ctx->plan.xc, ctx->cells, ctx->dtype, ctx->vq, s);
+  efe::k::coupling_partials(d, ctx->vq, ctx->part, ctx->hee_part, s);
+  efe::k::coupling_gather(d, ctx->part, 1, ctx->G, s);
+  efe::k::hee_reduce(d, ctx->hee_part, 1, ctx->Hee_raw, ctx->Hbar_ee, s);
+  return check_launch(ctx, "device rebuild");
+}
+
+// One predictor-corrector Magnus step, enqueued without host synchronisation.
+// Reads E(t + dt/2) and E(t + dt) from ctx->stepp[0..1].
+efe_status magnus_core(efe_ctx *ctx, void *Psi, int64_t ld, double dt, int fdir) {
+  hipStream_t s = ctx->stream;
+  const int no = ctx->norb;
+  const int64_t n = ctx->plan.n_quad;
+  double *Xp = ctx->X1;
+  efe::k::copy_rows((const double *)Psi, 2 * ld, ctx->X0, 2 * no, ctx->n_rows, 2 * no, s);
+  EFE_TRY(run_lanczos_dev(ctx, dt, ctx->X0, Xp, no, 0));
+  EFE_TRY(density_packed(ctx, Xp, ctx->rho_tmp));
+  efe::k::axpby(ctx->rho_prev, ctx->rho_tmp, 0.5, 0.5, ctx->rho_tmp, n, s);
+  EFE_TRY(rebuild_dev(ctx, ctx->rho_tmp, ctx->stepp + 0, fdir, 0));
+  EFE_TRY(run_lanczos_dev(ctx, dt, ctx->X0, Xp, no, 1));
+  EFE_TRY(density_packed(ctx, Xp, ctx->rho_prev));
+  EFE_TRY(rebuild_dev(ctx, ctx->rho_prev, ctx->stepp + 1, fdir, 1));
+  int nb = 0;
+  efe::k::dipole_partials(ctx->d, ctx->rho_prev, ctx->red, &nb, s);
+  efe::k::reduce_partials(ctx->red, nb, 3, ctx->mu_dev, s);
+  efe::k::copy_rows(Xp, 2 * no, (double *)Psi, 2 * ld, ctx->n_rows, 2 * no, s);
+  return check_launch(ctx, "device step");
+}
+
+// Private stream, fork/join events and pinned staging for captured steps.
+efe_status ensure_graph_resources(efe_ctx *ctx) {
+  if (!ctx->gstream) HIP_TRY(hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking));
+  if (!ctx->ev_in) HIP_TRY(hipEventCreateWithFlags(&ctx->ev_in, hipEventDisableTiming));
+  if (!ctx->ev_out) HIP_TRY(hipEventCreateWithFlags(&ctx->ev_out, hipEventDisableTiming));
+  if (!ctx->hpin) HIP_TRY(hipHostMalloc((void **)&ctx->hpin, (size_t)(16 + 4 * std::max(1, ctx->norb)) * sizeof(double)));
+  return EFE_OK;
+}
+
+void drop_graph(efe_ctx *ctx) {
+  if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  ctx->gexec = nullptr;
+  ctx->graph = nullptr;
+  ctx->gkey_psi = nullptr;
+}
+
+// Stage the field values of a step into the pinned buffer and copy them to
+// ctx->stepp on stream s (before the captured work that reads them).
+efe_status stage_params(efe_ctx *ctx, double t, double dt, const efe_field *field, hipStream_t s) {
+  ctx->hpin[0] = field_value(field, t + 0.5 * dt);
+  ctx->hpin[1] = field_value(field, t + dt);
+  HIP_TRY(hipMemcpyAsync(ctx->stepp, ctx->hpin, 2 * sizeof(double), hipMemcpyHostToDevice, s));
+  return EFE_OK;
+}
+
+// Statistics of a device-driven step -> pinned buffer (on stream s)
+efe_status stage_stats(efe_ctx *ctx, hipStream_t s) {
+  const int no = ctx->norb;
+  double *h = ctx->hpin + 8;
+  HIP_TRY(hipMemcpyAsync(h, ctx->mu_dev, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(h + 3, ctx->cgstat, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync((int *)(h + 5), ctx->flags, 4 * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync((int *)(h + 8), ctx->kstat, 2 * no * sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(h + 8 + no, ctx->estat, 2 * no * sizeof(double), hipMemcpyDeviceToHost, s));
+  return EFE_OK;
+}
+
+// After the stream has drained: check the device flags and fill stats.
+efe_status finish_stats(efe_ctx *ctx, efe_step_stats *stats) {
+  const int no = ctx->norb;
+  const double *h = ctx->hpin + 8;
+  const int *fl = (const int *)(h + 5);
+  const int *ks = (const int *)(h + 8);
+  const double *es = h + 8 + no;
+  if (fl[0] || fl[1]) {
+    ctx->err = "Lanczos did not reach the tolerance within kmax vectors";
+    return EFE_ERR_NOCONV;
+  }
+  if (fl[2] || fl[3]) {
+    ctx->err = "Poisson PCG did not reach the tolerance in the device iteration budget";
+    return EFE_ERR_NOCONV;
+  }
+  if (!std::isfinite(h[0]) || !std::isfinite(h[1]) || !std::isfinite(h[2])) {
+    ctx->err = "non-finite dipole after the step";
+    return EFE_ERR_NONFINITE;
+  }
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    for (int c = 0; c < no && c < 128; ++c) {
+      stats->k_pred[c] = ks[c];
+      stats->k_corr[c] = ks[no + c];
+      stats->err_pred_max = std::max(stats->err_pred_max, es[c]);
+      stats->err_corr_max = std::max(stats->err_corr_max, es[no + c]);
+    }
+    stats->cg_iters[0] = (int)h[3];
+    stats->cg_iters[1] = (int)h[4];
+    for (int k = 0; k < 3; ++k) stats->mu[k] = h[k];
+  }
+  return EFE_OK;
+}
+
+// Capture magnus_core for (Psi, ld, dt, field shape) on the context's private stream.
+efe_status capture_step(efe_ctx *ctx, void *Psi, int64_t ld, double dt, const efe_field *field) {
+  drop_graph(ctx);
+  const int fdir = (field && field->kind) ? field->direction : 2;
+  hipStream_t user = ctx->stream;
+  const bool timing = ctx->timer.on;
+  ctx->timer.on = false;
+  ctx->stream = ctx->gstream;
+  hipError_t e = hipStreamBeginCapture(ctx->gstream, hipStreamCaptureModeThreadLocal);
+  efe_status st = e == hipSuccess ? magnus_core(ctx, Psi, ld, dt, fdir) : EFE_ERR_HIP;
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(ctx->gstream, &g);
+  ctx->stream = user;
+  ctx->timer.on = timing;
+  if (e != hipSuccess || e2 != hipSuccess || st != EFE_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    if (ctx->err.empty()) ctx->err = "step capture failed";
+    return st != EFE_OK ? st : EFE_ERR_HIP;
+  }
+  ctx->graph = g;
+  HIP_TRY(hipGraphInstantiate(&ctx->gexec, g, nullptr, nullptr, 0));
+  ctx->gkey_psi = Psi;
+  ctx->gkey_ld = ld;
+  ctx->gkey_dt = dt;
+  ctx->gkey_fkind = field ? field->kind : 0;
+  ctx->gkey_fdir = fdir;
+  return EFE_OK;
+}
+
+bool graph_matches(const efe_ctx *ctx, void *Psi, int64_t ld, double dt, const efe_field *field) {
+  const int fdir = (field && field->kind) ? field->direction : 2;
+  return ctx->gexec && ctx->gkey_psi == Psi && ctx->gkey_ld == ld && ctx->gkey_dt == dt &&
+         ctx->gkey_fkind == (field ? field->kind : 0) && ctx->gkey_fdir == fdir;
 }
 
 efe_status check_ctx(efe_ctx *ctx) {
@@ -687,6 +974,14 @@ efe_status efe_free(efe_ctx *ctx) {
   if (ctx->stream) hipStreamSynchronize(ctx->stream);
   else hipDeviceSynchronize();
   timer_reset(ctx);
+  drop_graph(ctx);
+  if (ctx->gstream) {
+    (void)hipStreamSynchronize(ctx->gstream);
+    (void)hipStreamDestroy(ctx->gstream);
+  }
+  if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
+  if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
+  if (ctx->hpin) (void)hipHostFree(ctx->hpin);
   for (void *p : ctx->allocs) hipFree(p);
   delete ctx;
   return EFE_OK;
@@ -863,6 +1158,175 @@ efe_status dipole(efe_ctx *ctx, const void *Psi, int64_t ld, double mu[3]) {
   EFE_TRY(pack_in(ctx, Psi, ld, ctx->norb, ctx->X0));
   EFE_TRY(density_packed(ctx, ctx->X0, ctx->rho_tmp));
   return dipole_of(ctx, ctx->rho_tmp, mu);
+}
+
+efe_status magnus_step_graph(efe_ctx *ctx, void *Psi, int64_t ld, double t, double dt, const efe_field *field,
+                             efe_step_stats *stats) {
+  if (!ctx || !Psi || ld < ctx->norb || !std::isfinite(t) || !std::isfinite(dt)) return EFE_ERR_ARG;
+  EFE_TRY(validate_field(ctx, field));
+  if (!ctx->ham_valid || ctx->cells_mode != 0) {
+    ctx->err = "magnus_step_graph needs the Hamiltonian of the current orbitals (call efe_set_hamiltonian)";
+    return EFE_ERR_STATE;
+  }
+  EFE_TRY(ensure_graph_resources(ctx));
+  if (!graph_matches(ctx, Psi, ld, dt, field)) EFE_TRY(capture_step(ctx, Psi, ld, dt, field));
+  ctx->ham_valid = false;   // restored on success
+  HIP_TRY(hipEventRecord(ctx->ev_in, ctx->stream));
+  HIP_TRY(hipStreamWaitEvent(ctx->gstream, ctx->ev_in, 0));
+  EFE_TRY(stage_params(ctx, t, dt, field, ctx->gstream));
+  HIP_TRY(hipGraphLaunch(ctx->gexec, ctx->gstream));
+  EFE_TRY(stage_stats(ctx, ctx->gstream));
+  HIP_TRY(hipEventRecord(ctx->ev_out, ctx->gstream));
+  HIP_TRY(hipStreamWaitEvent(ctx->stream, ctx->ev_out, 0));
+  HIP_TRY(hipStreamSynchronize(ctx->gstream));
+  EFE_TRY(finish_stats(ctx, stats));
+  ctx->ham_valid = true;
+  return EFE_OK;
+}
+
+efe_status efe_batch_create(efe_ctx *const *ctxs, int32_t n, efe_batch **out) {
+  if (!ctxs || n < 1 || !out) return EFE_ERR_ARG;
+  *out = nullptr;
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i]) return EFE_ERR_ARG;
+    for (int k = 0; k < i; ++k)
+      if (ctxs[k] == ctxs[i]) return EFE_ERR_ARG;
+  }
+  efe_batch *b = new (std::nothrow) efe_batch();
+  if (!b) return EFE_ERR_ALLOC;
+  b->m.assign(ctxs, ctxs + n);
+  b->ev.assign(n, nullptr);
+  hipError_t e = hipStreamCreateWithFlags(&b->bs, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->e0, hipEventDisableTiming);
+  for (int i = 0; i < n && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&b->ev[i], hipEventDisableTiming);
+  for (int i = 0; i < n && e == hipSuccess; ++i)
+    if (ensure_graph_resources(b->m[i]) != EFE_OK) e = hipErrorOutOfMemory;
+  *out = b;
+  if (e != hipSuccess) {
+    b->err = std::string("batch resources: ") + hip_err(e);
+    return EFE_ERR_HIP;
+  }
+  return EFE_OK;
+}
+
+efe_status efe_batch_free(efe_batch *b) {
+  if (!b) return EFE_OK;
+  if (b->bs) (void)hipStreamSynchronize(b->bs);
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (hipEvent_t e : b->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (b->e0) (void)hipEventDestroy(b->e0);
+  if (b->bs) (void)hipStreamDestroy(b->bs);
+  delete b;
+  return EFE_OK;
+}
+
+const char *efe_batch_error(const efe_batch *b) { return b ? b->err.c_str() : "null batch"; }
+
+efe_status efe_batch_step(efe_batch *b, void *const *Psi, const int64_t *ld, double t, double dt,
+                          const efe_field *const *fields, efe_step_stats *stats) {
+  if (!b || !Psi || !ld || !std::isfinite(t) || !std::isfinite(dt)) return EFE_ERR_ARG;
+  const int n = (int)b->m.size();
+  b->err.clear();
+  for (int i = 0; i < n; ++i) {
+    efe_ctx *c = b->m[i];
+    const efe_field *f = fields ? fields[i] : nullptr;
+    if (!Psi[i] || ld[i] < c->norb) return EFE_ERR_ARG;
+    if (validate_field(c, f) != EFE_OK) {
+      b->err = "member " + std::to_string(i) + ": " + c->err;
+      return EFE_ERR_ARG;
+    }
+    if (!c->ham_valid || c->cells_mode != 0) {
+      b->err = "member " + std::to_string(i) + " needs the Hamiltonian of its orbitals (efe_set_hamiltonian)";
+      return EFE_ERR_STATE;
+    }
+  }
+  // (re)capture: members run as concurrent branches forked from the batch stream
+  bool same = b->gexec && b->dt == dt;
+  for (int i = 0; same && i < n; ++i) {
+    const efe_field *f = fields ? fields[i] : nullptr;
+    same = b->psi[i] == Psi[i] && b->ld[i] == ld[i] && b->fkind[i] == (f ? f->kind : 0) &&
+           b->fdir[i] == ((f && f->kind) ? f->direction : 2);
+  }
+  if (!same) {
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+    b->psi.assign(Psi, Psi + n);
+    b->ld.assign(ld, ld + n);
+    b->fkind.assign(n, 0);
+    b->fdir.assign(n, 2);
+    for (int i = 0; i < n; ++i) {
+      const efe_field *f = fields ? fields[i] : nullptr;
+      b->fkind[i] = f ? f->kind : 0;
+      b->fdir[i] = (f && f->kind) ? f->direction : 2;
+    }
+    b->dt = dt;
+    hipError_t e = hipStreamBeginCapture(b->bs, hipStreamCaptureModeThreadLocal);
+    efe_status st = EFE_OK;
+    if (e == hipSuccess) e = hipEventRecord(b->e0, b->bs);
+    for (int i = 0; i < n && e == hipSuccess && st == EFE_OK; ++i) {
+      efe_ctx *c = b->m[i];
+      e = hipStreamWaitEvent(c->gstream, b->e0, 0);
+      if (e != hipSuccess) break;
+      hipStream_t user = c->stream;
+      const bool timing = c->timer.on;
+      c->timer.on = false;
+      c->stream = c->gstream;
+      st = magnus_core(c, Psi[i], ld[i], dt, b->fdir[i]);
+      c->stream = user;
+      c->timer.on = timing;
+      if (st != EFE_OK) b->err = "member " + std::to_string(i) + ": " + c->err;
+      if (st == EFE_OK) e = hipEventRecord(b->ev[i], c->gstream);
+      if (st == EFE_OK && e == hipSuccess) e = hipStreamWaitEvent(b->bs, b->ev[i], 0);
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->bs, &g);
+    if (e != hipSuccess || e2 != hipSuccess || st != EFE_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      if (b->err.empty()) b->err = std::string("batch capture: ") + hip_err(e != hipSuccess ? e : e2);
+      return st != EFE_OK ? st : EFE_ERR_HIP;
+    }
+    b->graph = g;
+    e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      b->err = std::string("batch graph instantiate: ") + hip_err(e);
+      return EFE_ERR_HIP;
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    efe_ctx *c = b->m[i];
+    c->ham_valid = false;
+    if (hipEventRecord(c->ev_in, c->stream) != hipSuccess || hipStreamWaitEvent(b->bs, c->ev_in, 0) != hipSuccess) {
+      b->err = "batch: stream ordering failed";
+      return EFE_ERR_HIP;
+    }
+    EFE_TRY(stage_params(c, t, dt, fields ? fields[i] : nullptr, b->bs));
+  }
+  if (hipGraphLaunch(b->gexec, b->bs) != hipSuccess) {
+    b->err = "batch graph launch failed";
+    return EFE_ERR_HIP;
+  }
+  for (int i = 0; i < n; ++i) EFE_TRY(stage_stats(b->m[i], b->bs));
+  if (hipEventRecord(b->e0, b->bs) != hipSuccess) return EFE_ERR_HIP;
+  for (int i = 0; i < n; ++i)
+    if (hipStreamWaitEvent(b->m[i]->stream, b->e0, 0) != hipSuccess) return EFE_ERR_HIP;
+  if (hipStreamSynchronize(b->bs) != hipSuccess) {
+    b->err = "batch step failed on the device";
+    return EFE_ERR_HIP;
+  }
+  efe_status first = EFE_OK;
+  for (int i = 0; i < n; ++i) {
+    efe_status st = finish_stats(b->m[i], stats ? stats + i : nullptr);
+    if (st == EFE_OK) b->m[i]->ham_valid = true;
+    else if (first == EFE_OK) {
+      first = st;
+      b->err = "member " + std::to_string(i) + ": " + b->m[i]->err;
+    }
+  }
+  return first;
 }
 
 efe_status efe_enable_timing(efe_ctx *ctx, int32_t on) {

@@ -74,8 +74,8 @@ void copy_rows(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t
 void axpby(const double *x, const double *y, double a, double b, double *out, int64_t n, hipStream_t s);
 
 // rebuild of the cell blocks: mode 0 = Hamiltonian, 1..3 = position operator x/y/z
-void rebuild_cells(const DevData &d, int mode, const double *rho, const double *phi, double efield,
-                   int fdir, int xc, void *cells, int dtype, double *vq, hipStream_t s);
+void rebuild_cells(const DevData &d, int mode, const double *rho, const double *phi, const double *efield, int fdir,
+                   int xc, void *cells, int dtype, double *vq, hipStream_t s);
 void coupling_partials(const DevData &d, const double *vq, double *part, double *hee_part, hipStream_t s);
 void coupling_gather(const DevData &d, const double *part, int kinetic, double *G, hipStream_t s);
 void hee_reduce(const DevData &d, const double *hee_part, int kinetic, double *Hee_raw, double *Hbar_ee,
@@ -84,18 +84,27 @@ void hee_reduce(const DevData &d, const double *hee_part, int kinetic, double *H
 // Hbar X
 // raises the dynamic LDS limit of the cell-product kernels for cells of nloc nodes; 0 on success
 int cell_apply_init(int nloc);
-void cell_apply(const DevData &d, const void *cells, int dtype, const double *X, double *Y, int ncolr,
-                int64_t ldr, hipStream_t s);
+void cell_apply(const DevData &d, const void *cells, int dtype, const double *X, double *Y, int ncolr, int64_t ldr,
+                hipStream_t s, const int *any = nullptr);
 void couple_apply(const DevData &d, const double *G, const double *Hee, const double *X, double *Y,
-                  int ncolr, int64_t ldr, double *scratch, hipStream_t s);
+                  int ncolr, int64_t ldr, double *scratch, hipStream_t s, const int *any = nullptr);
 
 // density and Poisson
 void psiE(const DevData &d, const double *X, int ncolr, int64_t ldr, double *psiE, hipStream_t s);
 void density(const DevData &d, const double *X, int ncol, int64_t ldr, const double *psiE, double *rho,
              hipStream_t s);
 void poisson_rhs(const DevData &d, const double *rho, double *dvec, double *rhs, hipStream_t s);
-void stiffness_apply(const DevData &d, const double *x, double *y, double *t1, double *t2, hipStream_t s);
-void fdm_apply(const DevData &d, const double *r, double *z, double *t1, double *t2, hipStream_t s);
+void stiffness_apply(const DevData &d, const double *x, double *y, double *t1, double *t2, hipStream_t s,
+                     const int *skip = nullptr);
+void fdm_apply(const DevData &d, const double *r, double *z, double *t1, double *t2, hipStream_t s,
+               const int *skip = nullptr);
+// device-side PCG pieces (all skipped while *skip != 0)
+void axpby_dev(const double *x, const double *y, double a, const double *b, double *out, int64_t n, const int *skip,
+               hipStream_t s);
+void pcg_update(double *x, double *r, const double *p, const double *q, const double *alpha, int64_t n,
+                const int *skip, hipStream_t s);
+void pcg_scalar(int op, double *S, double tol2, int *done, hipStream_t s);
+void set_scalar(double *p, double v, hipStream_t s);
 void set_boundary(const DevData &d, double *phi, hipStream_t s);
 // partial dot products: out[blk] partials; returns number of blocks used
 int dot_partials(const double *x, const double *y, int64_t n, double *part, hipStream_t s);
@@ -106,9 +115,12 @@ void dipole_partials(const DevData &d, const double *rho, double *part, int *nbl
 int lz_dots(const double *q0, const double *qb, int64_t bs, int nq, const double *w, int64_t nrows, int ncol,
             const int *mask, const int *any, int with_norm, double *part, hipStream_t s);
 int lz_update(const double *q0, const double *qb, int64_t bs, int nq, const double *coef, const double *gw, double *w,
-              int64_t nrows, int ncol, const int *mask, const int *any, double *part, hipStream_t s);
+              int64_t nrows, int ncol, const int *mask, const int *any, double *part, hipStream_t s,
+              int zero_masked = 0);
+// nq_dev (optional): device count that bounds nq (the largest k of the columns)
 void lz_combine(const double *q0, const double *qb, int64_t bs, int nq, const double *coef, double *out,
-                int64_t nrows, int ncol, hipStream_t s);
+                int64_t nrows, int ncol, hipStream_t s, const int *nq_dev = nullptr);
+void lz_kmax(const int *kused, int ncol, int *kmaxu, hipStream_t s);
 void lz_init(const double *h0, int ncol, double *beta0, double *sig, int *active, int *kused, hipStream_t s);
 void lz_coef1(const double *h, const double *sig, int j, int ncol, const int *active, double *alpha_j, double *coef,
               double *gsc, double *msc, hipStream_t s);
@@ -118,6 +130,8 @@ void lz_coef2(const double *h2, const double *nrm1, const double *sig, int j, in
               double *gsc, double *msc, hipStream_t s);
 void lz_beta(const double *nrm1, const double *nrm2, const int *need, const int *active, const double *msc, int j,
              int ncol, double *beta_j, double *sig, hipStream_t s);
+// any = OR of the active flags of ncol columns
+void lz_any(const int *active, int ncol, int *any, hipStream_t s);
 void lz_comb_coef(const double *u, const double *sig, const double *beta0, const int *kused, int kmax, int nl,
                   int ncol, double *coef, hipStream_t s);
 void tridiag_exp(const double *alpha, const double *beta, int j, int ncol, int kmax, double tau,

@@ -37,7 +37,7 @@ template <> __device__ __forceinline__ uint16_t cast_out<uint16_t>(double v) { r
 template <typename T>
 __global__ void __launch_bounds__(kThreads)
 k_rebuild(const DevData d, const int *__restrict__ cell_list, int n, int mode, const double *__restrict__ rho,
-          const double *__restrict__ phi, double efield, int fdir, int xc, T *__restrict__ cells,
+          const double *__restrict__ phi, const double *__restrict__ efield_p, int fdir, int xc, T *__restrict__ cells,
           double *__restrict__ vq) {
   extern __shared__ double sm[];
   const Geom &g = d.g;
@@ -86,6 +86,7 @@ k_rebuild(const DevData d, const int *__restrict__ cell_list, int n, int mode, c
     __syncthreads();
   }
   const double jac = 0.125 * g.h[0] * g.h[1] * g.h[2];
+  const double efield = efield_p ? *efield_p : 0.0;
   for (int q = threadIdx.x; q < n3; q += blockDim.x) {
     int i = q % n, j = (q / n) % n, k = q / (n * n);
     double x[3] = {g.lo[0] + e[0] * g.h[0] + (tab[tox + i] + 1.0) * 0.5 * g.h[0],
@@ -402,7 +403,8 @@ __global__ void k_rhs_finish(const DevData d, const double *__restrict__ dvec, d
 
 // out = A_axis in (banded 1-D operator, bandwidth p), over all nodes
 __global__ void k_axis_band(const DevData d, const double *__restrict__ A, int axis, const double *__restrict__ in,
-                            double *__restrict__ out) {
+                            double *__restrict__ out, const int *__restrict__ skip) {
+  if (skip && *skip) return;
   const Geom &g = d.g;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.n_nodes) return;
@@ -416,7 +418,9 @@ __global__ void k_axis_band(const DevData d, const double *__restrict__ A, int a
 }
 
 // y (+)= x on interior nodes; boundary of y zeroed
-__global__ void k_interior_acc(const DevData d, const double *__restrict__ x, double *__restrict__ y, int accumulate) {
+__global__ void k_interior_acc(const DevData d, const double *__restrict__ x, double *__restrict__ y, int accumulate,
+                               const int *__restrict__ skip) {
+  if (skip && *skip) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.g.n_nodes) return;
   double v = d.Dm12[i] != 0.0 ? x[i] : 0.0;
@@ -426,7 +430,8 @@ __global__ void k_interior_acc(const DevData d, const double *__restrict__ x, do
 // fast diagonalisation transform along one axis on interior nodes:
 // fwd: out_i = sum_a V[a][i] in_a ; back: out_a = sum_i V[a][i] in_i (V: m x m, m = nn - 2)
 __global__ void k_fdm_axis(const DevData d, const double *__restrict__ V, int axis, int back,
-                           const double *__restrict__ in, double *__restrict__ out) {
+                           const double *__restrict__ in, double *__restrict__ out, const int *__restrict__ skip) {
+  if (skip && *skip) return;
   const Geom &g = d.g;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.n_nodes) return;
@@ -444,7 +449,8 @@ __global__ void k_fdm_axis(const DevData d, const double *__restrict__ V, int ax
   out[i] = s;
 }
 
-__global__ void k_fdm_scale(const DevData d, double *__restrict__ t) {
+__global__ void k_fdm_scale(const DevData d, double *__restrict__ t, const int *__restrict__ skip) {
+  if (skip && *skip) return;
   const Geom &g = d.g;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= g.n_nodes) return;
@@ -518,6 +524,58 @@ __global__ void k_axpby(const double *x, const double *y, double a, double b, do
   if (i < n) out[i] = a * x[i] + b * y[i];
 }
 
+// out = a x + (*b) y  (skipped when *skip)
+__global__ void k_axpby_dev(const double *x, const double *y, double a, const double *__restrict__ b, double *out,
+                            int64_t n, const int *__restrict__ skip) {
+  if (skip && *skip) return;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = a * x[i] + *b * y[i];
+}
+
+// x += alpha p ; r -= alpha q  (skipped when *skip)
+__global__ void k_pcg_update(double *__restrict__ x, double *__restrict__ r, const double *__restrict__ p,
+                             const double *__restrict__ q, const double *__restrict__ alpha, int64_t n,
+                             const int *__restrict__ skip) {
+  if (skip && *skip) return;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const double a = *alpha;
+    x[i] += a * p[i];
+    r[i] -= a * q[i];
+  }
+}
+
+// Scalar bookkeeping of the preconditioned CG on the device (one thread).
+// S: [0] r.z  [1] previous r.z  [2] p.q  [3] r.r  [4] rhs.rhs  [5] alpha  [6] beta  [7] iterations
+__global__ void k_pcg_scalar(int op, double *__restrict__ S, double tol2, int *__restrict__ done) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  switch (op) {
+    case 0:   // start: converged already?
+      *done = (S[3] <= tol2 * S[4] || S[4] == 0.0) ? 1 : 0;
+      S[7] = 0.0;
+      break;
+    case 1:   // beta from r.z (first iteration: 0)
+      if (!*done) S[6] = S[7] == 0.0 ? 0.0 : S[0] / S[1];
+      break;
+    case 2:   // alpha = r.z / p.q
+      if (!*done) {
+        S[5] = S[0] / S[2];
+        S[1] = S[0];
+      }
+      break;
+    case 3:   // after the update: count and test
+      if (!*done) {
+        S[7] += 1.0;
+        if (S[3] <= tol2 * S[4]) *done = 1;
+      }
+      break;
+  }
+}
+
+__global__ void k_set_scalar(double *__restrict__ p, double v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
 __global__ void k_copy_rows(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t nrows, int ncolr) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nrows * ncolr) return;
@@ -553,8 +611,8 @@ static size_t rebuild_lds(const Geom &g, int n) {
   return dbl * sizeof(double) + P * P * sizeof(int) + 64;
 }
 
-void rebuild_cells(const DevData &d, int mode, const double *rho, const double *phi, double efield, int fdir, int xc,
-                   void *cells, int dtype, double *vq, hipStream_t s) {
+void rebuild_cells(const DevData &d, int mode, const double *rho, const double *phi, const double *efield, int fdir,
+                   int xc, void *cells, int dtype, double *vq, hipStream_t s) {
   for (int cls = 0; cls < 2; ++cls) {
     int nc = cls ? d.n_enr : d.n_ord;
     if (nc == 0) continue;
@@ -633,26 +691,45 @@ void poisson_rhs(const DevData &d, const double *rho, double *dvec, double *rhs,
 }
 
 // y = K_II x for x with zero boundary: K = K1 x M1 x M1 + M1 x K1 x M1 + M1 x M1 x K1
-void stiffness_apply(const DevData &d, const double *x, double *y, double *t1, double *t2, hipStream_t s) {
+void stiffness_apply(const DevData &d, const double *x, double *y, double *t1, double *t2, hipStream_t s,
+                     const int *skip) {
   const unsigned nb = nblocks(d.g.n_nodes, 256);
   for (int term = 0; term < 3; ++term) {
-    hipLaunchKernelGGL(k_axis_band, dim3(nb), dim3(256), 0, s, d, term == 0 ? d.K1[0] : d.M1[0], 0, x, t1);
-    hipLaunchKernelGGL(k_axis_band, dim3(nb), dim3(256), 0, s, d, term == 1 ? d.K1[1] : d.M1[1], 1, t1, t2);
-    hipLaunchKernelGGL(k_axis_band, dim3(nb), dim3(256), 0, s, d, term == 2 ? d.K1[2] : d.M1[2], 2, t2, t1);
-    hipLaunchKernelGGL(k_interior_acc, dim3(nb), dim3(256), 0, s, d, t1, y, term > 0 ? 1 : 0);
+    hipLaunchKernelGGL(k_axis_band, dim3(nb), dim3(256), 0, s, d, term == 0 ? d.K1[0] : d.M1[0], 0, x, t1, skip);
+    hipLaunchKernelGGL(k_axis_band, dim3(nb), dim3(256), 0, s, d, term == 1 ? d.K1[1] : d.M1[1], 1, t1, t2, skip);
+    hipLaunchKernelGGL(k_axis_band, dim3(nb), dim3(256), 0, s, d, term == 2 ? d.K1[2] : d.M1[2], 2, t2, t1, skip);
+    hipLaunchKernelGGL(k_interior_acc, dim3(nb), dim3(256), 0, s, d, t1, y, term > 0 ? 1 : 0, skip);
   }
 }
 
 // z = K_II^-1 r on interior nodes by fast diagonalisation
-void fdm_apply(const DevData &d, const double *r, double *z, double *t1, double *t2, hipStream_t s) {
+void fdm_apply(const DevData &d, const double *r, double *z, double *t1, double *t2, hipStream_t s, const int *skip) {
   const unsigned nb = nblocks(d.g.n_nodes, 256);
-  hipLaunchKernelGGL(k_fdm_axis, dim3(nb), dim3(256), 0, s, d, d.fdmV[0], 0, 0, r, t1);
-  hipLaunchKernelGGL(k_fdm_axis, dim3(nb), dim3(256), 0, s, d, d.fdmV[1], 1, 0, t1, t2);
-  hipLaunchKernelGGL(k_fdm_axis, dim3(nb), dim3(256), 0, s, d, d.fdmV[2], 2, 0, t2, t1);
-  hipLaunchKernelGGL(k_fdm_scale, dim3(nb), dim3(256), 0, s, d, t1);
-  hipLaunchKernelGGL(k_fdm_axis, dim3(nb), dim3(256), 0, s, d, d.fdmV[2], 2, 1, t1, t2);
-  hipLaunchKernelGGL(k_fdm_axis, dim3(nb), dim3(256), 0, s, d, d.fdmV[1], 1, 1, t2, t1);
-  hipLaunchKernelGGL(k_fdm_axis, dim3(nb), dim3(256), 0, s, d, d.fdmV[0], 0, 1, t1, z);
+  hipLaunchKernelGGL(k_fdm_axis, dim3(nb), dim3(256), 0, s, d, d.fdmV[0], 0, 0, r, t1, skip);
+  hipLaunchKernelGGL(k_fdm_axis, dim3(nb), dim3(256), 0, s, d, d.fdmV[1], 1, 0, t1, t2, skip);
+  hipLaunchKernelGGL(k_fdm_axis, dim3(nb), dim3(256), 0, s, d, d.fdmV[2], 2, 0, t2, t1, skip);
+  hipLaunchKernelGGL(k_fdm_scale, dim3(nb), dim3(256), 0, s, d, t1, skip);
+  hipLaunchKernelGGL(k_fdm_axis, dim3(nb), dim3(256), 0, s, d, d.fdmV[2], 2, 1, t1, t2, skip);
+  hipLaunchKernelGGL(k_fdm_axis, dim3(nb), dim3(256), 0, s, d, d.fdmV[1], 1, 1, t2, t1, skip);
+  hipLaunchKernelGGL(k_fdm_axis, dim3(nb), dim3(256), 0, s, d, d.fdmV[0], 0, 1, t1, z, skip);
+}
+
+void axpby_dev(const double *x, const double *y, double a, const double *b, double *out, int64_t n, const int *skip,
+               hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_axpby_dev, dim3(nblocks(n, 256)), dim3(256), 0, s, x, y, a, b, out, n, skip);
+}
+
+void pcg_update(double *x, double *r, const double *p, const double *q, const double *alpha, int64_t n,
+                const int *skip, hipStream_t s) {
+  if (n > 0) hipLaunchKernelGGL(k_pcg_update, dim3(nblocks(n, 256)), dim3(256), 0, s, x, r, p, q, alpha, n, skip);
+}
+
+void pcg_scalar(int op, double *S, double tol2, int *done, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_scalar, dim3(1), dim3(64), 0, s, op, S, tol2, done);
+}
+
+void set_scalar(double *p, double v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_scalar, dim3(1), dim3(64), 0, s, p, v);
 }
 
 void set_boundary(const DevData &d, double *phi, hipStream_t s) {

@@ -90,7 +90,8 @@ inline size_t cell_lds_bytes(int nloc, size_t esz) {
 template <typename T, int CMT>
 __global__ void __launch_bounds__(kCellWaves * 64)
 k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, const T *__restrict__ cells,
-             const double *__restrict__ X, double *__restrict__ Y, int ncolr, int64_t ldr) {
+             const double *__restrict__ X, double *__restrict__ Y, int ncolr, int64_t ldr, const int *__restrict__ any) {
+  if (any && *any == 0) return;
   typedef typename Mfma<T>::C C;
   typedef typename Mfma<T>::Acc Acc;
   constexpr int kAIns = CellChunk<T>::kAIns, kPer = CellChunk<T>::kPer;
@@ -228,7 +229,8 @@ constexpr int KMT = 3;    // 16-row tiles of Y_E per block (48 functions)
 
 __global__ void __launch_bounds__(64)
 k_couple_c(const DevData d, const double *__restrict__ G, const double *__restrict__ X, double *__restrict__ Y,
-           int ncolr, int64_t ldr, int64_t tiles_per_wave) {
+           int ncolr, int64_t ldr, int64_t tiles_per_wave, const int *__restrict__ any) {
+  if (any && *any == 0) return;
   const int nk = d.nk;
   const int64_t nr = d.nr;
   const int lane = threadIdx.x, kr = lane >> 4, cl = lane & 15;
@@ -278,7 +280,8 @@ k_couple_c(const DevData d, const double *__restrict__ G, const double *__restri
 
 __global__ void __launch_bounds__(64)
 k_couple_e(const DevData d, const double *__restrict__ G, const double *__restrict__ X, int ncolr, int64_t ldr,
-           int64_t tiles_per_wave, double *__restrict__ part) {
+           int64_t tiles_per_wave, double *__restrict__ part, const int *__restrict__ any) {
+  if (any && *any == 0) return;
   const int nk = d.nk;
   const int64_t nr = d.nr;
   const int lane = threadIdx.x, kr = lane >> 4, cl = lane & 15;
@@ -334,7 +337,8 @@ k_couple_e(const DevData d, const double *__restrict__ G, const double *__restri
 // fourth partial, then combines the quarters in a fixed order.
 __global__ void __launch_bounds__(256)
 k_couple_final(const DevData d, const double *__restrict__ part, int nblk, const double *__restrict__ Hee,
-               const double *__restrict__ X, double *__restrict__ Y, int ncolr, int64_t ldr) {
+               const double *__restrict__ X, double *__restrict__ Y, int ncolr, int64_t ldr, const int *__restrict__ any) {
+  if (any && *any == 0) return;
   __shared__ double red[4][64];
   const int nk = d.nk, nout = nk * ncolr;
   const int o = blockIdx.x * 64 + (threadIdx.x & 63), q = threadIdx.x >> 6;
@@ -468,7 +472,7 @@ inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs
 
 template <typename T, int CMT>
 void launch_apply_m(const DevData &d, const T *cells, const double *X, double *Y, int ncolr, int64_t ldr,
-                    hipStream_t s) {
+                    hipStream_t s, const int *any) {
   const unsigned ny = (unsigned)((ncolr + kCellCols - 1) / kCellCols);
   const size_t lds = cell_lds_bytes(d.g.nloc, sizeof(T));
   for (int c = 0; c < 8; ++c) {
@@ -476,16 +480,17 @@ void launch_apply_m(const DevData &d, const T *cells, const double *X, double *Y
     if (cnt == 0) continue;
     const int *list = d.colour_cells + d.colour_off[c];
     hipLaunchKernelGGL((k_cell_apply<T, CMT>), dim3((unsigned)cnt, ny), dim3(kCellWaves * 64), lds, s, d, list,
-                       d.colour_off[c], cells, X, Y, ncolr, ldr);
+                       d.colour_off[c], cells, X, Y, ncolr, ldr, any);
   }
 }
 
 template <typename T>
-void launch_apply(const DevData &d, const T *cells, const double *X, double *Y, int ncolr, int64_t ldr, hipStream_t s) {
+void launch_apply(const DevData &d, const T *cells, const double *X, double *Y, int ncolr, int64_t ldr, hipStream_t s,
+                  const int *any) {
   const int nmt = (d.g.nloc + 15) / 16;     // M tiles per cell; wave group w >> 1 takes ceil(nmt / 4)
-  if (nmt <= 8) launch_apply_m<T, 2>(d, cells, X, Y, ncolr, ldr, s);
-  else if (nmt <= 16) launch_apply_m<T, 4>(d, cells, X, Y, ncolr, ldr, s);
-  else launch_apply_m<T, 6>(d, cells, X, Y, ncolr, ldr, s);
+  if (nmt <= 8) launch_apply_m<T, 2>(d, cells, X, Y, ncolr, ldr, s, any);
+  else if (nmt <= 16) launch_apply_m<T, 4>(d, cells, X, Y, ncolr, ldr, s, any);
+  else launch_apply_m<T, 6>(d, cells, X, Y, ncolr, ldr, s, any);
 }
 
 }  // namespace
@@ -505,13 +510,13 @@ int cell_apply_init(int nloc) {
 }
 
 void cell_apply(const DevData &d, const void *cells, int dtype, const double *X, double *Y, int ncolr, int64_t ldr,
-                hipStream_t s) {
-  if (dtype == 0) launch_apply<double>(d, (const double *)cells, X, Y, ncolr, ldr, s);
-  else launch_apply<float>(d, (const float *)cells, X, Y, ncolr, ldr, s);
+                hipStream_t s, const int *any) {
+  if (dtype == 0) launch_apply<double>(d, (const double *)cells, X, Y, ncolr, ldr, s, any);
+  else launch_apply<float>(d, (const float *)cells, X, Y, ncolr, ldr, s, any);
 }
 
 void couple_apply(const DevData &d, const double *G, const double *Hee, const double *X, double *Y, int ncolr,
-                  int64_t ldr, double *scratch, hipStream_t s) {
+                  int64_t ldr, double *scratch, hipStream_t s, const int *any) {
   if (d.nk == 0) return;
   int nblk = 1;
   const int nout = d.nk * ncolr;
@@ -521,15 +526,16 @@ void couple_apply(const DevData &d, const double *G, const double *Hee, const do
     const unsigned nz = (unsigned)((d.nk + KMT * 16 - 1) / (KMT * 16));
     const int64_t tpc = (ntiles + kCoupleCWaves - 1) / kCoupleCWaves;
     hipLaunchKernelGGL(k_couple_c, dim3((unsigned)((ntiles + tpc - 1) / tpc), ny), dim3(64), 0, s, d, G, X, Y, ncolr,
-                       ldr, tpc);
+                       ldr, tpc, any);
     const int64_t tpe = (ntiles + kCouplePartials - 1) / kCouplePartials;
     nblk = (int)((ntiles + tpe - 1) / tpe);
-    hipLaunchKernelGGL(k_couple_e, dim3((unsigned)nblk, ny, nz), dim3(64), 0, s, d, G, X, ncolr, ldr, tpe, scratch);
+    hipLaunchKernelGGL(k_couple_e, dim3((unsigned)nblk, ny, nz), dim3(64), 0, s, d, G, X, ncolr, ldr, tpe, scratch,
+                       any);
   } else {
     k::zero(scratch, (int64_t)nout, s);
   }
   hipLaunchKernelGGL(k_couple_final, dim3(nblocks((int64_t)nout, 64)), dim3(256), 0, s, d, scratch, nblk, Hee, X, Y,
-                     ncolr, ldr);
+                     ncolr, ldr, any);
 }
 
 void tridiag_exp(const double *alpha, const double *beta, int j, int ncol, int kmax, double tau, const double *beta0,

@@ -96,12 +96,13 @@ k_lz_dots(Basis B, int l0, int nl, const double2 *__restrict__ w, int64_t nrows,
 
 // w <- gw[c] w - sum_{l < nl} coef[l0 + l][c] slot_{l0+l}  (in place, mask[c] != 0),
 // two rows per step; with_norm writes the partial ||w||^2 of the result to
-// part[blk][c].  gw == nullptr means 1.
+// part[blk][c].  gw == nullptr means 1.  zero_masked clears the columns with
+// mask[c] == 0 instead (stopped columns: their later slots stay zero).
 template <int NL>
 __global__ void __launch_bounds__(kLzThreads)
 k_lz_update(Basis B, int l0, int nl, const double2 *__restrict__ coef, const double *__restrict__ gw,
             double2 *__restrict__ w, int64_t nrows, int ncol, const int *__restrict__ mask,
-            const int *__restrict__ any, int with_norm, double2 *__restrict__ part) {
+            const int *__restrict__ any, int with_norm, int zero_masked, double2 *__restrict__ part) {
   if (any && *any == 0) return;
   extern __shared__ double2 lz_sm[];
   double2 *cs = lz_sm;                       // nl * ncol
@@ -112,6 +113,10 @@ k_lz_update(Basis B, int l0, int nl, const double2 *__restrict__ coef, const dou
   const int c = threadIdx.x % ncol, r0 = threadIdx.x / ncol;
   const bool on = r0 < R && mask[c] != 0;
   double nrm = 0.0;
+  if (r0 < R && !on && zero_masked) {
+    for (int64_t r = (int64_t)blockIdx.x * R + r0; r < nrows; r += (int64_t)gridDim.x * R)
+      w[r * ncol + c] = make_double2(0.0, 0.0);
+  }
   if (on) {
     const double g = gw ? gw[c] : 1.0;
     const double2 *q[NL];
@@ -167,7 +172,12 @@ k_lz_update(Basis B, int l0, int nl, const double2 *__restrict__ coef, const dou
 template <int NL>
 __global__ void __launch_bounds__(kLzThreads)
 k_lz_combine(Basis B, int l0, int nl, const double2 *__restrict__ coef, double2 *__restrict__ out, int64_t nrows,
-             int ncol, int acc_out) {
+             int ncol, int acc_out, const int *__restrict__ nq_dev) {
+  if (nq_dev) {
+    const int lim = *nq_dev - l0;
+    if (lim <= 0 && acc_out) return;
+    nl = lim < nl ? (lim > 0 ? lim : 0) : nl;
+  }
   extern __shared__ double2 lz_sm[];
   double2 *cs = lz_sm;
   for (int t = threadIdx.x; t < nl * ncol; t += blockDim.x) cs[t] = coef[(int64_t)l0 * ncol + t];
@@ -187,12 +197,14 @@ k_lz_combine(Basis B, int l0, int nl, const double2 *__restrict__ coef, double2 
 #pragma unroll
     for (int l = 0; l < NL; ++l)
       if (l < nl) {
-        const double2 qa = q[l][oa], qb = q[l][ob];
         const double2 h = cs[l * ncol + c];
-        va.x += h.x * qa.x - h.y * qa.y;
-        va.y += h.x * qa.y + h.y * qa.x;
-        vb.x += h.x * qb.x - h.y * qb.y;
-        vb.y += h.x * qb.y + h.y * qb.x;
+        if (h.x != 0.0 || h.y != 0.0) {   // slots past a column's k hold unused data
+          const double2 qa = q[l][oa], qb = q[l][ob];
+          va.x += h.x * qa.x - h.y * qa.y;
+          va.y += h.x * qa.y + h.y * qa.x;
+          vb.x += h.x * qb.x - h.y * qb.y;
+          vb.y += h.x * qb.y + h.y * qb.x;
+        }
       }
     out[oa] = va;
     out[ob] = vb;
@@ -203,10 +215,12 @@ k_lz_combine(Basis B, int l0, int nl, const double2 *__restrict__ coef, double2 
 #pragma unroll
     for (int l = 0; l < NL; ++l)
       if (l < nl) {
-        const double2 qa = q[l][oa];
         const double2 h = cs[l * ncol + c];
-        va.x += h.x * qa.x - h.y * qa.y;
-        va.y += h.x * qa.y + h.y * qa.x;
+        if (h.x != 0.0 || h.y != 0.0) {
+          const double2 qa = q[l][oa];
+          va.x += h.x * qa.x - h.y * qa.y;
+          va.y += h.x * qa.y + h.y * qa.x;
+        }
       }
     out[oa] = va;
   }
@@ -316,6 +330,25 @@ __global__ void k_lz_comb_coef(const double *__restrict__ u, const double *__res
   coef[t] = v;
 }
 
+__global__ void k_lz_kmax(const int *__restrict__ kused, int ncol, int *__restrict__ kmaxu) {
+  __shared__ int m;
+  if (threadIdx.x == 0) m = 0;
+  __syncthreads();
+  for (int c = threadIdx.x; c < ncol; c += blockDim.x) atomicMax(&m, kused[c]);
+  __syncthreads();
+  if (threadIdx.x == 0) *kmaxu = m;
+}
+
+__global__ void k_lz_any(const int *__restrict__ active, int ncol, int *__restrict__ any) {
+  __shared__ int flag;
+  if (threadIdx.x == 0) flag = 0;
+  __syncthreads();
+  for (int c = threadIdx.x; c < ncol; c += blockDim.x)
+    if (active[c]) atomicOr(&flag, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) *any = flag;
+}
+
 inline int lz_grid(int64_t nrows, int ncol, int threads) {
   const int R = threads / ncol;
   const int64_t need = (nrows + R - 1) / R;
@@ -353,7 +386,7 @@ int lz_dots(const double *q0, const double *qb, int64_t bs, int nq, const double
 }
 
 int lz_update(const double *q0, const double *qb, int64_t bs, int nq, const double *coef, const double *gw, double *w,
-              int64_t nrows, int ncol, const int *mask, const int *any, double *part, hipStream_t s) {
+              int64_t nrows, int ncol, const int *mask, const int *any, double *part, hipStream_t s, int zero_masked) {
   const Basis B{(const double2 *)q0, (const double2 *)qb, bs / 2};
   const int nb = lz_grid(nrows, ncol, kLzUpdThreads);
   const size_t lds = ((size_t)kLzChunk * ncol + kLzUpdThreads) * sizeof(double2);
@@ -363,19 +396,19 @@ int lz_update(const double *q0, const double *qb, int64_t bs, int nq, const doub
     const double *g = l0 == 0 ? gw : nullptr;
     if (nl <= 4)
       hipLaunchKernelGGL(k_lz_update<4>, dim3(nb), dim3(kLzUpdThreads), lds, s, B, l0, nl, (const double2 *)coef, g,
-                         (double2 *)w, nrows, ncol, mask, any, wn, (double2 *)part);
+                         (double2 *)w, nrows, ncol, mask, any, wn, l0 == 0 ? zero_masked : 0, (double2 *)part);
     else if (nl <= 8)
       hipLaunchKernelGGL(k_lz_update<8>, dim3(nb), dim3(kLzUpdThreads), lds, s, B, l0, nl, (const double2 *)coef, g,
-                         (double2 *)w, nrows, ncol, mask, any, wn, (double2 *)part);
+                         (double2 *)w, nrows, ncol, mask, any, wn, l0 == 0 ? zero_masked : 0, (double2 *)part);
     else
       hipLaunchKernelGGL(k_lz_update<kLzChunk>, dim3(nb), dim3(kLzUpdThreads), lds, s, B, l0, nl, (const double2 *)coef,
-                         g, (double2 *)w, nrows, ncol, mask, any, wn, (double2 *)part);
+                         g, (double2 *)w, nrows, ncol, mask, any, wn, l0 == 0 ? zero_masked : 0, (double2 *)part);
   }
   return nb;
 }
 
 void lz_combine(const double *q0, const double *qb, int64_t bs, int nq, const double *coef, double *out,
-                int64_t nrows, int ncol, hipStream_t s) {
+                int64_t nrows, int ncol, hipStream_t s, const int *nq_dev) {
   const Basis B{(const double2 *)q0, (const double2 *)qb, bs / 2};
   const int nb = lz_grid(nrows, ncol, kLzUpdThreads);
   const size_t lds = (size_t)kLzChunk * ncol * sizeof(double2);
@@ -388,13 +421,13 @@ void lz_combine(const double *q0, const double *qb, int64_t bs, int nq, const do
     const int acc = l0 > 0 ? 1 : 0;
     if (nl <= 4)
       hipLaunchKernelGGL(k_lz_combine<4>, dim3(nb), dim3(kLzUpdThreads), lds, s, B, l0, nl, (const double2 *)coef,
-                         (double2 *)out, nrows, ncol, acc);
+                         (double2 *)out, nrows, ncol, acc, nq_dev);
     else if (nl <= 8)
       hipLaunchKernelGGL(k_lz_combine<8>, dim3(nb), dim3(kLzUpdThreads), lds, s, B, l0, nl, (const double2 *)coef,
-                         (double2 *)out, nrows, ncol, acc);
+                         (double2 *)out, nrows, ncol, acc, nq_dev);
     else
       hipLaunchKernelGGL(k_lz_combine<kLzChunk>, dim3(nb), dim3(kLzUpdThreads), lds, s, B, l0, nl,
-                         (const double2 *)coef, (double2 *)out, nrows, ncol, acc);
+                         (const double2 *)coef, (double2 *)out, nrows, ncol, acc, nq_dev);
   }
 }
 
@@ -424,6 +457,14 @@ void lz_beta(const double *nrm1, const double *nrm2, const int *need, const int 
              int ncol, double *beta_j, double *sig, hipStream_t s) {
   hipLaunchKernelGGL(k_lz_beta, dim3((ncol + 63) / 64), dim3(64), 0, s, (const double2 *)nrm1, (const double2 *)nrm2,
                      need, active, msc, j, ncol, beta_j, sig);
+}
+
+void lz_kmax(const int *kused, int ncol, int *kmaxu, hipStream_t s) {
+  hipLaunchKernelGGL(k_lz_kmax, dim3(1), dim3(128), 0, s, kused, ncol, kmaxu);
+}
+
+void lz_any(const int *active, int ncol, int *any, hipStream_t s) {
+  hipLaunchKernelGGL(k_lz_any, dim3(1), dim3(128), 0, s, active, ncol, any);
 }
 
 void lz_comb_coef(const double *u, const double *sig, const double *beta0, const int *kused, int kmax, int nl,

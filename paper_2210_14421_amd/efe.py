@@ -78,6 +78,14 @@ _lanczos = _sig("lanczos_expm", C.c_int32, [C.c_void_p, C.c_int32, C.c_double, C
                                             _ip, _ip, _dp])
 _magnus = _sig("magnus_step", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_double,
                                           C.POINTER(EfeField), _ip, C.POINTER(EfeStepStats)])
+_magnus_graph = _sig("magnus_step_graph", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_double,
+                                                      C.POINTER(EfeField), C.POINTER(EfeStepStats)])
+_batch_create = _sig("efe_batch_create", C.c_int32, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p)])
+_batch_free = _sig("efe_batch_free", C.c_int32, [C.c_void_p])
+_batch_error = _sig("efe_batch_error", C.c_char_p, [C.c_void_p])
+_batch_step = _sig("efe_batch_step", C.c_int32, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.c_double,
+                                                 C.c_double, C.POINTER(C.POINTER(EfeField)),
+                                                 C.POINTER(EfeStepStats)])
 _density = _sig("density", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p])
 _hartree = _sig("efe_hartree", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, _ip])
 _dipole = _sig("dipole", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, _dp])
@@ -88,7 +96,8 @@ _last_error = _sig("efe_last_error", C.c_char_p, [C.c_void_p])
 EXPORTED = ["efe_plan_create", "efe_plan_free", "efe_plan_sizes", "efe_plan_get", "efe_plan_error",
             "efe_setup", "efe_free", "efe_dims", "efe_set_options", "efe_initial_state",
             "efe_set_hamiltonian", "efe_apply_H", "lanczos_expm", "magnus_step", "density",
-            "efe_hartree", "dipole", "efe_enable_timing", "efe_get_timing", "efe_last_error"]
+            "efe_hartree", "dipole", "efe_enable_timing", "efe_get_timing", "efe_last_error",
+            "magnus_step_graph", "efe_batch_create", "efe_batch_free", "efe_batch_error", "efe_batch_step"]
 
 
 class EfeError(RuntimeError):
@@ -180,6 +189,12 @@ def make_field(direction=2, A=(), w=(), phi=(), t0=0.0, s=1.0):
     return f, (A, w, phi)
 
 
+def _stats_dict(st, n):
+    return dict(k_pred=np.array(st.k_pred[:n]), k_corr=np.array(st.k_corr[:n]),
+                err_pred_max=st.err_pred_max, err_corr_max=st.err_corr_max,
+                cg_iters=tuple(st.cg_iters), mu=np.array(st.mu[:3]))
+
+
 class Context:
     """A GPU context: static data uploaded, workspace allocated."""
 
@@ -263,16 +278,21 @@ class Context:
                              er.ctypes.data_as(_dp)))
         return ku, er
 
-    def magnus_step(self, Psi, t, dt, field=None, k_force=None):
+    def magnus_step(self, Psi, t, dt, field=None, k_force=None, graph=False):
+        """One Magnus-2 step in place.  graph=True replays a captured hipGraph of
+        the device-driven step (no k_force)."""
         st = EfeStepStats()
-        kf = None if k_force is None else _arr(k_force, np.int32).reshape(-1)
         f = C.byref(field) if field is not None else None
-        self._check(_magnus(self._c, self._ptr(Psi, self.torch.complex128, self.n_rows), Psi.shape[1], float(t),
-                            float(dt), f, None if kf is None else kf.ctypes.data_as(_ip), C.byref(st)))
-        n = self.norb
-        return dict(k_pred=np.array(st.k_pred[:n]), k_corr=np.array(st.k_corr[:n]),
-                    err_pred_max=st.err_pred_max, err_corr_max=st.err_corr_max,
-                    cg_iters=tuple(st.cg_iters), mu=np.array(st.mu[:3]))
+        ptr = self._ptr(Psi, self.torch.complex128, self.n_rows)
+        if graph:
+            if k_force is not None:
+                raise ValueError("k_force is not available with graph=True")
+            self._check(_magnus_graph(self._c, ptr, Psi.shape[1], float(t), float(dt), f, C.byref(st)))
+        else:
+            kf = None if k_force is None else _arr(k_force, np.int32).reshape(-1)
+            self._check(_magnus(self._c, ptr, Psi.shape[1], float(t), float(dt), f,
+                                None if kf is None else kf.ctypes.data_as(_ip), C.byref(st)))
+        return _stats_dict(st, self.norb)
 
     def density(self, Psi, rho=None):
         torch = self.torch
@@ -309,6 +329,48 @@ class Context:
         if getattr(self, "_c", None):
             _free(self._c)
             self._c = None
+
+    def __del__(self):
+        self.close()
+
+
+class Batch:
+    """Independent propagations stepped together: one captured hipGraph per
+    step with the members' device-driven steps as concurrent branches.  Holds
+    references to the contexts; close() before closing them."""
+
+    def __init__(self, contexts):
+        self.members = list(contexts)
+        arr = (C.c_void_p * len(self.members))(*[c._c for c in self.members])
+        self._b = C.c_void_p()
+        st = _batch_create(arr, len(self.members), C.byref(self._b))
+        if st != EFE_OK:
+            msg = _batch_error(self._b).decode() if self._b else ""
+            _batch_free(self._b)
+            self._b = None
+            raise EfeError(st, msg)
+
+    def step(self, Psis, t, dt, fields=None):
+        """One Magnus-2 step of every member in place; returns the per-member stats."""
+        n = len(self.members)
+        if len(Psis) != n:
+            raise ValueError(f"{n} orbital blocks expected")
+        ptrs = (C.c_void_p * n)(*[m._ptr(P, m.torch.complex128, m.n_rows).value for m, P in zip(self.members, Psis)])
+        lds = (C.c_int64 * n)(*[P.shape[1] for P in Psis])
+        fptr = None
+        if fields is not None:
+            fp = (C.POINTER(EfeField) * n)(*[C.pointer(f) if f is not None else None for f in fields])
+            fptr = fp
+        stats = (EfeStepStats * n)()
+        st = _batch_step(self._b, ptrs, lds, float(t), float(dt), fptr, stats)
+        if st != EFE_OK:
+            raise EfeError(st, _batch_error(self._b).decode())
+        return [_stats_dict(stats[i], m.norb) for i, m in enumerate(self.members)]
+
+    def close(self):
+        if getattr(self, "_b", None):
+            _batch_free(self._b)
+            self._b = None
 
     def __del__(self):
         self.close()
