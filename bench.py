@@ -171,6 +171,77 @@ def cpu_baseline(spec, hx_per_step):
                       f"coupling, vector work, density and Poisson excluded"}
 
 
+def batch_members():
+    """The batched workload: Na2, Na4 and Na6 (seeds 2, 4, 6) each kicked along
+    x, y, z with 1e-4 and 1e-3, plus Na8 kicked along x, y, z with 1e-3: 21
+    independent propagations, FP32 products, FP64 Krylov."""
+    from workloads import na_cluster
+    out = []
+    for natom, seed in ((2, 2), (4, 4), (6, 6)):
+        for kick in (1e-4, 1e-3):
+            for d in "xyz":
+                out.append((natom, seed, d, kick))
+    for d in "xyz":
+        out.append((8, 0, d, 1e-3))
+    return out
+
+
+def run_batch(steps, warmup, kmax, dtype="f32"):
+    import numpy as np
+    import torch
+    from workloads import na_cluster
+    from paper_2210_14421_amd.efe import Context, Batch
+    t0 = time.time()
+    specs = {}
+    ctxs, Psis = [], []
+    for natom, seed, d, kick in batch_members():
+        spec = specs.setdefault((natom, seed), na_cluster(natom, seed=seed))
+        c = Context(spec, dtype=dtype, kmax=kmax)
+        P = c.initial_state()
+        c.lanczos_expm(P, -kick, op=d)
+        c.set_hamiltonian(P, 0.0)
+        ctxs.append(c)
+        Psis.append(P)
+    torch.cuda.synchronize()
+    print(f"[bench] batch of {len(ctxs)}: set-up {time.time() - t0:.1f} s", file=sys.stderr, flush=True)
+    batch = Batch(ctxs)
+    dt = specs[(8, 0)].dt
+    t = 0.0
+    for _ in range(max(1, warmup)):      # the first step captures the graph
+        batch.step(Psis, t, dt)
+        t += dt
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ks = []
+    for i in range(steps):
+        st = batch.step(Psis, t, dt)
+        t += dt
+        ks.append([float(np.mean(x["k_corr"])) for x in st])
+        print(f"[bench] batch step {i}: {1e3 * (time.perf_counter() - t1) / (i + 1):.1f} ms/step", file=sys.stderr,
+              flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t1
+    batch.close()
+    # the same members stepped one after another by the host-driven magnus_step
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for c, P in zip(ctxs, Psis):
+        c.magnus_step(P, t, dt)
+    torch.cuda.synchronize()
+    seq_ms = 1e3 * (time.perf_counter() - t2)
+    for c in ctxs:
+        c.close()
+    n = len(ctxs)
+    return {"metric": "batched Magnus steps/s (21 independent Na2/Na4/Na6/Na8 propagations, one hipGraph per step)",
+            "value": n * steps / wall, "unit": "propagation-steps/s", "n_gpus": 1, "steps": steps,
+            "warmup": warmup, "ms_per_step": 1e3 * wall / steps, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32 products, f64 Krylov", "data": "synthetic",
+            "config": {"workload": "Na2/Na4/Na6 x {x,y,z} x {1e-4,1e-3} + Na8 x {x,y,z} x 1e-3, dt 0.02, tol 1e-10",
+                       "members": n, "kmax": kmax},
+            "sequential_ms_per_step": seq_ms, "speedup_vs_sequential": seq_ms / (1e3 * wall / steps),
+            "krylov_k_mean_last": ks[-1] if ks else None}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,7 +250,7 @@ def main():
     ap.add_argument("--kmax", type=int, default=40)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="na8", choices=["na8", "tiny", "na2"])
+    ap.add_argument("--workload", default="na8", choices=["na8", "tiny", "na2", "batch"])
     ap.add_argument("--mode", default="step", choices=["step", "apply"])
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
     args = ap.parse_args()
@@ -189,8 +260,11 @@ def main():
         sys.exit(2)
     import torch
     from workloads import na8, tiny, na_cluster
-    spec = {"na8": na8, "tiny": tiny, "na2": lambda: na_cluster(2, seed=2)}[args.workload]()
     torch.cuda.set_device(0)
+    if args.workload == "batch":
+        print(json.dumps(run_batch(args.steps, args.warmup, min(args.kmax, 20))))
+        return
+    spec = {"na8": na8, "tiny": tiny, "na2": lambda: na_cluster(2, seed=2)}[args.workload]()
     if args.mode == "apply":
         run_apply_mode(spec, args.dtype, max(1, args.steps))
         return
