@@ -221,6 +221,30 @@ const char *efe_batch_error(const efe_batch *batch);
 efe_status efe_batch_step(efe_batch *batch, void *const *Psi, const int64_t *ld, double t, double dt,
                           const efe_field *const *fields, efe_step_stats *stats);
 
+/* Reverse mode of one magnus_step from (Psi = X_n, t, dt, field): on entry
+ * Psibar holds Xbar_{n+1} = dL/dRe X_{n+1} + i dL/dIm X_{n+1} (device, n_rows x
+ * norb, leading dimension ldb); on return it holds Xbar_n, including the loss
+ * term of the dipole at t (mubar = dL/dmu(t), host, 3 doubles).  dLdE (host,
+ * 2 doubles) receives dL/dE(t) and dL/dE(t + dt/2), the sensitivities to the
+ * field values of eq. (VField) that the step uses.  The forward step is
+ * recomputed inside (the same adaptive Krylov dimensions); the exponentials'
+ * adjoints are exp(+i dt H) on Krylov spaces of the adjoint blocks, and their
+ * Frechet derivatives, through the potential, are cross densities of the two
+ * Krylov spaces integrated over s by 10-point Gauss-Legendre; the Hartree and
+ * xc responses use the same Poisson solve (homogeneous) and f_xc.  Leaves the
+ * cell blocks holding a potential-only operator: call efe_set_hamiltonian
+ * before the next forward step.  Workspace (about 15 orbital blocks) is
+ * allocated on the first call. */
+efe_status magnus_adjoint(efe_ctx *ctx, const void *Psi, int64_t ld, double t, double dt,
+                          const efe_field *field, const double mubar[3], void *Psibar, int64_t ldb,
+                          double dLdE[2]);
+
+/* Adjoint of the dipole of Psi: Psibar = 2 f_a Vbar[mubar . x] Psi_a (the
+ * terminal condition of a reverse sweep; mubar host).  Leaves the cell blocks
+ * as magnus_adjoint does. */
+efe_status dipole_adjoint(efe_ctx *ctx, const void *Psi, int64_t ld, const double mubar[3], void *Psibar,
+                          int64_t ldb);
+
 /* rho(q) = sum_a f_a |psi_a(q)|^2 at every quadrature point (device output,
  * n_quad doubles), psi = M^-1/2 Psi evaluated through the EFE basis. */
 efe_status density(efe_ctx *ctx, const void *Psi, int64_t ld, double *rho_q);

@@ -78,6 +78,11 @@ struct efe_ctx {
   int64_t gkey_ld = 0;
   double gkey_dt = 0.0;
   int gkey_fkind = -1, gkey_fdir = -1;
+  // adjoint step workspace (allocated on first use)
+  double *adj_XB = nullptr, *adj_XA = nullptr, *adj_W1 = nullptr, *adj_Z = nullptr, *adj_B = nullptr;
+  double *adj_rho_n = nullptr, *adj_rho_m = nullptr, *adj_u = nullptr, *adj_gm = nullptr, *adj_gn = nullptr;
+  double *adj_phib = nullptr, *adj_psiE = nullptr, *adj_coef = nullptr, *adj_f2 = nullptr, *adj_zero = nullptr;
+  double adj_dt = 0.0;
   int *one_mask = nullptr;   // all-ones column mask
   // state
   int cells_mode = -1;      // -1 nothing built, 0 Hamiltonian, 1..3 position operator
@@ -406,14 +411,14 @@ efe_status reduce_to(efe_ctx *ctx, double *part, int nblk, int nval, double *dev
 }
 
 // Hartree: (1/4pi) K phi = d with phi = g on the boundary; PCG with the FDM inverse.
-efe_status hartree(efe_ctx *ctx, const double *rho, double *phi, int *iters) {
+efe_status hartree(efe_ctx *ctx, const double *rho, double *phi, int *iters, bool homogeneous = false) {
   const DevData &d = ctx->d;
   hipStream_t s = ctx->stream;
   const int64_t N = d.g.n_nodes;
   double *x = ctx->cg[0], *r = ctx->cg[1], *z = ctx->cg[2], *p = ctx->cg[3], *q = ctx->cg[4], *t1 = ctx->cg[5],
          *t2 = ctx->cg[6];
   tstart(ctx, 5);
-  efe::k::poisson_rhs(d, rho, ctx->dvec, ctx->rhs, s);
+  efe::k::poisson_rhs(d, rho, ctx->dvec, ctx->rhs, s, homogeneous ? 0 : 1);
   efe::k::fdm_apply(d, ctx->rhs, x, t1, t2, s);
   efe::k::stiffness_apply(d, x, q, t1, t2, s);
   efe::k::axpby(ctx->rhs, q, 1.0, -1.0, r, N, s);
@@ -449,7 +454,7 @@ efe_status hartree(efe_ctx *ctx, const double *rho, double *phi, int *iters) {
     ++it;
   }
   HIP_TRY(hipMemcpyAsync(phi, x, N * sizeof(double), hipMemcpyDeviceToDevice, s));
-  efe::k::set_boundary(d, phi, s);
+  if (!homogeneous) efe::k::set_boundary(d, phi, s);
   tstop(ctx, 5);
   if (iters) *iters = it;
   return check_launch(ctx, "hartree");
@@ -483,7 +488,7 @@ efe_status rebuild(efe_ctx *ctx, int mode, const double *rho, double t, const ef
     EFE_TRY(hartree(ctx, rho, ctx->phi, cg_iters));
     efield = field_value(field, t);
     if (field && field->kind) fdir = field->direction;
-  }
+  }   // mode 4: rho carries the potential g(q) of a potential-only operator
   tstart(ctx, 6);
   efe::k::set_scalar(ctx->stepp + 2, efield, s);
   efe::k::rebuild_cells(d, mode, rho, ctx->phi, ctx->stepp + 2, fdir, ctx->plan.xc, ctx->cells, ctx->dtype, ctx->vq, s);
@@ -848,6 +853,142 @@ bool graph_matches(const efe_ctx *ctx, void *Psi, int64_t ld, double dt, const e
   const int fdir = (field && field->kind) ? field->direction : 2;
   return ctx->gexec && ctx->gkey_psi == Psi && ctx->gkey_ld == ld && ctx->gkey_dt == dt &&
          ctx->gkey_fkind == (field ? field->kind : 0) && ctx->gkey_fdir == fdir;
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint of one Magnus-2 step (reverse mode).  Notation: X_n the orbitals,
+// rho_n = rho(X_n), H_n = Hbar[rho_n, t_n], P = exp(-i dt H_n) X_n,
+// rho_m = (rho_n + rho(P))/2, H_m = Hbar[rho_m, t_n + dt/2],
+// X_{n+1} = exp(-i dt H_m) X_n.  With L real and Xbar = dL/dRe X + i dL/dIm X:
+//  * exp(-i dt H) X:  Xbar_in += exp(+i dt H) Xbar_out, and the potential
+//    sensitivity vbar(q) = W_q dt int_0^1 sum_a Im[conj(a_s(q)) b_s(q)] ds with
+//    b_s = exp(-i s dt H) X, a_s = exp(+i (1-s) dt H) Xbar_out evaluated at the
+//    points (the Frechet derivative of the exponential, Gauss-Legendre in s on
+//    the Krylov spaces of X and Xbar_out);
+//  * v = v_N + v_H[rho] + v_xc(rho) - E(t) x_d:  rhobar(q) = W_q g(q) with
+//    g = B (4 pi K^-1 B^T vbar) + f_xc vbar / W  and dL/dE(t) = -sum_q vbar x_d;
+//  * rho(X) = sum_a f_a |Phi X_a|^2:  Xbar += 2 f_a Vbar[g] X_a (the
+//    potential-only operator of g, the same assembly as Hbar without kinetic
+//    and static terms).
+// The loss term at t_n enters as rhobar_n += W (mubar . x).
+// ---------------------------------------------------------------------------
+constexpr int kAdjNodes = 10;   // exact for frequencies |dt (l_i - l_j)| <~ 9
+
+void gauss_legendre01(int m, double *x, double *w) {
+  const double pi = 3.14159265358979323846;
+  for (int i = 0; i < m; ++i) {
+    double z = std::cos(pi * (i + 0.75) / (m + 0.5)), dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= m; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = m * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= m; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = m * (z * p1 - p0) / (z * z - 1.0);
+    x[i] = 0.5 * (1.0 - z);
+    w[i] = 1.0 / ((1.0 - z * z) * dp * dp);   // (2 / ((1-z^2) P'^2)) / 2 for [0, 1]
+  }
+}
+
+efe_status ensure_adjoint_buffers(efe_ctx *ctx) {
+  if (ctx->adj_XB) return EFE_OK;
+  const efe::Plan &pl = ctx->plan;
+  EFE_TRY(dalloc(ctx, &ctx->adj_XB, ctx->blk));
+  EFE_TRY(dalloc(ctx, &ctx->adj_XA, ctx->blk));
+  EFE_TRY(dalloc(ctx, &ctx->adj_W1, ctx->blk));
+  EFE_TRY(dalloc(ctx, &ctx->adj_Z, 2 * ctx->blk));
+  EFE_TRY(dalloc(ctx, &ctx->adj_B, (int64_t)kAdjNodes * ctx->blk));
+  EFE_TRY(dalloc(ctx, &ctx->adj_rho_n, pl.n_quad));
+  EFE_TRY(dalloc(ctx, &ctx->adj_rho_m, pl.n_quad));
+  EFE_TRY(dalloc(ctx, &ctx->adj_u, pl.n_quad));
+  EFE_TRY(dalloc(ctx, &ctx->adj_gm, pl.n_quad));
+  EFE_TRY(dalloc(ctx, &ctx->adj_gn, pl.n_quad));
+  EFE_TRY(dalloc(ctx, &ctx->adj_phib, pl.n_nodes));
+  EFE_TRY(dalloc(ctx, &ctx->adj_zero, std::max<int64_t>(pl.n_nodes, pl.n_quad)));
+  EFE_TRY(dalloc(ctx, &ctx->adj_psiE, (int64_t)std::max(1, ctx->d.ne) * 2 * ctx->ncolr));
+  EFE_TRY(dalloc(ctx, &ctx->adj_coef, (int64_t)kAdjNodes * ctx->kmax * ctx->ncolr));
+  std::vector<double> f2(std::max(1, pl.norb));
+  for (int a = 0; a < pl.norb; ++a) f2[a] = 2.0 * pl.occ[a];
+  EFE_TRY(upload(ctx, &ctx->adj_f2, f2));
+  efe::k::zero(ctx->adj_zero, std::max<int64_t>(pl.n_nodes, pl.n_quad), ctx->stream);
+  return EFE_OK;
+}
+
+// vbar-related point function: u(q) = int_0^1 sum_a Im[conj(a_s) b_s] ds for the
+// Lanczos just run from Xbar (slot 0 = Xbar, basis in ctx->Q), the b_s blocks
+// in adj_B, nodes s_g, weights w_g.
+efe_status adj_cross(efe_ctx *ctx, const double *Xbar, int kx, const double *sg, const double *wg) {
+  hipStream_t s = ctx->stream;
+  const int no = ctx->norb;
+  const int64_t nr = ctx->n_rows, bs = nr * 2 * no;
+  double taus[kAdjNodes];
+  for (int g = 0; g < kAdjNodes; ++g) taus[g] = -(1.0 - sg[g]) * ctx->adj_dt;
+  efe::k::tridiag_coef(ctx->alpha, ctx->beta, ctx->kused, no, ctx->kmax, taus, kAdjNodes, ctx->beta0, ctx->sig,
+                       ctx->adj_coef, s);
+  efe::k::zero(ctx->adj_u, ctx->plan.n_quad, s);
+  for (int g = 0; g < kAdjNodes; ++g) {
+    efe::k::lz_combine(Xbar, ctx->Q, bs, kx, ctx->adj_coef + (int64_t)g * ctx->kmax * 2 * no, ctx->adj_W1, nr, no, s);
+    efe::k::interleave(ctx->adj_W1, ctx->adj_B + (int64_t)g * ctx->blk, ctx->adj_Z, nr, no, s);
+    efe::k::psiE(ctx->d, ctx->adj_Z, 4 * no, 4 * no, ctx->adj_psiE, s);
+    efe::k::cross_density(ctx->d, ctx->adj_Z, no, ctx->adj_psiE, wg[g], ctx->adj_u, s);
+  }
+  return check_launch(ctx, "adjoint cross density");
+}
+
+// b_g = exp(-i s_g dt H) X0 from the Lanczos just run from X0
+void adj_fwd_nodes(efe_ctx *ctx, int kx, const double *sg) {
+  hipStream_t s = ctx->stream;
+  const int no = ctx->norb;
+  const int64_t nr = ctx->n_rows, bs = nr * 2 * no;
+  double taus[kAdjNodes];
+  for (int g = 0; g < kAdjNodes; ++g) taus[g] = sg[g] * ctx->adj_dt;
+  efe::k::tridiag_coef(ctx->alpha, ctx->beta, ctx->kused, no, ctx->kmax, taus, kAdjNodes, ctx->beta0, ctx->sig,
+                       ctx->adj_coef, s);
+  for (int g = 0; g < kAdjNodes; ++g)
+    efe::k::lz_combine(ctx->X0, ctx->Q, bs, kx, ctx->adj_coef + (int64_t)g * ctx->kmax * 2 * no,
+                       ctx->adj_B + (int64_t)g * ctx->blk, nr, no, s);
+}
+
+// g(q) and dL/dE from u: phibar = 4 pi K^-1 B^T (dt W u); g = B phibar + dt f_xc(rho) u + mubar.x + a gin
+efe_status adj_potential_of(efe_ctx *ctx, const double *rho, const double mubar[3], double a, const double *gin,
+                            double *g, int fdir, double *dLdE) {
+  hipStream_t s = ctx->stream;
+  const int64_t nq = ctx->plan.n_quad;
+  efe::k::axpby(ctx->adj_u, ctx->adj_u, ctx->adj_dt, 0.0, ctx->rho_tmp, nq, s);
+  int it = 0;
+  EFE_TRY(hartree(ctx, ctx->rho_tmp, ctx->adj_phib, &it, true));
+  efe::k::adj_potential(ctx->d, ctx->adj_phib, rho, ctx->adj_u, ctx->adj_dt, ctx->plan.xc, mubar, a, gin, g, s);
+  double mu[3];
+  EFE_TRY(dipole_of(ctx, ctx->adj_u, mu));    // sum_q W x_d u
+  *dLdE = -ctx->adj_dt * mu[fdir];
+  return check_launch(ctx, "adjoint potential");
+}
+
+// Y_acc += 2 f_a Vbar[g] X   (overwrites the cell blocks)
+efe_status adj_density_term(efe_ctx *ctx, const double *g, const double *X, double *Yacc) {
+  int it = 0;
+  EFE_TRY(rebuild(ctx, 4, g, 0.0, nullptr, &it));
+  EFE_TRY(apply_op(ctx, X, ctx->adj_W1, ctx->ncolr, ctx->ncolr));
+  efe::k::axpy_cols(Yacc, ctx->adj_W1, ctx->adj_f2, 1.0, ctx->n_rows, ctx->norb, ctx->stream);
+  return check_launch(ctx, "adjoint density term");
+}
+
+int max_k(const std::vector<int32_t> &k) {
+  int m = 0;
+  for (int v : k) m = std::max(m, v);
+  return m;
 }
 
 efe_status check_ctx(efe_ctx *ctx) {
@@ -1327,6 +1468,74 @@ efe_status efe_batch_step(efe_batch *b, void *const *Psi, const int64_t *ld, dou
     }
   }
   return first;
+}
+
+efe_status magnus_adjoint(efe_ctx *ctx, const void *Psi, int64_t ld, double t, double dt, const efe_field *field,
+                          const double mubar[3], void *Psibar, int64_t ldb, double dLdE[2]) {
+  if (!ctx || !Psi || !Psibar || !mubar || !dLdE || ld < ctx->norb || ldb < ctx->norb || !std::isfinite(t) ||
+      !std::isfinite(dt))
+    return EFE_ERR_ARG;
+  EFE_TRY(validate_field(ctx, field));
+  EFE_TRY(ensure_adjoint_buffers(ctx));
+  hipStream_t s = ctx->stream;
+  const int no = ctx->norb;
+  const int64_t nq = ctx->plan.n_quad;
+  const int fdir = (field && field->kind) ? field->direction : 2;
+  double sg[kAdjNodes], wg[kAdjNodes];
+  gauss_legendre01(kAdjNodes, sg, wg);
+  ctx->adj_dt = dt;
+  ctx->ham_valid = false;
+  std::vector<int32_t> k1(no), k2(no);
+  int it = 0;
+  const double zero3[3] = {0.0, 0.0, 0.0};
+  EFE_TRY(pack_in(ctx, Psi, ld, no, ctx->X0));
+  EFE_TRY(pack_in(ctx, Psibar, ldb, no, ctx->adj_XB));
+  // forward recomputation: rho_n, H_n, P, rho_m, H_m
+  EFE_TRY(density_packed(ctx, ctx->X0, ctx->adj_rho_n));
+  EFE_TRY(rebuild(ctx, 0, ctx->adj_rho_n, t, field, &it));
+  EFE_TRY(run_lanczos(ctx, dt, ctx->X0, ctx->X1, no, nullptr, k1.data(), nullptr));
+  EFE_TRY(density_packed(ctx, ctx->X1, ctx->rho_tmp));
+  efe::k::axpby(ctx->adj_rho_n, ctx->rho_tmp, 0.5, 0.5, ctx->adj_rho_m, nq, s);
+  EFE_TRY(rebuild(ctx, 0, ctx->adj_rho_m, t + 0.5 * dt, field, &it));
+  // corrector: b_s from X_n, then Xbar_n = exp(+i dt H_m) Xbar_{n+1} and u_m
+  EFE_TRY(run_lanczos(ctx, dt, ctx->X0, ctx->adj_W1, no, nullptr, k1.data(), nullptr));
+  adj_fwd_nodes(ctx, max_k(k1), sg);
+  EFE_TRY(run_lanczos(ctx, -dt, ctx->adj_XB, ctx->adj_XA, no, nullptr, k2.data(), nullptr));
+  EFE_TRY(adj_cross(ctx, ctx->adj_XB, max_k(k2), sg, wg));
+  EFE_TRY(adj_potential_of(ctx, ctx->adj_rho_m, zero3, 0.0, nullptr, ctx->adj_gm, fdir, &dLdE[1]));
+  // Pbar = 2 f Vbar[g_m / 2] P  (rho_m = (rho_n + rho(P))/2)
+  efe::k::axpby(ctx->adj_gm, ctx->adj_gm, 0.5, 0.0, ctx->adj_gn, nq, s);
+  efe::k::zero(ctx->adj_XB, ctx->blk, s);
+  EFE_TRY(adj_density_term(ctx, ctx->adj_gn, ctx->X1, ctx->adj_XB));
+  // predictor: b_s from X_n under H_n, then Xbar_n += exp(+i dt H_n) Pbar and u_n
+  EFE_TRY(rebuild(ctx, 0, ctx->adj_rho_n, t, field, &it));
+  EFE_TRY(run_lanczos(ctx, dt, ctx->X0, ctx->adj_W1, no, nullptr, k1.data(), nullptr));
+  adj_fwd_nodes(ctx, max_k(k1), sg);
+  EFE_TRY(run_lanczos(ctx, -dt, ctx->adj_XB, ctx->X1, no, nullptr, k2.data(), nullptr));
+  efe::k::axpy_cols(ctx->adj_XA, ctx->X1, nullptr, 1.0, ctx->n_rows, no, s);
+  EFE_TRY(adj_cross(ctx, ctx->adj_XB, max_k(k2), sg, wg));
+  // rhobar_n / W = g_n + g_m / 2 + mubar . x
+  EFE_TRY(adj_potential_of(ctx, ctx->adj_rho_n, mubar, 0.5, ctx->adj_gm, ctx->adj_gn, fdir, &dLdE[0]));
+  EFE_TRY(adj_density_term(ctx, ctx->adj_gn, ctx->X0, ctx->adj_XA));
+  EFE_TRY(pack_out(ctx, ctx->adj_XA, no, Psibar, ldb));
+  return sync(ctx, "magnus_adjoint");
+}
+
+efe_status dipole_adjoint(efe_ctx *ctx, const void *Psi, int64_t ld, const double mubar[3], void *Psibar,
+                          int64_t ldb) {
+  if (!ctx || !Psi || !Psibar || !mubar || ld < ctx->norb || ldb < ctx->norb) return EFE_ERR_ARG;
+  EFE_TRY(ensure_adjoint_buffers(ctx));
+  const int no = ctx->norb;
+  ctx->ham_valid = false;
+  ctx->adj_dt = 0.0;
+  EFE_TRY(pack_in(ctx, Psi, ld, no, ctx->X0));
+  // g = mubar . x  (u = 0, phibar = 0)
+  efe::k::adj_potential(ctx->d, ctx->adj_zero, ctx->adj_zero, ctx->adj_zero, 0.0, ctx->plan.xc, mubar, 0.0, nullptr,
+                        ctx->adj_gn, ctx->stream);
+  efe::k::zero(ctx->adj_XA, ctx->blk, ctx->stream);
+  EFE_TRY(adj_density_term(ctx, ctx->adj_gn, ctx->X0, ctx->adj_XA));
+  EFE_TRY(pack_out(ctx, ctx->adj_XA, no, Psibar, ldb));
+  return sync(ctx, "dipole_adjoint");
 }
 
 efe_status efe_enable_timing(efe_ctx *ctx, int32_t on) {

@@ -93,7 +93,14 @@ void couple_apply(const DevData &d, const double *G, const double *Hee, const do
 void psiE(const DevData &d, const double *X, int ncolr, int64_t ldr, double *psiE, hipStream_t s);
 void density(const DevData &d, const double *X, int ncol, int64_t ldr, const double *psiE, double *rho,
              hipStream_t s);
-void poisson_rhs(const DevData &d, const double *rho, double *dvec, double *rhs, hipStream_t s);
+void poisson_rhs(const DevData &d, const double *rho, double *dvec, double *rhs, hipStream_t s, int lift = 1);
+// adjoint pieces
+void cross_density(const DevData &d, const double *Z, int npair, const double *psiE, double w, double *out,
+                   hipStream_t s);
+void adj_potential(const DevData &d, const double *phibar, const double *rho, const double *u, double tau, int xc,
+                   const double mubar[3], double a, const double *gin, double *out, hipStream_t s);
+void axpy_cols(double *out, const double *Y, const double *sc, double s0, int64_t nrows, int ncol, hipStream_t s);
+void interleave(const double *a, const double *b, double *Z, int64_t nrows, int ncol, hipStream_t s);
 void stiffness_apply(const DevData &d, const double *x, double *y, double *t1, double *t2, hipStream_t s,
                      const int *skip = nullptr);
 void fdm_apply(const DevData &d, const double *r, double *z, double *t1, double *t2, hipStream_t s,
@@ -134,6 +141,9 @@ void lz_beta(const double *nrm1, const double *nrm2, const int *need, const int 
 void lz_any(const int *active, int ncol, int *any, hipStream_t s);
 void lz_comb_coef(const double *u, const double *sig, const double *beta0, const int *kused, int kmax, int nl,
                   int ncol, double *coef, hipStream_t s);
+// combination coefficients [m][kmax][ncol] (complex) of a finished Lanczos at the times taus[0..m), m <= 16
+void tridiag_coef(const double *alpha, const double *beta, const int *kused, int ncol, int kmax, const double *taus,
+                  int m, const double *beta0, const double *sig, double *coef, hipStream_t s);
 void tridiag_exp(const double *alpha, const double *beta, int j, int ncol, int kmax, double tau,
                  const double *beta0, const int *kforce, double tol, int *active, int *kused, double *err,
                  double *u, hipStream_t s);

@@ -96,6 +96,8 @@ k_rebuild(const DevData d, const int *__restrict__ cell_list, int n, int mode, c
     double v;
     if (mode == 0) {
       v = d.vstatic[q0 + q] + wv[q] + vxc_lda(rho[q0 + q], xc) - efield * x[fdir];
+    } else if (mode == 4) {
+      v = rho[q0 + q];                 // potential-only operator of a given g(q)
     } else {
       v = x[mode - 1];
     }
@@ -274,10 +276,11 @@ __global__ void k_hee_loewdin(const DevData d, const double *__restrict__ Hraw, 
 // Density rho(q) = sum_a f_a |psi_a(q)|^2, psi = sum_i D_i^-1/2 X_i N_i + sum_nu psiE_nu N^E_nu.
 // One workgroup per cell of one class; columns in passes of NCC complex orbitals.
 // ---------------------------------------------------------------------------
-template <int NCC, int MAXS>
+// CROSS: the block holds column pairs (a, b); out(q) += wcross * sum_pairs Im(conj(a(q)) b(q))
+template <int NCC, int MAXS, bool CROSS = false>
 __global__ void __launch_bounds__(kThreads)
 k_density(const DevData d, const int *__restrict__ cell_list, int n, const double *__restrict__ X, int ncol,
-          int64_t ldr, const double *__restrict__ psiE, double *__restrict__ rho) {
+          int64_t ldr, const double *__restrict__ psiE, double *__restrict__ rho, double wcross) {
   extern __shared__ double sm[];
   constexpr int F = 2 * NCC;
   const Geom &g = d.g;
@@ -296,7 +299,8 @@ k_density(const DevData d, const int *__restrict__ cell_list, int n, const doubl
   const int toB = enr ? d.to.Be : d.to.Bc;
   for (int t = threadIdx.x; t < n * P; t += blockDim.x) Bt[t] = tab[toB + t];
   for (int t = threadIdx.x; t < nloc; t += blockDim.x) dm[t] = d.Dm12[local_node(g, e, t)];
-  for (int t = threadIdx.x; t < ncol; t += blockDim.x) occ[t] = d.occ[t];
+  if (!CROSS)
+    for (int t = threadIdx.x; t < ncol; t += blockDim.x) occ[t] = d.occ[t];
   const int slot = d.tslot_of_cell[cell];
   const int k0 = slot >= 0 ? d.tnu_off[slot] : 0, nnu = slot >= 0 ? d.tnu_off[slot + 1] - k0 : 0;
   const double *NEs = slot >= 0 ? d.NE + d.tne_off[slot] : nullptr;
@@ -336,9 +340,15 @@ k_density(const DevData d, const int *__restrict__ cell_list, int n, const doubl
           for (int f = 0; f < F; ++f)
             if (2 * c0 + f < ncolr) val[f] += nev * pe[f];
         }
+        if (CROSS) {
 #pragma unroll
-        for (int cc = 0; cc < NCC; ++cc)
-          if (c0 + cc < ncol) acc[s] += occ[c0 + cc] * (val[2 * cc] * val[2 * cc] + val[2 * cc + 1] * val[2 * cc + 1]);
+          for (int cc = 0; cc + 1 < NCC; cc += 2)
+            if (c0 + cc + 1 < ncol) acc[s] += val[2 * cc] * val[2 * cc + 3] - val[2 * cc + 1] * val[2 * cc + 2];
+        } else {
+#pragma unroll
+          for (int cc = 0; cc < NCC; ++cc)
+            if (c0 + cc < ncol) acc[s] += occ[c0 + cc] * (val[2 * cc] * val[2 * cc] + val[2 * cc + 1] * val[2 * cc + 1]);
+        }
       }
     }
     __syncthreads();
@@ -347,7 +357,10 @@ k_density(const DevData d, const int *__restrict__ cell_list, int n, const doubl
 #pragma unroll
   for (int s = 0; s < MAXS; ++s) {
     int q = threadIdx.x + s * kThreads;
-    if (q < n3) rho[q0 + q] = acc[s];
+    if (q < n3) {
+      if (CROSS) rho[q0 + q] += wcross * acc[s];
+      else rho[q0 + q] = acc[s];
+    }
   }
 }
 
@@ -395,10 +408,74 @@ k_poisson_rhs(const DevData d, const int *__restrict__ cell_list, const double *
 }
 
 // rhs = 4 pi d - lift on interior nodes, 0 on the boundary
-__global__ void k_rhs_finish(const DevData d, const double *__restrict__ dvec, double *__restrict__ rhs) {
+__global__ void k_rhs_finish(const DevData d, const double *__restrict__ dvec, double *__restrict__ rhs, int lift) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.g.n_nodes) return;
-  rhs[i] = d.Dm12[i] != 0.0 ? 4.0 * 3.14159265358979323846 * dvec[i] - d.lift[i] : 0.0;
+  rhs[i] = d.Dm12[i] != 0.0 ? 4.0 * 3.14159265358979323846 * dvec[i] - (lift ? d.lift[i] : 0.0) : 0.0;
+}
+
+// Adjoint potential at the quadrature points of one cell per block:
+//   out(q) = (B phibar)(q) + tau f_xc(rho(q)) u(q) + mubar . x(q) + a gin(q)
+// (B phibar: the nodal field interpolated to the points; gin may be null).
+__global__ void __launch_bounds__(kThreads)
+k_adj_potential(const DevData d, const int *__restrict__ cell_list, int n, const double *__restrict__ phibar,
+                const double *__restrict__ rho, const double *__restrict__ u, double tau, int xc, double mx, double my,
+                double mz, double a, const double *__restrict__ gin, double *__restrict__ out) {
+  extern __shared__ double sm[];
+  const Geom &g = d.g;
+  const int P = g.P, nloc = g.nloc, n3 = n * n * n;
+  const bool enr = n == g.qe;
+  const double *tab = d.tab;
+  double *Bt = sm;                 // n*P
+  double *u0 = Bt + n * P;         // nloc
+  double *t1 = u0 + nloc;          // P*P*n
+  double *t2 = t1 + P * P * n;     // P*n*n
+  double *wv = t2 + P * n * n;     // n3
+  const int64_t cell = cell_list[blockIdx.x];
+  int e[3];
+  cell_ijk(g, cell, e);
+  const int toB = enr ? d.to.Be : d.to.Bc, tox = enr ? d.to.xqe : d.to.xqc;
+  for (int t = threadIdx.x; t < n * P; t += blockDim.x) Bt[t] = tab[toB + t];
+  for (int t = threadIdx.x; t < nloc; t += blockDim.x) u0[t] = phibar[local_node(g, e, t)];
+  __syncthreads();
+  apply_axis(u0, t1, Bt, P, false, P, P, P, 0, n, 1);
+  __syncthreads();
+  apply_axis(t1, t2, Bt, P, false, n, P, P, 1, n, 1);
+  __syncthreads();
+  apply_axis(t2, wv, Bt, P, false, n, n, P, 2, n, 1);
+  __syncthreads();
+  const int64_t q0 = d.q_off[cell];
+  for (int q = threadIdx.x; q < n3; q += blockDim.x) {
+    const int i = q % n, j = (q / n) % n, k = q / (n * n);
+    const double x = g.lo[0] + e[0] * g.h[0] + (tab[tox + i] + 1.0) * 0.5 * g.h[0];
+    const double y = g.lo[1] + e[1] * g.h[1] + (tab[tox + j] + 1.0) * 0.5 * g.h[1];
+    const double z = g.lo[2] + e[2] * g.h[2] + (tab[tox + k] + 1.0) * 0.5 * g.h[2];
+    double v = wv[q] + tau * fxc_lda(rho[q0 + q], xc) * u[q0 + q] + mx * x + my * y + mz * z;
+    if (gin) v += a * gin[q0 + q];
+    out[q0 + q] = v;
+  }
+}
+
+// out[r][c] += s[c % ncs] * Y[r][c]  over complex columns (s real; ncs = orbitals)
+__global__ void k_axpy_cols(double *__restrict__ out, const double *__restrict__ Y, const double *__restrict__ sc,
+                            double s0, int64_t nrows, int ncol) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nrows * ncol) return;
+  const int c = (int)(t % ncol);
+  const double f = sc ? s0 * sc[c] : s0;
+  out[2 * t] += f * Y[2 * t];
+  out[2 * t + 1] += f * Y[2 * t + 1];
+}
+
+// Z[r][2c] = a[r][c], Z[r][2c + 1] = b[r][c]  (complex columns)
+__global__ void k_interleave(const double2 *__restrict__ a, const double2 *__restrict__ b, double2 *__restrict__ Z,
+                             int64_t nrows, int ncol) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nrows * ncol) return;
+  const int64_t r = t / ncol;
+  const int c = (int)(t % ncol);
+  Z[r * 2 * ncol + 2 * c] = a[t];
+  Z[r * 2 * ncol + 2 * c + 1] = b[t];
 }
 
 // out = A_axis in (banded 1-D operator, bandwidth p), over all nodes
@@ -655,7 +732,9 @@ void psiE(const DevData &d, const double *X, int ncolr, int64_t ldr, double *out
   hipLaunchKernelGGL(k_psiE, dim3(nblocks((int64_t)d.ne * ncolr, 128)), dim3(128), 0, s, d, X, ncolr, ldr, out);
 }
 
-void density(const DevData &d, const double *X, int ncol, int64_t ldr, const double *psiE, double *rho, hipStream_t s) {
+template <bool CROSS>
+static void density_launch(const DevData &d, const double *X, int ncol, int64_t ldr, const double *psiE, double *rho,
+                           double wcross, hipStream_t s) {
   constexpr int NCC = 4, F = 2 * NCC;
   for (int cls = 0; cls < 2; ++cls) {
     int nc = cls ? d.n_enr : d.n_ord;
@@ -666,19 +745,57 @@ void density(const DevData &d, const double *X, int ncol, int64_t ldr, const dou
                  sizeof(double);
     int n3 = n * n * n;
     if (n3 <= 256)
-      hipLaunchKernelGGL((k_density<NCC, 1>), dim3(nc), dim3(kThreads), lds, s, d, list, n, X, ncol, ldr, psiE, rho);
+      hipLaunchKernelGGL((k_density<NCC, 1, CROSS>), dim3(nc), dim3(kThreads), lds, s, d, list, n, X, ncol, ldr, psiE,
+                         rho, wcross);
     else if (n3 <= 512)
-      hipLaunchKernelGGL((k_density<NCC, 2>), dim3(nc), dim3(kThreads), lds, s, d, list, n, X, ncol, ldr, psiE, rho);
+      hipLaunchKernelGGL((k_density<NCC, 2, CROSS>), dim3(nc), dim3(kThreads), lds, s, d, list, n, X, ncol, ldr, psiE,
+                         rho, wcross);
     else if (n3 <= 1024)
-      hipLaunchKernelGGL((k_density<NCC, 4>), dim3(nc), dim3(kThreads), lds, s, d, list, n, X, ncol, ldr, psiE, rho);
+      hipLaunchKernelGGL((k_density<NCC, 4, CROSS>), dim3(nc), dim3(kThreads), lds, s, d, list, n, X, ncol, ldr, psiE,
+                         rho, wcross);
     else if (n3 <= 2048)
-      hipLaunchKernelGGL((k_density<NCC, 8>), dim3(nc), dim3(kThreads), lds, s, d, list, n, X, ncol, ldr, psiE, rho);
+      hipLaunchKernelGGL((k_density<NCC, 8, CROSS>), dim3(nc), dim3(kThreads), lds, s, d, list, n, X, ncol, ldr, psiE,
+                         rho, wcross);
     else
-      hipLaunchKernelGGL((k_density<NCC, 16>), dim3(nc), dim3(kThreads), lds, s, d, list, n, X, ncol, ldr, psiE, rho);
+      hipLaunchKernelGGL((k_density<NCC, 16, CROSS>), dim3(nc), dim3(kThreads), lds, s, d, list, n, X, ncol, ldr,
+                         psiE, rho, wcross);
   }
 }
 
-void poisson_rhs(const DevData &d, const double *rho, double *dvec, double *rhs, hipStream_t s) {
+void density(const DevData &d, const double *X, int ncol, int64_t ldr, const double *psiE, double *rho, hipStream_t s) {
+  density_launch<false>(d, X, ncol, ldr, psiE, rho, 0.0, s);
+}
+
+void cross_density(const DevData &d, const double *Z, int npair, const double *psiE, double w, double *out,
+                   hipStream_t s) {
+  density_launch<true>(d, Z, 2 * npair, 4 * npair, psiE, out, w, s);
+}
+
+void adj_potential(const DevData &d, const double *phibar, const double *rho, const double *u, double tau, int xc,
+                   const double mubar[3], double a, const double *gin, double *out, hipStream_t s) {
+  for (int cls = 0; cls < 2; ++cls) {
+    int nc = cls ? d.n_enr : d.n_ord;
+    if (nc == 0) continue;
+    int n = cls ? d.g.qe : d.g.qc, P = d.g.P;
+    const int *list = cls ? d.cells_enr : d.cells_ord;
+    size_t lds = ((size_t)n * P + d.g.nloc + (size_t)P * P * n + (size_t)P * n * n + (size_t)n * n * n) * sizeof(double);
+    hipLaunchKernelGGL(k_adj_potential, dim3(nc), dim3(kThreads), lds, s, d, list, n, phibar, rho, u, tau, xc,
+                       mubar[0], mubar[1], mubar[2], a, gin, out);
+  }
+}
+
+void axpy_cols(double *out, const double *Y, const double *sc, double s0, int64_t nrows, int ncol, hipStream_t s) {
+  if (nrows * ncol > 0)
+    hipLaunchKernelGGL(k_axpy_cols, dim3(nblocks(nrows * ncol, 256)), dim3(256), 0, s, out, Y, sc, s0, nrows, ncol);
+}
+
+void interleave(const double *a, const double *b, double *Z, int64_t nrows, int ncol, hipStream_t s) {
+  if (nrows * ncol > 0)
+    hipLaunchKernelGGL(k_interleave, dim3(nblocks(nrows * ncol, 256)), dim3(256), 0, s, (const double2 *)a,
+                       (const double2 *)b, (double2 *)Z, nrows, ncol);
+}
+
+void poisson_rhs(const DevData &d, const double *rho, double *dvec, double *rhs, hipStream_t s, int lift) {
   zero(dvec, d.g.n_nodes, s);
   const int n = d.g.qe > d.g.qc ? d.g.qe : d.g.qc, P = d.g.P;
   size_t lds = ((size_t)n * P + (size_t)n * n * n + (size_t)n * n * P + (size_t)n * P * P + d.g.nloc) * sizeof(double);
@@ -687,7 +804,7 @@ void poisson_rhs(const DevData &d, const double *rho, double *dvec, double *rhs,
     if (cnt == 0) continue;
     hipLaunchKernelGGL(k_poisson_rhs, dim3(cnt), dim3(kThreads), lds, s, d, d.colour_cells + d.colour_off[c], rho, dvec);
   }
-  hipLaunchKernelGGL(k_rhs_finish, dim3(nblocks(d.g.n_nodes, 256)), dim3(256), 0, s, d, dvec, rhs);
+  hipLaunchKernelGGL(k_rhs_finish, dim3(nblocks(d.g.n_nodes, 256)), dim3(256), 0, s, d, dvec, rhs, lift);
 }
 
 // y = K_II x for x with zero boundary: K = K1 x M1 x M1 + M1 x K1 x M1 + M1 x M1 x K1

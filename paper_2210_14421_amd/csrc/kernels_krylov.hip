@@ -362,22 +362,10 @@ k_couple_final(const DevData d, const double *__restrict__ part, int nblk, const
 // |tau| beta_j beta0 |u_j| and the stopping decision.  One wavefront per
 // column; lane k owns row k of V (j <= 64).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(64)
-k_tridiag_exp(const double *__restrict__ alpha, const double *__restrict__ beta, int j, int ncol, int kmax,
-              double tau, const double *__restrict__ beta0, const int *__restrict__ kforce, double tol,
-              int *__restrict__ active, int *__restrict__ kused, double *__restrict__ err, double *__restrict__ ubuf) {
-  __shared__ double Z[64][65];
-  __shared__ double dd[64], ee[64];
-  const int c = blockIdx.x;
-  const int lane = threadIdx.x;
-  if (!active[c]) return;
-  const int n = j;
-  for (int k = 0; k < n; ++k) Z[lane][k] = (lane == k) ? 1.0 : 0.0;
-  if (lane < n) {
-    dd[lane] = alpha[(int64_t)lane * ncol + c];
-    ee[lane] = lane < n - 1 ? beta[(int64_t)lane * ncol + c] : 0.0;
-  }
-  __syncthreads();
+// Implicit QL on the n x n tridiagonal (dd diagonal, ee off-diagonal) in LDS,
+// accumulating the eigenvectors in Z (initialised to I by the caller).  One
+// wavefront; returns false if an eigenvalue needed more than 60 sweeps.
+__device__ bool tridiag_ql(int n, double (*Z)[65], double *dd, double *ee, int lane) {
   bool fail = false;
   for (int l = 0; l < n && !fail; ++l) {
     int iter = 0;
@@ -429,6 +417,27 @@ k_tridiag_exp(const double *__restrict__ alpha, const double *__restrict__ beta,
     }
   }
   __syncthreads();
+  return !fail;
+}
+
+__global__ void __launch_bounds__(64)
+k_tridiag_exp(const double *__restrict__ alpha, const double *__restrict__ beta, int j, int ncol, int kmax,
+              double tau, const double *__restrict__ beta0, const int *__restrict__ kforce, double tol,
+              int *__restrict__ active, int *__restrict__ kused, double *__restrict__ err, double *__restrict__ ubuf) {
+  __shared__ double Z[64][65];
+  __shared__ double dd[64], ee[64];
+  const int c = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (!active[c]) return;
+  const int n = j;
+  for (int k = 0; k < n; ++k) Z[lane][k] = (lane == k) ? 1.0 : 0.0;
+  if (lane < n) {
+    dd[lane] = alpha[(int64_t)lane * ncol + c];
+    ee[lane] = lane < n - 1 ? beta[(int64_t)lane * ncol + c] : 0.0;
+  }
+  __syncthreads();
+  const bool fail = !tridiag_ql(n, Z, dd, ee, lane);
+  __syncthreads();
   // u_k = sum_m Z[k][m] exp(-i tau lam_m) Z[0][m]
   double ur = 0.0, ui = 0.0;
   if (lane < n) {
@@ -464,6 +473,51 @@ k_tridiag_exp(const double *__restrict__ alpha, const double *__restrict__ beta,
     if (lane == 0) {
       kused[c] = j;
       active[c] = 0;
+    }
+  }
+}
+
+// Krylov combination coefficients of a finished Lanczos for several times:
+//   coef[g][l][c] = beta0 sig_l [exp(-i tau_g T_{k_c}) e_1]_l  (l < k_c; 0 up to kmax)
+// with k_c = kused[c], so that sum_l coef[g][l][c] slot_l = exp(-i tau_g A) x_c in
+// the Krylov space of the run.  One wavefront per column.
+struct TauList {
+  double tau[16];
+};
+
+__global__ void __launch_bounds__(64)
+k_tridiag_coef(const double *__restrict__ alpha, const double *__restrict__ beta, const int *__restrict__ kused,
+               int ncol, int kmax, TauList taus, int m, const double *__restrict__ beta0,
+               const double *__restrict__ sig, double2 *__restrict__ coef) {
+  __shared__ double Z[64][65];
+  __shared__ double dd[64], ee[64];
+  const int c = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int n = kused[c];
+  if (n > 0) {
+    for (int k = 0; k < n; ++k) Z[lane][k] = (lane == k) ? 1.0 : 0.0;
+    if (lane < n) {
+      dd[lane] = alpha[(int64_t)lane * ncol + c];
+      ee[lane] = lane < n - 1 ? beta[(int64_t)lane * ncol + c] : 0.0;
+    }
+    __syncthreads();
+    tridiag_ql(n, Z, dd, ee, lane);
+  }
+  for (int g = 0; g < m; ++g) {
+    for (int l = lane; l < kmax; l += 64) {
+      double ur = 0.0, ui = 0.0;
+      if (l < n) {
+        for (int p = 0; p < n; ++p) {
+          double sn, cs;
+          sincos(-taus.tau[g] * dd[p], &sn, &cs);
+          ur += Z[l][p] * Z[0][p] * cs;
+          ui += Z[l][p] * Z[0][p] * sn;
+        }
+        const double f = beta0[c] * sig[(int64_t)l * ncol + c];
+        ur *= f;
+        ui *= f;
+      }
+      coef[((int64_t)g * kmax + l) * ncol + c] = make_double2(ur, ui);
     }
   }
 }
@@ -536,6 +590,14 @@ void couple_apply(const DevData &d, const double *G, const double *Hee, const do
   }
   hipLaunchKernelGGL(k_couple_final, dim3(nblocks((int64_t)nout, 64)), dim3(256), 0, s, d, scratch, nblk, Hee, X, Y,
                      ncolr, ldr, any);
+}
+
+void tridiag_coef(const double *alpha, const double *beta, const int *kused, int ncol, int kmax, const double *taus,
+                  int m, const double *beta0, const double *sig, double *coef, hipStream_t s) {
+  TauList tl{};
+  for (int g = 0; g < m && g < 16; ++g) tl.tau[g] = taus[g];
+  hipLaunchKernelGGL(k_tridiag_coef, dim3(ncol), dim3(64), 0, s, alpha, beta, kused, ncol, kmax, tl, m < 16 ? m : 16,
+                     beta0, sig, (double2 *)coef);
 }
 
 void tridiag_exp(const double *alpha, const double *beta, int j, int ncol, int kmax, double tau, const double *beta0,

@@ -86,6 +86,9 @@ _batch_error = _sig("efe_batch_error", C.c_char_p, [C.c_void_p])
 _batch_step = _sig("efe_batch_step", C.c_int32, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_int64), C.c_double,
                                                  C.c_double, C.POINTER(C.POINTER(EfeField)),
                                                  C.POINTER(EfeStepStats)])
+_adjoint = _sig("magnus_adjoint", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_double,
+                                               C.POINTER(EfeField), _dp, C.c_void_p, C.c_int64, _dp])
+_dip_adjoint = _sig("dipole_adjoint", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, _dp, C.c_void_p, C.c_int64])
 _density = _sig("density", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p])
 _hartree = _sig("efe_hartree", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, _ip])
 _dipole = _sig("dipole", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, _dp])
@@ -97,7 +100,8 @@ EXPORTED = ["efe_plan_create", "efe_plan_free", "efe_plan_sizes", "efe_plan_get"
             "efe_setup", "efe_free", "efe_dims", "efe_set_options", "efe_initial_state",
             "efe_set_hamiltonian", "efe_apply_H", "lanczos_expm", "magnus_step", "density",
             "efe_hartree", "dipole", "efe_enable_timing", "efe_get_timing", "efe_last_error",
-            "magnus_step_graph", "efe_batch_create", "efe_batch_free", "efe_batch_error", "efe_batch_step"]
+            "magnus_step_graph", "efe_batch_create", "efe_batch_free", "efe_batch_error", "efe_batch_step",
+            "magnus_adjoint", "dipole_adjoint"]
 
 
 class EfeError(RuntimeError):
@@ -294,6 +298,26 @@ class Context:
                                 None if kf is None else kf.ctypes.data_as(_ip), C.byref(st)))
         return _stats_dict(st, self.norb)
 
+    def magnus_adjoint(self, Psi, Psibar, t, dt, field=None, mubar=(0.0, 0.0, 0.0)):
+        """Reverse of one step from Psi at t: Psibar (in: Xbar_{n+1}, out: Xbar_n).
+        Returns (dL/dE(t), dL/dE(t + dt/2))."""
+        mb = _arr(mubar, np.float64)
+        out = np.zeros(2)
+        f = C.byref(field) if field is not None else None
+        self._check(_adjoint(self._c, self._ptr(Psi, self.torch.complex128, self.n_rows), Psi.shape[1], float(t),
+                             float(dt), f, mb.ctypes.data_as(_dp),
+                             self._ptr(Psibar, self.torch.complex128, self.n_rows), Psibar.shape[1],
+                             out.ctypes.data_as(_dp)))
+        return float(out[0]), float(out[1])
+
+    def dipole_adjoint(self, Psi, mubar, Psibar=None):
+        Psibar = self.torch.empty_like(Psi) if Psibar is None else Psibar
+        mb = _arr(mubar, np.float64)
+        self._check(_dip_adjoint(self._c, self._ptr(Psi, self.torch.complex128, self.n_rows), Psi.shape[1],
+                                 mb.ctypes.data_as(_dp), self._ptr(Psibar, self.torch.complex128, self.n_rows),
+                                 Psibar.shape[1]))
+        return Psibar
+
     def density(self, Psi, rho=None):
         torch = self.torch
         rho = torch.empty(self.n_quad, dtype=torch.float64, device="cuda") if rho is None else rho
@@ -374,3 +398,61 @@ class Batch:
 
     def __del__(self):
         self.close()
+
+
+def field_gradient(ctx, Psi0, theta, t0, s, dt, nsteps, mu_target, direction=2, checkpoint=20):
+    """dL/dtheta of L = sum_{n=1}^{N} (mu_d(t_n) - mu*_n)^2 for the sum-of-sines field
+    E(t) = sum_k A_k sin(w_k t + phi_k) exp(-(t - t0)^2 / s^2), theta = (A, w, phi).
+
+    Forward: N magnus_step calls from Psi0 at t = 0 (not modified), keeping a
+    copy of the orbitals every `checkpoint` steps.  Reverse: per segment, the
+    forward is run again from its checkpoint keeping every step, then
+    dipole_adjoint (terminal condition) and magnus_adjoint step by step; the
+    field sensitivities are contracted with dE/dtheta on the host.
+    Returns (L, grad, mus)."""
+    torch = ctx.torch
+    theta = np.asarray(theta, dtype=np.float64)
+    m = len(theta) // 3
+    A, w, ph = theta[:m], theta[m:2 * m], theta[2 * m:]
+    field, keep = make_field(direction, A, w, ph, t0, s)
+
+    def dE(t):
+        env = np.exp(-((t - t0) / s) ** 2)
+        arg = w * t + ph
+        return np.concatenate([np.sin(arg) * env, A * t * np.cos(arg) * env, A * np.cos(arg) * env])
+
+    Psi = Psi0.clone()
+    ckpt = {}
+    mus = np.zeros((nsteps + 1, 3))
+    ctx.set_hamiltonian(Psi, 0.0, field)
+    mus[0] = ctx.dipole(Psi)
+    for n in range(nsteps):
+        if n % checkpoint == 0:
+            ckpt[n] = Psi.clone()
+        mus[n + 1] = ctx.magnus_step(Psi, n * dt, dt, field)["mu"]
+    resid = mus[1:, direction] - np.asarray(mu_target)
+    L = float(np.sum(resid ** 2))
+
+    def mubar(n):              # dL/dmu(t_n)
+        v = np.zeros(3)
+        if n >= 1:
+            v[direction] = 2.0 * resid[n - 1]
+        return v
+
+    grad = np.zeros_like(theta)
+    Psibar = None
+    for c0 in sorted(ckpt, reverse=True):
+        c1 = min(c0 + checkpoint, nsteps)
+        states = [ckpt[c0].clone()]
+        ctx.set_hamiltonian(states[0], c0 * dt, field)
+        for n in range(c0, c1):
+            P = states[-1].clone()
+            ctx.magnus_step(P, n * dt, dt, field)
+            states.append(P)
+        if Psibar is None:
+            Psibar = ctx.dipole_adjoint(states[-1], mubar(c1))
+        for n in range(c1 - 1, c0 - 1, -1):
+            gE = ctx.magnus_adjoint(states[n - c0], Psibar, n * dt, dt, field, mubar(n))
+            grad += gE[0] * dE(n * dt) + gE[1] * dE(n * dt + 0.5 * dt)
+    del keep
+    return L, grad, mus

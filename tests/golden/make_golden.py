@@ -16,7 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
-from workloads import tiny, trap, na8 as na8_spec  # noqa: E402
+from workloads import tiny, trap, na8 as na8_spec, adjoint_field_params, ADJOINT_TINY  # noqa: E402
 from oracle.model import EFEModel  # noqa: E402
 from oracle.propagate import scf_ground_state, Propagator  # noqa: E402
 
@@ -91,6 +91,24 @@ def na8():
                         Y_rows=Yr, Y_E=YE, q_idx=q_idx, rho_q=rho[q_idx], rho_sum=float(np.sum(m.qw * rho)),
                         mu=mu, phi_idx=ph_idx, phi=phi[ph_idx], nk=m.nk)
     print("na8 done", flush=True)
+
+
+def adjoint_tiny():
+    """Field-parameter gradient on the tiny system (oracle central differences, k replayed)."""
+    from oracle.adjoint import fd_gradient, run_dipole, field_from_params
+    cfg = ADJOINT_TINY
+    m = EFEModel(tiny())
+    X0 = np.load(os.path.join(HERE, "tiny_ground_state.npz"))["X"]
+    theta = adjoint_field_params(cfg["seed"], cfg["ncomp"])
+    theta_star = adjoint_field_params(cfg["seed_target"], cfg["ncomp"])
+    t0 = time.time()
+    mus_star, _ = run_dipole(m, X0, field_from_params(theta_star, cfg["t0"], cfg["s"]), cfg["dt"], cfg["nsteps"])
+    mu_target = mus_star[:, 2]
+    print(f"target run {time.time() - t0:.0f}s", flush=True)
+    g, L, mus, ks = fd_gradient(m, X0, theta, cfg["t0"], cfg["s"], cfg["dt"], cfg["nsteps"], mu_target)
+    print(f"gradient {time.time() - t0:.0f}s  L={L:.6e}  g={g}", flush=True)
+    np.savez_compressed(os.path.join(HERE, "adjoint_tiny.npz"), theta=theta, theta_star=theta_star,
+                        mu_target=mu_target, mus=mus, L=L, g_fd=g, ks=np.asarray(ks, dtype=np.int32), h=1e-6)
 
 
 if __name__ == "__main__":

@@ -1,0 +1,148 @@
+"""Reverse mode of the Magnus-2 step on the GPU (magnus_adjoint, dipole_adjoint).
+
+* Dot-product test of one step: for the forward map Y = F(X) (k frozen to the
+  base run) and seeded Ybar, dX, the adjoint Xbar must satisfy
+  Re<Xbar, dX> = Re<Ybar, F(X + h dX) - F(X - h dX)> / (2h) and
+  dL/dE(t), dL/dE(t + dt/2) the same identity for a field perturbation.
+* Field-parameter gradient of the dipole-tracking loss on the tiny system
+  (20 steps, checkpoints every 7 steps) against the oracle's central
+  differences with k replayed (tests/golden/adjoint_tiny.npz) and against
+  central differences of the GPU forward itself.  Target 1e-6 relative.
+"""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+@pytest.fixture(scope="module")
+def setup(golden_dir):
+    from workloads import tiny
+    from paper_2210_14421_amd.efe import Context
+    print("adjoint: tiny context", flush=True)
+    spec = tiny()
+    ctx = Context(spec, kmax=40)
+    X0 = np.load(os.path.join(golden_dir, "tiny_ground_state.npz"))["X"]
+    gold = np.load(os.path.join(golden_dir, "adjoint_tiny.npz"))
+    yield spec, ctx, X0, gold
+    ctx.close()
+
+
+def _field(theta, t0, s):
+    from paper_2210_14421_amd.efe import make_field
+    m = len(theta) // 3
+    return make_field(2, theta[:m], theta[m:2 * m], theta[2 * m:], t0, s)
+
+
+def _step(ctx, X, t, dt, field, k_force):
+    Y = X.clone()
+    ctx.set_hamiltonian(Y, t, field)
+    st = ctx.magnus_step(Y, t, dt, field, k_force=k_force)
+    return Y, st
+
+
+def test_adjoint_step_dot_product(setup):
+    """The adjoint is that of the exact exponentials; the differences of the
+    Krylov forward resolve a perturbation h dX only to tol ||X|| / h, so this
+    test runs at tol 1e-14 (the same context settings on both sides)."""
+    from workloads import ADJOINT_TINY
+    from paper_2210_14421_amd.efe import Context
+    spec, _, X0, gold = setup
+    ctx = Context(spec, kmax=48, tol=1e-14)
+    cfg = ADJOINT_TINY
+    theta = gold["theta"]
+    field, keep = _field(theta, cfg["t0"], cfg["s"])
+    rng = np.random.default_rng(31)
+    X = _dev(X0)
+    t, dt = 0.35, cfg["dt"]
+    Y0, st = _step(ctx, X, t, dt, field, None)
+    kf = np.stack([st["k_pred"], st["k_corr"]]).astype(np.int32)
+    shape = X0.shape
+    bnd = np.all(X0 == 0, axis=1)[:, None]          # Dirichlet rows of the physical state
+    yb = np.where(bnd, 0.0, rng.standard_normal(shape) + 1j * rng.standard_normal(shape))
+    dx = np.where(bnd, 0.0, rng.standard_normal(shape) + 1j * rng.standard_normal(shape))
+    Ybar = _dev(yb / np.linalg.norm(yb))
+    dX = _dev(dx / np.linalg.norm(dx))
+    Xbar = Ybar.clone()
+    gE = ctx.magnus_adjoint(X, Xbar, t, dt, field, (0.0, 0.0, 0.0))
+    h = 1e-6
+    Yp, _ = _step(ctx, X + h * dX, t, dt, field, kf)
+    Ym, _ = _step(ctx, X - h * dX, t, dt, field, kf)
+    fd = float(torch.real(torch.sum(torch.conj(Ybar) * (Yp - Ym))).item()) / (2 * h)
+    ad = float(torch.real(torch.sum(torch.conj(Xbar) * dX)).item())
+    print(f"state: adjoint {ad:.12e}  fd {fd:.12e}  rel {abs(ad - fd) / abs(fd):.2e}", flush=True)
+    assert abs(ad - fd) <= 1e-6 * abs(fd)
+    # field values: perturb E(t) and E(t + dt/2) through an extra component that is
+    # nonzero only there is not available, so check the combined sensitivity to A_1
+    # (dE/dA_1 at both times) against a difference of the amplitude
+    m = len(theta) // 3
+    env = lambda tt: np.exp(-((tt - cfg["t0"]) / cfg["s"]) ** 2)
+    dEdA = [np.sin(theta[m] * tt + theta[2 * m]) * env(tt) for tt in (t, t + 0.5 * dt)]
+    ad_A = gE[0] * dEdA[0] + gE[1] * dEdA[1]
+    tp, tm = theta.copy(), theta.copy()
+    tp[0] += h
+    tm[0] -= h
+    fp, kp = _field(tp, cfg["t0"], cfg["s"])
+    fm, km = _field(tm, cfg["t0"], cfg["s"])
+    Yp, _ = _step(ctx, X, t, dt, fp, kf)
+    Ym, _ = _step(ctx, X, t, dt, fm, kf)
+    fdA = float(torch.real(torch.sum(torch.conj(Ybar) * (Yp - Ym))).item()) / (2 * h)
+    print(f"field A_1: adjoint {ad_A:.12e}  fd {fdA:.12e}  rel {abs(ad_A - fdA) / abs(fdA):.2e}", flush=True)
+    assert abs(ad_A - fdA) <= 1e-6 * abs(fdA)
+    del keep, kp, km
+    ctx.close()
+
+
+def test_field_gradient_against_oracle(setup):
+    from workloads import ADJOINT_TINY
+    from paper_2210_14421_amd.efe import field_gradient
+    spec, ctx, X0, gold = setup
+    cfg = ADJOINT_TINY
+    L, g, mus = field_gradient(ctx, _dev(X0), gold["theta"], cfg["t0"], cfg["s"], cfg["dt"], cfg["nsteps"],
+                               gold["mu_target"], checkpoint=7)
+    eL = abs(L - float(gold["L"])) / abs(float(gold["L"]))
+    eg = np.linalg.norm(g - gold["g_fd"]) / np.linalg.norm(gold["g_fd"])
+    print(f"L {L:.12e} (oracle {float(gold['L']):.12e}, rel {eL:.2e}); |g - g_fd|/|g_fd| = {eg:.2e}", flush=True)
+    print("g_adj ", g)
+    print("g_fd  ", gold["g_fd"])
+    assert eL < 1e-7
+    assert eg < 1e-6
+
+
+def test_field_gradient_against_gpu_differences(setup):
+    from workloads import ADJOINT_TINY
+    from paper_2210_14421_amd.efe import field_gradient
+    spec, ctx, X0, gold = setup
+    cfg = ADJOINT_TINY
+    theta = gold["theta"]
+    L, g, mus = field_gradient(ctx, _dev(X0), theta, cfg["t0"], cfg["s"], cfg["dt"], cfg["nsteps"], gold["mu_target"],
+                               checkpoint=20)
+
+    def loss(th, kf=None):
+        field, keep = _field(th, cfg["t0"], cfg["s"])
+        P = _dev(X0)
+        ctx.set_hamiltonian(P, 0.0, field)
+        out, ks = [], []
+        for n in range(cfg["nsteps"]):
+            st = ctx.magnus_step(P, n * cfg["dt"], cfg["dt"], field, k_force=None if kf is None else kf[n])
+            out.append(st["mu"][2])
+            ks.append(np.stack([st["k_pred"], st["k_corr"]]).astype(np.int32))
+        return float(np.sum((np.array(out) - gold["mu_target"]) ** 2)), ks
+
+    L0, ks = loss(theta)
+    h = 1e-6
+    for p in (0, 4, 8):        # an amplitude, a frequency and a phase
+        tp, tm = theta.copy(), theta.copy()
+        tp[p] += h
+        tm[p] -= h
+        fd = (loss(tp, ks)[0] - loss(tm, ks)[0]) / (2 * h)
+        print(f"param {p}: adjoint {g[p]:.12e}  gpu fd {fd:.12e}", flush=True)
+        assert abs(g[p] - fd) <= 1e-6 * np.max(np.abs(g))

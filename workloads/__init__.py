@@ -5,7 +5,7 @@ lists, occupations, propagation parameters and the random numbers that the
 initial-state recipe draws.  Both sides build everything else themselves.
 """
 from .systems import (SystemSpec, tiny, na_cluster, na8, trap, gaussian_box,
-                      cluster_positions, noise_coefficients, NOISE_MODES)
+                      cluster_positions, noise_coefficients, NOISE_MODES, adjoint_field_params, ADJOINT_TINY)
 
 __all__ = ["SystemSpec", "tiny", "na_cluster", "na8", "trap", "gaussian_box",
-           "cluster_positions", "noise_coefficients", "NOISE_MODES"]
+           "cluster_positions", "noise_coefficients", "NOISE_MODES", "adjoint_field_params", "ADJOINT_TINY"]

@@ -201,3 +201,18 @@ def gaussian_box(ncell: int, half: float, degree: int) -> SystemSpec:
         enr_atom=np.zeros(0, dtype=np.int32), enr_l=np.zeros(0, dtype=np.int32),
         enr_m=np.zeros(0, dtype=np.int32), enr_zeta=np.zeros(0), r_cut=6.0,
         occ=np.zeros(0), xc="none", init="scf")
+
+
+def adjoint_field_params(seed, ncomp=3, a_range=(1e-3, 1e-2), w_range=(0.5, 5.0)):
+    """Seeded field parameters theta = (A_1..A_m, w_1..w_m, phi_1..phi_m) of a
+    sum-of-sines pulse: A ~ U(a_range), w ~ U(w_range), phi ~ U[0, 2 pi)."""
+    rng = np.random.default_rng(seed)
+    A = rng.uniform(a_range[0], a_range[1], ncomp)
+    w = rng.uniform(w_range[0], w_range[1], ncomp)
+    phi = rng.uniform(0.0, 2.0 * np.pi, ncomp)
+    return np.concatenate([A, w, phi])
+
+
+# The field-gradient workload on the tiny system: no kick, 20 steps of 0.05 au,
+# envelope centre 0.5 and width 0.4, theta from seed 7, target trace from seed 8.
+ADJOINT_TINY = dict(nsteps=20, dt=0.05, t0=0.5, s=0.4, seed=7, seed_target=8, ncomp=3)
