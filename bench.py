@@ -242,6 +242,45 @@ def run_batch(steps, warmup, kmax, dtype="f32"):
             "krylov_k_mean_last": ks[-1] if ks else None}
 
 
+def run_adjoint(steps, kmax):
+    """Na8 driven by the sum-of-sines field along z (seed 7 parameters, t0 = 4,
+    s = 2; no kick): forward steps, then the reverse sweep over them with the
+    checkpointed driver.  Reports ms per forward step and per adjoint step."""
+    import numpy as np
+    import torch
+    from workloads import na8, adjoint_field_params
+    from paper_2210_14421_amd.efe import Context, make_field
+    spec = na8()
+    theta = adjoint_field_params(7, 8, (1e-3, 1e-2), (0.05, 0.5))
+    m = len(theta) // 3
+    field, keep = make_field(2, theta[:m], theta[m:2 * m], theta[2 * m:], 4.0, 2.0)
+    ctx = Context(spec, dtype="f64", kmax=kmax)
+    Psi = ctx.initial_state()
+    ctx.set_hamiltonian(Psi, 0.0, field)
+    states = [Psi.clone()]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for n in range(steps):
+        ctx.magnus_step(Psi, n * spec.dt, spec.dt, field)
+        states.append(Psi.clone())
+    torch.cuda.synchronize()
+    fwd = (time.perf_counter() - t0) / steps
+    Psibar = ctx.dipole_adjoint(states[-1], (0.0, 0.0, 1.0))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for n in range(steps - 1, -1, -1):
+        ctx.magnus_adjoint(states[n], Psibar, n * spec.dt, spec.dt, field, (0.0, 0.0, 1.0))
+        print(f"[bench] adjoint step {n}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    adj = (time.perf_counter() - t1) / steps
+    ctx.close()
+    del keep
+    return {"metric": "adjoint Magnus step time at Na8 (field-driven, dL/dmu_z = 1 at every step)",
+            "value": 1e3 * adj, "unit": "ms per adjoint step", "n_gpus": 1, "steps": steps,
+            "higher_is_better": False, "forward_ms_per_step": 1e3 * fwd, "adjoint_over_forward": adj / fwd,
+            "dtype": "f64", "data": "synthetic", "config": {"workload": "Na8, field of 8 sines (seed 7), t0 4, s 2"}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -250,7 +289,7 @@ def main():
     ap.add_argument("--kmax", type=int, default=40)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="na8", choices=["na8", "tiny", "na2", "batch"])
+    ap.add_argument("--workload", default="na8", choices=["na8", "tiny", "na2", "batch", "adjoint"])
     ap.add_argument("--mode", default="step", choices=["step", "apply"])
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
     args = ap.parse_args()
@@ -263,6 +302,9 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "batch":
         print(json.dumps(run_batch(args.steps, args.warmup, min(args.kmax, 20))))
+        return
+    if args.workload == "adjoint":
+        print(json.dumps(run_adjoint(args.steps, min(args.kmax, 24))))
         return
     spec = {"na8": na8, "tiny": tiny, "na2": lambda: na_cluster(2, seed=2)}[args.workload]()
     if args.mode == "apply":
