@@ -75,7 +75,7 @@ def traffic_summary(dtype):
     unchanged (otherwise traffic is reported as null)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "cell_apply_na8_traffic.json")
-    src = os.path.join(ROOT, "paper_2210_14421_amd", "csrc", "kernels_krylov.hip")
+    src = os.path.join(ROOT, "paper_2210_14421_amd", "csrc", "kernels_cell.hip")
     if not os.path.exists(path):
         return None
     with open(path) as f:

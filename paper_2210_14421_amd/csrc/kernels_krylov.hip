@@ -1,8 +1,8 @@
-// HIP kernels of the Krylov part of the Magnus step:
-//   Hbar X  = sum_c P_c^T Hbar_c P_c X  (cell blocks on MFMA) + enrichment coupling
-//   Lanczos recurrence with full reorthogonalisation (Sec. 2.6, eq. (AdaptiveKrylov))
-//   exp(-i tau T_k) e_1 and the a-posteriori estimate (eq. (AdaptiveKrylovErr))
-//   Krylov combination beta0 Q_k u.
+// HIP kernels of the Krylov part of the Magnus step (the cell products are in
+// kernels_cell.hip, the Lanczos vector kernels in kernels_lanczos.hip):
+//   enrichment coupling of Hbar X (Sec. 2.2-2.3) on the FP64 MFMA;
+//   exp(-i tau T_k) e_1 and the a-posteriori estimate (Sec. 2.6, eqs. (AdaptiveKrylov),
+//   (AdaptiveKrylovErr)), and the combination coefficients of a finished run.
 // Orbital blocks are node-major with ncol interleaved complex columns.
 #include <hip/hip_runtime.h>
 
@@ -16,200 +16,6 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
-
-// ---------------------------------------------------------------------------
-// Cell products Y[nodes_c] += Hbar_c X[nodes_c] for the cells of one colour
-// (no two cells of a colour share a node; the 8 colours are the parity
-// classes of the cell index and run one launch each, in order).  The first
-// colour to reach a node stores instead of adding, so Y needs no clearing
-// beforehand.  Hbar_c is symmetric, so row k of the row-major block is the
-// MFMA A-operand column k; the 16x16x4 MFMA accumulates in registers.
-// ---------------------------------------------------------------------------
-constexpr int kApplyMaxLoc = 384;   // nloc of degree <= 6 is 343
-
-template <typename T> struct Mfma;
-template <> struct Mfma<double> {
-  typedef double C;
-  typedef v4d Acc;
-  static __device__ __forceinline__ Acc mma(C a, C b, Acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-  // output register r of a lane holds row lane/16 + 4 r, column lane%16
-  static __device__ __forceinline__ int row(int kr, int r) { return kr + 4 * r; }
-};
-template <> struct Mfma<float> {
-  typedef float C;
-  typedef v4f Acc;
-  static __device__ __forceinline__ Acc mma(C a, C b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
-  // output register r of a lane holds row 4 (lane/16) + r, column lane%16
-  static __device__ __forceinline__ int row(int kr, int r) { return 4 * kr + r; }
-};
-
-// One workgroup of 8 waves per (cell, chunk of 96 columns); two workgroups
-// share a CU.  Operands pass through LDS in chunks of 8 k-rows, three chunks in
-// flight: the chunk's rows of the symmetric cell block (contiguous in memory)
-// and the gathered rows of X are copied global -> LDS by the direct-to-LDS
-// loads (global_load_lds_dwordx4, 16 B per lane at LDS base + 16 * lane), so
-// no registers hold data in flight.  Every wave issues the same number of
-// copies per chunk (padding copies land in a scratch line), which lets a
-// fixed vmcnt wait certify that the chunk has arrived before the barrier.
-// Wave w takes the M tiles (w >> 1) + 4 i and the three 16-column N tiles of
-// half (w & 1): every SIMD then carries the same number of tiles.
-constexpr int kCellWaves = 8;
-constexpr int kCellNT = 3;                  // N tiles per wave
-constexpr int kCellCols = 2 * kCellNT * 16; // columns per workgroup
-constexpr int kCellKC = 8;                  // k-rows per chunk
-constexpr int kCellNS = 3;                  // chunks in flight
-constexpr int kCellLDX = 112;               // LDS row stride of X (doubles): the 4 rows of a B read hit disjoint banks
-constexpr int kCellXStage = kCellKC * kCellLDX * 8;
-
-// s_waitcnt with vmcnt = N and no wait on the other counters (gfx9 encoding)
-template <int N>
-__device__ __forceinline__ void wait_vmcnt() {
-  static_assert(N >= 0 && N < 64, "vmcnt range");
-  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
-}
-
-typedef const void __attribute__((address_space(1))) *gptr_t;
-typedef void __attribute__((address_space(3))) *lptr_t;
-
-__device__ __forceinline__ void copy16_to_lds(const void *src, void *lds_base) {
-  __builtin_amdgcn_global_load_lds((gptr_t)src, (lptr_t)lds_base, 16, 0, 0);
-}
-
-template <typename T>
-struct CellChunk {
-  // A-chunk copies per wave per chunk, sized for the largest cell (nloc <= 384)
-  static constexpr int kAIns = (kCellKC * kApplyMaxLoc * (int)sizeof(T) + 1024 * kCellWaves - 1) / (1024 * kCellWaves);
-  static constexpr int kPer = kAIns + kCellKC / kCellWaves;   // copies per wave per chunk
-};
-
-inline size_t cell_lds_bytes(int nloc, size_t esz) {
-  const size_t aseg = (kCellKC * nloc * esz + 1023) / 1024;
-  return kCellNS * (aseg * 1024 + kCellXStage) + 1024;
-}
-
-template <typename T, int CMT>
-__global__ void __launch_bounds__(kCellWaves * 64)
-k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, const T *__restrict__ cells,
-             const double *__restrict__ X, double *__restrict__ Y, int ncolr, int64_t ldr, const int *__restrict__ any) {
-  if (any && *any == 0) return;
-  typedef typename Mfma<T>::C C;
-  typedef typename Mfma<T>::Acc Acc;
-  constexpr int kAIns = CellChunk<T>::kAIns, kPer = CellChunk<T>::kPer;
-  __shared__ int64_t rowoff[kApplyMaxLoc];
-  __shared__ unsigned char first[kApplyMaxLoc];   // this cell's colour is the first to reach the node
-  extern __shared__ __attribute__((aligned(16))) unsigned char cell_sm[];
-  const Geom &g = d.g;
-  const int nloc = g.nloc;
-  const int abytes = kCellKC * nloc * (int)sizeof(T);
-  const int aseg = (abytes + 1023) / 1024;
-  unsigned char *As = cell_sm;                                   // kCellNS * aseg KB
-  unsigned char *Xs = cell_sm + kCellNS * aseg * 1024;           // kCellNS * kCellXStage
-  unsigned char *junk = Xs + kCellNS * kCellXStage;              // 1 KB target of padding copies
-  const int ci = blockIdx.x;
-  const int col0 = blockIdx.y * kCellCols;
-  const int wcol = ncolr - col0 < kCellCols ? ncolr - col0 : kCellCols;   // columns of this chunk (even)
-  const int64_t cell = cell_list[ci];
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int kr = lane >> 4, cl = lane & 15;
-  const int mg = wave >> 1, nh = wave & 1;
-  int e[3];
-  cell_ijk(g, cell, e);
-  for (int l = tid; l < nloc; l += kCellWaves * 64) {
-    rowoff[l] = local_node(g, e, l) * ldr;
-    // colours run in the order (e_x & 1) + 2 (e_y & 1) + 4 (e_z & 1); a node on a
-    // face shared along some axis is reached first by the even cell of that axis
-    const int li[3] = {l % g.P, (l / g.P) % g.P, l / (g.P * g.P)};
-    bool later = false;
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-      const bool shared = (li[ax] == 0 && e[ax] > 0) || (li[ax] == g.p && e[ax] < g.nc[ax] - 1);
-      later |= shared && (e[ax] & 1);
-    }
-    first[l] = later ? 0 : 1;
-  }
-  // X stages start zeroed: pad columns are never copied into
-  for (int i = tid; i < kCellNS * kCellXStage / 8; i += kCellWaves * 64) ((double *)Xs)[i] = 0.0;
-  __syncthreads();
-  const unsigned char *Ag = (const unsigned char *)(cells + (int64_t)(slot0 + ci) * g.cstride);   // 16-byte aligned
-  const int64_t ablock = g.cstride * (int64_t)sizeof(T);   // padded block: copies never cross into the next one
-  const int nchunk = (nloc + kCellKC - 1) / kCellKC;
-  auto issue = [&](int kc) {
-    const int st = kc % kCellNS;
-    const int64_t abase = (int64_t)kc * abytes;
-#pragma unroll
-    for (int i = 0; i < kAIns; ++i) {
-      const int seg = wave + kCellWaves * i;
-      const int64_t off = abase + (int64_t)seg * 1024 + lane * 16;
-      const bool ok = seg < aseg && off + 16 <= ablock;
-      copy16_to_lds(Ag + (ok ? off : 0), seg < aseg ? As + (st * aseg + seg) * 1024 : junk);
-    }
-#pragma unroll
-    for (int i = 0; i < kCellKC / kCellWaves; ++i) {
-      const int r = wave + kCellWaves * i;
-      const int k = kc * kCellKC + r;
-      if (k < nloc) {
-        if (2 * lane < wcol) copy16_to_lds(X + rowoff[k] + col0 + 2 * lane, Xs + st * kCellXStage + r * kCellLDX * 8);
-      } else {
-        copy16_to_lds(X, junk);
-      }
-    }
-  };
-  const int nmt = (nloc + 15) / 16;
-  Acc acc[CMT][kCellNT];
-#pragma unroll
-  for (int i = 0; i < CMT; ++i)
-#pragma unroll
-    for (int j = 0; j < kCellNT; ++j) acc[i][j] = Acc{0, 0, 0, 0};
-#pragma unroll
-  for (int c = 0; c < kCellNS - 1; ++c)
-    if (c < nchunk) issue(c);
-  for (int kc = 0; kc < nchunk; ++kc) {
-    // this wave's copies of chunk kc are done once at most (chunks issued after it) * kPer remain
-    if (kc + 1 < nchunk) wait_vmcnt<kPer * (kCellNS - 2)>();
-    else wait_vmcnt<0>();
-    __builtin_amdgcn_s_barrier();
-    if (kc + kCellNS - 1 < nchunk) issue(kc + kCellNS - 1);
-    const int st = kc % kCellNS;
-    const T *Al = (const T *)(As + st * aseg * 1024);
-    const double *Xl = (const double *)(Xs + st * kCellXStage);
-#pragma unroll
-    for (int s4 = 0; s4 < kCellKC / 4; ++s4) {
-      const int kl = s4 * 4 + kr;
-      const bool kok = kc * kCellKC + kl < nloc;
-      C b[kCellNT];
-#pragma unroll
-      for (int j = 0; j < kCellNT; ++j) b[j] = (C)Xl[kl * kCellLDX + (nh * kCellNT + j) * 16 + cl];
-#pragma unroll
-      for (int i = 0; i < CMT; ++i) {
-        const int t = mg + 4 * i;
-        if (t < nmt) {
-          const int m = t * 16 + cl;
-          const C a = (kok && m < nloc) ? (C)Al[kl * nloc + m] : (C)0;
-#pragma unroll
-          for (int j = 0; j < kCellNT; ++j) acc[i][j] = Mfma<T>::mma(a, b[j], acc[i][j]);
-        }
-      }
-    }
-  }
-  // D layout of the 16x16 MFMA (differs between the f64 and f32 forms)
-#pragma unroll
-  for (int i = 0; i < CMT; ++i) {
-    if (mg + 4 * i >= nmt) continue;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = (mg + 4 * i) * 16 + Mfma<T>::row(kr, r);
-      if (row >= nloc) continue;
-      double *yr = Y + rowoff[row];
-      const bool f = first[row] != 0;
-#pragma unroll
-      for (int j = 0; j < kCellNT; ++j) {
-        const int col = col0 + (nh * kCellNT + j) * 16 + cl;
-        if (col < ncolr) yr[col] = f ? (double)acc[i][j][r] : yr[col] + (double)acc[i][j][r];
-      }
-    }
-  }
-}
 
 // ---------------------------------------------------------------------------
 // Enrichment coupling: Y_C[r] += G[r] X_E ;  Y_E = G^T X_C[R] + Hbar^ee X_E
@@ -524,50 +330,9 @@ k_tridiag_coef(const double *__restrict__ alpha, const double *__restrict__ beta
 
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-template <typename T, int CMT>
-void launch_apply_m(const DevData &d, const T *cells, const double *X, double *Y, int ncolr, int64_t ldr,
-                    hipStream_t s, const int *any) {
-  const unsigned ny = (unsigned)((ncolr + kCellCols - 1) / kCellCols);
-  const size_t lds = cell_lds_bytes(d.g.nloc, sizeof(T));
-  for (int c = 0; c < 8; ++c) {
-    const int cnt = d.colour_off[c + 1] - d.colour_off[c];
-    if (cnt == 0) continue;
-    const int *list = d.colour_cells + d.colour_off[c];
-    hipLaunchKernelGGL((k_cell_apply<T, CMT>), dim3((unsigned)cnt, ny), dim3(kCellWaves * 64), lds, s, d, list,
-                       d.colour_off[c], cells, X, Y, ncolr, ldr, any);
-  }
-}
-
-template <typename T>
-void launch_apply(const DevData &d, const T *cells, const double *X, double *Y, int ncolr, int64_t ldr, hipStream_t s,
-                  const int *any) {
-  const int nmt = (d.g.nloc + 15) / 16;     // M tiles per cell; wave group w >> 1 takes ceil(nmt / 4)
-  if (nmt <= 8) launch_apply_m<T, 2>(d, cells, X, Y, ncolr, ldr, s, any);
-  else if (nmt <= 16) launch_apply_m<T, 4>(d, cells, X, Y, ncolr, ldr, s, any);
-  else launch_apply_m<T, 6>(d, cells, X, Y, ncolr, ldr, s, any);
-}
-
 }  // namespace
 
 namespace k {
-
-int cell_apply_init(int nloc) {
-  const size_t l64 = cell_lds_bytes(nloc, 8), l32 = cell_lds_bytes(nloc, 4);
-  int st = 0;
-  st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<double, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l64);
-  st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<double, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l64);
-  st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<double, 6>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l64);
-  st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<float, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l32);
-  st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<float, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l32);
-  st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<float, 6>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l32);
-  return st;
-}
-
-void cell_apply(const DevData &d, const void *cells, int dtype, const double *X, double *Y, int ncolr, int64_t ldr,
-                hipStream_t s, const int *any) {
-  if (dtype == 0) launch_apply<double>(d, (const double *)cells, X, Y, ncolr, ldr, s, any);
-  else launch_apply<float>(d, (const float *)cells, X, Y, ncolr, ldr, s, any);
-}
 
 void couple_apply(const DevData &d, const double *G, const double *Hee, const double *X, double *Y, int ncolr,
                   int64_t ldr, double *scratch, hipStream_t s, const int *any) {
