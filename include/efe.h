@@ -89,9 +89,10 @@ typedef struct {
 } efe_system;
 
 typedef struct {
-  int32_t prod_dtype;      /* EFE_F64 or EFE_F32 (type of the stored cell blocks and of
-                              the cell products); EFE_BF16 is reserved and rejected
-                              with EFE_ERR_ARG                                     */
+  int32_t prod_dtype;      /* type of the stored cell blocks: EFE_F64 (FP64 products),
+                              EFE_F32 (FP32 products, FP32 accumulation) or EFE_BF16
+                              (BF16 blocks widened to FP32 products); the coupling,
+                              Lanczos, Poisson and densities stay FP64            */
   int32_t kmax;            /* maximum Krylov dimension (1..64)                    */
   double krylov_tol;       /* stop when the estimate of eq. (AdaptiveKrylovErr) <= tol * ||psi|| */
   double cg_tol;           /* Poisson: relative residual                          */

@@ -218,7 +218,7 @@ efe_status build_device(efe_ctx *ctx) {
     g.lo[i] = pl.lo[i];
     g.h[i] = pl.h[i];
   }
-  g.p = pl.p; g.P = pl.P; g.nloc = pl.nloc; g.cstride = ((int64_t)pl.nloc * pl.nloc + 3) / 4 * 4; g.qc = pl.qc; g.qe = pl.qe; g.n_nodes = pl.n_nodes;
+  g.p = pl.p; g.P = pl.P; g.nloc = pl.nloc; g.cstride = ((int64_t)pl.nloc * pl.nloc + 7) / 8 * 8; g.qc = pl.qc; g.qe = pl.qe; g.n_nodes = pl.n_nodes;
   const int P = pl.P, NP = P * (P + 1) / 2;
   // 1-D tables
   std::vector<double> tab;
@@ -283,6 +283,7 @@ efe_status build_device(efe_ctx *ctx) {
   EFE_TRY(upload(ctx, &d.occ, pl.occ));
   // enrichment
   d.ne = pl.nenr; d.nk = pl.nk; d.nt = (int)pl.tcell.size(); d.nr = pl.n_urows();
+  for (size_t t = 0; t + 1 < pl.tnu_off.size(); ++t) d.max_tnu = std::max(d.max_tnu, pl.tnu_off[t + 1] - pl.tnu_off[t]);
   EFE_TRY(upload(ctx, &d.tcell, pl.tcell));
   EFE_TRY(upload(ctx, &d.tnu_off, pl.tnu_off));
   EFE_TRY(upload(ctx, &d.tnu, pl.tnu));
@@ -378,6 +379,10 @@ efe_status build_device(efe_ctx *ctx) {
   EFE_TRY(dalloc(ctx, &ctx->kstat, 2 * std::max(1, pl.norb)));
   EFE_TRY(dalloc(ctx, &ctx->estat, 2 * std::max(1, pl.norb)));
   EFE_TRY(dalloc(ctx, &ctx->cgstat, 2));
+  if (efe::k::density_init(d.g) != 0) {
+    ctx->err = "density kernels: dynamic LDS limit not accepted";
+    return EFE_ERR_HIP;
+  }
   if (efe::k::cell_apply_init(pl.nloc) != 0) {
     ctx->err = "cell-product kernels: dynamic LDS limit not accepted";
     return EFE_ERR_HIP;
@@ -1090,7 +1095,7 @@ efe_status efe_plan_get(const efe_plan *plan, const char *name, double *out, int
 efe_status efe_setup(const efe_system *sys, const efe_options *opt, efe_ctx **out) {
   if (!sys || !opt || !out) return EFE_ERR_ARG;
   *out = nullptr;
-  if (opt->prod_dtype < 0 || opt->prod_dtype > 1 || opt->kmax < 1 || opt->kmax > 64) return EFE_ERR_ARG;
+  if (opt->prod_dtype < 0 || opt->prod_dtype > 2 || opt->kmax < 1 || opt->kmax > 64) return EFE_ERR_ARG;
   efe_ctx *ctx = new (std::nothrow) efe_ctx();
   if (!ctx) return EFE_ERR_ALLOC;
   ctx->opt = *opt;

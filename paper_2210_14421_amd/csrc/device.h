@@ -12,7 +12,7 @@ struct Geom {
   int nc[3];
   int64_t nn[3];
   int p, P, nloc;
-  int64_t cstride;   // elements between stored cell blocks: nloc^2 rounded up to 4 (16-byte aligned blocks)
+  int64_t cstride;   // elements between stored cell blocks: nloc^2 rounded up to 8 (16-byte aligned blocks)
   int qc, qe;
   double lo[3], h[3];
   int64_t n_nodes;
@@ -44,6 +44,7 @@ struct DevData {
   double *occ = nullptr;          // norb
   // enrichment
   int ne = 0, nk = 0, nt = 0;     // enrichment functions, kept directions, T-cells
+  int max_tnu = 0;                // most enrichment functions nonzero on one T-cell
   int64_t nr = 0;                 // union rows
   int *tcell = nullptr, *tnu_off = nullptr, *tnu = nullptr;
   int *tslot_of_cell = nullptr;   // n_cells, -1 if not a T-cell
@@ -91,6 +92,8 @@ void couple_apply(const DevData &d, const double *G, const double *Hee, const do
 
 // density and Poisson
 void psiE(const DevData &d, const double *X, int ncolr, int64_t ldr, double *psiE, hipStream_t s);
+// raises the dynamic LDS limit of the density kernels; 0 on success
+int density_init(const Geom &g);
 void density(const DevData &d, const double *X, int ncol, int64_t ldr, const double *psiE, double *rho,
              hipStream_t s);
 void poisson_rhs(const DevData &d, const double *rho, double *dvec, double *rhs, hipStream_t s, int lift = 1);

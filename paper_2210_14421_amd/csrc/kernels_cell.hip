@@ -30,6 +30,21 @@ template <> struct Mfma<double> {
   // output register r of a lane holds row lane/16 + 4 r, column lane%16
   static __device__ __forceinline__ int row(int kr, int r) { return kr + 4 * r; }
 };
+// BF16 cell blocks (bit patterns in uint16_t): widened to FP32 on the way into
+// the FP32 MFMA.  The product is HBM-bound, so the storage halves the traffic of
+// the blocks while X keeps FP32 operands (H Xbar stays linear in X).
+template <> struct Mfma<uint16_t> {
+  typedef float C;
+  typedef v4f Acc;
+  static __device__ __forceinline__ Acc mma(C a, C b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+  static __device__ __forceinline__ int row(int kr, int r) { return 4 * kr + r; }
+};
+
+template <typename T, typename C> __device__ __forceinline__ C widen(T v) { return (C)v; }
+template <> __device__ __forceinline__ float widen<uint16_t, float>(uint16_t v) {
+  return __uint_as_float((unsigned)v << 16);
+}
+
 template <> struct Mfma<float> {
   typedef float C;
   typedef v4f Acc;
@@ -180,7 +195,7 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
         const int t = mg + 4 * i;
         if (t < nmt) {
           const int m = t * 16 + cl;
-          const C a = (kok && m < nloc) ? (C)Al[kl * nloc + m] : (C)0;
+          const C a = (kok && m < nloc) ? widen<T, C>(Al[kl * nloc + m]) : (C)0;
 #pragma unroll
           for (int j = 0; j < kCellNT; ++j) acc[i][j] = Mfma<T>::mma(a, b[j], acc[i][j]);
         }
@@ -234,7 +249,7 @@ void launch_apply(const DevData &d, const T *cells, const double *X, double *Y, 
 namespace k {
 
 int cell_apply_init(int nloc) {
-  const size_t l64 = cell_lds_bytes(nloc, 8), l32 = cell_lds_bytes(nloc, 4);
+  const size_t l64 = cell_lds_bytes(nloc, 8), l32 = cell_lds_bytes(nloc, 4), l16 = cell_lds_bytes(nloc, 2);
   int st = 0;
   st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<double, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l64);
   st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<double, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l64);
@@ -242,13 +257,17 @@ int cell_apply_init(int nloc) {
   st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<float, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l32);
   st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<float, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l32);
   st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<float, 6>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l32);
+  st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<uint16_t, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l16);
+  st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<uint16_t, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l16);
+  st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<uint16_t, 6>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l16);
   return st;
 }
 
 void cell_apply(const DevData &d, const void *cells, int dtype, const double *X, double *Y, int ncolr, int64_t ldr,
                 hipStream_t s, const int *any) {
   if (dtype == 0) launch_apply<double>(d, (const double *)cells, X, Y, ncolr, ldr, s, any);
-  else launch_apply<float>(d, (const float *)cells, X, Y, ncolr, ldr, s, any);
+  else if (dtype == 1) launch_apply<float>(d, (const float *)cells, X, Y, ncolr, ldr, s, any);
+  else launch_apply<uint16_t>(d, (const uint16_t *)cells, X, Y, ncolr, ldr, s, any);
 }
 
 }  // namespace k

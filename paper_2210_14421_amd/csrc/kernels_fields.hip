@@ -209,6 +209,128 @@ k_coupling_partials(const DevData d, const double *__restrict__ vq, double *__re
   }
 }
 
+// The same partial sums on the FP64 16x16x4 MFMA, one workgroup of 4 waves per
+// T-cell, the points streamed through LDS in chunks of 64:
+//   part[l][nu] = sum_q B_l(q) F(q, nu),   F(q, nu) = W_q v(q) N^E_nu(q)
+//     (A operand B_l(q) = b(i_q, a_l) b(j_q, b_l) b(k_q, c_l) from the 1-D table;
+//      wave w takes the M tiles w + 4 i of the nloc node rows, all N tiles);
+//   hee[mu][nu] = sum_q N^E_mu(q) F(q, nu)  (the 3 x 3 tiles of 48 functions
+//      dealt round-robin to the waves).
+constexpr int kCpChunk = 64;
+typedef double v4d_t __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256)
+k_coupling_mfma(const DevData d, const double *__restrict__ vq, double *__restrict__ part,
+                double *__restrict__ hee_part) {
+  __shared__ double bt[16 * 8];                       // n x P (n <= 16, P <= 8)
+  __shared__ double wq[kCpChunk];
+  __shared__ double nec[48][kCpChunk + 1];
+  const Geom &g = d.g;
+  const int slot = blockIdx.x;
+  const int64_t cell = d.tcell[slot];
+  const bool enr = d.is_enr[cell] != 0;
+  const int n = enr ? g.qe : g.qc, n3 = n * n * n, P = g.P, nloc = g.nloc;
+  const double *tab = d.tab;
+  const int toB = enr ? d.to.Be : d.to.Bc, tow = enr ? d.to.wqe : d.to.wqc;
+  for (int t = threadIdx.x; t < n * P; t += blockDim.x) bt[t] = tab[toB + t];
+  const int k0 = d.tnu_off[slot], nnu = d.tnu_off[slot + 1] - k0;
+  const double *NEs = d.NE + d.tne_off[slot];
+  const int64_t q0 = d.q_off[cell];
+  const double jac = 0.125 * g.h[0] * g.h[1] * g.h[2];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kr = lane >> 4, cl = lane & 15;
+  const int nmt = (nloc + 15) / 16, nnt = (nnu + 15) / 16;
+  // node index decomposition of this lane's rows in each of its M tiles
+  int la[4], lb[4], lc[4];
+  bool lok[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int l = (wave + 4 * i) * 16 + cl;
+    lok[i] = wave + 4 * i < nmt && l < nloc;
+    la[i] = l % P;
+    lb[i] = (l / P) % P;
+    lc[i] = l / (P * P);
+  }
+  v4d_t acc[4][3], acch[3];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) acc[i][j] = v4d_t{0, 0, 0, 0};
+#pragma unroll
+  for (int j = 0; j < 3; ++j) acch[j] = v4d_t{0, 0, 0, 0};
+  for (int qc = 0; qc < n3; qc += kCpChunk) {
+    __syncthreads();
+    for (int t = threadIdx.x; t < kCpChunk; t += blockDim.x) {
+      const int q = qc + t;
+      double v = 0.0;
+      if (q < n3) {
+        const int i = q % n, j = (q / n) % n, k = q / (n * n);
+        v = jac * tab[tow + i] * tab[tow + j] * tab[tow + k] * vq[q0 + q];
+      }
+      wq[t] = v;
+    }
+    for (int t = threadIdx.x; t < 48 * kCpChunk; t += blockDim.x) {
+      const int kk = t / kCpChunk, qq = t % kCpChunk;
+      nec[kk][qq] = (kk < nnu && qc + qq < n3) ? NEs[(int64_t)kk * n3 + qc + qq] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int s4 = 0; s4 < kCpChunk / 4; ++s4) {
+      const int qq = s4 * 4 + kr, q = qc + qq;
+      const bool qok = q < n3;
+      const int qi = q % n, qj = (q / n) % n, qk = q / (n * n);
+      const double w = wq[qq];
+      double bv[3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) bv[j] = w * nec[j * 16 + cl][qq];        // F(q, nu)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if (wave + 4 * i >= nmt) continue;
+        const double a = (qok && lok[i]) ? bt[qi * P + la[i]] * bt[qj * P + lb[i]] * bt[qk * P + lc[i]] : 0.0;
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+          if (j < nnt) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[j], acc[i][j], 0, 0, 0);
+      }
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const int u = wave + 4 * j;             // tile (u / 3, u % 3) of hee
+        if (u >= nnt * nnt) continue;
+        const int mt = u / nnt, nt = u % nnt;
+        const double a = nec[mt * 16 + cl][qq];
+        const double b = w * nec[nt * 16 + cl][qq];
+        acch[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acch[j], 0, 0, 0);
+      }
+    }
+  }
+  double *ps = part + d.tpart_off[slot];
+  double *hs = hee_part + d.thee_off[slot];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if (wave + 4 * i >= nmt) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int l = (wave + 4 * i) * 16 + kr + 4 * r;
+      if (l >= nloc) continue;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const int kk = j * 16 + cl;
+        if (j < nnt && kk < nnu) ps[(int64_t)l * nnu + kk] = acc[i][j][r];
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const int u = wave + 4 * j;
+    if (u >= nnt * nnt) continue;
+    const int mt = u / nnt, nt = u % nnt;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int mu = mt * 16 + kr + 4 * r, nu = nt * 16 + cl;
+      if (mu < nnu && nu < nnu) hs[mu * nnu + nu] = acch[j][r];
+    }
+  }
+}
+
 // G[r][kappa] = D^-1/2_r sum_nu (Kce[r][nu] + sum_cells part) S[nu][kappa]  (Hbar^ce rows)
 __global__ void __launch_bounds__(64)
 k_coupling_gather(const DevData d, const double *__restrict__ part, int kinetic, double *__restrict__ G) {
@@ -361,6 +483,96 @@ k_density(const DevData d, const int *__restrict__ cell_list, int n, const doubl
       if (CROSS) rho[q0 + q] += wcross * acc[s];
       else rho[q0 + q] = acc[s];
     }
+  }
+}
+
+// Density (or cross density) on cells whose Gauss rule has P points per axis
+// (the ordinary cells): the three interpolation stages run in place on a
+// nloc x 44 LDS tile of columns (each thread owns whole lines), two passes for
+// 88 columns; the enrichment part adds sum_nu N^E_nu(q) psiE[nu] per point.
+constexpr int kDenCols = 44;
+
+template <bool CROSS>
+__global__ void __launch_bounds__(kThreads)
+k_density_sq(const DevData d, const int *__restrict__ cell_list, const double *__restrict__ X, int ncol, int64_t ldr,
+             const double *__restrict__ psiE, double *__restrict__ rho, double wcross) {
+  extern __shared__ double sm[];
+  const Geom &g = d.g;
+  const int P = g.P, nloc = g.nloc;
+  const double *tab = d.tab;
+  double *Bt = sm;                 // P*P
+  double *dm = Bt + P * P;         // nloc
+  double *occ = dm + nloc;         // 128
+  double *u = occ + 128;           // nloc * kDenCols
+  const int64_t cell = cell_list[blockIdx.x];
+  int e[3];
+  cell_ijk(g, cell, e);
+  for (int t = threadIdx.x; t < P * P; t += blockDim.x) Bt[t] = tab[d.to.Bc + t];
+  for (int t = threadIdx.x; t < nloc; t += blockDim.x) dm[t] = d.Dm12[local_node(g, e, t)];
+  if (!CROSS)
+    for (int t = threadIdx.x; t < ncol; t += blockDim.x) occ[t] = d.occ[t];
+  const int slot = d.tslot_of_cell[cell];
+  const int k0 = slot >= 0 ? d.tnu_off[slot] : 0, nnu = slot >= 0 ? d.tnu_off[slot + 1] - k0 : 0;
+  const double *NEs = slot >= 0 ? d.NE + d.tne_off[slot] : nullptr;
+  const int ncolr = 2 * ncol;
+  double acc[2] = {0.0, 0.0};       // points threadIdx.x and threadIdx.x + kThreads (nloc <= 512)
+  __syncthreads();
+  for (int col0 = 0; col0 < ncolr; col0 += kDenCols) {
+    const int w = ncolr - col0 < kDenCols ? ncolr - col0 : kDenCols;
+    for (int t = threadIdx.x; t < nloc * kDenCols; t += blockDim.x) {
+      const int l = t / kDenCols, f = t % kDenCols;
+      u[t] = f < w ? dm[l] * X[local_node(g, e, l) * ldr + col0 + f] : 0.0;
+    }
+    __syncthreads();
+    const int nline = nloc / P;
+    for (int ax = 0; ax < 3; ++ax) {
+      const int stride = ax == 0 ? 1 : (ax == 1 ? P : P * P);
+      for (int t = threadIdx.x; t < nline * kDenCols; t += blockDim.x) {
+        const int L = t / kDenCols, f = t % kDenCols;
+        const int base = ax == 0 ? L * P : (ax == 1 ? (L % P) + (L / P) * P * P : L);
+        double in[8];
+        for (int j = 0; j < P; ++j) in[j] = u[(base + j * stride) * kDenCols + f];
+        for (int i = 0; i < P; ++i) {
+          double v = 0.0;
+          for (int j = 0; j < P; ++j) v += Bt[i * P + j] * in[j];
+          u[(base + i * stride) * kDenCols + f] = v;
+        }
+      }
+      __syncthreads();
+    }
+    for (int h = 0; h < 2; ++h) {
+      const int q = threadIdx.x + h * kThreads;
+      if (q >= nloc) continue;
+      double val[kDenCols];
+#pragma unroll
+      for (int f = 0; f < kDenCols; ++f) val[f] = u[q * kDenCols + f];
+      for (int kk = 0; kk < nnu; ++kk) {
+        const double nev = NEs[(int64_t)kk * nloc + q];
+        const double *pe = psiE + (int64_t)d.tnu[k0 + kk] * ncolr + col0;
+#pragma unroll
+        for (int f = 0; f < kDenCols; ++f)
+          if (f < w) val[f] += nev * pe[f];
+      }
+      double a = 0.0;
+      if (CROSS) {
+#pragma unroll
+        for (int f = 0; f + 3 < kDenCols; f += 4)
+          if (f + 3 < w) a += val[f] * val[f + 3] - val[f + 1] * val[f + 2];
+      } else {
+#pragma unroll
+        for (int f = 0; f + 1 < kDenCols; f += 2)
+          if (f + 1 < w) a += occ[(col0 + f) / 2] * (val[f] * val[f] + val[f + 1] * val[f + 1]);
+      }
+      acc[h] += a;
+    }
+    __syncthreads();
+  }
+  const int64_t q0 = d.q_off[cell];
+  for (int h = 0; h < 2; ++h) {
+    const int q = threadIdx.x + h * kThreads;
+    if (q >= nloc) continue;
+    if (CROSS) rho[q0 + q] += wcross * acc[h];
+    else rho[q0 + q] = acc[h];
   }
 }
 
@@ -710,6 +922,10 @@ void rebuild_cells(const DevData &d, int mode, const double *rho, const double *
 
 void coupling_partials(const DevData &d, const double *vq, double *part, double *hee_part, hipStream_t s) {
   if (d.nt == 0) return;
+  if (d.g.qe <= 16 && d.g.qc <= 16 && d.g.P <= 8 && d.max_tnu <= 48) {
+    hipLaunchKernelGGL(k_coupling_mfma, dim3(d.nt), dim3(256), 0, s, d, vq, part, hee_part);
+    return;
+  }
   const int n = d.g.qe > d.g.qc ? d.g.qe : d.g.qc, P = d.g.P;
   size_t lds = ((size_t)n * P + 2 * n * n * n + n * n * P + n * P * P + d.g.nloc) * sizeof(double);
   hipLaunchKernelGGL(k_coupling_partials, dim3(d.nt), dim3(kThreads), lds, s, d, vq, part, hee_part);
@@ -732,6 +948,19 @@ void psiE(const DevData &d, const double *X, int ncolr, int64_t ldr, double *out
   hipLaunchKernelGGL(k_psiE, dim3(nblocks((int64_t)d.ne * ncolr, 128)), dim3(128), 0, s, d, X, ncolr, ldr, out);
 }
 
+static size_t density_sq_lds(const Geom &g) {
+  return ((size_t)g.P * g.P + g.nloc + 128 + (size_t)g.nloc * kDenCols) * sizeof(double);
+}
+
+int density_init(const Geom &g) {
+  int st = 0;
+  st |= (int)hipFuncSetAttribute((const void *)k_density_sq<false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)density_sq_lds(g));
+  st |= (int)hipFuncSetAttribute((const void *)k_density_sq<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)density_sq_lds(g));
+  return st;
+}
+
 template <bool CROSS>
 static void density_launch(const DevData &d, const double *X, int ncol, int64_t ldr, const double *psiE, double *rho,
                            double wcross, hipStream_t s) {
@@ -741,6 +970,11 @@ static void density_launch(const DevData &d, const double *X, int ncol, int64_t 
     if (nc == 0) continue;
     int n = cls ? d.g.qe : d.g.qc, P = d.g.P;
     const int *list = cls ? d.cells_enr : d.cells_ord;
+    if (n == P && d.g.nloc <= 2 * kThreads && ncol <= 128) {
+      hipLaunchKernelGGL((k_density_sq<CROSS>), dim3(nc), dim3(kThreads), density_sq_lds(d.g), s, d, list, X, ncol,
+                         ldr, psiE, rho, wcross);
+      continue;
+    }
     size_t lds = ((size_t)n * P + d.g.nloc + (size_t)d.g.nloc * F + (size_t)P * P * n * F + (size_t)P * n * n * F + ncol) *
                  sizeof(double);
     int n3 = n * n * n;

@@ -78,6 +78,30 @@ def test_apply_H_parity(env):
     assert np.abs(Y[:model.mesh.n_nodes][model.bnd]).max() == 0.0
 
 
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-6), ("bf16", 1e-2)])
+def test_apply_H_reduced_precision(env, dtype, tol):
+    """FP32 blocks (FP32 products and accumulation) and BF16 blocks (widened to
+    FP32): Hbar X against the FP64 oracle.  The bound is the storage rounding
+    (2^-24 and 2^-9 relative per entry) amplified by the cancellation in the
+    kinetic rows."""
+    from paper_2210_14421_amd.efe import Context
+    spec, model, X0, _ = env
+    ctx = Context(spec, dtype=dtype, kmax=64)
+    try:
+        ctx.set_hamiltonian(_dev(X0), 0.0)
+        rng = np.random.default_rng(11)
+        X = np.zeros((model.n_rows, spec.norb), dtype=np.complex128)
+        act = np.concatenate([model.interior, model.mesh.n_nodes + np.arange(model.nk)])
+        X[act] = rng.standard_normal((len(act), spec.norb)) + 1j * rng.standard_normal((len(act), spec.norb))
+        Y = ctx.apply_H(_dev(X)).cpu().numpy()
+        ref = model.hamiltonian_from_density(model.density(X0)) @ X
+        e = _rel(Y, ref)
+        print(f"{dtype} Hbar X rel err {e:.2e}")
+        assert e < tol
+    finally:
+        ctx.close()
+
+
 def test_lanczos_parity(env):
     from oracle.propagate import lanczos_expm
     spec, model, X0, ctx = env
