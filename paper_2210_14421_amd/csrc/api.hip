@@ -53,6 +53,7 @@ struct efe_ctx {
   double *cg[7] = {nullptr};
   double *part = nullptr, *hee_part = nullptr, *G = nullptr, *Hee_raw = nullptr, *Hbar_ee = nullptr;
   double *psiE = nullptr, *red = nullptr, *small = nullptr, *couple_scr = nullptr;
+  efe::k::DenWork den, adj_den;   // density workspaces (forward columns; adjoint column pairs)
   int64_t red_len = 0;
   double *alpha = nullptr, *beta = nullptr, *beta0 = nullptr, *errv = nullptr, *ubuf = nullptr;
   int *active = nullptr, *kused = nullptr, *kforce = nullptr, *need = nullptr, *anyflag = nullptr;
@@ -305,6 +306,13 @@ efe_status build_device(efe_ctx *ctx) {
   EFE_TRY(upload(ctx, &d.urow_cnt, pl.urow_cnt));
   EFE_TRY(upload(ctx, &d.urow_pair, pl.urow_pair));
   EFE_TRY(upload(ctx, &d.S, pl.S));
+  EFE_TRY(upload(ctx, &d.C, pl.c));
+  EFE_TRY(upload(ctx, &d.node_urow, pl.node_urow));
+  EFE_TRY(upload(ctx, &d.ta_off, pl.ta_off));
+  EFE_TRY(upload(ctx, &d.ta_nu, pl.ta_nu));
+  EFE_TRY(upload(ctx, &d.tna_off, pl.tna_off));
+  EFE_TRY(upload(ctx, &d.NA, pl.NA));
+  for (size_t t = 0; t + 1 < pl.ta_off.size(); ++t) d.max_ta = std::max(d.max_ta, pl.ta_off[t + 1] - pl.ta_off[t]);
   EFE_TRY(upload(ctx, &d.Kce, pl.Kce));
   EFE_TRY(upload(ctx, &d.Kee, pl.Kee));
   for (int dd = 0; dd < 3; ++dd) {
@@ -343,10 +351,14 @@ efe_status build_device(efe_ctx *ctx) {
   EFE_TRY(dalloc(ctx, &ctx->Hee_raw, (int64_t)d.ne * d.ne));
   EFE_TRY(dalloc(ctx, &ctx->Hbar_ee, (int64_t)d.nk * d.nk));
   EFE_TRY(dalloc(ctx, &ctx->psiE, (int64_t)d.ne * ctx->ncolr));
+  if (efe::k::density_folded_ok(d)) {
+    EFE_TRY(dalloc(ctx, &ctx->den.U, std::max<int64_t>(1, d.nr * ctx->ncolr)));
+    EFE_TRY(dalloc(ctx, &ctx->den.part, std::max<int64_t>(1, efe::k::density_part_size(d, ctx->ncolr))));
+  }
   ctx->red_len = std::max<int64_t>({(int64_t)efe::k::kDotBlocksMax * (ctx->kmax + 1) * ctx->ncolr, pl.n_cells * 3, 4096});
   EFE_TRY(dalloc(ctx, &ctx->red, ctx->red_len));
   EFE_TRY(dalloc(ctx, &ctx->small, (int64_t)ctx->kmax * ctx->ncolr + 64));
-  EFE_TRY(dalloc(ctx, &ctx->couple_scr, (int64_t)efe::k::kCouplePartials * std::max(1, d.nk) * ctx->ncolr));
+  EFE_TRY(dalloc(ctx, &ctx->couple_scr, (int64_t)efe::k::kCoupleScratch * std::max(1, d.nk) * ctx->ncolr));
   EFE_TRY(dalloc(ctx, &ctx->alpha, (int64_t)ctx->kmax * pl.norb));
   EFE_TRY(dalloc(ctx, &ctx->beta, (int64_t)ctx->kmax * pl.norb));
   EFE_TRY(dalloc(ctx, &ctx->beta0, pl.norb));
@@ -509,7 +521,7 @@ efe_status density_packed(efe_ctx *ctx, const double *X, double *rho) {
   const DevData &d = ctx->d;
   tstart(ctx, 4);
   efe::k::psiE(d, X, ctx->ncolr, ctx->ncolr, ctx->psiE, ctx->stream);
-  efe::k::density(d, X, ctx->norb, ctx->ncolr, ctx->psiE, rho, ctx->stream);
+  efe::k::density(d, X, ctx->norb, ctx->ncolr, ctx->psiE, rho, ctx->den, ctx->stream);
   tstop(ctx, 4);
   return check_launch(ctx, "density");
 }
@@ -923,6 +935,10 @@ efe_status ensure_adjoint_buffers(efe_ctx *ctx) {
   EFE_TRY(dalloc(ctx, &ctx->adj_phib, pl.n_nodes));
   EFE_TRY(dalloc(ctx, &ctx->adj_zero, std::max<int64_t>(pl.n_nodes, pl.n_quad)));
   EFE_TRY(dalloc(ctx, &ctx->adj_psiE, (int64_t)std::max(1, ctx->d.ne) * 2 * ctx->ncolr));
+  if (efe::k::density_folded_ok(ctx->d)) {
+    EFE_TRY(dalloc(ctx, &ctx->adj_den.U, std::max<int64_t>(1, ctx->d.nr * 2 * ctx->ncolr)));
+    EFE_TRY(dalloc(ctx, &ctx->adj_den.part, std::max<int64_t>(1, efe::k::density_part_size(ctx->d, 2 * ctx->ncolr))));
+  }
   EFE_TRY(dalloc(ctx, &ctx->adj_coef, (int64_t)kAdjNodes * ctx->kmax * ctx->ncolr));
   std::vector<double> f2(std::max(1, pl.norb));
   for (int a = 0; a < pl.norb; ++a) f2[a] = 2.0 * pl.occ[a];
@@ -947,7 +963,7 @@ efe_status adj_cross(efe_ctx *ctx, const double *Xbar, int kx, const double *sg,
     efe::k::lz_combine(Xbar, ctx->Q, bs, kx, ctx->adj_coef + (int64_t)g * ctx->kmax * 2 * no, ctx->adj_W1, nr, no, s);
     efe::k::interleave(ctx->adj_W1, ctx->adj_B + (int64_t)g * ctx->blk, ctx->adj_Z, nr, no, s);
     efe::k::psiE(ctx->d, ctx->adj_Z, 4 * no, 4 * no, ctx->adj_psiE, s);
-    efe::k::cross_density(ctx->d, ctx->adj_Z, no, ctx->adj_psiE, wg[g], ctx->adj_u, s);
+    efe::k::cross_density(ctx->d, ctx->adj_Z, no, ctx->adj_psiE, wg[g], ctx->adj_u, ctx->adj_den, s);
   }
   return check_launch(ctx, "adjoint cross density");
 }

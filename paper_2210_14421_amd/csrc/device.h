@@ -56,6 +56,12 @@ struct DevData {
   int64_t *urow_node = nullptr;
   int *urow_cnt = nullptr, *urow_pair = nullptr;
   double *S = nullptr;            // ne x nk
+  double *C = nullptr;            // nr x ne: orthogonalisation coefficients c on the union rows
+  int *node_urow = nullptr;       // n_nodes: union row of the node, -1
+  int *ta_off = nullptr, *ta_nu = nullptr;   // per slot: enrichment functions with an atomic part there
+  int64_t *tna_off = nullptr;     // per slot: offset of its atomic values
+  double *NA = nullptr;           // s_nu N^A_nu(q) at the points of those slots
+  int max_ta = 0;                 // most atomic functions on one T-cell
   double *Kce = nullptr;          // nr x ne
   double *Kee = nullptr;          // ne x ne
   // Poisson
@@ -68,7 +74,7 @@ struct DevData {
 namespace k {
 
 constexpr int kDotBlocksMax = 1024;   // partial blocks of the column reductions
-constexpr int kCouplePartials = 2048; // partial sums of the enrichment-row coupling product
+constexpr int kCoupleScratch = 520;  // n_k x ncolr blocks: workgroup partials and first-level sums of Y_E
 
 void zero(double *p, int64_t n, hipStream_t s);
 void copy_rows(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t nrows, int ncolr, hipStream_t s);
@@ -91,15 +97,22 @@ void couple_apply(const DevData &d, const double *G, const double *Hee, const do
                   int ncolr, int64_t ldr, double *scratch, hipStream_t s, const int *any = nullptr);
 
 // density and Poisson
+// workspace of the density: U holds the folded union rows (n_R x ncolr), part
+// the per-pass partial sums on the enrichment cells (density_part_size doubles)
+struct DenWork {
+  double *U = nullptr, *part = nullptr;
+};
+bool density_folded_ok(const DevData &d);
+int64_t density_part_size(const DevData &d, int ncolr);
 void psiE(const DevData &d, const double *X, int ncolr, int64_t ldr, double *psiE, hipStream_t s);
 // raises the dynamic LDS limit of the density kernels; 0 on success
 int density_init(const Geom &g);
 void density(const DevData &d, const double *X, int ncol, int64_t ldr, const double *psiE, double *rho,
-             hipStream_t s);
+             const DenWork &w, hipStream_t s);
 void poisson_rhs(const DevData &d, const double *rho, double *dvec, double *rhs, hipStream_t s, int lift = 1);
 // adjoint pieces
 void cross_density(const DevData &d, const double *Z, int npair, const double *psiE, double w, double *out,
-                   hipStream_t s);
+                   const DenWork &work, hipStream_t s);
 void adj_potential(const DevData &d, const double *phibar, const double *rho, const double *u, double tau, int xc,
                    const double mubar[3], double a, const double *gin, double *out, hipStream_t s);
 void axpy_cols(double *out, const double *Y, const double *sc, double s0, int64_t nrows, int ncol, hipStream_t s);

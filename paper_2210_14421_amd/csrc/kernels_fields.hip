@@ -576,6 +576,324 @@ k_density_sq(const DevData d, const int *__restrict__ cell_list, const double *_
   }
 }
 
+// ---------------------------------------------------------------------------
+// Density through folded nodal values.  The orthogonalised enrichment function
+// is N^E_nu = s_nu N^A_nu - sum_i c_{i nu} N_i (Sec. 2.2), so
+//   psi(q) = sum_i N_i(q) u_i + sum_{nu atomic on the cell} s_nu N^A_nu(q) psiE_nu,
+//   u_i = D_i^-1/2 X_i - sum_nu c_{i nu} psiE_nu.
+// The correction of u is nonzero on the union rows only: k_fold_rows writes
+// those rows into U (n_R x ncolr); every other node reads D^-1/2 X.  The
+// ordinary cells then need no enrichment term at all, and the enrichment
+// cells only the atomic parts (stored once, at their points).
+// ---------------------------------------------------------------------------
+// U = D^-1/2 X[R] - C psiE on the FP64 16x16x4 MFMA: one wave per block walks
+// a contiguous range of 16-row tiles of R for 96 columns (blockIdx.y);
+// A(i, k) = C[r0 + i][k], B(k, j) = psiE[k][j], the epilogue adds the scaled rows.
+constexpr int kFoldWaves = 4096;
+constexpr int kFoldNT = 6;
+
+__global__ void __launch_bounds__(64)
+k_fold_rows(const DevData d, const double *__restrict__ X, int ncolr, int64_t ldr, const double *__restrict__ psiE,
+            double *__restrict__ U, int64_t tiles_per_wave) {
+  typedef double v4d __attribute__((ext_vector_type(4)));
+  const int ne = d.ne;
+  const int64_t nr = d.nr;
+  const int lane = threadIdx.x, kr = lane >> 4, cl = lane & 15;
+  const int n0 = blockIdx.y * kFoldNT * 16;
+  const int64_t ntiles = (nr + 15) / 16;
+  const int64_t t_begin = (int64_t)blockIdx.x * tiles_per_wave;
+  const int64_t t_end = t_begin + tiles_per_wave < ntiles ? t_begin + tiles_per_wave : ntiles;
+  int col[kFoldNT];
+  bool cok[kFoldNT];
+#pragma unroll
+  for (int nt = 0; nt < kFoldNT; ++nt) {
+    col[nt] = n0 + nt * 16 + cl;
+    cok[nt] = col[nt] < ncolr;
+  }
+  const int nks = (ne + 3) / 4;
+  for (int64_t t = t_begin; t < t_end; ++t) {
+    const int64_t r0 = t * 16;
+    v4d acc[kFoldNT];
+#pragma unroll
+    for (int nt = 0; nt < kFoldNT; ++nt) acc[nt] = v4d{0, 0, 0, 0};
+    const int64_t ra = r0 + cl;
+    const bool rok = ra < nr;
+    for (int ks = 0; ks < nks; ++ks) {
+      const int k = ks * 4 + kr;
+      const bool kok = k < ne;
+      const double a = (rok && kok) ? d.C[ra * ne + k] : 0.0;
+#pragma unroll
+      for (int nt = 0; nt < kFoldNT; ++nt) {
+        const double bv = (kok && cok[nt]) ? psiE[(int64_t)k * ncolr + col[nt]] : 0.0;
+        acc[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[nt], 0, 0, 0);
+      }
+    }
+    // output register r of a lane holds row kr + 4 r, column cl
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = r0 + kr + 4 * r;
+      if (row >= nr) continue;
+      const int64_t node = d.urow_node[row];
+      const double dm = d.Dm12[node];
+      const double *xr = X + node * ldr;
+      double *ur = U + row * ncolr;
+#pragma unroll
+      for (int nt = 0; nt < kFoldNT; ++nt)
+        if (cok[nt]) ur[col[nt]] = dm * xr[col[nt]] - acc[nt][r];
+    }
+  }
+}
+
+// Density (or cross density) on the cells of one class, NP = P GLL nodes and N
+// Gauss points per axis, sum-factorised in passes of F = 8 NFG columns.
+//   stage X:  items (c, b, f) load the x-line of folded nodal values and
+//             interpolate it to t1[c][b][i][f] (LDS, row stride FS);
+//   stage YZ: lanes (j, i, fg) contract t1 along y into t2[c][f] for their 8
+//             columns (registers), then along z to the N points (i, j, k), add
+//             the atomic part, and sum occupation-weighted squares (or the
+//             cross term) over their columns; the NFG lanes of one (j, i) are
+//             adjacent and are reduced by shuffles.
+// INWG: one workgroup per cell loops over the passes and keeps the point sums
+// in registers.  Otherwise one workgroup per (cell, pass) writes a partial
+// per pass (part[pass][cell index][q], summed by k_den_sum).  Workgroup b runs
+// on XCD b mod 8; each XCD takes a contiguous chunk of the cell list and the
+// passes of a cell are consecutive workgroups there, so the cell's atomic
+// values and the nodes it shares with its neighbours come from L2 after the
+// first read.
+// CROSS: the columns hold pairs (a, b); the point value is sum Im(conj(a) b).
+template <int NP, int N, int NFG, bool INWG, bool CROSS>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3)))
+k_den(const DevData d, const int *__restrict__ cell_list, int ncells, const double *__restrict__ X, int ncol,
+      int64_t ldr, const double *__restrict__ U, const double *__restrict__ psiE, double *__restrict__ out,
+      double *__restrict__ part, int npass, double wcross) {
+  constexpr int F = 8 * NFG, F2 = F / 2, FS = F + 2, NL = NP * NP * NP, N3 = N * N * N;
+  constexpr int NITEM = NP * NP * F2, NIT = (NITEM + kThreads - 1) / kThreads;
+  constexpr int kMaxA = 48;
+  __shared__ double Bt[N * NP];
+  __shared__ __attribute__((aligned(16))) double t1[NP * NP * N * FS];
+  __shared__ __attribute__((aligned(16))) double psA[INWG ? 2 : kMaxA * F];
+  __shared__ int64_t loff[NL];
+  __shared__ double lsc[NL];   // D^-1/2 of the node, or 1 where the value comes from U
+  __shared__ int lur[NL];
+  __shared__ double locc[CROSS ? 1 : 128];
+  const Geom &g = d.g;
+  const int tid = threadIdx.x;
+  const int ncolr = 2 * ncol;
+  if (!CROSS)
+    for (int t = tid; t < 128; t += kThreads) locc[t] = t < ncol ? d.occ[t] : 0.0;
+  int ci, pass0, pass1;
+  if (INWG) {
+    ci = blockIdx.x;
+    pass0 = 0;
+    pass1 = npass;
+  } else {
+    // XCD x takes the cells [x chunk, (x + 1) chunk) of the list (neighbours share nodes in L2)
+    const int b = blockIdx.x, xcd = b & 7, sl = b >> 3, chunk = (ncells + 7) / 8;
+    const int cl = sl / npass;
+    ci = xcd * chunk + cl;
+    pass0 = sl % npass;
+    pass1 = pass0 + 1;
+    if (cl >= chunk || ci >= ncells) return;
+  }
+  const int64_t cell = cell_list[ci];
+  int e[3];
+  cell_ijk(g, cell, e);
+  const int toB = N == NP ? d.to.Bc : d.to.Be;
+  for (int t = tid; t < N * NP; t += kThreads) Bt[t] = d.tab[toB + t];
+  for (int l = tid; l < NL; l += kThreads) {
+    const int64_t node = local_node(g, e, l);
+    const int ur = d.nr > 0 ? d.node_urow[node] : -1;
+    loff[l] = node * ldr;
+    lur[l] = ur;
+    lsc[l] = ur >= 0 ? 1.0 : d.Dm12[node];
+  }
+  int na = 0;
+  const double *NAc = nullptr;
+  int ta0 = 0;
+  if (!INWG) {
+    const int slot = d.tslot_of_cell[cell];
+    if (slot >= 0) {
+      ta0 = d.ta_off[slot];
+      na = d.ta_off[slot + 1] - ta0;
+      NAc = d.NA + d.tna_off[slot];
+    }
+  }
+  // stage-YZ lane
+  const int fg = tid % NFG, ij = tid / NFG, jj = ij / N, ii = ij % N;
+  (void)NL;
+  const bool yz = ij < N * N;
+  double acc[INWG ? N : 1];
+#pragma unroll
+  for (int k = 0; k < (INWG ? N : 1); ++k) acc[k] = 0.0;
+  __syncthreads();
+  double Bj[NP];
+#pragma unroll
+  for (int b = 0; b < NP; ++b) Bj[b] = yz ? Bt[jj * NP + b] : 0.0;
+  for (int pass = pass0; pass < pass1; ++pass) {
+    const int c0 = pass * F;
+    if (!INWG)
+      for (int t = tid; t < ((na + 7) & ~7) * F; t += kThreads) {
+        const int a = t / F, f = t % F;
+        psA[t] = (a < na && c0 + f < ncolr) ? psiE[(int64_t)d.ta_nu[ta0 + a] * ncolr + c0 + f] : 0.0;
+      }
+    // stage X: items (c b, column pair); every load of the thread first
+    double2 u[NIT][NP];
+#pragma unroll
+    for (int r = 0; r < NIT; ++r) {
+      const int it = tid + r * kThreads;
+      const int cb = it / F2, col = c0 + 2 * (it % F2);
+      const bool ok = it < NITEM && col < ncolr;
+#pragma unroll
+      for (int a = 0; a < NP; ++a) {
+        const int l = a + NP * cb;
+        double2 v = make_double2(0.0, 0.0);
+        if (ok) {
+          const int ur = lur[l];
+          const double *src = ur >= 0 ? U + (int64_t)ur * ncolr + col : X + loff[l] + col;
+          v = *(const double2 *)src;
+        }
+        u[r][a] = v;
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < NIT; ++r) {
+      const int it = tid + r * kThreads;
+      if (it >= NITEM) continue;
+      const int cb = it / F2, h = it % F2;
+      double sc[NP];
+#pragma unroll
+      for (int a = 0; a < NP; ++a) sc[a] = lsc[a + NP * cb];
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        double2 v = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int a = 0; a < NP; ++a) {
+          const double bb = Bt[i * NP + a] * sc[a];
+          v.x += bb * u[r][a].x;
+          v.y += bb * u[r][a].y;
+        }
+        *(double2 *)(t1 + (cb * N + i) * FS + 2 * h) = v;
+        __builtin_amdgcn_sched_barrier(0);   // keeps the table reads of one point at a time in registers
+      }
+    }
+    __syncthreads();
+    if (yz) {
+      double t2[NP][8];
+#pragma unroll
+      for (int c = 0; c < NP; ++c) {
+#pragma unroll
+        for (int f = 0; f < 8; ++f) t2[c][f] = 0.0;
+#pragma unroll
+        for (int b = 0; b < NP; ++b) {
+          const double2 *src = (const double2 *)(t1 + ((c * NP + b) * N + ii) * FS + fg * 8);
+#pragma unroll
+          for (int f2 = 0; f2 < 4; ++f2) {
+            const double2 x = src[f2];
+            t2[c][2 * f2] += Bj[b] * x.x;
+            t2[c][2 * f2 + 1] += Bj[b] * x.y;
+          }
+          // without the fence the scheduler hoists all NP^2 row reads (8 NP^2 registers)
+          if (b & 1) __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+      // weights of the lane's four complex columns (occupations, or 1 per complete pair)
+      const int cc0 = (c0 + fg * 8) / 2;
+      double w[4];
+#pragma unroll
+      for (int o = 0; o < 4; ++o) {
+        const int cc = cc0 + o;
+        if (CROSS) w[o] = (o % 2 == 0 && cc + 1 < ncol) ? 1.0 : 0.0;
+        else w[o] = locc[cc < 128 ? cc : 127];
+      }
+      auto point = [&](int k) -> double {
+        double v[8];
+#pragma unroll
+        for (int f = 0; f < 8; ++f) v[f] = 0.0;
+#pragma unroll
+        for (int c = 0; c < NP; ++c) {
+          const double bk = Bt[k * NP + c];
+#pragma unroll
+          for (int f = 0; f < 8; ++f) v[f] += bk * t2[c][f];
+        }
+        if (NAc) {
+          // atomic values in groups of eight loads in flight (psA rows past na are zero)
+          const int q = ii + N * (jj + N * k);
+          for (int a0 = 0; a0 < na; a0 += 8) {
+            double av[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) av[u] = NAc[(int64_t)(a0 + u < na ? a0 + u : a0) * N3 + q];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+              const double2 *ps = (const double2 *)(psA + (a0 + u) * F + fg * 8);
+#pragma unroll
+              for (int f2 = 0; f2 < 4; ++f2) {
+                const double2 x = ps[f2];
+                v[2 * f2] += av[u] * x.x;
+                v[2 * f2 + 1] += av[u] * x.y;
+              }
+            }
+          }
+        }
+        double r = 0.0;
+        if (CROSS) {
+#pragma unroll
+          for (int pp = 0; pp < 2; ++pp) r += w[2 * pp] * (v[4 * pp] * v[4 * pp + 3] - v[4 * pp + 1] * v[4 * pp + 2]);
+        } else {
+#pragma unroll
+          for (int o = 0; o < 4; ++o) r += w[o] * (v[2 * o] * v[2 * o] + v[2 * o + 1] * v[2 * o + 1]);
+        }
+        return r;
+      };
+      if (INWG) {
+#pragma unroll
+        for (int k = 0; k < (INWG ? N : 1); ++k) acc[k] += point(k);
+      } else {
+        // the NFG lanes of (j, i) are adjacent and all inside this branch
+        double *pp = part + ((int64_t)pass * ncells + ci) * N3 + ii + N * jj;
+#pragma unroll 1
+        for (int k = 0; k < N; ++k) {
+          double r = point(k);
+#pragma unroll
+          for (int m = 1; m < NFG; m <<= 1) r += __shfl_xor(r, m);
+          if (fg == 0) pp[N * N * k] = r;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (INWG) {
+#pragma unroll
+    for (int k = 0; k < (INWG ? N : 1); ++k) {
+#pragma unroll
+      for (int m = 1; m < NFG; m <<= 1) acc[k] += __shfl_xor(acc[k], m);
+    }
+    if (yz && fg == 0) {
+      const int64_t q0 = d.q_off[cell];
+#pragma unroll
+      for (int k = 0; k < (INWG ? N : 1); ++k) {
+        const int64_t q = q0 + ii + N * (jj + N * k);
+        if (CROSS) out[q] += wcross * acc[k];
+        else out[q] = acc[k];
+      }
+    }
+  }
+}
+
+// out[q] = sum over passes of the partials (fixed order), or += w * that sum
+template <bool CROSS>
+__global__ void k_den_sum(const DevData d, const int *__restrict__ cell_list, int ncells, int n3,
+                          const double *__restrict__ part, int npass, double *__restrict__ out, double wcross) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tot = (int64_t)ncells * n3;
+  if (t >= tot) return;
+  const int ci = (int)(t / n3), q = (int)(t - (int64_t)ci * n3);
+  double s = 0.0;
+  for (int p = 0; p < npass; ++p) s += part[p * tot + t];
+  const int64_t o = d.q_off[cell_list[ci]] + q;
+  if (CROSS) out[o] += wcross * s;
+  else out[o] = s;
+}
+
 // psiE[nu][col] = sum_kappa S[nu][kappa] X[n_nodes + kappa][col]
 __global__ void k_psiE(const DevData d, const double *__restrict__ X, int ncolr, int64_t ldr, double *__restrict__ out) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -962,8 +1280,8 @@ int density_init(const Geom &g) {
 }
 
 template <bool CROSS>
-static void density_launch(const DevData &d, const double *X, int ncol, int64_t ldr, const double *psiE, double *rho,
-                           double wcross, hipStream_t s) {
+static void density_launch_generic(const DevData &d, const double *X, int ncol, int64_t ldr, const double *psiE,
+                                   double *rho, double wcross, hipStream_t s) {
   constexpr int NCC = 4, F = 2 * NCC;
   for (int cls = 0; cls < 2; ++cls) {
     int nc = cls ? d.n_enr : d.n_ord;
@@ -996,13 +1314,72 @@ static void density_launch(const DevData &d, const double *X, int ncol, int64_t 
   }
 }
 
-void density(const DevData &d, const double *X, int ncol, int64_t ldr, const double *psiE, double *rho, hipStream_t s) {
-  density_launch<false>(d, X, ncol, ldr, psiE, rho, 0.0, s);
+constexpr int kDenOrdGroups = 2;   // 8-column groups per pass on ordinary cells
+
+inline int den_passes(int ncolr, int groups) { return (ncolr + 8 * groups - 1) / (8 * groups); }
+
+template <int NP, int N, int NFG, bool CROSS>
+static void den_class(const DevData &d, const int *list, int ncells, const double *X, int ncol, int64_t ldr,
+                      const double *psiE, double *rho, double wcross, const double *U, double *part, hipStream_t s) {
+  if (ncells == 0) return;
+  const int np = den_passes(2 * ncol, NFG);
+  const unsigned nb = (unsigned)(8 * ((ncells + 7) / 8) * np);
+  hipLaunchKernelGGL((k_den<NP, N, NFG, false, CROSS>), dim3(nb), dim3(kThreads), 0, s, d, list, ncells, X, ncol,
+                     ldr, U, psiE, rho, part, np, wcross);
+  constexpr int N3 = N * N * N;
+  hipLaunchKernelGGL((k_den_sum<CROSS>), dim3(nblocks((int64_t)ncells * N3, 256)), dim3(256), 0, s, d, list, ncells,
+                     N3, part, np, rho, wcross);
 }
 
-void cross_density(const DevData &d, const double *Z, int npair, const double *psiE, double w, double *out,
-                   hipStream_t s) {
-  density_launch<true>(d, Z, 2 * npair, 4 * npair, psiE, out, w, s);
+template <int NP, bool CROSS>
+static void density_launch_folded(const DevData &d, const double *X, int ncol, int64_t ldr, const double *psiE,
+                                  double *rho, double wcross, const DenWork &w, hipStream_t s) {
+  const int ncolr = 2 * ncol;
+  if (d.nr > 0) {
+    const int64_t ntiles = (d.nr + 15) / 16;
+    const int64_t nw = ntiles < kFoldWaves ? ntiles : kFoldWaves;
+    const int64_t tpw = (ntiles + nw - 1) / nw;
+    const unsigned ny = (unsigned)((ncolr + 16 * kFoldNT - 1) / (16 * kFoldNT));
+    hipLaunchKernelGGL(k_fold_rows, dim3((unsigned)((ntiles + tpw - 1) / tpw), ny), dim3(64), 0, s, d, X, ncolr, ldr,
+                       psiE, w.U, tpw);
+  }
+  // ordinary cells: one workgroup per cell over all passes (no atomic part, no partials)
+  if (d.n_ord > 0)
+    hipLaunchKernelGGL((k_den<NP, NP, kDenOrdGroups, true, CROSS>), dim3(d.n_ord), dim3(kThreads), 0, s, d,
+                       d.cells_ord, d.n_ord, X, ncol, ldr, w.U, psiE, rho, nullptr, den_passes(ncolr, kDenOrdGroups),
+                       wcross);
+  den_class<NP, 2 * NP, 1, CROSS>(d, d.cells_enr, d.n_enr, X, ncol, ldr, psiE, rho, wcross, w.U, w.part, s);
+}
+
+// the folded kernels cover GLL degree 4 and 5 with the default rules (p+1 and
+// 2p+2 Gauss points per axis) and at most 48 atomic functions per cell
+bool density_folded_ok(const DevData &d) {
+  return (d.g.P == 5 || d.g.P == 6) && d.g.qc == d.g.P && d.g.qe == 2 * d.g.P && d.max_ta <= 48;
+}
+
+int64_t density_part_size(const DevData &d, int ncolr) {
+  return (int64_t)den_passes(ncolr, 1) * d.n_enr * d.g.qe * d.g.qe * d.g.qe;
+}
+
+template <bool CROSS>
+static void density_launch(const DevData &d, const double *X, int ncol, int64_t ldr, const double *psiE, double *rho,
+                           double wcross, const DenWork &w, hipStream_t s) {
+  if (!density_folded_ok(d) || !w.U || !w.part || (!CROSS && ncol > 128)) {
+    density_launch_generic<CROSS>(d, X, ncol, ldr, psiE, rho, wcross, s);
+    return;
+  }
+  if (d.g.P == 5) density_launch_folded<5, CROSS>(d, X, ncol, ldr, psiE, rho, wcross, w, s);
+  else density_launch_folded<6, CROSS>(d, X, ncol, ldr, psiE, rho, wcross, w, s);
+}
+
+void density(const DevData &d, const double *X, int ncol, int64_t ldr, const double *psiE, double *rho,
+             const DenWork &w, hipStream_t s) {
+  density_launch<false>(d, X, ncol, ldr, psiE, rho, 0.0, w, s);
+}
+
+void cross_density(const DevData &d, const double *Z, int npair, const double *psiE, double wt, double *out,
+                   const DenWork &w, hipStream_t s) {
+  density_launch<true>(d, Z, 2 * npair, 4 * npair, psiE, out, wt, w, s);
 }
 
 void adj_potential(const DevData &d, const double *phibar, const double *rho, const double *u, double tau, int xc,

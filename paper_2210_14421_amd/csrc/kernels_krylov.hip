@@ -18,20 +18,24 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
-// Enrichment coupling: Y_C[r] += G[r] X_E ;  Y_E = G^T X_C[R] + Hbar^ee X_E
-// (G = Hbar^ce on the union rows R of the cells where an enrichment function
-// is nonzero, row-major n_R x n_k).  One wave per block walks a contiguous
-// range of 16-row tiles of R on the FP64 16x16x4 MFMA; a block covers KNT
-// 16-column tiles (blockIdx.y).
-//   k_couple_c:  Y_C tile (16 x 16 N) += G tile (16 x n_k) . X_E (n_k x 16 N),
-//                added into Y.
-//   k_couple_e:  Y_E (16 M x 16 N) += G tile^T (16 M x 16 rows) . X[R tile],
-//                KMT M tiles per block (blockIdx.z), kept in registers over the
-//                range and written as the wave's partial sum; the partials are
-//                reduced in a fixed order (deterministic).
+// Enrichment coupling (Sec. 2.2-2.3), G = Hbar^ce on the union rows R of the
+// cells where an enrichment function is nonzero (row-major n_R x n_k):
+//   Y_C[R] += G X_E            (added into the rows the cell products wrote)
+//   Y_E     = G^T X[R] + Hbar^ee X_E
+// on the FP64 16x16x4 MFMA.
+//   k_couple_c: one wave per block walks a contiguous range of 16-row tiles of
+//               R; a block covers KNT 16-column tiles (blockIdx.y).
+//   k_couple_e: a workgroup of kCpWaves waves takes a contiguous range of
+//               tiles, 48 columns (blockIdx.y) and 48 functions (blockIdx.z);
+//               wave w walks every kCpWaves-th tile of the range and keeps its
+//               Y_E sums in registers; the waves' sums are added in LDS in wave
+//               order and written as the workgroup's partial, and two
+//               reduction kernels sum the partials in a fixed order.
+// The two products run as separate launches: the Y_E sums hold 72 registers,
+// which in one fused kernel would cut the occupancy of the Y_C stream.
+// ---------------------------------------------------------------------------
 constexpr int kCoupleCWaves = 4096;   // four per SIMD
 constexpr int KNT = 6;    // 16-column tiles per block (88 columns = 5.5 tiles)
-constexpr int KMT = 3;    // 16-row tiles of Y_E per block (48 functions)
 
 __global__ void __launch_bounds__(64)
 k_couple_c(const DevData d, const double *__restrict__ G, const double *__restrict__ X, double *__restrict__ Y,
@@ -84,78 +88,114 @@ k_couple_c(const DevData d, const double *__restrict__ G, const double *__restri
   }
 }
 
-__global__ void __launch_bounds__(64)
+constexpr int kCpWaves = 4;
+constexpr int kCpBlocks = 512;   // workgroups per 48-column slice
+constexpr int kCpNT = 3;         // 16-column tiles per slice
+constexpr int kCpMT = 3;         // 16-row tiles of Y_E (n_k <= 48)
+constexpr int kCpSlices = 8;     // first-level reduction slices
+static_assert(kCpBlocks + kCpSlices <= k::kCoupleScratch, "coupling scratch");
+
+__global__ void __launch_bounds__(kCpWaves * 64) __attribute__((amdgpu_waves_per_eu(3)))
 k_couple_e(const DevData d, const double *__restrict__ G, const double *__restrict__ X, int ncolr, int64_t ldr,
-           int64_t tiles_per_wave, double *__restrict__ part, const int *__restrict__ any) {
+           int64_t tiles_per_block, double *__restrict__ part, const int *__restrict__ any) {
   if (any && *any == 0) return;
+  __shared__ double red[kCpMT * 16 * kCpNT * 16];
   const int nk = d.nk;
   const int64_t nr = d.nr;
-  const int lane = threadIdx.x, kr = lane >> 4, cl = lane & 15;
-  const int n0 = blockIdx.y * KNT * 16, m0 = blockIdx.z * KMT * 16;
+  const int tid = threadIdx.x, lane = tid & 63, kr = lane >> 4, cl = lane & 15;
+  const int wave = tid >> 6;
+  const int n0 = blockIdx.y * kCpNT * 16, m0 = blockIdx.z * kCpMT * 16;
   const int64_t ntiles = (nr + 15) / 16;
-  const int64_t t_begin = (int64_t)blockIdx.x * tiles_per_wave;
-  const int64_t t_end = t_begin + tiles_per_wave < ntiles ? t_begin + tiles_per_wave : ntiles;
-  int col[KNT];
-  bool cok[KNT];
+  const int64_t t_begin = (int64_t)blockIdx.x * tiles_per_block;
+  const int64_t t_end = t_begin + tiles_per_block < ntiles ? t_begin + tiles_per_block : ntiles;
+  int col[kCpNT];
+  bool cok[kCpNT];
 #pragma unroll
-  for (int nt = 0; nt < KNT; ++nt) {
+  for (int nt = 0; nt < kCpNT; ++nt) {
     col[nt] = n0 + nt * 16 + cl;
     cok[nt] = col[nt] < ncolr;
   }
-  v4d acc[KMT][KNT];
+  v4d acc_e[kCpMT][kCpNT];
 #pragma unroll
-  for (int mt = 0; mt < KMT; ++mt)
+  for (int mt = 0; mt < kCpMT; ++mt)
 #pragma unroll
-    for (int nt = 0; nt < KNT; ++nt) acc[mt][nt] = v4d{0, 0, 0, 0};
-  // A(i, k) = G[r + k][m0 + i], B(k, j) = X[node(r + k)][j]; four k-steps per tile
-  for (int64_t r4 = t_begin * 4; r4 < t_end * 4; ++r4) {
-    const int64_t rk = r4 * 4 + kr;
-    const bool rok = rk < nr;
-    const double *xr = X + (rok ? (int64_t)d.urow_node[rk] * ldr : 0);
-    double b[KNT];
+    for (int nt = 0; nt < kCpNT; ++nt) acc_e[mt][nt] = v4d{0, 0, 0, 0};
+  for (int64_t t = t_begin + wave; t < t_end; t += kCpWaves) {
+    const int64_t r0 = t * 16;
+    // Y_E sums: A(i, k) = G[r0 + 4 s + k][16 mt + i], B(k, j) = X[node(r0 + 4 s + k)][j]
 #pragma unroll
-    for (int nt = 0; nt < KNT; ++nt) b[nt] = (rok && cok[nt]) ? xr[col[nt]] : 0.0;
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int64_t rk = r0 + 4 * s4 + kr;
+      const bool ok = rk < nr;
+      const double *xr = X + (ok ? (int64_t)d.urow_node[rk] * ldr : 0);
+      double b[kCpNT];
 #pragma unroll
-    for (int mt = 0; mt < KMT; ++mt) {
-      const int m = m0 + mt * 16 + cl;
-      const double a = (rok && m < nk) ? G[rk * nk + m] : 0.0;
+      for (int nt = 0; nt < kCpNT; ++nt) b[nt] = (ok && cok[nt]) ? xr[col[nt]] : 0.0;
 #pragma unroll
-      for (int nt = 0; nt < KNT; ++nt) acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[nt], acc[mt][nt], 0, 0, 0);
-    }
-  }
-  // partial Y_E of this wave: part[blockIdx.x][m][col]
-  double *pw = part + (int64_t)blockIdx.x * nk * ncolr;
+      for (int mt = 0; mt < kCpMT; ++mt) {
+        const int m = m0 + mt * 16 + cl;
+        const double a = (ok && m < nk) ? G[rk * nk + m] : 0.0;
 #pragma unroll
-  for (int mt = 0; mt < KMT; ++mt)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int m = m0 + mt * 16 + kr + 4 * r;
-      if (m < nk) {
-#pragma unroll
-        for (int nt = 0; nt < KNT; ++nt)
-          if (cok[nt]) pw[(int64_t)m * ncolr + col[nt]] = acc[mt][nt][r];
+        for (int nt = 0; nt < kCpNT; ++nt)
+          acc_e[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[nt], acc_e[mt][nt], 0, 0, 0);
       }
     }
+  }
+  // workgroup partial of Y_E: red[m][c] = sum over waves in wave order
+  for (int w = 0; w < kCpWaves; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int mt = 0; mt < kCpMT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int nt = 0; nt < kCpNT; ++nt) {
+            const int idx = (mt * 16 + kr + 4 * r) * (kCpNT * 16) + nt * 16 + cl;
+            red[idx] = (w == 0 ? 0.0 : red[idx]) + acc_e[mt][nt][r];
+          }
+    }
+    __syncthreads();
+  }
+  // part[block][m][column]
+  double *pb = part + (int64_t)blockIdx.x * nk * ncolr;
+  for (int idx = tid; idx < kCpMT * 16 * kCpNT * 16; idx += kCpWaves * 64) {
+    const int m = m0 + idx / (kCpNT * 16), c = n0 + idx % (kCpNT * 16);
+    if (m < nk && c < ncolr) pb[(int64_t)m * ncolr + c] = red[idx];
+  }
 }
 
-// Y_E[k][c] = sum_b part[b][k][c] + sum_k' Hbar^ee[k][k'] X_E[k'][c]; a block of
-// 4 x 64 threads reduces 64 consecutive outputs, each quarter over every
-// fourth partial, then combines the quarters in a fixed order.
+// first level: lvl1[s][o] = sum of the partials of slice s (a contiguous range
+// of workgroups); the four quarters of a block take every fourth partial of
+// the range and are combined in a fixed order
 __global__ void __launch_bounds__(256)
-k_couple_final(const DevData d, const double *__restrict__ part, int nblk, const double *__restrict__ Hee,
-               const double *__restrict__ X, double *__restrict__ Y, int ncolr, int64_t ldr, const int *__restrict__ any) {
+k_couple_sum(const double *__restrict__ part, int nblk, int nout, double *__restrict__ lvl1,
+             const int *__restrict__ any) {
   if (any && *any == 0) return;
   __shared__ double red[4][64];
-  const int nk = d.nk, nout = nk * ncolr;
-  const int o = blockIdx.x * 64 + (threadIdx.x & 63), q = threadIdx.x >> 6;
+  const int o = blockIdx.x * 64 + (threadIdx.x & 63), q = threadIdx.x >> 6, sl = blockIdx.y;
+  const int per = (nblk + kCpSlices - 1) / kCpSlices;
+  const int b0 = sl * per, b1 = b0 + per < nblk ? b0 + per : nblk;
   double s = 0.0;
   if (o < nout)
-    for (int b = q; b < nblk; b += 4) s += part[(int64_t)b * nout + o];
+    for (int b = b0 + q; b < b1; b += 4) s += part[(int64_t)b * nout + o];
   red[q][threadIdx.x & 63] = s;
   __syncthreads();
   if (q != 0 || o >= nout) return;
   const int lo = threadIdx.x;
-  s = red[0][lo] + red[1][lo] + red[2][lo] + red[3][lo];
+  lvl1[(int64_t)sl * nout + o] = red[0][lo] + red[1][lo] + red[2][lo] + red[3][lo];
+}
+
+// Y_E[k][c] = sum_s lvl1[s][k][c] + sum_k' Hbar^ee[k][k'] X_E[k'][c]
+__global__ void __launch_bounds__(64)
+k_couple_final(const DevData d, const double *__restrict__ lvl1, int nsl, const double *__restrict__ Hee,
+               const double *__restrict__ X, double *__restrict__ Y, int ncolr, int64_t ldr,
+               const int *__restrict__ any) {
+  if (any && *any == 0) return;
+  const int nk = d.nk, nout = nk * ncolr;
+  const int o = blockIdx.x * 64 + threadIdx.x;
+  if (o >= nout) return;
+  double s = 0.0;
+  for (int sl = 0; sl < nsl; ++sl) s += lvl1[(int64_t)sl * nout + o];
   const int k = o / ncolr, c = o % ncolr;
   for (int kp = 0; kp < nk; ++kp) s += Hee[k * nk + kp] * X[(d.g.n_nodes + kp) * ldr + c];
   Y[(d.g.n_nodes + k) * ldr + c] = s;
@@ -337,24 +377,29 @@ namespace k {
 void couple_apply(const DevData &d, const double *G, const double *Hee, const double *X, double *Y, int ncolr,
                   int64_t ldr, double *scratch, hipStream_t s, const int *any) {
   if (d.nk == 0) return;
-  int nblk = 1;
   const int nout = d.nk * ncolr;
+  double *lvl1 = scratch + (int64_t)kCpBlocks * nout;
+  int nsl = 1;
   if (d.nr > 0) {
     const int64_t ntiles = (d.nr + 15) / 16;
-    const unsigned ny = (unsigned)((ncolr + KNT * 16 - 1) / (KNT * 16));
-    const unsigned nz = (unsigned)((d.nk + KMT * 16 - 1) / (KMT * 16));
+    const int64_t tpb = (ntiles + kCpBlocks - 1) / kCpBlocks;
+    const int nblk = (int)((ntiles + tpb - 1) / tpb);
+    const unsigned ny = (unsigned)((ncolr + kCpNT * 16 - 1) / (kCpNT * 16));
+    const unsigned nz = (unsigned)((d.nk + kCpMT * 16 - 1) / (kCpMT * 16));
+    const unsigned nyc = (unsigned)((ncolr + KNT * 16 - 1) / (KNT * 16));
     const int64_t tpc = (ntiles + kCoupleCWaves - 1) / kCoupleCWaves;
-    hipLaunchKernelGGL(k_couple_c, dim3((unsigned)((ntiles + tpc - 1) / tpc), ny), dim3(64), 0, s, d, G, X, Y, ncolr,
+    hipLaunchKernelGGL(k_couple_c, dim3((unsigned)((ntiles + tpc - 1) / tpc), nyc), dim3(64), 0, s, d, G, X, Y, ncolr,
                        ldr, tpc, any);
-    const int64_t tpe = (ntiles + kCouplePartials - 1) / kCouplePartials;
-    nblk = (int)((ntiles + tpe - 1) / tpe);
-    hipLaunchKernelGGL(k_couple_e, dim3((unsigned)nblk, ny, nz), dim3(64), 0, s, d, G, X, ncolr, ldr, tpe, scratch,
-                       any);
+    hipLaunchKernelGGL(k_couple_e, dim3((unsigned)nblk, ny, nz), dim3(kCpWaves * 64), 0, s, d, G, X, ncolr, ldr, tpb,
+                       scratch, any);
+    nsl = kCpSlices;
+    hipLaunchKernelGGL(k_couple_sum, dim3(nblocks((int64_t)nout, 64), kCpSlices), dim3(256), 0, s, scratch, nblk, nout,
+                       lvl1, any);
   } else {
-    k::zero(scratch, (int64_t)nout, s);
+    k::zero(lvl1, (int64_t)nout, s);
   }
-  hipLaunchKernelGGL(k_couple_final, dim3(nblocks((int64_t)nout, 64)), dim3(256), 0, s, d, scratch, nblk, Hee, X, Y,
-                     ncolr, ldr, any);
+  hipLaunchKernelGGL(k_couple_final, dim3(nblocks((int64_t)nout, 64)), dim3(64), 0, s, d, lvl1, nsl, Hee, X, Y, ncolr,
+                     ldr, any);
 }
 
 void tridiag_coef(const double *alpha, const double *beta, const int *kused, int ncol, int kmax, const double *taus,

@@ -521,9 +521,16 @@ efe_status build_plan(const efe_system &s, Plan &pl) {
     }
   }
   pl.tne_off.assign(NT + 1, 0);
+  pl.ta_off.assign(NT + 1, 0);
+  pl.ta_nu.clear();
+  pl.tna_off.assign(NT + 1, 0);
   for (int t = 0; t < NT; ++t) {
     int n = pl.n1d(pl.tcell[t]);
     pl.tne_off[t + 1] = pl.tne_off[t] + (int64_t)n * n * n * (pl.tnu_off[t + 1] - pl.tnu_off[t]);
+    for (int k = pl.tnu_off[t]; k < pl.tnu_off[t + 1]; ++k)
+      if (pl.tnu_has_atomic[k]) pl.ta_nu.push_back(pl.tnu[k]);
+    pl.ta_off[t + 1] = (int)pl.ta_nu.size();
+    pl.tna_off[t + 1] = pl.tna_off[t] + (int64_t)n * n * n * (pl.ta_off[t + 1] - pl.ta_off[t]);
   }
 
   pl.enr_scale.assign(ne, 0.0);
@@ -534,6 +541,7 @@ efe_status build_plan(const efe_system &s, Plan &pl) {
   pl.Kce.assign(NR * ne, 0.0);
   pl.Kee.assign((size_t)ne * ne, 0.0);
   pl.NE.assign(pl.tne_off[NT], 0.0);
+  pl.NA.assign(pl.tna_off[NT], 0.0);
   pl.nk = 0; pl.ndrop = 0;
 
   if (ne > 0) {
@@ -684,9 +692,13 @@ efe_status build_plan(const efe_system &s, Plan &pl) {
         interp3(P, n, Bt, Bt, dBz.data(), cc.data(), gz, w1, w2);
         for (size_t q = 0; q < nq; ++q) { val[q] = -val[q]; gx[q] = -gx[q]; gy[q] = -gy[q]; gz[q] = -gz[q]; }
         if (pl.tnu_has_atomic[k]) {
+          int ai = 0;
+          for (int kk = k0; kk < k; ++kk) ai += pl.tnu_has_atomic[kk];
+          double *na = pl.NA.data() + pl.tna_off[t] + (int64_t)ai * nq;
           for (size_t q = 0; q < nq; ++q) {
             double g3[3];
             double a = atomic_value(pl, v, &X[3 * q], g3);
+            na[q] = pl.enr_scale[v] * a;
             val[q] += pl.enr_scale[v] * a;
             gx[q] += pl.enr_scale[v] * g3[0];
             gy[q] += pl.enr_scale[v] * g3[1];

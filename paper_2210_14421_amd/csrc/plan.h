@@ -58,6 +58,11 @@ struct Plan {
   std::vector<uint8_t> tnu_has_atomic;   // per (slot, nu): cell in the atom's cutoff set
   std::vector<int64_t> tne_off;          // per slot: offset of its N^E values
   std::vector<double> NE;                // N^E_nu(q) at T-cell points: [slot][nu_local][q]
+  // atomic parts alone, s_nu N^A_nu(q), at the points of the T-cells where they are nonzero
+  // (the enrichment cells): [slot][atomic nu in tnu order][q]
+  std::vector<int> ta_off, ta_nu;        // per slot: atomic enrichment indices
+  std::vector<int64_t> tna_off;          // per slot: offset of its atomic values
+  std::vector<double> NA;
   std::vector<int64_t> urow_node;        // union rows (interior nodes of T-cells)
   std::vector<int> node_urow;            // n_nodes, -1 if not a union row
   std::vector<int> urow_cnt;             // cells of the row's node that are T-cells
