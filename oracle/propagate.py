@@ -14,6 +14,13 @@
   predictor step with Hbar[rho(t), t], rho_mid = (rho(t) + rho_pred)/2, field at
   t + dt/2, one corrector step.
 * delta kick: psi <- exp(i kappa Zbar_d) psi with the Loewdin position operator.
+* Sec. 2.5 names a second way to the midpoint Hamiltonian: extrapolation from
+  m > 2 previous steps.  Scheme "extrap" takes m = 3: the density at t + dt/2 is
+  the quadratic through rho(t), rho(t - dt), rho(t - 2 dt) evaluated there
+  (weights 15/8, -10/8, 3/8), Hbar is evaluated at that density with the field
+  at t + dt/2, and one exponential makes the step.  Until three densities of the
+  current dt are known (after a refresh or a change of dt) a step is a
+  predictor-corrector step.
 """
 from __future__ import annotations
 
@@ -85,22 +92,38 @@ def lanczos_expm(A, tau, X, tol=1e-10, kmax=64, k_force: Optional[Sequence[int]]
     return Y, ks, errs
 
 
-class Propagator:
-    """Magnus-2 predictor-corrector propagation of the orbital block (eq. ApproxMagnus)."""
+# quadratic extrapolation to t + dt/2 from the values at t, t - dt, t - 2 dt
+EXTRAP3 = (15.0 / 8.0, -10.0 / 8.0, 3.0 / 8.0)
 
-    def __init__(self, model, X, t=0.0, field=None, tol=None, kmax=None):
+
+def extrapolate_midpoint(history):
+    """Value at t + dt/2 of the quadratic through history = [f(t - 2dt), f(t - dt), f(t)]."""
+    return EXTRAP3[0] * history[-1] + EXTRAP3[1] * history[-2] + EXTRAP3[2] * history[-3]
+
+
+class Propagator:
+    """Magnus-2 propagation of the orbital block (eq. ApproxMagnus); the midpoint
+    Hamiltonian by predictor-corrector (scheme "pc") or by extrapolation from the
+    three previous densities (scheme "extrap")."""
+
+    def __init__(self, model, X, t=0.0, field=None, tol=None, kmax=None, scheme="pc"):
+        if scheme not in ("pc", "extrap"):
+            raise ValueError(f"unknown scheme {scheme!r}")
         self.model = model
         self.X = np.asarray(X, dtype=np.complex128).copy()
         self.t = float(t)
         self.field = field
         self.tol = model.spec.krylov_tol if tol is None else tol
         self.kmax = model.spec.kmax if kmax is None else kmax
+        self.scheme = scheme
         self.refresh()
 
     def refresh(self):
-        """(Re)build rho and Hbar for the current orbitals and time."""
+        """(Re)build rho and Hbar for the current orbitals and time; the density
+        history restarts from rho."""
         self.rho = self.model.density(self.X)
         self.H = self.model.hamiltonian_from_density(self.rho, self.t, self.field)
+        self.hist, self.hist_dt = [self.rho], None
 
     def kick(self, kappa, direction=2):
         """psi <- exp(i kappa Zbar_d) psi, then refresh the Hamiltonian."""
@@ -110,16 +133,24 @@ class Propagator:
         return k
 
     def step(self, dt, k_force=None):
-        """One Magnus-2 step; returns (mu, k_pred, k_corr)."""
+        """One Magnus-2 step; returns (mu, k_pred, k_corr) (k_pred = 0 for an
+        extrapolated step, which has no predictor)."""
         m = self.model
         kp_f = None if k_force is None else k_force[0]
         kc_f = None if k_force is None else k_force[1]
-        Xp, kp, _ = lanczos_expm(self.H, dt, self.X, self.tol, self.kmax, kp_f)
-        rho_mid = 0.5 * (self.rho + m.density(Xp))
+        hist = self.hist if self.hist_dt == dt else [self.rho]
+        if self.scheme == "extrap" and len(hist) >= 3:
+            rho_mid = extrapolate_midpoint(hist)
+            kp = np.zeros(self.X.shape[1], dtype=np.int32)
+        else:
+            Xp, kp, _ = lanczos_expm(self.H, dt, self.X, self.tol, self.kmax, kp_f)
+            rho_mid = 0.5 * (self.rho + m.density(Xp))
         Hmid = m.hamiltonian_from_density(rho_mid, self.t + 0.5 * dt, self.field)
         self.X, kc, _ = lanczos_expm(Hmid, dt, self.X, self.tol, self.kmax, kc_f)
         self.t += dt
-        self.refresh()
+        self.rho = m.density(self.X)
+        self.H = m.hamiltonian_from_density(self.rho, self.t, self.field)
+        self.hist, self.hist_dt = (hist + [self.rho])[-3:], dt
         return m.dipole(self.rho), kp, kc
 
     def run(self, dt, nsteps, k_force=None):

@@ -191,3 +191,94 @@ def test_second_order_in_dt(trap_setup):
     e = [abs(mu_at(dt) - ref) for dt in (0.2, 0.1)]
     slope = math.log(e[0] / e[1]) / math.log(2.0)
     assert 1.8 < slope < 2.3, (e, slope)
+
+
+# ---- extrapolated midpoint Hamiltonian (Sec. 2.5, m = 3 previous steps) ----------
+
+def test_extrapolation_weights_reproduce_quadratics():
+    """The midpoint value of a quadratic is exact; a cubic leaves an O(dt^3) error."""
+    from oracle.propagate import extrapolate_midpoint
+    rng = np.random.default_rng(5)
+    a, b, c, d = rng.standard_normal((4, 50))
+    t, dt = 0.7, 0.05
+    quad = lambda s: a + b * s + c * s * s
+    hist = [quad(t - 2 * dt), quad(t - dt), quad(t)]
+    np.testing.assert_allclose(extrapolate_midpoint(hist), quad(t + 0.5 * dt), rtol=1e-13, atol=1e-13)
+    errs = []
+    for h in (0.1, 0.05):
+        cub = lambda s: d * s ** 3
+        e = extrapolate_midpoint([cub(t - 2 * h), cub(t - h), cub(t)]) - cub(t + 0.5 * h)
+        errs.append(np.abs(e).max())
+    # error of the quadratic through t-2h, t-h, t at t+h/2: f'''/6 (1/2)(3/2)(5/2) h^3 = (15/8) d h^3
+    np.testing.assert_allclose(errs[0], 15.0 / 8.0 * np.abs(d).max() * 0.1 ** 3, rtol=1e-10)
+    assert 7.9 < errs[0] / errs[1] < 8.1
+
+
+def test_extrap_starts_with_predictor_corrector_steps(tiny_model, tiny_gs):
+    m = tiny_model
+    X0 = tiny_gs["X"]
+    Pa, Pb = Propagator(m, X0), Propagator(m, X0, scheme="extrap")
+    for P in (Pa, Pb):
+        P.kick(1e-3, 2)
+    for n in range(3):
+        ra, rb = Pa.step(0.05), Pb.step(0.05)
+        if n < 2:
+            assert np.array_equal(Pa.X, Pb.X) and np.all(rb[1] > 0)
+        else:
+            assert np.all(rb[1] == 0) and not np.array_equal(Pa.X, Pb.X)
+            # both are second-order approximations of the same midpoint
+            assert abs(ra[0][2] - rb[0][2]) < 1e-3 * abs(ra[0][2])
+    # a new dt restarts the history: the next step is again a predictor-corrector step
+    assert np.all(Pb.step(0.025)[1] > 0)
+    np.testing.assert_allclose(Pb.X.conj().T @ Pb.X, np.eye(2), atol=1e-11)
+
+
+def test_extrap_kohn_theorem_in_trap(trap_setup):
+    m, X0 = trap_setup
+    P = Propagator(m, X0, tol=1e-12, scheme="extrap")
+    kappa, w, N = 1e-3, 1.0, 2.0
+    P.kick(kappa, 2)
+    ts, mu = [], []
+    for _ in range(16):
+        mu.append(P.step(0.1)[0][2])
+        ts.append(P.t)
+    exact = N * kappa * np.sin(w * np.array(ts)) / w
+    err = np.abs(np.array(mu) - exact).max() / np.abs(exact).max()
+    assert err < 0.05, err
+
+
+def test_extrap_second_order_in_dt(trap_setup):
+    """Both schemes converge to the same solution; the extrapolated one at order 2."""
+    m, X0 = trap_setup
+    T = 0.8
+
+    def mu_at(dt, scheme):
+        P = Propagator(m, X0, tol=1e-13, kmax=100, scheme=scheme)
+        P.kick(1e-2, 2)
+        for _ in range(int(round(T / dt))):
+            mu = P.step(dt)[0]
+        return mu[2]
+
+    ref = mu_at(0.0125, "pc")
+    e = [abs(mu_at(dt, "extrap") - ref) for dt in (0.1, 0.05)]
+    slope = math.log(e[0] / e[1]) / math.log(2.0)
+    assert 1.7 < slope < 2.4, (e, slope)
+
+
+def test_extrap_second_order_with_field(trap_setup):
+    """Field-driven (no kick): the field enters at t + dt/2, so the order stays 2."""
+    from oracle.model import Field
+    m, X0 = trap_setup
+    field = Field(direction=2, A=np.array([0.02]), w=np.array([2.0]), phi=np.array([0.3]), t0=0.4, s=0.5)
+    T = 0.8
+
+    def mu_at(dt, scheme):
+        P = Propagator(m, X0, tol=1e-13, kmax=100, field=field, scheme=scheme)
+        for _ in range(int(round(T / dt))):
+            mu = P.step(dt)[0]
+        return mu[2]
+
+    ref = mu_at(0.0125, "pc")
+    e = [abs(mu_at(dt, "extrap") - ref) for dt in (0.1, 0.05)]
+    slope = math.log(e[0] / e[1]) / math.log(2.0)
+    assert 1.7 < slope < 2.4, (e, slope)
