@@ -192,6 +192,30 @@ efe_status lanczos_expm(efe_ctx *ctx, int32_t op, double tau, void *X, int32_t n
 efe_status magnus_step(efe_ctx *ctx, void *Psi, int64_t ld, double t, double dt,
                        const efe_field *field, const int32_t *k_force, efe_step_stats *stats);
 
+/* flags of magnus_step_extrap */
+enum { EFE_STEP_KEEP_HAM = 1 };
+
+/* One Magnus-2 step, eq. (ApproxMagnus), with the midpoint Hamiltonian
+ * extrapolated from previous steps (Sec. 2.5 names extrapolation from m > 2
+ * previous steps as the alternative to the predictor-corrector).  Here m = 3:
+ * rho_mid = 15/8 rho_n - 10/8 rho_{n-1} + 3/8 rho_{n-2} (the quadratic through
+ * the last three time levels, at t + dt/2), Psi <- exp(-i dt Hbar[rho_mid,
+ * t + dt/2]) Psi, then rho_{n+1} and the dipole: one exponential per step.
+ * The context keeps the densities of its last three steps (magnus_step and
+ * this call both record them; efe_set_hamiltonian, the captured and batched
+ * steps, the adjoint calls and position-operator exponentials restart the
+ * record).  While fewer than three densities of this dt are known the call
+ * makes a predictor-corrector step instead (k_pred of stats > 0; it needs the
+ * Hamiltonian of the current orbitals).  flags: EFE_STEP_KEEP_HAM also builds
+ * Hbar[rho_{n+1}, t + dt] at the end, as magnus_step does; without it the
+ * context holds the midpoint Hamiltonian and a later magnus_step needs
+ * efe_set_hamiltonian first.  k_force: host [2][norb] (the corrector half is
+ * used by an extrapolated step) or NULL.  Other arguments as magnus_step;
+ * EFE_ERR_ARG for unknown flags, EFE_ERR_STATE without a known density. */
+efe_status magnus_step_extrap(efe_ctx *ctx, void *Psi, int64_t ld, double t, double dt,
+                              const efe_field *field, const int32_t *k_force, int32_t flags,
+                              efe_step_stats *stats);
+
 /* The same step as magnus_step, enqueued with no host round trip and replayed
  * from a hipGraph captured on the first call (and again whenever Psi, ld, dt or
  * the field's kind/direction change).  Every Lanczos runs kmax iterations whose

@@ -49,6 +49,11 @@ struct efe_ctx {
   void *cells = nullptr;
   double *Q = nullptr, *X0 = nullptr, *X1 = nullptr;
   double *rho_prev = nullptr, *rho_tmp = nullptr, *vq = nullptr;
+  // densities of the last (up to) three time levels, spaced by hist_dt: the
+  // newest is rho_hist[hist_head]; hist_n = 0 means unknown (seeded from rho_prev)
+  double *rho_hist[3] = {nullptr, nullptr, nullptr};
+  int hist_n = 0, hist_head = 0;
+  double hist_dt = 0.0;
   double *phi = nullptr, *dvec = nullptr, *rhs = nullptr;
   double *cg[7] = {nullptr};
   double *part = nullptr, *hee_part = nullptr, *G = nullptr, *Hee_raw = nullptr, *Hbar_ee = nullptr;
@@ -339,6 +344,7 @@ efe_status build_device(efe_ctx *ctx) {
   EFE_TRY(dalloc(ctx, &ctx->X0, ctx->blk));
   EFE_TRY(dalloc(ctx, &ctx->X1, ctx->blk));
   EFE_TRY(dalloc(ctx, &ctx->rho_prev, pl.n_quad));
+  for (int h = 0; h < 3; ++h) EFE_TRY(dalloc(ctx, &ctx->rho_hist[h], pl.n_quad));
   EFE_TRY(dalloc(ctx, &ctx->rho_tmp, pl.n_quad));
   EFE_TRY(dalloc(ctx, &ctx->vq, pl.n_quad));
   EFE_TRY(dalloc(ctx, &ctx->phi, pl.n_nodes));
@@ -1036,6 +1042,129 @@ efe_status pack_out(efe_ctx *ctx, const double *src, int ncol, void *dst, int64_
   return check_launch(ctx, "unpack");
 }
 
+// ---------------------------------------------------------------------------
+// Density history for the extrapolated midpoint Hamiltonian (Sec. 2.5): every
+// host-driven step pushes rho_{n+1}; a step of another dt keeps only the
+// newest density; efe_set_hamiltonian and the device-driven steps restart it.
+// ---------------------------------------------------------------------------
+efe_status hist_seed(efe_ctx *ctx) {
+  if (ctx->hist_n > 0) return EFE_OK;
+  HIP_TRY(hipMemcpyAsync(ctx->rho_hist[ctx->hist_head], ctx->rho_prev, ctx->plan.n_quad * sizeof(double),
+                         hipMemcpyDeviceToDevice, ctx->stream));
+  ctx->hist_n = 1;
+  ctx->hist_dt = std::nan("");
+  return EFE_OK;
+}
+
+int hist_usable(const efe_ctx *ctx, double dt) { return ctx->hist_dt == dt ? ctx->hist_n : std::min(ctx->hist_n, 1); }
+
+const double *hist_at(const efe_ctx *ctx, int back) { return ctx->rho_hist[(ctx->hist_head + 3 - back) % 3]; }
+
+efe_status hist_push(efe_ctx *ctx, double dt) {
+  if (ctx->hist_dt != dt) ctx->hist_n = std::min(ctx->hist_n, 1);
+  ctx->hist_head = (ctx->hist_head + 1) % 3;
+  HIP_TRY(hipMemcpyAsync(ctx->rho_hist[ctx->hist_head], ctx->rho_prev, ctx->plan.n_quad * sizeof(double),
+                         hipMemcpyDeviceToDevice, ctx->stream));
+  ctx->hist_n = std::min(ctx->hist_n + 1, 3);
+  ctx->hist_dt = dt;
+  return EFE_OK;
+}
+
+// The predictor-corrector step (host-driven adaptive Lanczos); the caller has
+// checked the arguments and the Hamiltonian.
+efe_status step_pc(efe_ctx *ctx, void *Psi, int64_t ld, double t, double dt, const efe_field *field,
+                   const int32_t *k_force, efe_step_stats *stats) {
+  timer_reset(ctx);
+  tstart(ctx, 7);
+  const int no = ctx->norb;
+  const int64_t n = ctx->plan.n_quad;
+  double *Xp = ctx->X1;
+  std::vector<int32_t> kp(no), kc(no);
+  std::vector<double> ep(no), ec(no);
+  int cg[2] = {0, 0};
+  ctx->ham_valid = false;   // restored on success
+  EFE_TRY(pack_in(ctx, Psi, ld, no, ctx->X0));
+  // predictor with Hbar[rho_n, t]
+  EFE_TRY(run_lanczos(ctx, dt, ctx->X0, Xp, no, k_force ? k_force : nullptr, kp.data(), ep.data()));
+  // midpoint Hamiltonian from rho_mid = (rho_n + rho_p)/2 at t + dt/2
+  EFE_TRY(density_packed(ctx, Xp, ctx->rho_tmp));
+  efe::k::axpby(ctx->rho_prev, ctx->rho_tmp, 0.5, 0.5, ctx->rho_tmp, n, ctx->stream);
+  EFE_TRY(rebuild(ctx, 0, ctx->rho_tmp, t + 0.5 * dt, field, &cg[0]));
+  // corrector from Psi_n
+  EFE_TRY(run_lanczos(ctx, dt, ctx->X0, Xp, no, k_force ? k_force + no : nullptr, kc.data(), ec.data()));
+  // end of step: rho_{n+1}, Hbar[rho_{n+1}, t + dt], dipole
+  EFE_TRY(density_packed(ctx, Xp, ctx->rho_prev));
+  EFE_TRY(rebuild(ctx, 0, ctx->rho_prev, t + dt, field, &cg[1]));
+  double mu[3];
+  EFE_TRY(dipole_of(ctx, ctx->rho_prev, mu));
+  if (!std::isfinite(mu[0]) || !std::isfinite(mu[1]) || !std::isfinite(mu[2])) {
+    ctx->err = "non-finite dipole after the step";
+    return EFE_ERR_NONFINITE;
+  }
+  EFE_TRY(pack_out(ctx, Xp, no, Psi, ld));
+  tstop(ctx, 7);
+  EFE_TRY(sync(ctx, "magnus_step"));
+  timer_collect(ctx);
+  ctx->ham_valid = true;
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    for (int c = 0; c < no && c < 128; ++c) {
+      stats->k_pred[c] = kp[c];
+      stats->k_corr[c] = kc[c];
+      stats->err_pred_max = std::max(stats->err_pred_max, ep[c]);
+      stats->err_corr_max = std::max(stats->err_corr_max, ec[c]);
+    }
+    stats->cg_iters[0] = cg[0];
+    stats->cg_iters[1] = cg[1];
+    for (int k = 0; k < 3; ++k) stats->mu[k] = mu[k];
+  }
+  return EFE_OK;
+}
+
+// One step with the midpoint Hamiltonian at the extrapolated density
+// rho_mid = 15/8 rho_n - 10/8 rho_{n-1} + 3/8 rho_{n-2} and the field at t + dt/2.
+efe_status step_extrap(efe_ctx *ctx, void *Psi, int64_t ld, double t, double dt, const efe_field *field,
+                       const int32_t *k_force, int keep_ham, efe_step_stats *stats) {
+  timer_reset(ctx);
+  tstart(ctx, 7);
+  const int no = ctx->norb;
+  const int64_t n = ctx->plan.n_quad;
+  double *Xp = ctx->X1;
+  std::vector<int32_t> kc(no);
+  std::vector<double> ec(no);
+  int cg[2] = {0, 0};
+  ctx->ham_valid = false;   // restored on success if keep_ham
+  EFE_TRY(pack_in(ctx, Psi, ld, no, ctx->X0));
+  efe::k::axpby(hist_at(ctx, 0), hist_at(ctx, 1), 15.0 / 8.0, -10.0 / 8.0, ctx->rho_tmp, n, ctx->stream);
+  efe::k::axpby(ctx->rho_tmp, hist_at(ctx, 2), 1.0, 3.0 / 8.0, ctx->rho_tmp, n, ctx->stream);
+  EFE_TRY(rebuild(ctx, 0, ctx->rho_tmp, t + 0.5 * dt, field, &cg[0]));
+  EFE_TRY(run_lanczos(ctx, dt, ctx->X0, Xp, no, k_force ? k_force + no : nullptr, kc.data(), ec.data()));
+  EFE_TRY(density_packed(ctx, Xp, ctx->rho_prev));
+  if (keep_ham) EFE_TRY(rebuild(ctx, 0, ctx->rho_prev, t + dt, field, &cg[1]));
+  double mu[3];
+  EFE_TRY(dipole_of(ctx, ctx->rho_prev, mu));
+  if (!std::isfinite(mu[0]) || !std::isfinite(mu[1]) || !std::isfinite(mu[2])) {
+    ctx->err = "non-finite dipole after the step";
+    return EFE_ERR_NONFINITE;
+  }
+  EFE_TRY(pack_out(ctx, Xp, no, Psi, ld));
+  tstop(ctx, 7);
+  EFE_TRY(sync(ctx, "magnus_step_extrap"));
+  timer_collect(ctx);
+  ctx->ham_valid = keep_ham != 0;
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    for (int c = 0; c < no && c < 128; ++c) {
+      stats->k_corr[c] = kc[c];
+      stats->err_corr_max = std::max(stats->err_corr_max, ec[c]);
+    }
+    stats->cg_iters[0] = cg[0];
+    stats->cg_iters[1] = cg[1];
+    for (int k = 0; k < 3; ++k) stats->mu[k] = mu[k];
+  }
+  return EFE_OK;
+}
+
 }  // namespace
 
 // ============================================================================ C ABI
@@ -1185,6 +1314,7 @@ efe_status efe_initial_state(efe_ctx *ctx, const int32_t *enr_index, const doubl
     for (int a = 0; a < no; ++a) Z[((size_t)r * no + a) * 2] = X[(size_t)r * no + a];
   HIP_TRY(hipMemcpy(Psi, Z.data(), Z.size() * sizeof(double), hipMemcpyHostToDevice));
   ctx->ham_valid = false;
+  ctx->hist_n = 0;
   return EFE_OK;
 }
 
@@ -1199,6 +1329,7 @@ efe_status efe_set_hamiltonian(efe_ctx *ctx, const void *Psi, double t, const ef
   EFE_TRY(sync(ctx, "set_hamiltonian"));
   timer_collect(ctx);
   ctx->ham_valid = true;
+  ctx->hist_n = 0;
   return EFE_OK;
 }
 
@@ -1229,6 +1360,7 @@ efe_status lanczos_expm(efe_ctx *ctx, int32_t op, double tau, void *X, int32_t n
     }
   } else {
     ctx->ham_valid = false;
+    ctx->hist_n = 0;
     EFE_TRY(rebuild(ctx, op, nullptr, 0.0, nullptr, nullptr));
   }
   EFE_TRY(pack_in(ctx, X, ld, ncol, ctx->X0));
@@ -1247,52 +1379,34 @@ efe_status magnus_step(efe_ctx *ctx, void *Psi, int64_t ld, double t, double dt,
     ctx->err = "magnus_step needs the Hamiltonian of the current orbitals (call efe_set_hamiltonian)";
     return EFE_ERR_STATE;
   }
-  timer_reset(ctx);
-  tstart(ctx, 7);
-  const int no = ctx->norb;
-  const int64_t n = ctx->plan.n_quad;
-  double *Xp = ctx->X1;
-  std::vector<int32_t> kp(no), kc(no);
-  std::vector<double> ep(no), ec(no);
-  int cg[2] = {0, 0};
-  ctx->ham_valid = false;   // restored on success
-  EFE_TRY(pack_in(ctx, Psi, ld, no, ctx->X0));
-  // predictor with Hbar[rho_n, t]
-  EFE_TRY(run_lanczos(ctx, dt, ctx->X0, Xp, no, k_force ? k_force : nullptr, kp.data(), ep.data()));
-  // midpoint Hamiltonian from rho_mid = (rho_n + rho_p)/2 at t + dt/2
-  EFE_TRY(density_packed(ctx, Xp, ctx->rho_tmp));
-  efe::k::axpby(ctx->rho_prev, ctx->rho_tmp, 0.5, 0.5, ctx->rho_tmp, n, ctx->stream);
-  EFE_TRY(rebuild(ctx, 0, ctx->rho_tmp, t + 0.5 * dt, field, &cg[0]));
-  // corrector from Psi_n
-  EFE_TRY(run_lanczos(ctx, dt, ctx->X0, Xp, no, k_force ? k_force + no : nullptr, kc.data(), ec.data()));
-  // end of step: rho_{n+1}, Hbar[rho_{n+1}, t + dt], dipole
-  EFE_TRY(density_packed(ctx, Xp, ctx->rho_prev));
-  EFE_TRY(rebuild(ctx, 0, ctx->rho_prev, t + dt, field, &cg[1]));
-  double mu[3];
-  EFE_TRY(dipole_of(ctx, ctx->rho_prev, mu));
-  if (!std::isfinite(mu[0]) || !std::isfinite(mu[1]) || !std::isfinite(mu[2])) {
-    ctx->err = "non-finite dipole after the step";
-    return EFE_ERR_NONFINITE;
-  }
-  EFE_TRY(pack_out(ctx, Xp, no, Psi, ld));
-  tstop(ctx, 7);
-  EFE_TRY(sync(ctx, "magnus_step"));
-  timer_collect(ctx);
-  ctx->ham_valid = true;
-  if (stats) {
-    std::memset(stats, 0, sizeof(*stats));
-    for (int c = 0; c < no && c < 128; ++c) {
-      stats->k_pred[c] = kp[c];
-      stats->k_corr[c] = kc[c];
-      stats->err_pred_max = std::max(stats->err_pred_max, ep[c]);
-      stats->err_corr_max = std::max(stats->err_corr_max, ec[c]);
-    }
-    stats->cg_iters[0] = cg[0];
-    stats->cg_iters[1] = cg[1];
-    for (int k = 0; k < 3; ++k) stats->mu[k] = mu[k];
-  }
-  return EFE_OK;
+  EFE_TRY(hist_seed(ctx));
+  EFE_TRY(step_pc(ctx, Psi, ld, t, dt, field, k_force, stats));
+  return hist_push(ctx, dt);
 }
+
+efe_status magnus_step_extrap(efe_ctx *ctx, void *Psi, int64_t ld, double t, double dt, const efe_field *field,
+                              const int32_t *k_force, int32_t flags, efe_step_stats *stats) {
+  if (!ctx || !Psi || ld < ctx->norb || !std::isfinite(t) || !std::isfinite(dt) || (flags & ~EFE_STEP_KEEP_HAM))
+    return EFE_ERR_ARG;
+  EFE_TRY(validate_field(ctx, field));
+  if (ctx->cells_mode != 0 || (ctx->hist_n == 0 && !ctx->ham_valid)) {
+    ctx->err = "magnus_step_extrap needs the density of the current orbitals (call efe_set_hamiltonian)";
+    return EFE_ERR_STATE;
+  }
+  EFE_TRY(hist_seed(ctx));
+  if (hist_usable(ctx, dt) < 3) {
+    if (!ctx->ham_valid) {
+      ctx->err = "a predictor-corrector start of magnus_step_extrap needs the Hamiltonian of the current orbitals "
+                 "(call efe_set_hamiltonian, or keep the Hamiltonian in the previous step)";
+      return EFE_ERR_STATE;
+    }
+    EFE_TRY(step_pc(ctx, Psi, ld, t, dt, field, k_force, stats));
+  } else {
+    EFE_TRY(step_extrap(ctx, Psi, ld, t, dt, field, k_force, flags & EFE_STEP_KEEP_HAM, stats));
+  }
+  return hist_push(ctx, dt);
+}
+
 
 efe_status density(efe_ctx *ctx, const void *Psi, int64_t ld, double *rho_q) {
   if (!ctx || !Psi || !rho_q || ld < ctx->norb) return EFE_ERR_ARG;
@@ -1343,6 +1457,7 @@ efe_status magnus_step_graph(efe_ctx *ctx, void *Psi, int64_t ld, double t, doub
   HIP_TRY(hipStreamSynchronize(ctx->gstream));
   EFE_TRY(finish_stats(ctx, stats));
   ctx->ham_valid = true;
+  ctx->hist_n = 0;   // the captured step does not track the density history
   return EFE_OK;
 }
 
@@ -1461,6 +1576,7 @@ efe_status efe_batch_step(efe_batch *b, void *const *Psi, const int64_t *ld, dou
   for (int i = 0; i < n; ++i) {
     efe_ctx *c = b->m[i];
     c->ham_valid = false;
+    c->hist_n = 0;
     if (hipEventRecord(c->ev_in, c->stream) != hipSuccess || hipStreamWaitEvent(b->bs, c->ev_in, 0) != hipSuccess) {
       b->err = "batch: stream ordering failed";
       return EFE_ERR_HIP;
@@ -1482,6 +1598,7 @@ efe_status efe_batch_step(efe_batch *b, void *const *Psi, const int64_t *ld, dou
   efe_status first = EFE_OK;
   for (int i = 0; i < n; ++i) {
     efe_status st = finish_stats(b->m[i], stats ? stats + i : nullptr);
+    b->m[i]->hist_n = 0;
     if (st == EFE_OK) b->m[i]->ham_valid = true;
     else if (first == EFE_OK) {
       first = st;
@@ -1506,6 +1623,7 @@ efe_status magnus_adjoint(efe_ctx *ctx, const void *Psi, int64_t ld, double t, d
   gauss_legendre01(kAdjNodes, sg, wg);
   ctx->adj_dt = dt;
   ctx->ham_valid = false;
+  ctx->hist_n = 0;
   std::vector<int32_t> k1(no), k2(no);
   int it = 0;
   const double zero3[3] = {0.0, 0.0, 0.0};
@@ -1548,6 +1666,7 @@ efe_status dipole_adjoint(efe_ctx *ctx, const void *Psi, int64_t ld, const doubl
   EFE_TRY(ensure_adjoint_buffers(ctx));
   const int no = ctx->norb;
   ctx->ham_valid = false;
+  ctx->hist_n = 0;
   ctx->adj_dt = 0.0;
   EFE_TRY(pack_in(ctx, Psi, ld, no, ctx->X0));
   // g = mubar . x  (u = 0, phibar = 0)

@@ -78,6 +78,9 @@ _lanczos = _sig("lanczos_expm", C.c_int32, [C.c_void_p, C.c_int32, C.c_double, C
                                             _ip, _ip, _dp])
 _magnus = _sig("magnus_step", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_double,
                                           C.POINTER(EfeField), _ip, C.POINTER(EfeStepStats)])
+_magnus_extrap = _sig("magnus_step_extrap", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_double,
+                                                        C.POINTER(EfeField), _ip, C.c_int32, C.POINTER(EfeStepStats)])
+EFE_STEP_KEEP_HAM = 1
 _magnus_graph = _sig("magnus_step_graph", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_double,
                                                       C.POINTER(EfeField), C.POINTER(EfeStepStats)])
 _batch_create = _sig("efe_batch_create", C.c_int32, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p)])
@@ -101,7 +104,7 @@ EXPORTED = ["efe_plan_create", "efe_plan_free", "efe_plan_sizes", "efe_plan_get"
             "efe_set_hamiltonian", "efe_apply_H", "lanczos_expm", "magnus_step", "density",
             "efe_hartree", "dipole", "efe_enable_timing", "efe_get_timing", "efe_last_error",
             "magnus_step_graph", "efe_batch_create", "efe_batch_free", "efe_batch_error", "efe_batch_step",
-            "magnus_adjoint", "dipole_adjoint"]
+            "magnus_adjoint", "dipole_adjoint", "magnus_step_extrap"]
 
 
 class EfeError(RuntimeError):
@@ -282,13 +285,24 @@ class Context:
                              er.ctypes.data_as(_dp)))
         return ku, er
 
-    def magnus_step(self, Psi, t, dt, field=None, k_force=None, graph=False):
+    def magnus_step(self, Psi, t, dt, field=None, k_force=None, graph=False, scheme="pc", keep_ham=True):
         """One Magnus-2 step in place.  graph=True replays a captured hipGraph of
-        the device-driven step (no k_force)."""
+        the device-driven step (no k_force).  scheme="extrap" takes the midpoint
+        Hamiltonian at the density extrapolated from the last three steps
+        (magnus_step_extrap); keep_ham=False leaves the midpoint Hamiltonian."""
         st = EfeStepStats()
         f = C.byref(field) if field is not None else None
         ptr = self._ptr(Psi, self.torch.complex128, self.n_rows)
-        if graph:
+        if scheme not in ("pc", "extrap"):
+            raise ValueError(f"unknown scheme {scheme!r}")
+        if scheme == "extrap":
+            if graph:
+                raise ValueError("the extrapolated step is host-driven (graph=False)")
+            kf = None if k_force is None else _arr(k_force, np.int32).reshape(-1)
+            self._check(_magnus_extrap(self._c, ptr, Psi.shape[1], float(t), float(dt), f,
+                                       None if kf is None else kf.ctypes.data_as(_ip),
+                                       EFE_STEP_KEEP_HAM if keep_ham else 0, C.byref(st)))
+        elif graph:
             if k_force is not None:
                 raise ValueError("k_force is not available with graph=True")
             self._check(_magnus_graph(self._c, ptr, Psi.shape[1], float(t), float(dt), f, C.byref(st)))

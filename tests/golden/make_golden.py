@@ -1,6 +1,6 @@
 """Write the stored expected values under tests/golden/ (calls only the oracle).
 
-Usage: python tests/golden/make_golden.py [tiny_gs] [trap_gs] [tiny_traj] [na8]
+Usage: python tests/golden/make_golden.py [tiny_gs] [trap_gs] [tiny_traj] [tiny_extrap] [na8] [adjoint_tiny]
 
 Every file written here is produced by the FP64 oracle from the seeded inputs of
 ``workloads``; nothing comes from the GPU library.
@@ -57,6 +57,27 @@ def tiny_traj():
     np.savez_compressed(os.path.join(HERE, "tiny_traj.npz"), mu_ground=mu0, mu=np.array(mus),
                         k=np.array(ks, dtype=np.int32), k_kick=k_kick, X_final=P.X,
                         rho_final=P.rho, dt=spec.dt, kick=spec.kick)
+
+
+def tiny_extrap():
+    """Kick 1e-3 along z, then 100 steps of 0.05 au with the midpoint Hamiltonian
+    extrapolated from the last three steps (the first two steps predictor-corrector)."""
+    spec = tiny()
+    m = EFEModel(spec)
+    X0 = np.load(os.path.join(HERE, "tiny_ground_state.npz"))["X"]
+    P = Propagator(m, X0, tol=spec.krylov_tol, kmax=spec.kmax, scheme="extrap")
+    k_kick = P.kick(spec.kick, spec.kick_dir)
+    mus = [m.dipole(P.rho)]
+    ks = []
+    t0 = time.time()
+    for n in range(100):
+        mu, kp, kc = P.step(spec.dt)
+        mus.append(mu)
+        ks.append(np.stack([kp, kc]))
+        if n % 20 == 0:
+            print(f"step {n} mu_z={mu[2]:.6e} k={kp},{kc} ({time.time() - t0:.0f}s)", flush=True)
+    np.savez_compressed(os.path.join(HERE, "tiny_extrap.npz"), mu=np.array(mus), k=np.array(ks, dtype=np.int32),
+                        k_kick=k_kick, X_final=P.X, dt=spec.dt, kick=spec.kick)
 
 
 def na8():
