@@ -192,6 +192,30 @@ efe_status lanczos_expm(efe_ctx *ctx, int32_t op, double tau, void *X, int32_t n
 efe_status magnus_step(efe_ctx *ctx, void *Psi, int64_t ld, double t, double dt,
                        const efe_field *field, const int32_t *k_force, efe_step_stats *stats);
 
+/* Applied field of a spectrum run: kind 0 = delta kick of strength kappa at
+ * t = 0; kind 1 = the Gaussian kappa exp(-(t - t0)^2 / (2 s^2)) of Sec. 3.1-3.2. */
+typedef struct {
+  int32_t kind;
+  double kappa, t0, s;
+} efe_pulse;
+
+/* Absorption spectrum of Sec. 3.2 from the dipole traces of ndir runs
+ * (ndir 1..3), run r perturbed along dirs[r] (0..2, host array).  mu: device,
+ * [ndir][nt + 1][3], the dipole at t_n = n dt with t_0 = 0 the start of the run
+ * (mu at n = 0 is the unperturbed dipole that is subtracted).  For each
+ * frequency omega[i] (device, nw): alpha_r = int_0^T exp(-t/tau)
+ * (mu_r,d(t) - mu_r,d(0)) exp(i omega t) dt / F[E](omega) (trapezoid rule;
+ * F[E] = kappa for the kick, kappa s sqrt(2 pi) exp(-omega^2 s^2/2)
+ * exp(i omega t0) for the Gaussian) and S[i] = (2 omega / (3 pi)) sum_r Im
+ * alpha_r, the normalisation of the Thomas-Reiche-Kuhn sum rule (int S =
+ * N_e for an isotropic response given all three directions).  S: device, nw;
+ * alpha: device [ndir][nw][2] (re, im) or NULL.  hip_stream: a hipStream_t or
+ * NULL for the null stream; the call waits for its kernel.  EFE_ERR_ARG for
+ * out-of-range sizes, directions, dt, tau or pulse. */
+efe_status absorption_spectrum(const double *mu, const int32_t *dirs, int32_t ndir, int64_t nt, double dt,
+                               const efe_pulse *pulse, double tau, const double *omega, int64_t nw,
+                               double *S, double *alpha, void *hip_stream);
+
 /* flags of magnus_step_extrap */
 enum { EFE_STEP_KEEP_HAM = 1 };
 

@@ -1384,6 +1384,23 @@ efe_status magnus_step(efe_ctx *ctx, void *Psi, int64_t ld, double t, double dt,
   return hist_push(ctx, dt);
 }
 
+efe_status absorption_spectrum(const double *mu, const int32_t *dirs, int32_t ndir, int64_t nt, double dt,
+                               const efe_pulse *pulse, double tau, const double *omega, int64_t nw, double *S,
+                               double *alpha, void *hip_stream) {
+  if (!mu || !dirs || !pulse || !omega || !S || ndir < 1 || ndir > 3 || nt < 1 || nw < 1 || nw > (1LL << 31) ||
+      !(dt > 0.0) || !(tau > 0.0) || (pulse->kind != 0 && pulse->kind != 1) || !std::isfinite(pulse->kappa) ||
+      pulse->kappa == 0.0 || (pulse->kind == 1 && !(pulse->s > 0.0)))
+    return EFE_ERR_ARG;
+  for (int r = 0; r < ndir; ++r)
+    if (dirs[r] < 0 || dirs[r] > 2) return EFE_ERR_ARG;
+  hipStream_t st = (hipStream_t)hip_stream;
+  efe::k::spectrum(mu, dirs, ndir, nt + 1, dt, tau, pulse->kind, pulse->kappa, pulse->t0, pulse->s, omega, nw, S,
+                   alpha, st);
+  if (hipGetLastError() != hipSuccess) return EFE_ERR_HIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return EFE_ERR_HIP;
+  return EFE_OK;
+}
+
 efe_status magnus_step_extrap(efe_ctx *ctx, void *Psi, int64_t ld, double t, double dt, const efe_field *field,
                               const int32_t *k_force, int32_t flags, efe_step_stats *stats) {
   if (!ctx || !Psi || ld < ctx->norb || !std::isfinite(t) || !std::isfinite(dt) || (flags & ~EFE_STEP_KEEP_HAM))

@@ -134,6 +134,11 @@ int dot_partials(const double *x, const double *y, int64_t n, double *part, hipS
 void reduce_partials(const double *part, int nblk, int nval, double *out, hipStream_t s);
 void dipole_partials(const DevData &d, const double *rho, double *part, int *nblk, hipStream_t s);
 
+// absorption spectrum (Sec. 3.2): S[nw], alpha[ndir][nw][2] (may be null) from traces mu[ndir][nt1][3]
+void spectrum(const double *mu, const int *dirs, int ndir, int64_t nt1, double dt, double tau, int kind,
+              double kappa, double t0, double s, const double *omega, int64_t nw, double *S, double *alpha,
+              hipStream_t st);
+
 // Lanczos vectors (unnormalised basis: slot 0 = q0, slot l >= 1 = qb + (l - 1) * bs)
 int lz_dots(const double *q0, const double *qb, int64_t bs, int nq, const double *w, int64_t nrows, int ncol,
             const int *mask, const int *any, int with_norm, double *part, hipStream_t s);

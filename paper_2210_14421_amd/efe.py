@@ -50,6 +50,10 @@ class EfeField(C.Structure):
                 ("A", _dp), ("w", _dp), ("phi", _dp), ("t0", C.c_double), ("s", C.c_double)]
 
 
+class EfePulse(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("kappa", C.c_double), ("t0", C.c_double), ("s", C.c_double)]
+
+
 class EfeStepStats(C.Structure):
     _fields_ = [("k_pred", C.c_int32 * 128), ("k_corr", C.c_int32 * 128), ("err_pred_max", C.c_double),
                 ("err_corr_max", C.c_double), ("cg_iters", C.c_int32 * 2), ("mu", C.c_double * 3)]
@@ -81,6 +85,9 @@ _magnus = _sig("magnus_step", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c
 _magnus_extrap = _sig("magnus_step_extrap", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_double,
                                                         C.POINTER(EfeField), _ip, C.c_int32, C.POINTER(EfeStepStats)])
 EFE_STEP_KEEP_HAM = 1
+_spectrum = _sig("absorption_spectrum", C.c_int32, [C.c_void_p, _ip, C.c_int32, C.c_int64, C.c_double,
+                                                     C.POINTER(EfePulse), C.c_double, C.c_void_p, C.c_int64,
+                                                     C.c_void_p, C.c_void_p, C.c_void_p])
 _magnus_graph = _sig("magnus_step_graph", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_double,
                                                       C.POINTER(EfeField), C.POINTER(EfeStepStats)])
 _batch_create = _sig("efe_batch_create", C.c_int32, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p)])
@@ -104,7 +111,7 @@ EXPORTED = ["efe_plan_create", "efe_plan_free", "efe_plan_sizes", "efe_plan_get"
             "efe_set_hamiltonian", "efe_apply_H", "lanczos_expm", "magnus_step", "density",
             "efe_hartree", "dipole", "efe_enable_timing", "efe_get_timing", "efe_last_error",
             "magnus_step_graph", "efe_batch_create", "efe_batch_free", "efe_batch_error", "efe_batch_step",
-            "magnus_adjoint", "dipole_adjoint", "magnus_step_extrap"]
+            "magnus_adjoint", "dipole_adjoint", "magnus_step_extrap", "absorption_spectrum"]
 
 
 class EfeError(RuntimeError):
@@ -182,6 +189,37 @@ class Plan:
         if getattr(self, "_p", None):
             _plan_free(self._p)
             self._p = None
+
+
+def absorption_spectrum(mu, dirs, dt, omega, tau, pulse, with_alpha=False):
+    """S(omega) of Sec. 3.2 on the GPU from dipole traces.
+
+    mu: cuda float64 tensor [ndir][nt + 1][3] (run r perturbed along dirs[r]);
+    omega: cuda float64 tensor [nw]; pulse: dict(kind="kick"|"gauss", kappa, t0, s).
+    Returns S (cuda [nw]) and, with with_alpha, alpha (cuda complex128 [ndir][nw])."""
+    import torch
+    if mu.dtype != torch.float64 or not mu.is_cuda or mu.dim() != 3 or mu.shape[2] != 3:
+        raise ValueError("mu must be a cuda float64 tensor [ndir][nt + 1][3]")
+    if omega.dtype != torch.float64 or not omega.is_cuda or omega.dim() != 1:
+        raise ValueError("omega must be a cuda float64 tensor [nw]")
+    mu, omega = mu.contiguous(), omega.contiguous()
+    d = _arr(dirs, np.int32)
+    if len(d) != mu.shape[0]:
+        raise ValueError("one direction per trace")
+    p = EfePulse()
+    p.kind = {"kick": 0, "gauss": 1}[pulse["kind"]]
+    p.kappa, p.t0, p.s = float(pulse["kappa"]), float(pulse.get("t0", 0.0)), float(pulse.get("s", 1.0))
+    S = torch.empty(omega.shape[0], dtype=torch.float64, device=omega.device)
+    alpha = torch.empty((mu.shape[0], omega.shape[0], 2), dtype=torch.float64, device=omega.device) if with_alpha else None
+    st = _spectrum(C.c_void_p(mu.data_ptr()), d.ctypes.data_as(_ip), len(d), mu.shape[1] - 1, float(dt), C.byref(p),
+                   float(tau), C.c_void_p(omega.data_ptr()), omega.shape[0], C.c_void_p(S.data_ptr()),
+                   C.c_void_p(alpha.data_ptr()) if with_alpha else None,
+                   C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if st != EFE_OK:
+        raise EfeError(st, "absorption_spectrum")
+    if with_alpha:
+        return S, torch.view_as_complex(alpha)
+    return S
 
 
 def make_field(direction=2, A=(), w=(), phi=(), t0=0.0, s=1.0):
