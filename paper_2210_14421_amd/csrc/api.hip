@@ -57,6 +57,7 @@ struct efe_ctx {
   double *phi = nullptr, *dvec = nullptr, *rhs = nullptr;
   double *cg[7] = {nullptr};
   double *part = nullptr, *hee_part = nullptr, *G = nullptr, *Hee_raw = nullptr, *Hbar_ee = nullptr;
+  double *hee_blk = nullptr;   // block sums of the H^ee partials
   double *psiE = nullptr, *red = nullptr, *small = nullptr, *couple_scr = nullptr;
   efe::k::DenWork den, adj_den;   // density workspaces (forward columns; adjoint column pairs)
   int64_t red_len = 0;
@@ -355,6 +356,7 @@ efe_status build_device(efe_ctx *ctx) {
   EFE_TRY(dalloc(ctx, &ctx->hee_part, thee[d.nt]));
   EFE_TRY(dalloc(ctx, &ctx->G, d.nr * std::max(1, d.nk)));
   EFE_TRY(dalloc(ctx, &ctx->Hee_raw, (int64_t)d.ne * d.ne));
+  EFE_TRY(dalloc(ctx, &ctx->hee_blk, std::max<int64_t>(1, efe::k::hee_scratch_size(d))));
   EFE_TRY(dalloc(ctx, &ctx->Hbar_ee, (int64_t)d.nk * d.nk));
   EFE_TRY(dalloc(ctx, &ctx->psiE, (int64_t)d.ne * ctx->ncolr));
   if (efe::k::density_folded_ok(d)) {
@@ -517,7 +519,7 @@ efe_status rebuild(efe_ctx *ctx, int mode, const double *rho, double t, const ef
   efe::k::rebuild_cells(d, mode, rho, ctx->phi, ctx->stepp + 2, fdir, ctx->plan.xc, ctx->cells, ctx->dtype, ctx->vq, s);
   efe::k::coupling_partials(d, ctx->vq, ctx->part, ctx->hee_part, s);
   efe::k::coupling_gather(d, ctx->part, mode == 0 ? 1 : 0, ctx->G, s);
-  efe::k::hee_reduce(d, ctx->hee_part, mode == 0 ? 1 : 0, ctx->Hee_raw, ctx->Hbar_ee, s);
+  efe::k::hee_reduce(d, ctx->hee_part, mode == 0 ? 1 : 0, ctx->Hee_raw, ctx->Hbar_ee, ctx->hee_blk, s);
   tstop(ctx, 6);
   ctx->cells_mode = mode;
   return check_launch(ctx, "rebuild");
@@ -745,7 +747,7 @@ efe_status rebuild_dev(efe_ctx *ctx, const double *rho, const double *efield, in
   efe::k::rebuild_cells(d, 0, rho, ctx->phi, efield, fdir, ctx->plan.xc, ctx->cells, ctx->dtype, ctx->vq, s);
   efe::k::coupling_partials(d, ctx->vq, ctx->part, ctx->hee_part, s);
   efe::k::coupling_gather(d, ctx->part, 1, ctx->G, s);
-  efe::k::hee_reduce(d, ctx->hee_part, 1, ctx->Hee_raw, ctx->Hbar_ee, s);
+  efe::k::hee_reduce(d, ctx->hee_part, 1, ctx->Hee_raw, ctx->Hbar_ee, ctx->hee_blk, s);
   return check_launch(ctx, "device rebuild");
 }
 

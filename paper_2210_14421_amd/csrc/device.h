@@ -85,8 +85,10 @@ void rebuild_cells(const DevData &d, int mode, const double *rho, const double *
                    int xc, void *cells, int dtype, double *vq, hipStream_t s);
 void coupling_partials(const DevData &d, const double *vq, double *part, double *hee_part, hipStream_t s);
 void coupling_gather(const DevData &d, const double *part, int kinetic, double *G, hipStream_t s);
+// scratch: hee_scratch_size(d) doubles
+int64_t hee_scratch_size(const DevData &d);
 void hee_reduce(const DevData &d, const double *hee_part, int kinetic, double *Hee_raw, double *Hbar_ee,
-                hipStream_t s);
+                double *scratch, hipStream_t s);
 
 // Hbar X
 // raises the dynamic LDS limit of the cell-product kernels for cells of nloc nodes; 0 on success

@@ -332,65 +332,137 @@ k_coupling_mfma(const DevData d, const double *__restrict__ vq, double *__restri
 }
 
 // G[r][kappa] = D^-1/2_r sum_nu (Kce[r][nu] + sum_cells part) S[nu][kappa]  (Hbar^ce rows)
+// G[r][kp] = D_r^-1/2 sum_nu a[r][nu] S[nu][kp] with a[r][nu] = Kce[r][nu] (kinetic)
+// + the partials of the T-cells that contain the node of union row r, on the
+// FP64 16x16x4 MFMA: one wave per block walks a contiguous range of 16-row
+// tiles for 48 columns of G (blockIdx.y).  Lane (row i, k) forms its entries
+// of the A tile a[r0 + i][4 s + k] from the row's cell pairs (at most 8).
+constexpr int kGatherWaves = 4096;
+
 __global__ void __launch_bounds__(64)
-k_coupling_gather(const DevData d, const double *__restrict__ part, int kinetic, double *__restrict__ G) {
-  extern __shared__ double sm[];
+k_coupling_gather(const DevData d, const double *__restrict__ part, int kinetic, double *__restrict__ G,
+                  int64_t tiles_per_wave) {
+  typedef double v4d __attribute__((ext_vector_type(4)));
   const int ne = d.ne, nk = d.nk;
-  double *Ss = sm;                          // ne*nk
-  double *acc = Ss + ne * nk;               // 64*ne
-  for (int t = threadIdx.x; t < ne * nk; t += blockDim.x) Ss[t] = d.S[t];
-  __syncthreads();
-  const int64_t r = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  if (r >= d.nr) return;
-  double *a = acc + threadIdx.x * ne;
-  for (int v = 0; v < ne; ++v) a[v] = kinetic ? d.Kce[r * ne + v] : 0.0;
-  const int cnt = d.urow_cnt[r];
-  for (int k = 0; k < cnt; ++k) {
-    int pr = d.urow_pair[r * 8 + k];
-    int slot = pr >> 8, l = pr & 255;
-    int k0 = d.tnu_off[slot], nnu = d.tnu_off[slot + 1] - k0;
-    const double *ps = part + d.tpart_off[slot] + (int64_t)l * nnu;
-    for (int kk = 0; kk < nnu; ++kk) a[d.tnu[k0 + kk]] += ps[kk];
-  }
-  const double dm = d.Dm12[d.urow_node[r]];
-  for (int kp = 0; kp < nk; ++kp) {
-    double s = 0.0;
-    for (int v = 0; v < ne; ++v) s += a[v] * Ss[v * nk + kp];
-    G[r * nk + kp] = dm * s;
+  const int64_t nr = d.nr;
+  const int lane = threadIdx.x, kr = lane >> 4, cl = lane & 15;
+  const int n0 = blockIdx.y * 48;
+  const int64_t ntiles = (nr + 15) / 16;
+  const int64_t t_begin = (int64_t)blockIdx.x * tiles_per_wave;
+  const int64_t t_end = t_begin + tiles_per_wave < ntiles ? t_begin + tiles_per_wave : ntiles;
+  const int nks = (ne + 3) / 4;
+  for (int64_t t = t_begin; t < t_end; ++t) {
+    const int64_t r0 = t * 16, ra = r0 + cl;
+    const bool rok = ra < nr;
+    // the row's (slot, local node) pairs: base offset of the partials and the slot
+    int cnt = rok ? d.urow_cnt[ra] : 0;
+    int slot[8];
+    int64_t base[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      slot[p] = 0;
+      base[p] = 0;
+      if (p < cnt) {
+        const int pr = d.urow_pair[ra * 8 + p];
+        const int sl = pr >> 8, l = pr & 255;
+        const int nnu = d.tnu_off[sl + 1] - d.tnu_off[sl];
+        slot[p] = sl;
+        base[p] = d.tpart_off[sl] + (int64_t)l * nnu;
+      }
+    }
+    v4d acc[3];
+#pragma unroll
+    for (int nt = 0; nt < 3; ++nt) acc[nt] = v4d{0, 0, 0, 0};
+    for (int ks = 0; ks < nks; ++ks) {
+      const int nu = ks * 4 + kr;
+      double a = 0.0;
+      if (rok && nu < ne) {
+        a = kinetic ? d.Kce[ra * ne + nu] : 0.0;
+#pragma unroll
+        for (int p = 0; p < 8; ++p) {
+          if (p < cnt) {
+            const int pos = d.tpos[(int64_t)slot[p] * ne + nu];
+            if (pos >= 0) a += part[base[p] + pos];
+          }
+        }
+      }
+#pragma unroll
+      for (int nt = 0; nt < 3; ++nt) {
+        const int kp = n0 + nt * 16 + cl;
+        const double bv = (nu < ne && kp < nk) ? d.S[nu * nk + kp] : 0.0;
+        acc[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[nt], 0, 0, 0);
+      }
+    }
+    // output register r of a lane holds row kr + 4 r, column cl
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = r0 + kr + 4 * r;
+      if (row >= nr) continue;
+      const double dm = d.Dm12[d.urow_node[row]];
+#pragma unroll
+      for (int nt = 0; nt < 3; ++nt) {
+        const int kp = n0 + nt * 16 + cl;
+        if (kp < nk) G[row * nk + kp] = dm * acc[nt][r];
+      }
+    }
   }
 }
 
-// H^ee = Kee + sum over T-cells of the partials (fixed slot order)
-__global__ void k_hee_sum(const DevData d, const double *__restrict__ hee_part, int kinetic, double *__restrict__ Hraw) {
-  const int ne = d.ne;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= ne * ne) return;
-  const int mu = t / ne, nu = t % ne;
-  double s = kinetic ? d.Kee[t] : 0.0;
-  for (int slot = 0; slot < d.nt; ++slot) {
-    int i = d.tpos[(int64_t)slot * ne + mu], j = d.tpos[(int64_t)slot * ne + nu];
-    if (i >= 0 && j >= 0) {
-      int nnu = d.tnu_off[slot + 1] - d.tnu_off[slot];
-      s += hee_part[d.thee_off[slot] + i * nnu + j];
+// H^ee partial sums over contiguous ranges of T-cell slots: workgroup b adds the
+// nnu x nnu partials of its slots, one slot after another, into an LDS copy of
+// the ne x ne matrix (the entries of one slot are distinct) and writes it as
+// blk[b]; k_hee_sum adds the blocks in order.
+constexpr int kHeeBlocks = 64;
+
+__global__ void __launch_bounds__(256)
+k_hee_blocks(const DevData d, const double *__restrict__ hee_part, double *__restrict__ blk) {
+  extern __shared__ double hacc[];
+  const int ne = d.ne, ne2 = ne * ne;
+  for (int t = threadIdx.x; t < ne2; t += blockDim.x) hacc[t] = 0.0;
+  const int per = (d.nt + gridDim.x - 1) / gridDim.x;
+  const int s0 = blockIdx.x * per, s1 = s0 + per < d.nt ? s0 + per : d.nt;
+  __syncthreads();
+  for (int sl = s0; sl < s1; ++sl) {
+    const int k0 = d.tnu_off[sl], nnu = d.tnu_off[sl + 1] - k0;
+    const double *hp = hee_part + d.thee_off[sl];
+    for (int t = threadIdx.x; t < nnu * nnu; t += blockDim.x) {
+      const int i = t / nnu, j = t % nnu;
+      hacc[d.tnu[k0 + i] * ne + d.tnu[k0 + j]] += hp[t];
     }
+    __syncthreads();
   }
+  for (int t = threadIdx.x; t < ne2; t += blockDim.x) blk[(int64_t)blockIdx.x * ne2 + t] = hacc[t];
+}
+
+// H^ee = Kee + the block sums of k_hee_blocks (fixed order)
+__global__ void k_hee_sum(const DevData d, const double *__restrict__ blk, int nblk, int kinetic,
+                          double *__restrict__ Hraw) {
+  const int ne2 = d.ne * d.ne;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ne2) return;
+  double s = kinetic ? d.Kee[t] : 0.0;
+  for (int b = 0; b < nblk; ++b) s += blk[(int64_t)b * ne2 + t];
   Hraw[t] = s;
 }
 
-// Hbar^ee = S^T H^ee S
-__global__ void k_hee_loewdin(const DevData d, const double *__restrict__ Hraw, double *__restrict__ Hbar) {
+// Hbar^ee = S^T H^ee S in two products: T = H^ee S (ne x nk), then S^T T
+__global__ void k_hee_hs(const DevData d, const double *__restrict__ Hraw, double *__restrict__ T) {
+  const int ne = d.ne, nk = d.nk;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ne * nk) return;
+  const int mu = t / nk, b = t % nk;
+  double s = 0.0;
+  for (int nu = 0; nu < ne; ++nu) s += Hraw[mu * ne + nu] * d.S[nu * nk + b];
+  T[t] = s;
+}
+
+__global__ void k_hee_loewdin(const DevData d, const double *__restrict__ T, double *__restrict__ Hbar) {
   const int ne = d.ne, nk = d.nk;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nk * nk) return;
   const int a = t / nk, b = t % nk;
   double s = 0.0;
-  for (int mu = 0; mu < ne; ++mu) {
-    double sm = d.S[mu * nk + a];
-    if (sm == 0.0) continue;
-    double inner = 0.0;
-    for (int nu = 0; nu < ne; ++nu) inner += Hraw[mu * ne + nu] * d.S[nu * nk + b];
-    s += sm * inner;
-  }
+  for (int mu = 0; mu < ne; ++mu) s += d.S[mu * nk + a] * T[mu * nk + b];
   Hbar[t] = s;
 }
 
@@ -1251,14 +1323,27 @@ void coupling_partials(const DevData &d, const double *vq, double *part, double 
 
 void coupling_gather(const DevData &d, const double *part, int kinetic, double *G, hipStream_t s) {
   if (d.nr == 0 || d.nk == 0) return;
-  size_t lds = ((size_t)d.ne * d.nk + 64 * d.ne) * sizeof(double);
-  hipLaunchKernelGGL(k_coupling_gather, dim3(nblocks(d.nr, 64)), dim3(64), lds, s, d, part, kinetic, G);
+  const int64_t ntiles = (d.nr + 15) / 16;
+  const int64_t nw = ntiles < kGatherWaves ? ntiles : kGatherWaves;
+  const int64_t tpw = (ntiles + nw - 1) / nw;
+  const unsigned ny = (unsigned)((d.nk + 47) / 48);
+  hipLaunchKernelGGL(k_coupling_gather, dim3((unsigned)((ntiles + tpw - 1) / tpw), ny), dim3(64), 0, s, d, part,
+                     kinetic, G, tpw);
 }
 
-void hee_reduce(const DevData &d, const double *hee_part, int kinetic, double *Hraw, double *Hbar, hipStream_t s) {
+int64_t hee_scratch_size(const DevData &d) { return (int64_t)kHeeBlocks * d.ne * d.ne; }
+
+void hee_reduce(const DevData &d, const double *hee_part, int kinetic, double *Hraw, double *Hbar, double *scratch,
+                hipStream_t s) {
   if (d.ne == 0) return;
-  hipLaunchKernelGGL(k_hee_sum, dim3(nblocks(d.ne * d.ne, 64)), dim3(64), 0, s, d, hee_part, kinetic, Hraw);
-  hipLaunchKernelGGL(k_hee_loewdin, dim3(nblocks(d.nk * d.nk, 64)), dim3(64), 0, s, d, Hraw, Hbar);
+  const int nblk = d.nt > 0 ? kHeeBlocks : 0;
+  if (nblk > 0)
+    hipLaunchKernelGGL(k_hee_blocks, dim3(nblk), dim3(256), (size_t)d.ne * d.ne * sizeof(double), s, d, hee_part,
+                       scratch);
+  hipLaunchKernelGGL(k_hee_sum, dim3(nblocks(d.ne * d.ne, 64)), dim3(64), 0, s, d, scratch, nblk, kinetic, Hraw);
+  // the block sums are consumed: the scratch holds T = H^ee S next
+  hipLaunchKernelGGL(k_hee_hs, dim3(nblocks(d.ne * d.nk, 64)), dim3(64), 0, s, d, Hraw, scratch);
+  hipLaunchKernelGGL(k_hee_loewdin, dim3(nblocks(d.nk * d.nk, 64)), dim3(64), 0, s, d, scratch, Hbar);
 }
 
 void psiE(const DevData &d, const double *X, int ncolr, int64_t ldr, double *out, hipStream_t s) {

@@ -37,6 +37,86 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 constexpr int kCoupleCWaves = 4096;   // four per SIMD
 constexpr int KNT = 6;    // 16-column tiles per block (88 columns = 5.5 tiles)
 
+// Y_C += G X_E for n_k <= 48: a workgroup of kCcWaves waves per (range of
+// 16-row tiles, 48-column slice), X_E of the slice in LDS.  Per tile a wave
+// issues the loads of its A operands (G rows) and of the Y rows it updates
+// before the products, so one wait covers the tile.  Flat block b runs on XCD
+// b mod 8; the slices of one tile range are consecutive blocks of one XCD, so
+// the second slice reads the G tile from L2.
+constexpr int kCcWaves = 4;
+constexpr int kCcBlocks = 1024;   // tile ranges
+constexpr int kCcNT = 3;          // 16-column tiles per slice
+constexpr int kCcMaxK = 48;
+
+__global__ void __launch_bounds__(kCcWaves * 64) __attribute__((amdgpu_waves_per_eu(3)))
+k_couple_c48(const DevData d, const double *__restrict__ G, const double *__restrict__ X, double *__restrict__ Y,
+             int ncolr, int64_t ldr, int64_t tiles_per_block, int nranges, int nslice, const int *__restrict__ any) {
+  if (any && *any == 0) return;
+  __shared__ double xe[kCcMaxK * kCcNT * 16];
+  const int nk = d.nk;
+  const int64_t nr = d.nr;
+  const int b = blockIdx.x, xcd = b & 7, q = b >> 3;
+  const int slice = q % nslice, range = (q / nslice) * 8 + xcd;
+  if (range >= nranges) return;
+  const int tid = threadIdx.x, lane = tid & 63, kr = lane >> 4, cl = lane & 15, wave = tid >> 6;
+  const int n0 = slice * kCcNT * 16;
+  const double *XE = X + (int64_t)d.g.n_nodes * ldr;
+  for (int t = tid; t < kCcMaxK * kCcNT * 16; t += kCcWaves * 64) {
+    const int k = t / (kCcNT * 16), c = n0 + t % (kCcNT * 16);
+    xe[t] = (k < nk && c < ncolr) ? XE[(int64_t)k * ldr + c] : 0.0;
+  }
+  __syncthreads();
+  int col[kCcNT];
+  bool cok[kCcNT];
+#pragma unroll
+  for (int nt = 0; nt < kCcNT; ++nt) {
+    col[nt] = n0 + nt * 16 + cl;
+    cok[nt] = col[nt] < ncolr;
+  }
+  const int64_t ntiles = (nr + 15) / 16;
+  const int64_t t_begin = (int64_t)range * tiles_per_block;
+  const int64_t t_end = t_begin + tiles_per_block < ntiles ? t_begin + tiles_per_block : ntiles;
+  for (int64_t t = t_begin + wave; t < t_end; t += kCcWaves) {
+    const int64_t r0 = t * 16, ra = r0 + cl;
+    const bool rok = ra < nr;
+    double a[kCcMaxK / 4];
+#pragma unroll
+    for (int ks = 0; ks < kCcMaxK / 4; ++ks) {
+      const int k = ks * 4 + kr;
+      a[ks] = (rok && k < nk) ? G[ra * nk + k] : 0.0;
+    }
+    int64_t yoff[4];
+    double yv[4][kCcNT];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = r0 + kr + 4 * r;
+      yoff[r] = row < nr ? d.urow_node[row] * ldr : -1;
+#pragma unroll
+      for (int nt = 0; nt < kCcNT; ++nt) yv[r][nt] = (yoff[r] >= 0 && cok[nt]) ? Y[yoff[r] + col[nt]] : 0.0;
+    }
+    v4d acc[kCcNT];
+#pragma unroll
+    for (int nt = 0; nt < kCcNT; ++nt) acc[nt] = v4d{0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < kCcMaxK / 4; ++ks) {
+#pragma unroll
+      for (int nt = 0; nt < kCcNT; ++nt) {
+        const double bv = xe[(ks * 4 + kr) * (kCcNT * 16) + nt * 16 + cl];
+        acc[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], bv, acc[nt], 0, 0, 0);
+      }
+    }
+    // output register r of a lane holds row kr + 4 r, column cl
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (yoff[r] < 0) continue;
+#pragma unroll
+      for (int nt = 0; nt < kCcNT; ++nt)
+        if (cok[nt]) Y[yoff[r] + col[nt]] = yv[r][nt] + acc[nt][r];
+    }
+  }
+}
+
+// general n_k: one wave per block, X_E from global memory
 __global__ void __launch_bounds__(64)
 k_couple_c(const DevData d, const double *__restrict__ G, const double *__restrict__ X, double *__restrict__ Y,
            int ncolr, int64_t ldr, int64_t tiles_per_wave, const int *__restrict__ any) {
@@ -387,9 +467,18 @@ void couple_apply(const DevData &d, const double *G, const double *Hee, const do
     const unsigned ny = (unsigned)((ncolr + kCpNT * 16 - 1) / (kCpNT * 16));
     const unsigned nz = (unsigned)((d.nk + kCpMT * 16 - 1) / (kCpMT * 16));
     const unsigned nyc = (unsigned)((ncolr + KNT * 16 - 1) / (KNT * 16));
-    const int64_t tpc = (ntiles + kCoupleCWaves - 1) / kCoupleCWaves;
-    hipLaunchKernelGGL(k_couple_c, dim3((unsigned)((ntiles + tpc - 1) / tpc), nyc), dim3(64), 0, s, d, G, X, Y, ncolr,
-                       ldr, tpc, any);
+    if (d.nk <= kCcMaxK) {
+      const int64_t tpr = (ntiles + kCcBlocks - 1) / kCcBlocks;
+      const int nranges = (int)((ntiles + tpr - 1) / tpr);
+      const int nslice = (ncolr + kCcNT * 16 - 1) / (kCcNT * 16);
+      const unsigned nb = (unsigned)(((nranges + 7) / 8) * 8 * nslice);
+      hipLaunchKernelGGL(k_couple_c48, dim3(nb), dim3(kCcWaves * 64), 0, s, d, G, X, Y, ncolr, ldr, tpr, nranges,
+                         nslice, any);
+    } else {
+      const int64_t tpc = (ntiles + kCoupleCWaves - 1) / kCoupleCWaves;
+      hipLaunchKernelGGL(k_couple_c, dim3((unsigned)((ntiles + tpc - 1) / tpc), nyc), dim3(64), 0, s, d, G, X, Y,
+                         ncolr, ldr, tpc, any);
+    }
     hipLaunchKernelGGL(k_couple_e, dim3((unsigned)nblk, ny, nz), dim3(kCpWaves * 64), 0, s, d, G, X, ncolr, ldr, tpb,
                        scratch, any);
     nsl = kCpSlices;
