@@ -323,7 +323,7 @@ def main():
     ap.add_argument("--no-extrap", action="store_true")
     ap.add_argument("--workload", default="na8", choices=["na8", "tiny", "na2", "batch", "adjoint"])
     ap.add_argument("--mode", default="step", choices=["step", "apply"])
-    ap.add_argument("--dtype", default="f64", choices=["f64", "f32", "bf16"])
+    ap.add_argument("--dtype", default="f64", choices=["f64", "f32", "bf16", "f64sf"])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -387,6 +387,18 @@ def main():
                          "dtype": "f64", "value": ev, "unit": "steps/s", "ms_per_step": 1e3 * eres["wall"] / args.steps,
                          "speedup_vs_predictor_corrector": ev / value, "orthonormality_error": eres["orth"],
                          "stage_ms_per_step": {k: v / args.steps for k, v in eres["stage"].items() if k != "n_hx"}}
+    if not args.no_mixed:
+        # the same FP64 operator applied by sum factorisation (no stored cell blocks)
+        sres = run_gpu(spec, "f64sf", args.steps, args.warmup, args.kmax)
+        sv = args.steps / sres["wall"]
+        import numpy as np
+        dmu = np.max(np.linalg.norm(np.array(sres["mu"]) - np.array(res["mu"]), axis=1)) / \
+            np.max(np.linalg.norm(np.array(res["mu"]), axis=1))
+        out["sum_factorised"] = {"dtype": "f64, sum-factorised cell products, no stored blocks", "value": sv,
+                                 "unit": "steps/s", "ms_per_step": 1e3 * sres["wall"] / args.steps,
+                                 "speedup_vs_f64": sv / value, "dipole_rel_diff_vs_f64": float(dmu),
+                                 "stage_ms_per_step": {k: v / args.steps for k, v in sres["stage"].items()
+                                                       if k != "n_hx"}}
     if not args.no_extrap:
         out["spectrum"] = run_spectrum_timing()
     if not args.no_cpu:

@@ -279,6 +279,17 @@ efe_status build_device(efe_ctx *ctx) {
     d.colour_off[c + 1] = (int)colour.size();
   }
   EFE_TRY(upload(ctx, &d.colour_cells, colour));
+  {
+    std::vector<int> so, se;
+    d.sf_off[0] = d.sf_off[1] = 0;
+    for (int c = 0; c < 8; ++c) {
+      for (int v : col[c]) (pl.is_enr[v] ? se : so).push_back(v);
+      d.sf_off[2 * c + 2] = (int)so.size();
+      d.sf_off[2 * c + 3] = (int)se.size();
+    }
+    EFE_TRY(upload(ctx, &d.sf_ord, so));
+    EFE_TRY(upload(ctx, &d.sf_enr, se));
+  }
   std::vector<int> slot(pl.n_cells);
   for (size_t i = 0; i < colour.size(); ++i) slot[colour[i]] = (int)i;
   EFE_TRY(upload(ctx, &d.cell_slot, slot));
@@ -334,13 +345,26 @@ efe_status build_device(efe_ctx *ctx) {
   ctx->ncolr = 2 * pl.norb;
   ctx->n_rows = pl.n_nodes + pl.nk;
   ctx->blk = ctx->n_rows * ctx->ncolr;
-  const size_t esz = ctx->dtype == 0 ? 8 : (ctx->dtype == 1 ? 4 : 2);
-  void *cells = nullptr;
-  size_t cbytes = (size_t)pl.n_cells * d.g.cstride * esz;
-  hipError_t e = hipMalloc(&cells, cbytes);
-  if (e != hipSuccess) { ctx->err = "cell blocks: " + std::string(hip_err(e)); return EFE_ERR_ALLOC; }
-  ctx->allocs.push_back(cells);
-  ctx->cells = cells;
+  if (ctx->dtype == 3) {
+    // sum-factorised products read the potential at the points; no blocks are stored
+    if (!efe::k::sf_supported(d.g)) {
+      ctx->err = "sum-factorised products need degree 4 or 5 with the default Gauss rules";
+      return EFE_ERR_ARG;
+    }
+    if (efe::k::sf_init(d.g) != 0) {
+      ctx->err = "sum-factorised products: LDS limit not accepted";
+      return EFE_ERR_HIP;
+    }
+    ctx->cells = nullptr;
+  } else {
+    const size_t esz = ctx->dtype == 0 ? 8 : (ctx->dtype == 1 ? 4 : 2);
+    void *cells = nullptr;
+    size_t cbytes = (size_t)pl.n_cells * d.g.cstride * esz;
+    hipError_t e = hipMalloc(&cells, cbytes);
+    if (e != hipSuccess) { ctx->err = "cell blocks: " + std::string(hip_err(e)); return EFE_ERR_ALLOC; }
+    ctx->allocs.push_back(cells);
+    ctx->cells = cells;
+  }
   EFE_TRY(dalloc(ctx, &ctx->Q, ctx->blk * ctx->kmax));
   EFE_TRY(dalloc(ctx, &ctx->X0, ctx->blk));
   EFE_TRY(dalloc(ctx, &ctx->X1, ctx->blk));
@@ -420,7 +444,8 @@ efe_status apply_op(efe_ctx *ctx, const double *X, double *Y, int ncolr, int64_t
     return EFE_ERR_ARG;
   }
   tstart(ctx, 0);
-  efe::k::cell_apply(d, ctx->cells, ctx->dtype, X, Y, ncolr, ldr, s, any);
+  if (ctx->dtype == 3) efe::k::sf_apply(d, ctx->vq, ctx->cells_mode == 0 ? 1 : 0, X, Y, ncolr, ldr, s, any);
+  else efe::k::cell_apply(d, ctx->cells, ctx->dtype, X, Y, ncolr, ldr, s, any);
   tstop(ctx, 0);
   tstart(ctx, 1);
   efe::k::couple_apply(d, ctx->G, ctx->Hbar_ee, X, Y, ncolr, ldr, ctx->couple_scr, s, any);
@@ -1242,7 +1267,7 @@ efe_status efe_plan_get(const efe_plan *plan, const char *name, double *out, int
 efe_status efe_setup(const efe_system *sys, const efe_options *opt, efe_ctx **out) {
   if (!sys || !opt || !out) return EFE_ERR_ARG;
   *out = nullptr;
-  if (opt->prod_dtype < 0 || opt->prod_dtype > 2 || opt->kmax < 1 || opt->kmax > 64) return EFE_ERR_ARG;
+  if (opt->prod_dtype < 0 || opt->prod_dtype > 3 || opt->kmax < 1 || opt->kmax > 64) return EFE_ERR_ARG;
   efe_ctx *ctx = new (std::nothrow) efe_ctx();
   if (!ctx) return EFE_ERR_ALLOC;
   ctx->opt = *opt;

@@ -39,6 +39,10 @@ struct DevData {
   int *colour_cells = nullptr;    // cells grouped by colour
   int *cell_slot = nullptr;       // n_cells: storage slot of the cell block (colour-major order)
   int colour_off[9] = {0};
+  // cells of each colour by class (sum-factorised products): colour c's ordinary cells are
+  // sf_ord[sf_off[2c] .. sf_off[2c+2]), its enrichment cells sf_enr[sf_off[2c+1] .. sf_off[2c+3])
+  int *sf_ord = nullptr, *sf_enr = nullptr;
+  int sf_off[18] = {0};
   double *D = nullptr, *Dm12 = nullptr;   // lumped mass, D^-1/2 (0 on boundary)
   double *vstatic = nullptr;      // n_quad
   double *occ = nullptr;          // norb
@@ -95,6 +99,12 @@ void hee_reduce(const DevData &d, const double *hee_part, int kinetic, double *H
 int cell_apply_init(int nloc);
 void cell_apply(const DevData &d, const void *cells, int dtype, const double *X, double *Y, int ncolr, int64_t ldr,
                 hipStream_t s, const int *any = nullptr);
+// sum-factorised cell products (FP64, no stored blocks): Y = sum_c P_c^T Hbar_c P_c X from the
+// potential at the quadrature points (vq) and, with kinetic, the kinetic term
+bool sf_supported(const Geom &g);
+int sf_init(const Geom &g);
+void sf_apply(const DevData &d, const double *vq, int kinetic, const double *X, double *Y, int ncolr, int64_t ldr,
+              hipStream_t s, const int *any = nullptr);
 void couple_apply(const DevData &d, const double *G, const double *Hee, const double *X, double *Y,
                   int ncolr, int64_t ldr, double *scratch, hipStream_t s, const int *any = nullptr);
 

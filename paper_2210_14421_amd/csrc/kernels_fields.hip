@@ -104,6 +104,7 @@ k_rebuild(const DevData d, const int *__restrict__ cell_list, int n, int mode, c
     vq[q0 + q] = v;
     wv[q] = w * v;
   }
+  if (!cells) return;   // sum-factorised products: the potential at the points is all they read
   __syncthreads();
   // U[k][j][pa] = sum_i wv[k][j][i] G1[i][pa]
   for (int t = threadIdx.x; t < n * n * NP; t += blockDim.x) {
@@ -1298,7 +1299,7 @@ void rebuild_cells(const DevData &d, int mode, const double *rho, const double *
     int n = cls ? d.g.qe : d.g.qc;
     const int *list = cls ? d.cells_enr : d.cells_ord;
     size_t lds = rebuild_lds(d.g, n);
-    if (dtype == 0)
+    if (dtype == 0 || dtype == 3)
       hipLaunchKernelGGL(k_rebuild<double>, dim3(nc), dim3(kThreads), lds, s, d, list, n, mode, rho, phi, efield, fdir,
                          xc, (double *)cells, vq);
     else if (dtype == 1)
