@@ -84,14 +84,21 @@ k_sf_apply(const DevData d, const int *__restrict__ cell_list, const double *__r
   }
   __syncthreads();
 
-  // 1: x-lines (b, c) of u = D^-1/2 X
-  for (int it = tid; it < P2 * F; it += kSfThreads) {
+  // 1: x-lines (b, c) of u = D^-1/2 X; the thread of x-line item tid also loads the
+  // output rows it adds to in stage 5 (nodes another colour reached first)
+  static_assert(P * P * F <= kSfThreads, "one x-line item per thread");
+  const bool xl = tid < P2 * F;
+  double yold[P];
+  {
+    const int it = xl ? tid : 0;
     const int f = it % F, bc = it / F, col = c0 + f;
+    const bool ok = xl && col < ncolr;
     double u[P];
 #pragma unroll
     for (int a = 0; a < P; ++a) {
       const int l = a + P * bc;
-      u[a] = col < ncolr ? dm[l] * X[rowoff[l] + col] : 0.0;
+      u[a] = ok ? dm[l] * X[rowoff[l] + col] : 0.0;
+      yold[a] = (ok && !first[l]) ? Y[rowoff[l] + col] : 0.0;
     }
 #pragma unroll
     for (int a = 0; a < P; ++a) {
@@ -101,15 +108,17 @@ k_sf_apply(const DevData d, const int *__restrict__ cell_list, const double *__r
         sm += sM[0][a * P + a2] * u[a2];
         sk += sK[0][a * P + a2] * u[a2];
       }
-      mx[(a + P * bc) * F + f] = sm;
-      kx[(a + P * bc) * F + f] = sk;
+      if (xl) {
+        mx[(a + P * bc) * F + f] = sm;
+        kx[(a + P * bc) * F + f] = sk;
+      }
     }
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       double s = 0.0;
 #pragma unroll
       for (int a = 0; a < P; ++a) s += sB[i * P + a] * u[a];
-      px[(i + N * bc) * F + f] = s;       // [c][b][i]
+      if (xl) px[(i + N * bc) * F + f] = s;       // [c][b][i]
     }
   }
   __syncthreads();
@@ -204,8 +213,9 @@ k_sf_apply(const DevData d, const int *__restrict__ cell_list, const double *__r
     for (int b = 0; b < P; ++b) ry[(i + N * b + N * P * c) * F + f] = r[b];
   }
   __syncthreads();
-  // 5: back along x, lines (b, c); add the kinetic part, scale, store
-  for (int it = tid; it < P2 * F; it += kSfThreads) {
+  // 5: back along x, lines (b, c) (the item of stage 1); add the kinetic part, scale, store
+  if (xl) {
+    const int it = tid;
     const int f = it % F, bc = it / F, col = c0 + f;
     double r[P];
 #pragma unroll
@@ -216,13 +226,12 @@ k_sf_apply(const DevData d, const int *__restrict__ cell_list, const double *__r
 #pragma unroll
       for (int a = 0; a < P; ++a) r[a] += sB[i * P + a] * v;
     }
-    if (col >= ncolr) continue;
+    if (col < ncolr) {
 #pragma unroll
-    for (int a = 0; a < P; ++a) {
-      const int l = a + P * bc;
-      const double y = dm[l] * (yk[l * F + f] + r[a]);
-      double *yp = Y + rowoff[l] + col;
-      *yp = first[l] ? y : *yp + y;
+      for (int a = 0; a < P; ++a) {
+        const int l = a + P * bc;
+        Y[rowoff[l] + col] = yold[a] + dm[l] * (yk[l * F + f] + r[a]);
+      }
     }
   }
 }
@@ -232,12 +241,14 @@ size_t sf_lds() {
   return (size_t)(SfLayout<P, N, F>::R1 + SfLayout<P, N, F>::R2) * sizeof(double);
 }
 
-constexpr int kSfCols = 4;   // columns per workgroup
+constexpr int kSfColsOrd = 7;   // columns per workgroup, ordinary cells (P^2 F <= 256)
+constexpr int kSfColsEnr = 4;   // enrichment cells (LDS)
 
 template <int P>
 void sf_launch(const DevData &d, const double *vq, int kinetic, const double *X, double *Y, int ncolr, int64_t ldr,
                hipStream_t s, const int *any) {
-  const unsigned ny = (unsigned)((ncolr + kSfCols - 1) / kSfCols);
+  const unsigned nyo = (unsigned)((ncolr + kSfColsOrd - 1) / kSfColsOrd);
+  const unsigned nye = (unsigned)((ncolr + kSfColsEnr - 1) / kSfColsEnr);
   for (int c = 0; c < 8; ++c) {
     const int cnt = d.colour_off[c + 1] - d.colour_off[c];
     if (cnt == 0) continue;
@@ -247,11 +258,11 @@ void sf_launch(const DevData &d, const double *vq, int kinetic, const double *X,
       const int n = cls ? d.sf_off[2 * c + 3] - d.sf_off[2 * c + 1] : d.sf_off[2 * c + 2] - d.sf_off[2 * c];
       if (n == 0) continue;
       if (cls == 0)
-        hipLaunchKernelGGL((k_sf_apply<P, P, kSfCols>), dim3((unsigned)n, ny), dim3(kSfThreads),
-                           (sf_lds<P, P, kSfCols>()), s, d, list, vq, kinetic, X, Y, ncolr, ldr, any);
+        hipLaunchKernelGGL((k_sf_apply<P, P, kSfColsOrd>), dim3((unsigned)n, nyo), dim3(kSfThreads),
+                           (sf_lds<P, P, kSfColsOrd>()), s, d, list, vq, kinetic, X, Y, ncolr, ldr, any);
       else
-        hipLaunchKernelGGL((k_sf_apply<P, 2 * P, kSfCols>), dim3((unsigned)n, ny), dim3(kSfThreads),
-                           (sf_lds<P, 2 * P, kSfCols>()), s, d, list, vq, kinetic, X, Y, ncolr, ldr, any);
+        hipLaunchKernelGGL((k_sf_apply<P, 2 * P, kSfColsEnr>), dim3((unsigned)n, nye), dim3(kSfThreads),
+                           (sf_lds<P, 2 * P, kSfColsEnr>()), s, d, list, vq, kinetic, X, Y, ncolr, ldr, any);
     }
   }
 }
@@ -264,14 +275,14 @@ bool sf_supported(const Geom &g) { return (g.P == 5 || g.P == 6) && g.qc == g.P 
 
 int sf_init(const Geom &g) {
   int st = 0;
-  st |= (int)hipFuncSetAttribute((const void *)k_sf_apply<5, 5, kSfCols>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)sf_lds<5, 5, kSfCols>());
-  st |= (int)hipFuncSetAttribute((const void *)k_sf_apply<5, 10, kSfCols>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)sf_lds<5, 10, kSfCols>());
-  st |= (int)hipFuncSetAttribute((const void *)k_sf_apply<6, 6, kSfCols>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)sf_lds<6, 6, kSfCols>());
-  st |= (int)hipFuncSetAttribute((const void *)k_sf_apply<6, 12, kSfCols>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)sf_lds<6, 12, kSfCols>());
+  st |= (int)hipFuncSetAttribute((const void *)k_sf_apply<5, 5, kSfColsOrd>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)sf_lds<5, 5, kSfColsOrd>());
+  st |= (int)hipFuncSetAttribute((const void *)k_sf_apply<5, 10, kSfColsEnr>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)sf_lds<5, 10, kSfColsEnr>());
+  st |= (int)hipFuncSetAttribute((const void *)k_sf_apply<6, 6, kSfColsOrd>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)sf_lds<6, 6, kSfColsOrd>());
+  st |= (int)hipFuncSetAttribute((const void *)k_sf_apply<6, 12, kSfColsEnr>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)sf_lds<6, 12, kSfColsEnr>());
   (void)g;
   return st;
 }
