@@ -70,14 +70,29 @@ def lagrange(nodes: np.ndarray, x: np.ndarray):
 
 
 class Mesh:
-    """Uniform hex mesh of degree-p spectral elements with Dirichlet boundary."""
+    """Tensor-product hex mesh of degree-p spectral elements with Dirichlet boundary.
 
-    def __init__(self, ncell, lo, hi, p, r_cut=0.0, atoms=None, qcell=None, qenr=None):
+    Cells are uniform, or graded per axis by the cell boundaries ``bounds[d]``
+    (ncell[d] + 1 increasing values from lo[d] to hi[d]); each cell maps its
+    reference cube affinely, so every integral keeps its tensor-product form with
+    the cell's own sizes.
+    """
+
+    def __init__(self, ncell, lo, hi, p, r_cut=0.0, atoms=None, qcell=None, qenr=None, bounds=None):
         self.nc = np.array(ncell, dtype=np.int64)
         self.lo = np.array(lo, dtype=np.float64)
         self.hi = np.array(hi, dtype=np.float64)
         self.p = int(p)
-        self.h = (self.hi - self.lo) / self.nc
+        h = (self.hi - self.lo) / self.nc
+        if bounds is None:
+            self.bounds = [self.lo[d] + np.arange(self.nc[d] + 1) * h[d] for d in range(3)]
+        else:
+            self.bounds = [np.asarray(bounds[d], dtype=np.float64) for d in range(3)]
+            for d in range(3):
+                b = self.bounds[d]
+                if len(b) != self.nc[d] + 1 or np.any(np.diff(b) <= 0) or b[0] != self.lo[d] or b[-1] != self.hi[d]:
+                    raise ValueError("bounds must be ncell + 1 increasing values from lo to hi per axis")
+        self.hc = [np.diff(b) for b in self.bounds]      # cell sizes per axis
         self.nn = self.nc * self.p + 1
         self.n_nodes = int(np.prod(self.nn))
         self.n_cells = int(np.prod(self.nc))
@@ -89,7 +104,7 @@ class Mesh:
             g = np.arange(self.nn[d])
             e = np.minimum(g // self.p, self.nc[d] - 1)
             a = g - e * self.p
-            self.coord1d.append(self.lo[d] + e * self.h[d] + (self.xg[a] + 1.0) * 0.5 * self.h[d])
+            self.coord1d.append(self.bounds[d][e] + (self.xg[a] + 1.0) * 0.5 * self.hc[d][e])
         self.qcell = int(qcell) if qcell else self.p + 1
         self.qenr = int(qenr) if qenr else 2 * self.p + 2
         atoms = np.zeros((0, 3)) if atoms is None else np.asarray(atoms, dtype=np.float64)
@@ -164,8 +179,8 @@ class Mesh:
         for R in atoms:
             d2 = np.zeros(self.n_cells)
             for d in range(3):
-                lo = self.lo[d] + e[d] * self.h[d]
-                hi = lo + self.h[d]
+                lo = self.bounds[d][e[d]]
+                hi = lo + self.hc[d][e[d]]
                 gap = np.maximum(np.maximum(lo - R[d], R[d] - hi), 0.0)
                 d2 += gap * gap
             flags |= d2 < r_cut * r_cut
@@ -177,27 +192,34 @@ class Mesh:
         n = self.qenr if self.is_enr[c] else self.qcell
         xi, wi = gauss_rule(n)
         ex, ey, ez = self.cell_ijk(c)
-        pts1 = [self.lo[d] + e * self.h[d] + (xi + 1.0) * 0.5 * self.h[d]
-                for d, e in zip(range(3), (ex, ey, ez))]
+        hc = self.cell_size(c)
+        pts1 = [self.bounds[d][e] + (xi + 1.0) * 0.5 * hc[d] for d, e in zip(range(3), (ex, ey, ez))]
         Z, Y, X = np.meshgrid(pts1[2], pts1[1], pts1[0], indexing="ij")
         WZ, WY, WX = np.meshgrid(wi, wi, wi, indexing="ij")
         pts = np.stack([X.reshape(-1), Y.reshape(-1), Z.reshape(-1)], axis=1)
-        w = (WX * WY * WZ).reshape(-1) * np.prod(0.5 * self.h)
+        w = (WX * WY * WZ).reshape(-1) * np.prod(0.5 * hc)
         return pts, w, xi
 
-    def cell_shape(self, c):
-        """Cell basis at the cell's rule: B (nq, nloc) and grad (3, nq, nloc)."""
-        pts, w, xi = self.cell_rule(c)
+    def reference_shape(self, enriched):
+        """Basis B (nq, nloc) and reference-cube gradients (3, nq, nloc) at the Gauss rule
+        of a cell of the given class (the same for every cell of that class)."""
+        n = self.qenr if enriched else self.qcell
+        xi, _ = gauss_rule(n)
         V, dV = lagrange(self.xg, xi)           # (n, p+1)
-        n = len(xi)
         P = self.p + 1
-        # index helpers: point (i,j,k), node (a,b,c)
+        # point (i,j,k) x fastest, node (a,b,c) x fastest
         B = np.einsum("ia,jb,kc->kjicba", V, V, V).reshape(n ** 3, P ** 3)
-        sx, sy, sz = 2.0 / self.h
-        Gx = sx * np.einsum("ia,jb,kc->kjicba", dV, V, V).reshape(n ** 3, P ** 3)
-        Gy = sy * np.einsum("ia,jb,kc->kjicba", V, dV, V).reshape(n ** 3, P ** 3)
-        Gz = sz * np.einsum("ia,jb,kc->kjicba", V, V, dV).reshape(n ** 3, P ** 3)
-        return pts, w, B, np.stack([Gx, Gy, Gz])
+        Gx = np.einsum("ia,jb,kc->kjicba", dV, V, V).reshape(n ** 3, P ** 3)
+        Gy = np.einsum("ia,jb,kc->kjicba", V, dV, V).reshape(n ** 3, P ** 3)
+        Gz = np.einsum("ia,jb,kc->kjicba", V, V, dV).reshape(n ** 3, P ** 3)
+        return B, np.stack([Gx, Gy, Gz])
+
+    def cell_shape(self, c):
+        """Cell basis at the cell's rule: B (nq, nloc) and grad (3, nq, nloc); the
+        affine map of the cell scales the reference gradient along d by 2 / h_d."""
+        pts, w, _ = self.cell_rule(c)
+        B, G = self.reference_shape(bool(self.is_enr[c]))
+        return pts, w, B, G * (2.0 / self.cell_size(c))[:, None, None]
 
     def all_quadrature(self):
         """Points (n_quad, 3) and weights (n_quad,) over all cells, in cell order."""
@@ -212,7 +234,12 @@ class Mesh:
     def lumped_mass(self):
         """Diagonal classical mass from GLL quadrature: sum of cell weights per node."""
         D = np.zeros(self.n_nodes)
-        w3 = np.einsum("a,b,c->cba", self.wg, self.wg, self.wg).reshape(-1) * np.prod(0.5 * self.h)
+        w3 = np.einsum("a,b,c->cba", self.wg, self.wg, self.wg).reshape(-1)
         for c in range(self.n_cells):
-            np.add.at(D, self.cell_nodes(c), w3)
+            np.add.at(D, self.cell_nodes(c), w3 * np.prod(0.5 * self.cell_size(c)))
         return D
+
+    def cell_size(self, c):
+        """Edge lengths (3,) of cell c."""
+        e = self.cell_ijk(c)
+        return np.array([self.hc[d][e[d]] for d in range(3)])

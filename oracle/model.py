@@ -61,7 +61,7 @@ class EFEModel:
     def __init__(self, spec, drop_tol: Optional[float] = None):
         self.spec = spec
         self.mesh = m = Mesh(spec.ncell, spec.lo, spec.hi, spec.degree, spec.r_cut,
-                             spec.R, spec.qcell, spec.qenr)
+                             spec.R, spec.qcell, spec.qenr, getattr(spec, "bounds", None))
         self.D = m.lumped_mass()
         self.bnd = m.boundary_mask()
         self.interior = np.nonzero(~self.bnd)[0]
@@ -80,15 +80,15 @@ class EFEModel:
 
     # ------------------------------------------------------------------ shapes
     def shape(self, c):
-        """Points, weights, B, grad B of cell c (B and grad B depend only on the class)."""
+        """Points, weights, B, grad B of cell c (B and the reference gradients depend only
+        on the class; the gradient along d is scaled by 2 / h_d of the cell)."""
         m = self.mesh
         key = bool(m.is_enr[c])
         if key not in self._shape_cache:
-            _, _, B, G = m.cell_shape(c)
-            self._shape_cache[key] = (B, G)
+            self._shape_cache[key] = m.reference_shape(key)
         pts, w, _ = m.cell_rule(c)
         B, G = self._shape_cache[key]
-        return pts, w, B, G
+        return pts, w, B, G * (2.0 / m.cell_size(c))[:, None, None]
 
     # ------------------------------------------------------------- enrichment
     def _atomic(self, pts, grad):
@@ -434,16 +434,16 @@ class EFEModel:
         m = self.mesh
         xi, wi = gauss_rule(m.p + 1)
         V, dV = lagrange(m.xg, xi)
-        h = m.h[d]
-        Ke = (2.0 / h) * (dV.T @ (wi[:, None] * dV))
-        Me = (h / 2.0) * (V.T @ (wi[:, None] * V))
+        Kr = dV.T @ (wi[:, None] * dV)
+        Mr = V.T @ (wi[:, None] * V)
         n = m.nn[d]
         K1 = np.zeros((n, n))
         M1 = np.zeros((n, n))
         for e in range(m.nc[d]):
+            h = m.hc[d][e]
             s = slice(e * m.p, e * m.p + m.p + 1)
-            K1[s, s] += Ke
-            M1[s, s] += Me
+            K1[s, s] += (2.0 / h) * Kr
+            M1[s, s] += (h / 2.0) * Mr
         return K1, M1
 
     def interpolate_nodal(self, phi):

@@ -76,13 +76,14 @@ def test_tiny_mesh_sums_and_classes():
     for c in range(m.n_cells):
         ex, ey, ez = m.cell_ijk(c)
         p = P[m.q_off[c]:m.q_off[c + 1]]
-        lo = m.lo + np.array([ex, ey, ez]) * m.h
-        assert np.all(p > lo) and np.all(p < lo + m.h)
+        lo = m.lo + np.array([ex, ey, ez]) * 4.0
+        assert np.all(p > lo) and np.all(p < lo + 4.0)
+        np.testing.assert_allclose(m.cell_size(c), 4.0, rtol=1e-15)
     # cell nodes sit on the cell box, local order x fastest
     xyz = m.node_coords(m.cell_nodes(5))
     ex, ey, ez = m.cell_ijk(5)
-    lo = m.lo + np.array([ex, ey, ez]) * m.h
-    assert np.all(xyz >= lo - 1e-12) and np.all(xyz <= lo + m.h + 1e-12)
+    lo = m.lo + np.array([ex, ey, ez]) * 4.0
+    assert np.all(xyz >= lo - 1e-12) and np.all(xyz <= lo + 4.0 + 1e-12)
     assert xyz[1, 0] > xyz[0, 0] and xyz[1, 1] == xyz[0, 1]
 
 

@@ -51,6 +51,9 @@ class SystemSpec:
     quad_cell: int = 0            # Gauss points per direction, 0 -> degree + 1
     quad_enr: int = 0             # Gauss points per direction, 0 -> 2 degree + 2
     enr_drop_tol: float = 1e-8    # canonical-orthogonalisation threshold
+    # graded tensor-product mesh: per axis the ncell[d] + 1 cell boundaries from lo[d] to hi[d]
+    # (None: uniform cells)
+    bounds: Optional[Tuple[np.ndarray, np.ndarray, np.ndarray]] = None
     # propagation
     dt: float = 0.05
     nsteps: int = 1
@@ -178,6 +181,38 @@ def na_cluster(natom: int, seed: int, ncell: Optional[int] = None,
 def na8() -> SystemSpec:
     """8 Na atoms, 24^3 cells of degree 5 on [-20, 20]^3 (1,771,561 nodes), 44 orbitals."""
     return na_cluster(8, seed=0)
+
+
+def graded_bounds(lo: float, hi: float, ncell: int, beta: float) -> np.ndarray:
+    """ncell + 1 cell boundaries on [lo, hi] from x = c + a sinh(beta xi) / sinh(beta),
+    xi uniform on [-1, 1] (c, a the box centre and half-length; beta = 0: uniform).
+    Cells are finest at the centre and grow smoothly toward both faces."""
+    xi = np.linspace(-1.0, 1.0, ncell + 1)
+    c, a = 0.5 * (lo + hi), 0.5 * (hi - lo)
+    b = c + a * (xi if beta == 0.0 else np.sinh(beta * xi) / np.sinh(beta))
+    b[0], b[-1] = lo, hi
+    return b
+
+
+def tiny_graded() -> SystemSpec:
+    """The tiny system on a graded, axis-dependent 4^3 mesh of [-8, 8]^3."""
+    s = tiny()
+    s.name = "tiny_graded"
+    s.bounds = (np.array([-8.0, -2.5, 0.0, 3.0, 8.0]),
+                np.array([-8.0, -3.5, -0.5, 2.5, 8.0]),
+                np.array([-8.0, -4.0, 0.5, 4.0, 8.0]))
+    return s
+
+
+def na8_graded() -> SystemSpec:
+    """Na8 in a 70-bohr box (the domain length of the paper's Na_3 / Na_11 runs) with
+    the node count of na8(): 24^3 cells of degree 5, sinh-graded with beta = 1.93, so the
+    central cells keep about the 40/24 bohr of the uniform mesh and the outer ones reach 5.5."""
+    s = na_cluster(8, seed=0)
+    s.name = "Na8_graded"
+    s.lo, s.hi = (-35.0,) * 3, (35.0,) * 3
+    s.bounds = tuple(graded_bounds(-35.0, 35.0, 24, 1.93) for _ in range(3))
+    return s
 
 
 def trap(omega: float = 0.5, ncell: int = 6, half: float = 9.0, degree: int = 4,
