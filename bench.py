@@ -321,7 +321,8 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extrap", action="store_true")
-    ap.add_argument("--workload", default="na8", choices=["na8", "tiny", "na2", "batch", "adjoint"])
+    ap.add_argument("--no-graded", action="store_true")
+    ap.add_argument("--workload", default="na8", choices=["na8", "na8_graded", "tiny", "na2", "batch", "adjoint"])
     ap.add_argument("--mode", default="step", choices=["step", "apply"])
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32", "bf16", "f64sf"])
     args = ap.parse_args()
@@ -330,7 +331,7 @@ def main():
               "(the orbital-sharded design is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
     import torch
-    from workloads import na8, tiny, na_cluster
+    from workloads import na8, na8_graded, tiny, na_cluster
     torch.cuda.set_device(0)
     if args.workload == "batch":
         print(json.dumps(run_batch(args.steps, args.warmup, min(args.kmax, 20))))
@@ -338,7 +339,8 @@ def main():
     if args.workload == "adjoint":
         print(json.dumps(run_adjoint(args.steps, min(args.kmax, 24))))
         return
-    spec = {"na8": na8, "tiny": tiny, "na2": lambda: na_cluster(2, seed=2)}[args.workload]()
+    spec = {"na8": na8, "na8_graded": na8_graded, "tiny": tiny,
+            "na2": lambda: na_cluster(2, seed=2)}[args.workload]()
     if args.mode == "apply":
         run_apply_mode(spec, args.dtype, max(1, args.steps))
         return
@@ -399,6 +401,18 @@ def main():
                                  "speedup_vs_f64": sv / value, "dipole_rel_diff_vs_f64": float(dmu),
                                  "stage_ms_per_step": {k: v / args.steps for k, v in sres["stage"].items()
                                                        if k != "n_hx"}}
+    if not args.no_graded and args.workload == "na8":
+        # the same cluster in a 70-bohr box on a sinh-graded mesh with the same node count
+        gspec = na8_graded()
+        gres = run_gpu(gspec, "f64", args.steps, args.warmup, args.kmax)
+        gv = args.steps / gres["wall"]
+        out["graded"] = {"workload": "Na8 in [-35, 35]^3, 24^3 sinh-graded cells (1.68 .. 5.44 bohr) of degree 5",
+                         "dtype": "f64", "value": gv, "unit": "steps/s", "ms_per_step": 1e3 * gres["wall"] / args.steps,
+                         "ratio_vs_uniform_box": gv / value,
+                         "mean_krylov_dim": [float(sum(k[0] for k in gres["k"]) / len(gres["k"])),
+                                             float(sum(k[1] for k in gres["k"]) / len(gres["k"]))],
+                         "orthonormality_error": gres["orth"],
+                         "stage_ms_per_step": {k: v / args.steps for k, v in gres["stage"].items() if k != "n_hx"}}
     if not args.no_extrap:
         out["spectrum"] = run_spectrum_timing()
     if not args.no_cpu:

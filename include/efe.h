@@ -66,7 +66,7 @@ enum { EFE_OP_H = 0, EFE_OP_X = 1, EFE_OP_Y = 2, EFE_OP_Z = 3 };
 
 /* Physical system and discretisation.  Host memory, read during the call only. */
 typedef struct {
-  int32_t ncell[3];        /* uniform hex cells per axis                          */
+  int32_t ncell[3];        /* hex cells per axis                                  */
   double lo[3], hi[3];     /* box [lo, hi] in bohr                                */
   int32_t degree;          /* FE degree p (2..6): (p+1)^3 GLL nodes per cell      */
   int32_t natom;
@@ -86,6 +86,12 @@ typedef struct {
   int32_t quad_cell;       /* Gauss points per axis on ordinary cells; 0 -> p+1   */
   int32_t quad_enr;        /* ... on cells within r_cut of an atom; 0 -> 2p+2     */
   double enr_drop_tol;     /* drop M^ee eigenvalues below tol * max (canonical orthogonalisation) */
+  /* Graded tensor-product mesh (Sec. 2.7: finer cells near the atoms, coarser toward
+   * the faces): NULL for uniform cells, else ncell[0]+1 x-boundaries, then ncell[1]+1
+   * y-boundaries, then ncell[2]+1 z-boundaries, each list strictly increasing from
+   * lo[d] to hi[d] (EFE_ERR_ARG otherwise, EFE_ERR_NONFINITE for NaN/Inf).  Every
+   * cell is the affine image of the reference cube with its own edge lengths. */
+  const double *cell_bounds;
 } efe_system;
 
 typedef struct {

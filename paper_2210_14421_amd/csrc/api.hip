@@ -222,8 +222,6 @@ efe_status build_device(efe_ctx *ctx) {
   for (int i = 0; i < 3; ++i) {
     g.nc[i] = pl.nc[i];
     g.nn[i] = pl.nn[i];
-    g.lo[i] = pl.lo[i];
-    g.h[i] = pl.h[i];
   }
   g.p = pl.p; g.P = pl.P; g.nloc = pl.nloc; g.cstride = ((int64_t)pl.nloc * pl.nloc + 7) / 8 * 8; g.qc = pl.qc; g.qe = pl.qe; g.n_nodes = pl.n_nodes;
   const int P = pl.P, NP = P * (P + 1) / 2;
@@ -248,13 +246,9 @@ efe_status build_device(efe_ctx *ctx) {
     if (cls) d.to.G1e = put(G1); else d.to.G1c = put(G1);
   }
   {
-    std::vector<double> K, M;
-    for (int dd = 0; dd < 3; ++dd) {
-      K.insert(K.end(), pl.Kel[dd].begin(), pl.Kel[dd].end());
-      M.insert(M.end(), pl.Mel[dd].begin(), pl.Mel[dd].end());
-    }
-    d.to.Kel = put(K);
-    d.to.Mel = put(M);
+    d.to.Kr = put(pl.Kref);
+    d.to.Mr = put(pl.Mref);
+    for (int dd = 0; dd < 3; ++dd) d.to.xb[dd] = put(pl.xb[dd]);
     std::vector<double> pd(pair.begin(), pair.end());
     d.to.pair = put(pd);
   }

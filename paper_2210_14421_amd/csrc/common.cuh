@@ -15,6 +15,24 @@ __device__ __forceinline__ void cell_ijk(const Geom &g, int64_t c, int e[3]) {
   e[2] = (int)(c / ((int64_t)g.nc[0] * g.nc[1]));
 }
 
+// Lower corner and edge lengths of cell e (per-axis cell boundaries of the table).
+__device__ __forceinline__ void cell_box(const DevData &d, const int e[3], double lo[3], double h[3]) {
+  for (int a = 0; a < 3; ++a) {
+    const double b0 = d.tab[d.to.xb[a] + e[a]];
+    lo[a] = b0;
+    h[a] = d.tab[d.to.xb[a] + e[a] + 1] - b0;
+  }
+}
+
+// Jacobian h_x h_y h_z / 8 of the affine map from the reference cube onto cell c.
+__device__ __forceinline__ double cell_jacobian(const DevData &d, int64_t c) {
+  int e[3];
+  cell_ijk(d.g, c, e);
+  double lo[3], h[3];
+  cell_box(d, e, lo, h);
+  return 0.125 * h[0] * h[1] * h[2];
+}
+
 // global node of cell-local index l = a + P (b + P c)
 __device__ __forceinline__ int64_t local_node(const Geom &g, const int e[3], int l) {
   int a = l % g.P, b = (l / g.P) % g.P, c = l / (g.P * g.P);

@@ -14,7 +14,6 @@ struct Geom {
   int p, P, nloc;
   int64_t cstride;   // elements between stored cell blocks: nloc^2 rounded up to 8 (16-byte aligned blocks)
   int qc, qe;
-  double lo[3], h[3];
   int64_t n_nodes;
 };
 
@@ -23,7 +22,8 @@ struct TabOff {
   int Bc, dBc, Be, dBe;     // [n][P]
   int xqc, wqc, xqe, wqe;   // [n]
   int G1c, G1e;             // [n][NP]: B[i][a] B[i][a'] per unordered pair
-  int Kel, Mel;             // [3][P][P]
+  int Kr, Mr;               // [P][P] reference-cell stiffness / mass (cell edge h: 2/h Kr, h/2 Mr)
+  int xb[3];                // per axis: the nc[d] + 1 cell boundaries
   int pair;                 // [P][P] pair index (as doubles)
   int total;
 };

@@ -65,9 +65,11 @@ k_rebuild(const DevData d, const int *__restrict__ cell_list, int n, int mode, c
   const int tox = enr ? d.to.xqe : d.to.xqc, tow = enr ? d.to.wqe : d.to.wqc;
   for (int t = threadIdx.x; t < n * P; t += blockDim.x) Bt[t] = tab[toB + t];
   for (int t = threadIdx.x; t < n * NP; t += blockDim.x) G1[t] = tab[toG + t];
+  double clo[3], ch[3];
+  cell_box(d, e, clo, ch);
   for (int t = threadIdx.x; t < 3 * P2; t += blockDim.x) {
-    Kel[t] = tab[d.to.Kel + t];
-    Mel[t] = tab[d.to.Mel + t];
+    Kel[t] = tab[d.to.Kr + t % P2] * (2.0 / ch[t / P2]);
+    Mel[t] = tab[d.to.Mr + t % P2] * (0.5 * ch[t / P2]);
   }
   for (int t = threadIdx.x; t < P2; t += blockDim.x) pair[t] = (int)tab[d.to.pair + t];
   for (int t = threadIdx.x; t < nloc; t += blockDim.x) {
@@ -85,13 +87,13 @@ k_rebuild(const DevData d, const int *__restrict__ cell_list, int n, int mode, c
     apply_axis(t2, wv, Bt, P, false, n, n, P, 2, n, 1);      // [k][j][i] = v_H
     __syncthreads();
   }
-  const double jac = 0.125 * g.h[0] * g.h[1] * g.h[2];
+  const double jac = 0.125 * ch[0] * ch[1] * ch[2];
   const double efield = efield_p ? *efield_p : 0.0;
   for (int q = threadIdx.x; q < n3; q += blockDim.x) {
     int i = q % n, j = (q / n) % n, k = q / (n * n);
-    double x[3] = {g.lo[0] + e[0] * g.h[0] + (tab[tox + i] + 1.0) * 0.5 * g.h[0],
-                   g.lo[1] + e[1] * g.h[1] + (tab[tox + j] + 1.0) * 0.5 * g.h[1],
-                   g.lo[2] + e[2] * g.h[2] + (tab[tox + k] + 1.0) * 0.5 * g.h[2]};
+    double x[3] = {clo[0] + (tab[tox + i] + 1.0) * 0.5 * ch[0],
+                   clo[1] + (tab[tox + j] + 1.0) * 0.5 * ch[1],
+                   clo[2] + (tab[tox + k] + 1.0) * 0.5 * ch[2]};
     double w = jac * tab[tow + i] * tab[tow + j] * tab[tow + k];
     double v;
     if (mode == 0) {
@@ -176,7 +178,7 @@ k_coupling_partials(const DevData d, const double *__restrict__ vq, double *__re
   double *nod = t2 + n * P * P;  // nloc
   for (int t = threadIdx.x; t < n * P; t += blockDim.x) Bt[t] = tab[toB + t];
   const int64_t q0 = d.q_off[cell];
-  const double jac = 0.125 * g.h[0] * g.h[1] * g.h[2];
+  const double jac = cell_jacobian(d, cell);
   for (int q = threadIdx.x; q < n3; q += blockDim.x) {
     int i = q % n, j = (q / n) % n, k = q / (n * n);
     wv[q] = jac * tab[tow + i] * tab[tow + j] * tab[tow + k] * vq[q0 + q];
@@ -237,7 +239,7 @@ k_coupling_mfma(const DevData d, const double *__restrict__ vq, double *__restri
   const int k0 = d.tnu_off[slot], nnu = d.tnu_off[slot + 1] - k0;
   const double *NEs = d.NE + d.tne_off[slot];
   const int64_t q0 = d.q_off[cell];
-  const double jac = 0.125 * g.h[0] * g.h[1] * g.h[2];
+  const double jac = cell_jacobian(d, cell);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int kr = lane >> 4, cl = lane & 15;
   const int nmt = (nloc + 15) / 16, nnt = (nnu + 15) / 16;
@@ -993,7 +995,7 @@ k_poisson_rhs(const DevData d, const int *__restrict__ cell_list, const double *
   double *Bt = sm, *f = Bt + n * P, *t1 = f + n3, *t2 = t1 + n * n * P, *nod = t2 + n * P * P;
   for (int t = threadIdx.x; t < n * P; t += blockDim.x) Bt[t] = tab[toB + t];
   const int64_t q0 = d.q_off[cell];
-  const double jac = 0.125 * g.h[0] * g.h[1] * g.h[2];
+  const double jac = cell_jacobian(d, cell);
   for (int q = threadIdx.x; q < n3; q += blockDim.x) {
     int i = q % n, j = (q / n) % n, k = q / (n * n);
     f[q] = jac * tab[tow + i] * tab[tow + j] * tab[tow + k] * rho[q0 + q];
@@ -1048,11 +1050,13 @@ k_adj_potential(const DevData d, const int *__restrict__ cell_list, int n, const
   apply_axis(t2, wv, Bt, P, false, n, n, P, 2, n, 1);
   __syncthreads();
   const int64_t q0 = d.q_off[cell];
+  double clo[3], ch[3];
+  cell_box(d, e, clo, ch);
   for (int q = threadIdx.x; q < n3; q += blockDim.x) {
     const int i = q % n, j = (q / n) % n, k = q / (n * n);
-    const double x = g.lo[0] + e[0] * g.h[0] + (tab[tox + i] + 1.0) * 0.5 * g.h[0];
-    const double y = g.lo[1] + e[1] * g.h[1] + (tab[tox + j] + 1.0) * 0.5 * g.h[1];
-    const double z = g.lo[2] + e[2] * g.h[2] + (tab[tox + k] + 1.0) * 0.5 * g.h[2];
+    const double x = clo[0] + (tab[tox + i] + 1.0) * 0.5 * ch[0];
+    const double y = clo[1] + (tab[tox + j] + 1.0) * 0.5 * ch[1];
+    const double z = clo[2] + (tab[tox + k] + 1.0) * 0.5 * ch[2];
     double v = wv[q] + tau * fxc_lda(rho[q0 + q], xc) * u[q0 + q] + mx * x + my * y + mz * z;
     if (gin) v += a * gin[q0 + q];
     out[q0 + q] = v;
@@ -1179,14 +1183,16 @@ k_dipole(const DevData d, const double *__restrict__ rho, double *__restrict__ p
   int e[3];
   cell_ijk(g, cell, e);
   const int64_t q0 = d.q_off[cell];
-  const double jac = 0.125 * g.h[0] * g.h[1] * g.h[2];
+  double clo[3], ch[3];
+  cell_box(d, e, clo, ch);
+  const double jac = 0.125 * ch[0] * ch[1] * ch[2];
   double s[3] = {0.0, 0.0, 0.0};
   for (int q = threadIdx.x; q < n3; q += blockDim.x) {
     int i = q % n, j = (q / n) % n, k = q / (n * n);
     double w = jac * tab[tow + i] * tab[tow + j] * tab[tow + k] * rho[q0 + q];
-    s[0] += w * (g.lo[0] + e[0] * g.h[0] + (tab[tox + i] + 1.0) * 0.5 * g.h[0]);
-    s[1] += w * (g.lo[1] + e[1] * g.h[1] + (tab[tox + j] + 1.0) * 0.5 * g.h[1]);
-    s[2] += w * (g.lo[2] + e[2] * g.h[2] + (tab[tox + k] + 1.0) * 0.5 * g.h[2]);
+    s[0] += w * (clo[0] + (tab[tox + i] + 1.0) * 0.5 * ch[0]);
+    s[1] += w * (clo[1] + (tab[tox + j] + 1.0) * 0.5 * ch[1]);
+    s[2] += w * (clo[2] + (tab[tox + k] + 1.0) * 0.5 * ch[2]);
   }
   for (int dd = 0; dd < 3; ++dd) {
     double t = block_sum(s[dd], red);

@@ -59,12 +59,14 @@ k_sf_apply(const DevData d, const int *__restrict__ cell_list, const double *__r
   const bool enr = N != P;
   const int toB = enr ? d.to.Be : d.to.Bc, tow = enr ? d.to.wqe : d.to.wqc;
   for (int t = tid; t < N * P; t += kSfThreads) sB[t] = d.tab[toB + t];
+  double clo[3], ch[3];
+  cell_box(d, e, clo, ch);
   for (int t = tid; t < 3 * P2; t += kSfThreads) {
-    sK[t / P2][t % P2] = d.tab[d.to.Kel + t];
-    sM[t / P2][t % P2] = d.tab[d.to.Mel + t];
+    sK[t / P2][t % P2] = d.tab[d.to.Kr + t % P2] * (2.0 / ch[t / P2]);
+    sM[t / P2][t % P2] = d.tab[d.to.Mr + t % P2] * (0.5 * ch[t / P2]);
   }
   const int64_t q0 = d.q_off[cell];
-  const double jac = 0.125 * g.h[0] * g.h[1] * g.h[2];
+  const double jac = 0.125 * ch[0] * ch[1] * ch[2];
   for (int q = tid; q < N * N * N; q += kSfThreads) {
     const int i = q % N, j = (q / N) % N, k = q / (N * N);
     wv[q] = jac * d.tab[tow + i] * d.tab[tow + j] * d.tab[tow + k] * vq[q0 + q];

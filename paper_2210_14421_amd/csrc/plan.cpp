@@ -248,7 +248,7 @@ void Plan::cell_nodes(int64_t c, int64_t *out) const {
 double Plan::node_coord(int d, int64_t g) const {
   int64_t e = std::min<int64_t>(g / p, nc[d] - 1);
   int64_t a = g - e * p;
-  return lo[d] + e * h[d] + (xg[a] + 1.0) * 0.5 * h[d];
+  return cell_lo(d, (int)e) + (xg[a] + 1.0) * 0.5 * cell_h(d, (int)e);
 }
 
 // Atomic part of enrichment function nu (unnormalised): r^l exp(-zeta r) Y_lm(rhat) u(r),
@@ -286,7 +286,7 @@ double box_dist2(const Plan &pl, int64_t c, const double *R) {
   pl.cell_ijk(c, e);
   double d2 = 0.0;
   for (int d = 0; d < 3; ++d) {
-    double lo = pl.lo[d] + e[d] * pl.h[d], hi = lo + pl.h[d];
+    double lo = pl.cell_lo(d, e[d]), hi = lo + pl.cell_h(d, e[d]);
     double gap = std::max(std::max(lo - R[d], R[d] - hi), 0.0);
     d2 += gap * gap;
   }
@@ -302,14 +302,16 @@ void cell_points(const Plan &pl, int64_t c, std::vector<double> &X, std::vector<
   const std::vector<double> &wq = pl.is_enr[c] ? pl.wqe : pl.wqc;
   X.resize((size_t)3 * n * n * n);
   W.resize((size_t)n * n * n);
-  double jac = 0.125 * pl.h[0] * pl.h[1] * pl.h[2];
+  const double h[3] = {pl.cell_h(0, e[0]), pl.cell_h(1, e[1]), pl.cell_h(2, e[2])};
+  const double l[3] = {pl.cell_lo(0, e[0]), pl.cell_lo(1, e[1]), pl.cell_lo(2, e[2])};
+  double jac = 0.125 * h[0] * h[1] * h[2];
   for (int k = 0; k < n; ++k)
     for (int j = 0; j < n; ++j)
       for (int i = 0; i < n; ++i) {
         size_t q = (size_t)i + n * (j + (size_t)n * k);
-        X[3 * q + 0] = pl.lo[0] + e[0] * pl.h[0] + (xq[i] + 1.0) * 0.5 * pl.h[0];
-        X[3 * q + 1] = pl.lo[1] + e[1] * pl.h[1] + (xq[j] + 1.0) * 0.5 * pl.h[1];
-        X[3 * q + 2] = pl.lo[2] + e[2] * pl.h[2] + (xq[k] + 1.0) * 0.5 * pl.h[2];
+        X[3 * q + 0] = l[0] + (xq[i] + 1.0) * 0.5 * h[0];
+        X[3 * q + 1] = l[1] + (xq[j] + 1.0) * 0.5 * h[1];
+        X[3 * q + 2] = l[2] + (xq[k] + 1.0) * 0.5 * h[2];
         W[q] = jac * wq[i] * wq[j] * wq[k];
       }
 }
@@ -322,6 +324,20 @@ efe_status build_plan(const efe_system &s, Plan &pl) {
     if (s.ncell[d] < 1 || s.ncell[d] > 4096 || !(s.hi[d] > s.lo[d])) {
       pl.error = "invalid mesh: ncell must be 1..4096 and hi > lo";
       return EFE_ERR_ARG;
+    }
+  }
+  if (s.cell_bounds) {
+    const double *b = s.cell_bounds;
+    for (int d = 0; d < 3; ++d) {
+      for (int e = 0; e <= s.ncell[d]; ++e)
+        if (!std::isfinite(b[e])) { pl.error = "non-finite cell bounds"; return EFE_ERR_NONFINITE; }
+      bool ok = b[0] == s.lo[d] && b[s.ncell[d]] == s.hi[d];
+      for (int e = 0; e < s.ncell[d]; ++e) ok = ok && b[e + 1] > b[e];
+      if (!ok) {
+        pl.error = "cell bounds must increase strictly from lo to hi on every axis";
+        return EFE_ERR_ARG;
+      }
+      b += s.ncell[d] + 1;
     }
   }
   if (s.degree < 2 || s.degree > 6) { pl.error = "degree must be 2..6"; return EFE_ERR_ARG; }
@@ -352,7 +368,13 @@ efe_status build_plan(const efe_system &s, Plan &pl) {
   pl.p = s.degree; pl.P = s.degree + 1; pl.nloc = pl.P * pl.P * pl.P;
   for (int d = 0; d < 3; ++d) {
     pl.nc[d] = s.ncell[d]; pl.lo[d] = s.lo[d]; pl.hi[d] = s.hi[d];
-    pl.h[d] = (s.hi[d] - s.lo[d]) / s.ncell[d];
+    pl.xb[d].resize((size_t)s.ncell[d] + 1);
+    const double h = (s.hi[d] - s.lo[d]) / s.ncell[d];
+    for (int e = 0; e <= s.ncell[d]; ++e) pl.xb[d][e] = s.lo[d] + e * h;
+    if (s.cell_bounds) {
+      const double *b = s.cell_bounds + (d > 0 ? s.ncell[0] + 1 : 0) + (d > 1 ? s.ncell[1] + 1 : 0);
+      pl.xb[d].assign(b, b + s.ncell[d] + 1);
+    }
     pl.nn[d] = (int64_t)s.ncell[d] * pl.p + 1;
   }
   pl.n_nodes = pl.nn[0] * pl.nn[1] * pl.nn[2];
@@ -387,20 +409,18 @@ efe_status build_plan(const efe_system &s, Plan &pl) {
     std::vector<double> xe, we, V, dV;
     gauss_rule(P, xe, we);
     lagrange(pl.xg, xe, V, dV);
-    for (int d = 0; d < 3; ++d) {
-      pl.Kel[d].assign((size_t)P * P, 0.0);
-      pl.Mel[d].assign((size_t)P * P, 0.0);
-      for (int a = 0; a < P; ++a)
-        for (int b = 0; b < P; ++b) {
-          double k = 0, m = 0;
-          for (int q = 0; q < P; ++q) {
-            k += we[q] * dV[q * P + a] * dV[q * P + b];
-            m += we[q] * V[q * P + a] * V[q * P + b];
-          }
-          pl.Kel[d][a * P + b] = k * 2.0 / pl.h[d];
-          pl.Mel[d][a * P + b] = m * 0.5 * pl.h[d];
+    pl.Kref.assign((size_t)P * P, 0.0);
+    pl.Mref.assign((size_t)P * P, 0.0);
+    for (int a = 0; a < P; ++a)
+      for (int b = 0; b < P; ++b) {
+        double k = 0, m = 0;
+        for (int q = 0; q < P; ++q) {
+          k += we[q] * dV[q * P + a] * dV[q * P + b];
+          m += we[q] * V[q * P + a] * V[q * P + b];
         }
-    }
+        pl.Kref[a * P + b] = k;
+        pl.Mref[a * P + b] = m;
+      }
   }
 
   // ---- cell classes --------------------------------------------------------
@@ -439,9 +459,11 @@ efe_status build_plan(const efe_system &s, Plan &pl) {
   // ---- lumped mass -------------------------------------------------------------
   pl.D.assign(pl.n_nodes, 0.0);
   {
-    double jac = 0.125 * pl.h[0] * pl.h[1] * pl.h[2];
     std::vector<int64_t> nodes(pl.nloc);
     for (int64_t c = 0; c < NC; ++c) {
+      int e[3];
+      pl.cell_ijk(c, e);
+      const double jac = 0.125 * pl.cell_h(0, e[0]) * pl.cell_h(1, e[1]) * pl.cell_h(2, e[2]);
       pl.cell_nodes(c, nodes.data());
       for (int cz = 0; cz < P; ++cz)
         for (int by = 0; by < P; ++by)
@@ -669,10 +691,12 @@ efe_status build_plan(const efe_system &s, Plan &pl) {
       const double *Bt = pl.is_enr[c] ? pl.Be.data() : pl.Bc.data();
       const double *dBt = pl.is_enr[c] ? pl.dBe.data() : pl.dBc.data();
       std::vector<double> dBx((size_t)n * P), dBy((size_t)n * P), dBz((size_t)n * P);
+      int ec[3];
+      pl.cell_ijk(c, ec);
       for (size_t i = 0; i < dBx.size(); ++i) {
-        dBx[i] = dBt[i] * 2.0 / pl.h[0];
-        dBy[i] = dBt[i] * 2.0 / pl.h[1];
-        dBz[i] = dBt[i] * 2.0 / pl.h[2];
+        dBx[i] = dBt[i] * 2.0 / pl.cell_h(0, ec[0]);
+        dBy[i] = dBt[i] * 2.0 / pl.cell_h(1, ec[1]);
+        dBz[i] = dBt[i] * 2.0 / pl.cell_h(2, ec[2]);
       }
       size_t nq = W.size();
       int k0 = pl.tnu_off[t], k1 = pl.tnu_off[t + 1], nv = k1 - k0;
@@ -742,12 +766,14 @@ efe_status build_plan(const efe_system &s, Plan &pl) {
     int64_t n = pl.nn[d];
     pl.K1[d].assign((size_t)n * n, 0.0);
     pl.M1[d].assign((size_t)n * n, 0.0);
-    for (int e = 0; e < pl.nc[d]; ++e)
+    for (int e = 0; e < pl.nc[d]; ++e) {
+      const double h = pl.cell_h(d, e);
       for (int a = 0; a < P; ++a)
         for (int b = 0; b < P; ++b) {
-          pl.K1[d][(size_t)(e * p + a) * n + e * p + b] += pl.Kel[d][a * P + b];
-          pl.M1[d][(size_t)(e * p + a) * n + e * p + b] += pl.Mel[d][a * P + b];
+          pl.K1[d][(size_t)(e * p + a) * n + e * p + b] += pl.Kref[a * P + b] * 2.0 / h;
+          pl.M1[d][(size_t)(e * p + a) * n + e * p + b] += pl.Mref[a * P + b] * 0.5 * h;
         }
+    }
     int m = (int)n - 2;
     // generalised symmetric eigenproblem K v = lam M v on the interior, via M = L L^T
     std::vector<double> L((size_t)m * m, 0.0), K((size_t)m * m), C((size_t)m * m);

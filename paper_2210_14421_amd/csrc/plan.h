@@ -17,7 +17,8 @@ constexpr int kNoiseModes = 27;
 struct Plan {
   // ---- system -------------------------------------------------------------
   int nc[3] = {0, 0, 0};
-  double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0}, h[3] = {0, 0, 0};
+  double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  std::vector<double> xb[3];             // cell boundaries per axis (nc[d] + 1, increasing)
   int p = 0, P = 0, nloc = 0;
   int64_t nn[3] = {0, 0, 0};
   int64_t n_nodes = 0, n_cells = 0;
@@ -40,8 +41,9 @@ struct Plan {
   std::vector<double> xg, wg;            // GLL nodes/weights (P)
   std::vector<double> xqc, wqc, xqe, wqe;  // Gauss rules (qc, qe)
   std::vector<double> Bc, dBc, Be, dBe;  // Lagrange values/derivatives [n][P], d/dxi
-  // exact 1-D element matrices in physical scaling per axis [3][P*P]
-  std::vector<double> Kel[3], Mel[3];
+  // exact 1-D element matrices of the reference cell [P*P]: int dphi_a dphi_b, int phi_a phi_b;
+  // a cell of edge h along an axis has (2/h) Kref and (h/2) Mref there
+  std::vector<double> Kref, Mref;
 
   // ---- cells ----------------------------------------------------------------
   std::vector<uint8_t> is_enr;           // n_cells
@@ -94,6 +96,8 @@ struct Plan {
     e[2] = (int)(c / ((int64_t)nc[0] * nc[1]));
   }
   void cell_nodes(int64_t c, int64_t *out) const;
+  double cell_lo(int d, int e) const { return xb[d][e]; }
+  double cell_h(int d, int e) const { return xb[d][e + 1] - xb[d][e]; }
   double node_coord(int d, int64_t g) const;
   int64_t n_urows() const { return (int64_t)urow_node.size(); }
 };

@@ -37,7 +37,7 @@ class EfeSystem(C.Structure):
                 ("nuc_sigma", C.c_double), ("nenr", C.c_int32), ("enr_atom", _ip), ("enr_l", _ip),
                 ("enr_m", _ip), ("enr_zeta", _dp), ("r_cut", C.c_double), ("norb", C.c_int32),
                 ("occ", _dp), ("xc", C.c_int32), ("trap_omega", C.c_double), ("quad_cell", C.c_int32),
-                ("quad_enr", C.c_int32), ("enr_drop_tol", C.c_double)]
+                ("quad_enr", C.c_int32), ("enr_drop_tol", C.c_double), ("cell_bounds", _dp)]
 
 
 class EfeOptions(C.Structure):
@@ -158,6 +158,10 @@ class _SystemHolder:
         s.quad_cell = int(spec.quad_cell)
         s.quad_enr = int(spec.quad_enr)
         s.enr_drop_tol = float(spec.enr_drop_tol)
+        bounds = getattr(spec, "bounds", None)
+        if bounds is not None:
+            self.bounds = np.ascontiguousarray(np.concatenate([np.asarray(b, dtype=np.float64) for b in bounds]))
+            s.cell_bounds = self.bounds.ctypes.data_as(_dp)
         self.sys = s
 
 

@@ -1,6 +1,7 @@
 """Write the stored expected values under tests/golden/ (calls only the oracle).
 
 Usage: python tests/golden/make_golden.py [tiny_gs] [trap_gs] [tiny_traj] [tiny_extrap] [na8] [adjoint_tiny]
+       [tiny_graded_gs] [tiny_graded_traj] [na8_graded]
 
 Every file written here is produced by the FP64 oracle from the seeded inputs of
 ``workloads``; nothing comes from the GPU library.
@@ -16,7 +17,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
-from workloads import tiny, trap, na8 as na8_spec, adjoint_field_params, ADJOINT_TINY  # noqa: E402
+from workloads import (tiny, tiny_graded, trap, na8 as na8_spec, na8_graded as na8_graded_spec,  # noqa: E402
+                       adjoint_field_params, ADJOINT_TINY)
 from oracle.model import EFEModel  # noqa: E402
 from oracle.propagate import scf_ground_state, Propagator  # noqa: E402
 
@@ -80,7 +82,32 @@ def tiny_extrap():
                         k_kick=k_kick, X_final=P.X, dt=spec.dt, kick=spec.kick)
 
 
-def na8():
+def tiny_graded_gs():
+    m = EFEModel(tiny_graded())
+    X, eps, it = scf_ground_state(m, tol=1e-11, mix=0.5)
+    np.savez_compressed(os.path.join(HERE, "tiny_graded_ground_state.npz"), X=X, eps=eps, iterations=it)
+    print("tiny_graded ground state:", eps, it)
+
+
+def tiny_graded_traj():
+    """The tiny system on its graded mesh: kick 1e-3 along z, then 50 Magnus-2 steps of 0.05 au."""
+    spec = tiny_graded()
+    m = EFEModel(spec)
+    X0 = np.load(os.path.join(HERE, "tiny_graded_ground_state.npz"))["X"]
+    P = Propagator(m, X0, tol=spec.krylov_tol, kmax=spec.kmax)
+    k_kick = P.kick(spec.kick, spec.kick_dir)
+    mus = [m.dipole(P.rho)]
+    ks = []
+    for n in range(50):
+        mu, kp, kc = P.step(spec.dt)
+        mus.append(mu)
+        ks.append(np.stack([kp, kc]))
+    np.savez_compressed(os.path.join(HERE, "tiny_graded_traj.npz"), mu=np.array(mus),
+                        k=np.array(ks, dtype=np.int32), k_kick=k_kick, X_final=P.X, dt=spec.dt, kick=spec.kick)
+    print("tiny_graded trajectory: mu_z(50) =", mus[-1][2])
+
+
+def na8(spec=None, name="na8_sampled.npz"):
     """Na8 reference values at sampled rows/points for the full-size GPU parity test.
 
     Initial orbitals X0 (enrichment directions + seeded noise, Loewdin
@@ -88,7 +115,7 @@ def na8():
     Hartree potential at sampled nodes, and (Hbar[rho(X0), t=0] X0) at sampled
     node rows and at every enrichment row.
     """
-    spec = na8_spec()
+    spec = na8_spec() if spec is None else spec
     t0 = time.time()
     m = EFEModel(spec)
     print(f"na8 model {time.time() - t0:.0f}s", flush=True)
@@ -108,10 +135,15 @@ def na8():
     print(f"Hbar rows {time.time() - t0:.0f}s", flush=True)
     q_idx = np.sort(rng.choice(m.mesh.n_quad, 8192, replace=False))
     ph_idx = np.sort(rng.choice(N, 2048, replace=False))
-    np.savez_compressed(os.path.join(HERE, "na8_sampled.npz"), rows=rows, X0_rows=X0[rows], X0_E=X0[N:],
+    np.savez_compressed(os.path.join(HERE, name), rows=rows, X0_rows=X0[rows], X0_E=X0[N:],
                         Y_rows=Yr, Y_E=YE, q_idx=q_idx, rho_q=rho[q_idx], rho_sum=float(np.sum(m.qw * rho)),
                         mu=mu, phi_idx=ph_idx, phi=phi[ph_idx], nk=m.nk)
     print("na8 done", flush=True)
+
+
+def na8_graded():
+    """The same sampled values for Na8 in its 70-bohr box on the sinh-graded mesh."""
+    na8(na8_graded_spec(), "na8_graded_sampled.npz")
 
 
 def adjoint_tiny():

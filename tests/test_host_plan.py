@@ -14,7 +14,7 @@ import re
 import numpy as np
 import pytest
 
-from workloads import tiny, trap, na_cluster
+from workloads import tiny, tiny_graded, trap, na_cluster
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -38,12 +38,13 @@ def test_exports_every_declared_symbol():
     assert sorted(names) == sorted(efe.EXPORTED)
 
 
-@pytest.fixture(scope="module")
-def tiny_pair():
+@pytest.fixture(scope="module", params=["uniform", "graded"])
+def tiny_pair(request):
+    """The tiny system on its uniform mesh and on a graded, axis-dependent one (Sec. 2.7)."""
     _lib()
     from paper_2210_14421_amd.efe import Plan
     from oracle.model import EFEModel
-    s = tiny()
+    s = tiny() if request.param == "uniform" else tiny_graded()
     return Plan(s), EFEModel(s)
 
 
@@ -136,6 +137,18 @@ def test_plan_rejects_bad_input():
     s.enr_zeta = np.array([3.0, -1.0, 1.0, 1.0, 1.0])
     with pytest.raises(EfeError):
         Plan(s)
+    # graded meshes: boundaries must run strictly from lo to hi, and be finite
+    for bad in ([-8.0, -2.0, -2.0, 3.0, 8.0], [-7.0, -2.0, 0.0, 3.0, 8.0], [-8.0, -2.0, 0.0, 3.0, 8.5]):
+        s = tiny_graded()
+        s.bounds = (np.array(bad), s.bounds[1], s.bounds[2])
+        with pytest.raises(EfeError) as e:
+            Plan(s)
+        assert e.value.status == -1
+    s = tiny_graded()
+    s.bounds = (s.bounds[0], np.array([-8.0, np.nan, 0.0, 3.0, 8.0]), s.bounds[2])
+    with pytest.raises(EfeError) as e:
+        Plan(s)
+    assert e.value.status == -6
 
 
 def test_plan_na2_matches_oracle_setup():
