@@ -2,8 +2,20 @@
 
 * Sec. 2.6, eq. (AdaptiveKrylov): exp(-i tau Hbar) psi ~ ||psi|| Q_k exp(-i tau T_k) e_1,
   with Q_k the Lanczos vectors of Hbar started from psi and T_k tridiagonal.
-  Full reorthogonalisation: two classical Gram-Schmidt passes against all
-  previous Lanczos vectors.  exp(-i tau T_k) e_1 by eigendecomposition of T_k.
+  The section gives the three-term recurrence; in floating point the vectors
+  lose orthogonality once Ritz values converge, so two ways of keeping them
+  orthogonal are provided (both reduce to the recurrence in exact arithmetic):
+  - "partial" (default): each new vector is orthogonalised against the two
+    latest ones (one classical Gram-Schmidt pass, which also yields alpha_j and
+    the recurrence's beta_{j-1} term); Simon's omega recurrence (Simon 1984,
+    "The Lanczos algorithm with partial reorthogonalization") estimates
+    omega_{j+1,k} ~ q_{j+1}^H q_k from alpha, beta alone, and when an estimate
+    exceeds sqrt(eps) the vector, and the next one, get a Gram-Schmidt pass
+    against all previous vectors (semi-orthogonality, which keeps T_k the
+    projected operator to working accuracy); a pass is also made when the
+    local one cancelled most of the vector;
+  - "full": two classical Gram-Schmidt passes against all previous vectors.
+  exp(-i tau T_k) e_1 by eigendecomposition of T_k.
 * eq. (AdaptiveKrylovErr): the error estimate of the k-dimensional
   approximation is |tau| beta_k ||psi|| |[exp(-i tau T_k)]_{k,1}|, where beta_k is
   the next off-diagonal entry (the factor |tau| converts the Lanczos data of Hbar
@@ -44,26 +56,85 @@ def tridiag_exp_e1(alpha, beta, tau):
     return V @ (np.exp(-1j * tau * lam) * V[0, :])
 
 
-def lanczos_expm_column(Aop, tau, v, tol, kmax, k_force: Optional[int] = None):
+EPS = float(np.finfo(np.float64).eps)
+SQRT_EPS = math.sqrt(EPS)
+CANCEL_ETA = 1e-3      # a local pass leaving less than this fraction of w triggers a full pass
+
+
+def omega_next(alpha, beta, b_j, om_j, om_jm1, anorm):
+    """Simon's recurrence: estimates omega_{j+1,k} ~ q_{j+1}^H q_k, k = 1..j+1.
+
+    beta_j omega_{j+1,k} = beta_k omega_{j,k+1} + (alpha_k - alpha_j) omega_{j,k}
+                           + beta_{k-1} omega_{j,k-1} - beta_{j-1} omega_{j-1,k}
+    for k < j, plus a rounding term 2 eps ||A|| of the sign of the sum; omega_{j+1,j}
+    = eps ||A|| / beta_j (the explicit local orthogonalisation) and omega_{j+1,j+1} = 1.
+    alpha = [alpha_1..alpha_j], beta = [beta_1..beta_{j-1}], b_j = beta_j,
+    om_j[k-1] = omega_{j,k} (k = 1..j), om_jm1[k-1] = omega_{j-1,k} (k = 1..j-1)."""
+    j = len(alpha)
+    a_j = alpha[-1]
+    out = np.zeros(j + 1)
+    for k in range(1, j):
+        t = beta[k - 1] * om_j[k] + (alpha[k - 1] - a_j) * om_j[k - 1]
+        if k > 1:
+            t += beta[k - 2] * om_j[k - 2]
+        t -= beta[j - 2] * om_jm1[k - 1]
+        t += math.copysign(2.0 * EPS * anorm, t)
+        out[k - 1] = t / b_j
+    out[j - 1] = EPS * anorm / b_j
+    out[j] = 1.0
+    return out
+
+
+def lanczos_expm_column(Aop, tau, v, tol, kmax, k_force: Optional[int] = None, reorth: str = "partial",
+                        stats: Optional[dict] = None):
     """One column: returns (exp(-i tau A) v approximation, k, error estimate)."""
+    if reorth not in ("partial", "full"):
+        raise ValueError(f"unknown reorthogonalisation {reorth!r}")
     beta0 = float(np.linalg.norm(v))
     if beta0 == 0.0:
         return np.zeros_like(v), 0, 0.0
     Q = [v / beta0]
     alpha, beta = [], []
+    om_j, om_jm1 = np.array([1.0]), None
+    anorm, force = 0.0, False
     for j in range(1, kmax + 1):
         q = Q[-1]
         w = Aop(q)
-        a = float(np.real(np.vdot(q, w)))
-        alpha.append(a)
-        w = w - a * q
-        if j > 1:
-            w = w - beta[-1] * Q[-2]
-        Qm = np.stack(Q, axis=1)
-        for _ in range(2):                       # two CGS passes
-            h = Qm.conj().T @ w
-            w = w - Qm @ h
-        b = float(np.linalg.norm(w))
+        if reorth == "full":
+            a = float(np.real(np.vdot(q, w)))
+            alpha.append(a)
+            w = w - a * q
+            if j > 1:
+                w = w - beta[-1] * Q[-2]
+            Qm = np.stack(Q, axis=1)
+            for _ in range(2):                       # two CGS passes
+                h = Qm.conj().T @ w
+                w = w - Qm @ h
+            b = float(np.linalg.norm(w))
+        else:
+            # local pass: one CGS step against q_{j-1}, q_j (their coefficients from the same w)
+            w0 = float(np.linalg.norm(w))
+            Ql = np.stack(Q[-2:], axis=1)
+            h = Ql.conj().T @ w
+            w = w - Ql @ h
+            a = float(np.real(h[-1]))
+            alpha.append(a)
+            b = float(np.linalg.norm(w))
+            anorm = max(anorm, abs(a) + b + (beta[-1] if beta else 0.0))
+            if b > 0.0:
+                om_new = omega_next(alpha, beta, b, om_j, om_jm1, anorm)
+                exceed = j > 1 and float(np.max(np.abs(om_new[:j - 1]))) > SQRT_EPS
+            else:
+                om_new, exceed = np.zeros(j + 1), False
+            if b > 0.0 and (exceed or force or b < CANCEL_ETA * w0):
+                Qm = np.stack(Q, axis=1)
+                w = w - Qm @ (Qm.conj().T @ w)
+                b = float(np.linalg.norm(w))
+                om_new[:j] = EPS
+                if stats is not None:
+                    stats["reorth"] = stats.get("reorth", 0) + 1
+            force = exceed
+            om_jm1, om_j = om_j, om_new
         u = tridiag_exp_e1(alpha, beta, tau)
         err = abs(tau) * b * beta0 * abs(u[-1])
         tnorm = max(abs(alpha[i]) + (beta[i - 1] if i > 0 else 0.0) + (beta[i] if i < len(beta) else 0.0)
@@ -73,13 +144,14 @@ def lanczos_expm_column(Aop, tau, v, tol, kmax, k_force: Optional[int] = None):
         else:
             done = err <= tol * beta0 or b <= 1e-14 * tnorm
         if done:
-            return beta0 * (Qm @ u), j, err
+            return beta0 * (np.stack(Q, axis=1) @ u), j, err
         beta.append(b)
         Q.append(w / b)
     raise NoConvergence(f"Lanczos did not reach tol {tol} within {kmax} vectors")
 
 
-def lanczos_expm(A, tau, X, tol=1e-10, kmax=64, k_force: Optional[Sequence[int]] = None):
+def lanczos_expm(A, tau, X, tol=1e-10, kmax=64, k_force: Optional[Sequence[int]] = None, reorth: str = "partial",
+                 stats: Optional[dict] = None):
     """exp(-i tau A) X column by column.  A: matrix (sparse/dense) or callable."""
     Aop = A if callable(A) else (lambda q: A @ q)
     X = np.asarray(X, dtype=np.complex128)
@@ -88,7 +160,7 @@ def lanczos_expm(A, tau, X, tol=1e-10, kmax=64, k_force: Optional[Sequence[int]]
     errs = np.zeros(X.shape[1])
     for a in range(X.shape[1]):
         kf = None if k_force is None else int(k_force[a])
-        Y[:, a], ks[a], errs[a] = lanczos_expm_column(Aop, tau, X[:, a], tol, kmax, kf)
+        Y[:, a], ks[a], errs[a] = lanczos_expm_column(Aop, tau, X[:, a], tol, kmax, kf, reorth, stats)
     return Y, ks, errs
 
 

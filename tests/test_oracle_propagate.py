@@ -80,6 +80,105 @@ def test_lanczos_matches_dense_expm(tiny_model):
         assert 1e-2 < ek[0] / true < 1e2, (k, ek, true)
 
 
+def _spread_operator(n=500, seed=1):
+    """Hermitian A = U diag(lam) U^H: a dense cluster in [0, 1] and six isolated large
+    eigenvalues, whose Ritz values converge within a few steps (the situation in which
+    the three-term recurrence loses orthogonality)."""
+    rng = np.random.default_rng(seed)
+    lam = np.concatenate([np.linspace(0.0, 1.0, n - 6), [200.0, 400.0, 600.0, 800.0, 1000.0, 1200.0]])
+    U, _ = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    v = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    return U, lam, v / np.linalg.norm(v)
+
+
+def _plain_lanczos_loss(A, v, k):
+    """Largest |q_i^H q_l| (i != l) of k steps of the bare three-term recurrence."""
+    Q = [v]
+    beta = 0.0
+    for j in range(k):
+        w = A @ Q[-1]
+        a = np.real(np.vdot(Q[-1], w))
+        w = w - a * Q[-1] - (beta * Q[-2] if j > 0 else 0.0)
+        beta = np.linalg.norm(w)
+        Q.append(w / beta)
+    Qm = np.stack(Q, axis=1)
+    G = Qm.conj().T @ Qm
+    return float(np.max(np.abs(G - np.eye(len(Q)))))
+
+
+@pytest.mark.parametrize("tau", [0.02, 0.1])
+def test_partial_reorth_matches_exact_and_full(tau):
+    """Simon's partial reorthogonalisation: the exponential agrees with the exact one
+    to the Krylov tolerance and with full reorthogonalisation to rounding, while the
+    bare recurrence on the same operator loses orthogonality to O(1e-3) and more."""
+    U, lam, v = _spread_operator()
+    A = (U * lam) @ U.conj().T
+    exact = U @ (np.exp(-1j * tau * lam) * (U.conj().T @ v))
+    st = {}
+    y, k, _ = lanczos_expm_column(lambda q: A @ q, tau, v, 1e-10, 200, reorth="partial", stats=st)
+    yf, kf, _ = lanczos_expm_column(lambda q: A @ q, tau, v, 1e-10, 200, reorth="full")
+    assert k == kf
+    assert st.get("reorth", 0) >= 2                       # the estimates did trigger
+    assert np.linalg.norm(y - exact) < 10 * 1e-10
+    assert np.linalg.norm(y - yf) < 1e-13
+    assert _plain_lanczos_loss(A, v, k) > 1e-3
+
+
+def test_omega_estimates_bound_the_loss():
+    """The omega recurrence tracks the actual loss of orthogonality of the bare
+    recurrence from above (within a few orders) until it passes sqrt(eps)."""
+    from oracle.propagate import omega_next, SQRT_EPS
+    U, lam, v = _spread_operator()
+    A = (U * lam) @ U.conj().T
+    Q, alpha, beta = [v], [], []
+    om_j, om_jm1, anorm = np.array([1.0]), None, 0.0
+    checked = 0
+    for j in range(1, 40):
+        w = A @ Q[-1]
+        Ql = np.stack(Q[-2:], axis=1)
+        h = Ql.conj().T @ w
+        w = w - Ql @ h
+        alpha.append(float(np.real(h[-1])))
+        b = float(np.linalg.norm(w))
+        anorm = max(anorm, abs(alpha[-1]) + b + (beta[-1] if beta else 0.0))
+        om = omega_next(alpha, beta, b, om_j, om_jm1, anorm)
+        q = w / b
+        true = np.abs(np.stack(Q, axis=1).conj().T @ q)[:-1] if j > 1 else np.zeros(0)
+        est = np.abs(om[:j - 1])
+        if j > 1 and est.max() < SQRT_EPS:
+            assert true.max() <= 10 * est.max() + 1e-15, (j, true.max(), est.max())
+            checked += 1
+        if j > 1 and true.max() > SQRT_EPS:
+            assert est.max() > 0.1 * SQRT_EPS, (j, true.max(), est.max())
+            break
+        beta.append(b)
+        Q.append(q)
+        om_jm1, om_j = om_j, om
+    assert checked >= 5
+
+
+def test_partial_reorth_on_the_tiny_hamiltonian(tiny_model):
+    """On Hbar of the tiny system the partial and full variants agree to rounding with
+    the same k, and the exact exponential to the tolerance."""
+    m = tiny_model
+    H = m.hamiltonian(m.v_nuc)
+    act = np.concatenate([m.interior, m.mesh.n_nodes + np.arange(m.nk)])
+    lam, V = np.linalg.eigh(H[act][:, act].toarray())
+    rng = np.random.default_rng(4)
+    X = np.zeros((m.n_rows, 2), dtype=np.complex128)
+    X[act] = rng.standard_normal((len(act), 2)) + 1j * rng.standard_normal((len(act), 2))
+    X /= np.linalg.norm(X, axis=0)
+    tau = 0.2
+    st = {}
+    Yp, kp, _ = lanczos_expm(H, tau, X, tol=1e-10, kmax=200, reorth="partial", stats=st)
+    Yf, kf, _ = lanczos_expm(H, tau, X, tol=1e-10, kmax=200, reorth="full")
+    exact = np.zeros_like(X)
+    exact[act] = V @ (np.exp(-1j * tau * lam)[:, None] * (V.T @ X[act]))
+    assert list(kp) == list(kf)
+    assert np.max(np.linalg.norm(Yp - Yf, axis=0)) < 1e-13
+    assert np.max(np.linalg.norm(Yp - exact, axis=0)) < 10 * 1e-10
+
+
 def test_lanczos_eigenvector_one_step(tiny_model):
     m = tiny_model
     H = m.hamiltonian(m.v_nuc)
