@@ -61,6 +61,8 @@ enum {
 enum { EFE_F64 = 0, EFE_F32 = 1, EFE_BF16 = 2, EFE_F64_SF = 3 };
 /* adiabatic LDA (Sec. 2.1): none, Slater exchange, Slater + PW92 correlation */
 enum { EFE_XC_NONE = 0, EFE_XC_SLATER = 1, EFE_XC_SLATER_PW92 = 2 };
+/* Lanczos reorthogonalisation (efe_options.reorth) */
+enum { EFE_REORTH_PARTIAL = 0, EFE_REORTH_FULL = 1 };
 /* operator exponentiated by lanczos_expm: Hbar, or the Loewdin position operator */
 enum { EFE_OP_H = 0, EFE_OP_X = 1, EFE_OP_Y = 2, EFE_OP_Z = 3 };
 
@@ -107,6 +109,13 @@ typedef struct {
   double cg_tol;           /* Poisson: relative residual                          */
   int32_t cg_maxit;
   void *hip_stream;        /* hipStream_t, or 0                                   */
+  int32_t reorth;          /* keeping the Lanczos vectors orthogonal (Sec. 2.6 gives the
+                              bare three-term recurrence): EFE_REORTH_PARTIAL (0, default):
+                              each vector against the two latest, plus a pass against all
+                              previous ones when Simon's omega recurrence (1984) estimates
+                              a loss above sqrt(eps), for that vector and the next;
+                              EFE_REORTH_FULL (1): a pass against all previous vectors at
+                              every step, repeated where it cancelled most of the vector */
 } efe_options;
 
 /* External field E(t) = dir * sum_k A_k sin(w_k t + phi_k) exp(-(t-t0)^2/s^2),

@@ -65,6 +65,7 @@ struct efe_ctx {
   int *active = nullptr, *kused = nullptr, *kforce = nullptr, *need = nullptr, *anyflag = nullptr;
   double *h1 = nullptr, *h2n = nullptr, *nrm1 = nullptr, *nrm2 = nullptr;
   double *sig = nullptr, *coef = nullptr, *gsc = nullptr, *msc = nullptr;
+  efe::ProState pro;            // partial reorthogonalisation state of the Lanczos columns
   // device-driven step (no host round trip; capturable in a hipGraph)
   double *stepp = nullptr;      // [0] E(t + dt/2), [1] E(t + dt), [2] E of a host-driven rebuild
   double *pcg_S = nullptr;      // PCG scalars
@@ -395,6 +396,10 @@ efe_status build_device(efe_ctx *ctx) {
   EFE_TRY(dalloc(ctx, &ctx->kforce, pl.norb));
   EFE_TRY(dalloc(ctx, &ctx->need, pl.norb));
   EFE_TRY(dalloc(ctx, &ctx->anyflag, 1));
+  ctx->pro.ld = ctx->kmax + 2;
+  EFE_TRY(dalloc(ctx, &ctx->pro.om, (int64_t)3 * ctx->pro.ld * std::max(1, pl.norb)));
+  EFE_TRY(dalloc(ctx, &ctx->pro.anorm, std::max(1, pl.norb)));
+  EFE_TRY(dalloc(ctx, &ctx->pro.force, std::max(1, pl.norb)));
   EFE_TRY(dalloc(ctx, &ctx->h1, (int64_t)(ctx->kmax + 1) * ctx->ncolr));
   EFE_TRY(dalloc(ctx, &ctx->h2n, (int64_t)(ctx->kmax + 1) * ctx->ncolr));
   EFE_TRY(dalloc(ctx, &ctx->nrm1, ctx->ncolr));
@@ -578,12 +583,22 @@ efe_status lz_iteration(efe_ctx *ctx, double tau, const double *X, int ncol, int
   tstart(ctx, 2);
   double *a_j = ctx->alpha + (int64_t)(j - 1) * ncol;
   double *b_j = ctx->beta + (int64_t)(j - 1) * ncol;
-  int nb = efe::k::lz_dots(X, Qb, bs, j, w, nrows, ncol, ctx->active, any, 1, ctx->red, s);
-  efe::k::reduce_partials(ctx->red, nb, (j + 1) * ncolr, ctx->h1, s);
-  efe::k::lz_coef1(ctx->h1, ctx->sig, j, ncol, ctx->active, a_j, ctx->coef, ctx->gsc, ctx->msc, s);
-  nb = efe::k::lz_update(X, Qb, bs, j, ctx->coef, ctx->gsc, w, nrows, ncol, ctx->active, any, ctx->red, s, 1);
+  // first pass: all previous slots (full) or the two latest (partial); the
+  // second pass against all slots runs for the columns that need it
+  const bool partial = ctx->opt.reorth == EFE_REORTH_PARTIAL;
+  const int first = partial ? std::max(0, j - 2) : 0, nq = j - first;
+  const double *q0f = first == 0 ? X : Qb + (int64_t)(first - 1) * bs;
+  const double *qbf = Qb + (int64_t)first * bs;
+  int nb = efe::k::lz_dots(q0f, qbf, bs, nq, w, nrows, ncol, ctx->active, any, 1, ctx->red, s);
+  efe::k::reduce_partials(ctx->red, nb, (nq + 1) * ncolr, ctx->h1, s);
+  efe::k::lz_coef1(ctx->h1, ctx->sig, j, first, ncol, ctx->active, a_j, ctx->coef, ctx->gsc, ctx->msc, s);
+  nb = efe::k::lz_update(q0f, qbf, bs, nq, ctx->coef, ctx->gsc, w, nrows, ncol, ctx->active, any, ctx->red, s, 1);
   efe::k::reduce_partials(ctx->red, nb, ncolr, ctx->nrm1, s);
-  efe::k::lz_decide(ctx->nrm1, ncol, ctx->active, ctx->gsc, ctx->need, ctx->anyflag, s);
+  if (partial)
+    efe::k::lz_pro(ctx->nrm1, ctx->msc, ctx->alpha, ctx->beta, j, ncol, ctx->active, ctx->pro, ctx->need,
+                   ctx->anyflag, s);
+  else
+    efe::k::lz_decide(ctx->nrm1, ncol, ctx->active, ctx->gsc, ctx->need, ctx->anyflag, s);
   nb = efe::k::lz_dots(X, Qb, bs, j, w, nrows, ncol, ctx->need, ctx->anyflag, 0, ctx->red, s);
   efe::k::reduce_partials(ctx->red, nb, j * ncolr, ctx->h2n, s);
   efe::k::lz_coef2(ctx->h2n, ctx->nrm1, ctx->sig, j, ncol, ctx->need, ctx->coef, ctx->gsc, ctx->msc, s);
@@ -627,7 +642,7 @@ efe_status run_lanczos(efe_ctx *ctx, double tau, const double *X, double *out, i
   tstart(ctx, 2);
   int nb = efe::k::lz_dots(X, Qb, bs, 0, X, nrows, ncol, ctx->one_mask, nullptr, 1, ctx->red, s);
   efe::k::reduce_partials(ctx->red, nb, ncolr, ctx->small, s);
-  efe::k::lz_init(ctx->small, ncol, ctx->beta0, ctx->sig, ctx->active, ctx->kused, s);
+  efe::k::lz_init(ctx->small, ncol, ctx->beta0, ctx->sig, ctx->active, ctx->kused, ctx->pro, s);
   tstop(ctx, 2);
   std::vector<int> act(ncol);
   HIP_TRY(hipMemcpyAsync(act.data(), ctx->active, ncol * sizeof(int), hipMemcpyDeviceToHost, s));
@@ -707,7 +722,7 @@ efe_status run_lanczos_dev(efe_ctx *ctx, double tau, const double *X, double *ou
   const double tol = ctx->opt.krylov_tol > 0 ? ctx->opt.krylov_tol : 1e-10;
   int nb = efe::k::lz_dots(X, ctx->Q, bs, 0, X, nrows, ncol, ctx->one_mask, nullptr, 1, ctx->red, s);
   efe::k::reduce_partials(ctx->red, nb, ncolr, ctx->small, s);
-  efe::k::lz_init(ctx->small, ncol, ctx->beta0, ctx->sig, ctx->active, ctx->kused, s);
+  efe::k::lz_init(ctx->small, ncol, ctx->beta0, ctx->sig, ctx->active, ctx->kused, ctx->pro, s);
   efe::k::lz_any(ctx->active, ncol, ctx->lz_anyf, s);
   for (int j = 1; j <= ctx->kmax; ++j) EFE_TRY(lz_iteration(ctx, tau, X, ncol, j, nullptr, tol, ctx->lz_anyf));
   efe::k::lz_comb_coef(ctx->ubuf, ctx->sig, ctx->beta0, ctx->kused, ctx->kmax, ctx->kmax, ncol, ctx->coef, s);
@@ -1261,7 +1276,9 @@ efe_status efe_plan_get(const efe_plan *plan, const char *name, double *out, int
 efe_status efe_setup(const efe_system *sys, const efe_options *opt, efe_ctx **out) {
   if (!sys || !opt || !out) return EFE_ERR_ARG;
   *out = nullptr;
-  if (opt->prod_dtype < 0 || opt->prod_dtype > 3 || opt->kmax < 1 || opt->kmax > 64) return EFE_ERR_ARG;
+  if (opt->prod_dtype < 0 || opt->prod_dtype > 3 || opt->kmax < 1 || opt->kmax > 64 || opt->reorth < 0 ||
+      opt->reorth > 1)
+    return EFE_ERR_ARG;
   efe_ctx *ctx = new (std::nothrow) efe_ctx();
   if (!ctx) return EFE_ERR_ALLOC;
   ctx->opt = *opt;
@@ -1310,10 +1327,13 @@ efe_status efe_dims(const efe_ctx *ctx, int64_t dims[4]) {
 
 efe_status efe_set_options(efe_ctx *ctx, const efe_options *opt) {
   if (!ctx || !opt) return EFE_ERR_ARG;
-  if (opt->kmax < 1 || opt->kmax > ctx->kmax || opt->prod_dtype != ctx->dtype) {
-    ctx->err = "kmax may only decrease and the product dtype is fixed at setup";
+  if (opt->kmax < 1 || opt->kmax > ctx->kmax || opt->prod_dtype != ctx->dtype || opt->reorth < 0 ||
+      opt->reorth > 1) {
+    ctx->err = "kmax may only decrease, the product dtype is fixed at setup, reorth is 0 or 1";
     return EFE_ERR_ARG;
   }
+  // a captured step holds the Krylov settings it was recorded with: record again
+  drop_graph(ctx);
   ctx->opt = *opt;
   ctx->kmax = opt->kmax;
   ctx->stream = (hipStream_t)opt->hip_stream;

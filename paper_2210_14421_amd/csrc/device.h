@@ -28,6 +28,16 @@ struct TabOff {
   int total;
 };
 
+// Partial reorthogonalisation state of the Lanczos columns: three rows of omega
+// estimates [3][ld][ncol] (rows by Lanczos index modulo 3, ld = kmax + 2), the
+// running ||T|| estimate and the forced-pass flag per column.
+struct ProState {
+  double *om = nullptr;
+  double *anorm = nullptr;
+  int *force = nullptr;
+  int ld = 0;
+};
+
 struct DevData {
   Geom g;
   TabOff to;
@@ -161,9 +171,14 @@ int lz_update(const double *q0, const double *qb, int64_t bs, int nq, const doub
 void lz_combine(const double *q0, const double *qb, int64_t bs, int nq, const double *coef, double *out,
                 int64_t nrows, int ncol, hipStream_t s, const int *nq_dev = nullptr);
 void lz_kmax(const int *kused, int ncol, int *kmaxu, hipStream_t s);
-void lz_init(const double *h0, int ncol, double *beta0, double *sig, int *active, int *kused, hipStream_t s);
-void lz_coef1(const double *h, const double *sig, int j, int ncol, const int *active, double *alpha_j, double *coef,
-              double *gsc, double *msc, hipStream_t s);
+void lz_init(const double *h0, int ncol, double *beta0, double *sig, int *active, int *kused, const ProState &pro,
+             hipStream_t s);
+// first: the first slot of the dot pass the coefficients come from (0: all slots)
+void lz_coef1(const double *h, const double *sig, int j, int first, int ncol, const int *active, double *alpha_j,
+              double *coef, double *gsc, double *msc, hipStream_t s);
+// partial reorthogonalisation decision after the local pass of iteration j (sets need, any)
+void lz_pro(const double *nrm1, const double *msc, const double *alpha, const double *beta, int j, int ncol,
+            const int *active, const ProState &pro, int *need, int *any, hipStream_t s);
 void lz_decide(const double *nrm1, int ncol, const int *active, const double *gsc, int *need, int *any,
                hipStream_t s);
 void lz_coef2(const double *h2, const double *nrm1, const double *sig, int j, int ncol, const int *need, double *coef,

@@ -227,9 +227,13 @@ k_lz_combine(Basis B, int l0, int nl, const double2 *__restrict__ coef, double2 
 }
 
 // ------------------------------------------------------------ coefficients
-// Start: beta0 = ||X||, sig_0 = 1 / beta0, active = beta0 > 0.
+constexpr double kReorthEta = 1e-3;
+
+// Start: beta0 = ||X||, sig_0 = 1 / beta0, active = beta0 > 0; the partial
+// reorthogonalisation state (||T|| estimate, forced pass, omega_1 = 1) restarts.
 __global__ void k_lz_init(const double2 *__restrict__ h0, int ncol, double *__restrict__ beta0,
-                          double *__restrict__ sig, int *__restrict__ active, int *__restrict__ kused) {
+                          double *__restrict__ sig, int *__restrict__ active, int *__restrict__ kused,
+                          ProState pro) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncol) return;
   const double n2 = h0[c].x;
@@ -238,37 +242,105 @@ __global__ void k_lz_init(const double2 *__restrict__ h0, int ncol, double *__re
   sig[c] = b > 0.0 ? 1.0 / b : 0.0;
   active[c] = b > 0.0 ? 1 : 0;
   kused[c] = 0;
+  if (pro.om) {
+    pro.anorm[c] = 0.0;
+    pro.force[c] = 0;
+    pro.om[((int64_t)1 * pro.ld) * ncol + c] = 1.0;   // omega_{1,1} (row of q_1: 1 % 3)
+  }
 }
 
-// After the first dot pass of iteration j (slot j = Hbar slot_{j-1}):
-// h[l][c] = <slot_l, slot_j> for l < j and h[j][c] = ||slot_j||^2.
-// alpha_j = sig_{j-1}^2 Re h[j-1]; the first update is
+// After the first dot pass of iteration j (slot j = Hbar slot_{j-1}) over the
+// slots first .. j-1: h[l - first][c] = <slot_l, slot_j> and h[j - first][c] =
+// ||slot_j||^2.  alpha_j = sig_{j-1}^2 Re <slot_{j-1}, slot_j>; the first update is
 // slot_j <- g (slot_j - sum_l sig_l^2 h[l] slot_l) with g = 1 / ||slot_j||,
 // after which the Lanczos residual is msc * slot_j with msc = sig_{j-1} / g.
-__global__ void k_lz_coef1(const double2 *__restrict__ h, const double *__restrict__ sig, int j, int ncol,
+// first = 0: all previous slots; first = j - 2: the two latest (partial scheme).
+__global__ void k_lz_coef1(const double2 *__restrict__ h, const double *__restrict__ sig, int j, int first, int ncol,
                            const int *__restrict__ active, double *__restrict__ alpha_j, double2 *__restrict__ coef,
                            double *__restrict__ gsc, double *__restrict__ msc) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncol || !active[c]) return;
-  const double w2 = h[(int64_t)j * ncol + c].x;
+  const double w2 = h[(int64_t)(j - first) * ncol + c].x;
   const double g = w2 > 0.0 ? 1.0 / sqrt(w2) : 0.0;
   const double sj = sig[(int64_t)(j - 1) * ncol + c];
-  alpha_j[c] = sj * sj * h[(int64_t)(j - 1) * ncol + c].x;
-  for (int l = 0; l < j; ++l) {
+  alpha_j[c] = sj * sj * h[(int64_t)(j - 1 - first) * ncol + c].x;
+  for (int l = first; l < j; ++l) {
     const double s = sig[(int64_t)l * ncol + c];
     const double f = g * s * s;
-    const double2 v = h[(int64_t)l * ncol + c];
-    coef[(int64_t)l * ncol + c] = make_double2(f * v.x, f * v.y);
+    const double2 v = h[(int64_t)(l - first) * ncol + c];
+    coef[(int64_t)(l - first) * ncol + c] = make_double2(f * v.x, f * v.y);
   }
   gsc[c] = g;
   msc[c] = g > 0.0 ? sj / g : 0.0;
+}
+
+// Partial reorthogonalisation (Simon 1984): after the local pass of iteration j,
+// beta_j ~ msc ||slot_j|| and the omega recurrence estimates omega_{j+1,k} ~
+// q_{j+1}^H q_k from alpha_1..j, beta_1..j-1 and the rows omega_j, omega_{j-1}:
+//   beta_j omega_{j+1,k} = beta_k omega_{j,k+1} + (alpha_k - alpha_j) omega_{j,k}
+//                          + beta_{k-1} omega_{j,k-1} - beta_{j-1} omega_{j-1,k}  (k < j)
+// plus 2 eps ||T|| with the sign of the sum; omega_{j+1,j} = eps ||T|| / beta_j and
+// omega_{j+1,j+1} = 1 (||T|| = running max of |alpha_i| + beta_i + beta_{i-1}).
+// A column needs a pass against every previous slot when an estimate exceeds
+// sqrt(eps), when the previous iteration's estimates did (the pass is made for two
+// vectors in a row), or when the local pass cancelled most of the vector; the
+// estimates of a column that gets the pass restart at eps.  One thread per column.
+__global__ void k_lz_pro(const double2 *__restrict__ nrm1, const double *__restrict__ msc,
+                         const double *__restrict__ alpha, const double *__restrict__ beta, int j, int ncol,
+                         const int *__restrict__ active, ProState pro, int *__restrict__ need, int *__restrict__ any) {
+  __shared__ int flag;
+  if (threadIdx.x == 0) flag = 0;
+  __syncthreads();
+  constexpr double eps = 2.220446049250313e-16, sqrt_eps = 1.4901161193847656e-08;
+  for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
+    int nd = 0;
+    if (active[c]) {
+      const double n1 = nrm1[c].x;
+      const double bj = msc[c] * sqrt(n1 > 0.0 ? n1 : 0.0);
+      const double aj = alpha[(int64_t)(j - 1) * ncol + c];
+      const double bjm1 = j > 1 ? beta[(int64_t)(j - 2) * ncol + c] : 0.0;
+      double an = fmax(pro.anorm[c], fabs(aj) + bj + bjm1);
+      pro.anorm[c] = an;
+      // rows by Lanczos index modulo 3: omega_j (cur), omega_{j-1} (old), omega_{j+1} (new)
+      const double *cur = pro.om + (int64_t)((j % 3) * pro.ld) * ncol + c;
+      const double *old = pro.om + (int64_t)(((j + 2) % 3) * pro.ld) * ncol + c;
+      double *nw = pro.om + (int64_t)(((j + 1) % 3) * pro.ld) * ncol + c;
+      double mx = 0.0;
+      if (bj > 0.0) {
+        for (int k = 1; k < j; ++k) {
+          const double ojk1 = k + 1 == j ? 1.0 : cur[(int64_t)k * ncol];
+          double t = beta[(int64_t)(k - 1) * ncol + c] * ojk1 +
+                     (alpha[(int64_t)(k - 1) * ncol + c] - aj) * cur[(int64_t)(k - 1) * ncol];
+          if (k > 1) t += beta[(int64_t)(k - 2) * ncol + c] * cur[(int64_t)(k - 2) * ncol];
+          const double ojm1 = k == j - 1 ? 1.0 : old[(int64_t)(k - 1) * ncol];
+          t -= bjm1 * ojm1;
+          t += copysign(2.0 * eps * an, t);
+          const double o = t / bj;
+          nw[(int64_t)(k - 1) * ncol] = o;
+          mx = fmax(mx, fabs(o));
+        }
+        nw[(int64_t)(j - 1) * ncol] = eps * an / bj;
+      } else {
+        for (int k = 1; k <= j; ++k) nw[(int64_t)(k - 1) * ncol] = 0.0;
+      }
+      nw[(int64_t)j * ncol] = 1.0;
+      const int exceed = (j > 1 && mx > sqrt_eps) ? 1 : 0;
+      nd = (bj > 0.0 && (exceed || pro.force[c] || n1 < kReorthEta * kReorthEta)) ? 1 : 0;
+      if (nd)
+        for (int k = 1; k <= j; ++k) nw[(int64_t)(k - 1) * ncol] = eps;
+      pro.force[c] = exceed;
+    }
+    need[c] = nd;
+    if (nd) atomicOr(&flag, 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *any = flag;
 }
 
 // Daniel-Gragg-Kaufman-Stewart test: the first pass loses at most
 // eps ||w|| / ||w'|| of orthogonality, so a second pass is made only for
 // columns where it cancelled most of w (||w'|| < kReorthEta ||w||; the slot was
 // scaled to ||w|| = 1).
-constexpr double kReorthEta = 1e-3;
 __global__ void k_lz_decide(const double2 *__restrict__ nrm1, int ncol, const int *__restrict__ active,
                             const double *__restrict__ gsc, int *__restrict__ need, int *__restrict__ any) {
   __shared__ int flag;
@@ -431,15 +503,22 @@ void lz_combine(const double *q0, const double *qb, int64_t bs, int nq, const do
   }
 }
 
-void lz_init(const double *h0, int ncol, double *beta0, double *sig, int *active, int *kused, hipStream_t s) {
+void lz_init(const double *h0, int ncol, double *beta0, double *sig, int *active, int *kused, const ProState &pro,
+             hipStream_t s) {
   hipLaunchKernelGGL(k_lz_init, dim3((ncol + 63) / 64), dim3(64), 0, s, (const double2 *)h0, ncol, beta0, sig, active,
-                     kused);
+                     kused, pro);
 }
 
-void lz_coef1(const double *h, const double *sig, int j, int ncol, const int *active, double *alpha_j, double *coef,
-              double *gsc, double *msc, hipStream_t s) {
-  hipLaunchKernelGGL(k_lz_coef1, dim3((ncol + 63) / 64), dim3(64), 0, s, (const double2 *)h, sig, j, ncol, active,
-                     alpha_j, (double2 *)coef, gsc, msc);
+void lz_coef1(const double *h, const double *sig, int j, int first, int ncol, const int *active, double *alpha_j,
+              double *coef, double *gsc, double *msc, hipStream_t s) {
+  hipLaunchKernelGGL(k_lz_coef1, dim3((ncol + 63) / 64), dim3(64), 0, s, (const double2 *)h, sig, j, first, ncol,
+                     active, alpha_j, (double2 *)coef, gsc, msc);
+}
+
+void lz_pro(const double *nrm1, const double *msc, const double *alpha, const double *beta, int j, int ncol,
+            const int *active, const ProState &pro, int *need, int *any, hipStream_t s) {
+  hipLaunchKernelGGL(k_lz_pro, dim3(1), dim3(128), 0, s, (const double2 *)nrm1, msc, alpha, beta, j, ncol, active, pro,
+                     need, any);
 }
 
 void lz_decide(const double *nrm1, int ncol, const int *active, const double *gsc, int *need, int *any,

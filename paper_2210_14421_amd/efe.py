@@ -42,7 +42,11 @@ class EfeSystem(C.Structure):
 
 class EfeOptions(C.Structure):
     _fields_ = [("prod_dtype", C.c_int32), ("kmax", C.c_int32), ("krylov_tol", C.c_double),
-                ("cg_tol", C.c_double), ("cg_maxit", C.c_int32), ("hip_stream", C.c_void_p)]
+                ("cg_tol", C.c_double), ("cg_maxit", C.c_int32), ("hip_stream", C.c_void_p),
+                ("reorth", C.c_int32)]
+
+
+REORTH = {"partial": 0, "full": 1}
 
 
 class EfeField(C.Structure):
@@ -247,7 +251,8 @@ def _stats_dict(st, n):
 class Context:
     """A GPU context: static data uploaded, workspace allocated."""
 
-    def __init__(self, spec, dtype="f64", kmax=None, tol=None, cg_tol=1e-12, cg_maxit=50, stream=None):
+    def __init__(self, spec, dtype="f64", kmax=None, tol=None, cg_tol=1e-12, cg_maxit=50, stream=None,
+                 reorth="partial"):
         import torch
         self.torch = torch
         self.spec = spec
@@ -258,6 +263,7 @@ class Context:
         o.krylov_tol = float(tol if tol is not None else spec.krylov_tol)
         o.cg_tol = float(cg_tol)
         o.cg_maxit = int(cg_maxit)
+        o.reorth = REORTH[reorth]
         s = stream if stream is not None else torch.cuda.current_stream()
         o.hip_stream = C.c_void_p(s.cuda_stream)
         self._opt = o
