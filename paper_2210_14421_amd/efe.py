@@ -280,6 +280,19 @@ class Context:
         self.norb = spec.norb
         self.kmax = o.kmax
 
+    def set_options(self, kmax=None, tol=None, reorth=None):
+        """Change the Krylov settings of the live context (kmax only downwards); a
+        captured step is recorded again at its next use."""
+        o = self._opt
+        if kmax is not None:
+            o.kmax = int(kmax)
+        if tol is not None:
+            o.krylov_tol = float(tol)
+        if reorth is not None:
+            o.reorth = REORTH[reorth]
+        self._check(_set_options(self._c, C.byref(o)))
+        self.kmax = o.kmax
+
     # -- helpers ---------------------------------------------------------------
     def _check(self, st):
         if st != EFE_OK:

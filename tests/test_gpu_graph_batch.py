@@ -87,6 +87,30 @@ def test_graph_recaptures_on_new_block(tiny_gs):
         cb.close()
 
 
+def test_graph_recaptures_after_new_options(tiny_gs):
+    """A captured step holds its Krylov settings: after set_options (here the full
+    reorthogonalisation and a tighter tolerance) the next graph step is recorded
+    again and equals a host-driven step with the new settings."""
+    from workloads import tiny
+    from paper_2210_14421_amd.efe import Context
+    spec = tiny()
+    ca, cb = Context(spec, kmax=40, reorth="full", tol=1e-12), Context(spec, kmax=40)
+    try:
+        Pa, Pb = _kicked(ca, tiny_gs), _kicked(cb, tiny_gs)
+        cb.magnus_step(Pb, 0.0, spec.dt, graph=True)          # captured with the default settings
+        cb.set_options(reorth="full", tol=1e-12)
+        Pb2 = _kicked(cb, tiny_gs)
+        Pb.copy_(Pb2)
+        cb.set_hamiltonian(Pb, 0.0)
+        sa = ca.magnus_step(Pa, 0.0, spec.dt)
+        sb = cb.magnus_step(Pb, 0.0, spec.dt, graph=True)
+        assert list(sa["k_pred"]) == list(sb["k_pred"]) and list(sa["k_corr"]) == list(sb["k_corr"])
+        assert _rel(Pb, Pa) < 1e-12
+    finally:
+        ca.close()
+        cb.close()
+
+
 def test_batch_matches_members_alone(tiny_gs):
     from workloads import tiny, trap
     from paper_2210_14421_amd.efe import Context, Batch
