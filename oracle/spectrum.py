@@ -17,6 +17,14 @@ Readings (the printed formula divides by the field transform twice):
 * pulses: a delta kick of strength kappa at t = 0 (F[E] = kappa), or the
   Gaussian kappa exp(-(t - t0)^2 / (2 s^2)) of Sec. 3.1-3.2, whose transform is
   kappa s sqrt(2 pi) exp(-omega^2 s^2 / 2) exp(i omega t0).
+
+Sec. 3.5 (high-harmonic generation): the dipole power spectrum is the squared
+modulus of the windowed Fourier transform of the dipole acceleration.  Readings
+(the printed derivative reads d/dt^2): P(omega) = |int_0^T exp(-i omega t)
+exp(-t^2/tau) mu_d''(t) dt|^2 with the Gaussian window as printed, mu_d'' by the
+second central difference at the interior samples t_1 .. t_{N-1}, and the
+trapezoid rule over those samples.  The sinusoidal pulse of that section is
+kappa sin(pi t/T) sin(omega t) on [0, T].
 """
 from __future__ import annotations
 
@@ -59,3 +67,22 @@ def absorption_spectrum(traces, directions, dt, omega, tau, pulse):
     for mu, d in zip(traces, directions):
         acc += np.imag(polarizability(mu, d, dt, omega, tau, pulse))
     return 2.0 * omega / (3.0 * math.pi) * acc
+
+
+def dipole_acceleration(mu_d, dt):
+    """mu''(t_n), n = 1 .. N-1, by the second central difference of the samples mu_d[0..N]."""
+    mu_d = np.asarray(mu_d, dtype=np.float64)
+    return (mu_d[2:] - 2.0 * mu_d[1:-1] + mu_d[:-2]) / (dt * dt)
+
+
+def power_spectrum(mu, direction, dt, omega, tau):
+    """P(omega) = |int exp(-i omega t) exp(-t^2 / tau) mu_d''(t) dt|^2 over t_1 .. t_{N-1}
+    (trapezoid rule), mu[n][3] sampled at t_n = n dt."""
+    mu = np.asarray(mu, dtype=np.float64)
+    acc = dipole_acceleration(mu[:, direction], dt)
+    t = dt * np.arange(1, len(mu) - 1)
+    w = np.full(len(t), dt)
+    w[0] = w[-1] = 0.5 * dt
+    f = w * np.exp(-t * t / tau) * acc
+    F = np.exp(-1j * np.outer(np.asarray(omega, dtype=np.float64), t)) @ f
+    return np.abs(F) ** 2

@@ -99,3 +99,79 @@ def test_kohn_mode_spectrum_in_trap(golden_dir):
     print("trap spectrum: peak", w[np.argmax(S)], "max deviation from the ideal", err, "sum rule", total)
     assert err < 0.05
     assert abs(total - 2.0) < 0.1
+
+
+# ---------------------------------------------------------------- power spectrum (Sec. 3.5)
+
+def _windowed_exact(f, t_a, t_b, omega, tau):
+    """|int_{t_a}^{t_b} exp(-i w t) exp(-t^2/tau) f(t) dt|^2 by adaptive quadrature."""
+    from scipy.integrate import quad
+    out = []
+    g = lambda t: math.exp(-t * t / tau) * f(t)
+    for w in omega:
+        if w == 0.0:
+            re, im = quad(g, t_a, t_b, limit=400, epsabs=0, epsrel=1e-12)[0], 0.0
+        else:      # QAWO: the oscillatory factor is integrated exactly against the polynomial fits
+            re = quad(g, t_a, t_b, weight="cos", wvar=w, limit=800, epsabs=0, epsrel=1e-12)[0]
+            im = -quad(g, t_a, t_b, weight="sin", wvar=w, limit=800, epsabs=0, epsrel=1e-12)[0]
+        out.append(re * re + im * im)
+    return np.array(out)
+
+
+def test_power_spectrum_of_a_cubic_dipole():
+    """mu = 2 + t/2 - 0.3 t^2 + 0.07 t^3: the second difference is exact (mu'' = -0.6 + 0.42 t),
+    so P equals the windowed integral of mu'' over [t_1, t_{N-1}] to the trapezoid error."""
+    from oracle.spectrum import power_spectrum, dipole_acceleration
+    dt, N, tau = 0.005, 4000, 50.0
+    t = dt * np.arange(N + 1)
+    mu = np.zeros((N + 1, 3))
+    mu[:, 1] = 2.0 + 0.5 * t - 0.3 * t ** 2 + 0.07 * t ** 3
+    np.testing.assert_allclose(dipole_acceleration(mu[:, 1], dt), -0.6 + 0.42 * t[1:-1], rtol=0, atol=2e-7)
+    omega = np.array([0.0, 0.4, 1.3, 2.9])
+    P = power_spectrum(mu, 1, dt, omega, tau)
+    ref = _windowed_exact(lambda x: -0.6 + 0.42 * x, t[1], t[-2], omega, tau)
+    np.testing.assert_allclose(P, ref, rtol=1e-4)
+    # the window is exp(-t^2/tau): with exp(-t/tau) the value differs by orders
+    alt = _windowed_exact(lambda x: (-0.6 + 0.42 * x) * math.exp(x * x / tau - x / tau), t[1], t[-2], omega[:1], tau)
+    assert abs(alt[0] - P[0]) > 0.5 * P[0]
+
+
+def test_power_spectrum_of_linear_dipole_vanishes():
+    from oracle.spectrum import power_spectrum
+    dt = 0.05
+    t = dt * np.arange(2001)
+    mu = np.stack([3.0 - 0.2 * t, 0.1 * t, np.full_like(t, 7.0)], axis=1)
+    P = power_spectrum(mu, 0, dt, np.linspace(0.0, 3.0, 7), 1e5)
+    assert np.max(P) < 1e-16
+
+
+def test_power_spectrum_peaks_at_the_oscillation():
+    """mu = sin(w0 t): |F[mu'']|^2 peaks at w0 (not at w0/2 or 2 w0) and equals
+    w0^4 |F[sin]|^2 there up to the O((w0 dt)^2) error of the difference."""
+    from oracle.spectrum import power_spectrum
+    w0, dt, N, tau = 0.7, 0.02, 20000, 1e5
+    t = dt * np.arange(N + 1)
+    mu = np.zeros((N + 1, 3))
+    mu[:, 2] = np.sin(w0 * t)
+    omega = np.linspace(0.05, 2.0, 391)
+    P = power_spectrum(mu, 2, dt, omega, tau)
+    assert abs(omega[np.argmax(P)] - w0) <= 0.005 + 1e-12
+    # at omega = w0: sin(w0 t) exp(-i w0 t) = sin(2 w0 t)/2 - i (1 - cos(2 w0 t))/2
+    from scipy.integrate import quad
+    g0 = lambda x: -w0 * w0 * math.exp(-x * x / tau)
+    a, b = t[1], t[-2]
+    re = 0.5 * quad(g0, a, b, weight="sin", wvar=2 * w0, limit=800)[0]
+    im = -0.5 * quad(g0, a, b, limit=400)[0] + 0.5 * quad(g0, a, b, weight="cos", wvar=2 * w0, limit=800)[0]
+    np.testing.assert_allclose(P[np.argmin(np.abs(omega - w0))], re * re + im * im, rtol=1e-3)
+
+
+def test_hhg_field_is_the_sinusoidal_pulse():
+    """The sum-of-sines parameters reproduce kappa sin(pi t/T) sin(omega t) on [0, T]."""
+    from oracle.model import Field
+    from workloads import hhg_field
+    p = hhg_field(kappa=0.01, omega=0.03, ncycles=5)
+    f = Field(direction=p["direction"], A=p["A"], w=p["w"], phi=p["phi"], t0=p["t0"], s=p["s"])
+    T = p["T"]
+    assert abs(T - 5 * 2 * math.pi / 0.03) < 1e-9
+    for t in np.linspace(0.0, T, 97):
+        assert abs(f.E(t) - 0.01 * math.sin(math.pi * t / T) * math.sin(0.03 * t)) < 1e-15

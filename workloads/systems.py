@@ -183,6 +183,17 @@ def na8() -> SystemSpec:
     return na_cluster(8, seed=0)
 
 
+def hhg_field(kappa: float = 0.01, omega: float = 0.03, ncycles: int = 5, direction: int = 0) -> dict:
+    """The sinusoidal pulse of the high-harmonic study, kappa sin(pi t / T) sin(omega t) on
+    [0, T], T = ncycles 2 pi / omega, in the sum-of-sines form the field interface takes
+    (sum_k A_k sin(w_k t + phi_k) with a flat envelope, s = inf), using
+    sin(a) sin(b) = (cos(a - b) - cos(a + b)) / 2 and cos(x) = sin(x + pi/2)."""
+    T = ncycles * 2.0 * np.pi / omega
+    return dict(direction=direction, A=np.array([0.5 * kappa, -0.5 * kappa]),
+                w=np.array([omega - np.pi / T, omega + np.pi / T]), phi=np.array([0.5 * np.pi, 0.5 * np.pi]),
+                t0=0.0, s=float("inf"), T=T)
+
+
 def graded_bounds(lo: float, hi: float, ncell: int, beta: float) -> np.ndarray:
     """ncell + 1 cell boundaries on [lo, hi] from x = c + a sinh(beta xi) / sinh(beta),
     xi uniform on [-1, 1] (c, a the box centre and half-length; beta = 0: uniform).
