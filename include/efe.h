@@ -234,6 +234,17 @@ efe_status absorption_spectrum(const double *mu, const int32_t *dirs, int32_t nd
                                const efe_pulse *pulse, double tau, const double *omega, int64_t nw,
                                double *S, double *alpha, void *hip_stream);
 
+/* Dipole power spectrum of a driven run (Sec. 3.5, high-harmonic generation):
+ * P[i] = |int_0^T exp(-i omega_i t) exp(-t^2/tau) mu_d''(t) dt|^2 with mu_d'' the
+ * second central difference of the samples and the trapezoid rule over the
+ * interior samples t_1 .. t_{nt-1} (the Gaussian window as printed).  mu: device,
+ * [nt + 1][3], the dipole at t_n = n dt; direction d: 0..2; omega: device, nw;
+ * P: device, nw.  hip_stream: a hipStream_t or NULL for the null stream; the
+ * call waits for its kernel.  EFE_ERR_ARG for nt < 2, nw out of 1..2^31, a
+ * direction out of range, dt not positive and finite, or tau not positive. */
+efe_status power_spectrum(const double *mu, int32_t direction, int64_t nt, double dt, double tau,
+                          const double *omega, int64_t nw, double *P, void *hip_stream);
+
 /* flags of magnus_step_extrap */
 enum { EFE_STEP_KEEP_HAM = 1 };
 

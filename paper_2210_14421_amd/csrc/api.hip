@@ -1442,6 +1442,18 @@ efe_status absorption_spectrum(const double *mu, const int32_t *dirs, int32_t nd
   return EFE_OK;
 }
 
+efe_status power_spectrum(const double *mu, int32_t direction, int64_t nt, double dt, double tau,
+                          const double *omega, int64_t nw, double *P, void *hip_stream) {
+  if (!mu || !omega || !P || direction < 0 || direction > 2 || nt < 2 || nw < 1 || nw > (1LL << 31) ||
+      !(dt > 0.0) || !std::isfinite(dt) || !(tau > 0.0))
+    return EFE_ERR_ARG;
+  hipStream_t st = (hipStream_t)hip_stream;
+  efe::k::power_spectrum(mu, direction, nt + 1, dt, tau, omega, nw, P, st);
+  if (hipGetLastError() != hipSuccess) return EFE_ERR_HIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return EFE_ERR_HIP;
+  return EFE_OK;
+}
+
 efe_status magnus_step_extrap(efe_ctx *ctx, void *Psi, int64_t ld, double t, double dt, const efe_field *field,
                               const int32_t *k_force, int32_t flags, efe_step_stats *stats) {
   if (!ctx || !Psi || ld < ctx->norb || !std::isfinite(t) || !std::isfinite(dt) || (flags & ~EFE_STEP_KEEP_HAM))

@@ -157,6 +157,9 @@ void reduce_partials(const double *part, int nblk, int nval, double *out, hipStr
 void dipole_partials(const DevData &d, const double *rho, double *part, int *nblk, hipStream_t s);
 
 // absorption spectrum (Sec. 3.2): S[nw], alpha[ndir][nw][2] (may be null) from traces mu[ndir][nt1][3]
+// P[i] = |int exp(-t^2/tau) mu_dir''(t) exp(-i omega_i t) dt|^2 (mu: device [nt1][3], nt1 >= 3)
+void power_spectrum(const double *mu, int dir, int64_t nt1, double dt, double tau, const double *omega, int64_t nw,
+                    double *P, hipStream_t st);
 void spectrum(const double *mu, const int *dirs, int ndir, int64_t nt1, double dt, double tau, int kind,
               double kappa, double t0, double s, const double *omega, int64_t nw, double *S, double *alpha,
               hipStream_t st);

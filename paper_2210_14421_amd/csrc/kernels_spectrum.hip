@@ -1,6 +1,7 @@
 // Absorption spectrum from dipole traces (Sec. 3.2): the windowed Fourier
 // transform of the dipole response of each perturbed run, divided by the
 // transform of the applied field, and S(omega) = (2 omega / 3 pi) sum_d Im alpha_dd.
+// Dipole power spectrum of a driven run (Sec. 3.5): |windowed transform of mu''|^2.
 #include <hip/hip_runtime.h>
 
 #include "device.h"
@@ -73,9 +74,52 @@ k_spectrum(const double *__restrict__ mu, Dirs dirs, int ndir, int64_t nt1, doub
   if (threadIdx.x == 0) S[iw] = 2.0 * w / (3.0 * 3.14159265358979323846) * sum_im;
 }
 
+// Dipole power spectrum (Sec. 3.5): one workgroup per frequency;
+// P(omega) = |sum_n w_n exp(-t_n^2 / tau) mu''(t_n) exp(-i omega t_n)|^2 over the interior
+// samples n = 1 .. nt1 - 2 (second central difference, trapezoid weights dt, dt/2 at the
+// two ends), reduced in a fixed order.  mu: [nt1][3].
+__global__ void __launch_bounds__(kSpecThreads)
+k_power_spectrum(const double *__restrict__ mu, int dir, int64_t nt1, double dt, double tau,
+                 const double *__restrict__ omega, double *__restrict__ P, int64_t nw) {
+  __shared__ double red[2][kSpecThreads];
+  const int64_t iw = blockIdx.x;
+  if (iw >= nw) return;
+  const double w = omega[iw];
+  const double idt2 = 1.0 / (dt * dt);
+  double re = 0.0, im = 0.0;
+  for (int64_t n = 1 + threadIdx.x; n <= nt1 - 2; n += kSpecThreads) {
+    const double t = dt * (double)n;
+    const double acc = (mu[(n + 1) * 3 + dir] - 2.0 * mu[n * 3 + dir] + mu[(n - 1) * 3 + dir]) * idt2;
+    const double wt = (n == 1 || n == nt1 - 2) ? 0.5 * dt : dt;
+    const double f = wt * exp(-t * t / tau) * acc;
+    double sn, cs;
+    sincos(w * t, &sn, &cs);
+    re += f * cs;
+    im -= f * sn;
+  }
+  red[0][threadIdx.x] = re;
+  red[1][threadIdx.x] = im;
+  __syncthreads();
+  for (int h = kSpecThreads / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) {
+      red[0][threadIdx.x] += red[0][threadIdx.x + h];
+      red[1][threadIdx.x] += red[1][threadIdx.x + h];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) P[iw] = red[0][0] * red[0][0] + red[1][0] * red[1][0];
+}
+
 }  // namespace
 
 namespace k {
+
+void power_spectrum(const double *mu, int dir, int64_t nt1, double dt, double tau, const double *omega, int64_t nw,
+                    double *P, hipStream_t st) {
+  hipLaunchKernelGGL(k_power_spectrum, dim3((unsigned)nw), dim3(kSpecThreads), 0, st, mu, dir, nt1, dt, tau, omega,
+                     P, nw);
+}
+
 
 void spectrum(const double *mu, const int *dirs, int ndir, int64_t nt1, double dt, double tau, int kind,
               double kappa, double t0, double s, const double *omega, int64_t nw, double *S, double *alpha,

@@ -89,6 +89,8 @@ _magnus = _sig("magnus_step", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c
 _magnus_extrap = _sig("magnus_step_extrap", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_double,
                                                         C.POINTER(EfeField), _ip, C.c_int32, C.POINTER(EfeStepStats)])
 EFE_STEP_KEEP_HAM = 1
+_power = _sig("power_spectrum", C.c_int32, [C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_double, C.c_void_p,
+                                            C.c_int64, C.c_void_p, C.c_void_p])
 _spectrum = _sig("absorption_spectrum", C.c_int32, [C.c_void_p, _ip, C.c_int32, C.c_int64, C.c_double,
                                                      C.POINTER(EfePulse), C.c_double, C.c_void_p, C.c_int64,
                                                      C.c_void_p, C.c_void_p, C.c_void_p])
@@ -115,7 +117,7 @@ EXPORTED = ["efe_plan_create", "efe_plan_free", "efe_plan_sizes", "efe_plan_get"
             "efe_set_hamiltonian", "efe_apply_H", "lanczos_expm", "magnus_step", "density",
             "efe_hartree", "dipole", "efe_enable_timing", "efe_get_timing", "efe_last_error",
             "magnus_step_graph", "efe_batch_create", "efe_batch_free", "efe_batch_error", "efe_batch_step",
-            "magnus_adjoint", "dipole_adjoint", "magnus_step_extrap", "absorption_spectrum"]
+            "magnus_adjoint", "dipole_adjoint", "magnus_step_extrap", "absorption_spectrum", "power_spectrum"]
 
 
 class EfeError(RuntimeError):
@@ -228,6 +230,24 @@ def absorption_spectrum(mu, dirs, dt, omega, tau, pulse, with_alpha=False):
     if with_alpha:
         return S, torch.view_as_complex(alpha)
     return S
+
+
+def power_spectrum(mu, direction, dt, omega, tau):
+    """Dipole power spectrum of a driven run (Sec. 3.5): mu (device float64 [nt + 1, 3]),
+    omega (device float64 [nw]); returns P (device, nw)."""
+    import torch
+    for name, t in (("mu", mu), ("omega", omega)):
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise ValueError(f"{name}: contiguous float64 device tensor expected")
+    if mu.dim() != 2 or mu.shape[1] != 3:
+        raise ValueError("mu: [nt + 1, 3] expected")
+    P = torch.empty(omega.shape[0], dtype=torch.float64, device=omega.device)
+    st = _power(C.c_void_p(mu.data_ptr()), int(direction), mu.shape[0] - 1, float(dt), float(tau),
+                C.c_void_p(omega.data_ptr()), omega.shape[0], C.c_void_p(P.data_ptr()),
+                C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if st != EFE_OK:
+        raise EfeError(st, "power_spectrum")
+    return P
 
 
 def make_field(direction=2, A=(), w=(), phi=(), t0=0.0, s=1.0):
