@@ -98,7 +98,7 @@ inline size_t cell_lds_bytes(int nloc, size_t esz) {
 }
 
 template <typename T, int CMT>
-__global__ void __launch_bounds__(kCellWaves * 64)
+__global__ void __launch_bounds__(kCellWaves * 64) __attribute__((amdgpu_waves_per_eu(CMT <= 4 ? 4 : 2)))
 k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, const T *__restrict__ cells,
              const double *__restrict__ X, double *__restrict__ Y, int ncolr, int64_t ldr, const int *__restrict__ any) {
   if (any && *any == 0) return;
@@ -183,23 +183,28 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
     const int st = kc % kCellNS;
     const T *Al = (const T *)(As + st * aseg * 1024);
     const double *Xl = (const double *)(Xs + st * kCellXStage);
+    // per k-step: the step's operands first (one LDS wait), then its MFMAs.  Rows m past
+    // nloc read neighbouring LDS words: they only reach output rows that are never stored.
+    // k-rows past nloc (last chunk) are zeroed, as their X rows are not copied.
 #pragma unroll
     for (int s4 = 0; s4 < kCellKC / 4; ++s4) {
       const int kl = s4 * 4 + kr;
       const bool kok = kc * kCellKC + kl < nloc;
-      C b[kCellNT];
+      C b[kCellNT], a[CMT];
 #pragma unroll
       for (int j = 0; j < kCellNT; ++j) b[j] = (C)Xl[kl * kCellLDX + (nh * kCellNT + j) * 16 + cl];
 #pragma unroll
       for (int i = 0; i < CMT; ++i) {
-        const int t = mg + 4 * i;
-        if (t < nmt) {
-          const int m = t * 16 + cl;
-          const C a = (kok && m < nloc) ? widen<T, C>(Al[kl * nloc + m]) : (C)0;
-#pragma unroll
-          for (int j = 0; j < kCellNT; ++j) acc[i][j] = Mfma<T>::mma(a, b[j], acc[i][j]);
-        }
+        const int t = min(mg + 4 * i, nmt - 1);
+        const C v = widen<T, C>(Al[kl * nloc + t * 16 + cl]);
+        a[i] = kok ? v : (C)0;
       }
+#pragma unroll
+      for (int i = 0; i < CMT; ++i)
+        if (mg + 4 * i < nmt) {
+#pragma unroll
+          for (int j = 0; j < kCellNT; ++j) acc[i][j] = Mfma<T>::mma(a[i], b[j], acc[i][j]);
+        }
     }
   }
   // D layout of the 16x16 MFMA (differs between the f64 and f32 forms)
