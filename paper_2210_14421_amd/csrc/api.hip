@@ -71,6 +71,8 @@ struct efe_ctx {
   double *pcg_S = nullptr;      // PCG scalars
   int *pcg_done = nullptr;
   int *lz_anyf = nullptr;       // some column of the running Lanczos still active
+  int *lz_pin = nullptr;        // pinned copies of lz_anyf after the iterations in flight (2)
+  hipEvent_t lz_ev[2] = {nullptr, nullptr};
   int *lz_kmaxu = nullptr;      // largest k of the finished Lanczos
   int *flags = nullptr;         // [0] predictor, [1] corrector Lanczos not converged; [2], [3] PCG not converged
   double *mu_dev = nullptr;     // dipole of the step
@@ -644,37 +646,53 @@ efe_status run_lanczos(efe_ctx *ctx, double tau, const double *X, double *out, i
   efe::k::reduce_partials(ctx->red, nb, ncolr, ctx->small, s);
   efe::k::lz_init(ctx->small, ncol, ctx->beta0, ctx->sig, ctx->active, ctx->kused, ctx->pro, s);
   tstop(ctx, 2);
-  std::vector<int> act(ncol);
-  HIP_TRY(hipMemcpyAsync(act.data(), ctx->active, ncol * sizeof(int), hipMemcpyDeviceToHost, s));
+  efe::k::lz_any(ctx->active, ncol, ctx->lz_anyf, s);
   std::vector<double> b0h(ncol);
   HIP_TRY(hipMemcpyAsync(b0h.data(), ctx->beta0, ncol * sizeof(double), hipMemcpyDeviceToHost, s));
   EFE_TRY(sync(ctx, "lanczos start"));
-  bool any = false;
-  for (int c = 0; c < ncol; ++c) any |= act[c] != 0;
   for (int c = 0; c < ncol; ++c)
     if (!std::isfinite(b0h[c])) { ctx->err = "non-finite input orbital"; return EFE_ERR_NONFINITE; }
-  // Iteration j: slot j = A slot_{j-1}; classical Gram-Schmidt of slot j
-  // against slots 0..j-1 (the pass contains the three-term recurrence: its
-  // slot_{j-1} coefficient gives alpha_j); a second pass for the columns where
-  // the first one cancelled most of the vector; beta_j; tridiagonal
-  // exponential and stopping test.
-  int j = 0;
+  if (!ctx->lz_pin) HIP_TRY(hipHostMalloc((void **)&ctx->lz_pin, 4 * sizeof(int)));
+  for (hipEvent_t &e : ctx->lz_ev)
+    if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  // Iteration j: slot j = A slot_{j-1}; Gram-Schmidt of slot j (local or full
+  // pass, then a pass against all slots where needed), beta_j, tridiagonal
+  // exponential and stopping test.  The host keeps one iteration in flight ahead
+  // of the one whose stopping flag it reads: iteration j + 1 is enqueued before the
+  // flag after iteration j is waited for, and its kernels return at once when no
+  // column was left (device flag lz_anyf), so the stream does not idle between
+  // iterations.  The flag copies go to a pinned pair of slots, one per iteration
+  // in flight.
+  int enq = 0;
+  auto enqueue = [&]() -> efe_status {
+    ++enq;
+    EFE_TRY(lz_iteration(ctx, tau, X, ncol, enq, kf, tol, ctx->lz_anyf));
+    HIP_TRY(hipMemcpyAsync(ctx->lz_pin + (enq & 1), ctx->lz_anyf, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(ctx->lz_ev[enq & 1], s));
+    return EFE_OK;
+  };
+  bool any = false;
+  for (int c = 0; c < ncol; ++c) any |= b0h[c] > 0.0;
+  if (any) EFE_TRY(enqueue());
+  int last = 0;
   while (any) {
-    ++j;
-    EFE_TRY(lz_iteration(ctx, tau, X, ncol, j, kf, tol, nullptr));
-    HIP_TRY(hipMemcpyAsync(act.data(), ctx->active, ncol * sizeof(int), hipMemcpyDeviceToHost, s));
-    EFE_TRY(sync(ctx, "lanczos iteration"));
-    any = false;
-    for (int c = 0; c < ncol; ++c) any |= act[c] != 0;
-    if (!any) break;
-    if (j == kmax) {
+    ++last;
+    if (enq < kmax) EFE_TRY(enqueue());
+    HIP_TRY(hipEventSynchronize(ctx->lz_ev[last & 1]));
+    any = ctx->lz_pin[last & 1] != 0;
+    if (any && last == kmax) {
+      (void)hipStreamSynchronize(s);
       ctx->err = "Lanczos did not reach the tolerance within kmax vectors";
       return EFE_ERR_NOCONV;
     }
   }
+  // the iteration enqueued after the last active one returned at once: it is no Hbar X
+  ctx->timer.n_hx -= enq - last;
+  const int j = enq;   // slots that may hold vectors; the combination stops at each column's k
   tstart(ctx, 2);
   efe::k::lz_comb_coef(ctx->ubuf, ctx->sig, ctx->beta0, ctx->kused, kmax, j, ncol, ctx->coef, s);
-  efe::k::lz_combine(X, Qb, bs, j, ctx->coef, out, nrows, ncol, s);
+  efe::k::lz_kmax(ctx->kused, ncol, ctx->lz_kmaxu, s);
+  efe::k::lz_combine(X, Qb, bs, j, ctx->coef, out, nrows, ncol, s, ctx->lz_kmaxu);
   tstop(ctx, 2);
   std::vector<int> ku(ncol);
   std::vector<double> ev(ncol);
@@ -1311,6 +1329,9 @@ efe_status efe_free(efe_ctx *ctx) {
   if (ctx->ev_in) (void)hipEventDestroy(ctx->ev_in);
   if (ctx->ev_out) (void)hipEventDestroy(ctx->ev_out);
   if (ctx->hpin) (void)hipHostFree(ctx->hpin);
+  if (ctx->lz_pin) (void)hipHostFree(ctx->lz_pin);
+  for (hipEvent_t e : ctx->lz_ev)
+    if (e) (void)hipEventDestroy(e);
   for (void *p : ctx->allocs) hipFree(p);
   delete ctx;
   return EFE_OK;
