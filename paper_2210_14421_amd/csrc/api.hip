@@ -722,7 +722,8 @@ __global__ void k_lz_finish(const int *__restrict__ kused, const double *__restr
   if (c == 0) *flag = *any;
   if (c >= ncol) return;
   kstat[c] = kused[c];
-  estat[c] = beta0[c] > 0.0 ? errv[c] : 0.0;
+  const double b = beta0[c];   // NaN for a non-finite input column: passed on to the host check
+  estat[c] = b > 0.0 ? errv[c] : (b == 0.0 ? 0.0 : b);
 }
 
 __global__ void k_pcg_finish(const double *__restrict__ S, const int *__restrict__ done, double *__restrict__ iters,
@@ -878,6 +879,11 @@ efe_status finish_stats(efe_ctx *ctx, efe_step_stats *stats) {
     ctx->err = "Poisson PCG did not reach the tolerance in the device iteration budget";
     return EFE_ERR_NOCONV;
   }
+  for (int c = 0; c < 2 * no; ++c)
+    if (!std::isfinite(es[c])) {
+      ctx->err = "non-finite orbital entering an exponential of the step";
+      return EFE_ERR_NONFINITE;
+    }
   if (!std::isfinite(h[0]) || !std::isfinite(h[1]) || !std::isfinite(h[2])) {
     ctx->err = "non-finite dipole after the step";
     return EFE_ERR_NONFINITE;

@@ -237,7 +237,8 @@ __global__ void k_lz_init(const double2 *__restrict__ h0, int ncol, double *__re
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncol) return;
   const double n2 = h0[c].x;
-  const double b = sqrt(n2 > 0.0 ? n2 : 0.0);
+  // a NaN norm stays NaN (the host reports a non-finite input), only a zero column is inactive
+  const double b = n2 > 0.0 || n2 != n2 ? sqrt(n2) : 0.0;
   beta0[c] = b;
   sig[c] = b > 0.0 ? 1.0 / b : 0.0;
   active[c] = b > 0.0 ? 1 : 0;
