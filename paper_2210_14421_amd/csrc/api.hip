@@ -333,6 +333,13 @@ efe_status build_device(efe_ctx *ctx) {
     EFE_TRY(upload(ctx, &d.K1[dd], pl.K1[dd]));
     EFE_TRY(upload(ctx, &d.M1[dd], pl.M1[dd]));
     EFE_TRY(upload(ctx, &d.fdmV[dd], pl.fdmV[dd]));
+    {
+      const int64_t m = pl.nn[dd] - 2;
+      std::vector<double> vt((size_t)(m * m));
+      for (int64_t a = 0; a < m; ++a)
+        for (int64_t i = 0; i < m; ++i) vt[(size_t)(i * m + a)] = pl.fdmV[dd][(size_t)(a * m + i)];
+      EFE_TRY(upload(ctx, &d.fdmVT[dd], vt));
+    }
     EFE_TRY(upload(ctx, &d.fdmL[dd], pl.fdmL[dd]));
   }
   EFE_TRY(upload(ctx, &d.gbnd, pl.gbnd));

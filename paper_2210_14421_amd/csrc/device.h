@@ -81,6 +81,7 @@ struct DevData {
   // Poisson
   double *K1[3] = {nullptr, nullptr, nullptr}, *M1[3] = {nullptr, nullptr, nullptr};
   double *fdmV[3] = {nullptr, nullptr, nullptr}, *fdmL[3] = {nullptr, nullptr, nullptr};
+  double *fdmVT[3] = {nullptr, nullptr, nullptr};   // transposes of fdmV (rows of the back transform)
   double *gbnd = nullptr, *lift = nullptr;
 };
 

@@ -1133,6 +1133,65 @@ __global__ void k_fdm_axis(const DevData d, const double *__restrict__ V, int ax
   out[i] = s;
 }
 
+// The same transform on 16 interior lines per workgroup (lines along `axis` at 16 consecutive
+// values of the fastest other coordinate u and one value of the slowest v): the lines pass
+// through LDS, each thread forms one output o of all 16 lines from the coalesced row W[k][.]
+// (W = V for the forward transform, V^T for the back one), and the results leave through LDS.
+// For m <= kFdmMaxM; only interior nodes are written.
+constexpr int kFdmLines = 16, kFdmMaxM = 256;
+
+__global__ void __launch_bounds__(kFdmMaxM)
+k_fdm_lines(const DevData d, const double *__restrict__ W, int axis, const double *__restrict__ in,
+            double *__restrict__ out, const int *__restrict__ skip) {
+  if (skip && *skip) return;
+  __shared__ double tile[kFdmLines][kFdmMaxM + 1];
+  const Geom &g = d.g;
+  const int m = (int)g.nn[axis] - 2;
+  const int au = axis == 0 ? 1 : 0, av = axis == 2 ? 1 : 2;      // the other axes, u fastest
+  const int nu = (int)g.nn[au] - 2;
+  const int u0 = 1 + kFdmLines * blockIdx.x, v = 1 + blockIdx.y;
+  const int64_t st[3] = {1, g.nn[0], g.nn[0] * g.nn[1]};
+  const int64_t base = u0 * st[au] + (int64_t)v * st[av];
+  const int tid = threadIdx.x;
+  // consecutive threads take consecutive addresses: along the line for axis 0, across lines otherwise
+  auto at = [&](int idx, int &ln, int &kk) {
+    if (axis == 0) { ln = idx / m; kk = idx - ln * m; }
+    else { ln = idx % kFdmLines; kk = idx / kFdmLines; }
+  };
+  for (int idx = tid; idx < kFdmLines * m; idx += kFdmMaxM) {
+    int ln, kk;
+    at(idx, ln, kk);
+    tile[ln][kk] = u0 + ln <= nu ? in[base + ln * st[au] + (int64_t)(kk + 1) * st[axis]] : 0.0;
+  }
+  __syncthreads();
+  double acc[kFdmLines];
+#pragma unroll
+  for (int l = 0; l < kFdmLines; ++l) acc[l] = 0.0;
+  if (tid < m) {
+    for (int k = 0; k < m; ++k) {
+      const double w = W[(int64_t)k * m + tid];
+#pragma unroll
+      for (int l = 0; l < kFdmLines; ++l) acc[l] += w * tile[l][k];
+    }
+  }
+  __syncthreads();
+  if (tid < m)
+#pragma unroll
+    for (int l = 0; l < kFdmLines; ++l) tile[l][tid] = acc[l];
+  __syncthreads();
+  for (int idx = tid; idx < kFdmLines * m; idx += kFdmMaxM) {
+    int ln, kk;
+    at(idx, ln, kk);
+    if (u0 + ln <= nu) out[base + ln * st[au] + (int64_t)(kk + 1) * st[axis]] = tile[ln][kk];
+  }
+}
+
+__global__ void k_fdm_zero_boundary(const DevData d, double *__restrict__ t, const int *__restrict__ skip) {
+  if (skip && *skip) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < d.g.n_nodes && d.Dm12[i] == 0.0) t[i] = 0.0;
+}
+
 __global__ void k_fdm_scale(const DevData d, double *__restrict__ t, const int *__restrict__ skip) {
   if (skip && *skip) return;
   const Geom &g = d.g;
@@ -1525,6 +1584,23 @@ void stiffness_apply(const DevData &d, const double *x, double *y, double *t1, d
 // z = K_II^-1 r on interior nodes by fast diagonalisation
 void fdm_apply(const DevData &d, const double *r, double *z, double *t1, double *t2, hipStream_t s, const int *skip) {
   const unsigned nb = nblocks(d.g.n_nodes, 256);
+  bool lines = d.fdmVT[0] && d.fdmVT[1] && d.fdmVT[2];
+  for (int a = 0; a < 3; ++a) lines = lines && d.g.nn[a] - 2 <= kFdmMaxM && d.g.nn[a] >= 3;
+  if (lines) {
+    auto grid = [&](int axis) {
+      const int au = axis == 0 ? 1 : 0, av = axis == 2 ? 1 : 2;
+      return dim3((unsigned)((d.g.nn[au] - 2 + kFdmLines - 1) / kFdmLines), (unsigned)(d.g.nn[av] - 2));
+    };
+    hipLaunchKernelGGL(k_fdm_lines, grid(0), dim3(kFdmMaxM), 0, s, d, d.fdmV[0], 0, r, t1, skip);
+    hipLaunchKernelGGL(k_fdm_lines, grid(1), dim3(kFdmMaxM), 0, s, d, d.fdmV[1], 1, t1, t2, skip);
+    hipLaunchKernelGGL(k_fdm_lines, grid(2), dim3(kFdmMaxM), 0, s, d, d.fdmV[2], 2, t2, t1, skip);
+    hipLaunchKernelGGL(k_fdm_scale, dim3(nb), dim3(256), 0, s, d, t1, skip);
+    hipLaunchKernelGGL(k_fdm_lines, grid(2), dim3(kFdmMaxM), 0, s, d, d.fdmVT[2], 2, t1, t2, skip);
+    hipLaunchKernelGGL(k_fdm_lines, grid(1), dim3(kFdmMaxM), 0, s, d, d.fdmVT[1], 1, t2, t1, skip);
+    hipLaunchKernelGGL(k_fdm_lines, grid(0), dim3(kFdmMaxM), 0, s, d, d.fdmVT[0], 0, t1, z, skip);
+    hipLaunchKernelGGL(k_fdm_zero_boundary, dim3(nb), dim3(256), 0, s, d, z, skip);
+    return;
+  }
   hipLaunchKernelGGL(k_fdm_axis, dim3(nb), dim3(256), 0, s, d, d.fdmV[0], 0, 0, r, t1, skip);
   hipLaunchKernelGGL(k_fdm_axis, dim3(nb), dim3(256), 0, s, d, d.fdmV[1], 1, 0, t1, t2, skip);
   hipLaunchKernelGGL(k_fdm_axis, dim3(nb), dim3(256), 0, s, d, d.fdmV[2], 2, 0, t2, t1, skip);
