@@ -1463,7 +1463,8 @@ efe_status absorption_spectrum(const double *mu, const int32_t *dirs, int32_t nd
                                const efe_pulse *pulse, double tau, const double *omega, int64_t nw, double *S,
                                double *alpha, void *hip_stream) {
   if (!mu || !dirs || !pulse || !omega || !S || ndir < 1 || ndir > 3 || nt < 1 || nw < 1 || nw > (1LL << 31) ||
-      !(dt > 0.0) || !(tau > 0.0) || (pulse->kind != 0 && pulse->kind != 1) || !std::isfinite(pulse->kappa) ||
+      !(dt > 0.0) || !std::isfinite(dt) || !(tau > 0.0) || (pulse->kind != 0 && pulse->kind != 1) ||
+      !std::isfinite(pulse->kappa) ||
       pulse->kappa == 0.0 || (pulse->kind == 1 && !(pulse->s > 0.0)))
     return EFE_ERR_ARG;
   for (int r = 0; r < ndir; ++r)
