@@ -227,6 +227,7 @@ k_coupling_mfma(const DevData d, const double *__restrict__ vq, double *__restri
                 double *__restrict__ hee_part) {
   __shared__ double bt[16 * 8];                       // n x P (n <= 16, P <= 8)
   __shared__ double wq[kCpChunk];
+  __shared__ int qoff[kCpChunk];                      // bt row offsets of the point's (i, j, k), packed
   __shared__ double nec[48][kCpChunk + 1];
   const Geom &g = d.g;
   const int slot = blockIdx.x;
@@ -266,11 +267,14 @@ k_coupling_mfma(const DevData d, const double *__restrict__ vq, double *__restri
     for (int t = threadIdx.x; t < kCpChunk; t += blockDim.x) {
       const int q = qc + t;
       double v = 0.0;
+      int off = 0;
       if (q < n3) {
         const int i = q % n, j = (q / n) % n, k = q / (n * n);
         v = jac * tab[tow + i] * tab[tow + j] * tab[tow + k] * vq[q0 + q];
+        off = (i * P) | ((j * P) << 8) | ((k * P) << 16);
       }
       wq[t] = v;
+      qoff[t] = off;
     }
     for (int t = threadIdx.x; t < 48 * kCpChunk; t += blockDim.x) {
       const int kk = t / kCpChunk, qq = t % kCpChunk;
@@ -281,7 +285,8 @@ k_coupling_mfma(const DevData d, const double *__restrict__ vq, double *__restri
     for (int s4 = 0; s4 < kCpChunk / 4; ++s4) {
       const int qq = s4 * 4 + kr, q = qc + qq;
       const bool qok = q < n3;
-      const int qi = q % n, qj = (q / n) % n, qk = q / (n * n);
+      const int qo = qoff[qq];
+      const int oi = qo & 255, oj = (qo >> 8) & 255, ok = qo >> 16;
       const double w = wq[qq];
       double bv[3];
 #pragma unroll
@@ -289,7 +294,7 @@ k_coupling_mfma(const DevData d, const double *__restrict__ vq, double *__restri
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         if (wave + 4 * i >= nmt) continue;
-        const double a = (qok && lok[i]) ? bt[qi * P + la[i]] * bt[qj * P + lb[i]] * bt[qk * P + lc[i]] : 0.0;
+        const double a = (qok && lok[i]) ? bt[oi + la[i]] * bt[oj + lb[i]] * bt[ok + lc[i]] : 0.0;
 #pragma unroll
         for (int j = 0; j < 3; ++j)
           if (j < nnt) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[j], acc[i][j], 0, 0, 0);
