@@ -5,9 +5,9 @@
   The section gives the three-term recurrence; in floating point the vectors
   lose orthogonality once Ritz values converge, so two ways of keeping them
   orthogonal are provided (both reduce to the recurrence in exact arithmetic):
-  - "partial" (default): each new vector is orthogonalised against the two
-    latest ones (one classical Gram-Schmidt pass, which also yields alpha_j and
-    the recurrence's beta_{j-1} term); Simon's omega recurrence (Simon 1984,
+  - "partial" (default): the three-term recurrence itself, with alpha_j the
+    q_j coefficient of A q_j (computed) and beta_{j-1} the previous norm (known);
+    Simon's omega recurrence (Simon 1984,
     "The Lanczos algorithm with partial reorthogonalization") estimates
     omega_{j+1,k} ~ q_{j+1}^H q_k from alpha, beta alone, and when an estimate
     exceeds sqrt(eps) the vector, and the next one, get a Gram-Schmidt pass
@@ -112,12 +112,13 @@ def lanczos_expm_column(Aop, tau, v, tol, kmax, k_force: Optional[int] = None, r
                 w = w - Qm @ h
             b = float(np.linalg.norm(w))
         else:
-            # local pass: one CGS step against q_{j-1}, q_j (their coefficients from the same w)
+            # three-term step: the q_j coefficient from w, the q_{j-1} one the known beta_{j-1}
             w0 = float(np.linalg.norm(w))
-            Ql = np.stack(Q[-2:], axis=1)
-            h = Ql.conj().T @ w
-            w = w - Ql @ h
-            a = float(np.real(h[-1]))
+            h = np.vdot(q, w)
+            w = w - h * q
+            if j > 1:
+                w = w - beta[-1] * Q[-2]
+            a = float(np.real(h))
             alpha.append(a)
             b = float(np.linalg.norm(w))
             anorm = max(anorm, abs(a) + b + (beta[-1] if beta else 0.0))

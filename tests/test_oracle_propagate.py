@@ -135,10 +135,9 @@ def test_omega_estimates_bound_the_loss():
     checked = 0
     for j in range(1, 40):
         w = A @ Q[-1]
-        Ql = np.stack(Q[-2:], axis=1)
-        h = Ql.conj().T @ w
-        w = w - Ql @ h
-        alpha.append(float(np.real(h[-1])))
+        h = np.vdot(Q[-1], w)
+        w = w - h * Q[-1] - (beta[-1] * Q[-2] if j > 1 else 0.0)
+        alpha.append(float(np.real(h)))
         b = float(np.linalg.norm(w))
         anorm = max(anorm, abs(alpha[-1]) + b + (beta[-1] if beta else 0.0))
         om = omega_next(alpha, beta, b, om_j, om_jm1, anorm)
