@@ -594,13 +594,23 @@ efe_status lz_iteration(efe_ctx *ctx, double tau, const double *X, int ncol, int
   double *b_j = ctx->beta + (int64_t)(j - 1) * ncol;
   // first pass: all previous slots (full) or the two latest (partial); the
   // second pass against all slots runs for the columns that need it
+  // first pass: all previous slots (full), or the three-term step (partial: the q_j coefficient
+  // from the dot with slot j - 1, the q_{j-1} one from the known beta_{j-1})
   const bool partial = ctx->opt.reorth == EFE_REORTH_PARTIAL;
   const int first = partial ? std::max(0, j - 2) : 0, nq = j - first;
   const double *q0f = first == 0 ? X : Qb + (int64_t)(first - 1) * bs;
   const double *qbf = Qb + (int64_t)first * bs;
-  int nb = efe::k::lz_dots(q0f, qbf, bs, nq, w, nrows, ncol, ctx->active, any, 1, ctx->red, s);
-  efe::k::reduce_partials(ctx->red, nb, (nq + 1) * ncolr, ctx->h1, s);
-  efe::k::lz_coef1(ctx->h1, ctx->sig, j, first, ncol, ctx->active, a_j, ctx->coef, ctx->gsc, ctx->msc, s);
+  int nb;
+  if (partial) {
+    const double *q0d = j == 1 ? X : Qb + (int64_t)(j - 2) * bs;   // slot j - 1
+    nb = efe::k::lz_dots(q0d, Qb + (int64_t)(j - 1) * bs, bs, 1, w, nrows, ncol, ctx->active, any, 1, ctx->red, s);
+    efe::k::reduce_partials(ctx->red, nb, 2 * ncolr, ctx->h1, s);
+    efe::k::lz_coef3(ctx->h1, ctx->sig, ctx->beta, j, ncol, ctx->active, a_j, ctx->coef, ctx->gsc, ctx->msc, s);
+  } else {
+    nb = efe::k::lz_dots(q0f, qbf, bs, nq, w, nrows, ncol, ctx->active, any, 1, ctx->red, s);
+    efe::k::reduce_partials(ctx->red, nb, (nq + 1) * ncolr, ctx->h1, s);
+    efe::k::lz_coef1(ctx->h1, ctx->sig, j, first, ncol, ctx->active, a_j, ctx->coef, ctx->gsc, ctx->msc, s);
+  }
   nb = efe::k::lz_update(q0f, qbf, bs, nq, ctx->coef, ctx->gsc, w, nrows, ncol, ctx->active, any, ctx->red, s, 1);
   efe::k::reduce_partials(ctx->red, nb, ncolr, ctx->nrm1, s);
   if (partial)

@@ -180,6 +180,9 @@ void lz_init(const double *h0, int ncol, double *beta0, double *sig, int *active
 // first: the first slot of the dot pass the coefficients come from (0: all slots)
 void lz_coef1(const double *h, const double *sig, int j, int first, int ncol, const int *active, double *alpha_j,
               double *coef, double *gsc, double *msc, hipStream_t s);
+// three-term step of iteration j from the dot with slot j - 1 and the known beta_{j-1}
+void lz_coef3(const double *h, const double *sig, const double *beta, int j, int ncol, const int *active,
+              double *alpha_j, double *coef, double *gsc, double *msc, hipStream_t s);
 // partial reorthogonalisation decision after the local pass of iteration j (sets need, any)
 void lz_pro(const double *nrm1, const double *msc, const double *alpha, const double *beta, int j, int ncol,
             const int *active, const ProState &pro, int *need, int *any, hipStream_t s);

@@ -275,6 +275,34 @@ __global__ void k_lz_coef1(const double2 *__restrict__ h, const double *__restri
   msc[c] = g > 0.0 ? sj / g : 0.0;
 }
 
+// Three-term step of iteration j (partial scheme): h[0][c] = <slot_{j-1}, slot_j>, h[1][c] =
+// ||slot_j||^2.  alpha_j = sig_{j-1}^2 Re h[0]; the update (slots j-2, j-1) is
+// slot_j <- g (slot_j - beta_{j-1} sig_{j-2} / sig_{j-1} slot_{j-2} - sig_{j-1}^2 h[0] slot_{j-1}),
+// g = 1 / ||slot_j||: the recurrence's beta_{j-1} q_{j-1} written in the stored slots.
+__global__ void k_lz_coef3(const double2 *__restrict__ h, const double *__restrict__ sig,
+                           const double *__restrict__ beta, int j, int ncol, const int *__restrict__ active,
+                           double *__restrict__ alpha_j, double2 *__restrict__ coef, double *__restrict__ gsc,
+                           double *__restrict__ msc) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncol || !active[c]) return;
+  const double w2 = h[ncol + c].x;
+  const double g = w2 > 0.0 ? 1.0 / sqrt(w2) : 0.0;
+  const double sj = sig[(int64_t)(j - 1) * ncol + c];
+  const double2 v = h[c];
+  alpha_j[c] = sj * sj * v.x;
+  const double f = g * sj * sj;
+  if (j >= 2) {
+    const double sp = sig[(int64_t)(j - 2) * ncol + c];
+    const double bp = beta[(int64_t)(j - 2) * ncol + c];
+    coef[c] = make_double2(sj > 0.0 ? g * bp * sp / sj : 0.0, 0.0);
+    coef[(int64_t)ncol + c] = make_double2(f * v.x, f * v.y);
+  } else {
+    coef[c] = make_double2(f * v.x, f * v.y);
+  }
+  gsc[c] = g;
+  msc[c] = g > 0.0 ? sj / g : 0.0;
+}
+
 // Partial reorthogonalisation (Simon 1984): after the local pass of iteration j,
 // beta_j ~ msc ||slot_j|| and the omega recurrence estimates omega_{j+1,k} ~
 // q_{j+1}^H q_k from alpha_1..j, beta_1..j-1 and the rows omega_j, omega_{j-1}:
@@ -513,6 +541,12 @@ void lz_init(const double *h0, int ncol, double *beta0, double *sig, int *active
 void lz_coef1(const double *h, const double *sig, int j, int first, int ncol, const int *active, double *alpha_j,
               double *coef, double *gsc, double *msc, hipStream_t s) {
   hipLaunchKernelGGL(k_lz_coef1, dim3((ncol + 63) / 64), dim3(64), 0, s, (const double2 *)h, sig, j, first, ncol,
+                     active, alpha_j, (double2 *)coef, gsc, msc);
+}
+
+void lz_coef3(const double *h, const double *sig, const double *beta, int j, int ncol, const int *active,
+              double *alpha_j, double *coef, double *gsc, double *msc, hipStream_t s) {
+  hipLaunchKernelGGL(k_lz_coef3, dim3((ncol + 63) / 64), dim3(64), 0, s, (const double2 *)h, sig, beta, j, ncol,
                      active, alpha_j, (double2 *)coef, gsc, msc);
 }
 
