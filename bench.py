@@ -110,12 +110,15 @@ def run_apply_mode(spec, dtype, n_apply):
 
 
 def roofline(spec, res, dtype):
-    """Cell-product kernel against the MFMA peak of its dtype, per launch.
+    """Cell-product kernel against the lower of its roofs, per launch.
 
     One Hbar X is one launch per cell colour (parity class); a launch multiplies
     the 216 x 216 blocks of its cells into the 88 real columns of the orbital
-    block: 2 * nloc^2 * ncol flops per cell.  The launch duration is the
-    library's HIP-event time of all cell launches divided by their number."""
+    block: 2 * nloc^2 * ncol flops per cell.  The roof is the MFMA peak of the
+    block dtype or the arithmetic intensity times the HBM bandwidth, whichever
+    is lower; the achieved figure is flops or algorithmic bytes per launch over
+    the launch duration, the library's HIP-event time of all cell launches
+    divided by their number."""
     P = spec.degree + 1
     nloc = P ** 3
     ncells = spec.ncell[0] * spec.ncell[1] * spec.ncell[2]
@@ -127,14 +130,31 @@ def roofline(spec, res, dtype):
     flop_per_launch = flop_per_hx / ncolour
     n_hx = res["stage"]["n_hx"]
     launch_s = res["stage"]["cell_hx"] * 1e-3 / (n_hx * ncolour)
-    achieved = flop_per_launch / launch_s / 1e12
     tr = traffic_summary(dtype)
-    peak = PEAK_TFLOPS["f32" if dtype == "bf16" else dtype]    # BF16 blocks feed the FP32 MFMA
-    return {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+    # algorithmic bytes of a launch: its cell blocks, the gathered orbital rows, the output rows
+    # written, and the output rows read where the colour is not the first to reach the node
+    # (node-in-cell incidences beyond the first: prod_d (nn_d + nc_d - 1) - n_nodes per Hbar X)
+    esz = {"f64": 8, "f32": 4, "bf16": 2}[dtype]
+    nn = [n * spec.degree + 1 for n in spec.ncell]
+    incid = 1
+    for a in range(3):
+        incid *= nn[a] + spec.ncell[a] - 1
+    yreads = (incid - nn[0] * nn[1] * nn[2]) / ncolour
+    row = ncolr * 8
+    cells_l = ncells / ncolour
+    bytes_launch = cells_l * nloc * nloc * esz + 2 * cells_l * nloc * row + yreads * row
+    ai = flop_per_launch / bytes_launch
+    mfma_peak = PEAK_TFLOPS["f32" if dtype == "bf16" else dtype]    # BF16 blocks feed the FP32 MFMA
+    if mfma_peak <= ai * HBM_GBS / 1e3:        # the MFMA roof is the lower one
+        bound, achieved, peak, unit = "mfma", flop_per_launch / launch_s / 1e12, mfma_peak, "TFLOP/s"
+    else:
+        bound, achieved, peak, unit = "hbm", bytes_launch / launch_s / 1e9, HBM_GBS, "GB/s"
+    return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
             "frac": achieved / peak, "traffic": None if tr is None else tr["total"],
-            "kernel": "k_cell_apply", "flop_per_launch": flop_per_launch, "launch_avg_us": launch_s * 1e6,
-            "launches_per_hx": ncolour, "hx_per_step": n_hx / max(1, len(res["k"])),
-            "traffic_detail": tr}
+            "kernel": "k_cell_apply", "flop_per_launch": flop_per_launch, "bytes_per_launch": bytes_launch,
+            "arithmetic_intensity": ai, "tflops": flop_per_launch / launch_s / 1e12,
+            "launch_avg_us": launch_s * 1e6, "launches_per_hx": ncolour,
+            "hx_per_step": n_hx / max(1, len(res["k"])), "traffic_detail": tr}
 
 
 def cpu_baseline(spec, hx_per_step):
