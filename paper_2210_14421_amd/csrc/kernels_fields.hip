@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include "common.cuh"
+#include "plan.h"
 
 namespace efe {
 
@@ -30,7 +31,9 @@ template <> __device__ __forceinline__ uint16_t cast_out<uint16_t>(double v) { r
 // launch share the Gauss rule size n).  The potential part
 //   V[(a,b,c),(a',b',c')] = sum_ijk W v(i,j,k) B_i(a)B_i(a') B_j(b)B_j(b') B_k(c)B_k(c')
 // depends on the unordered pairs {a,a'}, {b,b'}, {c,c'} only, and is built by
-// three contractions over the pair tables G1[i][pair] = B_i(a) B_i(a').
+// three contractions over the pair tables G1[i][pair] = B_i(a) B_i(a'): over i
+// once for all (k, j), then per z-pair over k and over j, so that no n x NP x NP
+// intermediate is held (LDS within 160 KB up to degree 6 with 14 Gauss points).
 // mode 0: Hamiltonian (kinetic + v_static + v_H + v_xc - E x_dir); mode 1..3:
 // position operator along x/y/z (v = x_d, no kinetic term).
 // ---------------------------------------------------------------------------
@@ -51,12 +54,13 @@ k_rebuild(const DevData d, const int *__restrict__ cell_list, int n, int mode, c
   double *Mel = Kel + 3 * P2;            // 3*P2
   double *dm = Mel + 3 * P2;             // nloc
   double *wv = dm + nloc;                // n3
-  double *U = wv + n3;                   // n*n*NP
-  double *W2 = U + n * n * NP;           // n*NP*NP
-  double *Vc = W2 + n * NP * NP;         // NP*NP
+  // U: n*n*NP, or the Hartree interpolation's u0, t1, t2 (nloc + P2*n + n*n*P) if larger
+  const int usz = n * n * NP > nloc + P2 * n + n * n * P ? n * n * NP : nloc + P2 * n + n * n * P;
+  double *U = wv + n3;
+  double *Z = U + usz;                   // n*NP
+  double *Vc = Z + n * NP;               // NP*NP
   int *pair = (int *)(Vc + NP * NP);     // P2 ints
-  // scratch for the Hartree interpolation aliases U / W2
-  double *u0 = U, *t1 = U + nloc, *t2 = W2;
+  double *u0 = U, *t1 = U + nloc, *t2 = t1 + P2 * n;
 
   const int64_t cell = cell_list[blockIdx.x];
   int e[3];
@@ -116,21 +120,23 @@ k_rebuild(const DevData d, const int *__restrict__ cell_list, int n, int mode, c
     U[t] = s;
   }
   __syncthreads();
-  // W2[k][pb][pa] = sum_j G1[j][pb] U[k][j][pa]
-  for (int t = threadIdx.x; t < n * NP * NP; t += blockDim.x) {
-    int pa = t % NP, pb = (t / NP) % NP, k = t / (NP * NP);
-    double s = 0.0;
-    for (int j = 0; j < n; ++j) s += G1[j * NP + pb] * U[(k * n + j) * NP + pa];
-    W2[t] = s;
-  }
-  __syncthreads();
   T *out = cells + (int64_t)d.cell_slot[cell] * d.g.cstride;   // colour-major storage
   for (int c = 0; c < P; ++c)
     for (int c2 = c; c2 < P; ++c2) {
       const int pc = pair[c * P + c2];
-      for (int t = threadIdx.x; t < NP * NP; t += blockDim.x) {
+      // Z[j][pa] = sum_k G1[k][pc] U[k][j][pa]
+      for (int t = threadIdx.x; t < n * NP; t += blockDim.x) {
+        const int pa = t % NP, j = t / NP;
         double s = 0.0;
-        for (int k = 0; k < n; ++k) s += G1[k * NP + pc] * W2[k * NP * NP + t];
+        for (int k = 0; k < n; ++k) s += G1[k * NP + pc] * U[(k * n + j) * NP + pa];
+        Z[t] = s;
+      }
+      __syncthreads();
+      // Vc[pb][pa] = sum_j G1[j][pb] Z[j][pa]
+      for (int t = threadIdx.x; t < NP * NP; t += blockDim.x) {
+        const int pa = t % NP, pb = t / NP;
+        double s = 0.0;
+        for (int j = 0; j < n; ++j) s += G1[j * NP + pb] * Z[j * NP + pa];
         Vc[t] = s;
       }
       __syncthreads();
@@ -216,12 +222,14 @@ k_coupling_partials(const DevData d, const double *__restrict__ vq, double *__re
 // T-cell, the points streamed through LDS in chunks of 64:
 //   part[l][nu] = sum_q B_l(q) F(q, nu),   F(q, nu) = W_q v(q) N^E_nu(q)
 //     (A operand B_l(q) = b(i_q, a_l) b(j_q, b_l) b(k_q, c_l) from the 1-D table;
-//      wave w takes the M tiles w + 4 i of the nloc node rows, all N tiles);
+//      wave w takes the M tiles w + 4 i, i < MT, of the nloc node rows, all N
+//      tiles: MT = 4 covers nloc <= 256, MT = 6 nloc <= 384);
 //   hee[mu][nu] = sum_q N^E_mu(q) F(q, nu)  (the 3 x 3 tiles of 48 functions
 //      dealt round-robin to the waves).
 constexpr int kCpChunk = 64;
 typedef double v4d_t __attribute__((ext_vector_type(4)));
 
+template <int MT>
 __global__ void __launch_bounds__(256)
 k_coupling_mfma(const DevData d, const double *__restrict__ vq, double *__restrict__ part,
                 double *__restrict__ hee_part) {
@@ -245,19 +253,19 @@ k_coupling_mfma(const DevData d, const double *__restrict__ vq, double *__restri
   const int kr = lane >> 4, cl = lane & 15;
   const int nmt = (nloc + 15) / 16, nnt = (nnu + 15) / 16;
   // node index decomposition of this lane's rows in each of its M tiles
-  int la[4], lb[4], lc[4];
-  bool lok[4];
+  int la[MT], lb[MT], lc[MT];
+  bool lok[MT];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < MT; ++i) {
     const int l = (wave + 4 * i) * 16 + cl;
     lok[i] = wave + 4 * i < nmt && l < nloc;
     la[i] = l % P;
     lb[i] = (l / P) % P;
     lc[i] = l / (P * P);
   }
-  v4d_t acc[4][3], acch[3];
+  v4d_t acc[MT][3], acch[3];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < MT; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) acc[i][j] = v4d_t{0, 0, 0, 0};
 #pragma unroll
@@ -292,7 +300,7 @@ k_coupling_mfma(const DevData d, const double *__restrict__ vq, double *__restri
 #pragma unroll
       for (int j = 0; j < 3; ++j) bv[j] = w * nec[j * 16 + cl][qq];        // F(q, nu)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
+      for (int i = 0; i < MT; ++i) {
         if (wave + 4 * i >= nmt) continue;
         const double a = (qok && lok[i]) ? bt[oi + la[i]] * bt[oj + lb[i]] * bt[ok + lc[i]] : 0.0;
 #pragma unroll
@@ -313,7 +321,7 @@ k_coupling_mfma(const DevData d, const double *__restrict__ vq, double *__restri
   double *ps = part + d.tpart_off[slot];
   double *hs = hee_part + d.thee_off[slot];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < MT; ++i) {
     if (wave + 4 * i >= nmt) continue;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -372,7 +380,7 @@ k_coupling_gather(const DevData d, const double *__restrict__ part, int kinetic,
       base[p] = 0;
       if (p < cnt) {
         const int pr = d.urow_pair[ra * 8 + p];
-        const int sl = pr >> 8, l = pr & 255;
+        const int sl = pr >> kPairShift, l = pr & ((1 << kPairShift) - 1);
         const int nnu = d.tnu_off[sl + 1] - d.tnu_off[sl];
         slot[p] = sl;
         base[p] = d.tpart_off[sl] + (int64_t)l * nnu;
@@ -1355,9 +1363,9 @@ void copy_rows(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t
 
 static size_t rebuild_lds(const Geom &g, int n) {
   const int P = g.P, NP = P * (P + 1) / 2;
-  size_t dbl = (size_t)n * P + n * NP + 6 * P * P + g.nloc + n * n * n + n * n * NP + n * NP * NP + NP * NP;
-  size_t need_interp = (size_t)g.nloc + P * P * n;   // u0 + t1 inside U
-  if (need_interp > (size_t)n * n * NP) dbl += need_interp - (size_t)n * n * NP;
+  const size_t ua = (size_t)n * n * NP, ub = (size_t)g.nloc + P * P * n + n * n * P;
+  const size_t usz = ua > ub ? ua : ub;   // U, or the interpolation's u0, t1, t2
+  const size_t dbl = (size_t)n * P + n * NP + 6 * P * P + g.nloc + n * n * n + usz + n * NP + NP * NP;
   return dbl * sizeof(double) + P * P * sizeof(int) + 64;
 }
 
@@ -1383,8 +1391,9 @@ void rebuild_cells(const DevData &d, int mode, const double *rho, const double *
 
 void coupling_partials(const DevData &d, const double *vq, double *part, double *hee_part, hipStream_t s) {
   if (d.nt == 0) return;
-  if (d.g.qe <= 16 && d.g.qc <= 16 && d.g.P <= 8 && d.max_tnu <= 48) {
-    hipLaunchKernelGGL(k_coupling_mfma, dim3(d.nt), dim3(256), 0, s, d, vq, part, hee_part);
+  if (d.g.qe <= 16 && d.g.qc <= 16 && d.g.P <= 8 && d.max_tnu <= 48 && d.g.nloc <= 384) {
+    if (d.g.nloc <= 256) hipLaunchKernelGGL(k_coupling_mfma<4>, dim3(d.nt), dim3(256), 0, s, d, vq, part, hee_part);
+    else hipLaunchKernelGGL(k_coupling_mfma<6>, dim3(d.nt), dim3(256), 0, s, d, vq, part, hee_part);
     return;
   }
   const int n = d.g.qe > d.g.qc ? d.g.qe : d.g.qc, P = d.g.P;

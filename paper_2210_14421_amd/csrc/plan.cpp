@@ -515,6 +515,7 @@ efe_status build_plan(const efe_system &s, Plan &pl) {
     }
   }
   const int NT = (int)pl.tcell.size();
+  if (NT >= (1 << (31 - kPairShift))) { pl.error = "too many enrichment cells for the union-row pairs"; return EFE_ERR_ARG; }
   pl.node_urow.assign(pl.n_nodes, -1);
   pl.urow_node.clear();
   {
@@ -538,7 +539,7 @@ efe_status build_plan(const efe_system &s, Plan &pl) {
       for (int l = 0; l < pl.nloc; ++l) {
         int r = pl.node_urow[nodes[l]];
         if (r < 0) continue;
-        pl.urow_pair[(size_t)r * 8 + pl.urow_cnt[r]++] = t * 256 + l;
+        pl.urow_pair[(size_t)r * 8 + pl.urow_cnt[r]++] = (t << kPairShift) | l;
       }
     }
   }
@@ -623,7 +624,7 @@ efe_status build_plan(const efe_system &s, Plan &pl) {
     for (int64_t r = 0; r < NR; ++r)
       for (int k = 0; k < pl.urow_cnt[r]; ++k) {
         int pr = pl.urow_pair[(size_t)r * 8 + k];
-        int t = pr / 256, l = pr % 256;
+        int t = pr >> kPairShift, l = pr & ((1 << kPairShift) - 1);
         for (int v = 0; v < ne; ++v) pl.b[(size_t)r * ne + v] += bpart[((size_t)t * pl.nloc + l) * ne + v];
       }
     for (int t = 0; t < NT; ++t)
@@ -754,7 +755,7 @@ efe_status build_plan(const efe_system &s, Plan &pl) {
     for (int64_t r = 0; r < NR; ++r)
       for (int k = 0; k < pl.urow_cnt[r]; ++k) {
         int pr = pl.urow_pair[(size_t)r * 8 + k];
-        int t = pr / 256, l = pr % 256;
+        int t = pr >> kPairShift, l = pr & ((1 << kPairShift) - 1);
         for (int v = 0; v < ne; ++v) pl.Kce[(size_t)r * ne + v] += kce_part[((size_t)t * pl.nloc + l) * ne + v];
       }
     for (int t = 0; t < NT; ++t)

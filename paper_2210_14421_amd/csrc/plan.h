@@ -12,6 +12,7 @@ namespace efe {
 
 constexpr int kMaxP = 7;          // degree <= 6
 constexpr int kMaxQ = 16;         // Gauss points per axis
+constexpr int kPairShift = 9;     // union-row pair: slot << kPairShift | local node (nloc <= 343 < 512)
 constexpr int kNoiseModes = 27;
 
 struct Plan {
@@ -68,7 +69,7 @@ struct Plan {
   std::vector<int64_t> urow_node;        // union rows (interior nodes of T-cells)
   std::vector<int> node_urow;            // n_nodes, -1 if not a union row
   std::vector<int> urow_cnt;             // cells of the row's node that are T-cells
-  std::vector<int> urow_pair;            // [row][8]: slot * 256 + local node
+  std::vector<int> urow_pair;            // [row][8]: slot << kPairShift | local node
   std::vector<double> b, c;              // n_R x nenr
   std::vector<double> MAA, Mee;          // nenr x nenr
   std::vector<double> Mee_eval, Mee_evec;

@@ -70,6 +70,36 @@ def test_plan_mass_and_enrichment(tiny_pair):
     assert np.abs(S - m.S).max() < 1e-11 * np.abs(m.S).max()
 
 
+@pytest.mark.parametrize("degree", [2, 3, 6])
+def test_plan_enrichment_every_degree(degree):
+    """The enrichment set-up at the degrees the workloads do not use.  Degree 6
+    has 343 local nodes per cell: the (T-cell slot, local node) pairs of the
+    union rows must keep local indices past 255 (a byte-wide field wrapped them
+    and gave an indefinite M^ee with fewer than five directions kept)."""
+    import dataclasses
+    _lib()
+    from paper_2210_14421_amd.efe import Plan
+    from oracle.model import EFEModel
+    s = dataclasses.replace(tiny(), degree=degree)
+    p, m = Plan(s), EFEModel(s)
+    ne = s.nenr
+    assert p.n_nodes == m.mesh.n_nodes and p.n_kept == m.nk == ne
+    np.testing.assert_allclose(p.get("MAA", ne * ne).reshape(ne, ne), m.MAA, atol=1e-13)
+    np.testing.assert_allclose(p.get("Mee", ne * ne).reshape(ne, ne), m.Mee, atol=1e-13)
+    c = p.get("c", p.n_nodes * ne).reshape(-1, ne)
+    assert np.abs(c - m.c).max() < 1e-12 * np.abs(m.c).max()
+    S = p.get("S", ne * m.nk).reshape(ne, m.nk)
+    assert np.abs(S - m.S).max() < 1e-10 * np.abs(m.S).max()
+    Kce = np.zeros((m.mesh.n_nodes, ne))
+    for cell in m.tcells:
+        pts, w, B, G = m.shape(cell)
+        NE, dNE = m.enrichment_on_cell(cell, grad=True)
+        np.add.at(Kce, m.mesh.cell_nodes(cell), 0.5 * sum(G[d].T @ (w[:, None] * dNE[d]) for d in range(3)))
+    Kce[m.bnd] = 0.0
+    got = p.get("Kce", p.n_nodes * ne).reshape(-1, ne)
+    assert np.abs(got - Kce).max() < 1e-11 * np.abs(Kce).max()
+
+
 def test_plan_static_potential(tiny_pair):
     p, m = tiny_pair
     np.testing.assert_allclose(p.get("vstatic", p.n_quad), m.v_nuc + m.v_trap, rtol=1e-13, atol=1e-13)
