@@ -100,6 +100,23 @@ def test_plan_enrichment_every_degree(degree):
     assert np.abs(got - Kce).max() < 1e-11 * np.abs(Kce).max()
 
 
+def test_plan_many_enrichment_functions():
+    """lattice13: 52 enrichment functions, all kept, 52 nonzero on a central T-cell."""
+    _lib()
+    from paper_2210_14421_amd.efe import Plan
+    from oracle.model import EFEModel
+    from workloads import lattice13
+    s = lattice13()
+    p, m = Plan(s), EFEModel(s)
+    ne = s.nenr
+    assert p.n_kept == m.nk == ne == 52
+    np.testing.assert_allclose(p.get("Mee", ne * ne).reshape(ne, ne), m.Mee, atol=1e-13)
+    c = p.get("c", p.n_nodes * ne).reshape(-1, ne)
+    assert np.abs(c - m.c).max() < 1e-12 * np.abs(m.c).max()
+    S = p.get("S", ne * m.nk).reshape(ne, m.nk)
+    assert np.abs(S - m.S).max() < 1e-11 * np.abs(m.S).max()
+
+
 def test_plan_static_potential(tiny_pair):
     p, m = tiny_pair
     np.testing.assert_allclose(p.get("vstatic", p.n_quad), m.v_nuc + m.v_trap, rtol=1e-13, atol=1e-13)

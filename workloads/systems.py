@@ -205,6 +205,24 @@ def graded_bounds(lo: float, hi: float, ncell: int, beta: float) -> np.ndarray:
     return b
 
 
+def lattice13() -> SystemSpec:
+    """Thirteen Z = 1 atoms on a 2.5-bohr lattice (the centre, the 8 cube corners
+    and 4 face points) in the tiny box, each with a 1s (zeta 2.5) and three 2p
+    (zeta 1.8) enrichment functions: 52 functions, all nonzero on the central
+    cells, so more than 48 meet on one T-cell and more than 48 are kept."""
+    base = tiny()
+    pos = [(0.0, 0.0, 0.0)] + [(a, b, c) for a in (-2.5, 2.5) for b in (-2.5, 2.5) for c in (-2.5, 2.5)] + \
+          [(2.5, 0.0, 0.0), (-2.5, 0.0, 0.0), (0.0, 2.5, 0.0), (0.0, -2.5, 0.0)]
+    R = np.array(pos)
+    na = len(R)
+    return dataclasses.replace(
+        base, name="lattice13", R=R, Z=np.full(na, 1.0),
+        enr_atom=np.repeat(np.arange(na), 4).astype(np.int32),
+        enr_l=np.tile([0, 1, 1, 1], na).astype(np.int32),
+        enr_m=np.tile([0, -1, 0, 1], na).astype(np.int32),
+        enr_zeta=np.tile([2.5, 1.8, 1.8, 1.8], na).astype(float))
+
+
 def tiny_graded() -> SystemSpec:
     """The tiny system on a graded, axis-dependent 4^3 mesh of [-8, 8]^3."""
     s = tiny()
