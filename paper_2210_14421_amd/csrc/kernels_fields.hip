@@ -165,6 +165,7 @@ k_rebuild(const DevData d, const int *__restrict__ cell_list, int n, int mode, c
 //   part[slot][l][nu_local] = sum_q W v N_l(q) N^E_nu(q)
 //   hee_part[slot][mu_local][nu_local] = sum_q W v N^E_mu N^E_nu
 // ---------------------------------------------------------------------------
+template <bool HEE>
 __global__ void __launch_bounds__(kThreads)
 k_coupling_partials(const DevData d, const double *__restrict__ vq, double *__restrict__ part,
                     double *__restrict__ hee_part) {
@@ -205,7 +206,7 @@ k_coupling_partials(const DevData d, const double *__restrict__ vq, double *__re
     __syncthreads();
     apply_axis(t2, nod, Bt, P, true, P, P, n, 2, P, 1);   // [c][b][a]
     // H^ee partial row kk: one wave per mu
-    for (int mm = wid; mm < nnu; mm += nw) {
+    for (int mm = wid; HEE && mm < nnu; mm += nw) {
       const double *nm = NEs + (int64_t)mm * n3;
       double s = 0.0;
       for (int q = lane; q < n3; q += 64) s += f[q] * nm[q];
@@ -229,7 +230,7 @@ k_coupling_partials(const DevData d, const double *__restrict__ vq, double *__re
 constexpr int kCpChunk = 64;
 typedef double v4d_t __attribute__((ext_vector_type(4)));
 
-template <int MT>
+template <int MT, bool PART>
 __global__ void __launch_bounds__(256)
 k_coupling_mfma(const DevData d, const double *__restrict__ vq, double *__restrict__ part,
                 double *__restrict__ hee_part) {
@@ -301,7 +302,7 @@ k_coupling_mfma(const DevData d, const double *__restrict__ vq, double *__restri
       for (int j = 0; j < 3; ++j) bv[j] = w * nec[j * 16 + cl][qq];        // F(q, nu)
 #pragma unroll
       for (int i = 0; i < MT; ++i) {
-        if (wave + 4 * i >= nmt) continue;
+        if (!PART || wave + 4 * i >= nmt) continue;
         const double a = (qok && lok[i]) ? bt[oi + la[i]] * bt[oj + lb[i]] * bt[ok + lc[i]] : 0.0;
 #pragma unroll
         for (int j = 0; j < 3; ++j)
@@ -322,7 +323,7 @@ k_coupling_mfma(const DevData d, const double *__restrict__ vq, double *__restri
   double *hs = hee_part + d.thee_off[slot];
 #pragma unroll
   for (int i = 0; i < MT; ++i) {
-    if (wave + 4 * i >= nmt) continue;
+    if (!PART || wave + 4 * i >= nmt) continue;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int l = (wave + 4 * i) * 16 + kr + 4 * r;
@@ -1391,14 +1392,15 @@ void rebuild_cells(const DevData &d, int mode, const double *rho, const double *
 
 void coupling_partials(const DevData &d, const double *vq, double *part, double *hee_part, hipStream_t s) {
   if (d.nt == 0) return;
-  if (d.g.qe <= 16 && d.g.qc <= 16 && d.g.P <= 8 && d.max_tnu <= 48 && d.g.nloc <= 384) {
-    if (d.g.nloc <= 256) hipLaunchKernelGGL(k_coupling_mfma<4>, dim3(d.nt), dim3(256), 0, s, d, vq, part, hee_part);
-    else hipLaunchKernelGGL(k_coupling_mfma<6>, dim3(d.nt), dim3(256), 0, s, d, vq, part, hee_part);
-    return;
-  }
   const int n = d.g.qe > d.g.qc ? d.g.qe : d.g.qc, P = d.g.P;
   size_t lds = ((size_t)n * P + 2 * n * n * n + n * n * P + n * P * P + d.g.nloc) * sizeof(double);
-  hipLaunchKernelGGL(k_coupling_partials, dim3(d.nt), dim3(kThreads), lds, s, d, vq, part, hee_part);
+  if (d.g.qe <= 16 && d.g.qc <= 16 && d.g.P <= 8 && d.max_tnu <= 48) {
+    // node part by the three axis contractions, H^ee (a dense product over the points) on MFMA
+    hipLaunchKernelGGL(k_coupling_partials<false>, dim3(d.nt), dim3(kThreads), lds, s, d, vq, part, hee_part);
+    hipLaunchKernelGGL((k_coupling_mfma<4, false>), dim3(d.nt), dim3(256), 0, s, d, vq, part, hee_part);
+    return;
+  }
+  hipLaunchKernelGGL(k_coupling_partials<true>, dim3(d.nt), dim3(kThreads), lds, s, d, vq, part, hee_part);
 }
 
 void coupling_gather(const DevData &d, const double *part, int kinetic, double *G, hipStream_t s) {

@@ -12,7 +12,7 @@ the oracle at the same degree:
 * the sum-factorised products, built for degrees 4 and 5 only, are refused
   with EFE_ERR_ARG.
 Degree 6 (343 local nodes, 22 M tiles) runs the cell kernel's six-tile form at
-one workgroup per CU and the coupling partials' six-tile form; degrees 2 and 3
+one workgroup per CU; degrees 2 and 3
 (27 and 64 local nodes) the two-tile form with most M tiles empty, and the
 smallest Poisson grids (7^3 and 11^3 unknowns).
 
