@@ -407,8 +407,8 @@ def main():
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32", "bf16", "f64sf"])
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the orbital-sharded design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the orbitals would be sharded across GPUs, which is not built)", file=sys.stderr)
         sys.exit(2)
     import torch
     from workloads import na8, na8_graded, tiny, na_cluster
