@@ -182,7 +182,9 @@ efe_status efe_initial_state(efe_ctx *ctx, const int32_t *enr_index, const doubl
 
 /* Rebuilds Hbar[rho(Psi), t] (Sec. 2.2 eq. (Hmn) with v_KS of Sec. 2.1) and
  * keeps rho(Psi) as the density of the current time level; required before
- * the first magnus_step and after any change of Psi outside magnus_step. */
+ * the first magnus_step and after any change of Psi outside magnus_step.
+ * Psi: device, n_rows x norb, PACKED (leading dimension = norb; a strided
+ * block must be packed by the caller first). */
 efe_status efe_set_hamiltonian(efe_ctx *ctx, const void *Psi, double t, const efe_field *field);
 
 /* Y = Hbar X for the Hamiltonian last built (ncol <= norb columns). */
@@ -190,8 +192,10 @@ efe_status efe_apply_H(efe_ctx *ctx, const void *X, void *Y, int32_t ncol, int64
 
 /* X <- exp(-i tau A) X, A = Hbar (op EFE_OP_H, Hamiltonian last built) or the
  * Loewdin position operator along x/y/z (no kinetic term, v = x_d), by the
- * adaptive Lanczos method of Sec. 2.6 with full reorthogonalisation, one Krylov
- * space per orbital.  k_force (host, ncol, may be NULL) fixes the Krylov
+ * adaptive Lanczos method of Sec. 2.6, one Krylov space per orbital, with the
+ * reorthogonalisation that efe_options.reorth selects (EFE_REORTH_PARTIAL by
+ * default: Simon's omega recurrence decides when a vector gets a pass against
+ * all previous ones; EFE_REORTH_FULL: a pass at every step).  k_force (host, ncol, may be NULL) fixes the Krylov
  * dimension of each column; otherwise each column stops at the first k whose
  * estimate |tau| beta_k ||x|| |[exp(-i tau T_k)]_{k,1}| <= tol ||x||, or at an
  * invariant subspace.  k_used, err_est: host outputs (ncol, may be NULL).
@@ -294,7 +298,7 @@ efe_status efe_batch_free(efe_batch *batch);
 const char *efe_batch_error(const efe_batch *batch);
 /* Psi[i], ld[i]: member i's device block; fields: NULL or n pointers (each may
  * be NULL); stats: NULL or n entries.  Re-captures when a pointer, ld, dt or a
- * field's kind/direction changes.  Errors name the first failing member in
+ * field's kind/direction changes, or a member's efe_set_options.  Errors name the first failing member in
  * efe_batch_error. */
 efe_status efe_batch_step(efe_batch *batch, void *const *Psi, const int64_t *ld, double t, double dt,
                           const efe_field *const *fields, efe_step_stats *stats);
@@ -316,6 +320,15 @@ efe_status efe_batch_step(efe_batch *batch, void *const *Psi, const int64_t *ld,
 efe_status magnus_adjoint(efe_ctx *ctx, const void *Psi, int64_t ld, double t, double dt,
                           const efe_field *field, const double mubar[3], void *Psibar, int64_t ldb,
                           double dLdE[2]);
+
+/* Chain rule of the pulse parameters (host arithmetic, no GPU): for a kind-1
+ * field E(t) = sum_k A_k sin(w_k t + phi_k) exp(-(t-t0)^2/s^2) of eq. (VField)
+ * and sensitivities dLdE[i] = dL/dE(t[i]) (host, n values, e.g. the pairs that
+ * magnus_adjoint returns for t and t + dt/2), grad = sum_i dLdE[i] dE(t[i])/dtheta
+ * with theta = (A_1..A_m, w_1..w_m, phi_1..phi_m) (host, 3 ncomp doubles).
+ * EFE_ERR_ARG for another field kind or missing arrays, EFE_ERR_NONFINITE for
+ * NaN/Inf in t or dLdE. */
+efe_status efe_field_vjp(const efe_field *field, int64_t n, const double *t, const double *dLdE, double *grad);
 
 /* Adjoint of the dipole of Psi: Psibar = 2 f_a Vbar[mubar . x] Psi_a (the
  * terminal condition of a reverse sweep; mubar host).  Leaves the cell blocks

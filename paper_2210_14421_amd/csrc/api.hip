@@ -38,6 +38,7 @@ struct efe_ctx {
   efe::Plan plan;
   efe::DevData d;
   efe_options opt{};
+  uint64_t opt_gen = 0;     // bumped by efe_set_options: captured steps of older settings are stale
   hipStream_t stream = nullptr;
   std::string err;
   int dtype = 0;
@@ -110,6 +111,7 @@ struct efe_batch {
   std::vector<void *> psi;
   std::vector<int64_t> ld;
   std::vector<int> fkind, fdir;
+  std::vector<uint64_t> gen;   // each member's options generation at capture
   double dt = 0.0;
   std::string err;
 };
@@ -1377,7 +1379,9 @@ efe_status efe_set_options(efe_ctx *ctx, const efe_options *opt) {
     return EFE_ERR_ARG;
   }
   // a captured step holds the Krylov settings it was recorded with: record again
+  // (the context's own graph now, and any batch holding the context at its next step)
   drop_graph(ctx);
+  ++ctx->opt_gen;
   ctx->opt = *opt;
   ctx->kmax = opt->kmax;
   ctx->stream = (hipStream_t)opt->hip_stream;
@@ -1639,7 +1643,7 @@ efe_status efe_batch_step(efe_batch *b, void *const *Psi, const int64_t *ld, dou
   for (int i = 0; same && i < n; ++i) {
     const efe_field *f = fields ? fields[i] : nullptr;
     same = b->psi[i] == Psi[i] && b->ld[i] == ld[i] && b->fkind[i] == (f ? f->kind : 0) &&
-           b->fdir[i] == ((f && f->kind) ? f->direction : 2);
+           b->fdir[i] == ((f && f->kind) ? f->direction : 2) && b->gen[i] == b->m[i]->opt_gen;
   }
   if (!same) {
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
@@ -1650,6 +1654,8 @@ efe_status efe_batch_step(efe_batch *b, void *const *Psi, const int64_t *ld, dou
     b->ld.assign(ld, ld + n);
     b->fkind.assign(n, 0);
     b->fdir.assign(n, 2);
+    b->gen.assign(n, 0);
+    for (int i = 0; i < n; ++i) b->gen[i] = b->m[i]->opt_gen;
     for (int i = 0; i < n; ++i) {
       const efe_field *f = fields ? fields[i] : nullptr;
       b->fkind[i] = f ? f->kind : 0;
@@ -1791,6 +1797,25 @@ efe_status dipole_adjoint(efe_ctx *ctx, const void *Psi, int64_t ld, const doubl
   EFE_TRY(adj_density_term(ctx, ctx->adj_gn, ctx->X0, ctx->adj_XA));
   EFE_TRY(pack_out(ctx, ctx->adj_XA, no, Psibar, ldb));
   return sync(ctx, "dipole_adjoint");
+}
+
+efe_status efe_field_vjp(const efe_field *f, int64_t n, const double *t, const double *dLdE, double *grad) {
+  if (!f || f->kind != 1 || f->ncomp < 1 || !f->A || !f->w || !f->phi || !(f->s > 0.0) || n < 0 ||
+      (n > 0 && (!t || !dLdE)) || !grad)
+    return EFE_ERR_ARG;
+  const int m = f->ncomp;
+  for (int k = 0; k < 3 * m; ++k) grad[k] = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    if (!std::isfinite(t[i]) || !std::isfinite(dLdE[i])) return EFE_ERR_NONFINITE;
+    const double x = (t[i] - f->t0) / f->s, env = std::exp(-x * x) * dLdE[i];
+    for (int k = 0; k < m; ++k) {
+      const double arg = f->w[k] * t[i] + f->phi[k], sn = std::sin(arg), cs = std::cos(arg);
+      grad[k] += sn * env;                          // dE/dA_k
+      grad[m + k] += f->A[k] * t[i] * cs * env;     // dE/dw_k
+      grad[2 * m + k] += f->A[k] * cs * env;        // dE/dphi_k
+    }
+  }
+  return EFE_OK;
 }
 
 efe_status efe_enable_timing(efe_ctx *ctx, int32_t on) {

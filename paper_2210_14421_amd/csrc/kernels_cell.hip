@@ -3,7 +3,7 @@
 // 16x16x4 MFMA (FP64, or FP32 blocks with FP32 accumulation).
 #include <hip/hip_runtime.h>
 
-#include "common.cuh"
+#include "common.h"
 
 namespace efe {
 

@@ -6,7 +6,7 @@
 // Sec. 2.1-2.3 of the paper (eqs. (Hmn), (TDKSDiscrete2), (DiscretePoisson)).
 #include <hip/hip_runtime.h>
 
-#include "common.cuh"
+#include "common.h"
 #include "plan.h"
 
 namespace efe {

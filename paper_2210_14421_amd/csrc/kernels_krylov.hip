@@ -8,7 +8,7 @@
 
 #include <cfloat>
 
-#include "common.cuh"
+#include "common.h"
 
 namespace efe {
 

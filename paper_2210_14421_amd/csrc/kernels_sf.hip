@@ -7,7 +7,7 @@
 // weighted potential at those points.  FP64 on the vector ALU.
 #include <hip/hip_runtime.h>
 
-#include "common.cuh"
+#include "common.h"
 
 namespace efe {
 namespace {

@@ -111,13 +111,15 @@ _dipole = _sig("dipole", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, _dp])
 _timing_on = _sig("efe_enable_timing", C.c_int32, [C.c_void_p, C.c_int32])
 _timing_get = _sig("efe_get_timing", C.c_int32, [C.c_void_p, _dp, C.POINTER(C.c_int64)])
 _last_error = _sig("efe_last_error", C.c_char_p, [C.c_void_p])
+_field_vjp = _sig("efe_field_vjp", C.c_int32, [C.POINTER(EfeField), C.c_int64, _dp, _dp, _dp])
 
 EXPORTED = ["efe_plan_create", "efe_plan_free", "efe_plan_sizes", "efe_plan_get", "efe_plan_error",
             "efe_setup", "efe_free", "efe_dims", "efe_set_options", "efe_initial_state",
             "efe_set_hamiltonian", "efe_apply_H", "lanczos_expm", "magnus_step", "density",
             "efe_hartree", "dipole", "efe_enable_timing", "efe_get_timing", "efe_last_error",
             "magnus_step_graph", "efe_batch_create", "efe_batch_free", "efe_batch_error", "efe_batch_step",
-            "magnus_adjoint", "dipole_adjoint", "magnus_step_extrap", "absorption_spectrum", "power_spectrum"]
+            "magnus_adjoint", "dipole_adjoint", "magnus_step_extrap", "absorption_spectrum", "power_spectrum",
+            "efe_field_vjp"]
 
 
 class EfeError(RuntimeError):
@@ -260,6 +262,19 @@ def make_field(direction=2, A=(), w=(), phi=(), t0=0.0, s=1.0):
     f.A, f.w, f.phi = A.ctypes.data_as(_dp), w.ctypes.data_as(_dp), phi.ctypes.data_as(_dp)
     f.t0, f.s = float(t0), float(s)
     return f, (A, w, phi)
+
+
+def field_vjp(field, t, dLdE):
+    """sum_i dLdE[i] dE(t[i])/dtheta for a sum-of-sines field (efe_field_vjp);
+    theta = (A, w, phi).  Returns 3 ncomp doubles."""
+    tt, gg = _arr(t, np.float64), _arr(dLdE, np.float64)
+    if tt.shape != gg.shape:
+        raise ValueError("one sensitivity per time")
+    out = np.zeros(3 * int(field.ncomp))
+    st = _field_vjp(C.byref(field), len(tt), tt.ctypes.data_as(_dp), gg.ctypes.data_as(_dp), out.ctypes.data_as(_dp))
+    if st != EFE_OK:
+        raise EfeError(st, "efe_field_vjp")
+    return out
 
 
 def _stats_dict(st, n):
@@ -493,61 +508,3 @@ class Batch:
 
     def __del__(self):
         self.close()
-
-
-def field_gradient(ctx, Psi0, theta, t0, s, dt, nsteps, mu_target, direction=2, checkpoint=20):
-    """dL/dtheta of L = sum_{n=1}^{N} (mu_d(t_n) - mu*_n)^2 for the sum-of-sines field
-    E(t) = sum_k A_k sin(w_k t + phi_k) exp(-(t - t0)^2 / s^2), theta = (A, w, phi).
-
-    Forward: N magnus_step calls from Psi0 at t = 0 (not modified), keeping a
-    copy of the orbitals every `checkpoint` steps.  Reverse: per segment, the
-    forward is run again from its checkpoint keeping every step, then
-    dipole_adjoint (terminal condition) and magnus_adjoint step by step; the
-    field sensitivities are contracted with dE/dtheta on the host.
-    Returns (L, grad, mus)."""
-    torch = ctx.torch
-    theta = np.asarray(theta, dtype=np.float64)
-    m = len(theta) // 3
-    A, w, ph = theta[:m], theta[m:2 * m], theta[2 * m:]
-    field, keep = make_field(direction, A, w, ph, t0, s)
-
-    def dE(t):
-        env = np.exp(-((t - t0) / s) ** 2)
-        arg = w * t + ph
-        return np.concatenate([np.sin(arg) * env, A * t * np.cos(arg) * env, A * np.cos(arg) * env])
-
-    Psi = Psi0.clone()
-    ckpt = {}
-    mus = np.zeros((nsteps + 1, 3))
-    ctx.set_hamiltonian(Psi, 0.0, field)
-    mus[0] = ctx.dipole(Psi)
-    for n in range(nsteps):
-        if n % checkpoint == 0:
-            ckpt[n] = Psi.clone()
-        mus[n + 1] = ctx.magnus_step(Psi, n * dt, dt, field)["mu"]
-    resid = mus[1:, direction] - np.asarray(mu_target)
-    L = float(np.sum(resid ** 2))
-
-    def mubar(n):              # dL/dmu(t_n)
-        v = np.zeros(3)
-        if n >= 1:
-            v[direction] = 2.0 * resid[n - 1]
-        return v
-
-    grad = np.zeros_like(theta)
-    Psibar = None
-    for c0 in sorted(ckpt, reverse=True):
-        c1 = min(c0 + checkpoint, nsteps)
-        states = [ckpt[c0].clone()]
-        ctx.set_hamiltonian(states[0], c0 * dt, field)
-        for n in range(c0, c1):
-            P = states[-1].clone()
-            ctx.magnus_step(P, n * dt, dt, field)
-            states.append(P)
-        if Psibar is None:
-            Psibar = ctx.dipole_adjoint(states[-1], mubar(c1))
-        for n in range(c1 - 1, c0 - 1, -1):
-            gE = ctx.magnus_adjoint(states[n - c0], Psibar, n * dt, dt, field, mubar(n))
-            grad += gE[0] * dE(n * dt) + gE[1] * dE(n * dt + 0.5 * dt)
-    del keep
-    return L, grad, mus

@@ -5,9 +5,11 @@
   Re<Xbar, dX> = Re<Ybar, F(X + h dX) - F(X - h dX)> / (2h) and
   dL/dE(t), dL/dE(t + dt/2) the same identity for a field perturbation.
 * Field-parameter gradient of the dipole-tracking loss on the tiny system
-  (20 steps, checkpoints every 7 steps) against the oracle's central
-  differences with k replayed (tests/golden/adjoint_tiny.npz) and against
-  central differences of the GPU forward itself.  Target 1e-6 relative.
+  (20 steps, checkpoints every 7 steps), taken by torch.autograd.grad through
+  MagnusFn (the reverse sweep of the library's adjoint steps), against the
+  oracle's central differences with k replayed (tests/golden/adjoint_tiny.npz)
+  and against central differences of the GPU forward itself.  Target 1e-6
+  relative.
 """
 import os
 
@@ -103,7 +105,7 @@ def test_adjoint_step_dot_product(setup):
 
 def test_field_gradient_against_oracle(setup):
     from workloads import ADJOINT_TINY
-    from paper_2210_14421_amd.efe import field_gradient
+    from paper_2210_14421_amd.adjoint import field_gradient
     spec, ctx, X0, gold = setup
     cfg = ADJOINT_TINY
     L, g, mus = field_gradient(ctx, _dev(X0), gold["theta"], cfg["t0"], cfg["s"], cfg["dt"], cfg["nsteps"],
@@ -119,7 +121,7 @@ def test_field_gradient_against_oracle(setup):
 
 def test_field_gradient_against_gpu_differences(setup):
     from workloads import ADJOINT_TINY
-    from paper_2210_14421_amd.efe import field_gradient
+    from paper_2210_14421_amd.adjoint import field_gradient
     spec, ctx, X0, gold = setup
     cfg = ADJOINT_TINY
     theta = gold["theta"]
@@ -146,3 +148,33 @@ def test_field_gradient_against_gpu_differences(setup):
         fd = (loss(tp, ks)[0] - loss(tm, ks)[0]) / (2 * h)
         print(f"param {p}: adjoint {g[p]:.12e}  gpu fd {fd:.12e}", flush=True)
         assert abs(g[p] - fd) <= 1e-6 * np.max(np.abs(g))
+
+
+def test_autograd_through_magnus_fn(setup):
+    """torch.autograd.grad of a loss written in torch on MagnusFn's dipole trace:
+    the tiny loss against the oracle's k-replayed central differences (1e-6), and a
+    loss on another dipole component and on mu(t_0) (no dependence: zero gradient
+    from mu(t_0)) against the same sweep's linearity."""
+    from workloads import ADJOINT_TINY
+    from paper_2210_14421_amd.adjoint import MagnusFn
+    spec, ctx, X0, gold = setup
+    cfg = ADJOINT_TINY
+    theta = torch.tensor(gold["theta"], dtype=torch.float64, requires_grad=True)
+    Psi0 = _dev(X0)
+    mus = MagnusFn.apply(theta, Psi0, ctx, cfg["t0"], cfg["s"], cfg["dt"], cfg["nsteps"], 2, 5)
+    assert mus.shape == (cfg["nsteps"] + 1, 3) and mus.dtype == torch.float64
+    target = torch.from_numpy(gold["mu_target"])
+    L = ((mus[1:, 2] - target) ** 2).sum()
+    (g,) = torch.autograd.grad(L, theta, retain_graph=True)
+    eg = float(np.linalg.norm(g.numpy() - gold["g_fd"]) / np.linalg.norm(gold["g_fd"]))
+    print(f"autograd: L {float(L):.12e} (oracle {float(gold['L']):.12e}); |g - g_fd|/|g_fd| = {eg:.2e}", flush=True)
+    assert abs(float(L) - float(gold["L"])) <= 1e-7 * abs(float(gold["L"]))
+    assert eg < 1e-6
+    # linearity of the reverse sweep in dL/dmu: L2 = 3 L - 2 sum mu_x(t_n) + 5 mu_z(t_0)
+    L2 = 3.0 * L - 2.0 * mus[1:, 0].sum() + 5.0 * mus[0, 2]
+    (g2,) = torch.autograd.grad(L2, theta, retain_graph=True)
+    (gx,) = torch.autograd.grad(mus[1:, 0].sum(), theta)
+    lin = float(np.linalg.norm(g2.numpy() - (3.0 * g.numpy() - 2.0 * gx.numpy())) / np.linalg.norm(g2.numpy()))
+    print(f"autograd linearity {lin:.2e}", flush=True)
+    assert lin < 1e-8
+    assert torch.equal(Psi0, _dev(X0))                      # the input orbitals are not modified

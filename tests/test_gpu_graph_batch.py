@@ -147,6 +147,46 @@ def test_batch_matches_members_alone(tiny_gs):
             c.close()
 
 
+def test_batch_recaptures_after_member_options(tiny_gs):
+    """A batch graph holds every member's Krylov settings: after set_options on one
+    member (full reorthogonalisation, tighter tolerance) the next batch step is
+    recorded again and that member equals its host-driven step with the new
+    settings, while the other member is unchanged."""
+    from workloads import tiny
+    from paper_2210_14421_amd.efe import Context, Batch
+    spec = tiny()
+    print("batch re-capture after set_options", flush=True)
+    ref_new = Context(spec, kmax=40, reorth="full", tol=1e-12)
+    ref_old = Context(spec, kmax=40)
+    members = [Context(spec, kmax=40), Context(spec, kmax=40)]
+    batch = None
+    try:
+        Pn, Po = _kicked(ref_new, tiny_gs, "z"), _kicked(ref_old, tiny_gs, "x")
+        P_mem = [_kicked(members[0], tiny_gs, "z"), _kicked(members[1], tiny_gs, "x")]
+        batch = Batch(members)
+        batch.step(P_mem, 0.0, spec.dt)                       # captured with the default settings
+        ref_old.magnus_step(Po, 0.0, spec.dt)
+        members[0].set_options(reorth="full", tol=1e-12)
+        P_mem[0].copy_(_kicked(members[0], tiny_gs, "z"))
+        members[0].set_hamiltonian(P_mem[0], 0.0)
+        got = batch.step(P_mem, 0.0, spec.dt)                 # no field: t enters nothing
+        sn = ref_new.magnus_step(Pn, 0.0, spec.dt)
+        assert list(got[0]["k_pred"]) == list(sn["k_pred"]) and list(got[0]["k_corr"]) == list(sn["k_corr"])
+        e0 = _rel(P_mem[0], Pn)
+        print(f"member 0 (new settings): k {got[0]['k_corr']} |dPsi| {e0:.2e}", flush=True)
+        assert e0 < 1e-12
+        so = ref_old.magnus_step(Po, spec.dt, spec.dt)
+        assert list(got[1]["k_corr"]) == list(so["k_corr"])
+        e1 = _rel(P_mem[1], Po)
+        print(f"member 1 (old settings): |dPsi| {e1:.2e}", flush=True)
+        assert e1 < 1e-12
+    finally:
+        if batch is not None:
+            batch.close()
+        for c in members + [ref_new, ref_old]:
+            c.close()
+
+
 def test_graph_step_na8():
     """One captured step at the full Na8 size equals the host-driven step."""
     from workloads import na8

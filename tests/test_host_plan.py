@@ -215,3 +215,37 @@ def test_plan_na2_matches_oracle_setup():
     assert kappa > 1e5
     S = p.get("S", ne * m.nk).reshape(ne, m.nk)
     assert np.abs(S - m.S).max() < 1e-12 * kappa * np.abs(m.S).max()
+
+
+def test_field_vjp_against_oracle_derivatives():
+    """efe_field_vjp (host arithmetic of the library) against the oracle's dE/dtheta
+    and central differences of the oracle's field E(t), on the 24-parameter pulse
+    of the adjoint workload and at the step and midpoint times of 40 steps."""
+    _lib()
+    from paper_2210_14421_amd.efe import make_field, field_vjp, EfeError
+    from oracle.adjoint import field_derivatives, field_from_params
+    from workloads import adjoint_field_params
+    theta = adjoint_field_params(7, 8, (1e-3, 1e-2), (0.05, 0.5))
+    m = len(theta) // 3
+    t0, s, dt = 4.0, 2.0, 0.02
+    f, keep = make_field(2, theta[:m], theta[m:2 * m], theta[2 * m:], t0, s)
+    t = np.sort(np.concatenate([dt * np.arange(40), dt * np.arange(40) + 0.5 * dt]))
+    g = np.random.default_rng(3).standard_normal(len(t))
+    got = field_vjp(f, t, g)
+    ref = sum(gi * field_derivatives(theta, t0, s, ti) for gi, ti in zip(g, t))
+    np.testing.assert_allclose(got, ref, rtol=1e-13, atol=1e-16 * np.max(np.abs(ref)))
+    h = 1e-6
+    fd = np.zeros_like(theta)
+    for p in range(len(theta)):
+        tp, tm = theta.copy(), theta.copy()
+        tp[p] += h
+        tm[p] -= h
+        Fp, Fm = field_from_params(tp, t0, s), field_from_params(tm, t0, s)
+        fd[p] = sum(gi * (Fp.E(ti) - Fm.E(ti)) for gi, ti in zip(g, t)) / (2 * h)
+    np.testing.assert_allclose(got, fd, rtol=1e-6, atol=1e-8 * np.max(np.abs(fd)))
+    f0, k0 = make_field(2)                                 # no field: nothing to differentiate
+    with pytest.raises(EfeError):
+        field_vjp(f0, t, g)
+    with pytest.raises(EfeError):
+        field_vjp(f, t, np.where(np.arange(len(t)) == 3, np.nan, g))
+    del keep, k0
