@@ -304,6 +304,29 @@ class EFEModel:
         YE = self.S.T @ (Hce.T @ Xc + Hee @ psiE)
         return Yr, YE
 
+    def cell_blocks(self, v_q, kinetic=True):
+        """Every cell block H_c of `cell_block`, stacked (n_cells, nloc, nloc).  The
+        kinetic term depends only on a cell's class and edge lengths, so it is formed
+        once per (class, edges) and added as in `cell_block`."""
+        m = self.mesh
+        out = np.empty((m.n_cells, m.nloc, m.nloc))
+        kin = {}
+        for c in range(m.n_cells):
+            pts, w, B, G = self.shape(c)
+            v = v_q[m.q_off[c]:m.q_off[c + 1]]
+            Hc = B.T @ ((w * v)[:, None] * B)
+            if kinetic:
+                key = (bool(m.is_enr[c]), tuple(m.cell_size(c)))
+                if key not in kin:
+                    kin[key] = 0.5 * sum(G[d].T @ (w[:, None] * G[d]) for d in range(3))
+                Hc += kin[key]
+            out[c] = Hc
+        return out
+
+    def operator(self, v_q, kinetic=True):
+        """Hbar of `hamiltonian` as a matrix-free operator (CellOperator)."""
+        return CellOperator(self, v_q, kinetic)
+
     def position_operator(self, d):
         """Zbar_d: Loewdin position operator (no kinetic term, v = x_d)."""
         return self.hamiltonian(self.qpts[:, d].copy(), kinetic=False)
@@ -464,6 +487,15 @@ class EFEModel:
         v, _ = self.potential_from_density(rho, t, field)
         return self.hamiltonian(v)
 
+    def operator_from_density(self, rho, t=0.0, field=None):
+        """Matrix-free Hbar[rho, t] with the Hartree potential by fast diagonalisation."""
+        phi = self.hartree(rho, solver="fdm")
+        return self.operator(self.ks_potential(rho, self.interpolate_nodal(phi), t, field))
+
+    def position_operator_free(self, d):
+        """Matrix-free Zbar_d (no kinetic term, v = x_d)."""
+        return self.operator(self.qpts[:, d].copy(), kinetic=False)
+
     # -------------------------------------------------------- initial states
     def enrichment_noise_state(self):
         """Enrichment directions plus low-frequency FE noise, Loewdin-orthonormalised.
@@ -500,3 +532,50 @@ class EFEModel:
         lam_g, V = np.linalg.eigh(G)
         X = X @ ((V / np.sqrt(lam_g)) @ V.T)
         return X.astype(np.complex128)
+
+
+class CellOperator:
+    """Hbar X without the assembled matrix, for meshes too large to assemble.
+
+    The same definitions as `EFEModel.hamiltonian` (eq. (Hmn), eq. (TDKSDiscrete2)):
+    Y_C = D^-1/2 sum_c P_c^T H_c P_c D^-1/2 X_C + D^-1/2 H^ce S X_E and
+    Y_E = S^T (H^ce)^T D^-1/2 X_C + S^T H^ee S X_E, with the cell blocks H_c of
+    `cell_block` (gathered and summed by a scatter matrix) and the coupling of
+    `coupling`.  Called on one column (n_rows,) or a block (n_rows, m).
+    """
+
+    def __init__(self, model, v_q, kinetic=True):
+        m = model.mesh
+        self.N = m.n_nodes
+        self.n_rows = model.n_rows
+        self.nodes = np.stack([m.cell_nodes(c) for c in range(m.n_cells)])
+        self.blocks = model.cell_blocks(v_q, kinetic)
+        self.dm = model.dm12()
+        nl = m.nloc
+        self.scatter = sp.csr_matrix((np.ones(m.n_cells * nl), (self.nodes.reshape(-1), np.arange(m.n_cells * nl))),
+                                     shape=(self.N, m.n_cells * nl))
+        self.has_enr = model.spec.nenr > 0
+        if self.has_enr:
+            self.Hce, self.Hee = model.coupling(v_q, kinetic)
+            self.S = model.S
+
+    def __call__(self, X):
+        X = np.asarray(X)
+        one = X.ndim == 1
+        X2 = (X[:, None] if one else X).astype(np.complex128)
+        N, ncol = self.N, X2.shape[1]
+        Xc = np.ascontiguousarray(self.dm[:, None] * X2[:N])
+        Xr = Xc.view(np.float64)                          # (N, 2 ncol): re and im as real columns
+        loc = np.empty((self.blocks.shape[0], self.blocks.shape[1], 2 * ncol))
+        step = 512
+        for c0 in range(0, self.blocks.shape[0], step):
+            c1 = min(c0 + step, self.blocks.shape[0])
+            loc[c0:c1] = np.matmul(self.blocks[c0:c1], Xr[self.nodes[c0:c1]])
+        Yc = np.ascontiguousarray(self.scatter @ loc.reshape(-1, 2 * ncol)).view(np.complex128)
+        Y = np.zeros((self.n_rows, ncol), dtype=np.complex128)
+        if self.has_enr:
+            psiE = self.S @ X2[N:]
+            Yc = Yc + self.Hce @ psiE
+            Y[N:] = self.S.T @ (self.Hce.T @ Xc + self.Hee @ psiE)
+        Y[:N] = self.dm[:, None] * Yc
+        return Y[:, 0] if one else Y

@@ -5,7 +5,10 @@
   The section gives the three-term recurrence; in floating point the vectors
   lose orthogonality once Ritz values converge, so two ways of keeping them
   orthogonal are provided (both reduce to the recurrence in exact arithmetic):
-  - "partial" (default): the three-term recurrence itself, with alpha_j the
+  - "full" (default, the plain scheme every stored reference is made with): the
+    three-term step, then two classical Gram-Schmidt passes against all previous
+    vectors;
+  - "partial": the three-term recurrence itself, with alpha_j the
     q_j coefficient of A q_j (computed) and beta_{j-1} the previous norm (known);
     Simon's omega recurrence (Simon 1984,
     "The Lanczos algorithm with partial reorthogonalization") estimates
@@ -13,8 +16,7 @@
     exceeds sqrt(eps) the vector, and the next one, get a Gram-Schmidt pass
     against all previous vectors (semi-orthogonality, which keeps T_k the
     projected operator to working accuracy); a pass is also made when the
-    local one cancelled most of the vector;
-  - "full": two classical Gram-Schmidt passes against all previous vectors.
+    local one cancelled most of the vector.
   exp(-i tau T_k) e_1 by eigendecomposition of T_k.
 * eq. (AdaptiveKrylovErr): the error estimate of the k-dimensional
   approximation is |tau| beta_k ||psi|| |[exp(-i tau T_k)]_{k,1}|, where beta_k is
@@ -85,9 +87,10 @@ def omega_next(alpha, beta, b_j, om_j, om_jm1, anorm):
     return out
 
 
-def lanczos_expm_column(Aop, tau, v, tol, kmax, k_force: Optional[int] = None, reorth: str = "partial",
-                        stats: Optional[dict] = None):
-    """One column: returns (exp(-i tau A) v approximation, k, error estimate)."""
+def _lanczos_column(tau, v, tol, kmax, k_force: Optional[int] = None, reorth: str = "full",
+                    stats: Optional[dict] = None):
+    """One column as a generator: yields each Lanczos vector q_j and is sent A q_j;
+    returns (exp(-i tau A) v approximation, k, error estimate)."""
     if reorth not in ("partial", "full"):
         raise ValueError(f"unknown reorthogonalisation {reorth!r}")
     beta0 = float(np.linalg.norm(v))
@@ -99,7 +102,7 @@ def lanczos_expm_column(Aop, tau, v, tol, kmax, k_force: Optional[int] = None, r
     anorm, force = 0.0, False
     for j in range(1, kmax + 1):
         q = Q[-1]
-        w = Aop(q)
+        w = yield q
         if reorth == "full":
             a = float(np.real(np.vdot(q, w)))
             alpha.append(a)
@@ -151,17 +154,55 @@ def lanczos_expm_column(Aop, tau, v, tol, kmax, k_force: Optional[int] = None, r
     raise NoConvergence(f"Lanczos did not reach tol {tol} within {kmax} vectors")
 
 
-def lanczos_expm(A, tau, X, tol=1e-10, kmax=64, k_force: Optional[Sequence[int]] = None, reorth: str = "partial",
-                 stats: Optional[dict] = None):
-    """exp(-i tau A) X column by column.  A: matrix (sparse/dense) or callable."""
-    Aop = A if callable(A) else (lambda q: A @ q)
+def lanczos_expm_column(Aop, tau, v, tol, kmax, k_force: Optional[int] = None, reorth: str = "full",
+                        stats: Optional[dict] = None):
+    """One column: returns (exp(-i tau A) v approximation, k, error estimate)."""
+    gen = _lanczos_column(tau, v, tol, kmax, k_force, reorth, stats)
+    try:
+        q = next(gen)
+        while True:
+            q = gen.send(Aop(q))
+    except StopIteration as stop:
+        return stop.value
+
+
+def lanczos_expm(A, tau, X, tol=1e-10, kmax=64, k_force: Optional[Sequence[int]] = None, reorth: str = "full",
+                 stats: Optional[dict] = None, block=False):
+    """exp(-i tau A) X, one Krylov space per column.  A: matrix (sparse/dense) or callable.
+
+    block=False: the columns one after another.  block=True (A callable on an
+    (n, m) block): the columns' recurrences advance together and A is applied once
+    per iteration to the block of the still-running columns' vectors; each column
+    runs the same steps as alone (the columns are independent problems)."""
     X = np.asarray(X, dtype=np.complex128)
     Y = np.empty_like(X)
     ks = np.zeros(X.shape[1], dtype=np.int32)
     errs = np.zeros(X.shape[1])
+    if not block:
+        Aop = A if callable(A) else (lambda q: A @ q)
+        for a in range(X.shape[1]):
+            kf = None if k_force is None else int(k_force[a])
+            Y[:, a], ks[a], errs[a] = lanczos_expm_column(Aop, tau, X[:, a], tol, kmax, kf, reorth, stats)
+        return Y, ks, errs
+    Ablk = A if callable(A) else (lambda B: A @ B)
+    gens, qs = {}, {}
     for a in range(X.shape[1]):
         kf = None if k_force is None else int(k_force[a])
-        Y[:, a], ks[a], errs[a] = lanczos_expm_column(Aop, tau, X[:, a], tol, kmax, kf, reorth, stats)
+        g = _lanczos_column(tau, X[:, a], tol, kmax, kf, reorth, stats)
+        try:
+            qs[a] = next(g)
+            gens[a] = g
+        except StopIteration as stop:
+            Y[:, a], ks[a], errs[a] = stop.value
+    while gens:
+        cols = sorted(gens)
+        W = Ablk(np.stack([qs[a] for a in cols], axis=1))
+        for i, a in enumerate(cols):
+            try:
+                qs[a] = gens[a].send(W[:, i])
+            except StopIteration as stop:
+                Y[:, a], ks[a], errs[a] = stop.value
+                del gens[a], qs[a]
     return Y, ks, errs
 
 
@@ -179,9 +220,15 @@ class Propagator:
     Hamiltonian by predictor-corrector (scheme "pc") or by extrapolation from the
     three previous densities (scheme "extrap")."""
 
-    def __init__(self, model, X, t=0.0, field=None, tol=None, kmax=None, scheme="pc"):
+    def __init__(self, model, X, t=0.0, field=None, tol=None, kmax=None, scheme="pc", reorth="full",
+                 matrix_free=False):
+        """matrix_free: Hbar as `EFEModel.operator` (cell blocks and coupling applied
+        without assembly, Hartree by fast diagonalisation) and the Lanczos columns
+        advanced together (for large meshes); otherwise the assembled matrix."""
         if scheme not in ("pc", "extrap"):
             raise ValueError(f"unknown scheme {scheme!r}")
+        self.reorth = reorth
+        self.matrix_free = matrix_free
         self.model = model
         self.X = np.asarray(X, dtype=np.complex128).copy()
         self.t = float(t)
@@ -195,13 +242,22 @@ class Propagator:
         """(Re)build rho and Hbar for the current orbitals and time; the density
         history restarts from rho."""
         self.rho = self.model.density(self.X)
-        self.H = self.model.hamiltonian_from_density(self.rho, self.t, self.field)
+        self.H = self._ham(self.rho, self.t)
         self.hist, self.hist_dt = [self.rho], None
+
+    def _ham(self, rho, t):
+        if self.matrix_free:
+            return self.model.operator_from_density(rho, t, self.field)
+        return self.model.hamiltonian_from_density(rho, t, self.field)
+
+    def _expm(self, A, tau, X, k_force):
+        return lanczos_expm(A, tau, X, self.tol, self.kmax, k_force, reorth=self.reorth, block=self.matrix_free)
 
     def kick(self, kappa, direction=2):
         """psi <- exp(i kappa Zbar_d) psi, then refresh the Hamiltonian."""
-        Z = self.model.position_operator(direction)
-        self.X, k, _ = lanczos_expm(Z, -kappa, self.X, self.tol, self.kmax)
+        Z = self.model.position_operator_free(direction) if self.matrix_free else \
+            self.model.position_operator(direction)
+        self.X, k, _ = self._expm(Z, -kappa, self.X, None)
         self.refresh()
         return k
 
@@ -216,13 +272,15 @@ class Propagator:
             rho_mid = extrapolate_midpoint(hist)
             kp = np.zeros(self.X.shape[1], dtype=np.int32)
         else:
-            Xp, kp, _ = lanczos_expm(self.H, dt, self.X, self.tol, self.kmax, kp_f)
+            Xp, kp, _ = self._expm(self.H, dt, self.X, kp_f)
             rho_mid = 0.5 * (self.rho + m.density(Xp))
-        Hmid = m.hamiltonian_from_density(rho_mid, self.t + 0.5 * dt, self.field)
-        self.X, kc, _ = lanczos_expm(Hmid, dt, self.X, self.tol, self.kmax, kc_f)
+        Hmid = self._ham(rho_mid, self.t + 0.5 * dt)
+        self.X, kc, _ = self._expm(Hmid, dt, self.X, kc_f)
+        del Hmid
         self.t += dt
         self.rho = m.density(self.X)
-        self.H = m.hamiltonian_from_density(self.rho, self.t, self.field)
+        self.H = None
+        self.H = self._ham(self.rho, self.t)
         self.hist, self.hist_dt = (hist + [self.rho])[-3:], dt
         return m.dipole(self.rho), kp, kc
 

@@ -1,10 +1,14 @@
 """Write the stored expected values under tests/golden/ (calls only the oracle).
 
 Usage: python tests/golden/make_golden.py [tiny_gs] [trap_gs] [tiny_traj] [tiny_extrap] [na8] [adjoint_tiny]
-       [tiny_graded_gs] [tiny_graded_traj] [na8_graded]
+       [tiny_graded_gs] [tiny_graded_traj] [na8_graded] [na8_step] [na2_traj]
 
 Every file written here is produced by the FP64 oracle from the seeded inputs of
-``workloads``; nothing comes from the GPU library.
+``workloads``; nothing comes from the GPU library.  Every stored trajectory and
+gradient uses the oracle's plain Lanczos scheme (Sec. 2.6, eq. (AdaptiveKrylov):
+the three-term step followed by two classical Gram-Schmidt passes against all
+previous vectors, reorth="full"), never the partial reorthogonalisation the GPU
+library runs by default; the files record the scheme under "lanczos".
 """
 from __future__ import annotations
 
@@ -18,7 +22,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 from workloads import (tiny, tiny_graded, trap, na8 as na8_spec, na8_graded as na8_graded_spec,  # noqa: E402
-                       adjoint_field_params, ADJOINT_TINY)
+                       na_cluster, adjoint_field_params, ADJOINT_TINY)
 from oracle.model import EFEModel  # noqa: E402
 from oracle.propagate import scf_ground_state, Propagator  # noqa: E402
 
@@ -44,7 +48,7 @@ def tiny_traj():
     spec = tiny()
     m = EFEModel(spec)
     X0 = np.load(os.path.join(HERE, "tiny_ground_state.npz"))["X"]
-    P = Propagator(m, X0, tol=spec.krylov_tol, kmax=spec.kmax)
+    P = Propagator(m, X0, tol=spec.krylov_tol, kmax=spec.kmax, reorth="full")
     mu0 = m.dipole(P.rho)
     k_kick = P.kick(spec.kick, spec.kick_dir)
     mus = [m.dipole(P.rho)]
@@ -58,7 +62,7 @@ def tiny_traj():
             print(f"step {n} mu_z={mu[2]:.6e} k={kp},{kc} ({time.time() - t0:.0f}s)", flush=True)
     np.savez_compressed(os.path.join(HERE, "tiny_traj.npz"), mu_ground=mu0, mu=np.array(mus),
                         k=np.array(ks, dtype=np.int32), k_kick=k_kick, X_final=P.X,
-                        rho_final=P.rho, dt=spec.dt, kick=spec.kick)
+                        rho_final=P.rho, dt=spec.dt, kick=spec.kick, lanczos="full")
 
 
 def tiny_extrap():
@@ -67,7 +71,7 @@ def tiny_extrap():
     spec = tiny()
     m = EFEModel(spec)
     X0 = np.load(os.path.join(HERE, "tiny_ground_state.npz"))["X"]
-    P = Propagator(m, X0, tol=spec.krylov_tol, kmax=spec.kmax, scheme="extrap")
+    P = Propagator(m, X0, tol=spec.krylov_tol, kmax=spec.kmax, scheme="extrap", reorth="full")
     k_kick = P.kick(spec.kick, spec.kick_dir)
     mus = [m.dipole(P.rho)]
     ks = []
@@ -79,7 +83,7 @@ def tiny_extrap():
         if n % 20 == 0:
             print(f"step {n} mu_z={mu[2]:.6e} k={kp},{kc} ({time.time() - t0:.0f}s)", flush=True)
     np.savez_compressed(os.path.join(HERE, "tiny_extrap.npz"), mu=np.array(mus), k=np.array(ks, dtype=np.int32),
-                        k_kick=k_kick, X_final=P.X, dt=spec.dt, kick=spec.kick)
+                        k_kick=k_kick, X_final=P.X, dt=spec.dt, kick=spec.kick, lanczos="full")
 
 
 def tiny_graded_gs():
@@ -94,7 +98,7 @@ def tiny_graded_traj():
     spec = tiny_graded()
     m = EFEModel(spec)
     X0 = np.load(os.path.join(HERE, "tiny_graded_ground_state.npz"))["X"]
-    P = Propagator(m, X0, tol=spec.krylov_tol, kmax=spec.kmax)
+    P = Propagator(m, X0, tol=spec.krylov_tol, kmax=spec.kmax, reorth="full")
     k_kick = P.kick(spec.kick, spec.kick_dir)
     mus = [m.dipole(P.rho)]
     ks = []
@@ -103,7 +107,8 @@ def tiny_graded_traj():
         mus.append(mu)
         ks.append(np.stack([kp, kc]))
     np.savez_compressed(os.path.join(HERE, "tiny_graded_traj.npz"), mu=np.array(mus),
-                        k=np.array(ks, dtype=np.int32), k_kick=k_kick, X_final=P.X, dt=spec.dt, kick=spec.kick)
+                        k=np.array(ks, dtype=np.int32), k_kick=k_kick, X_final=P.X, dt=spec.dt, kick=spec.kick,
+                        lanczos="full")
     print("tiny_graded trajectory: mu_z(50) =", mus[-1][2])
 
 
@@ -146,6 +151,66 @@ def na8_graded():
     na8(na8_graded_spec(), "na8_graded_sampled.npz")
 
 
+def cluster_steps(spec, nsteps, name):
+    """Kicked Magnus-2 steps of a sodium cluster by the oracle's matrix-free route
+    (cell blocks and coupling applied without assembly, Lanczos columns advanced
+    together, Hartree by fast diagonalisation; the plain Lanczos scheme).
+
+    Stores the dipole before and after the kick and after every step, the Krylov
+    dimension of every column (kick, predictor, corrector), and the orbitals at
+    sampled node rows and at every enrichment row after the kick and each step."""
+    t0 = time.time()
+    m = EFEModel(spec)
+    print(f"{name}: model {time.time() - t0:.0f}s", flush=True)
+    X0 = m.enrichment_noise_state()
+    P = Propagator(m, X0, tol=spec.krylov_tol, kmax=spec.kmax, reorth="full", matrix_free=True)
+    mu0 = m.dipole(P.rho)
+    print(f"{name}: initial state and Hamiltonian {time.time() - t0:.0f}s  mu0={mu0}", flush=True)
+    k_kick = P.kick(spec.kick, spec.kick_dir)
+    N = m.mesh.n_nodes
+    rng = np.random.default_rng(2025)
+    near = np.nonzero(np.any(m.c != 0.0, axis=1))[0]
+    rows = np.unique(np.concatenate([rng.choice(m.interior, 64, replace=False), rng.choice(near, 64, replace=False)]))
+    mus, ks, Xr, XE, secs = [m.dipole(P.rho)], [], [P.X[rows]], [P.X[N:]], []
+    print(f"{name}: kick k={k_kick} {time.time() - t0:.0f}s  mu={mus[-1]}", flush=True)
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except ImportError:
+        threads = os.cpu_count()
+    cpu = "unknown"
+    with open("/proc/cpuinfo") as f:
+        for line in f:
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    for n in range(nsteps):
+        ts = time.time()
+        mu, kp, kc = P.step(spec.dt)
+        secs.append(time.time() - ts)
+        mus.append(mu)
+        ks.append(np.stack([kp, kc]))
+        Xr.append(P.X[rows])
+        XE.append(P.X[N:])
+        print(f"{name}: step {n} k={kp},{kc} {time.time() - t0:.0f}s  mu={mu}", flush=True)
+        # written after every step: the steps done so far are kept if a later one is cut short
+        np.savez_compressed(os.path.join(HERE, name), mu_ground=mu0, mu=np.array(mus),
+                            k=np.array(ks, dtype=np.int32), k_kick=k_kick, rows=rows, X_rows=np.array(Xr),
+                            X_E=np.array(XE), dt=spec.dt, kick=spec.kick, kick_dir=spec.kick_dir, lanczos="full",
+                            step_seconds=np.array(secs), threads=threads, cpu_model=cpu)
+    print(f"{name}: done {time.time() - t0:.0f}s", flush=True)
+
+
+def na8_step():
+    """Na8 (the benchmark system): z kick 1e-3 and two Magnus-2 steps of 0.02 au."""
+    cluster_steps(na8_spec(), 2, "na8_step.npz")
+
+
+def na2_traj():
+    """Na2 (seed 2; a member of the batched workload): x kick 1e-3 and ten steps."""
+    cluster_steps(na_cluster(2, seed=2, kick=1e-3, kick_dir=0), 10, "na2_traj.npz")
+
+
 def adjoint_tiny():
     """Field-parameter gradient on the tiny system (oracle central differences, k replayed)."""
     from oracle.adjoint import fd_gradient, run_dipole, field_from_params
@@ -161,7 +226,8 @@ def adjoint_tiny():
     g, L, mus, ks = fd_gradient(m, X0, theta, cfg["t0"], cfg["s"], cfg["dt"], cfg["nsteps"], mu_target)
     print(f"gradient {time.time() - t0:.0f}s  L={L:.6e}  g={g}", flush=True)
     np.savez_compressed(os.path.join(HERE, "adjoint_tiny.npz"), theta=theta, theta_star=theta_star,
-                        mu_target=mu_target, mus=mus, L=L, g_fd=g, ks=np.asarray(ks, dtype=np.int32), h=1e-6)
+                        mu_target=mu_target, mus=mus, L=L, g_fd=g, ks=np.asarray(ks, dtype=np.int32), h=1e-6,
+                        lanczos="full")
 
 
 if __name__ == "__main__":
