@@ -190,6 +190,22 @@ efe_status efe_set_hamiltonian(efe_ctx *ctx, const void *Psi, double t, const ef
 /* Y = Hbar X for the Hamiltonian last built (ncol <= norb columns). */
 efe_status efe_apply_H(efe_ctx *ctx, const void *X, void *Y, int32_t ncol, int64_t ld);
 
+/* For callers that cannot allocate memory (code under hipGraph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the same Y = Hbar X as
+ * efe_apply_H with no device or host allocation, no host synchronisation and no
+ * use of the context's work blocks.  X and Y: device, n_rows x ncol, PACKED
+ * (leading dimension = ncol), distinct, Y fully overwritten; the call returns
+ * once the kernels are enqueued on the context's stream (synchronise before
+ * reading Y).  The enrichment coupling's partial sums live in a static device
+ * array of EFE_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends and
+ * shared by every call on that GPU: calls that overlap on one GPU (other
+ * streams or contexts) race on it.  EFE_ERR_ARG if 520 n_enr_kept 2 ncol
+ * doubles exceed it (Na8, 48 directions: up to 84 orbitals per call);
+ * EFE_ERR_STATE without a Hamiltonian or when another GPU than the context's
+ * is current. */
+#define EFE_NOALLOC_SCRATCH_BYTES (32LL << 20)
+efe_status efe_apply_H_noalloc(efe_ctx *ctx, const void *X, void *Y, int32_t ncol);
+
 /* X <- exp(-i tau A) X, A = Hbar (op EFE_OP_H, Hamiltonian last built) or the
  * Loewdin position operator along x/y/z (no kinetic term, v = x_d), by the
  * adaptive Lanczos method of Sec. 2.6, one Krylov space per orbital, with the

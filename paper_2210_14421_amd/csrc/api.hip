@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -39,6 +40,7 @@ struct efe_ctx {
   efe::DevData d;
   efe_options opt{};
   uint64_t opt_gen = 0;     // bumped by efe_set_options: captured steps of older settings are stale
+  int device = 0;           // the GPU current at efe_setup (owns every buffer of the context)
   hipStream_t stream = nullptr;
   std::string err;
   int dtype = 0;
@@ -116,7 +118,37 @@ struct efe_batch {
   std::string err;
 };
 
+// Workspace of efe_apply_H_noalloc: the coupling's partial sums live in this
+// static device array (one copy per GPU, held until the process ends) instead of
+// memory the library allocates.  Host code never uses the array's name as a
+// device address: efe_setup resolves each GPU's copy with hipGetSymbolAddress once,
+// with that GPU current, and the entry point passes that address to the kernels.
+constexpr int64_t kNoAllocDoubles = EFE_NOALLOC_SCRATCH_BYTES / 8;
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// Address of this GPU's copy of the static workspace (resolved on first use per device).
+efe_status resolve_scratch(efe_ctx *ctx, int dev) {
+  if (dev < 0 || dev >= kMaxDevices) {
+    ctx->err = "device index beyond the supported range";
+    return EFE_ERR_ARG;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return EFE_OK;
+  void *p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    ctx->err = std::string("hipGetSymbolAddress of the static workspace: ") + hipGetErrorString(e);
+    return EFE_ERR_HIP;
+  }
+  g_scratch_ptr[dev] = (double *)p;
+  return EFE_OK;
+}
 
 using efe::DevData;
 
@@ -1333,6 +1365,15 @@ efe_status efe_setup(const efe_system *sys, const efe_options *opt, efe_ctx **ou
     st = efe::build_plan(*sys, ctx->plan);
     if (st != EFE_OK) ctx->err = ctx->plan.error;
     else st = build_device(ctx);
+    if (st == EFE_OK) {
+      hipError_t e = hipGetDevice(&ctx->device);
+      if (e != hipSuccess) {
+        ctx->err = std::string("hipGetDevice: ") + hip_err(e);
+        st = EFE_ERR_HIP;
+      } else {
+        st = resolve_scratch(ctx, ctx->device);
+      }
+    }
   } catch (const std::bad_alloc &) {
     st = EFE_ERR_ALLOC;
     ctx->err = "host allocation failed";
@@ -1435,6 +1476,35 @@ efe_status efe_apply_H(efe_ctx *ctx, const void *X, void *Y, int32_t ncol, int64
   EFE_TRY(sync(ctx, "apply_H"));
   timer_collect(ctx);
   return EFE_OK;
+}
+
+efe_status efe_apply_H_noalloc(efe_ctx *ctx, const void *X, void *Y, int32_t ncol) {
+  if (!ctx || !X || !Y || X == Y || ncol < 1 || ncol > ctx->norb) return EFE_ERR_ARG;
+  if (ctx->cells_mode != 0) {
+    ctx->err = "no Hamiltonian built (call efe_set_hamiltonian)";
+    return EFE_ERR_STATE;
+  }
+  const int ncolr = 2 * ncol;
+  const int64_t need = (int64_t)efe::k::kCoupleScratch * std::max(1, ctx->d.nk) * ncolr;
+  if (need > kNoAllocDoubles) {
+    ctx->err = "efe_apply_H_noalloc: the coupling needs " + std::to_string(need * 8) + " bytes of workspace, more than " +
+               std::to_string((long long)EFE_NOALLOC_SCRATCH_BYTES) + " (fewer columns per call)";
+    return EFE_ERR_ARG;
+  }
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != ctx->device || dev < 0 || dev >= kMaxDevices || !g_scratch_ptr[dev]) {
+    ctx->err = "efe_apply_H_noalloc: the context's GPU must be current";
+    return EFE_ERR_STATE;
+  }
+  const DevData &d = ctx->d;
+  if (ctx->dtype == 3)
+    efe::k::sf_apply(d, ctx->vq, 1, (const double *)X, (double *)Y, ncolr, ncolr, ctx->stream, nullptr);
+  else
+    efe::k::cell_apply(d, ctx->cells, ctx->dtype, (const double *)X, (double *)Y, ncolr, ncolr, ctx->stream, nullptr);
+  efe::k::couple_apply(d, ctx->G, ctx->Hbar_ee, (const double *)X, (double *)Y, ncolr, ncolr, g_scratch_ptr[dev],
+                       ctx->stream, nullptr);
+  return check_launch(ctx, "apply_H_noalloc");
 }
 
 efe_status lanczos_expm(efe_ctx *ctx, int32_t op, double tau, void *X, int32_t ncol, int64_t ld,

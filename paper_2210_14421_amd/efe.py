@@ -82,6 +82,7 @@ _set_options = _sig("efe_set_options", C.c_int32, [C.c_void_p, C.POINTER(EfeOpti
 _initial_state = _sig("efe_initial_state", C.c_int32, [C.c_void_p, _ip, _dp, C.c_double, C.c_void_p])
 _set_ham = _sig("efe_set_hamiltonian", C.c_int32, [C.c_void_p, C.c_void_p, C.c_double, C.POINTER(EfeField)])
 _apply_H = _sig("efe_apply_H", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int64])
+_apply_H_noalloc = _sig("efe_apply_H_noalloc", C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32])
 _lanczos = _sig("lanczos_expm", C.c_int32, [C.c_void_p, C.c_int32, C.c_double, C.c_void_p, C.c_int32, C.c_int64,
                                             _ip, _ip, _dp])
 _magnus = _sig("magnus_step", C.c_int32, [C.c_void_p, C.c_void_p, C.c_int64, C.c_double, C.c_double,
@@ -119,7 +120,7 @@ EXPORTED = ["efe_plan_create", "efe_plan_free", "efe_plan_sizes", "efe_plan_get"
             "efe_hartree", "dipole", "efe_enable_timing", "efe_get_timing", "efe_last_error",
             "magnus_step_graph", "efe_batch_create", "efe_batch_free", "efe_batch_error", "efe_batch_step",
             "magnus_adjoint", "dipole_adjoint", "magnus_step_extrap", "absorption_spectrum", "power_spectrum",
-            "efe_field_vjp"]
+            "efe_field_vjp", "efe_apply_H_noalloc"]
 
 
 class EfeError(RuntimeError):
@@ -369,6 +370,16 @@ class Context:
         Y = self.torch.empty_like(X) if Y is None else Y
         self._check(_apply_H(self._c, self._ptr(X, self.torch.complex128, self.n_rows),
                              self._ptr(Y, self.torch.complex128, self.n_rows), ncol, ncol))
+        return Y
+
+    def apply_H_noalloc(self, X, Y):
+        """Y = Hbar X enqueued with no allocation (efe_apply_H_noalloc): X, Y packed
+        (n_rows x ncol contiguous), distinct; synchronise before reading Y."""
+        torch = self.torch
+        if X.shape != Y.shape or X.data_ptr() == Y.data_ptr():
+            raise ValueError("X and Y: distinct blocks of the same shape")
+        self._check(_apply_H_noalloc(self._c, self._ptr(X, torch.complex128, self.n_rows),
+                                     self._ptr(Y, torch.complex128, self.n_rows), X.shape[1]))
         return Y
 
     def lanczos_expm(self, X, tau, op="H", k_force: Optional[Sequence[int]] = None):

@@ -1,0 +1,106 @@
+"""efe_apply_H_noalloc (no allocation, static per-GPU workspace) against efe_apply_H.
+
+Two calls in a row on each system, the second with fewer columns than the
+first (the workspace keeps the first call's partial sums: the second must not
+see them); each output must equal efe_apply_H's on the same input.  Systems:
+tiny (5 enrichment directions, 2 orbitals), lattice13 (52 directions: the
+general coupling path), Na2 (12 directions, 11 orbitals); then the error paths
+(no Hamiltonian, more columns than orbitals, a workspace beyond the limit).
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+def _boundary(spec):
+    nn = [spec.ncell[d] * spec.degree + 1 for d in range(3)]
+    g = np.arange(nn[0] * nn[1] * nn[2])
+    ix, iy, iz = g % nn[0], (g // nn[0]) % nn[1], g // (nn[0] * nn[1])
+    return (ix == 0) | (ix == nn[0] - 1) | (iy == 0) | (iy == nn[1] - 1) | (iz == 0) | (iz == nn[2] - 1)
+
+
+def _block(ctx, spec, ncol, seed):
+    """Seeded complex block with zero Dirichlet rows, unit columns."""
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((ctx.n_rows, ncol)) + 1j * rng.standard_normal((ctx.n_rows, ncol))
+    X[:ctx.n_nodes][_boundary(spec)] = 0.0
+    X /= np.linalg.norm(X, axis=0)
+    return torch.from_numpy(X).to("cuda")
+
+
+def _check(spec, name, ncols):
+    from paper_2210_14421_amd.efe import Context
+    print(f"no-alloc apply: {name}, columns per call {ncols}", flush=True)
+    ctx = Context(spec, kmax=8)
+    try:
+        ctx.set_hamiltonian(_block(ctx, spec, spec.norb, 1), 0.0)
+        for call, ncol in enumerate(ncols):
+            X = _block(ctx, spec, ncol, 10 + call)
+            Yref = ctx.apply_H(X)
+            Y = torch.full_like(X, float("nan"))
+            ctx.apply_H_noalloc(X, Y)
+            torch.cuda.synchronize()
+            err = float((Y - Yref).abs().max() / Yref.abs().max())
+            print(f"  call {call}: {ncol} columns, max |Y - Y_ref| / max |Y_ref| = {err:.2e}", flush=True)
+            assert bool(torch.isfinite(Y).all())
+            assert err <= 1e-14
+    finally:
+        ctx.close()
+
+
+def test_noalloc_tiny():
+    from workloads import tiny
+    _check(tiny(), "tiny", [2, 1])
+
+
+def test_noalloc_many_enrichment():
+    from workloads import lattice13
+    s = lattice13()
+    _check(s, "lattice13", [s.norb, 1])
+
+
+def test_noalloc_na2():
+    from workloads import na_cluster
+    _check(na_cluster(2, seed=2), "Na2", [11, 4])
+
+
+def test_noalloc_error_paths():
+    from workloads import tiny, lattice13
+    from paper_2210_14421_amd.efe import Context, EfeError, EFE_ERR_STATE, EFE_ERR_ARG
+    spec = tiny()
+    ctx = Context(spec, kmax=8)
+    try:
+        X = _block(ctx, spec, 2, 3)
+        with pytest.raises(EfeError) as e:
+            ctx.apply_H_noalloc(X, torch.zeros_like(X))          # no Hamiltonian yet
+        assert e.value.status == EFE_ERR_STATE
+        ctx.set_hamiltonian(X, 0.0)
+        X3 = torch.zeros((ctx.n_rows, 3), dtype=torch.complex128, device="cuda")
+        with pytest.raises(EfeError) as e:
+            ctx.apply_H_noalloc(X3, torch.zeros_like(X3))        # more columns than orbitals
+        assert e.value.status == EFE_ERR_ARG
+    finally:
+        ctx.close()
+    # 52 directions x 80 orbitals: 520 x 52 x 160 doubles exceed the 32 MiB workspace
+    big = dataclasses.replace(lattice13(), occ=np.full(80, 0.05))
+    print("no-alloc apply: workspace limit (lattice13, 80 orbitals)", flush=True)
+    ctx = Context(big, kmax=4)
+    try:
+        ctx.set_hamiltonian(_block(ctx, big, 80, 4), 0.0)
+        X = _block(ctx, big, 80, 5)
+        with pytest.raises(EfeError) as e:
+            ctx.apply_H_noalloc(X, torch.zeros_like(X))
+        assert e.value.status == EFE_ERR_ARG and "workspace" in str(e.value)
+        X = _block(ctx, big, 40, 6)                              # within the limit: equal to efe_apply_H
+        Y = torch.zeros_like(X)
+        ctx.apply_H_noalloc(X, Y)
+        torch.cuda.synchronize()
+        Yref = ctx.apply_H(X)
+        assert float((Y - Yref).abs().max() / Yref.abs().max()) <= 1e-14
+    finally:
+        ctx.close()
