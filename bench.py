@@ -22,7 +22,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "Magnus steps/s at Na8 (44 orbitals) + H.X roofline fraction, mixed vs plain FP64"
-PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
 HBM_GBS = 8000.0
 
 
@@ -109,16 +108,25 @@ def run_apply_mode(spec, dtype, n_apply):
     print(json.dumps({"mode": "apply", "dtype": dtype, "n_apply": n_apply, "calibration_copy_bytes": a.numel() * 8}))
 
 
-def roofline(spec, res, dtype):
-    """Cell-product kernel against the lower of its roofs, per launch.
+# arithmetic each stored-block type is multiplied in: the MFMA peak of that instruction
+MFMA_OF = {"f64": ("f64", 78.6), "f32": ("f32", 157.3), "bf16": ("f32", 157.3)}
+BLOCK_BYTES = {"f64": 8, "f32": 4, "bf16": 2}
 
-    One Hbar X is one launch per cell colour (parity class); a launch multiplies
-    the 216 x 216 blocks of its cells into the 88 real columns of the orbital
-    block: 2 * nloc^2 * ncol flops per cell.  The roof is the MFMA peak of the
-    block dtype or the arithmetic intensity times the HBM bandwidth, whichever
-    is lower; the achieved figure is flops or algorithmic bytes per launch over
-    the launch duration, the library's HIP-event time of all cell launches
-    divided by their number."""
+
+def roofline(spec, res, dtype):
+    """Cell-product kernel against the lower of its roofs, per Hbar X.
+
+    One Hbar X is one launch per cell colour (parity class); the launches multiply
+    the nloc x nloc blocks of every cell into the 2 N_orb real columns of the
+    orbital block: 2 nloc^2 (2 N_orb) flops per cell.  Algorithmic bytes of one
+    Hbar X are the unique ones: the orbital block read once, the result written
+    once and every stored block read once (the gathers of nodes shared between
+    cells and the read-modify-write of later colours are not algorithmic).  The
+    roof is the MFMA peak of the instruction the blocks are multiplied with, or the
+    arithmetic intensity times the HBM bandwidth, whichever is lower; the achieved
+    figure is flops or unique bytes over the time of all colour launches of one
+    Hbar X (HIP events of the library on its stream).  The per-launch figures with
+    the gathered bytes are kept as secondary keys."""
     P = spec.degree + 1
     nloc = P ** 3
     ncells = spec.ncell[0] * spec.ncell[1] * spec.ncell[2]
@@ -126,48 +134,89 @@ def roofline(spec, res, dtype):
     for n in spec.ncell:
         ncolour *= min(2, n)
     ncolr = 2 * spec.norb
-    flop_per_hx = 2.0 * nloc * nloc * ncolr * ncells
-    flop_per_launch = flop_per_hx / ncolour
-    n_hx = res["stage"]["n_hx"]
-    launch_s = res["stage"]["cell_hx"] * 1e-3 / (n_hx * ncolour)
-    tr = traffic_summary(dtype)
-    # algorithmic bytes of a launch: its cell blocks, the gathered orbital rows, the output rows
-    # written, and the output rows read where the colour is not the first to reach the node
-    # (node-in-cell incidences beyond the first: prod_d (nn_d + nc_d - 1) - n_nodes per Hbar X)
-    esz = {"f64": 8, "f32": 4, "bf16": 2}[dtype]
     nn = [n * spec.degree + 1 for n in spec.ncell]
+    n_nodes = nn[0] * nn[1] * nn[2]
+    flop_hx = 2.0 * nloc * nloc * ncolr * ncells
+    n_hx = res["stage"]["n_hx"]
+    hx_s = res["stage"]["cell_hx"] * 1e-3 / n_hx
+    esz = BLOCK_BYTES[dtype]
+    row = ncolr * 8
+    unique_hx = 2.0 * n_nodes * row + ncells * nloc * nloc * esz
+    ai = flop_hx / unique_hx
+    inst, mfma_peak = MFMA_OF[dtype]
+    if mfma_peak <= ai * HBM_GBS / 1e3:        # the MFMA roof is the lower one
+        bound, achieved, peak, unit = "mfma", flop_hx / hx_s / 1e12, mfma_peak, "TFLOP/s"
+    else:
+        bound, achieved, peak, unit = "hbm", unique_hx / hx_s / 1e9, HBM_GBS, "GB/s"
+    # per launch, with the gathered rows and the later colours' reads of Y
     incid = 1
     for a in range(3):
         incid *= nn[a] + spec.ncell[a] - 1
-    yreads = (incid - nn[0] * nn[1] * nn[2]) / ncolour
-    row = ncolr * 8
+    yreads = (incid - n_nodes) / ncolour
     cells_l = ncells / ncolour
     bytes_launch = cells_l * nloc * nloc * esz + 2 * cells_l * nloc * row + yreads * row
-    ai = flop_per_launch / bytes_launch
-    mfma_peak = PEAK_TFLOPS["f32" if dtype == "bf16" else dtype]    # BF16 blocks feed the FP32 MFMA
-    if mfma_peak <= ai * HBM_GBS / 1e3:        # the MFMA roof is the lower one
-        bound, achieved, peak, unit = "mfma", flop_per_launch / launch_s / 1e12, mfma_peak, "TFLOP/s"
-    else:
-        bound, achieved, peak, unit = "hbm", bytes_launch / launch_s / 1e9, HBM_GBS, "GB/s"
-    return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": None if tr is None else tr["total"],
-            "kernel": "k_cell_apply", "flop_per_launch": flop_per_launch, "bytes_per_launch": bytes_launch,
-            "arithmetic_intensity": ai, "tflops": flop_per_launch / launch_s / 1e12,
-            "launch_avg_us": launch_s * 1e6, "launches_per_hx": ncolour,
+    launch_s = hx_s / ncolour
+    tr = traffic_summary(dtype)
+    return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
+            "traffic": None if tr is None else tr["total"] * ncolour,
+            "kernel": "k_cell_apply", "mfma_instruction": inst, "flop_per_hx": flop_hx,
+            "unique_bytes_per_hx": unique_hx, "arithmetic_intensity": ai, "hx_us": hx_s * 1e6,
+            "tflops": flop_hx / hx_s / 1e12, "unique_GBps": unique_hx / hx_s / 1e9,
+            "launches_per_hx": ncolour, "launch_avg_us": launch_s * 1e6,
+            "per_launch_bytes_with_gathers": bytes_launch, "per_launch_GBps_with_gathers": bytes_launch / launch_s / 1e9,
             "hx_per_step": n_hx / max(1, len(res["k"])), "traffic_detail": tr}
 
 
-def cpu_baseline(spec, hx_per_step):
-    """Time the FP64 oracle's cell route of Hbar X over every cell and scale to steps/s.
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
-    The oracle model is set up untimed; the timed sample is one pass of
-    ``EFEModel.cell_block`` over all cells with the product into an 88-column
-    block (the cell part of one Hbar X), scaled by the Hbar X count per step
-    measured on the GPU.  Enrichment coupling, Lanczos vector work, densities
-    and Poisson solves are not included, so the figure is an upper bound of the
-    oracle's steps/s.
-    """
+
+def oracle_tiny_steps(nsteps=2):
+    """Complete oracle Magnus-2 steps of the tiny system (assembled route, plain
+    Lanczos), kicked from the stored ground state, at one BLAS thread and at all:
+    seconds per step for each."""
     import numpy as np
+    from threadpoolctl import threadpool_limits, threadpool_info
+    from oracle.model import EFEModel
+    from oracle.propagate import Propagator
+    from workloads import tiny
+    spec = tiny()
+    X0 = np.load(os.path.join(ROOT, "tests", "golden", "tiny_ground_state.npz"))["X"]
+    m = EFEModel(spec)
+    out = {}
+    allc = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    for label, nthr in (("1_thread", 1), ("all_cores", allc)):
+        with threadpool_limits(limits=nthr):
+            P = Propagator(m, X0, tol=spec.krylov_tol, kmax=spec.kmax)
+            P.kick(spec.kick, spec.kick_dir)
+            t0 = time.perf_counter()
+            for _ in range(nsteps):
+                P.step(spec.dt)
+            out[label] = {"threads": nthr, "s_per_step": (time.perf_counter() - t0) / nsteps,
+                          "steps_per_s": nsteps / (time.perf_counter() - t0)}
+    return out
+
+
+def cpu_baseline(spec, hx_per_step):
+    """The FP64 oracle timed on this host's cores.
+
+    value (Na8 steps/s, an ESTIMATE and an upper bound): one pass of the oracle's
+    cell route (`EFEModel.cell_block` over all 13,824 cells, each block multiplied
+    into the 88 real columns: the cell part of one Hbar X) is timed at all cores and
+    scaled by the Hbar X count per step measured on the GPU; the coupling, Lanczos
+    vector work, densities, Poisson solves and rebuilds are not in the sample.
+    measured: complete oracle Magnus steps of the tiny system at one thread and at
+    all cores.  reference_run: the complete Na8 oracle steps of the stored reference
+    (tests/golden/na8_step.npz), timed where that file was written."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
     from oracle.model import EFEModel
     t_setup = time.perf_counter()
     m = EFEModel(spec)
@@ -182,15 +231,22 @@ def cpu_baseline(spec, hx_per_step):
         nodes = mesh.cell_nodes(c)
         Y[nodes] += m.cell_block(c, v) @ X[nodes]
     dt = time.perf_counter() - t0
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        cores = os.cpu_count()
-    return {"value": 1.0 / (dt * hx_per_step), "unit": "steps/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"oracle cell part of one Hbar X ({mesh.n_cells} cells, {dt:.1f} s; set-up "
-                      f"{t_setup:.0f} s untimed), scaled to {hx_per_step:.0f} Hbar X per step; enrichment "
-                      f"coupling, vector work, density and Poisson excluded"}
+    cores = int(max([i.get("num_threads", 1) for i in threadpool_info()] + [1]))
+    out = {"value": 1.0 / (dt * hx_per_step), "unit": "steps/s", "cores": cores, "kind": "oracle",
+           "estimate": True, "cpu_model": _cpu_model(),
+           "sample": f"Na8 estimate (upper bound): oracle cell part of one Hbar X ({mesh.n_cells} cells, {dt:.1f} s "
+                     f"at {cores} threads; set-up {t_setup:.0f} s untimed) scaled to {hx_per_step:.0f} Hbar X per "
+                     f"step; coupling, vector work, densities, Poisson and rebuilds excluded"}
+    out["measured_tiny"] = oracle_tiny_steps()
+    ref = os.path.join(ROOT, "tests", "golden", "na8_step.npz")
+    if os.path.exists(ref):
+        z = np.load(ref)
+        if "step_seconds" in z:
+            out["reference_run_na8"] = {"s_per_step": [float(x) for x in z["step_seconds"]],
+                                        "threads": int(z["threads"]), "cpu_model": str(z["cpu_model"]),
+                                        "note": "complete matrix-free oracle steps (plain Lanczos) where the "
+                                                "stored Na8 reference was written"}
+    return out
 
 
 def batch_members():
