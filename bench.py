@@ -16,6 +16,7 @@ import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -25,7 +26,10 @@ METRIC = "Magnus steps/s at Na8 (44 orbitals) + H.X roofline fraction, mixed vs 
 HBM_GBS = 8000.0
 
 
-def run_gpu(spec, dtype, steps, warmup, kmax, scheme="pc", reorth="partial"):
+TUNE_CACHE = os.environ.get("EFE_TUNE_CACHE", os.path.join(tempfile.gettempdir(), "efe_tune.json"))
+
+
+def run_gpu(spec, dtype, steps, warmup, kmax, scheme="pc", reorth="partial", autotune=True):
     import numpy as np
     import torch
     from paper_2210_14421_amd.efe import Context
@@ -34,6 +38,9 @@ def run_gpu(spec, dtype, steps, warmup, kmax, scheme="pc", reorth="partial"):
     Psi = ctx.initial_state()
     ctx.lanczos_expm(Psi, -spec.kick, op="z")
     ctx.set_hamiltonian(Psi, 0.0)
+    tune = ctx.autotune(cache=TUNE_CACHE) if autotune else None
+    if tune is not None:
+        print(f"[bench] {dtype}: autotuned cell products: {tune}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     setup_s = time.time() - t0
     print(f"[bench] {dtype}: setup + initial state + kick {setup_s:.1f} s", file=sys.stderr, flush=True)
@@ -63,7 +70,7 @@ def run_gpu(spec, dtype, steps, warmup, kmax, scheme="pc", reorth="partial"):
     G = Psi.conj().T @ Psi
     orth = float((G - torch.eye(spec.norb, dtype=G.dtype, device=G.device)).abs().max())
     ctx.close()
-    return dict(wall=wall, stage=stage, k=ks, mu=mus, orth=orth, setup_s=setup_s)
+    return dict(wall=wall, stage=stage, k=ks, mu=mus, orth=orth, setup_s=setup_s, tune=tune)
 
 
 def traffic_summary(dtype):
@@ -495,7 +502,7 @@ def main():
                                f"dt {spec.dt}, Krylov tol {spec.krylov_tol}, z kick {spec.kick}",
                    "precision": "FP64 products, FP64 Lanczos",
                    "lanczos_reorthogonalisation": "partial (Simon's omega recurrence)"},
-        "roofline": roof,
+        "roofline": roof, "autotune": res["tune"],
         "stage_ms_per_step": {k: v / args.steps for k, v in res["stage"].items() if k != "n_hx"},
         "krylov_k_mean": res["k"], "orthonormality_error": res["orth"],
     }
@@ -508,7 +515,7 @@ def main():
             np.max(np.linalg.norm(np.array(res["mu"]), axis=1))
         out["mixed"] = {"dtype": "f32 products, FP64 Lanczos", "value": mv, "unit": "steps/s",
                         "ms_per_step": 1e3 * mres["wall"] / args.steps, "speedup_vs_f64": mv / value,
-                        "roofline": mroof, "dipole_rel_diff_vs_f64": float(dmu),
+                        "roofline": mroof, "autotune": mres["tune"], "dipole_rel_diff_vs_f64": float(dmu),
                         "stage_ms_per_step": {k: v / args.steps for k, v in mres["stage"].items() if k != "n_hx"}}
     if not args.no_mixed:
         bres = run_gpu(spec, "bf16", args.steps, args.warmup, args.kmax)
@@ -519,7 +526,7 @@ def main():
             np.max(np.linalg.norm(np.array(res["mu"]), axis=1))
         out["mixed_bf16"] = {"dtype": "bf16 cell blocks, f32 products, FP64 Lanczos", "value": bv, "unit": "steps/s",
                              "ms_per_step": 1e3 * bres["wall"] / args.steps, "speedup_vs_f64": bv / value,
-                             "roofline": broof, "dipole_rel_diff_vs_f64": float(dmu),
+                             "roofline": broof, "autotune": bres["tune"], "dipole_rel_diff_vs_f64": float(dmu),
                              "stage_ms_per_step": {k: v / args.steps for k, v in bres["stage"].items() if k != "n_hx"}}
     if not args.no_extrap:
         # one exponential per step: the midpoint Hamiltonian at the density extrapolated from three steps

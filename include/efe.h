@@ -364,6 +364,22 @@ efe_status efe_hartree(efe_ctx *ctx, const double *rho_q, double *phi, int32_t *
 /* Electronic dipole mu_d = sum_q W_q x_d(q) rho(q) of Psi (host output mu[3]). */
 efe_status dipole(efe_ctx *ctx, const void *Psi, int64_t ld, double mu[3]);
 
+/* Autotuner of the cell products (Sec. 2.3: the dense cell blocks applied as batched
+ * products over the orbital block).  Times, on the context's own operator and the
+ * orbitals of the last efe_set_hamiltonian, every kernel shape available for its
+ * block type (pipeline depth and k-rows per chunk of the dense MFMA kernel; for
+ * FP64 blocks also the sum-factorised application of the same operator), checks
+ * each result against the default shape's (the dense shapes add the terms in the
+ * same order: identical bits; sum factorisation within 1e-11 in the 2-norm),
+ * and keeps the fastest for every later product of the context.  cache_path (may
+ * be NULL): a JSON file of earlier choices keyed by GPU, degree, quadrature, columns,
+ * block type, cells and enrichment directions; a cached choice is taken without
+ * timing unless flags has EFE_TUNE_FORCE, and a new one is written back.  report
+ * (host, may be NULL): "choice=<name> cached=<0|1> <name>=<us per Hbar X> ...".
+ * EFE_ERR_STATE without a Hamiltonian; EFE_ERR_ARG if the cache cannot be written. */
+enum { EFE_TUNE_FORCE = 1 };
+efe_status efe_autotune(efe_ctx *ctx, const char *cache_path, int32_t flags, char *report, int32_t report_len);
+
 /* Device time of the last call's stages in ms: [0] Hbar X cell products,
  * [1] enrichment coupling, [2] Lanczos vector work, [3] tridiagonal
  * exponentials, [4] density, [5] Poisson, [6] rebuild, [7] total; and the

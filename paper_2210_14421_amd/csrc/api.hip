@@ -7,7 +7,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <memory>
+#include <sstream>
 #include <mutex>
 #include <new>
 #include <string>
@@ -41,6 +44,7 @@ struct efe_ctx {
   efe_options opt{};
   uint64_t opt_gen = 0;     // bumped by efe_set_options: captured steps of older settings are stale
   int device = 0;           // the GPU current at efe_setup (owns every buffer of the context)
+  int cell_variant = 0;     // cell-product kernel shape chosen by efe_autotune (kSFVariant: sum factorisation)
   hipStream_t stream = nullptr;
   std::string err;
   int dtype = 0;
@@ -477,6 +481,17 @@ efe_status build_device(efe_ctx *ctx) {
 }
 
 // --------------------------------------------------------------------------- building blocks
+constexpr int kSFVariant = 100;   // cell_variant of an FP64 context that applies the blocks by sum factorisation
+
+// Cell part of Y = A X with the kernel shape of the context (efe_autotune) or the given variant.
+void cell_products(efe_ctx *ctx, const double *X, double *Y, int ncolr, int64_t ldr, hipStream_t s, const int *any,
+                   int variant = -1) {
+  const DevData &d = ctx->d;
+  const int v = variant >= 0 ? variant : ctx->cell_variant;
+  if (ctx->dtype == 3 || v == kSFVariant) efe::k::sf_apply(d, ctx->vq, ctx->cells_mode == 0 ? 1 : 0, X, Y, ncolr, ldr, s, any);
+  else efe::k::cell_apply(d, ctx->cells, ctx->dtype, X, Y, ncolr, ldr, s, any, v);
+}
+
 // Y = A X with the operator currently held in the cell blocks (rows with stride ldr doubles)
 efe_status apply_op(efe_ctx *ctx, const double *X, double *Y, int ncolr, int64_t ldr, const int *any = nullptr) {
   const DevData &d = ctx->d;
@@ -486,8 +501,7 @@ efe_status apply_op(efe_ctx *ctx, const double *X, double *Y, int ncolr, int64_t
     return EFE_ERR_ARG;
   }
   tstart(ctx, 0);
-  if (ctx->dtype == 3) efe::k::sf_apply(d, ctx->vq, ctx->cells_mode == 0 ? 1 : 0, X, Y, ncolr, ldr, s, any);
-  else efe::k::cell_apply(d, ctx->cells, ctx->dtype, X, Y, ncolr, ldr, s, any);
+  cell_products(ctx, X, Y, ncolr, ldr, s, any);
   tstop(ctx, 0);
   tstart(ctx, 1);
   efe::k::couple_apply(d, ctx->G, ctx->Hbar_ee, X, Y, ncolr, ldr, ctx->couple_scr, s, any);
@@ -1498,10 +1512,7 @@ efe_status efe_apply_H_noalloc(efe_ctx *ctx, const void *X, void *Y, int32_t nco
     return EFE_ERR_STATE;
   }
   const DevData &d = ctx->d;
-  if (ctx->dtype == 3)
-    efe::k::sf_apply(d, ctx->vq, 1, (const double *)X, (double *)Y, ncolr, ncolr, ctx->stream, nullptr);
-  else
-    efe::k::cell_apply(d, ctx->cells, ctx->dtype, (const double *)X, (double *)Y, ncolr, ncolr, ctx->stream, nullptr);
+  cell_products(ctx, (const double *)X, (double *)Y, ncolr, ncolr, ctx->stream, nullptr);
   efe::k::couple_apply(d, ctx->G, ctx->Hbar_ee, (const double *)X, (double *)Y, ncolr, ncolr, g_scratch_ptr[dev],
                        ctx->stream, nullptr);
   return check_launch(ctx, "apply_H_noalloc");
@@ -1884,6 +1895,151 @@ efe_status efe_field_vjp(const efe_field *f, int64_t n, const double *t, const d
       grad[m + k] += f->A[k] * t[i] * cs * env;     // dE/dw_k
       grad[2 * m + k] += f->A[k] * cs * env;        // dE/dphi_k
     }
+  }
+  return EFE_OK;
+}
+
+efe_status efe_autotune(efe_ctx *ctx, const char *cache_path, int32_t flags, char *report, int32_t report_len) {
+  if (!ctx || (flags & ~EFE_TUNE_FORCE) || (report && report_len < 1)) return EFE_ERR_ARG;
+  if (ctx->cells_mode != 0) {
+    ctx->err = "efe_autotune needs a Hamiltonian (call efe_set_hamiltonian)";
+    return EFE_ERR_STATE;
+  }
+  const DevData &d = ctx->d;
+  hipStream_t s = ctx->stream;
+  // candidates: the pipeline variants of the dense kernel for this block type, and for FP64
+  // blocks the same operator by sum factorisation; a sum-factorised context has one shape
+  std::vector<int> cand;
+  std::vector<std::string> names;
+  char nm[64];
+  if (ctx->dtype == 3) {
+    cand.push_back(0);
+    names.push_back("sum_factorised");
+  } else {
+    const size_t esz = ctx->dtype == 0 ? 8 : (ctx->dtype == 1 ? 4 : 2);
+    const int nv = efe::k::cell_variant_count(d.g.nloc, esz);
+    for (int v = 0; v < nv; ++v) {
+      efe::k::cell_variant_name(v, nm, sizeof(nm));
+      cand.push_back(v);
+      names.push_back(nm);
+    }
+    if (ctx->dtype == 0 && efe::k::sf_supported(d.g) && efe::k::sf_init(d.g) == 0) {
+      cand.push_back(kSFVariant);
+      names.push_back("sum_factorised");
+    }
+  }
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, ctx->device));
+  std::ostringstream key;
+  key << prop.gcnArchName << " cu" << prop.multiProcessorCount << " p" << d.g.p << " nloc" << d.g.nloc << " q"
+      << d.g.qc << "," << d.g.qe << " ncolr" << ctx->ncolr << " dtype" << ctx->dtype << " cells"
+      << ctx->plan.n_cells << " enr" << d.nk;
+  const std::string k = key.str();
+  std::vector<std::string> lines;   // entries of the cache file, one per line
+  int chosen = -1;
+  if (cache_path && *cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    const std::string head = "\"" + k + "\":";
+    while (std::getline(in, line)) {
+      if (line.empty() || line[0] != '"') continue;
+      while (!line.empty() && (line.back() == ',' || line.back() == ' ' || line.back() == '\r')) line.pop_back();
+      if (line.compare(0, head.size(), head) == 0) {
+        const std::string tag = "\"choice\": \"";
+        const size_t a = line.find(tag);
+        if (a != std::string::npos) {
+          const size_t b = line.find('"', a + tag.size());
+          const std::string nmc = line.substr(a + tag.size(), b - a - tag.size());
+          for (size_t i = 0; i < names.size(); ++i)
+            if (names[i] == nmc) chosen = (int)i;
+        }
+        continue;   // replaced below if tuned again
+      }
+      lines.push_back(line);
+    }
+  }
+  std::ostringstream rep;
+  if (chosen >= 0 && !(flags & EFE_TUNE_FORCE)) {
+    rep << "choice=" << names[chosen] << " cached=1";
+  } else {
+    // time every candidate on the context's own operator and orbitals (X0 holds the orbitals
+    // of the last efe_set_hamiltonian), each checked against the default shape's result
+    const int ncolr = ctx->ncolr;
+    double *X = ctx->X0, *Y = ctx->X1, *Yref = ctx->Q;
+    const int64_t n = ctx->plan.n_nodes * ncolr;   // the cell products write the classical rows only
+    // squared 2-norm of a block on the device (fixed-order partial sums)
+    auto norm2 = [&](const double *a, double &out) -> efe_status {
+      const int nb = efe::k::dot_partials(a, a, n, ctx->red, s);
+      efe::k::reduce_partials(ctx->red, nb, 1, ctx->small, s);
+      HIP_TRY(hipMemcpyAsync(&out, ctx->small, sizeof(double), hipMemcpyDeviceToHost, s));
+      return sync(ctx, "autotune check");
+    };
+    cell_products(ctx, X, Yref, ncolr, ncolr, s, nullptr, cand[0]);
+    double rr = 0.0;
+    EFE_TRY(norm2(Yref, rr));
+    std::vector<double> tus(cand.size(), 0.0);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const int reps = 3;
+    int best = 0;
+    for (size_t i = 0; i < cand.size(); ++i) {
+      cell_products(ctx, X, Y, ncolr, ncolr, s, nullptr, cand[i]);   // warm-up and check
+      efe::k::axpby(Y, Yref, 1.0, -1.0, Y, n, s);
+      double dd = 0.0;
+      EFE_TRY(norm2(Y, dd));
+      const double tol2 = cand[i] == kSFVariant ? 1e-22 * rr : 0.0;   // dense shapes give the same bits
+      if (!(dd <= tol2)) {
+        rep << " " << names[i] << "=rejected(" << std::sqrt(dd / (rr > 0 ? rr : 1.0)) << ")";
+        tus[i] = -1.0;
+        continue;
+      }
+      HIP_TRY(hipEventRecord(e0, s));
+      for (int r = 0; r < reps; ++r) cell_products(ctx, X, Y, ncolr, ncolr, s, nullptr, cand[i]);
+      HIP_TRY(hipEventRecord(e1, s));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      tus[i] = 1e3 * ms / reps;
+      if (tus[best] < 0.0 || tus[i] < tus[best]) best = (int)i;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    EFE_TRY(check_launch(ctx, "autotune"));
+    chosen = best;
+    std::ostringstream ent;
+    ent << "\"" << k << "\": {\"choice\": \"" << names[chosen] << "\", \"times_us\": {";
+    bool first = true;
+    for (size_t i = 0; i < cand.size(); ++i) {
+      if (tus[i] < 0.0) continue;
+      ent << (first ? "" : ", ") << "\"" << names[i] << "\": " << tus[i];
+      first = false;
+    }
+    ent << "}}";
+    rep << " choice=" << names[chosen] << " cached=0";
+    for (size_t i = 0; i < cand.size(); ++i)
+      if (tus[i] >= 0.0) rep << " " << names[i] << "=" << tus[i];
+    if (cache_path && *cache_path) {
+      lines.push_back(ent.str());
+      std::ofstream out(cache_path, std::ios::trunc);
+      out << "{\n";
+      for (size_t i = 0; i < lines.size(); ++i) out << lines[i] << (i + 1 < lines.size() ? ",\n" : "\n");
+      out << "}\n";
+      if (!out) {
+        ctx->err = std::string("efe_autotune: cannot write ") + cache_path;
+        return EFE_ERR_ARG;
+      }
+    }
+  }
+  const int v = cand[chosen];
+  if (ctx->dtype != 3 && v != ctx->cell_variant) {
+    ctx->cell_variant = v;
+    drop_graph(ctx);     // captured steps hold the previous kernel shape
+    ++ctx->opt_gen;
+  }
+  if (report) {
+    const std::string r = rep.str();
+    std::snprintf(report, (size_t)report_len, "%s", r.c_str());
   }
   return EFE_OK;
 }

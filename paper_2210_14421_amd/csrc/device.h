@@ -109,7 +109,11 @@ void hee_reduce(const DevData &d, const double *hee_part, int kinetic, double *H
 // raises the dynamic LDS limit of the cell-product kernels for cells of nloc nodes; 0 on success
 int cell_apply_init(int nloc);
 void cell_apply(const DevData &d, const void *cells, int dtype, const double *X, double *Y, int ncolr, int64_t ldr,
-                hipStream_t s, const int *any = nullptr);
+                hipStream_t s, const int *any = nullptr, int variant = 0);
+// pipeline variants of the cell products that fit the LDS for cells of nloc nodes and
+// blocks of esz bytes (all give the same bits; variant 0 is the default), and their names
+int cell_variant_count(int nloc, size_t esz);
+void cell_variant_name(int v, char *out, int len);
 // sum-factorised cell products (FP64, no stored blocks): Y = sum_c P_c^T Hbar_c P_c X from the
 // potential at the quadrature points (vq) and, with kinetic, the kinetic term
 bool sf_supported(const Geom &g);

@@ -3,6 +3,8 @@
 // 16x16x4 MFMA (FP64, or FP32 blocks with FP32 accumulation).
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
+
 #include "common.h"
 
 namespace efe {
@@ -53,9 +55,11 @@ template <> struct Mfma<float> {
   static __device__ __forceinline__ int row(int kr, int r) { return 4 * kr + r; }
 };
 
-// One workgroup of 8 waves per (cell, chunk of 96 columns); two workgroups
-// share a CU.  Operands pass through LDS in chunks of 8 k-rows, three chunks in
-// flight: the chunk's rows of the symmetric cell block (contiguous in memory)
+// One workgroup of 8 waves per (cell, chunk of 96 columns).  Operands pass
+// through LDS in chunks of KC k-rows, NS chunks in flight (the defaults, 8 and 3,
+// let two workgroups share a CU; the other (NS, KC) pairs are the autotuner's
+// candidates, and all of them add the k terms in the same order, so every
+// variant gives the same bits): the chunk's rows of the symmetric cell block (contiguous in memory)
 // and the gathered rows of X are copied global -> LDS by the direct-to-LDS
 // loads (global_load_lds_dwordx4, 16 B per lane at LDS base + 16 * lane), so
 // no registers hold data in flight.  Every wave issues the same number of
@@ -66,10 +70,8 @@ template <> struct Mfma<float> {
 constexpr int kCellWaves = 8;
 constexpr int kCellNT = 3;                  // N tiles per wave
 constexpr int kCellCols = 2 * kCellNT * 16; // columns per workgroup
-constexpr int kCellKC = 8;                  // k-rows per chunk
-constexpr int kCellNS = 3;                  // chunks in flight
 constexpr int kCellLDX = 112;               // LDS row stride of X (doubles): the 4 rows of a B read hit disjoint banks
-constexpr int kCellXStage = kCellKC * kCellLDX * 8;
+template <int KC> constexpr int x_stage() { return KC * kCellLDX * 8; }
 
 // s_waitcnt with vmcnt = N and no wait on the other counters (gfx9 encoding)
 template <int N>
@@ -85,36 +87,39 @@ __device__ __forceinline__ void copy16_to_lds(const void *src, void *lds_base) {
   __builtin_amdgcn_global_load_lds((gptr_t)src, (lptr_t)lds_base, 16, 0, 0);
 }
 
-template <typename T>
+template <typename T, int KC>
 struct CellChunk {
   // A-chunk copies per wave per chunk, sized for the largest cell (nloc <= 384)
-  static constexpr int kAIns = (kCellKC * kApplyMaxLoc * (int)sizeof(T) + 1024 * kCellWaves - 1) / (1024 * kCellWaves);
-  static constexpr int kPer = kAIns + kCellKC / kCellWaves;   // copies per wave per chunk
+  static constexpr int kAIns = (KC * kApplyMaxLoc * (int)sizeof(T) + 1024 * kCellWaves - 1) / (1024 * kCellWaves);
+  static constexpr int kXIns = (KC + kCellWaves - 1) / kCellWaves;   // X-row copies per wave per chunk
+  static constexpr int kPer = kAIns + kXIns;                         // copies per wave per chunk
 };
 
-inline size_t cell_lds_bytes(int nloc, size_t esz) {
-  const size_t aseg = (kCellKC * nloc * esz + 1023) / 1024;
-  return kCellNS * (aseg * 1024 + kCellXStage) + 1024;
+inline size_t cell_lds_bytes(int nloc, size_t esz, int ns, int kc) {
+  const size_t aseg = ((size_t)kc * nloc * esz + 1023) / 1024;
+  return (size_t)ns * (aseg * 1024 + (size_t)kc * kCellLDX * 8) + 1024;
 }
 
-template <typename T, int CMT>
+template <typename T, int CMT, int NS, int KC>
 __global__ void __launch_bounds__(kCellWaves * 64) __attribute__((amdgpu_waves_per_eu(CMT <= 4 ? 4 : 2)))
 k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, const T *__restrict__ cells,
              const double *__restrict__ X, double *__restrict__ Y, int ncolr, int64_t ldr, const int *__restrict__ any) {
+  static_assert(KC % 4 == 0 && NS >= 2, "chunks of whole k-steps, at least one in flight");
   if (any && *any == 0) return;
   typedef typename Mfma<T>::C C;
   typedef typename Mfma<T>::Acc Acc;
-  constexpr int kAIns = CellChunk<T>::kAIns, kPer = CellChunk<T>::kPer;
+  constexpr int kAIns = CellChunk<T, KC>::kAIns, kXIns = CellChunk<T, KC>::kXIns, kPer = CellChunk<T, KC>::kPer;
+  constexpr int kXStage = x_stage<KC>();
   __shared__ int64_t rowoff[kApplyMaxLoc];
   __shared__ unsigned char first[kApplyMaxLoc];   // this cell's colour is the first to reach the node
   extern __shared__ __attribute__((aligned(16))) unsigned char cell_sm[];
   const Geom &g = d.g;
   const int nloc = g.nloc;
-  const int abytes = kCellKC * nloc * (int)sizeof(T);
+  const int abytes = KC * nloc * (int)sizeof(T);
   const int aseg = (abytes + 1023) / 1024;
-  unsigned char *As = cell_sm;                                   // kCellNS * aseg KB
-  unsigned char *Xs = cell_sm + kCellNS * aseg * 1024;           // kCellNS * kCellXStage
-  unsigned char *junk = Xs + kCellNS * kCellXStage;              // 1 KB target of padding copies
+  unsigned char *As = cell_sm;                                   // NS * aseg KB
+  unsigned char *Xs = cell_sm + NS * aseg * 1024;                // NS * kXStage
+  unsigned char *junk = Xs + NS * kXStage;                       // 1 KB target of padding copies
   const int ci = blockIdx.x;
   const int col0 = blockIdx.y * kCellCols;
   const int wcol = ncolr - col0 < kCellCols ? ncolr - col0 : kCellCols;   // columns of this chunk (even)
@@ -139,13 +144,13 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
     first[l] = later ? 0 : 1;
   }
   // X stages start zeroed: pad columns are never copied into
-  for (int i = tid; i < kCellNS * kCellXStage / 8; i += kCellWaves * 64) ((double *)Xs)[i] = 0.0;
+  for (int i = tid; i < NS * kXStage / 8; i += kCellWaves * 64) ((double *)Xs)[i] = 0.0;
   __syncthreads();
   const unsigned char *Ag = (const unsigned char *)(cells + (int64_t)(slot0 + ci) * g.cstride);   // 16-byte aligned
   const int64_t ablock = g.cstride * (int64_t)sizeof(T);   // padded block: copies never cross into the next one
-  const int nchunk = (nloc + kCellKC - 1) / kCellKC;
+  const int nchunk = (nloc + KC - 1) / KC;
   auto issue = [&](int kc) {
-    const int st = kc % kCellNS;
+    const int st = kc % NS;
     const int64_t abase = (int64_t)kc * abytes;
 #pragma unroll
     for (int i = 0; i < kAIns; ++i) {
@@ -155,11 +160,11 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
       copy16_to_lds(Ag + (ok ? off : 0), seg < aseg ? As + (st * aseg + seg) * 1024 : junk);
     }
 #pragma unroll
-    for (int i = 0; i < kCellKC / kCellWaves; ++i) {
+    for (int i = 0; i < kXIns; ++i) {
       const int r = wave + kCellWaves * i;
-      const int k = kc * kCellKC + r;
-      if (k < nloc) {
-        if (2 * lane < wcol) copy16_to_lds(X + rowoff[k] + col0 + 2 * lane, Xs + st * kCellXStage + r * kCellLDX * 8);
+      const int k = kc * KC + r;
+      if (r < KC && k < nloc) {
+        if (2 * lane < wcol) copy16_to_lds(X + rowoff[k] + col0 + 2 * lane, Xs + st * kXStage + r * kCellLDX * 8);
       } else {
         copy16_to_lds(X, junk);
       }
@@ -172,24 +177,24 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
 #pragma unroll
     for (int j = 0; j < kCellNT; ++j) acc[i][j] = Acc{0, 0, 0, 0};
 #pragma unroll
-  for (int c = 0; c < kCellNS - 1; ++c)
+  for (int c = 0; c < NS - 1; ++c)
     if (c < nchunk) issue(c);
   for (int kc = 0; kc < nchunk; ++kc) {
     // this wave's copies of chunk kc are done once at most (chunks issued after it) * kPer remain
-    if (kc + 1 < nchunk) wait_vmcnt<kPer * (kCellNS - 2)>();
+    if (kc + NS - 2 < nchunk) wait_vmcnt<kPer * (NS - 2)>();
     else wait_vmcnt<0>();
     __builtin_amdgcn_s_barrier();
-    if (kc + kCellNS - 1 < nchunk) issue(kc + kCellNS - 1);
-    const int st = kc % kCellNS;
+    if (kc + NS - 1 < nchunk) issue(kc + NS - 1);
+    const int st = kc % NS;
     const T *Al = (const T *)(As + st * aseg * 1024);
-    const double *Xl = (const double *)(Xs + st * kCellXStage);
+    const double *Xl = (const double *)(Xs + st * kXStage);
     // per k-step: the step's operands first (one LDS wait), then its MFMAs.  Rows m past
     // nloc read neighbouring LDS words: they only reach output rows that are never stored.
     // k-rows past nloc (last chunk) are zeroed, as their X rows are not copied.
 #pragma unroll
-    for (int s4 = 0; s4 < kCellKC / 4; ++s4) {
+    for (int s4 = 0; s4 < KC / 4; ++s4) {
       const int kl = s4 * 4 + kr;
-      const bool kok = kc * kCellKC + kl < nloc;
+      const bool kok = kc * KC + kl < nloc;
       C b[kCellNT], a[CMT];
 #pragma unroll
       for (int j = 0; j < kCellNT; ++j) b[j] = (C)Xl[kl * kCellLDX + (nh * kCellNT + j) * 16 + cl];
@@ -226,53 +231,107 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
   }
 }
 
-template <typename T, int CMT>
+template <typename T, int CMT, int NS, int KC>
 void launch_apply_m(const DevData &d, const T *cells, const double *X, double *Y, int ncolr, int64_t ldr,
                     hipStream_t s, const int *any) {
   const unsigned ny = (unsigned)((ncolr + kCellCols - 1) / kCellCols);
-  const size_t lds = cell_lds_bytes(d.g.nloc, sizeof(T));
+  const size_t lds = cell_lds_bytes(d.g.nloc, sizeof(T), NS, KC);
   for (int c = 0; c < 8; ++c) {
     const int cnt = d.colour_off[c + 1] - d.colour_off[c];
     if (cnt == 0) continue;
     const int *list = d.colour_cells + d.colour_off[c];
-    hipLaunchKernelGGL((k_cell_apply<T, CMT>), dim3((unsigned)cnt, ny), dim3(kCellWaves * 64), lds, s, d, list,
-                       d.colour_off[c], cells, X, Y, ncolr, ldr, any);
+    hipLaunchKernelGGL((k_cell_apply<T, CMT, NS, KC>), dim3((unsigned)cnt, ny), dim3(kCellWaves * 64), lds, s, d,
+                       list, d.colour_off[c], cells, X, Y, ncolr, ldr, any);
+  }
+}
+
+// Pipeline variants (chunks in flight NS, k-rows per chunk KC) for cells of up to 256
+// nodes (degree <= 5); variant 0 is the default.  Degree 6 cells use the default only.
+constexpr int kCellVariants = 6;
+constexpr int kVarNS[kCellVariants] = {3, 2, 4, 2, 6, 4};
+constexpr int kVarKC[kCellVariants] = {8, 8, 4, 16, 4, 8};
+
+template <typename T, int CMT, int V>
+void launch_v(const DevData &d, const T *cells, const double *X, double *Y, int ncolr, int64_t ldr, hipStream_t s,
+              const int *any) {
+  launch_apply_m<T, CMT, kVarNS[V], kVarKC[V]>(d, cells, X, Y, ncolr, ldr, s, any);
+}
+
+template <typename T, int CMT>
+void launch_variant(int v, const DevData &d, const T *cells, const double *X, double *Y, int ncolr, int64_t ldr,
+                    hipStream_t s, const int *any) {
+  switch (v) {
+    case 1: launch_v<T, CMT, 1>(d, cells, X, Y, ncolr, ldr, s, any); break;
+    case 2: launch_v<T, CMT, 2>(d, cells, X, Y, ncolr, ldr, s, any); break;
+    case 3: launch_v<T, CMT, 3>(d, cells, X, Y, ncolr, ldr, s, any); break;
+    case 4: launch_v<T, CMT, 4>(d, cells, X, Y, ncolr, ldr, s, any); break;
+    case 5: launch_v<T, CMT, 5>(d, cells, X, Y, ncolr, ldr, s, any); break;
+    default: launch_v<T, CMT, 0>(d, cells, X, Y, ncolr, ldr, s, any); break;
   }
 }
 
 template <typename T>
 void launch_apply(const DevData &d, const T *cells, const double *X, double *Y, int ncolr, int64_t ldr, hipStream_t s,
-                  const int *any) {
+                  const int *any, int v) {
   const int nmt = (d.g.nloc + 15) / 16;     // M tiles per cell; wave group w >> 1 takes ceil(nmt / 4)
-  if (nmt <= 8) launch_apply_m<T, 2>(d, cells, X, Y, ncolr, ldr, s, any);
-  else if (nmt <= 16) launch_apply_m<T, 4>(d, cells, X, Y, ncolr, ldr, s, any);
-  else launch_apply_m<T, 6>(d, cells, X, Y, ncolr, ldr, s, any);
+  if (nmt <= 8) launch_variant<T, 2>(v, d, cells, X, Y, ncolr, ldr, s, any);
+  else if (nmt <= 16) launch_variant<T, 4>(v, d, cells, X, Y, ncolr, ldr, s, any);
+  else launch_apply_m<T, 6, 3, 8>(d, cells, X, Y, ncolr, ldr, s, any);
+}
+
+template <typename T, int CMT, int V>
+int set_lds_v(size_t esz, int nloc) {
+  return (int)hipFuncSetAttribute((const void *)k_cell_apply<T, CMT, kVarNS[V], kVarKC[V]>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)cell_lds_bytes(nloc, esz, kVarNS[V], kVarKC[V]));
+}
+
+template <typename T, int CMT>
+int set_lds_all(int nloc) {
+  const size_t e = sizeof(T);
+  return set_lds_v<T, CMT, 0>(e, nloc) | set_lds_v<T, CMT, 1>(e, nloc) | set_lds_v<T, CMT, 2>(e, nloc) |
+         set_lds_v<T, CMT, 3>(e, nloc) | set_lds_v<T, CMT, 4>(e, nloc) | set_lds_v<T, CMT, 5>(e, nloc);
 }
 
 }  // namespace
 
 namespace k {
 
+int cell_variant_count(int nloc, size_t esz) {
+  if ((nloc + 15) / 16 > 16) return 1;
+  int n = 0;
+  while (n < kCellVariants && cell_lds_bytes(nloc, esz, kVarNS[n], kVarKC[n]) <= 156 * 1024) ++n;   // + static LDS
+  return n;
+}
+
+void cell_variant_name(int v, char *out, int len) {
+  if (v < 0 || v >= kCellVariants) v = 0;
+  snprintf(out, len, "dense_ns%d_kc%d", kVarNS[v], kVarKC[v]);
+}
+
 int cell_apply_init(int nloc) {
-  const size_t l64 = cell_lds_bytes(nloc, 8), l32 = cell_lds_bytes(nloc, 4), l16 = cell_lds_bytes(nloc, 2);
   int st = 0;
-  st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<double, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l64);
-  st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<double, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l64);
-  st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<double, 6>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l64);
-  st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<float, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l32);
-  st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<float, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l32);
-  st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<float, 6>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l32);
-  st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<uint16_t, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l16);
-  st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<uint16_t, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l16);
-  st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<uint16_t, 6>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l16);
+  const int nmt = (nloc + 15) / 16;
+  if (nmt <= 8) {
+    st |= set_lds_all<double, 2>(nloc) | set_lds_all<float, 2>(nloc) | set_lds_all<uint16_t, 2>(nloc);
+  } else if (nmt <= 16) {
+    st |= set_lds_all<double, 4>(nloc) | set_lds_all<float, 4>(nloc) | set_lds_all<uint16_t, 4>(nloc);
+  } else {
+    st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<double, 6, 3, 8>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)cell_lds_bytes(nloc, 8, 3, 8));
+    st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<float, 6, 3, 8>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)cell_lds_bytes(nloc, 4, 3, 8));
+    st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<uint16_t, 6, 3, 8>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)cell_lds_bytes(nloc, 2, 3, 8));
+  }
   return st;
 }
 
 void cell_apply(const DevData &d, const void *cells, int dtype, const double *X, double *Y, int ncolr, int64_t ldr,
-                hipStream_t s, const int *any) {
-  if (dtype == 0) launch_apply<double>(d, (const double *)cells, X, Y, ncolr, ldr, s, any);
-  else if (dtype == 1) launch_apply<float>(d, (const float *)cells, X, Y, ncolr, ldr, s, any);
-  else launch_apply<uint16_t>(d, (const uint16_t *)cells, X, Y, ncolr, ldr, s, any);
+                hipStream_t s, const int *any, int variant) {
+  if (dtype == 0) launch_apply<double>(d, (const double *)cells, X, Y, ncolr, ldr, s, any, variant);
+  else if (dtype == 1) launch_apply<float>(d, (const float *)cells, X, Y, ncolr, ldr, s, any, variant);
+  else launch_apply<uint16_t>(d, (const uint16_t *)cells, X, Y, ncolr, ldr, s, any, variant);
 }
 
 }  // namespace k

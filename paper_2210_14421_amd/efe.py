@@ -113,6 +113,8 @@ _timing_on = _sig("efe_enable_timing", C.c_int32, [C.c_void_p, C.c_int32])
 _timing_get = _sig("efe_get_timing", C.c_int32, [C.c_void_p, _dp, C.POINTER(C.c_int64)])
 _last_error = _sig("efe_last_error", C.c_char_p, [C.c_void_p])
 _field_vjp = _sig("efe_field_vjp", C.c_int32, [C.POINTER(EfeField), C.c_int64, _dp, _dp, _dp])
+_autotune = _sig("efe_autotune", C.c_int32, [C.c_void_p, C.c_char_p, C.c_int32, C.c_char_p, C.c_int32])
+EFE_TUNE_FORCE = 1
 
 EXPORTED = ["efe_plan_create", "efe_plan_free", "efe_plan_sizes", "efe_plan_get", "efe_plan_error",
             "efe_setup", "efe_free", "efe_dims", "efe_set_options", "efe_initial_state",
@@ -120,7 +122,7 @@ EXPORTED = ["efe_plan_create", "efe_plan_free", "efe_plan_sizes", "efe_plan_get"
             "efe_hartree", "dipole", "efe_enable_timing", "efe_get_timing", "efe_last_error",
             "magnus_step_graph", "efe_batch_create", "efe_batch_free", "efe_batch_error", "efe_batch_step",
             "magnus_adjoint", "dipole_adjoint", "magnus_step_extrap", "absorption_spectrum", "power_spectrum",
-            "efe_field_vjp", "efe_apply_H_noalloc"]
+            "efe_field_vjp", "efe_apply_H_noalloc", "efe_autotune"]
 
 
 class EfeError(RuntimeError):
@@ -457,6 +459,25 @@ class Context:
         mu = (C.c_double * 3)()
         self._check(_dipole(self._c, self._ptr(Psi, self.torch.complex128, self.n_rows), Psi.shape[1], mu))
         return np.array(mu[:3])
+
+    def autotune(self, cache=None, force=False):
+        """Pick the fastest cell-product kernel shape for this context (efe_autotune).
+        Returns dict(choice, cached, times_us)."""
+        buf = C.create_string_buffer(4096)
+        self._check(_autotune(self._c, None if cache is None else os.fspath(cache).encode(),
+                              EFE_TUNE_FORCE if force else 0, buf, len(buf)))
+        out = {"times_us": {}, "rejected": {}}
+        for tok in buf.value.decode().split():
+            name, _, val = tok.partition("=")
+            if name == "choice":
+                out["choice"] = val
+            elif name == "cached":
+                out["cached"] = val == "1"
+            elif val.startswith("rejected"):
+                out["rejected"][name] = val
+            else:
+                out["times_us"][name] = float(val)
+        return out
 
     def enable_timing(self, on=True):
         self._check(_timing_on(self._c, 1 if on else 0))
