@@ -58,7 +58,7 @@ enum {
 };
 
 /* product dtype of the cell-block and enrichment-coupling products */
-enum { EFE_F64 = 0, EFE_F32 = 1, EFE_BF16 = 2, EFE_F64_SF = 3 };
+enum { EFE_F64 = 0, EFE_F32 = 1, EFE_BF16 = 2, EFE_F64_SF = 3, EFE_BF16X3 = 4 };
 /* adiabatic LDA (Sec. 2.1): none, Slater exchange, Slater + PW92 correlation */
 enum { EFE_XC_NONE = 0, EFE_XC_SLATER = 1, EFE_XC_SLATER_PW92 = 2 };
 /* Lanczos reorthogonalisation (efe_options.reorth) */
@@ -98,11 +98,14 @@ typedef struct {
 
 typedef struct {
   int32_t prod_dtype;      /* type of the stored cell blocks: EFE_F64 (FP64 products),
-                              EFE_F32 (FP32 products, FP32 accumulation) or EFE_BF16
-                              (BF16 blocks widened to FP32 products); or EFE_F64_SF:
-                              no stored blocks, the same operator applied in FP64 by
-                              sum factorisation from the potential at the points
-                              (degree 4 or 5 with the default Gauss rules only);
+                              EFE_F32 (FP32 products, FP32 accumulation), EFE_BF16
+                              (BF16 blocks and the orbital rows rounded to BF16,
+                              products on the BF16 MFMA, FP32 accumulation) or
+                              EFE_BF16X3 (both operands as hi/lo BF16 pairs, three
+                              BF16 MFMAs per product: about 16 significant bits); or
+                              EFE_F64_SF: no stored blocks, the same operator applied
+                              in FP64 by sum factorisation from the potential at the
+                              points (degree 4 or 5 with the default Gauss rules only);
                               the coupling, Lanczos, Poisson and densities stay FP64 */
   int32_t kmax;            /* maximum Krylov dimension (1..64)                    */
   double krylov_tol;       /* stop when the estimate of eq. (AdaptiveKrylovErr) <= tol * ||psi|| */

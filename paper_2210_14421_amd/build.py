@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libefe.so")
-SOURCES = ["plan.cpp", "kernels_fields.hip", "kernels_cell.hip", "kernels_krylov.hip", "kernels_lanczos.hip", "kernels_spectrum.hip", "kernels_sf.hip", "api.hip"]
+SOURCES = ["plan.cpp", "kernels_fields.hip", "kernels_cell.hip", "kernels_cell_bf16.hip", "kernels_krylov.hip", "kernels_lanczos.hip", "kernels_spectrum.hip", "kernels_sf.hip", "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

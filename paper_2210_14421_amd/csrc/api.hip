@@ -399,13 +399,17 @@ efe_status build_device(efe_ctx *ctx) {
     }
     ctx->cells = nullptr;
   } else {
-    const size_t esz = ctx->dtype == 0 ? 8 : (ctx->dtype == 1 ? 4 : 2);
+    // FP64 / FP32 blocks of nloc^2 (16-byte aligned stride); BF16 blocks as padded rows, one
+    // plane or a hi/lo pair, zeroed once so that the row padding is finite
+    const bool bf = ctx->dtype == 2 || ctx->dtype == 4;
+    const size_t cbytes = bf ? (size_t)pl.n_cells * efe::k::bf16_block_elems(d.g, ctx->dtype == 4 ? 2 : 1) * 2
+                             : (size_t)pl.n_cells * d.g.cstride * (ctx->dtype == 0 ? 8 : 4);
     void *cells = nullptr;
-    size_t cbytes = (size_t)pl.n_cells * d.g.cstride * esz;
     hipError_t e = hipMalloc(&cells, cbytes);
     if (e != hipSuccess) { ctx->err = "cell blocks: " + std::string(hip_err(e)); return EFE_ERR_ALLOC; }
     ctx->allocs.push_back(cells);
     ctx->cells = cells;
+    if (bf) HIP_TRY(hipMemset(cells, 0, cbytes));
   }
   EFE_TRY(dalloc(ctx, &ctx->Q, ctx->blk * ctx->kmax));
   EFE_TRY(dalloc(ctx, &ctx->X0, ctx->blk));
@@ -1365,7 +1369,7 @@ efe_status efe_plan_get(const efe_plan *plan, const char *name, double *out, int
 efe_status efe_setup(const efe_system *sys, const efe_options *opt, efe_ctx **out) {
   if (!sys || !opt || !out) return EFE_ERR_ARG;
   *out = nullptr;
-  if (opt->prod_dtype < 0 || opt->prod_dtype > 3 || opt->kmax < 1 || opt->kmax > 64 || opt->reorth < 0 ||
+  if (opt->prod_dtype < 0 || opt->prod_dtype > 4 || opt->kmax < 1 || opt->kmax > 64 || opt->reorth < 0 ||
       opt->reorth > 1)
     return EFE_ERR_ARG;
   efe_ctx *ctx = new (std::nothrow) efe_ctx();
@@ -1915,8 +1919,11 @@ efe_status efe_autotune(efe_ctx *ctx, const char *cache_path, int32_t flags, cha
   if (ctx->dtype == 3) {
     cand.push_back(0);
     names.push_back("sum_factorised");
+  } else if (ctx->dtype == 2 || ctx->dtype == 4) {
+    cand.push_back(0);
+    names.push_back(ctx->dtype == 2 ? "bf16_mfma" : "bf16x3_mfma");
   } else {
-    const size_t esz = ctx->dtype == 0 ? 8 : (ctx->dtype == 1 ? 4 : 2);
+    const size_t esz = ctx->dtype == 0 ? 8 : 4;
     const int nv = efe::k::cell_variant_count(d.g.nloc, esz);
     for (int v = 0; v < nv; ++v) {
       efe::k::cell_variant_name(v, nm, sizeof(nm));

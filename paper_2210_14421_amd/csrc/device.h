@@ -110,6 +110,12 @@ void hee_reduce(const DevData &d, const double *hee_part, int kinetic, double *H
 int cell_apply_init(int nloc);
 void cell_apply(const DevData &d, const void *cells, int dtype, const double *X, double *Y, int ncolr, int64_t ldr,
                 hipStream_t s, const int *any = nullptr, int variant = 0);
+// BF16 products (16x16x32 BF16 MFMA, FP32 accumulation): blocks of planes (1: BF16,
+// 2: hi/lo split) BF16 planes of nloc rows padded to 8 elements; raises the LDS limit
+int cell_bf16_init(int nloc);
+int64_t bf16_block_elems(const Geom &g, int planes);
+void cell_apply_bf16(const DevData &d, const uint16_t *cells, int planes, const double *X, double *Y, int ncolr,
+                     int64_t ldr, hipStream_t s, const int *any = nullptr);
 // pipeline variants of the cell products that fit the LDS for cells of nloc nodes and
 // blocks of esz bytes (all give the same bits; variant 0 is the default), and their names
 int cell_variant_count(int nloc, size_t esz);

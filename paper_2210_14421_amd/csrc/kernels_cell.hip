@@ -1,6 +1,7 @@
 // Cell part of Hbar X (Sec. 2.3, eq. (TDKSDiscrete2)): Y = sum_c P_c^T Hbar_c P_c X
 // with the dense symmetric cell blocks Hbar_c = D_c^-1/2 (K_c / 2 + V_c) D_c^-1/2, on the
-// 16x16x4 MFMA (FP64, or FP32 blocks with FP32 accumulation).
+// 16x16x4 MFMA (FP64, or FP32 blocks with FP32 accumulation); BF16 products are in
+// kernels_cell_bf16.hip.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -32,20 +33,7 @@ template <> struct Mfma<double> {
   // output register r of a lane holds row lane/16 + 4 r, column lane%16
   static __device__ __forceinline__ int row(int kr, int r) { return kr + 4 * r; }
 };
-// BF16 cell blocks (bit patterns in uint16_t): widened to FP32 on the way into
-// the FP32 MFMA.  The product is HBM-bound, so the storage halves the traffic of
-// the blocks while X keeps FP32 operands (H Xbar stays linear in X).
-template <> struct Mfma<uint16_t> {
-  typedef float C;
-  typedef v4f Acc;
-  static __device__ __forceinline__ Acc mma(C a, C b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
-  static __device__ __forceinline__ int row(int kr, int r) { return 4 * kr + r; }
-};
-
 template <typename T, typename C> __device__ __forceinline__ C widen(T v) { return (C)v; }
-template <> __device__ __forceinline__ float widen<uint16_t, float>(uint16_t v) {
-  return __uint_as_float((unsigned)v << 16);
-}
 
 template <> struct Mfma<float> {
   typedef float C;
@@ -313,25 +301,23 @@ int cell_apply_init(int nloc) {
   int st = 0;
   const int nmt = (nloc + 15) / 16;
   if (nmt <= 8) {
-    st |= set_lds_all<double, 2>(nloc) | set_lds_all<float, 2>(nloc) | set_lds_all<uint16_t, 2>(nloc);
+    st |= set_lds_all<double, 2>(nloc) | set_lds_all<float, 2>(nloc);
   } else if (nmt <= 16) {
-    st |= set_lds_all<double, 4>(nloc) | set_lds_all<float, 4>(nloc) | set_lds_all<uint16_t, 4>(nloc);
+    st |= set_lds_all<double, 4>(nloc) | set_lds_all<float, 4>(nloc);
   } else {
     st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<double, 6, 3, 8>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)cell_lds_bytes(nloc, 8, 3, 8));
     st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<float, 6, 3, 8>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                    (int)cell_lds_bytes(nloc, 4, 3, 8));
-    st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<uint16_t, 6, 3, 8>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)cell_lds_bytes(nloc, 2, 3, 8));
   }
-  return st;
+  return st | cell_bf16_init(nloc);
 }
 
 void cell_apply(const DevData &d, const void *cells, int dtype, const double *X, double *Y, int ncolr, int64_t ldr,
                 hipStream_t s, const int *any, int variant) {
   if (dtype == 0) launch_apply<double>(d, (const double *)cells, X, Y, ncolr, ldr, s, any, variant);
   else if (dtype == 1) launch_apply<float>(d, (const float *)cells, X, Y, ncolr, ldr, s, any, variant);
-  else launch_apply<uint16_t>(d, (const uint16_t *)cells, X, Y, ncolr, ldr, s, any, variant);
+  else cell_apply_bf16(d, (const uint16_t *)cells, dtype == 4 ? 2 : 1, X, Y, ncolr, ldr, s, any);
 }
 
 }  // namespace k

@@ -1,0 +1,278 @@
+// Cell part of Hbar X (Sec. 2.3, eq. (TDKSDiscrete2)) with BF16 products on the
+// 16x16x32 BF16 MFMA and FP32 accumulation: Y = sum_c P_c^T Hbar_c P_c X with the
+// symmetric cell blocks stored in BF16 and the gathered rows of X rounded to BF16
+// on the way into LDS.  The split form keeps each operand as a pair of BF16 values
+// (hi = bf16(x), lo = bf16(x - hi)) and adds hi*hi + hi*lo + lo*hi: three MFMAs
+// per product, about 16 significant bits.
+//
+// Storage of the blocks (both forms): row r of a cell's block at r * lda with lda =
+// nloc rounded up to 8 elements (every 8-element chunk of a row is one aligned 16-byte
+// copy), nloc * lda elements per plane; the split form stores the hi plane, then
+// the lo plane.
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+
+namespace efe {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kBWaves = 8;
+constexpr int kBCols = 96;       // columns per workgroup (six 16-column N tiles)
+constexpr int kBRow = 64;        // LDS bytes per operand row of one k-step (32 BF16)
+constexpr int kBXPlane = kBCols * kBRow;
+
+// 16-byte slot of chunk q (8 k-values) in LDS row r: a row-dependent XOR keeps the
+// 16 rows read by one MFMA operand load on distinct banks.
+__device__ __forceinline__ int slot_of(int r, int q) { return q ^ ((r >> 1) & 3); }
+
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_val(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
+
+typedef const void __attribute__((address_space(1))) *gptr_t;
+typedef void __attribute__((address_space(3))) *lptr_t;
+
+__device__ __forceinline__ void copy16(const void *src, void *lds_base) {
+  __builtin_amdgcn_global_load_lds((gptr_t)src, (lptr_t)lds_base, 16, 0, 0);
+}
+
+inline size_t bf16_lds_bytes(int mmax, int planes) {
+  return (size_t)2 * planes * ((size_t)mmax * kBRow + kBXPlane) + 1024;
+}
+
+// One workgroup of 8 waves per (cell, 96 columns).  K advances in steps of 32 k-rows,
+// two stages in LDS: the A operand rows [m][32 k] (copied global -> LDS directly, one
+// 16-byte chunk per lane) and the B operand [n][32 k] (X rows loaded into registers,
+// rounded to BF16, written transposed).  Wave w takes the M tiles (w >> 1) + 4 i and
+// the N tiles 3 (w & 1) .. 3 (w & 1) + 2.  MMAX: rows of A staged (nloc rounded up to
+// whole M tiles); PL: 1 (BF16) or 2 (split).
+template <int MMAX, int CMT, int PL>
+__global__ void __launch_bounds__(kBWaves * 64)
+k_cell_bf16(const DevData d, const int *__restrict__ cell_list, int slot0, const uint16_t *__restrict__ cells,
+            const double *__restrict__ X, double *__restrict__ Y, int ncolr, int64_t ldr, const int *__restrict__ any) {
+  static_assert(MMAX % 16 == 0 && (MMAX / 16 + 3) / 4 <= CMT, "M tiles per wave");
+  if (any && *any == 0) return;
+  constexpr int kAIns = (MMAX / 16 + kBWaves - 1) / kBWaves;   // A copies per wave per plane and step
+  constexpr int kAPlane = MMAX * kBRow;
+  constexpr int kStage = PL * (kAPlane + kBXPlane);
+  __shared__ int64_t rowoff[MMAX];
+  __shared__ unsigned char first[MMAX];
+  extern __shared__ __attribute__((aligned(16))) unsigned char bsm[];
+  unsigned char *junk = bsm + 2 * kStage;
+  const Geom &g = d.g;
+  const int nloc = g.nloc;
+  const int lda = (nloc + 7) & ~7;
+  const int64_t plane = (int64_t)nloc * lda;
+  const int nmt = (nloc + 15) / 16;
+  const int nks = (nloc + 31) / 32;
+  const int ci = blockIdx.x;
+  const int col0 = blockIdx.y * kBCols;
+  const int wcol = ncolr - col0 < kBCols ? ncolr - col0 : kBCols;
+  const int64_t cell = cell_list[ci];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int mg = wave >> 1, nh = wave & 1;
+  int e[3];
+  cell_ijk(g, cell, e);
+  for (int l = tid; l < nloc; l += kBWaves * 64) {
+    rowoff[l] = local_node(g, e, l) * ldr;
+    // colours run in the order (e_x & 1) + 2 (e_y & 1) + 4 (e_z & 1); a node on a
+    // face shared along some axis is reached first by the even cell of that axis
+    const int li[3] = {l % g.P, (l / g.P) % g.P, l / (g.P * g.P)};
+    bool later = false;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const bool shared = (li[ax] == 0 && e[ax] > 0) || (li[ax] == g.p && e[ax] < g.nc[ax] - 1);
+      later |= shared && (e[ax] & 1);
+    }
+    first[l] = later ? 0 : 1;
+  }
+  __syncthreads();
+  const uint16_t *Ag = cells + (int64_t)(slot0 + ci) * PL * plane;
+  // A rows of k-step s: instruction i of a wave copies rows 16 (wave + 8 i) .. +15, lane L
+  // row 16 (.) + L / 4 into LDS slot L & 3, which holds chunk slot ^ swizzle of that row.
+  // Rows past nloc and chunks past the row end copy the block's first chunk instead
+  // (finite values that only meet zero rows of X or output rows never stored).
+  auto issueA = [&](int s, int st) {
+#pragma unroll
+    for (int pl = 0; pl < PL; ++pl)
+#pragma unroll
+      for (int i = 0; i < kAIns; ++i) {
+        const int ins = wave + kBWaves * i;
+        if (ins < MMAX / 16) {
+          const int r = 16 * ins + (lane >> 2), sl = lane & 3;
+          const int q = sl ^ ((r >> 1) & 3);
+          const int k0 = 32 * s + 8 * q;
+          const bool ok = r < nloc && k0 < nloc;
+          copy16(Ag + pl * plane + (ok ? (int64_t)r * lda + k0 : 0),
+                 bsm + st * kStage + pl * kAPlane + ins * 1024);
+        } else {
+          copy16(Ag, junk);
+        }
+      }
+  };
+  // B operand of k-step s: thread t < 384 takes column n = t % 96 and chunk q = t / 96
+  // (k = 32 s + 8 q .. + 7), eight loads of X, rounded (and split) to BF16
+  const int xn = tid % kBCols, xq = tid / kBCols;
+  const bool xthr = tid < 4 * kBCols;
+  double xv[8];
+  auto loadX = [&](int s) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = 32 * s + 8 * xq + j;
+      xv[j] = (xthr && xn < wcol && k < nloc) ? X[rowoff[k] + col0 + xn] : 0.0;
+    }
+  };
+  auto writeX = [&](int st) {
+    if (!xthr) return;
+    uint32_t hi[4], lo[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float f0 = (float)xv[2 * j], f1 = (float)xv[2 * j + 1];
+      const uint16_t h0 = bf16_rne(f0), h1 = bf16_rne(f1);
+      hi[j] = (uint32_t)h0 | ((uint32_t)h1 << 16);
+      if (PL == 2) {
+        const uint16_t l0 = bf16_rne(f0 - bf16_val(h0)), l1 = bf16_rne(f1 - bf16_val(h1));
+        lo[j] = (uint32_t)l0 | ((uint32_t)l1 << 16);
+      }
+    }
+    unsigned char *xb = bsm + st * kStage + PL * kAPlane + xn * kBRow + slot_of(xn, xq) * 16;
+    *(u32x4 *)xb = u32x4{hi[0], hi[1], hi[2], hi[3]};
+    if (PL == 2) *(u32x4 *)(xb + kBXPlane) = u32x4{lo[0], lo[1], lo[2], lo[3]};
+  };
+  v4f acc[CMT][3];
+#pragma unroll
+  for (int i = 0; i < CMT; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+  const int cl = lane & 15, kg = lane >> 4;
+  issueA(0, 0);
+  loadX(0);
+  writeX(0);
+  wait_vm<0>();
+  __syncthreads();
+  for (int s = 0; s < nks; ++s) {
+    const int st = s & 1;
+    if (s + 1 < nks) {
+      issueA(s + 1, st ^ 1);
+      loadX(s + 1);
+    }
+    const unsigned char *Ast = bsm + st * kStage;
+    const unsigned char *Bst = Ast + PL * kAPlane;
+    bf16x8 b[3], bl[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int n = 16 * (3 * nh + j) + cl;
+      b[j] = *(const bf16x8 *)(Bst + n * kBRow + slot_of(n, kg) * 16);
+      if (PL == 2) bl[j] = *(const bf16x8 *)(Bst + kBXPlane + n * kBRow + slot_of(n, kg) * 16);
+    }
+#pragma unroll
+    for (int i = 0; i < CMT; ++i) {
+      const int t = mg + 4 * i;
+      if (t < nmt) {
+        const int m = 16 * t + cl;
+        const bf16x8 a = *(const bf16x8 *)(Ast + m * kBRow + slot_of(m, kg) * 16);
+        bf16x8 al;
+        if (PL == 2) al = *(const bf16x8 *)(Ast + kAPlane + m * kBRow + slot_of(m, kg) * 16);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[i][j], 0, 0, 0);
+          if (PL == 2) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, b[j], acc[i][j], 0, 0, 0);
+          }
+        }
+      }
+    }
+    if (s + 1 < nks) writeX(st ^ 1);
+    wait_vm<0>();
+    __syncthreads();
+  }
+  // output register r of a lane holds row 4 (lane / 16) + r, column lane % 16 of its tile
+#pragma unroll
+  for (int i = 0; i < CMT; ++i) {
+    const int t = mg + 4 * i;
+    if (t >= nmt) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * t + 4 * kg + r;
+      if (row >= nloc) continue;
+      double *yr = Y + rowoff[row];
+      const bool f = first[row] != 0;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const int col = col0 + 16 * (3 * nh + j) + cl;
+        if (col < ncolr) yr[col] = f ? (double)acc[i][j][r] : yr[col] + (double)acc[i][j][r];
+      }
+    }
+  }
+}
+
+template <int MMAX, int CMT, int PL>
+void launch_bf16(const DevData &d, const uint16_t *cells, const double *X, double *Y, int ncolr, int64_t ldr,
+                 hipStream_t s, const int *any) {
+  const unsigned ny = (unsigned)((ncolr + kBCols - 1) / kBCols);
+  const size_t lds = bf16_lds_bytes(MMAX, PL);
+  for (int c = 0; c < 8; ++c) {
+    const int cnt = d.colour_off[c + 1] - d.colour_off[c];
+    if (cnt == 0) continue;
+    const int *list = d.colour_cells + d.colour_off[c];
+    hipLaunchKernelGGL((k_cell_bf16<MMAX, CMT, PL>), dim3((unsigned)cnt, ny), dim3(kBWaves * 64), lds, s, d, list,
+                       d.colour_off[c], cells, X, Y, ncolr, ldr, any);
+  }
+}
+
+template <int MMAX, int CMT, int PL>
+int set_lds_bf16() {
+  return (int)hipFuncSetAttribute((const void *)k_cell_bf16<MMAX, CMT, PL>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)bf16_lds_bytes(MMAX, PL));
+}
+
+}  // namespace
+
+namespace k {
+
+int64_t bf16_block_elems(const Geom &g, int planes) {
+  return (int64_t)planes * g.nloc * ((g.nloc + 7) & ~7);
+}
+
+int cell_bf16_init(int nloc) {
+  if (nloc > 352) return 1;
+  int st = 0;
+  if (nloc <= 128) st |= set_lds_bf16<128, 2, 1>() | set_lds_bf16<128, 2, 2>();
+  else if (nloc <= 224) st |= set_lds_bf16<224, 4, 1>() | set_lds_bf16<224, 4, 2>();
+  else st |= set_lds_bf16<352, 6, 1>() | set_lds_bf16<352, 6, 2>();
+  return st;
+}
+
+void cell_apply_bf16(const DevData &d, const uint16_t *cells, int planes, const double *X, double *Y, int ncolr,
+                     int64_t ldr, hipStream_t s, const int *any) {
+  const int nloc = d.g.nloc;
+  if (nloc <= 128) {
+    if (planes == 1) launch_bf16<128, 2, 1>(d, cells, X, Y, ncolr, ldr, s, any);
+    else launch_bf16<128, 2, 2>(d, cells, X, Y, ncolr, ldr, s, any);
+  } else if (nloc <= 224) {
+    if (planes == 1) launch_bf16<224, 4, 1>(d, cells, X, Y, ncolr, ldr, s, any);
+    else launch_bf16<224, 4, 2>(d, cells, X, Y, ncolr, ldr, s, any);
+  } else {
+    if (planes == 1) launch_bf16<352, 6, 1>(d, cells, X, Y, ncolr, ldr, s, any);
+    else launch_bf16<352, 6, 2>(d, cells, X, Y, ncolr, ldr, s, any);
+  }
+}
+
+}  // namespace k
+}  // namespace efe

@@ -21,10 +21,33 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
   return (uint16_t)(u >> 16);
 }
 
-template <typename T> __device__ __forceinline__ T cast_out(double v);
-template <> __device__ __forceinline__ double cast_out<double>(double v) { return v; }
-template <> __device__ __forceinline__ float cast_out<float>(double v) { return (float)v; }
-template <> __device__ __forceinline__ uint16_t cast_out<uint16_t>(double v) { return f32_to_bf16((float)v); }
+// Stored forms of the cell blocks: FP64 / FP32 rows of nloc elements; BF16 rows
+// padded to a multiple of 8 elements (one plane), or a hi/lo pair of BF16 planes
+// (hi = bf16(v), lo = bf16(v - hi)).  The padding columns are zero from set-up.
+struct Bf16Rows { uint16_t v; };
+struct Bf16Split { uint16_t v; };
+template <typename T> struct Store {
+  static constexpr int planes = 1;
+  static constexpr bool padded = false;
+  static __device__ __forceinline__ void put(T *o, int64_t i, int64_t, double v) { o[i] = (T)v; }
+};
+template <> struct Store<Bf16Rows> {
+  static constexpr int planes = 1;
+  static constexpr bool padded = true;
+  static __device__ __forceinline__ void put(Bf16Rows *o, int64_t i, int64_t, double v) {
+    ((uint16_t *)o)[i] = f32_to_bf16((float)v);
+  }
+};
+template <> struct Store<Bf16Split> {
+  static constexpr int planes = 2;
+  static constexpr bool padded = true;
+  static __device__ __forceinline__ void put(Bf16Split *o, int64_t i, int64_t plane, double v) {
+    const float f = (float)v;
+    const uint16_t h = f32_to_bf16(f);
+    ((uint16_t *)o)[i] = h;
+    ((uint16_t *)o)[i + plane] = f32_to_bf16(f - __uint_as_float((uint32_t)h << 16));
+  }
+};
 
 // ---------------------------------------------------------------------------
 // Cell-block rebuild.  One workgroup per cell of one class (all cells of a
@@ -120,7 +143,10 @@ k_rebuild(const DevData d, const int *__restrict__ cell_list, int n, int mode, c
     U[t] = s;
   }
   __syncthreads();
-  T *out = cells + (int64_t)d.cell_slot[cell] * d.g.cstride;   // colour-major storage
+  // colour-major storage
+  const int64_t lda = Store<T>::padded ? (int64_t)((nloc + 7) & ~7) : (int64_t)nloc;
+  const int64_t plane = Store<T>::padded ? (int64_t)nloc * lda : d.g.cstride;
+  T *out = cells + (int64_t)d.cell_slot[cell] * Store<T>::planes * plane;
   for (int c = 0; c < P; ++c)
     for (int c2 = c; c2 < P; ++c2) {
       const int pc = pair[c * P + c2];
@@ -150,10 +176,10 @@ k_rebuild(const DevData d, const int *__restrict__ cell_list, int n, int mode, c
                         Mel[0 * P2 + a * P + a2] * Mel[1 * P2 + b * P + b2] * Kel[2 * P2 + c * P + c2]);
         }
         int row = rp + P2 * c, col = cp + P2 * c2;
-        out[(int64_t)row * nloc + col] = cast_out<T>(dm[row] * val * dm[col]);
+        Store<T>::put(out, (int64_t)row * lda + col, plane, dm[row] * val * dm[col]);
         if (c2 != c) {
           int row2 = rp + P2 * c2, col2 = cp + P2 * c;
-          out[(int64_t)row2 * nloc + col2] = cast_out<T>(dm[row2] * val * dm[col2]);
+          Store<T>::put(out, (int64_t)row2 * lda + col2, plane, dm[row2] * val * dm[col2]);
         }
       }
       __syncthreads();
@@ -1384,9 +1410,12 @@ void rebuild_cells(const DevData &d, int mode, const double *rho, const double *
     else if (dtype == 1)
       hipLaunchKernelGGL(k_rebuild<float>, dim3(nc), dim3(kThreads), lds, s, d, list, n, mode, rho, phi, efield, fdir,
                          xc, (float *)cells, vq);
+    else if (dtype == 2)
+      hipLaunchKernelGGL(k_rebuild<Bf16Rows>, dim3(nc), dim3(kThreads), lds, s, d, list, n, mode, rho, phi, efield,
+                         fdir, xc, (Bf16Rows *)cells, vq);
     else
-      hipLaunchKernelGGL(k_rebuild<uint16_t>, dim3(nc), dim3(kThreads), lds, s, d, list, n, mode, rho, phi, efield,
-                         fdir, xc, (uint16_t *)cells, vq);
+      hipLaunchKernelGGL(k_rebuild<Bf16Split>, dim3(nc), dim3(kThreads), lds, s, d, list, n, mode, rho, phi, efield,
+                         fdir, xc, (Bf16Split *)cells, vq);
   }
 }
 

@@ -23,7 +23,7 @@ _lib = C.CDLL(LIB_PATH)
 
 EFE_OK, EFE_ERR_ARG, EFE_ERR_ALLOC, EFE_ERR_HIP = 0, -1, -2, -3
 EFE_ERR_NOCONV, EFE_ERR_SINGULAR, EFE_ERR_NONFINITE, EFE_ERR_STATE = -4, -5, -6, -7
-DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "f64sf": 3}
+DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "f64sf": 3, "bf16x3": 4}
 XC = {"none": 0, "slater": 1, "slater_pw92": 2}
 OPS = {"H": 0, "x": 1, "y": 2, "z": 3}
 

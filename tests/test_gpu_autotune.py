@@ -75,7 +75,7 @@ def test_autotune_needs_hamiltonian():
         ctx.close()
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "bf16x3"])
 def test_autotune_na8(dtype, tmp_path):
     from workloads import na8
     from paper_2210_14421_amd.efe import Context
