@@ -1920,8 +1920,11 @@ efe_status efe_autotune(efe_ctx *ctx, const char *cache_path, int32_t flags, cha
     cand.push_back(0);
     names.push_back("sum_factorised");
   } else if (ctx->dtype == 2 || ctx->dtype == 4) {
-    cand.push_back(0);
-    names.push_back(ctx->dtype == 2 ? "bf16_mfma" : "bf16x3_mfma");
+    const int nv = efe::k::cell_bf16_variant_count(d.g.nloc);
+    for (int v = 0; v < nv; ++v) {
+      cand.push_back(v);
+      names.push_back(std::string(ctx->dtype == 2 ? "bf16_mfma" : "bf16x3_mfma") + (v ? "_w6" : ""));
+    }
   } else {
     const size_t esz = ctx->dtype == 0 ? 8 : 4;
     const int nv = efe::k::cell_variant_count(d.g.nloc, esz);

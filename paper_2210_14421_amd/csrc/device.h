@@ -115,7 +115,9 @@ void cell_apply(const DevData &d, const void *cells, int dtype, const double *X,
 int cell_bf16_init(int nloc);
 int64_t bf16_block_elems(const Geom &g, int planes);
 void cell_apply_bf16(const DevData &d, const uint16_t *cells, int planes, const double *X, double *Y, int ncolr,
-                     int64_t ldr, hipStream_t s, const int *any = nullptr);
+                     int64_t ldr, hipStream_t s, const int *any = nullptr, int variant = 0);
+// register-budget variants of the BF16 products (0: two workgroups per CU, 1: three)
+int cell_bf16_variant_count(int nloc);
 // pipeline variants of the cell products that fit the LDS for cells of nloc nodes and
 // blocks of esz bytes (all give the same bits; variant 0 is the default), and their names
 int cell_variant_count(int nloc, size_t esz);

@@ -88,8 +88,8 @@ inline size_t cell_lds_bytes(int nloc, size_t esz, int ns, int kc) {
   return (size_t)ns * (aseg * 1024 + (size_t)kc * kCellLDX * 8) + 1024;
 }
 
-template <typename T, int CMT, int NS, int KC>
-__global__ void __launch_bounds__(kCellWaves * 64) __attribute__((amdgpu_waves_per_eu(CMT <= 4 ? 4 : 2)))
+template <typename T, int CMT, int NS, int KC, int WPE>
+__global__ void __launch_bounds__(kCellWaves * 64) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, const T *__restrict__ cells,
              const double *__restrict__ X, double *__restrict__ Y, int ncolr, int64_t ldr, const int *__restrict__ any) {
   static_assert(KC % 4 == 0 && NS >= 2, "chunks of whole k-steps, at least one in flight");
@@ -200,26 +200,44 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
         }
     }
   }
-  // D layout of the 16x16 MFMA (differs between the f64 and f32 forms)
+  // D layout of the 16x16 MFMA (differs between the f64 and f32 forms).  Per tile, every
+  // earlier value of Y is loaded before any store, so that the loads of the rows a
+  // previous colour reached are in flight together.
+  // (FP64 accumulators leave room for half a tile's values at a time.)
+  constexpr int kRB = sizeof(C) == 8 ? 2 : 4;
 #pragma unroll
   for (int i = 0; i < CMT; ++i) {
     if (mg + 4 * i >= nmt) continue;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = (mg + 4 * i) * 16 + Mfma<T>::row(kr, r);
-      if (row >= nloc) continue;
-      double *yr = Y + rowoff[row];
-      const bool f = first[row] != 0;
+    for (int r0 = 0; r0 < 4; r0 += kRB) {
+      double old[kRB][kCellNT];
 #pragma unroll
-      for (int j = 0; j < kCellNT; ++j) {
-        const int col = col0 + (nh * kCellNT + j) * 16 + cl;
-        if (col < ncolr) yr[col] = f ? (double)acc[i][j][r] : yr[col] + (double)acc[i][j][r];
+      for (int r = 0; r < kRB; ++r) {
+        const int row = (mg + 4 * i) * 16 + Mfma<T>::row(kr, r0 + r);
+        const bool add = row < nloc && !first[row];
+        const double *yr = Y + (row < nloc ? rowoff[row] : 0);
+#pragma unroll
+        for (int j = 0; j < kCellNT; ++j) {
+          const int col = col0 + (nh * kCellNT + j) * 16 + cl;
+          old[r][j] = (add && col < ncolr) ? yr[col] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < kRB; ++r) {
+        const int row = (mg + 4 * i) * 16 + Mfma<T>::row(kr, r0 + r);
+        if (row >= nloc) continue;
+        double *yr = Y + rowoff[row];
+#pragma unroll
+        for (int j = 0; j < kCellNT; ++j) {
+          const int col = col0 + (nh * kCellNT + j) * 16 + cl;
+          if (col < ncolr) yr[col] = old[r][j] + (double)acc[i][j][r0 + r];
+        }
       }
     }
   }
 }
 
-template <typename T, int CMT, int NS, int KC>
+template <typename T, int CMT, int NS, int KC, int WPE = (CMT <= 4 ? 4 : 2)>
 void launch_apply_m(const DevData &d, const T *cells, const double *X, double *Y, int ncolr, int64_t ldr,
                     hipStream_t s, const int *any) {
   const unsigned ny = (unsigned)((ncolr + kCellCols - 1) / kCellCols);
@@ -228,21 +246,25 @@ void launch_apply_m(const DevData &d, const T *cells, const double *X, double *Y
     const int cnt = d.colour_off[c + 1] - d.colour_off[c];
     if (cnt == 0) continue;
     const int *list = d.colour_cells + d.colour_off[c];
-    hipLaunchKernelGGL((k_cell_apply<T, CMT, NS, KC>), dim3((unsigned)cnt, ny), dim3(kCellWaves * 64), lds, s, d,
+    hipLaunchKernelGGL((k_cell_apply<T, CMT, NS, KC, WPE>), dim3((unsigned)cnt, ny), dim3(kCellWaves * 64), lds, s, d,
                        list, d.colour_off[c], cells, X, Y, ncolr, ldr, any);
   }
 }
 
-// Pipeline variants (chunks in flight NS, k-rows per chunk KC) for cells of up to 256
-// nodes (degree <= 5); variant 0 is the default.  Degree 6 cells use the default only.
-constexpr int kCellVariants = 6;
-constexpr int kVarNS[kCellVariants] = {3, 2, 4, 2, 6, 4};
-constexpr int kVarKC[kCellVariants] = {8, 8, 4, 16, 4, 8};
+// Pipeline variants (chunks in flight NS, k-rows per chunk KC, waves per SIMD the
+// registers are budgeted for WPE) for cells of up to 256 nodes (degree <= 5); variant 0
+// is the default.  The last three budget registers for six waves per SIMD (three
+// workgroups per CU), for FP32 blocks only.  Degree 6 cells use the default only.
+constexpr int kCellVariants = 9;
+constexpr int kCellVariantsF64 = 6;
+constexpr int kVarNS[kCellVariants] = {3, 2, 4, 2, 6, 4, 3, 2, 2};
+constexpr int kVarKC[kCellVariants] = {8, 8, 4, 16, 4, 8, 8, 8, 16};
+constexpr int kVarWPE[kCellVariants] = {4, 4, 4, 4, 4, 4, 6, 6, 6};
 
 template <typename T, int CMT, int V>
 void launch_v(const DevData &d, const T *cells, const double *X, double *Y, int ncolr, int64_t ldr, hipStream_t s,
               const int *any) {
-  launch_apply_m<T, CMT, kVarNS[V], kVarKC[V]>(d, cells, X, Y, ncolr, ldr, s, any);
+  launch_apply_m<T, CMT, kVarNS[V], kVarKC[V], (CMT <= 4 ? kVarWPE[V] : 2)>(d, cells, X, Y, ncolr, ldr, s, any);
 }
 
 template <typename T, int CMT>
@@ -254,6 +276,9 @@ void launch_variant(int v, const DevData &d, const T *cells, const double *X, do
     case 3: launch_v<T, CMT, 3>(d, cells, X, Y, ncolr, ldr, s, any); break;
     case 4: launch_v<T, CMT, 4>(d, cells, X, Y, ncolr, ldr, s, any); break;
     case 5: launch_v<T, CMT, 5>(d, cells, X, Y, ncolr, ldr, s, any); break;
+    case 6: if (sizeof(T) == 4) { launch_v<T, CMT, 6>(d, cells, X, Y, ncolr, ldr, s, any); break; } [[fallthrough]];
+    case 7: if (sizeof(T) == 4) { launch_v<T, CMT, 7>(d, cells, X, Y, ncolr, ldr, s, any); break; } [[fallthrough]];
+    case 8: if (sizeof(T) == 4) { launch_v<T, CMT, 8>(d, cells, X, Y, ncolr, ldr, s, any); break; } [[fallthrough]];
     default: launch_v<T, CMT, 0>(d, cells, X, Y, ncolr, ldr, s, any); break;
   }
 }
@@ -269,7 +294,7 @@ void launch_apply(const DevData &d, const T *cells, const double *X, double *Y, 
 
 template <typename T, int CMT, int V>
 int set_lds_v(size_t esz, int nloc) {
-  return (int)hipFuncSetAttribute((const void *)k_cell_apply<T, CMT, kVarNS[V], kVarKC[V]>,
+  return (int)hipFuncSetAttribute((const void *)k_cell_apply<T, CMT, kVarNS[V], kVarKC[V], kVarWPE[V]>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)cell_lds_bytes(nloc, esz, kVarNS[V], kVarKC[V]));
 }
@@ -277,8 +302,11 @@ int set_lds_v(size_t esz, int nloc) {
 template <typename T, int CMT>
 int set_lds_all(int nloc) {
   const size_t e = sizeof(T);
-  return set_lds_v<T, CMT, 0>(e, nloc) | set_lds_v<T, CMT, 1>(e, nloc) | set_lds_v<T, CMT, 2>(e, nloc) |
-         set_lds_v<T, CMT, 3>(e, nloc) | set_lds_v<T, CMT, 4>(e, nloc) | set_lds_v<T, CMT, 5>(e, nloc);
+  int st = set_lds_v<T, CMT, 0>(e, nloc) | set_lds_v<T, CMT, 1>(e, nloc) | set_lds_v<T, CMT, 2>(e, nloc) |
+           set_lds_v<T, CMT, 3>(e, nloc) | set_lds_v<T, CMT, 4>(e, nloc) | set_lds_v<T, CMT, 5>(e, nloc);
+  if (sizeof(T) == 4)
+    st |= set_lds_v<T, CMT, 6>(e, nloc) | set_lds_v<T, CMT, 7>(e, nloc) | set_lds_v<T, CMT, 8>(e, nloc);
+  return st;
 }
 
 }  // namespace
@@ -287,14 +315,16 @@ namespace k {
 
 int cell_variant_count(int nloc, size_t esz) {
   if ((nloc + 15) / 16 > 16) return 1;
+  const int nv = esz == 4 ? kCellVariants : kCellVariantsF64;
   int n = 0;
-  while (n < kCellVariants && cell_lds_bytes(nloc, esz, kVarNS[n], kVarKC[n]) <= 156 * 1024) ++n;   // + static LDS
+  while (n < nv && cell_lds_bytes(nloc, esz, kVarNS[n], kVarKC[n]) <= 156 * 1024) ++n;   // + static LDS
   return n;
 }
 
 void cell_variant_name(int v, char *out, int len) {
   if (v < 0 || v >= kCellVariants) v = 0;
-  snprintf(out, len, "dense_ns%d_kc%d", kVarNS[v], kVarKC[v]);
+  if (kVarWPE[v] == 4) snprintf(out, len, "dense_ns%d_kc%d", kVarNS[v], kVarKC[v]);
+  else snprintf(out, len, "dense_ns%d_kc%d_w%d", kVarNS[v], kVarKC[v], kVarWPE[v]);
 }
 
 int cell_apply_init(int nloc) {
@@ -305,10 +335,10 @@ int cell_apply_init(int nloc) {
   } else if (nmt <= 16) {
     st |= set_lds_all<double, 4>(nloc) | set_lds_all<float, 4>(nloc);
   } else {
-    st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<double, 6, 3, 8>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)cell_lds_bytes(nloc, 8, 3, 8));
-    st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<float, 6, 3, 8>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)cell_lds_bytes(nloc, 4, 3, 8));
+    st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<double, 6, 3, 8, 2>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)cell_lds_bytes(nloc, 8, 3, 8));
+    st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<float, 6, 3, 8, 2>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)cell_lds_bytes(nloc, 4, 3, 8));
   }
   return st | cell_bf16_init(nloc);
 }
@@ -317,7 +347,7 @@ void cell_apply(const DevData &d, const void *cells, int dtype, const double *X,
                 hipStream_t s, const int *any, int variant) {
   if (dtype == 0) launch_apply<double>(d, (const double *)cells, X, Y, ncolr, ldr, s, any, variant);
   else if (dtype == 1) launch_apply<float>(d, (const float *)cells, X, Y, ncolr, ldr, s, any, variant);
-  else cell_apply_bf16(d, (const uint16_t *)cells, dtype == 4 ? 2 : 1, X, Y, ncolr, ldr, s, any);
+  else cell_apply_bf16(d, (const uint16_t *)cells, dtype == 4 ? 2 : 1, X, Y, ncolr, ldr, s, any, variant);
 }
 
 }  // namespace k

@@ -20,8 +20,8 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
-constexpr int kBWaves = 8;
 constexpr int kBCols = 96;       // columns per workgroup (six 16-column N tiles)
 constexpr int kBRow = 64;        // LDS bytes per operand row of one k-step (32 BF16)
 constexpr int kBXPlane = kBCols * kBRow;
@@ -54,19 +54,26 @@ inline size_t bf16_lds_bytes(int mmax, int planes) {
   return (size_t)2 * planes * ((size_t)mmax * kBRow + kBXPlane) + 1024;
 }
 
-// One workgroup of 8 waves per (cell, 96 columns).  K advances in steps of 32 k-rows,
-// two stages in LDS: the A operand rows [m][32 k] (copied global -> LDS directly, one
-// 16-byte chunk per lane) and the B operand [n][32 k] (X rows loaded into registers,
-// rounded to BF16, written transposed).  Wave w takes the M tiles (w >> 1) + 4 i and
-// the N tiles 3 (w & 1) .. 3 (w & 1) + 2.  MMAX: rows of A staged (nloc rounded up to
-// whole M tiles); PL: 1 (BF16) or 2 (split).
-template <int MMAX, int CMT, int PL>
-__global__ void __launch_bounds__(kBWaves * 64)
+// One workgroup per (cell, 96 columns) of 4 * 6 / NPW waves; wave w takes the M tiles
+// w / G + 4 i (G = 6 / NPW) and the NPW N tiles NPW (w % G) .. + NPW - 1.  K advances in
+// steps of 32 k-rows, two stages in LDS: the A operand rows [m][32 k] (copied global ->
+// LDS directly, one 16-byte chunk per lane) and the B operand [n][32 k] (X rows loaded
+// into registers, rounded to BF16, written transposed).  MMAX: rows of A staged (nloc
+// rounded up to whole M tiles); PL: 1 (BF16) or 2 (split); NPW 3 (8 waves) or 2 (12
+// waves, fewer registers per wave: three waves per SIMD for each of two workgroups).
+template <int MMAX, int CMT, int PL, int NPW, int WPE>
+__global__ void __launch_bounds__(4 * (6 / NPW) * 64) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_cell_bf16(const DevData d, const int *__restrict__ cell_list, int slot0, const uint16_t *__restrict__ cells,
             const double *__restrict__ X, double *__restrict__ Y, int ncolr, int64_t ldr, const int *__restrict__ any) {
   static_assert(MMAX % 16 == 0 && (MMAX / 16 + 3) / 4 <= CMT, "M tiles per wave");
+  static_assert(NPW == 2 || NPW == 3, "N tiles per wave");
+  constexpr int G = 6 / NPW;                   // N groups
+  constexpr int W = 4 * G;                     // waves per workgroup
+  constexpr int T = 64 * W;
+  constexpr int H = T / (4 * kBCols);          // threads per (column, chunk) of the B operand
+  constexpr int XV = 8 / H;                    // X values per thread and k-step
   if (any && *any == 0) return;
-  constexpr int kAIns = (MMAX / 16 + kBWaves - 1) / kBWaves;   // A copies per wave per plane and step
+  constexpr int kAIns = (MMAX / 16 + W - 1) / W;   // A copies per wave per plane and step
   constexpr int kAPlane = MMAX * kBRow;
   constexpr int kStage = PL * (kAPlane + kBXPlane);
   __shared__ int64_t rowoff[MMAX];
@@ -85,10 +92,10 @@ k_cell_bf16(const DevData d, const int *__restrict__ cell_list, int slot0, const
   const int64_t cell = cell_list[ci];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int mg = wave >> 1, nh = wave & 1;
+  const int mg = wave / G, ng = wave % G;
   int e[3];
   cell_ijk(g, cell, e);
-  for (int l = tid; l < nloc; l += kBWaves * 64) {
+  for (int l = tid; l < nloc; l += T) {
     rowoff[l] = local_node(g, e, l) * ldr;
     // colours run in the order (e_x & 1) + 2 (e_y & 1) + 4 (e_z & 1); a node on a
     // face shared along some axis is reached first by the even cell of that axis
@@ -103,7 +110,7 @@ k_cell_bf16(const DevData d, const int *__restrict__ cell_list, int slot0, const
   }
   __syncthreads();
   const uint16_t *Ag = cells + (int64_t)(slot0 + ci) * PL * plane;
-  // A rows of k-step s: instruction i of a wave copies rows 16 (wave + 8 i) .. +15, lane L
+  // A rows of k-step s: instruction i of a wave copies rows 16 (wave + W i) .. +15, lane L
   // row 16 (.) + L / 4 into LDS slot L & 3, which holds chunk slot ^ swizzle of that row.
   // Rows past nloc and chunks past the row end copy the block's first chunk instead
   // (finite values that only meet zero rows of X or output rows never stored).
@@ -112,7 +119,7 @@ k_cell_bf16(const DevData d, const int *__restrict__ cell_list, int slot0, const
     for (int pl = 0; pl < PL; ++pl)
 #pragma unroll
       for (int i = 0; i < kAIns; ++i) {
-        const int ins = wave + kBWaves * i;
+        const int ins = wave + W * i;
         if (ins < MMAX / 16) {
           const int r = 16 * ins + (lane >> 2), sl = lane & 3;
           const int q = sl ^ ((r >> 1) & 3);
@@ -125,23 +132,24 @@ k_cell_bf16(const DevData d, const int *__restrict__ cell_list, int slot0, const
         }
       }
   };
-  // B operand of k-step s: thread t < 384 takes column n = t % 96 and chunk q = t / 96
-  // (k = 32 s + 8 q .. + 7), eight loads of X, rounded (and split) to BF16
-  const int xn = tid % kBCols, xq = tid / kBCols;
-  const bool xthr = tid < 4 * kBCols;
-  double xv[8];
+  // B operand of k-step s: thread t < 384 H takes column n = t % 96, chunk q = (t / 96) % 4
+  // (k = 32 s + 8 q .. + 7) and part t / 384 of it (XV of the 8 k-values), rounded (and
+  // split) to BF16
+  const int xn = tid % kBCols, xq = (tid / kBCols) % 4, xp = tid / (4 * kBCols);
+  const bool xthr = tid < 4 * kBCols * H;
+  double xv[XV];
   auto loadX = [&](int s) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int k = 32 * s + 8 * xq + j;
+    for (int j = 0; j < XV; ++j) {
+      const int k = 32 * s + 8 * xq + XV * xp + j;
       xv[j] = (xthr && xn < wcol && k < nloc) ? X[rowoff[k] + col0 + xn] : 0.0;
     }
   };
   auto writeX = [&](int st) {
     if (!xthr) return;
-    uint32_t hi[4], lo[4];
+    uint32_t hi[XV / 2], lo[XV / 2];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < XV / 2; ++j) {
       const float f0 = (float)xv[2 * j], f1 = (float)xv[2 * j + 1];
       const uint16_t h0 = bf16_rne(f0), h1 = bf16_rne(f1);
       hi[j] = (uint32_t)h0 | ((uint32_t)h1 << 16);
@@ -150,15 +158,20 @@ k_cell_bf16(const DevData d, const int *__restrict__ cell_list, int slot0, const
         lo[j] = (uint32_t)l0 | ((uint32_t)l1 << 16);
       }
     }
-    unsigned char *xb = bsm + st * kStage + PL * kAPlane + xn * kBRow + slot_of(xn, xq) * 16;
-    *(u32x4 *)xb = u32x4{hi[0], hi[1], hi[2], hi[3]};
-    if (PL == 2) *(u32x4 *)(xb + kBXPlane) = u32x4{lo[0], lo[1], lo[2], lo[3]};
+    unsigned char *xb = bsm + st * kStage + PL * kAPlane + xn * kBRow + slot_of(xn, xq) * 16 + xp * 2 * XV;
+    if (XV == 8) {
+      *(u32x4 *)xb = u32x4{hi[0], hi[1], hi[2], hi[3]};
+      if (PL == 2) *(u32x4 *)(xb + kBXPlane) = u32x4{lo[0], lo[1], lo[2], lo[3]};
+    } else {
+      *(u32x2 *)xb = u32x2{hi[0], hi[1]};
+      if (PL == 2) *(u32x2 *)(xb + kBXPlane) = u32x2{lo[0], lo[1]};
+    }
   };
-  v4f acc[CMT][3];
+  v4f acc[CMT][NPW];
 #pragma unroll
   for (int i = 0; i < CMT; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < NPW; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
   const int cl = lane & 15, kg = lane >> 4;
   issueA(0, 0);
   loadX(0);
@@ -173,10 +186,10 @@ k_cell_bf16(const DevData d, const int *__restrict__ cell_list, int slot0, const
     }
     const unsigned char *Ast = bsm + st * kStage;
     const unsigned char *Bst = Ast + PL * kAPlane;
-    bf16x8 b[3], bl[3];
+    bf16x8 b[NPW], bl[NPW];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      const int n = 16 * (3 * nh + j) + cl;
+    for (int j = 0; j < NPW; ++j) {
+      const int n = 16 * (NPW * ng + j) + cl;
       b[j] = *(const bf16x8 *)(Bst + n * kBRow + slot_of(n, kg) * 16);
       if (PL == 2) bl[j] = *(const bf16x8 *)(Bst + kBXPlane + n * kBRow + slot_of(n, kg) * 16);
     }
@@ -189,7 +202,7 @@ k_cell_bf16(const DevData d, const int *__restrict__ cell_list, int slot0, const
         bf16x8 al;
         if (PL == 2) al = *(const bf16x8 *)(Ast + kAPlane + m * kBRow + slot_of(m, kg) * 16);
 #pragma unroll
-        for (int j = 0; j < 3; ++j) {
+        for (int j = 0; j < NPW; ++j) {
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[i][j], 0, 0, 0);
           if (PL == 2) {
             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl[j], acc[i][j], 0, 0, 0);
@@ -202,27 +215,40 @@ k_cell_bf16(const DevData d, const int *__restrict__ cell_list, int slot0, const
     wait_vm<0>();
     __syncthreads();
   }
-  // output register r of a lane holds row 4 (lane / 16) + r, column lane % 16 of its tile
+  // output register r of a lane holds row 4 (lane / 16) + r, column lane % 16 of its tile.
+  // Per tile, every earlier value of Y is loaded before any store, so that the loads of
+  // the rows a previous colour reached are in flight together.
 #pragma unroll
   for (int i = 0; i < CMT; ++i) {
     const int t = mg + 4 * i;
     if (t >= nmt) continue;
+    double old[4][NPW];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * t + 4 * kg + r;
+      const bool add = row < nloc && !first[row];
+      const double *yr = Y + (row < nloc ? rowoff[row] : 0);
+#pragma unroll
+      for (int j = 0; j < NPW; ++j) {
+        const int col = col0 + 16 * (NPW * ng + j) + cl;
+        old[r][j] = (add && col < ncolr) ? yr[col] : 0.0;
+      }
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = 16 * t + 4 * kg + r;
       if (row >= nloc) continue;
       double *yr = Y + rowoff[row];
-      const bool f = first[row] != 0;
 #pragma unroll
-      for (int j = 0; j < 3; ++j) {
-        const int col = col0 + 16 * (3 * nh + j) + cl;
-        if (col < ncolr) yr[col] = f ? (double)acc[i][j][r] : yr[col] + (double)acc[i][j][r];
+      for (int j = 0; j < NPW; ++j) {
+        const int col = col0 + 16 * (NPW * ng + j) + cl;
+        if (col < ncolr) yr[col] = old[r][j] + (double)acc[i][j][r];
       }
     }
   }
 }
 
-template <int MMAX, int CMT, int PL>
+template <int MMAX, int CMT, int PL, int NPW, int WPE>
 void launch_bf16(const DevData &d, const uint16_t *cells, const double *X, double *Y, int ncolr, int64_t ldr,
                  hipStream_t s, const int *any) {
   const unsigned ny = (unsigned)((ncolr + kBCols - 1) / kBCols);
@@ -231,15 +257,31 @@ void launch_bf16(const DevData &d, const uint16_t *cells, const double *X, doubl
     const int cnt = d.colour_off[c + 1] - d.colour_off[c];
     if (cnt == 0) continue;
     const int *list = d.colour_cells + d.colour_off[c];
-    hipLaunchKernelGGL((k_cell_bf16<MMAX, CMT, PL>), dim3((unsigned)cnt, ny), dim3(kBWaves * 64), lds, s, d, list,
+    hipLaunchKernelGGL((k_cell_bf16<MMAX, CMT, PL, NPW, WPE>), dim3((unsigned)cnt, ny), dim3(4 * (6 / NPW) * 64), lds,
+                       s, d, list,
                        d.colour_off[c], cells, X, Y, ncolr, ldr, any);
   }
 }
 
-template <int MMAX, int CMT, int PL>
+template <int MMAX, int CMT, int PL, int NPW, int WPE>
 int set_lds_bf16() {
-  return (int)hipFuncSetAttribute((const void *)k_cell_bf16<MMAX, CMT, PL>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)bf16_lds_bytes(MMAX, PL));
+  return (int)hipFuncSetAttribute((const void *)k_cell_bf16<MMAX, CMT, PL, NPW, WPE>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bf16_lds_bytes(MMAX, PL));
+}
+
+// variant 0: eight waves of three N tiles, four waves per SIMD (two workgroups per CU);
+// variant 1: twelve waves of two N tiles, six waves per SIMD
+template <int MMAX, int CMT, int PL>
+void launch_bf16_v(int v, const DevData &d, const uint16_t *cells, const double *X, double *Y, int ncolr,
+                   int64_t ldr, hipStream_t s, const int *any) {
+  if (v == 1) launch_bf16<MMAX, CMT, PL, 2, 6>(d, cells, X, Y, ncolr, ldr, s, any);
+  else launch_bf16<MMAX, CMT, PL, 3, 4>(d, cells, X, Y, ncolr, ldr, s, any);
+}
+
+template <int MMAX, int CMT>
+int set_lds_bf16_all() {
+  return set_lds_bf16<MMAX, CMT, 1, 3, 4>() | set_lds_bf16<MMAX, CMT, 2, 3, 4>() | set_lds_bf16<MMAX, CMT, 1, 2, 6>() |
+         set_lds_bf16<MMAX, CMT, 2, 2, 6>();
 }
 
 }  // namespace
@@ -250,27 +292,27 @@ int64_t bf16_block_elems(const Geom &g, int planes) {
   return (int64_t)planes * g.nloc * ((g.nloc + 7) & ~7);
 }
 
+int cell_bf16_variant_count(int nloc) { return nloc <= 224 ? 2 : 1; }
+
 int cell_bf16_init(int nloc) {
   if (nloc > 352) return 1;
-  int st = 0;
-  if (nloc <= 128) st |= set_lds_bf16<128, 2, 1>() | set_lds_bf16<128, 2, 2>();
-  else if (nloc <= 224) st |= set_lds_bf16<224, 4, 1>() | set_lds_bf16<224, 4, 2>();
-  else st |= set_lds_bf16<352, 6, 1>() | set_lds_bf16<352, 6, 2>();
-  return st;
+  if (nloc <= 128) return set_lds_bf16_all<128, 2>();
+  if (nloc <= 224) return set_lds_bf16_all<224, 4>();
+  return set_lds_bf16<352, 6, 1, 3, 2>() | set_lds_bf16<352, 6, 2, 3, 2>();
 }
 
 void cell_apply_bf16(const DevData &d, const uint16_t *cells, int planes, const double *X, double *Y, int ncolr,
-                     int64_t ldr, hipStream_t s, const int *any) {
+                     int64_t ldr, hipStream_t s, const int *any, int variant) {
   const int nloc = d.g.nloc;
   if (nloc <= 128) {
-    if (planes == 1) launch_bf16<128, 2, 1>(d, cells, X, Y, ncolr, ldr, s, any);
-    else launch_bf16<128, 2, 2>(d, cells, X, Y, ncolr, ldr, s, any);
+    if (planes == 1) launch_bf16_v<128, 2, 1>(variant, d, cells, X, Y, ncolr, ldr, s, any);
+    else launch_bf16_v<128, 2, 2>(variant, d, cells, X, Y, ncolr, ldr, s, any);
   } else if (nloc <= 224) {
-    if (planes == 1) launch_bf16<224, 4, 1>(d, cells, X, Y, ncolr, ldr, s, any);
-    else launch_bf16<224, 4, 2>(d, cells, X, Y, ncolr, ldr, s, any);
+    if (planes == 1) launch_bf16_v<224, 4, 1>(variant, d, cells, X, Y, ncolr, ldr, s, any);
+    else launch_bf16_v<224, 4, 2>(variant, d, cells, X, Y, ncolr, ldr, s, any);
   } else {
-    if (planes == 1) launch_bf16<352, 6, 1>(d, cells, X, Y, ncolr, ldr, s, any);
-    else launch_bf16<352, 6, 2>(d, cells, X, Y, ncolr, ldr, s, any);
+    if (planes == 1) launch_bf16<352, 6, 1, 3, 2>(d, cells, X, Y, ncolr, ldr, s, any);
+    else launch_bf16<352, 6, 2, 3, 2>(d, cells, X, Y, ncolr, ldr, s, any);
   }
 }
 
