@@ -167,13 +167,26 @@ def lanczos_expm_column(Aop, tau, v, tol, kmax, k_force: Optional[int] = None, r
 
 
 def lanczos_expm(A, tau, X, tol=1e-10, kmax=64, k_force: Optional[Sequence[int]] = None, reorth: str = "full",
-                 stats: Optional[dict] = None, block=False):
+                 stats: Optional[dict] = None, block=False, block_cols=None):
     """exp(-i tau A) X, one Krylov space per column.  A: matrix (sparse/dense) or callable.
 
     block=False: the columns one after another.  block=True (A callable on an
     (n, m) block): the columns' recurrences advance together and A is applied once
     per iteration to the block of the still-running columns' vectors; each column
-    runs the same steps as alone (the columns are independent problems)."""
+    runs the same steps as alone (the columns are independent problems).  With
+    block_cols, at most that many columns advance together (bounds the memory of
+    the Krylov vectors held at once)."""
+    if block and block_cols is not None and X.shape[1] > block_cols:
+        X = np.asarray(X, dtype=np.complex128)
+        Y = np.empty_like(X)
+        ks = np.zeros(X.shape[1], dtype=np.int32)
+        errs = np.zeros(X.shape[1])
+        for c0 in range(0, X.shape[1], block_cols):
+            c1 = min(c0 + block_cols, X.shape[1])
+            kf = None if k_force is None else k_force[c0:c1]
+            Y[:, c0:c1], ks[c0:c1], errs[c0:c1] = lanczos_expm(A, tau, X[:, c0:c1], tol, kmax, kf, reorth, stats,
+                                                              block=True)
+        return Y, ks, errs
     X = np.asarray(X, dtype=np.complex128)
     Y = np.empty_like(X)
     ks = np.zeros(X.shape[1], dtype=np.int32)
@@ -221,14 +234,16 @@ class Propagator:
     three previous densities (scheme "extrap")."""
 
     def __init__(self, model, X, t=0.0, field=None, tol=None, kmax=None, scheme="pc", reorth="full",
-                 matrix_free=False):
+                 matrix_free=False, block_cols=None):
         """matrix_free: Hbar as `EFEModel.operator` (cell blocks and coupling applied
         without assembly, Hartree by fast diagonalisation) and the Lanczos columns
-        advanced together (for large meshes); otherwise the assembled matrix."""
+        advanced together, at most block_cols at a time (for large meshes);
+        otherwise the assembled matrix."""
         if scheme not in ("pc", "extrap"):
             raise ValueError(f"unknown scheme {scheme!r}")
         self.reorth = reorth
         self.matrix_free = matrix_free
+        self.block_cols = block_cols
         self.model = model
         self.X = np.asarray(X, dtype=np.complex128).copy()
         self.t = float(t)
@@ -251,13 +266,16 @@ class Propagator:
         return self.model.hamiltonian_from_density(rho, t, self.field)
 
     def _expm(self, A, tau, X, k_force):
-        return lanczos_expm(A, tau, X, self.tol, self.kmax, k_force, reorth=self.reorth, block=self.matrix_free)
+        return lanczos_expm(A, tau, X, self.tol, self.kmax, k_force, reorth=self.reorth, block=self.matrix_free,
+                            block_cols=self.block_cols)
 
     def kick(self, kappa, direction=2):
         """psi <- exp(i kappa Zbar_d) psi, then refresh the Hamiltonian."""
+        self.H = None                              # released before the next operator is built
         Z = self.model.position_operator_free(direction) if self.matrix_free else \
             self.model.position_operator(direction)
         self.X, k, _ = self._expm(Z, -kappa, self.X, None)
+        del Z
         self.refresh()
         return k
 
@@ -274,6 +292,8 @@ class Propagator:
         else:
             Xp, kp, _ = self._expm(self.H, dt, self.X, kp_f)
             rho_mid = 0.5 * (self.rho + m.density(Xp))
+            del Xp
+        self.H = None                                  # rebuilt at the end of the step
         Hmid = self._ham(rho_mid, self.t + 0.5 * dt)
         self.X, kc, _ = self._expm(Hmid, dt, self.X, kc_f)
         del Hmid

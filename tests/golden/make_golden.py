@@ -163,7 +163,7 @@ def cluster_steps(spec, nsteps, name):
     m = EFEModel(spec)
     print(f"{name}: model {time.time() - t0:.0f}s", flush=True)
     X0 = m.enrichment_noise_state()
-    P = Propagator(m, X0, tol=spec.krylov_tol, kmax=spec.kmax, reorth="full", matrix_free=True)
+    P = Propagator(m, X0, tol=spec.krylov_tol, kmax=spec.kmax, reorth="full", matrix_free=True, block_cols=11)
     mu0 = m.dipole(P.rho)
     print(f"{name}: initial state and Hamiltonian {time.time() - t0:.0f}s  mu0={mu0}", flush=True)
     k_kick = P.kick(spec.kick, spec.kick_dir)

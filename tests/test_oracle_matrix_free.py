@@ -73,6 +73,9 @@ def test_lockstep_columns_equal_column_by_column(model, reorth):
     Y3, k3, _ = lanczos_expm(H, 0.2, X, tol=1e-10, kmax=64, k_force=kf, reorth=reorth, block=True)
     Y4, k4, _ = lanczos_expm(H, 0.2, X, tol=1e-10, kmax=64, k_force=kf, reorth=reorth)
     assert list(k3) == list(k4) and np.max(np.abs(Y3 - Y4)) <= 1e-13 * np.max(np.abs(Y4))
+    # at most three columns together: the same columns
+    Y5, k5, _ = lanczos_expm(H, 0.2, X, tol=1e-10, kmax=64, reorth=reorth, block=True, block_cols=3)
+    assert list(k5) == list(k1) and np.max(np.abs(Y5 - Y1)) <= 1e-13 * np.max(np.abs(Y1))
 
 
 def test_matrix_free_step_equals_assembled_step(model, golden_dir):
