@@ -82,13 +82,15 @@ def traffic_summary(dtype):
     unchanged (otherwise traffic is reported as null)."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "cell_apply_na8_traffic.json")
-    src = os.path.join(ROOT, "paper_2210_14421_amd", "csrc", "kernels_cell.hip")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for name in ("kernels_cell.hip", "kernels_cell_bf16.hip"):
+        with open(os.path.join(ROOT, "paper_2210_14421_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    sha = h.hexdigest()
     if rec.get("kernel_source_sha256") != sha or dtype not in rec.get("per_launch_bytes", {}):
         return None
     b = rec["per_launch_bytes"][dtype]
@@ -104,6 +106,8 @@ def run_apply_mode(spec, dtype, n_apply):
     ctx = Context(spec, dtype=dtype, kmax=4)
     Psi = ctx.initial_state()
     ctx.set_hamiltonian(Psi, 0.0)
+    tune = ctx.autotune(cache=TUNE_CACHE)        # the kernel shape the timed steps use
+    print(f"[bench] apply {dtype}: {tune}", file=sys.stderr, flush=True)
     Y = torch.empty_like(Psi)
     for _ in range(n_apply):
         ctx.apply_H(Psi, Y)
@@ -166,7 +170,7 @@ def roofline(spec, res, dtype):
     tr = traffic_summary(dtype)
     return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
             "traffic": None if tr is None else tr["total"] * ncolour,
-            "kernel": "k_cell_apply", "mfma_instruction": inst, "flop_per_hx": flop_hx,
+            "kernel": "k_cell_bf16" if dtype in ("bf16", "bf16x3") else "k_cell_apply", "mfma_instruction": inst, "flop_per_hx": flop_hx,
             "unique_bytes_per_hx": unique_hx, "arithmetic_intensity": ai, "hx_us": hx_s * 1e6,
             "tflops": flop_hx / hx_s / 1e12, "unique_GBps": unique_hx / hx_s / 1e9,
             "launches_per_hx": ncolour, "launch_avg_us": launch_s * 1e6,

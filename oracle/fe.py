@@ -16,6 +16,8 @@ Orderings (shared with the library only as a documented convention):
 """
 from __future__ import annotations
 
+import functools
+
 import numpy as np
 from numpy.polynomial import legendre as L
 
@@ -38,9 +40,14 @@ def gll_rule(p: int):
     return x, w
 
 
+@functools.lru_cache(maxsize=None)
 def gauss_rule(n: int):
-    """Gauss-Legendre nodes and weights on [-1, 1] (NumPy's routine)."""
-    return L.leggauss(n)
+    """Gauss-Legendre nodes and weights on [-1, 1] (NumPy's routine; computed once per n,
+    returned read-only)."""
+    x, w = L.leggauss(n)
+    x.setflags(write=False)
+    w.setflags(write=False)
+    return x, w
 
 
 def lagrange(nodes: np.ndarray, x: np.ndarray):

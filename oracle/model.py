@@ -69,6 +69,7 @@ class EFEModel:
         self.drop_tol = spec.enr_drop_tol if drop_tol is None else drop_tol
         self._shape_cache = {}
         self._enr_cache = {}
+        self._kin_cache = {}
         self._setup_enrichment()
         self.n_rows = m.n_nodes + self.nk
         # static potentials at every quadrature point
@@ -219,8 +220,21 @@ class EFEModel:
         v = v_q[m.q_off[c]:m.q_off[c + 1]]
         Hc = B.T @ ((w * v)[:, None] * B)
         if kinetic:
-            Hc += 0.5 * sum(G[d].T @ (w[:, None] * G[d]) for d in range(3))
+            Hc += self.kinetic_block(c)
         return Hc
+
+    def kinetic_block(self, c):
+        """1/2 int grad N . grad N on cell c: depends only on the cell's class and edge
+        lengths, formed once per (class, edges)."""
+        m = self.mesh
+        key = (bool(m.is_enr[c]), tuple(m.cell_size(c)))
+        K = self._kin_cache.get(key)
+        if K is None:
+            pts, w, B, G = self.shape(c)
+            K = 0.5 * sum(G[d].T @ (w[:, None] * G[d]) for d in range(3))
+            K.setflags(write=False)
+            self._kin_cache[key] = K
+        return K
 
     def coupling_on_cell(self, c, v_q, kinetic=True):
         """Cell c's contributions to H^ce (nloc x ne) and H^ee (ne x ne), from N^E at its points."""
@@ -305,21 +319,15 @@ class EFEModel:
         return Yr, YE
 
     def cell_blocks(self, v_q, kinetic=True):
-        """Every cell block H_c of `cell_block`, stacked (n_cells, nloc, nloc).  The
-        kinetic term depends only on a cell's class and edge lengths, so it is formed
-        once per (class, edges) and added as in `cell_block`."""
+        """Every cell block H_c of `cell_block`, stacked (n_cells, nloc, nloc)."""
         m = self.mesh
         out = np.empty((m.n_cells, m.nloc, m.nloc))
-        kin = {}
         for c in range(m.n_cells):
             pts, w, B, G = self.shape(c)
             v = v_q[m.q_off[c]:m.q_off[c + 1]]
             Hc = B.T @ ((w * v)[:, None] * B)
             if kinetic:
-                key = (bool(m.is_enr[c]), tuple(m.cell_size(c)))
-                if key not in kin:
-                    kin[key] = 0.5 * sum(G[d].T @ (w[:, None] * G[d]) for d in range(3))
-                Hc += kin[key]
+                Hc += self.kinetic_block(c)
             out[c] = Hc
         return out
 
@@ -423,7 +431,9 @@ class EFEModel:
         d = self.poisson_rhs(rho)
         rhs = 4.0 * math.pi * d[self.interior] - P["KIB"] @ g
         if solver == "direct":
-            phiI = spla.spsolve(P["KII"], rhs)
+            if "lu" not in P:
+                P["lu"] = spla.splu(P["KII"])          # K_II is fixed: factorised once
+            phiI = P["lu"].solve(rhs)
         elif solver == "cg":
             phiI, info = spla.cg(P["KII"], rhs, rtol=1e-14, atol=0.0, maxiter=20000)
             if info != 0:

@@ -16,6 +16,7 @@ import math
 import os
 
 import numpy as np
+from scipy.signal import fftconvolve
 import pytest
 
 from oracle.spectrum import absorption_spectrum, polarizability, pulse_transform, windowed_transform
@@ -66,7 +67,7 @@ def test_gaussian_pulse_convention():
     t = np.arange(0.0, 12 * tau, dt)
     E = kappa * np.exp(-((t - t0) ** 2) / (2 * s * s))
     G = N * np.sin(w0 * t) / w0
-    resp = np.convolve(G, E)[: len(t)] * dt             # mu(t) = int_0^t G(t - t') E(t') dt'
+    resp = fftconvolve(G, E)[: len(t)] * dt             # mu(t) = int_0^t G(t - t') E(t') dt'
     mu = np.zeros((len(t), 3))
     mu[:, 0] = resp
     w = np.linspace(0.1, 2.5, 40)
