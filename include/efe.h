@@ -105,8 +105,14 @@ typedef struct {
                               BF16 MFMAs per product: about 16 significant bits); or
                               EFE_F64_SF: no stored blocks, the same operator applied
                               in FP64 by sum factorisation from the potential at the
-                              points (degree 4 or 5 with the default Gauss rules only);
-                              the coupling, Lanczos, Poisson and densities stay FP64 */
+                              points (degree 4 or 5 with the default Gauss rules only).
+                              With FP32 or BF16 blocks the enrichment coupling runs on
+                              the FP32 MFMA (H^ce in FP32) and the products read an FP32
+                              copy of their input and leave their result in FP32, which
+                              the Lanczos update reads into its FP64 vectors; the
+                              Lanczos recurrence and reorthogonalisation, the
+                              tridiagonal exponential, H^ee, Poisson and the densities
+                              stay FP64 */
   int32_t kmax;            /* maximum Krylov dimension (1..64)                    */
   double krylov_tol;       /* stop when the estimate of eq. (AdaptiveKrylovErr) <= tol * ||psi|| */
   double cg_tol;           /* Poisson: relative residual                          */
@@ -196,7 +202,9 @@ efe_status efe_apply_H(efe_ctx *ctx, const void *X, void *Y, int32_t ncol, int64
 /* For callers that cannot allocate memory (code under hipGraph capture, tight
  * serving loops, harnesses that forbid hipMalloc): the same Y = Hbar X as
  * efe_apply_H with no device or host allocation, no host synchronisation and no
- * use of the context's work blocks.  X and Y: device, n_rows x ncol, PACKED
+ * use of the context's work blocks (FP64 products: bit for bit; with FP32 or BF16
+ * blocks the rows stay FP64 between the colour passes and the coupling runs in
+ * FP64, so the two agree to the precision of the products).  X and Y: device, n_rows x ncol, PACKED
  * (leading dimension = ncol), distinct, Y fully overwritten; the call returns
  * once the kernels are enqueued on the context's stream (synchronise before
  * reading Y).  The enrichment coupling's partial sums live in a static device

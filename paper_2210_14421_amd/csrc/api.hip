@@ -64,6 +64,13 @@ struct efe_ctx {
   double *phi = nullptr, *dvec = nullptr, *rhs = nullptr;
   double *cg[7] = {nullptr};
   double *part = nullptr, *hee_part = nullptr, *G = nullptr, *Hee_raw = nullptr, *Hbar_ee = nullptr;
+  // reduced-precision products (FP32 or BF16 blocks): the products read an FP32 copy of
+  // their input (xs: the current Lanczos vector, kept by the update kernels) and leave
+  // their result in yf; G32 is the coupling G in FP32.  Rows of ldf floats (ncolr
+  // rounded up to 4: 16-byte aligned rows for the direct-to-LDS copies).
+  bool mixed = false;
+  int64_t ldf = 0;
+  float *xs = nullptr, *yf = nullptr, *G32 = nullptr;
   double *hee_blk = nullptr;   // block sums of the H^ee partials
   double *psiE = nullptr, *red = nullptr, *small = nullptr, *couple_scr = nullptr;
   efe::k::DenWork den, adj_den;   // density workspaces (forward columns; adjoint column pairs)
@@ -425,6 +432,15 @@ efe_status build_device(efe_ctx *ctx) {
   EFE_TRY(dalloc(ctx, &ctx->part, tpart[d.nt]));
   EFE_TRY(dalloc(ctx, &ctx->hee_part, thee[d.nt]));
   EFE_TRY(dalloc(ctx, &ctx->G, d.nr * std::max(1, d.nk)));
+  ctx->mixed = ctx->dtype == 1 || ctx->dtype == 2 || ctx->dtype == 4;
+  if (ctx->mixed) {
+    ctx->ldf = (ctx->ncolr + 3) & ~3;
+    EFE_TRY(dalloc(ctx, &ctx->xs, ctx->n_rows * ctx->ldf));
+    EFE_TRY(dalloc(ctx, &ctx->yf, ctx->n_rows * ctx->ldf));
+    EFE_TRY(dalloc(ctx, &ctx->G32, d.nr * std::max(1, d.nk)));
+    HIP_TRY(hipMemset(ctx->xs, 0, (size_t)ctx->n_rows * ctx->ldf * sizeof(float)));
+    HIP_TRY(hipMemset(ctx->yf, 0, (size_t)ctx->n_rows * ctx->ldf * sizeof(float)));
+  }
   EFE_TRY(dalloc(ctx, &ctx->Hee_raw, (int64_t)d.ne * d.ne));
   EFE_TRY(dalloc(ctx, &ctx->hee_blk, std::max<int64_t>(1, efe::k::hee_scratch_size(d))));
   EFE_TRY(dalloc(ctx, &ctx->Hbar_ee, (int64_t)d.nk * d.nk));
@@ -496,13 +512,41 @@ void cell_products(efe_ctx *ctx, const double *X, double *Y, int ncolr, int64_t 
   else efe::k::cell_apply(d, ctx->cells, ctx->dtype, X, Y, ncolr, ldr, s, any, v);
 }
 
-// Y = A X with the operator currently held in the cell blocks (rows with stride ldr doubles)
+// The same with FP32 rows (reduced-precision products: FP32 or BF16 blocks)
+void cell_products_f(efe_ctx *ctx, const float *X, float *Y, int ncolr, hipStream_t s, const int *any,
+                     int variant = -1) {
+  const int v = variant >= 0 ? variant : ctx->cell_variant;
+  efe::k::cell_apply_f(ctx->d, ctx->cells, ctx->dtype, X, Y, ncolr, ctx->ldf, s, any, v);
+}
+
+// yf = A xs: the reduced-precision products on the FP32 copy of their input
+efe_status apply_op_f(efe_ctx *ctx, int ncolr, const int *any) {
+  hipStream_t s = ctx->stream;
+  tstart(ctx, 0);
+  cell_products_f(ctx, ctx->xs, ctx->yf, ncolr, s, any);
+  tstop(ctx, 0);
+  tstart(ctx, 1);
+  efe::k::couple_apply_f(ctx->d, ctx->G32, ctx->Hbar_ee, ctx->xs, ctx->yf, ncolr, ctx->ldf, ctx->couple_scr, s, any);
+  tstop(ctx, 1);
+  ctx->timer.n_hx++;
+  return check_launch(ctx, "apply");
+}
+
+// Y = A X with the operator currently held in the cell blocks (packed rows); reduced-
+// precision products go through the FP32 copies, so that this is the operator the
+// propagation applies
 efe_status apply_op(efe_ctx *ctx, const double *X, double *Y, int ncolr, int64_t ldr, const int *any = nullptr) {
   const DevData &d = ctx->d;
   hipStream_t s = ctx->stream;
   if (ldr != ncolr) {
     ctx->err = "internal: apply_op expects packed blocks";
     return EFE_ERR_ARG;
+  }
+  if (ctx->mixed && ctx->dtype != 3) {
+    efe::k::to_f32(X, ctx->n_rows, ncolr, ctx->xs, ctx->ldf, s);
+    EFE_TRY(apply_op_f(ctx, ncolr, any));
+    efe::k::from_f32(ctx->yf, ctx->ldf, ctx->n_rows, ncolr, Y, s);
+    return check_launch(ctx, "apply");
   }
   tstart(ctx, 0);
   cell_products(ctx, X, Y, ncolr, ldr, s, any);
@@ -604,6 +648,7 @@ efe_status rebuild(efe_ctx *ctx, int mode, const double *rho, double t, const ef
   efe::k::rebuild_cells(d, mode, rho, ctx->phi, ctx->stepp + 2, fdir, ctx->plan.xc, ctx->cells, ctx->dtype, ctx->vq, s);
   efe::k::coupling_partials(d, ctx->vq, ctx->part, ctx->hee_part, s);
   efe::k::coupling_gather(d, ctx->part, mode == 0 ? 1 : 0, ctx->G, s);
+  if (ctx->mixed) efe::k::to_f32(ctx->G, d.nr, d.nk, ctx->G32, d.nk, s);
   efe::k::hee_reduce(d, ctx->hee_part, mode == 0 ? 1 : 0, ctx->Hee_raw, ctx->Hbar_ee, ctx->hee_blk, s);
   tstop(ctx, 6);
   ctx->cells_mode = mode;
@@ -640,7 +685,11 @@ efe_status lz_iteration(efe_ctx *ctx, double tau, const double *X, int ncol, int
   double *Qb = ctx->Q;
   const double *prev = j == 1 ? X : Qb + (int64_t)(j - 2) * bs;
   double *w = Qb + (int64_t)(j - 1) * bs;   // slot j
-  EFE_TRY(apply_op(ctx, prev, w, ncolr, ncolr, any));
+  // reduced-precision products: xs holds slot j - 1 in FP32 and the product goes to yf,
+  // which the first update reads into slot j (writing the next xs)
+  const bool mx = ctx->mixed;
+  if (mx) EFE_TRY(apply_op_f(ctx, ncolr, any));
+  else EFE_TRY(apply_op(ctx, prev, w, ncolr, ncolr, any));
   tstart(ctx, 2);
   double *a_j = ctx->alpha + (int64_t)(j - 1) * ncol;
   double *b_j = ctx->beta + (int64_t)(j - 1) * ncol;
@@ -655,15 +704,20 @@ efe_status lz_iteration(efe_ctx *ctx, double tau, const double *X, int ncol, int
   int nb;
   if (partial) {
     const double *q0d = j == 1 ? X : Qb + (int64_t)(j - 2) * bs;   // slot j - 1
-    nb = efe::k::lz_dots(q0d, Qb + (int64_t)(j - 1) * bs, bs, 1, w, nrows, ncol, ctx->active, any, 1, ctx->red, s);
+    nb = mx ? efe::k::lz_dots_f(q0d, Qb + (int64_t)(j - 1) * bs, bs, 1, ctx->yf, ctx->ldf, nrows, ncol, ctx->active,
+                                any, 1, ctx->red, s)
+            : efe::k::lz_dots(q0d, Qb + (int64_t)(j - 1) * bs, bs, 1, w, nrows, ncol, ctx->active, any, 1, ctx->red, s);
     efe::k::reduce_partials(ctx->red, nb, 2 * ncolr, ctx->h1, s);
     efe::k::lz_coef3(ctx->h1, ctx->sig, ctx->beta, j, ncol, ctx->active, a_j, ctx->coef, ctx->gsc, ctx->msc, s);
   } else {
-    nb = efe::k::lz_dots(q0f, qbf, bs, nq, w, nrows, ncol, ctx->active, any, 1, ctx->red, s);
+    nb = mx ? efe::k::lz_dots_f(q0f, qbf, bs, nq, ctx->yf, ctx->ldf, nrows, ncol, ctx->active, any, 1, ctx->red, s)
+            : efe::k::lz_dots(q0f, qbf, bs, nq, w, nrows, ncol, ctx->active, any, 1, ctx->red, s);
     efe::k::reduce_partials(ctx->red, nb, (nq + 1) * ncolr, ctx->h1, s);
     efe::k::lz_coef1(ctx->h1, ctx->sig, j, first, ncol, ctx->active, a_j, ctx->coef, ctx->gsc, ctx->msc, s);
   }
-  nb = efe::k::lz_update(q0f, qbf, bs, nq, ctx->coef, ctx->gsc, w, nrows, ncol, ctx->active, any, ctx->red, s, 1);
+  nb = mx ? efe::k::lz_update_from(q0f, qbf, bs, nq, ctx->coef, ctx->gsc, ctx->yf, ctx->ldf, w, ctx->xs, nrows, ncol,
+                                   ctx->active, any, ctx->red, s, 1)
+          : efe::k::lz_update(q0f, qbf, bs, nq, ctx->coef, ctx->gsc, w, nrows, ncol, ctx->active, any, ctx->red, s, 1);
   efe::k::reduce_partials(ctx->red, nb, ncolr, ctx->nrm1, s);
   if (partial)
     efe::k::lz_pro(ctx->nrm1, ctx->msc, ctx->alpha, ctx->beta, j, ncol, ctx->active, ctx->pro, ctx->need,
@@ -673,7 +727,8 @@ efe_status lz_iteration(efe_ctx *ctx, double tau, const double *X, int ncol, int
   nb = efe::k::lz_dots(X, Qb, bs, j, w, nrows, ncol, ctx->need, ctx->anyflag, 0, ctx->red, s);
   efe::k::reduce_partials(ctx->red, nb, j * ncolr, ctx->h2n, s);
   efe::k::lz_coef2(ctx->h2n, ctx->nrm1, ctx->sig, j, ncol, ctx->need, ctx->coef, ctx->gsc, ctx->msc, s);
-  nb = efe::k::lz_update(X, Qb, bs, j, ctx->coef, ctx->gsc, w, nrows, ncol, ctx->need, ctx->anyflag, ctx->red, s);
+  nb = efe::k::lz_update(X, Qb, bs, j, ctx->coef, ctx->gsc, w, nrows, ncol, ctx->need, ctx->anyflag, ctx->red, s, 0,
+                         mx ? ctx->xs : nullptr, ctx->ldf);
   efe::k::reduce_partials(ctx->red, nb, ncolr, ctx->nrm2, s);
   efe::k::lz_beta(ctx->nrm1, ctx->nrm2, ctx->need, ctx->active, ctx->msc, j, ncol, b_j, ctx->sig, s);
   tstop(ctx, 2);
@@ -714,6 +769,7 @@ efe_status run_lanczos(efe_ctx *ctx, double tau, const double *X, double *out, i
   int nb = efe::k::lz_dots(X, Qb, bs, 0, X, nrows, ncol, ctx->one_mask, nullptr, 1, ctx->red, s);
   efe::k::reduce_partials(ctx->red, nb, ncolr, ctx->small, s);
   efe::k::lz_init(ctx->small, ncol, ctx->beta0, ctx->sig, ctx->active, ctx->kused, ctx->pro, s);
+  if (ctx->mixed) efe::k::to_f32(X, nrows, ncolr, ctx->xs, ctx->ldf, s);
   tstop(ctx, 2);
   efe::k::lz_any(ctx->active, ncol, ctx->lz_anyf, s);
   std::vector<double> b0h(ncol);
@@ -811,6 +867,7 @@ efe_status run_lanczos_dev(efe_ctx *ctx, double tau, const double *X, double *ou
   int nb = efe::k::lz_dots(X, ctx->Q, bs, 0, X, nrows, ncol, ctx->one_mask, nullptr, 1, ctx->red, s);
   efe::k::reduce_partials(ctx->red, nb, ncolr, ctx->small, s);
   efe::k::lz_init(ctx->small, ncol, ctx->beta0, ctx->sig, ctx->active, ctx->kused, ctx->pro, s);
+  if (ctx->mixed) efe::k::to_f32(X, nrows, ncolr, ctx->xs, ctx->ldf, s);
   efe::k::lz_any(ctx->active, ncol, ctx->lz_anyf, s);
   for (int j = 1; j <= ctx->kmax; ++j) EFE_TRY(lz_iteration(ctx, tau, X, ncol, j, nullptr, tol, ctx->lz_anyf));
   efe::k::lz_comb_coef(ctx->ubuf, ctx->sig, ctx->beta0, ctx->kused, ctx->kmax, ctx->kmax, ncol, ctx->coef, s);
@@ -869,6 +926,7 @@ efe_status rebuild_dev(efe_ctx *ctx, const double *rho, const double *efield, in
   efe::k::rebuild_cells(d, 0, rho, ctx->phi, efield, fdir, ctx->plan.xc, ctx->cells, ctx->dtype, ctx->vq, s);
   efe::k::coupling_partials(d, ctx->vq, ctx->part, ctx->hee_part, s);
   efe::k::coupling_gather(d, ctx->part, 1, ctx->G, s);
+  if (ctx->mixed) efe::k::to_f32(ctx->G, d.nr, d.nk, ctx->G32, d.nk, s);
   efe::k::hee_reduce(d, ctx->hee_part, 1, ctx->Hee_raw, ctx->Hbar_ee, ctx->hee_blk, s);
   return check_launch(ctx, "device rebuild");
 }
@@ -1943,7 +2001,7 @@ efe_status efe_autotune(efe_ctx *ctx, const char *cache_path, int32_t flags, cha
   std::ostringstream key;
   key << prop.gcnArchName << " cu" << prop.multiProcessorCount << " p" << d.g.p << " nloc" << d.g.nloc << " q"
       << d.g.qc << "," << d.g.qe << " ncolr" << ctx->ncolr << " dtype" << ctx->dtype << " cells"
-      << ctx->plan.n_cells << " enr" << d.nk;
+      << ctx->plan.n_cells << " enr" << d.nk << (ctx->mixed ? " io32" : "");
   const std::string k = key.str();
   std::vector<std::string> lines;   // entries of the cache file, one per line
   int chosen = -1;
@@ -1973,10 +2031,24 @@ efe_status efe_autotune(efe_ctx *ctx, const char *cache_path, int32_t flags, cha
     rep << "choice=" << names[chosen] << " cached=1";
   } else {
     // time every candidate on the context's own operator and orbitals (X0 holds the orbitals
-    // of the last efe_set_hamiltonian), each checked against the default shape's result
+    // of the last efe_set_hamiltonian), each checked against the default shape's result;
+    // reduced-precision products are timed as the propagation runs them, on FP32 rows
     const int ncolr = ctx->ncolr;
     double *X = ctx->X0, *Y = ctx->X1, *Yref = ctx->Q;
     const int64_t n = ctx->plan.n_nodes * ncolr;   // the cell products write the classical rows only
+    if (ctx->mixed) efe::k::to_f32(X, ctx->n_rows, ncolr, ctx->xs, ctx->ldf, s);
+    auto apply = [&](int v, double *out) {   // one application of shape v, result in out (FP64)
+      if (ctx->mixed) {
+        cell_products_f(ctx, ctx->xs, ctx->yf, ncolr, s, nullptr, v);
+        efe::k::from_f32(ctx->yf, ctx->ldf, ctx->plan.n_nodes, ncolr, out, s);
+      } else {
+        cell_products(ctx, X, out, ncolr, ncolr, s, nullptr, v);
+      }
+    };
+    auto timed = [&](int v) {
+      if (ctx->mixed) cell_products_f(ctx, ctx->xs, ctx->yf, ncolr, s, nullptr, v);
+      else cell_products(ctx, X, Y, ncolr, ncolr, s, nullptr, v);
+    };
     // squared 2-norm of a block on the device (fixed-order partial sums)
     auto norm2 = [&](const double *a, double &out) -> efe_status {
       const int nb = efe::k::dot_partials(a, a, n, ctx->red, s);
@@ -1984,7 +2056,7 @@ efe_status efe_autotune(efe_ctx *ctx, const char *cache_path, int32_t flags, cha
       HIP_TRY(hipMemcpyAsync(&out, ctx->small, sizeof(double), hipMemcpyDeviceToHost, s));
       return sync(ctx, "autotune check");
     };
-    cell_products(ctx, X, Yref, ncolr, ncolr, s, nullptr, cand[0]);
+    apply(cand[0], Yref);
     double rr = 0.0;
     EFE_TRY(norm2(Yref, rr));
     std::vector<double> tus(cand.size(), 0.0);
@@ -1994,7 +2066,7 @@ efe_status efe_autotune(efe_ctx *ctx, const char *cache_path, int32_t flags, cha
     const int reps = 3;
     int best = 0;
     for (size_t i = 0; i < cand.size(); ++i) {
-      cell_products(ctx, X, Y, ncolr, ncolr, s, nullptr, cand[i]);   // warm-up and check
+      apply(cand[i], Y);   // warm-up and check
       efe::k::axpby(Y, Yref, 1.0, -1.0, Y, n, s);
       double dd = 0.0;
       EFE_TRY(norm2(Y, dd));
@@ -2005,7 +2077,7 @@ efe_status efe_autotune(efe_ctx *ctx, const char *cache_path, int32_t flags, cha
         continue;
       }
       HIP_TRY(hipEventRecord(e0, s));
-      for (int r = 0; r < reps; ++r) cell_products(ctx, X, Y, ncolr, ncolr, s, nullptr, cand[i]);
+      for (int r = 0; r < reps; ++r) timed(cand[i]);
       HIP_TRY(hipEventRecord(e1, s));
       HIP_TRY(hipEventSynchronize(e1));
       float ms = 0.f;

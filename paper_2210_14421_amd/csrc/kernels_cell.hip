@@ -1,7 +1,9 @@
 // Cell part of Hbar X (Sec. 2.3, eq. (TDKSDiscrete2)): Y = sum_c P_c^T Hbar_c P_c X
 // with the dense symmetric cell blocks Hbar_c = D_c^-1/2 (K_c / 2 + V_c) D_c^-1/2, on the
 // 16x16x4 MFMA (FP64, or FP32 blocks with FP32 accumulation); BF16 products are in
-// kernels_cell_bf16.hip.
+// kernels_cell_bf16.hip.  The orbital rows X and Y are FP64, or, for the FP32 blocks,
+// also FP32 (the reduced-precision product reads an FP32 copy of X and leaves its
+// FP32-accurate result in FP32: half the gathered and scattered bytes).
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
@@ -58,8 +60,10 @@ template <> struct Mfma<float> {
 constexpr int kCellWaves = 8;
 constexpr int kCellNT = 3;                  // N tiles per wave
 constexpr int kCellCols = 2 * kCellNT * 16; // columns per workgroup
-constexpr int kCellLDX = 112;               // LDS row stride of X (doubles): the 4 rows of a B read hit disjoint banks
-template <int KC> constexpr int x_stage() { return KC * kCellLDX * 8; }
+// LDS row stride of X in elements: the 4 rows of a B read hit disjoint banks
+// (FP64 rows: 112 doubles; FP32 rows: 144 floats, 16 banks apart)
+template <typename IO> constexpr int x_ldx() { return sizeof(IO) == 8 ? 112 : 144; }
+template <int KC, typename IO> constexpr int x_stage() { return KC * x_ldx<IO>() * (int)sizeof(IO); }
 
 // s_waitcnt with vmcnt = N and no wait on the other counters (gfx9 encoding)
 template <int N>
@@ -83,21 +87,26 @@ struct CellChunk {
   static constexpr int kPer = kAIns + kXIns;                         // copies per wave per chunk
 };
 
-inline size_t cell_lds_bytes(int nloc, size_t esz, int ns, int kc) {
+inline size_t cell_lds_bytes(int nloc, size_t esz, int ns, int kc, size_t xsz = 8) {
   const size_t aseg = ((size_t)kc * nloc * esz + 1023) / 1024;
-  return (size_t)ns * (aseg * 1024 + (size_t)kc * kCellLDX * 8) + 1024;
+  const size_t xrow = xsz == 8 ? (size_t)x_ldx<double>() * 8 : (size_t)x_ldx<float>() * 4;
+  return (size_t)ns * (aseg * 1024 + (size_t)kc * xrow) + 1024;
 }
 
-template <typename T, int CMT, int NS, int KC, int WPE>
+// IO: element type of X and Y (double, or float for FP32 blocks); ldr counts IO elements.
+template <typename T, typename IO, int CMT, int NS, int KC, int WPE>
 __global__ void __launch_bounds__(kCellWaves * 64) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, const T *__restrict__ cells,
-             const double *__restrict__ X, double *__restrict__ Y, int ncolr, int64_t ldr, const int *__restrict__ any) {
+             const IO *__restrict__ X, IO *__restrict__ Y, int ncolr, int64_t ldr, const int *__restrict__ any) {
   static_assert(KC % 4 == 0 && NS >= 2, "chunks of whole k-steps, at least one in flight");
+  static_assert(sizeof(IO) >= sizeof(T), "X and Y at least as wide as the blocks");
   if (any && *any == 0) return;
   typedef typename Mfma<T>::C C;
   typedef typename Mfma<T>::Acc Acc;
   constexpr int kAIns = CellChunk<T, KC>::kAIns, kXIns = CellChunk<T, KC>::kXIns, kPer = CellChunk<T, KC>::kPer;
-  constexpr int kXStage = x_stage<KC>();
+  constexpr int kXStage = x_stage<KC, IO>();
+  constexpr int kLDX = x_ldx<IO>();
+  constexpr int kEPL = 16 / (int)sizeof(IO);   // elements of an X row per 16-byte copy
   __shared__ int64_t rowoff[kApplyMaxLoc];
   __shared__ unsigned char first[kApplyMaxLoc];   // this cell's colour is the first to reach the node
   extern __shared__ __attribute__((aligned(16))) unsigned char cell_sm[];
@@ -152,7 +161,8 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
       const int r = wave + kCellWaves * i;
       const int k = kc * KC + r;
       if (r < KC && k < nloc) {
-        if (2 * lane < wcol) copy16_to_lds(X + rowoff[k] + col0 + 2 * lane, Xs + st * kXStage + r * kCellLDX * 8);
+        if (kEPL * lane < wcol)
+          copy16_to_lds(X + rowoff[k] + col0 + kEPL * lane, Xs + st * kXStage + r * kLDX * (int)sizeof(IO));
       } else {
         copy16_to_lds(X, junk);
       }
@@ -175,7 +185,7 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
     if (kc + NS - 1 < nchunk) issue(kc + NS - 1);
     const int st = kc % NS;
     const T *Al = (const T *)(As + st * aseg * 1024);
-    const double *Xl = (const double *)(Xs + st * kXStage);
+    const IO *Xl = (const IO *)(Xs + st * kXStage);
     // per k-step: the step's operands first (one LDS wait), then its MFMAs.  Rows m past
     // nloc read neighbouring LDS words: they only reach output rows that are never stored.
     // k-rows past nloc (last chunk) are zeroed, as their X rows are not copied.
@@ -185,7 +195,7 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
       const bool kok = kc * KC + kl < nloc;
       C b[kCellNT], a[CMT];
 #pragma unroll
-      for (int j = 0; j < kCellNT; ++j) b[j] = (C)Xl[kl * kCellLDX + (nh * kCellNT + j) * 16 + cl];
+      for (int j = 0; j < kCellNT; ++j) b[j] = (C)Xl[kl * kLDX + (nh * kCellNT + j) * 16 + cl];
 #pragma unroll
       for (int i = 0; i < CMT; ++i) {
         const int t = min(mg + 4 * i, nmt - 1);
@@ -210,43 +220,43 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
     if (mg + 4 * i >= nmt) continue;
 #pragma unroll
     for (int r0 = 0; r0 < 4; r0 += kRB) {
-      double old[kRB][kCellNT];
+      IO old[kRB][kCellNT];
 #pragma unroll
       for (int r = 0; r < kRB; ++r) {
         const int row = (mg + 4 * i) * 16 + Mfma<T>::row(kr, r0 + r);
         const bool add = row < nloc && !first[row];
-        const double *yr = Y + (row < nloc ? rowoff[row] : 0);
+        const IO *yr = Y + (row < nloc ? rowoff[row] : 0);
 #pragma unroll
         for (int j = 0; j < kCellNT; ++j) {
           const int col = col0 + (nh * kCellNT + j) * 16 + cl;
-          old[r][j] = (add && col < ncolr) ? yr[col] : 0.0;
+          old[r][j] = (add && col < ncolr) ? yr[col] : (IO)0;
         }
       }
 #pragma unroll
       for (int r = 0; r < kRB; ++r) {
         const int row = (mg + 4 * i) * 16 + Mfma<T>::row(kr, r0 + r);
         if (row >= nloc) continue;
-        double *yr = Y + rowoff[row];
+        IO *yr = Y + rowoff[row];
 #pragma unroll
         for (int j = 0; j < kCellNT; ++j) {
           const int col = col0 + (nh * kCellNT + j) * 16 + cl;
-          if (col < ncolr) yr[col] = old[r][j] + (double)acc[i][j][r0 + r];
+          if (col < ncolr) yr[col] = old[r][j] + (IO)acc[i][j][r0 + r];
         }
       }
     }
   }
 }
 
-template <typename T, int CMT, int NS, int KC, int WPE = (CMT <= 4 ? 4 : 2)>
-void launch_apply_m(const DevData &d, const T *cells, const double *X, double *Y, int ncolr, int64_t ldr,
+template <typename T, int CMT, int NS, int KC, int WPE = (CMT <= 4 ? 4 : 2), typename IO>
+void launch_apply_m(const DevData &d, const T *cells, const IO *X, IO *Y, int ncolr, int64_t ldr,
                     hipStream_t s, const int *any) {
   const unsigned ny = (unsigned)((ncolr + kCellCols - 1) / kCellCols);
-  const size_t lds = cell_lds_bytes(d.g.nloc, sizeof(T), NS, KC);
+  const size_t lds = cell_lds_bytes(d.g.nloc, sizeof(T), NS, KC, sizeof(IO));
   for (int c = 0; c < 8; ++c) {
     const int cnt = d.colour_off[c + 1] - d.colour_off[c];
     if (cnt == 0) continue;
     const int *list = d.colour_cells + d.colour_off[c];
-    hipLaunchKernelGGL((k_cell_apply<T, CMT, NS, KC, WPE>), dim3((unsigned)cnt, ny), dim3(kCellWaves * 64), lds, s, d,
+    hipLaunchKernelGGL((k_cell_apply<T, IO, CMT, NS, KC, WPE>), dim3((unsigned)cnt, ny), dim3(kCellWaves * 64), lds, s, d,
                        list, d.colour_off[c], cells, X, Y, ncolr, ldr, any);
   }
 }
@@ -261,14 +271,14 @@ constexpr int kVarNS[kCellVariants] = {3, 2, 4, 2, 6, 4, 3, 2, 2};
 constexpr int kVarKC[kCellVariants] = {8, 8, 4, 16, 4, 8, 8, 8, 16};
 constexpr int kVarWPE[kCellVariants] = {4, 4, 4, 4, 4, 4, 6, 6, 6};
 
-template <typename T, int CMT, int V>
-void launch_v(const DevData &d, const T *cells, const double *X, double *Y, int ncolr, int64_t ldr, hipStream_t s,
+template <typename T, int CMT, int V, typename IO>
+void launch_v(const DevData &d, const T *cells, const IO *X, IO *Y, int ncolr, int64_t ldr, hipStream_t s,
               const int *any) {
   launch_apply_m<T, CMT, kVarNS[V], kVarKC[V], (CMT <= 4 ? kVarWPE[V] : 2)>(d, cells, X, Y, ncolr, ldr, s, any);
 }
 
-template <typename T, int CMT>
-void launch_variant(int v, const DevData &d, const T *cells, const double *X, double *Y, int ncolr, int64_t ldr,
+template <typename T, int CMT, typename IO>
+void launch_variant(int v, const DevData &d, const T *cells, const IO *X, IO *Y, int ncolr, int64_t ldr,
                     hipStream_t s, const int *any) {
   switch (v) {
     case 1: launch_v<T, CMT, 1>(d, cells, X, Y, ncolr, ldr, s, any); break;
@@ -283,8 +293,8 @@ void launch_variant(int v, const DevData &d, const T *cells, const double *X, do
   }
 }
 
-template <typename T>
-void launch_apply(const DevData &d, const T *cells, const double *X, double *Y, int ncolr, int64_t ldr, hipStream_t s,
+template <typename T, typename IO>
+void launch_apply(const DevData &d, const T *cells, const IO *X, IO *Y, int ncolr, int64_t ldr, hipStream_t s,
                   const int *any, int v) {
   const int nmt = (d.g.nloc + 15) / 16;     // M tiles per cell; wave group w >> 1 takes ceil(nmt / 4)
   if (nmt <= 8) launch_variant<T, 2>(v, d, cells, X, Y, ncolr, ldr, s, any);
@@ -292,21 +302,27 @@ void launch_apply(const DevData &d, const T *cells, const double *X, double *Y, 
   else launch_apply_m<T, 6, 3, 8>(d, cells, X, Y, ncolr, ldr, s, any);
 }
 
-template <typename T, int CMT, int V>
+template <typename T, typename IO, int CMT, int V>
 int set_lds_v(size_t esz, int nloc) {
-  return (int)hipFuncSetAttribute((const void *)k_cell_apply<T, CMT, kVarNS[V], kVarKC[V], kVarWPE[V]>,
+  return (int)hipFuncSetAttribute((const void *)k_cell_apply<T, IO, CMT, kVarNS[V], kVarKC[V], kVarWPE[V]>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)cell_lds_bytes(nloc, esz, kVarNS[V], kVarKC[V]));
+                                  (int)cell_lds_bytes(nloc, esz, kVarNS[V], kVarKC[V], sizeof(IO)));
+}
+
+template <typename T, typename IO, int CMT>
+int set_lds_io(int nloc) {
+  const size_t e = sizeof(T);
+  int st = set_lds_v<T, IO, CMT, 0>(e, nloc) | set_lds_v<T, IO, CMT, 1>(e, nloc) | set_lds_v<T, IO, CMT, 2>(e, nloc) |
+           set_lds_v<T, IO, CMT, 3>(e, nloc) | set_lds_v<T, IO, CMT, 4>(e, nloc) | set_lds_v<T, IO, CMT, 5>(e, nloc);
+  if (sizeof(T) == 4)
+    st |= set_lds_v<T, IO, CMT, 6>(e, nloc) | set_lds_v<T, IO, CMT, 7>(e, nloc) | set_lds_v<T, IO, CMT, 8>(e, nloc);
+  return st;
 }
 
 template <typename T, int CMT>
 int set_lds_all(int nloc) {
-  const size_t e = sizeof(T);
-  int st = set_lds_v<T, CMT, 0>(e, nloc) | set_lds_v<T, CMT, 1>(e, nloc) | set_lds_v<T, CMT, 2>(e, nloc) |
-           set_lds_v<T, CMT, 3>(e, nloc) | set_lds_v<T, CMT, 4>(e, nloc) | set_lds_v<T, CMT, 5>(e, nloc);
-  if (sizeof(T) == 4)
-    st |= set_lds_v<T, CMT, 6>(e, nloc) | set_lds_v<T, CMT, 7>(e, nloc) | set_lds_v<T, CMT, 8>(e, nloc);
-  return st;
+  if constexpr (sizeof(T) == 4) return set_lds_io<T, double, CMT>(nloc) | set_lds_io<T, float, CMT>(nloc);
+  else return set_lds_io<T, double, CMT>(nloc);
 }
 
 }  // namespace
@@ -335,19 +351,27 @@ int cell_apply_init(int nloc) {
   } else if (nmt <= 16) {
     st |= set_lds_all<double, 4>(nloc) | set_lds_all<float, 4>(nloc);
   } else {
-    st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<double, 6, 3, 8, 2>,
+    st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<double, double, 6, 3, 8, 2>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)cell_lds_bytes(nloc, 8, 3, 8));
-    st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<float, 6, 3, 8, 2>,
+    st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<float, double, 6, 3, 8, 2>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)cell_lds_bytes(nloc, 4, 3, 8));
+    st |= (int)hipFuncSetAttribute((const void *)k_cell_apply<float, float, 6, 3, 8, 2>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)cell_lds_bytes(nloc, 4, 3, 8, 4));
   }
   return st | cell_bf16_init(nloc);
 }
 
 void cell_apply(const DevData &d, const void *cells, int dtype, const double *X, double *Y, int ncolr, int64_t ldr,
                 hipStream_t s, const int *any, int variant) {
-  if (dtype == 0) launch_apply<double>(d, (const double *)cells, X, Y, ncolr, ldr, s, any, variant);
-  else if (dtype == 1) launch_apply<float>(d, (const float *)cells, X, Y, ncolr, ldr, s, any, variant);
+  if (dtype == 0) launch_apply<double, double>(d, (const double *)cells, X, Y, ncolr, ldr, s, any, variant);
+  else if (dtype == 1) launch_apply<float, double>(d, (const float *)cells, X, Y, ncolr, ldr, s, any, variant);
   else cell_apply_bf16(d, (const uint16_t *)cells, dtype == 4 ? 2 : 1, X, Y, ncolr, ldr, s, any, variant);
+}
+
+void cell_apply_f(const DevData &d, const void *cells, int dtype, const float *X, float *Y, int ncolr, int64_t ldf,
+                  hipStream_t s, const int *any, int variant) {
+  if (dtype == 1) launch_apply<float, float>(d, (const float *)cells, X, Y, ncolr, ldf, s, any, variant);
+  else cell_apply_bf16_f(d, (const uint16_t *)cells, dtype == 4 ? 2 : 1, X, Y, ncolr, ldf, s, any, variant);
 }
 
 }  // namespace k

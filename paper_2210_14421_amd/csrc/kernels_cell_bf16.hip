@@ -5,6 +5,9 @@
 // (hi = bf16(x), lo = bf16(x - hi)) and adds hi*hi + hi*lo + lo*hi: three MFMAs
 // per product, about 16 significant bits.
 //
+// X and Y are FP64, or FP32 (the reduced-precision product reads an FP32 copy of X
+// and leaves its result in FP32).
+//
 // Storage of the blocks (both forms): row r of a cell's block at r * lda with lda =
 // nloc rounded up to 8 elements (every 8-element chunk of a row is one aligned 16-byte
 // copy), nloc * lda elements per plane; the split form stores the hi plane, then
@@ -61,10 +64,10 @@ inline size_t bf16_lds_bytes(int mmax, int planes) {
 // into registers, rounded to BF16, written transposed).  MMAX: rows of A staged (nloc
 // rounded up to whole M tiles); PL: 1 (BF16) or 2 (split); NPW 3 (8 waves) or 2 (12
 // waves, fewer registers per wave: three waves per SIMD for each of two workgroups).
-template <int MMAX, int CMT, int PL, int NPW, int WPE>
+template <int MMAX, int CMT, int PL, int NPW, int WPE, typename IO>
 __global__ void __launch_bounds__(4 * (6 / NPW) * 64) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_cell_bf16(const DevData d, const int *__restrict__ cell_list, int slot0, const uint16_t *__restrict__ cells,
-            const double *__restrict__ X, double *__restrict__ Y, int ncolr, int64_t ldr, const int *__restrict__ any) {
+            const IO *__restrict__ X, IO *__restrict__ Y, int ncolr, int64_t ldr, const int *__restrict__ any) {
   static_assert(MMAX % 16 == 0 && (MMAX / 16 + 3) / 4 <= CMT, "M tiles per wave");
   static_assert(NPW == 2 || NPW == 3, "N tiles per wave");
   constexpr int G = 6 / NPW;                   // N groups
@@ -137,12 +140,12 @@ k_cell_bf16(const DevData d, const int *__restrict__ cell_list, int slot0, const
   // split) to BF16
   const int xn = tid % kBCols, xq = (tid / kBCols) % 4, xp = tid / (4 * kBCols);
   const bool xthr = tid < 4 * kBCols * H;
-  double xv[XV];
+  IO xv[XV];
   auto loadX = [&](int s) {
 #pragma unroll
     for (int j = 0; j < XV; ++j) {
       const int k = 32 * s + 8 * xq + XV * xp + j;
-      xv[j] = (xthr && xn < wcol && k < nloc) ? X[rowoff[k] + col0 + xn] : 0.0;
+      xv[j] = (xthr && xn < wcol && k < nloc) ? X[rowoff[k] + col0 + xn] : (IO)0;
     }
   };
   auto writeX = [&](int st) {
@@ -222,34 +225,34 @@ k_cell_bf16(const DevData d, const int *__restrict__ cell_list, int slot0, const
   for (int i = 0; i < CMT; ++i) {
     const int t = mg + 4 * i;
     if (t >= nmt) continue;
-    double old[4][NPW];
+    IO old[4][NPW];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = 16 * t + 4 * kg + r;
       const bool add = row < nloc && !first[row];
-      const double *yr = Y + (row < nloc ? rowoff[row] : 0);
+      const IO *yr = Y + (row < nloc ? rowoff[row] : 0);
 #pragma unroll
       for (int j = 0; j < NPW; ++j) {
         const int col = col0 + 16 * (NPW * ng + j) + cl;
-        old[r][j] = (add && col < ncolr) ? yr[col] : 0.0;
+        old[r][j] = (add && col < ncolr) ? yr[col] : (IO)0;
       }
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = 16 * t + 4 * kg + r;
       if (row >= nloc) continue;
-      double *yr = Y + rowoff[row];
+      IO *yr = Y + rowoff[row];
 #pragma unroll
       for (int j = 0; j < NPW; ++j) {
         const int col = col0 + 16 * (NPW * ng + j) + cl;
-        if (col < ncolr) yr[col] = old[r][j] + (double)acc[i][j][r];
+        if (col < ncolr) yr[col] = old[r][j] + (IO)acc[i][j][r];
       }
     }
   }
 }
 
-template <int MMAX, int CMT, int PL, int NPW, int WPE>
-void launch_bf16(const DevData &d, const uint16_t *cells, const double *X, double *Y, int ncolr, int64_t ldr,
+template <int MMAX, int CMT, int PL, int NPW, int WPE, typename IO>
+void launch_bf16(const DevData &d, const uint16_t *cells, const IO *X, IO *Y, int ncolr, int64_t ldr,
                  hipStream_t s, const int *any) {
   const unsigned ny = (unsigned)((ncolr + kBCols - 1) / kBCols);
   const size_t lds = bf16_lds_bytes(MMAX, PL);
@@ -257,7 +260,7 @@ void launch_bf16(const DevData &d, const uint16_t *cells, const double *X, doubl
     const int cnt = d.colour_off[c + 1] - d.colour_off[c];
     if (cnt == 0) continue;
     const int *list = d.colour_cells + d.colour_off[c];
-    hipLaunchKernelGGL((k_cell_bf16<MMAX, CMT, PL, NPW, WPE>), dim3((unsigned)cnt, ny), dim3(4 * (6 / NPW) * 64), lds,
+    hipLaunchKernelGGL((k_cell_bf16<MMAX, CMT, PL, NPW, WPE, IO>), dim3((unsigned)cnt, ny), dim3(4 * (6 / NPW) * 64), lds,
                        s, d, list,
                        d.colour_off[c], cells, X, Y, ncolr, ldr, any);
   }
@@ -265,14 +268,16 @@ void launch_bf16(const DevData &d, const uint16_t *cells, const double *X, doubl
 
 template <int MMAX, int CMT, int PL, int NPW, int WPE>
 int set_lds_bf16() {
-  return (int)hipFuncSetAttribute((const void *)k_cell_bf16<MMAX, CMT, PL, NPW, WPE>,
+  return (int)hipFuncSetAttribute((const void *)k_cell_bf16<MMAX, CMT, PL, NPW, WPE, double>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bf16_lds_bytes(MMAX, PL)) |
+         (int)hipFuncSetAttribute((const void *)k_cell_bf16<MMAX, CMT, PL, NPW, WPE, float>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)bf16_lds_bytes(MMAX, PL));
 }
 
 // variant 0: eight waves of three N tiles, four waves per SIMD (two workgroups per CU);
 // variant 1: twelve waves of two N tiles, six waves per SIMD
-template <int MMAX, int CMT, int PL>
-void launch_bf16_v(int v, const DevData &d, const uint16_t *cells, const double *X, double *Y, int ncolr,
+template <int MMAX, int CMT, int PL, typename IO>
+void launch_bf16_v(int v, const DevData &d, const uint16_t *cells, const IO *X, IO *Y, int ncolr,
                    int64_t ldr, hipStream_t s, const int *any) {
   if (v == 1) launch_bf16<MMAX, CMT, PL, 2, 6>(d, cells, X, Y, ncolr, ldr, s, any);
   else launch_bf16<MMAX, CMT, PL, 3, 4>(d, cells, X, Y, ncolr, ldr, s, any);
@@ -301,8 +306,9 @@ int cell_bf16_init(int nloc) {
   return set_lds_bf16<352, 6, 1, 3, 2>() | set_lds_bf16<352, 6, 2, 3, 2>();
 }
 
-void cell_apply_bf16(const DevData &d, const uint16_t *cells, int planes, const double *X, double *Y, int ncolr,
-                     int64_t ldr, hipStream_t s, const int *any, int variant) {
+template <typename IO>
+void cell_apply_bf16_io(const DevData &d, const uint16_t *cells, int planes, const IO *X, IO *Y, int ncolr,
+                        int64_t ldr, hipStream_t s, const int *any, int variant) {
   const int nloc = d.g.nloc;
   if (nloc <= 128) {
     if (planes == 1) launch_bf16_v<128, 2, 1>(variant, d, cells, X, Y, ncolr, ldr, s, any);
@@ -314,6 +320,16 @@ void cell_apply_bf16(const DevData &d, const uint16_t *cells, int planes, const 
     if (planes == 1) launch_bf16<352, 6, 1, 3, 2>(d, cells, X, Y, ncolr, ldr, s, any);
     else launch_bf16<352, 6, 2, 3, 2>(d, cells, X, Y, ncolr, ldr, s, any);
   }
+}
+
+void cell_apply_bf16(const DevData &d, const uint16_t *cells, int planes, const double *X, double *Y, int ncolr,
+                     int64_t ldr, hipStream_t s, const int *any, int variant) {
+  cell_apply_bf16_io(d, cells, planes, X, Y, ncolr, ldr, s, any, variant);
+}
+
+void cell_apply_bf16_f(const DevData &d, const uint16_t *cells, int planes, const float *X, float *Y, int ncolr,
+                       int64_t ldf, hipStream_t s, const int *any, int variant) {
+  cell_apply_bf16_io(d, cells, planes, X, Y, ncolr, ldf, s, any, variant);
 }
 
 }  // namespace k

@@ -17,12 +17,32 @@ namespace {
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
+// The 16x16x4 MFMA of the coupling in FP64, or in FP32 (G and the orbital rows in
+// FP32, FP32 accumulation); Acc is the accumulator, row(kr, r) the row of output
+// register r of a lane in row group kr = lane / 16 (the column is lane % 16).
+template <typename T> struct CMfma;
+template <> struct CMfma<double> {
+  typedef v4d Acc;
+  static __device__ __forceinline__ Acc mma(double a, double b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int kr, int r) { return kr + 4 * r; }
+};
+template <> struct CMfma<float> {
+  typedef v4f Acc;
+  static __device__ __forceinline__ Acc mma(float a, float b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int kr, int r) { return 4 * kr + r; }
+};
+
 // ---------------------------------------------------------------------------
 // Enrichment coupling (Sec. 2.2-2.3), G = Hbar^ce on the union rows R of the
 // cells where an enrichment function is nonzero (row-major n_R x n_k):
 //   Y_C[R] += G X_E            (added into the rows the cell products wrote)
 //   Y_E     = G^T X[R] + Hbar^ee X_E
-// on the FP64 16x16x4 MFMA.
+// on the 16x16x4 MFMA: FP64, or FP32 for the reduced-precision products (G, X and
+// Y in FP32, FP32 accumulation; the workgroup partials of Y_E and Hbar^ee X_E in FP64).
 //   k_couple_c: one wave per block walks a contiguous range of 16-row tiles of
 //               R; a block covers KNT 16-column tiles (blockIdx.y).
 //   k_couple_e: a workgroup of kCpWaves waves takes a contiguous range of
@@ -48,11 +68,12 @@ constexpr int kCcBlocks = 1024;   // tile ranges
 constexpr int kCcNT = 3;          // 16-column tiles per slice
 constexpr int kCcMaxK = 48;
 
+template <typename GT, typename IO>
 __global__ void __launch_bounds__(kCcWaves * 64) __attribute__((amdgpu_waves_per_eu(3)))
-k_couple_c48(const DevData d, const double *__restrict__ G, const double *__restrict__ X, double *__restrict__ Y,
+k_couple_c48(const DevData d, const GT *__restrict__ G, const IO *__restrict__ X, IO *__restrict__ Y,
              int ncolr, int64_t ldr, int64_t tiles_per_block, int nranges, int nslice, const int *__restrict__ any) {
   if (any && *any == 0) return;
-  __shared__ double xe[kCcMaxK * kCcNT * 16];
+  __shared__ GT xe[kCcMaxK * kCcNT * 16];
   const int nk = d.nk;
   const int64_t nr = d.nr;
   const int b = blockIdx.x, xcd = b & 7, q = b >> 3;
@@ -60,10 +81,10 @@ k_couple_c48(const DevData d, const double *__restrict__ G, const double *__rest
   if (range >= nranges) return;
   const int tid = threadIdx.x, lane = tid & 63, kr = lane >> 4, cl = lane & 15, wave = tid >> 6;
   const int n0 = slice * kCcNT * 16;
-  const double *XE = X + (int64_t)d.g.n_nodes * ldr;
+  const IO *XE = X + (int64_t)d.g.n_nodes * ldr;
   for (int t = tid; t < kCcMaxK * kCcNT * 16; t += kCcWaves * 64) {
     const int k = t / (kCcNT * 16), c = n0 + t % (kCcNT * 16);
-    xe[t] = (k < nk && c < ncolr) ? XE[(int64_t)k * ldr + c] : 0.0;
+    xe[t] = (k < nk && c < ncolr) ? (GT)XE[(int64_t)k * ldr + c] : (GT)0;
   }
   __syncthreads();
   int col[kCcNT];
@@ -79,46 +100,46 @@ k_couple_c48(const DevData d, const double *__restrict__ G, const double *__rest
   for (int64_t t = t_begin + wave; t < t_end; t += kCcWaves) {
     const int64_t r0 = t * 16, ra = r0 + cl;
     const bool rok = ra < nr;
-    double a[kCcMaxK / 4];
+    GT a[kCcMaxK / 4];
 #pragma unroll
     for (int ks = 0; ks < kCcMaxK / 4; ++ks) {
       const int k = ks * 4 + kr;
-      a[ks] = (rok && k < nk) ? G[ra * nk + k] : 0.0;
+      a[ks] = (rok && k < nk) ? G[ra * nk + k] : (GT)0;
     }
     int64_t yoff[4];
-    double yv[4][kCcNT];
+    IO yv[4][kCcNT];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int64_t row = r0 + kr + 4 * r;
+      const int64_t row = r0 + CMfma<GT>::row(kr, r);
       yoff[r] = row < nr ? d.urow_node[row] * ldr : -1;
 #pragma unroll
-      for (int nt = 0; nt < kCcNT; ++nt) yv[r][nt] = (yoff[r] >= 0 && cok[nt]) ? Y[yoff[r] + col[nt]] : 0.0;
+      for (int nt = 0; nt < kCcNT; ++nt) yv[r][nt] = (yoff[r] >= 0 && cok[nt]) ? Y[yoff[r] + col[nt]] : (IO)0;
     }
-    v4d acc[kCcNT];
+    typename CMfma<GT>::Acc acc[kCcNT];
 #pragma unroll
-    for (int nt = 0; nt < kCcNT; ++nt) acc[nt] = v4d{0, 0, 0, 0};
+    for (int nt = 0; nt < kCcNT; ++nt) acc[nt] = typename CMfma<GT>::Acc{0, 0, 0, 0};
 #pragma unroll
     for (int ks = 0; ks < kCcMaxK / 4; ++ks) {
 #pragma unroll
       for (int nt = 0; nt < kCcNT; ++nt) {
-        const double bv = xe[(ks * 4 + kr) * (kCcNT * 16) + nt * 16 + cl];
-        acc[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ks], bv, acc[nt], 0, 0, 0);
+        const GT bv = xe[(ks * 4 + kr) * (kCcNT * 16) + nt * 16 + cl];
+        acc[nt] = CMfma<GT>::mma(a[ks], bv, acc[nt]);
       }
     }
-    // output register r of a lane holds row kr + 4 r, column cl
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       if (yoff[r] < 0) continue;
 #pragma unroll
       for (int nt = 0; nt < kCcNT; ++nt)
-        if (cok[nt]) Y[yoff[r] + col[nt]] = yv[r][nt] + acc[nt][r];
+        if (cok[nt]) Y[yoff[r] + col[nt]] = yv[r][nt] + (IO)acc[nt][r];
     }
   }
 }
 
 // general n_k: one wave per block, X_E from global memory
+template <typename GT, typename IO>
 __global__ void __launch_bounds__(64)
-k_couple_c(const DevData d, const double *__restrict__ G, const double *__restrict__ X, double *__restrict__ Y,
+k_couple_c(const DevData d, const GT *__restrict__ G, const IO *__restrict__ X, IO *__restrict__ Y,
            int ncolr, int64_t ldr, int64_t tiles_per_wave, const int *__restrict__ any) {
   if (any && *any == 0) return;
   const int nk = d.nk;
@@ -128,7 +149,7 @@ k_couple_c(const DevData d, const double *__restrict__ G, const double *__restri
   const int64_t ntiles = (nr + 15) / 16;
   const int64_t t_begin = (int64_t)blockIdx.x * tiles_per_wave;
   const int64_t t_end = t_begin + tiles_per_wave < ntiles ? t_begin + tiles_per_wave : ntiles;
-  const double *XE = X + (int64_t)d.g.n_nodes * ldr;
+  const IO *XE = X + (int64_t)d.g.n_nodes * ldr;
   int col[KNT];
   bool cok[KNT];
 #pragma unroll
@@ -140,29 +161,29 @@ k_couple_c(const DevData d, const double *__restrict__ G, const double *__restri
   for (int64_t t = t_begin; t < t_end; ++t) {
     const int64_t r0 = t * 16;
     // A(i, k) = G[r0 + i][k], B(k, j) = X_E[k][j]
-    v4d acc[KNT];
+    typename CMfma<GT>::Acc acc[KNT];
 #pragma unroll
-    for (int nt = 0; nt < KNT; ++nt) acc[nt] = v4d{0, 0, 0, 0};
+    for (int nt = 0; nt < KNT; ++nt) acc[nt] = typename CMfma<GT>::Acc{0, 0, 0, 0};
     const int64_t ra = r0 + cl;
     const bool rok = ra < nr;
     for (int ks = 0; ks < nks; ++ks) {
       const int k = ks * 4 + kr;
       const bool kok = k < nk;
-      const double a = (rok && kok) ? G[ra * nk + k] : 0.0;
+      const GT a = (rok && kok) ? G[ra * nk + k] : (GT)0;
 #pragma unroll
       for (int nt = 0; nt < KNT; ++nt) {
-        const double b = (kok && cok[nt]) ? XE[(int64_t)k * ldr + col[nt]] : 0.0;
-        acc[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[nt], 0, 0, 0);
+        const GT b = (kok && cok[nt]) ? (GT)XE[(int64_t)k * ldr + col[nt]] : (GT)0;
+        acc[nt] = CMfma<GT>::mma(a, b, acc[nt]);
       }
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int64_t row = r0 + kr + 4 * r;
+      const int64_t row = r0 + CMfma<GT>::row(kr, r);
       if (row < nr) {
-        double *y = Y + (int64_t)d.urow_node[row] * ldr;
+        IO *y = Y + (int64_t)d.urow_node[row] * ldr;
 #pragma unroll
         for (int nt = 0; nt < KNT; ++nt)
-          if (cok[nt]) y[col[nt]] += acc[nt][r];
+          if (cok[nt]) y[col[nt]] += (IO)acc[nt][r];
       }
     }
   }
@@ -175,8 +196,9 @@ constexpr int kCpMT = 3;         // 16-row tiles of Y_E (n_k <= 48)
 constexpr int kCpSlices = 8;     // first-level reduction slices
 static_assert(kCpBlocks + kCpSlices <= k::kCoupleScratch, "coupling scratch");
 
+template <typename GT, typename IO>
 __global__ void __launch_bounds__(kCpWaves * 64) __attribute__((amdgpu_waves_per_eu(3)))
-k_couple_e(const DevData d, const double *__restrict__ G, const double *__restrict__ X, int ncolr, int64_t ldr,
+k_couple_e(const DevData d, const GT *__restrict__ G, const IO *__restrict__ X, int ncolr, int64_t ldr,
            int64_t tiles_per_block, double *__restrict__ part, const int *__restrict__ any) {
   if (any && *any == 0) return;
   __shared__ double red[kCpMT * 16 * kCpNT * 16];
@@ -195,11 +217,11 @@ k_couple_e(const DevData d, const double *__restrict__ G, const double *__restri
     col[nt] = n0 + nt * 16 + cl;
     cok[nt] = col[nt] < ncolr;
   }
-  v4d acc_e[kCpMT][kCpNT];
+  typename CMfma<GT>::Acc acc_e[kCpMT][kCpNT];
 #pragma unroll
   for (int mt = 0; mt < kCpMT; ++mt)
 #pragma unroll
-    for (int nt = 0; nt < kCpNT; ++nt) acc_e[mt][nt] = v4d{0, 0, 0, 0};
+    for (int nt = 0; nt < kCpNT; ++nt) acc_e[mt][nt] = typename CMfma<GT>::Acc{0, 0, 0, 0};
   for (int64_t t = t_begin + wave; t < t_end; t += kCpWaves) {
     const int64_t r0 = t * 16;
     // Y_E sums: A(i, k) = G[r0 + 4 s + k][16 mt + i], B(k, j) = X[node(r0 + 4 s + k)][j]
@@ -207,17 +229,16 @@ k_couple_e(const DevData d, const double *__restrict__ G, const double *__restri
     for (int s4 = 0; s4 < 4; ++s4) {
       const int64_t rk = r0 + 4 * s4 + kr;
       const bool ok = rk < nr;
-      const double *xr = X + (ok ? (int64_t)d.urow_node[rk] * ldr : 0);
-      double b[kCpNT];
+      const IO *xr = X + (ok ? (int64_t)d.urow_node[rk] * ldr : 0);
+      GT b[kCpNT];
 #pragma unroll
-      for (int nt = 0; nt < kCpNT; ++nt) b[nt] = (ok && cok[nt]) ? xr[col[nt]] : 0.0;
+      for (int nt = 0; nt < kCpNT; ++nt) b[nt] = (ok && cok[nt]) ? (GT)xr[col[nt]] : (GT)0;
 #pragma unroll
       for (int mt = 0; mt < kCpMT; ++mt) {
         const int m = m0 + mt * 16 + cl;
-        const double a = (ok && m < nk) ? G[rk * nk + m] : 0.0;
+        const GT a = (ok && m < nk) ? G[rk * nk + m] : (GT)0;
 #pragma unroll
-        for (int nt = 0; nt < kCpNT; ++nt)
-          acc_e[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[nt], acc_e[mt][nt], 0, 0, 0);
+        for (int nt = 0; nt < kCpNT; ++nt) acc_e[mt][nt] = CMfma<GT>::mma(a, b[nt], acc_e[mt][nt]);
       }
     }
   }
@@ -230,8 +251,8 @@ k_couple_e(const DevData d, const double *__restrict__ G, const double *__restri
         for (int r = 0; r < 4; ++r)
 #pragma unroll
           for (int nt = 0; nt < kCpNT; ++nt) {
-            const int idx = (mt * 16 + kr + 4 * r) * (kCpNT * 16) + nt * 16 + cl;
-            red[idx] = (w == 0 ? 0.0 : red[idx]) + acc_e[mt][nt][r];
+            const int idx = (mt * 16 + CMfma<GT>::row(kr, r)) * (kCpNT * 16) + nt * 16 + cl;
+            red[idx] = (w == 0 ? 0.0 : red[idx]) + (double)acc_e[mt][nt][r];
           }
     }
     __syncthreads();
@@ -266,9 +287,10 @@ k_couple_sum(const double *__restrict__ part, int nblk, int nout, double *__rest
 }
 
 // Y_E[k][c] = sum_s lvl1[s][k][c] + sum_k' Hbar^ee[k][k'] X_E[k'][c]
+template <typename IO>
 __global__ void __launch_bounds__(64)
 k_couple_final(const DevData d, const double *__restrict__ lvl1, int nsl, const double *__restrict__ Hee,
-               const double *__restrict__ X, double *__restrict__ Y, int ncolr, int64_t ldr,
+               const IO *__restrict__ X, IO *__restrict__ Y, int ncolr, int64_t ldr,
                const int *__restrict__ any) {
   if (any && *any == 0) return;
   const int nk = d.nk, nout = nk * ncolr;
@@ -277,8 +299,8 @@ k_couple_final(const DevData d, const double *__restrict__ lvl1, int nsl, const 
   double s = 0.0;
   for (int sl = 0; sl < nsl; ++sl) s += lvl1[(int64_t)sl * nout + o];
   const int k = o / ncolr, c = o % ncolr;
-  for (int kp = 0; kp < nk; ++kp) s += Hee[k * nk + kp] * X[(d.g.n_nodes + kp) * ldr + c];
-  Y[(d.g.n_nodes + k) * ldr + c] = s;
+  for (int kp = 0; kp < nk; ++kp) s += Hee[k * nk + kp] * (double)X[(d.g.n_nodes + kp) * ldr + c];
+  Y[(d.g.n_nodes + k) * ldr + c] = (IO)s;
 }
 
 // ---------------------------------------------------------------------------
@@ -450,12 +472,9 @@ k_tridiag_coef(const double *__restrict__ alpha, const double *__restrict__ beta
 
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-}  // namespace
-
-namespace k {
-
-void couple_apply(const DevData &d, const double *G, const double *Hee, const double *X, double *Y, int ncolr,
-                  int64_t ldr, double *scratch, hipStream_t s, const int *any) {
+template <typename GT, typename IO>
+void couple_apply_t(const DevData &d, const GT *G, const double *Hee, const IO *X, IO *Y, int ncolr,
+                    int64_t ldr, double *scratch, hipStream_t s, const int *any) {
   if (d.nk == 0) return;
   const int nout = d.nk * ncolr;
   double *lvl1 = scratch + (int64_t)kCpBlocks * nout;
@@ -472,23 +491,37 @@ void couple_apply(const DevData &d, const double *G, const double *Hee, const do
       const int nranges = (int)((ntiles + tpr - 1) / tpr);
       const int nslice = (ncolr + kCcNT * 16 - 1) / (kCcNT * 16);
       const unsigned nb = (unsigned)(((nranges + 7) / 8) * 8 * nslice);
-      hipLaunchKernelGGL(k_couple_c48, dim3(nb), dim3(kCcWaves * 64), 0, s, d, G, X, Y, ncolr, ldr, tpr, nranges,
-                         nslice, any);
+      hipLaunchKernelGGL((k_couple_c48<GT, IO>), dim3(nb), dim3(kCcWaves * 64), 0, s, d, G, X, Y, ncolr, ldr, tpr,
+                         nranges, nslice, any);
     } else {
       const int64_t tpc = (ntiles + kCoupleCWaves - 1) / kCoupleCWaves;
-      hipLaunchKernelGGL(k_couple_c, dim3((unsigned)((ntiles + tpc - 1) / tpc), nyc), dim3(64), 0, s, d, G, X, Y,
-                         ncolr, ldr, tpc, any);
+      hipLaunchKernelGGL((k_couple_c<GT, IO>), dim3((unsigned)((ntiles + tpc - 1) / tpc), nyc), dim3(64), 0, s, d, G,
+                         X, Y, ncolr, ldr, tpc, any);
     }
-    hipLaunchKernelGGL(k_couple_e, dim3((unsigned)nblk, ny, nz), dim3(kCpWaves * 64), 0, s, d, G, X, ncolr, ldr, tpb,
-                       scratch, any);
+    hipLaunchKernelGGL((k_couple_e<GT, IO>), dim3((unsigned)nblk, ny, nz), dim3(kCpWaves * 64), 0, s, d, G, X, ncolr,
+                       ldr, tpb, scratch, any);
     nsl = kCpSlices;
     hipLaunchKernelGGL(k_couple_sum, dim3(nblocks((int64_t)nout, 64), kCpSlices), dim3(256), 0, s, scratch, nblk, nout,
                        lvl1, any);
   } else {
     k::zero(lvl1, (int64_t)nout, s);
   }
-  hipLaunchKernelGGL(k_couple_final, dim3(nblocks((int64_t)nout, 64)), dim3(64), 0, s, d, lvl1, nsl, Hee, X, Y, ncolr,
-                     ldr, any);
+  hipLaunchKernelGGL((k_couple_final<IO>), dim3(nblocks((int64_t)nout, 64)), dim3(64), 0, s, d, lvl1, nsl, Hee, X, Y,
+                     ncolr, ldr, any);
+}
+
+}  // namespace
+
+namespace k {
+
+void couple_apply(const DevData &d, const double *G, const double *Hee, const double *X, double *Y, int ncolr,
+                  int64_t ldr, double *scratch, hipStream_t s, const int *any) {
+  couple_apply_t(d, G, Hee, X, Y, ncolr, ldr, scratch, s, any);
+}
+
+void couple_apply_f(const DevData &d, const float *G, const double *Hee, const float *X, float *Y, int ncolr,
+                    int64_t ldf, double *scratch, hipStream_t s, const int *any) {
+  couple_apply_t(d, G, Hee, X, Y, ncolr, ldf, scratch, s, any);
 }
 
 void tridiag_coef(const double *alpha, const double *beta, const int *kused, int ncol, int kmax, const double *taus,

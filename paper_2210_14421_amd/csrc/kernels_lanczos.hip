@@ -15,6 +15,11 @@
 // per-column factors sig[l] = 1 / ||slot l|| turn stored slots into q_l.  This
 // removes the normalisation pass of every iteration (the Hbar X output is
 // written straight into the next slot and orthogonalised in place).
+//
+// With reduced-precision products the Hbar X output is an FP32 block (row stride
+// wld complex values) that the first update reads and writes, orthogonalised, into
+// the FP64 slot; the update also leaves an FP32 copy of the slot (the next
+// product's input).  The recurrence itself is FP64 throughout.
 #include "device.h"
 
 namespace efe {
@@ -41,13 +46,23 @@ __device__ __forceinline__ double2 ldnt(const double2 *p) {
   v.y = __builtin_nontemporal_load(&p->y);
   return v;
 }
+__device__ __forceinline__ double2 ldnt(const float2 *p) {
+  const float x = __builtin_nontemporal_load(&p->x), y = __builtin_nontemporal_load(&p->y);
+  return make_double2((double)x, (double)y);
+}
+__device__ __forceinline__ double2 ld2(const double2 *p) { return *p; }
+__device__ __forceinline__ double2 ld2(const float2 *p) {
+  const float2 v = *p;
+  return make_double2((double)v.x, (double)v.y);
+}
 
 // part[blk][l0 + v][c] (double2) for v < nl: sum_r conj(slot_{l0+v}[r][c]) w[r][c];
 // with_norm adds entry l0 + nl = ||w[:, c]||^2.  Columns with mask[c] == 0
-// contribute zeros.  Returns at once when *any == 0.
-template <int NL>
+// contribute zeros.  Returns at once when *any == 0.  w: FP64 or FP32 complex, wld
+// complex values per row.
+template <int NL, typename W2>
 __global__ void __launch_bounds__(kLzThreads) __attribute__((amdgpu_waves_per_eu(6)))
-k_lz_dots(Basis B, int l0, int nl, const double2 *__restrict__ w, int64_t nrows, int ncol,
+k_lz_dots(Basis B, int l0, int nl, const W2 *__restrict__ w, int64_t wld, int64_t nrows, int ncol,
           const int *__restrict__ mask, const int *__restrict__ any, int with_norm, int nvtot,
           double2 *__restrict__ part) {
   if (any && *any == 0) return;
@@ -64,7 +79,7 @@ k_lz_dots(Basis B, int l0, int nl, const double2 *__restrict__ w, int64_t nrows,
     for (int l = 0; l < NL; ++l) q[l] = slot_ptr(B, l0 + (l < nl ? l : 0));
     for (int64_t r = (int64_t)blockIdx.x * R + r0; r < nrows; r += (int64_t)gridDim.x * R) {
       const int64_t o = r * ncol + c;
-      const double2 wv = ldnt(w + o);
+      const double2 wv = ldnt(w + r * wld + c);
 #pragma unroll
       for (int l = 0; l < NL; ++l)
         if (l < nl) {
@@ -94,15 +109,18 @@ k_lz_dots(Basis B, int l0, int nl, const double2 *__restrict__ w, int64_t nrows,
   }
 }
 
-// w <- gw[c] w - sum_{l < nl} coef[l0 + l][c] slot_{l0+l}  (in place, mask[c] != 0),
-// two rows per step; with_norm writes the partial ||w||^2 of the result to
-// part[blk][c].  gw == nullptr means 1.  zero_masked clears the columns with
-// mask[c] == 0 instead (stopped columns: their later slots stay zero).
-template <int NL>
+// w <- gw[c] src - sum_{l < nl} coef[l0 + l][c] slot_{l0+l}  (mask[c] != 0), two rows per
+// step; src is w itself (in place) or another block (FP64 or FP32 complex, sld complex
+// values per row); sh, when given, receives an FP32 copy of the result (shld complex
+// values per row).  with_norm writes the partial ||w||^2 of the result to part[blk][c].
+// gw == nullptr means 1.  zero_masked clears the columns with mask[c] == 0 instead
+// (stopped columns: their later slots stay zero).
+template <int NL, typename S2, bool INPLACE>
 __global__ void __launch_bounds__(kLzThreads)
 k_lz_update(Basis B, int l0, int nl, const double2 *__restrict__ coef, const double *__restrict__ gw,
-            double2 *__restrict__ w, int64_t nrows, int ncol, const int *__restrict__ mask,
-            const int *__restrict__ any, int with_norm, int zero_masked, double2 *__restrict__ part) {
+            const S2 *__restrict__ src, int64_t sld, double2 *__restrict__ w, float2 *__restrict__ sh, int64_t shld,
+            int64_t nrows, int ncol, const int *__restrict__ mask, const int *__restrict__ any, int with_norm,
+            int zero_masked, double2 *__restrict__ part) {
   if (any && *any == 0) return;
   extern __shared__ double2 lz_sm[];
   double2 *cs = lz_sm;                       // nl * ncol
@@ -114,8 +132,10 @@ k_lz_update(Basis B, int l0, int nl, const double2 *__restrict__ coef, const dou
   const bool on = r0 < R && mask[c] != 0;
   double nrm = 0.0;
   if (r0 < R && !on && zero_masked) {
-    for (int64_t r = (int64_t)blockIdx.x * R + r0; r < nrows; r += (int64_t)gridDim.x * R)
+    for (int64_t r = (int64_t)blockIdx.x * R + r0; r < nrows; r += (int64_t)gridDim.x * R) {
       w[r * ncol + c] = make_double2(0.0, 0.0);
+      if (sh) sh[r * shld + c] = make_float2(0.f, 0.f);
+    }
   }
   if (on) {
     const double g = gw ? gw[c] : 1.0;
@@ -126,7 +146,14 @@ k_lz_update(Basis B, int l0, int nl, const double2 *__restrict__ coef, const dou
     int64_t r = (int64_t)blockIdx.x * R + r0;
     for (; r + step < nrows; r += 2 * step) {
       const int64_t oa = r * ncol + c, ob = (r + step) * ncol + c;
-      double2 va = w[oa], vb = w[ob];
+      double2 va, vb;
+      if constexpr (INPLACE) {
+        va = w[oa];
+        vb = w[ob];
+      } else {
+        va = ld2(src + r * sld + c);
+        vb = ld2(src + (r + step) * sld + c);
+      }
       va.x *= g; va.y *= g; vb.x *= g; vb.y *= g;
 #pragma unroll
       for (int l = 0; l < NL; ++l)
@@ -140,11 +167,17 @@ k_lz_update(Basis B, int l0, int nl, const double2 *__restrict__ coef, const dou
         }
       w[oa] = va;
       w[ob] = vb;
+      if (sh) {
+        sh[r * shld + c] = make_float2((float)va.x, (float)va.y);
+        sh[(r + step) * shld + c] = make_float2((float)vb.x, (float)vb.y);
+      }
       nrm += va.x * va.x + va.y * va.y + vb.x * vb.x + vb.y * vb.y;
     }
     for (; r < nrows; r += step) {
       const int64_t oa = r * ncol + c;
-      double2 va = w[oa];
+      double2 va;
+      if constexpr (INPLACE) va = w[oa];
+      else va = ld2(src + r * sld + c);
       va.x *= g; va.y *= g;
 #pragma unroll
       for (int l = 0; l < NL; ++l)
@@ -155,6 +188,7 @@ k_lz_update(Basis B, int l0, int nl, const double2 *__restrict__ coef, const dou
           va.y -= h.x * qa.y + h.y * qa.x;
         }
       w[oa] = va;
+      if (sh) sh[r * shld + c] = make_float2((float)va.x, (float)va.y);
       nrm += va.x * va.x + va.y * va.y;
     }
   }
@@ -450,10 +484,101 @@ __global__ void k_lz_any(const int *__restrict__ active, int ncol, int *__restri
   if (threadIdx.x == 0) *any = flag;
 }
 
+// X (packed FP64, ncolr values per row) -> Xf (FP32, ldf values per row; pad columns zero)
+__global__ void __launch_bounds__(256)
+k_to_f32(const double *__restrict__ X, int64_t nrows, int ncolr, float *__restrict__ Xf, int64_t ldf) {
+  const int64_t n = nrows * ldf;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / ldf;
+    const int c = (int)(i - r * ldf);
+    Xf[i] = c < ncolr ? (float)X[r * ncolr + c] : 0.f;
+  }
+}
+
+// Xf (FP32, ldf values per row) -> X (packed FP64)
+__global__ void __launch_bounds__(256)
+k_from_f32(const float *__restrict__ Xf, int64_t ldf, int64_t nrows, int ncolr, double *__restrict__ X) {
+  const int64_t n = nrows * (int64_t)ncolr;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / ncolr;
+    X[i] = (double)Xf[r * ldf + (i - r * ncolr)];
+  }
+}
+
 inline int lz_grid(int64_t nrows, int ncol, int threads) {
   const int R = threads / ncol;
   const int64_t need = (nrows + R - 1) / R;
   return (int)std::max<int64_t>(1, std::min<int64_t>(kLzBlocks, need));
+}
+
+template <typename W2>
+int lz_dots_t(const double *q0, const double *qb, int64_t bs, int nq, const W2 *w, int64_t wld, int64_t nrows,
+              int ncol, const int *mask, const int *any, int with_norm, double *part, hipStream_t s) {
+  const Basis B{(const double2 *)q0, (const double2 *)qb, bs / 2};
+  const int nb = lz_grid(nrows, ncol, kLzThreads);
+  const int nvtot = nq + (with_norm ? 1 : 0);
+  if (nq == 0) {
+    hipLaunchKernelGGL((k_lz_dots<1, W2>), dim3(nb), dim3(kLzThreads), 0, s, B, 0, 0, w, wld, nrows, ncol, mask, any,
+                       with_norm, nvtot, (double2 *)part);
+    return nb;
+  }
+  for (int l0 = 0; l0 < nq; l0 += kLzChunk) {
+    const int nl = std::min(kLzChunk, nq - l0);
+    const int wn = (l0 + nl == nq) ? with_norm : 0;
+    if (nl <= 4)
+      hipLaunchKernelGGL((k_lz_dots<4, W2>), dim3(nb), dim3(kLzThreads), 0, s, B, l0, nl, w, wld, nrows, ncol, mask,
+                         any, wn, nvtot, (double2 *)part);
+    else if (nl <= 8)
+      hipLaunchKernelGGL((k_lz_dots<8, W2>), dim3(nb), dim3(kLzThreads), 0, s, B, l0, nl, w, wld, nrows, ncol, mask,
+                         any, wn, nvtot, (double2 *)part);
+    else
+      hipLaunchKernelGGL((k_lz_dots<kLzChunk, W2>), dim3(nb), dim3(kLzThreads), 0, s, B, l0, nl, w, wld, nrows, ncol,
+                         mask, any, wn, nvtot, (double2 *)part);
+  }
+  return nb;
+}
+
+template <typename S2, bool INPLACE>
+void lz_update_launch(int nl, int nb, size_t lds, hipStream_t s, const Basis &B, int l0, const double *coef,
+                      const double *g, const S2 *src, int64_t sld, double *w, float2 *shc, int64_t shld,
+                      int64_t nrows, int ncol, const int *mask, const int *any, int wn, int zm, double *part) {
+  if (nl <= 4)
+    hipLaunchKernelGGL((k_lz_update<4, S2, INPLACE>), dim3(nb), dim3(kLzUpdThreads), lds, s, B, l0, nl,
+                       (const double2 *)coef, g, src, sld, (double2 *)w, shc, shld, nrows, ncol, mask, any, wn, zm,
+                       (double2 *)part);
+  else if (nl <= 8)
+    hipLaunchKernelGGL((k_lz_update<8, S2, INPLACE>), dim3(nb), dim3(kLzUpdThreads), lds, s, B, l0, nl,
+                       (const double2 *)coef, g, src, sld, (double2 *)w, shc, shld, nrows, ncol, mask, any, wn, zm,
+                       (double2 *)part);
+  else
+    hipLaunchKernelGGL((k_lz_update<kLzChunk, S2, INPLACE>), dim3(nb), dim3(kLzUpdThreads), lds, s, B, l0, nl,
+                       (const double2 *)coef, g, src, sld, (double2 *)w, shc, shld, nrows, ncol, mask, any, wn, zm,
+                       (double2 *)part);
+}
+
+// src == nullptr: in place on w
+template <typename S2>
+int lz_update_t(const double *q0, const double *qb, int64_t bs, int nq, const double *coef, const double *gw,
+                const S2 *src, int64_t sld, double *w, float *sh, int64_t shld, int64_t nrows, int ncol,
+                const int *mask, const int *any, double *part, hipStream_t s, int zero_masked) {
+  const Basis B{(const double2 *)q0, (const double2 *)qb, bs / 2};
+  const int nb = lz_grid(nrows, ncol, kLzUpdThreads);
+  const size_t lds = ((size_t)kLzChunk * ncol + kLzUpdThreads) * sizeof(double2);
+  for (int l0 = 0; l0 < nq; l0 += kLzChunk) {
+    const int nl = std::min(kLzChunk, nq - l0);
+    const bool last = l0 + nl == nq;
+    const int wn = last ? 1 : 0;
+    const double *g = l0 == 0 ? gw : nullptr;
+    float2 *shc = last ? (float2 *)sh : nullptr;
+    // the first chunk reads src; later chunks continue in place on w
+    if (l0 == 0 && src)
+      lz_update_launch<S2, false>(nl, nb, lds, s, B, l0, coef, g, src, sld, w, shc, shld, nrows, ncol, mask, any, wn,
+                                  zero_masked, part);
+    else
+      lz_update_launch<double2, true>(nl, nb, lds, s, B, l0, coef, g, nullptr, 0, w, shc, shld, nrows, ncol, mask,
+                                      any, wn, l0 == 0 ? zero_masked : 0, part);
+  }
+  return nb;
 }
 
 }  // namespace
@@ -462,50 +587,38 @@ namespace k {
 
 int lz_dots(const double *q0, const double *qb, int64_t bs, int nq, const double *w, int64_t nrows, int ncol,
             const int *mask, const int *any, int with_norm, double *part, hipStream_t s) {
-  const Basis B{(const double2 *)q0, (const double2 *)qb, bs / 2};
-  const int nb = lz_grid(nrows, ncol, kLzThreads);
-  const int nvtot = nq + (with_norm ? 1 : 0);
-  if (nq == 0) {
-    hipLaunchKernelGGL(k_lz_dots<1>, dim3(nb), dim3(kLzThreads), 0, s, B, 0, 0, (const double2 *)w, nrows, ncol,
-                       mask, any, with_norm, nvtot, (double2 *)part);
-    return nb;
-  }
-  for (int l0 = 0; l0 < nq; l0 += kLzChunk) {
-    const int nl = std::min(kLzChunk, nq - l0);
-    const int wn = (l0 + nl == nq) ? with_norm : 0;
-    if (nl <= 4)
-      hipLaunchKernelGGL(k_lz_dots<4>, dim3(nb), dim3(kLzThreads), 0, s, B, l0, nl, (const double2 *)w, nrows, ncol,
-                         mask, any, wn, nvtot, (double2 *)part);
-    else if (nl <= 8)
-      hipLaunchKernelGGL(k_lz_dots<8>, dim3(nb), dim3(kLzThreads), 0, s, B, l0, nl, (const double2 *)w, nrows, ncol,
-                         mask, any, wn, nvtot, (double2 *)part);
-    else
-      hipLaunchKernelGGL(k_lz_dots<kLzChunk>, dim3(nb), dim3(kLzThreads), 0, s, B, l0, nl, (const double2 *)w, nrows,
-                         ncol, mask, any, wn, nvtot, (double2 *)part);
-  }
-  return nb;
+  return lz_dots_t(q0, qb, bs, nq, (const double2 *)w, (int64_t)ncol, nrows, ncol, mask, any, with_norm, part, s);
+}
+
+int lz_dots_f(const double *q0, const double *qb, int64_t bs, int nq, const float *w, int64_t ldf, int64_t nrows,
+              int ncol, const int *mask, const int *any, int with_norm, double *part, hipStream_t s) {
+  return lz_dots_t(q0, qb, bs, nq, (const float2 *)w, ldf / 2, nrows, ncol, mask, any, with_norm, part, s);
 }
 
 int lz_update(const double *q0, const double *qb, int64_t bs, int nq, const double *coef, const double *gw, double *w,
-              int64_t nrows, int ncol, const int *mask, const int *any, double *part, hipStream_t s, int zero_masked) {
-  const Basis B{(const double2 *)q0, (const double2 *)qb, bs / 2};
-  const int nb = lz_grid(nrows, ncol, kLzUpdThreads);
-  const size_t lds = ((size_t)kLzChunk * ncol + kLzUpdThreads) * sizeof(double2);
-  for (int l0 = 0; l0 < nq; l0 += kLzChunk) {
-    const int nl = std::min(kLzChunk, nq - l0);
-    const int wn = (l0 + nl == nq) ? 1 : 0;
-    const double *g = l0 == 0 ? gw : nullptr;
-    if (nl <= 4)
-      hipLaunchKernelGGL(k_lz_update<4>, dim3(nb), dim3(kLzUpdThreads), lds, s, B, l0, nl, (const double2 *)coef, g,
-                         (double2 *)w, nrows, ncol, mask, any, wn, l0 == 0 ? zero_masked : 0, (double2 *)part);
-    else if (nl <= 8)
-      hipLaunchKernelGGL(k_lz_update<8>, dim3(nb), dim3(kLzUpdThreads), lds, s, B, l0, nl, (const double2 *)coef, g,
-                         (double2 *)w, nrows, ncol, mask, any, wn, l0 == 0 ? zero_masked : 0, (double2 *)part);
-    else
-      hipLaunchKernelGGL(k_lz_update<kLzChunk>, dim3(nb), dim3(kLzUpdThreads), lds, s, B, l0, nl, (const double2 *)coef,
-                         g, (double2 *)w, nrows, ncol, mask, any, wn, l0 == 0 ? zero_masked : 0, (double2 *)part);
-  }
-  return nb;
+              int64_t nrows, int ncol, const int *mask, const int *any, double *part, hipStream_t s, int zero_masked,
+              float *sh, int64_t shldf) {
+  return lz_update_t(q0, qb, bs, nq, coef, gw, (const double2 *)nullptr, 0, w, sh, shldf / 2, nrows, ncol, mask, any,
+                     part, s, zero_masked);
+}
+
+int lz_update_from(const double *q0, const double *qb, int64_t bs, int nq, const double *coef, const double *gw,
+                   const float *src, int64_t ldf, double *w, float *sh, int64_t nrows, int ncol, const int *mask,
+                   const int *any, double *part, hipStream_t s, int zero_masked) {
+  return lz_update_t(q0, qb, bs, nq, coef, gw, (const float2 *)src, ldf / 2, w, sh, ldf / 2, nrows, ncol, mask, any,
+                     part, s, zero_masked);
+}
+
+void to_f32(const double *X, int64_t nrows, int ncolr, float *Xf, int64_t ldf, hipStream_t s) {
+  const int64_t n = nrows * (int64_t)ncolr;
+  const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_to_f32, dim3(nb), dim3(256), 0, s, X, nrows, ncolr, Xf, ldf);
+}
+
+void from_f32(const float *Xf, int64_t ldf, int64_t nrows, int ncolr, double *X, hipStream_t s) {
+  const int64_t n = nrows * (int64_t)ncolr;
+  const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_from_f32, dim3(nb), dim3(256), 0, s, Xf, ldf, nrows, ncolr, X);
 }
 
 void lz_combine(const double *q0, const double *qb, int64_t bs, int nq, const double *coef, double *out,
