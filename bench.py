@@ -523,7 +523,7 @@ def main():
             np.max(np.linalg.norm(np.array(res["mu"]), axis=1))
         out["mixed"] = {"dtype": "f32 products, FP64 Lanczos", "value": mv, "unit": "steps/s",
                         "ms_per_step": 1e3 * mres["wall"] / args.steps, "speedup_vs_f64": mv / value,
-                        "roofline": mroof, "autotune": mres["tune"], "dipole_rel_diff_vs_f64": float(dmu),
+                        "roofline": mroof, "autotune": mres["tune"], "dipole_rel_diff_vs_f64": float(dmu), "krylov_k_mean": mres["k"],
                         "stage_ms_per_step": {k: v / args.steps for k, v in mres["stage"].items() if k != "n_hx"}}
     if not args.no_mixed:
         bres = run_gpu(spec, "bf16", args.steps, args.warmup, args.kmax)
@@ -535,7 +535,7 @@ def main():
         out["mixed_bf16"] = {"dtype": "bf16 products (blocks and orbital rows in BF16, BF16 MFMA), FP64 Lanczos",
                              "value": bv, "unit": "steps/s",
                              "ms_per_step": 1e3 * bres["wall"] / args.steps, "speedup_vs_f64": bv / value,
-                             "roofline": broof, "autotune": bres["tune"], "dipole_rel_diff_vs_f64": float(dmu),
+                             "roofline": broof, "autotune": bres["tune"], "dipole_rel_diff_vs_f64": float(dmu), "krylov_k_mean": bres["k"],
                              "stage_ms_per_step": {k: v / args.steps for k, v in bres["stage"].items() if k != "n_hx"}}
     if not args.no_mixed:
         xres = run_gpu(spec, "bf16x3", args.steps, args.warmup, args.kmax)
@@ -546,7 +546,7 @@ def main():
             np.max(np.linalg.norm(np.array(res["mu"]), axis=1))
         out["mixed_bf16x3"] = {"dtype": "split bf16 products (hi/lo pairs, three BF16 MFMAs), FP64 Lanczos",
                                "value": xv, "unit": "steps/s", "ms_per_step": 1e3 * xres["wall"] / args.steps,
-                               "speedup_vs_f64": xv / value, "roofline": xroof, "autotune": xres["tune"],
+                               "speedup_vs_f64": xv / value, "roofline": xroof, "autotune": xres["tune"], "krylov_k_mean": xres["k"],
                                "dipole_rel_diff_vs_f64": float(dmu),
                                "stage_ms_per_step": {k: v / args.steps for k, v in xres["stage"].items() if k != "n_hx"}}
     if not args.no_extrap:

@@ -64,13 +64,16 @@ struct efe_ctx {
   double *phi = nullptr, *dvec = nullptr, *rhs = nullptr;
   double *cg[7] = {nullptr};
   double *part = nullptr, *hee_part = nullptr, *G = nullptr, *Hee_raw = nullptr, *Hbar_ee = nullptr;
-  // reduced-precision products (FP32 or BF16 blocks): the products read an FP32 copy of
-  // their input (xs: the current Lanczos vector, kept by the update kernels) and leave
-  // their result in yf; G32 is the coupling G in FP32.  Rows of ldf floats (ncolr
-  // rounded up to 4: 16-byte aligned rows for the direct-to-LDS copies).
+  // reduced-precision products (FP32 or BF16 blocks): the products read a reduced-precision
+  // copy of their input (xs: the current Lanczos vector, kept by the update kernels; BF16
+  // for BF16 blocks, FP32 otherwise) and leave their result in yf (FP32); G32 is the
+  // coupling G in FP32.  Rows of ldf elements (ncolr rounded up to 4: 16-byte aligned
+  // FP32 rows for the direct-to-LDS copies).
   bool mixed = false;
+  int xs_bf16 = 0;
   int64_t ldf = 0;
-  float *xs = nullptr, *yf = nullptr, *G32 = nullptr;
+  void *xs = nullptr;
+  float *yf = nullptr, *G32 = nullptr;
   double *hee_blk = nullptr;   // block sums of the H^ee partials
   double *psiE = nullptr, *red = nullptr, *small = nullptr, *couple_scr = nullptr;
   efe::k::DenWork den, adj_den;   // density workspaces (forward columns; adjoint column pairs)
@@ -435,7 +438,10 @@ efe_status build_device(efe_ctx *ctx) {
   ctx->mixed = ctx->dtype == 1 || ctx->dtype == 2 || ctx->dtype == 4;
   if (ctx->mixed) {
     ctx->ldf = (ctx->ncolr + 3) & ~3;
-    EFE_TRY(dalloc(ctx, &ctx->xs, ctx->n_rows * ctx->ldf));
+    ctx->xs_bf16 = ctx->dtype == 2 ? 1 : 0;
+    float *xsf = nullptr;   // FP32 elements; a BF16 copy uses the first half
+    EFE_TRY(dalloc(ctx, &xsf, ctx->n_rows * ctx->ldf));
+    ctx->xs = xsf;
     EFE_TRY(dalloc(ctx, &ctx->yf, ctx->n_rows * ctx->ldf));
     EFE_TRY(dalloc(ctx, &ctx->G32, d.nr * std::max(1, d.nk)));
     HIP_TRY(hipMemset(ctx->xs, 0, (size_t)ctx->n_rows * ctx->ldf * sizeof(float)));
@@ -513,20 +519,23 @@ void cell_products(efe_ctx *ctx, const double *X, double *Y, int ncolr, int64_t 
 }
 
 // The same with FP32 rows (reduced-precision products: FP32 or BF16 blocks)
-void cell_products_f(efe_ctx *ctx, const float *X, float *Y, int ncolr, hipStream_t s, const int *any,
+void cell_products_f(efe_ctx *ctx, const void *X, float *Y, int ncolr, hipStream_t s, const int *any,
                      int variant = -1) {
   const int v = variant >= 0 ? variant : ctx->cell_variant;
   efe::k::cell_apply_f(ctx->d, ctx->cells, ctx->dtype, X, Y, ncolr, ctx->ldf, s, any, v);
 }
 
-// yf = A xs: the reduced-precision products on the FP32 copy of their input
-efe_status apply_op_f(efe_ctx *ctx, int ncolr, const int *any) {
+// yf = A xs: the reduced-precision products on the reduced-precision copy of their input;
+// the coupling reads the FP32 copy, or with BF16 blocks the FP64 rows X64 (the enrichment
+// rows carry the core states, whose coupling terms BF16 rounding would spoil)
+efe_status apply_op_f(efe_ctx *ctx, int ncolr, const int *any, const double *X64) {
   hipStream_t s = ctx->stream;
   tstart(ctx, 0);
   cell_products_f(ctx, ctx->xs, ctx->yf, ncolr, s, any);
   tstop(ctx, 0);
   tstart(ctx, 1);
-  efe::k::couple_apply_f(ctx->d, ctx->G32, ctx->Hbar_ee, ctx->xs, ctx->yf, ncolr, ctx->ldf, ctx->couple_scr, s, any);
+  efe::k::couple_apply_f(ctx->d, ctx->G32, ctx->Hbar_ee, (const float *)ctx->xs, ctx->xs_bf16 ? X64 : nullptr,
+                         ctx->yf, ncolr, ctx->ldf, ctx->couple_scr, s, any);
   tstop(ctx, 1);
   ctx->timer.n_hx++;
   return check_launch(ctx, "apply");
@@ -543,8 +552,8 @@ efe_status apply_op(efe_ctx *ctx, const double *X, double *Y, int ncolr, int64_t
     return EFE_ERR_ARG;
   }
   if (ctx->mixed && ctx->dtype != 3) {
-    efe::k::to_f32(X, ctx->n_rows, ncolr, ctx->xs, ctx->ldf, s);
-    EFE_TRY(apply_op_f(ctx, ncolr, any));
+    efe::k::to_shadow(X, ctx->n_rows, ncolr, ctx->xs, ctx->ldf, ctx->xs_bf16, s);
+    EFE_TRY(apply_op_f(ctx, ncolr, any, X));
     efe::k::from_f32(ctx->yf, ctx->ldf, ctx->n_rows, ncolr, Y, s);
     return check_launch(ctx, "apply");
   }
@@ -688,7 +697,7 @@ efe_status lz_iteration(efe_ctx *ctx, double tau, const double *X, int ncol, int
   // reduced-precision products: xs holds slot j - 1 in FP32 and the product goes to yf,
   // which the first update reads into slot j (writing the next xs)
   const bool mx = ctx->mixed;
-  if (mx) EFE_TRY(apply_op_f(ctx, ncolr, any));
+  if (mx) EFE_TRY(apply_op_f(ctx, ncolr, any, prev));
   else EFE_TRY(apply_op(ctx, prev, w, ncolr, ncolr, any));
   tstart(ctx, 2);
   double *a_j = ctx->alpha + (int64_t)(j - 1) * ncol;
@@ -715,8 +724,8 @@ efe_status lz_iteration(efe_ctx *ctx, double tau, const double *X, int ncol, int
     efe::k::reduce_partials(ctx->red, nb, (nq + 1) * ncolr, ctx->h1, s);
     efe::k::lz_coef1(ctx->h1, ctx->sig, j, first, ncol, ctx->active, a_j, ctx->coef, ctx->gsc, ctx->msc, s);
   }
-  nb = mx ? efe::k::lz_update_from(q0f, qbf, bs, nq, ctx->coef, ctx->gsc, ctx->yf, ctx->ldf, w, ctx->xs, nrows, ncol,
-                                   ctx->active, any, ctx->red, s, 1)
+  nb = mx ? efe::k::lz_update_from(q0f, qbf, bs, nq, ctx->coef, ctx->gsc, ctx->yf, ctx->ldf, w, ctx->xs, ctx->xs_bf16,
+                                   nrows, ncol, ctx->active, any, ctx->red, s, 1)
           : efe::k::lz_update(q0f, qbf, bs, nq, ctx->coef, ctx->gsc, w, nrows, ncol, ctx->active, any, ctx->red, s, 1);
   efe::k::reduce_partials(ctx->red, nb, ncolr, ctx->nrm1, s);
   if (partial)
@@ -728,7 +737,7 @@ efe_status lz_iteration(efe_ctx *ctx, double tau, const double *X, int ncol, int
   efe::k::reduce_partials(ctx->red, nb, j * ncolr, ctx->h2n, s);
   efe::k::lz_coef2(ctx->h2n, ctx->nrm1, ctx->sig, j, ncol, ctx->need, ctx->coef, ctx->gsc, ctx->msc, s);
   nb = efe::k::lz_update(X, Qb, bs, j, ctx->coef, ctx->gsc, w, nrows, ncol, ctx->need, ctx->anyflag, ctx->red, s, 0,
-                         mx ? ctx->xs : nullptr, ctx->ldf);
+                         mx ? ctx->xs : nullptr, ctx->ldf, ctx->xs_bf16);
   efe::k::reduce_partials(ctx->red, nb, ncolr, ctx->nrm2, s);
   efe::k::lz_beta(ctx->nrm1, ctx->nrm2, ctx->need, ctx->active, ctx->msc, j, ncol, b_j, ctx->sig, s);
   tstop(ctx, 2);
@@ -769,7 +778,7 @@ efe_status run_lanczos(efe_ctx *ctx, double tau, const double *X, double *out, i
   int nb = efe::k::lz_dots(X, Qb, bs, 0, X, nrows, ncol, ctx->one_mask, nullptr, 1, ctx->red, s);
   efe::k::reduce_partials(ctx->red, nb, ncolr, ctx->small, s);
   efe::k::lz_init(ctx->small, ncol, ctx->beta0, ctx->sig, ctx->active, ctx->kused, ctx->pro, s);
-  if (ctx->mixed) efe::k::to_f32(X, nrows, ncolr, ctx->xs, ctx->ldf, s);
+  if (ctx->mixed) efe::k::to_shadow(X, nrows, ncolr, ctx->xs, ctx->ldf, ctx->xs_bf16, s);
   tstop(ctx, 2);
   efe::k::lz_any(ctx->active, ncol, ctx->lz_anyf, s);
   std::vector<double> b0h(ncol);
@@ -867,7 +876,7 @@ efe_status run_lanczos_dev(efe_ctx *ctx, double tau, const double *X, double *ou
   int nb = efe::k::lz_dots(X, ctx->Q, bs, 0, X, nrows, ncol, ctx->one_mask, nullptr, 1, ctx->red, s);
   efe::k::reduce_partials(ctx->red, nb, ncolr, ctx->small, s);
   efe::k::lz_init(ctx->small, ncol, ctx->beta0, ctx->sig, ctx->active, ctx->kused, ctx->pro, s);
-  if (ctx->mixed) efe::k::to_f32(X, nrows, ncolr, ctx->xs, ctx->ldf, s);
+  if (ctx->mixed) efe::k::to_shadow(X, nrows, ncolr, ctx->xs, ctx->ldf, ctx->xs_bf16, s);
   efe::k::lz_any(ctx->active, ncol, ctx->lz_anyf, s);
   for (int j = 1; j <= ctx->kmax; ++j) EFE_TRY(lz_iteration(ctx, tau, X, ncol, j, nullptr, tol, ctx->lz_anyf));
   efe::k::lz_comb_coef(ctx->ubuf, ctx->sig, ctx->beta0, ctx->kused, ctx->kmax, ctx->kmax, ncol, ctx->coef, s);
@@ -2036,7 +2045,7 @@ efe_status efe_autotune(efe_ctx *ctx, const char *cache_path, int32_t flags, cha
     const int ncolr = ctx->ncolr;
     double *X = ctx->X0, *Y = ctx->X1, *Yref = ctx->Q;
     const int64_t n = ctx->plan.n_nodes * ncolr;   // the cell products write the classical rows only
-    if (ctx->mixed) efe::k::to_f32(X, ctx->n_rows, ncolr, ctx->xs, ctx->ldf, s);
+    if (ctx->mixed) efe::k::to_shadow(X, ctx->n_rows, ncolr, ctx->xs, ctx->ldf, ctx->xs_bf16, s);
     auto apply = [&](int v, double *out) {   // one application of shape v, result in out (FP64)
       if (ctx->mixed) {
         cell_products_f(ctx, ctx->xs, ctx->yf, ncolr, s, nullptr, v);

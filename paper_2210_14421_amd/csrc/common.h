@@ -110,6 +110,24 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
   return s;
 }
 
+// BF16 orbital rows: the products with BF16 blocks read a BF16 copy of their input
+// (round to nearest even of the FP32 value, as the products would round it)
+struct Bf16 {
+  uint16_t v;
+};
+__device__ __forceinline__ uint16_t bf16_bits(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float to_float(float v) { return v; }
+__device__ __forceinline__ float to_float(double v) { return (float)v; }
+__device__ __forceinline__ float to_float(Bf16 v) { return __uint_as_float((uint32_t)v.v << 16); }
+// element of a reduced-precision copy from an FP64 value
+template <typename T> __device__ __forceinline__ T narrow(double v);
+template <> __device__ __forceinline__ float narrow<float>(double v) { return (float)v; }
+template <> __device__ __forceinline__ Bf16 narrow<Bf16>(double v) { return Bf16{bf16_bits((float)v)}; }
+
 __device__ __forceinline__ double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;

@@ -110,8 +110,9 @@ void hee_reduce(const DevData &d, const double *hee_part, int kinetic, double *H
 int cell_apply_init(int nloc);
 void cell_apply(const DevData &d, const void *cells, int dtype, const double *X, double *Y, int ncolr, int64_t ldr,
                 hipStream_t s, const int *any = nullptr, int variant = 0);
-// the same with FP32 X and Y (ldf floats per row, a multiple of 4) for FP32 and BF16 blocks
-void cell_apply_f(const DevData &d, const void *cells, int dtype, const float *X, float *Y, int ncolr, int64_t ldf,
+// the same with FP32 Y (ldf floats per row, a multiple of 4) and X in the reduced-precision
+// copy: FP32 for FP32 and split BF16 blocks, BF16 for BF16 blocks
+void cell_apply_f(const DevData &d, const void *cells, int dtype, const void *X, float *Y, int ncolr, int64_t ldf,
                   hipStream_t s, const int *any = nullptr, int variant = 0);
 // BF16 products (16x16x32 BF16 MFMA, FP32 accumulation): blocks of planes (1: BF16,
 // 2: hi/lo split) BF16 planes of nloc rows padded to 8 elements; raises the LDS limit
@@ -119,8 +120,8 @@ int cell_bf16_init(int nloc);
 int64_t bf16_block_elems(const Geom &g, int planes);
 void cell_apply_bf16(const DevData &d, const uint16_t *cells, int planes, const double *X, double *Y, int ncolr,
                      int64_t ldr, hipStream_t s, const int *any = nullptr, int variant = 0);
-void cell_apply_bf16_f(const DevData &d, const uint16_t *cells, int planes, const float *X, float *Y, int ncolr,
-                       int64_t ldf, hipStream_t s, const int *any = nullptr, int variant = 0);
+void cell_apply_bf16_f(const DevData &d, const uint16_t *cells, int planes, const void *X, int x_bf16, float *Y,
+                       int ncolr, int64_t ldf, hipStream_t s, const int *any = nullptr, int variant = 0);
 // register-budget variants of the BF16 products (0: two workgroups per CU, 1: three)
 int cell_bf16_variant_count(int nloc);
 // pipeline variants of the cell products that fit the LDS for cells of nloc nodes and
@@ -135,9 +136,10 @@ void sf_apply(const DevData &d, const double *vq, int kinetic, const double *X, 
               hipStream_t s, const int *any = nullptr);
 void couple_apply(const DevData &d, const double *G, const double *Hee, const double *X, double *Y,
                   int ncolr, int64_t ldr, double *scratch, hipStream_t s, const int *any = nullptr);
-// FP32 coupling products (G, X, Y in FP32 with ldf floats per row; FP32 MFMA)
-void couple_apply_f(const DevData &d, const float *G, const double *Hee, const float *X, float *Y, int ncolr,
-                    int64_t ldf, double *scratch, hipStream_t s, const int *any = nullptr);
+// FP32 coupling products (FP32 MFMA; G and Y in FP32, Y with ldf floats per row); X: the
+// FP32 copy (ldf floats per row), or, when X64 is given, the packed FP64 rows
+void couple_apply_f(const DevData &d, const float *G, const double *Hee, const float *X, const double *X64,
+                    float *Y, int ncolr, int64_t ldf, double *scratch, hipStream_t s, const int *any = nullptr);
 
 // density and Poisson
 // workspace of the density: U holds the folded union rows (n_R x ncolr), part
@@ -188,19 +190,23 @@ void spectrum(const double *mu, const int *dirs, int ndir, int64_t nt1, double d
 // Lanczos vectors (unnormalised basis: slot 0 = q0, slot l >= 1 = qb + (l - 1) * bs)
 int lz_dots(const double *q0, const double *qb, int64_t bs, int nq, const double *w, int64_t nrows, int ncol,
             const int *mask, const int *any, int with_norm, double *part, hipStream_t s);
-// in place on w; sh (optional): FP32 copy of the result, shldf floats per row
+// in place on w; sh (optional): reduced-precision copy of the result (FP32, or BF16 with
+// sh_bf16), shld elements per row
 int lz_update(const double *q0, const double *qb, int64_t bs, int nq, const double *coef, const double *gw, double *w,
               int64_t nrows, int ncol, const int *mask, const int *any, double *part, hipStream_t s,
-              int zero_masked = 0, float *sh = nullptr, int64_t shldf = 0);
+              int zero_masked = 0, void *sh = nullptr, int64_t shld = 0, int sh_bf16 = 0);
 // reduced-precision products: the dots with an FP32 product block (ldf floats per row), and
-// the first update reading it (src) into the FP64 slot w with an FP32 copy of the result in sh
+// the first update reading it (src) into the FP64 slot w with a reduced-precision copy of the
+// result in sh (FP32, or BF16 with sh_bf16; ldf elements per row)
 int lz_dots_f(const double *q0, const double *qb, int64_t bs, int nq, const float *w, int64_t ldf, int64_t nrows,
               int ncol, const int *mask, const int *any, int with_norm, double *part, hipStream_t s);
 int lz_update_from(const double *q0, const double *qb, int64_t bs, int nq, const double *coef, const double *gw,
-                   const float *src, int64_t ldf, double *w, float *sh, int64_t nrows, int ncol, const int *mask,
-                   const int *any, double *part, hipStream_t s, int zero_masked);
+                   const float *src, int64_t ldf, double *w, void *sh, int sh_bf16, int64_t nrows, int ncol,
+                   const int *mask, const int *any, double *part, hipStream_t s, int zero_masked);
 // packed FP64 block (ncolr values per row) <-> FP32 block of ldf floats per row (pad columns zero)
 void to_f32(const double *X, int64_t nrows, int ncolr, float *Xf, int64_t ldf, hipStream_t s);
+// packed FP64 block -> reduced-precision copy (FP32, or BF16 with bf16) of ldf elements per row
+void to_shadow(const double *X, int64_t nrows, int ncolr, void *Xs, int64_t ldf, int bf16, hipStream_t s);
 void from_f32(const float *Xf, int64_t ldf, int64_t nrows, int ncolr, double *X, hipStream_t s);
 // nq_dev (optional): device count that bounds nq (the largest k of the columns)
 void lz_combine(const double *q0, const double *qb, int64_t bs, int nq, const double *coef, double *out,

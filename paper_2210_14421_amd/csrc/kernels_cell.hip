@@ -368,10 +368,11 @@ void cell_apply(const DevData &d, const void *cells, int dtype, const double *X,
   else cell_apply_bf16(d, (const uint16_t *)cells, dtype == 4 ? 2 : 1, X, Y, ncolr, ldr, s, any, variant);
 }
 
-void cell_apply_f(const DevData &d, const void *cells, int dtype, const float *X, float *Y, int ncolr, int64_t ldf,
+void cell_apply_f(const DevData &d, const void *cells, int dtype, const void *X, float *Y, int ncolr, int64_t ldf,
                   hipStream_t s, const int *any, int variant) {
-  if (dtype == 1) launch_apply<float, float>(d, (const float *)cells, X, Y, ncolr, ldf, s, any, variant);
-  else cell_apply_bf16_f(d, (const uint16_t *)cells, dtype == 4 ? 2 : 1, X, Y, ncolr, ldf, s, any, variant);
+  if (dtype == 1) launch_apply<float, float>(d, (const float *)cells, (const float *)X, Y, ncolr, ldf, s, any, variant);
+  else cell_apply_bf16_f(d, (const uint16_t *)cells, dtype == 4 ? 2 : 1, X, dtype == 2 ? 1 : 0, Y, ncolr, ldf, s, any,
+                         variant);
 }
 
 }  // namespace k

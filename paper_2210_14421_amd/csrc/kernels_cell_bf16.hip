@@ -5,8 +5,8 @@
 // (hi = bf16(x), lo = bf16(x - hi)) and adds hi*hi + hi*lo + lo*hi: three MFMAs
 // per product, about 16 significant bits.
 //
-// X and Y are FP64, or FP32 (the reduced-precision product reads an FP32 copy of X
-// and leaves its result in FP32).
+// X and Y are FP64, or the product reads a reduced-precision copy of X (BF16 for the
+// BF16 blocks, FP32 for the split form) and leaves its result in FP32.
 //
 // Storage of the blocks (both forms): row r of a cell's block at r * lda with lda =
 // nloc rounded up to 8 elements (every 8-element chunk of a row is one aligned 16-byte
@@ -64,10 +64,10 @@ inline size_t bf16_lds_bytes(int mmax, int planes) {
 // into registers, rounded to BF16, written transposed).  MMAX: rows of A staged (nloc
 // rounded up to whole M tiles); PL: 1 (BF16) or 2 (split); NPW 3 (8 waves) or 2 (12
 // waves, fewer registers per wave: three waves per SIMD for each of two workgroups).
-template <int MMAX, int CMT, int PL, int NPW, int WPE, typename IO>
+template <int MMAX, int CMT, int PL, int NPW, int WPE, typename XT, typename IO>
 __global__ void __launch_bounds__(4 * (6 / NPW) * 64) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_cell_bf16(const DevData d, const int *__restrict__ cell_list, int slot0, const uint16_t *__restrict__ cells,
-            const IO *__restrict__ X, IO *__restrict__ Y, int ncolr, int64_t ldr, const int *__restrict__ any) {
+            const XT *__restrict__ X, IO *__restrict__ Y, int ncolr, int64_t ldr, const int *__restrict__ any) {
   static_assert(MMAX % 16 == 0 && (MMAX / 16 + 3) / 4 <= CMT, "M tiles per wave");
   static_assert(NPW == 2 || NPW == 3, "N tiles per wave");
   constexpr int G = 6 / NPW;                   // N groups
@@ -140,12 +140,12 @@ k_cell_bf16(const DevData d, const int *__restrict__ cell_list, int slot0, const
   // split) to BF16
   const int xn = tid % kBCols, xq = (tid / kBCols) % 4, xp = tid / (4 * kBCols);
   const bool xthr = tid < 4 * kBCols * H;
-  IO xv[XV];
+  XT xv[XV];
   auto loadX = [&](int s) {
 #pragma unroll
     for (int j = 0; j < XV; ++j) {
       const int k = 32 * s + 8 * xq + XV * xp + j;
-      xv[j] = (xthr && xn < wcol && k < nloc) ? X[rowoff[k] + col0 + xn] : (IO)0;
+      xv[j] = (xthr && xn < wcol && k < nloc) ? X[rowoff[k] + col0 + xn] : XT{};
     }
   };
   auto writeX = [&](int st) {
@@ -153,7 +153,7 @@ k_cell_bf16(const DevData d, const int *__restrict__ cell_list, int slot0, const
     uint32_t hi[XV / 2], lo[XV / 2];
 #pragma unroll
     for (int j = 0; j < XV / 2; ++j) {
-      const float f0 = (float)xv[2 * j], f1 = (float)xv[2 * j + 1];
+      const float f0 = to_float(xv[2 * j]), f1 = to_float(xv[2 * j + 1]);
       const uint16_t h0 = bf16_rne(f0), h1 = bf16_rne(f1);
       hi[j] = (uint32_t)h0 | ((uint32_t)h1 << 16);
       if (PL == 2) {
@@ -251,8 +251,8 @@ k_cell_bf16(const DevData d, const int *__restrict__ cell_list, int slot0, const
   }
 }
 
-template <int MMAX, int CMT, int PL, int NPW, int WPE, typename IO>
-void launch_bf16(const DevData &d, const uint16_t *cells, const IO *X, IO *Y, int ncolr, int64_t ldr,
+template <int MMAX, int CMT, int PL, int NPW, int WPE, typename XT, typename IO>
+void launch_bf16(const DevData &d, const uint16_t *cells, const XT *X, IO *Y, int ncolr, int64_t ldr,
                  hipStream_t s, const int *any) {
   const unsigned ny = (unsigned)((ncolr + kBCols - 1) / kBCols);
   const size_t lds = bf16_lds_bytes(MMAX, PL);
@@ -260,7 +260,8 @@ void launch_bf16(const DevData &d, const uint16_t *cells, const IO *X, IO *Y, in
     const int cnt = d.colour_off[c + 1] - d.colour_off[c];
     if (cnt == 0) continue;
     const int *list = d.colour_cells + d.colour_off[c];
-    hipLaunchKernelGGL((k_cell_bf16<MMAX, CMT, PL, NPW, WPE, IO>), dim3((unsigned)cnt, ny), dim3(4 * (6 / NPW) * 64), lds,
+    hipLaunchKernelGGL((k_cell_bf16<MMAX, CMT, PL, NPW, WPE, XT, IO>), dim3((unsigned)cnt, ny), dim3(4 * (6 / NPW) * 64),
+                       lds,
                        s, d, list,
                        d.colour_off[c], cells, X, Y, ncolr, ldr, any);
   }
@@ -268,16 +269,19 @@ void launch_bf16(const DevData &d, const uint16_t *cells, const IO *X, IO *Y, in
 
 template <int MMAX, int CMT, int PL, int NPW, int WPE>
 int set_lds_bf16() {
-  return (int)hipFuncSetAttribute((const void *)k_cell_bf16<MMAX, CMT, PL, NPW, WPE, double>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bf16_lds_bytes(MMAX, PL)) |
-         (int)hipFuncSetAttribute((const void *)k_cell_bf16<MMAX, CMT, PL, NPW, WPE, float>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)bf16_lds_bytes(MMAX, PL));
+  const int lds = (int)bf16_lds_bytes(MMAX, PL);
+  return (int)hipFuncSetAttribute((const void *)k_cell_bf16<MMAX, CMT, PL, NPW, WPE, double, double>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds) |
+         (int)hipFuncSetAttribute((const void *)k_cell_bf16<MMAX, CMT, PL, NPW, WPE, float, float>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds) |
+         (int)hipFuncSetAttribute((const void *)k_cell_bf16<MMAX, CMT, PL, NPW, WPE, Bf16, float>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
 // variant 0: eight waves of three N tiles, four waves per SIMD (two workgroups per CU);
 // variant 1: twelve waves of two N tiles, six waves per SIMD
-template <int MMAX, int CMT, int PL, typename IO>
-void launch_bf16_v(int v, const DevData &d, const uint16_t *cells, const IO *X, IO *Y, int ncolr,
+template <int MMAX, int CMT, int PL, typename XT, typename IO>
+void launch_bf16_v(int v, const DevData &d, const uint16_t *cells, const XT *X, IO *Y, int ncolr,
                    int64_t ldr, hipStream_t s, const int *any) {
   if (v == 1) launch_bf16<MMAX, CMT, PL, 2, 6>(d, cells, X, Y, ncolr, ldr, s, any);
   else launch_bf16<MMAX, CMT, PL, 3, 4>(d, cells, X, Y, ncolr, ldr, s, any);
@@ -306,8 +310,8 @@ int cell_bf16_init(int nloc) {
   return set_lds_bf16<352, 6, 1, 3, 2>() | set_lds_bf16<352, 6, 2, 3, 2>();
 }
 
-template <typename IO>
-void cell_apply_bf16_io(const DevData &d, const uint16_t *cells, int planes, const IO *X, IO *Y, int ncolr,
+template <typename XT, typename IO>
+void cell_apply_bf16_io(const DevData &d, const uint16_t *cells, int planes, const XT *X, IO *Y, int ncolr,
                         int64_t ldr, hipStream_t s, const int *any, int variant) {
   const int nloc = d.g.nloc;
   if (nloc <= 128) {
@@ -327,9 +331,10 @@ void cell_apply_bf16(const DevData &d, const uint16_t *cells, int planes, const 
   cell_apply_bf16_io(d, cells, planes, X, Y, ncolr, ldr, s, any, variant);
 }
 
-void cell_apply_bf16_f(const DevData &d, const uint16_t *cells, int planes, const float *X, float *Y, int ncolr,
-                       int64_t ldf, hipStream_t s, const int *any, int variant) {
-  cell_apply_bf16_io(d, cells, planes, X, Y, ncolr, ldf, s, any, variant);
+void cell_apply_bf16_f(const DevData &d, const uint16_t *cells, int planes, const void *X, int x_bf16, float *Y,
+                       int ncolr, int64_t ldf, hipStream_t s, const int *any, int variant) {
+  if (x_bf16 && planes == 1) cell_apply_bf16_io(d, cells, 1, (const Bf16 *)X, Y, ncolr, ldf, s, any, variant);
+  else cell_apply_bf16_io(d, cells, planes, (const float *)X, Y, ncolr, ldf, s, any, variant);
 }
 
 }  // namespace k

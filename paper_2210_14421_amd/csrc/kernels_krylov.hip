@@ -20,6 +20,10 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 // The 16x16x4 MFMA of the coupling in FP64, or in FP32 (G and the orbital rows in
 // FP32, FP32 accumulation); Acc is the accumulator, row(kr, r) the row of output
 // register r of a lane in row group kr = lane / 16 (the column is lane % 16).
+__device__ __forceinline__ double to_wide(double v) { return v; }
+__device__ __forceinline__ float to_wide(float v) { return v; }
+__device__ __forceinline__ float to_wide(Bf16 v) { return to_float(v); }
+
 template <typename T> struct CMfma;
 template <> struct CMfma<double> {
   typedef v4d Acc;
@@ -68,9 +72,9 @@ constexpr int kCcBlocks = 1024;   // tile ranges
 constexpr int kCcNT = 3;          // 16-column tiles per slice
 constexpr int kCcMaxK = 48;
 
-template <typename GT, typename IO>
+template <typename GT, typename XT, typename IO>
 __global__ void __launch_bounds__(kCcWaves * 64) __attribute__((amdgpu_waves_per_eu(3)))
-k_couple_c48(const DevData d, const GT *__restrict__ G, const IO *__restrict__ X, IO *__restrict__ Y,
+k_couple_c48(const DevData d, const GT *__restrict__ G, const XT *__restrict__ X, int64_t ldx, IO *__restrict__ Y,
              int ncolr, int64_t ldr, int64_t tiles_per_block, int nranges, int nslice, const int *__restrict__ any) {
   if (any && *any == 0) return;
   __shared__ GT xe[kCcMaxK * kCcNT * 16];
@@ -81,10 +85,10 @@ k_couple_c48(const DevData d, const GT *__restrict__ G, const IO *__restrict__ X
   if (range >= nranges) return;
   const int tid = threadIdx.x, lane = tid & 63, kr = lane >> 4, cl = lane & 15, wave = tid >> 6;
   const int n0 = slice * kCcNT * 16;
-  const IO *XE = X + (int64_t)d.g.n_nodes * ldr;
+  const XT *XE = X + (int64_t)d.g.n_nodes * ldx;
   for (int t = tid; t < kCcMaxK * kCcNT * 16; t += kCcWaves * 64) {
     const int k = t / (kCcNT * 16), c = n0 + t % (kCcNT * 16);
-    xe[t] = (k < nk && c < ncolr) ? (GT)XE[(int64_t)k * ldr + c] : (GT)0;
+    xe[t] = (k < nk && c < ncolr) ? (GT)to_wide(XE[(int64_t)k * ldx + c]) : (GT)0;
   }
   __syncthreads();
   int col[kCcNT];
@@ -137,9 +141,9 @@ k_couple_c48(const DevData d, const GT *__restrict__ G, const IO *__restrict__ X
 }
 
 // general n_k: one wave per block, X_E from global memory
-template <typename GT, typename IO>
+template <typename GT, typename XT, typename IO>
 __global__ void __launch_bounds__(64)
-k_couple_c(const DevData d, const GT *__restrict__ G, const IO *__restrict__ X, IO *__restrict__ Y,
+k_couple_c(const DevData d, const GT *__restrict__ G, const XT *__restrict__ X, int64_t ldx, IO *__restrict__ Y,
            int ncolr, int64_t ldr, int64_t tiles_per_wave, const int *__restrict__ any) {
   if (any && *any == 0) return;
   const int nk = d.nk;
@@ -149,7 +153,7 @@ k_couple_c(const DevData d, const GT *__restrict__ G, const IO *__restrict__ X, 
   const int64_t ntiles = (nr + 15) / 16;
   const int64_t t_begin = (int64_t)blockIdx.x * tiles_per_wave;
   const int64_t t_end = t_begin + tiles_per_wave < ntiles ? t_begin + tiles_per_wave : ntiles;
-  const IO *XE = X + (int64_t)d.g.n_nodes * ldr;
+  const XT *XE = X + (int64_t)d.g.n_nodes * ldx;
   int col[KNT];
   bool cok[KNT];
 #pragma unroll
@@ -172,7 +176,7 @@ k_couple_c(const DevData d, const GT *__restrict__ G, const IO *__restrict__ X, 
       const GT a = (rok && kok) ? G[ra * nk + k] : (GT)0;
 #pragma unroll
       for (int nt = 0; nt < KNT; ++nt) {
-        const GT b = (kok && cok[nt]) ? (GT)XE[(int64_t)k * ldr + col[nt]] : (GT)0;
+        const GT b = (kok && cok[nt]) ? (GT)to_wide(XE[(int64_t)k * ldx + col[nt]]) : (GT)0;
         acc[nt] = CMfma<GT>::mma(a, b, acc[nt]);
       }
     }
@@ -196,9 +200,9 @@ constexpr int kCpMT = 3;         // 16-row tiles of Y_E (n_k <= 48)
 constexpr int kCpSlices = 8;     // first-level reduction slices
 static_assert(kCpBlocks + kCpSlices <= k::kCoupleScratch, "coupling scratch");
 
-template <typename GT, typename IO>
+template <typename GT, typename XT>
 __global__ void __launch_bounds__(kCpWaves * 64) __attribute__((amdgpu_waves_per_eu(3)))
-k_couple_e(const DevData d, const GT *__restrict__ G, const IO *__restrict__ X, int ncolr, int64_t ldr,
+k_couple_e(const DevData d, const GT *__restrict__ G, const XT *__restrict__ X, int ncolr, int64_t ldx,
            int64_t tiles_per_block, double *__restrict__ part, const int *__restrict__ any) {
   if (any && *any == 0) return;
   __shared__ double red[kCpMT * 16 * kCpNT * 16];
@@ -229,10 +233,10 @@ k_couple_e(const DevData d, const GT *__restrict__ G, const IO *__restrict__ X, 
     for (int s4 = 0; s4 < 4; ++s4) {
       const int64_t rk = r0 + 4 * s4 + kr;
       const bool ok = rk < nr;
-      const IO *xr = X + (ok ? (int64_t)d.urow_node[rk] * ldr : 0);
+      const XT *xr = X + (ok ? (int64_t)d.urow_node[rk] * ldx : 0);
       GT b[kCpNT];
 #pragma unroll
-      for (int nt = 0; nt < kCpNT; ++nt) b[nt] = (ok && cok[nt]) ? (GT)xr[col[nt]] : (GT)0;
+      for (int nt = 0; nt < kCpNT; ++nt) b[nt] = (ok && cok[nt]) ? (GT)to_wide(xr[col[nt]]) : (GT)0;
 #pragma unroll
       for (int mt = 0; mt < kCpMT; ++mt) {
         const int m = m0 + mt * 16 + cl;
@@ -287,10 +291,10 @@ k_couple_sum(const double *__restrict__ part, int nblk, int nout, double *__rest
 }
 
 // Y_E[k][c] = sum_s lvl1[s][k][c] + sum_k' Hbar^ee[k][k'] X_E[k'][c]
-template <typename IO>
+template <typename XT, typename IO>
 __global__ void __launch_bounds__(64)
 k_couple_final(const DevData d, const double *__restrict__ lvl1, int nsl, const double *__restrict__ Hee,
-               const IO *__restrict__ X, IO *__restrict__ Y, int ncolr, int64_t ldr,
+               const XT *__restrict__ X, int64_t ldx, IO *__restrict__ Y, int ncolr, int64_t ldr,
                const int *__restrict__ any) {
   if (any && *any == 0) return;
   const int nk = d.nk, nout = nk * ncolr;
@@ -299,7 +303,7 @@ k_couple_final(const DevData d, const double *__restrict__ lvl1, int nsl, const 
   double s = 0.0;
   for (int sl = 0; sl < nsl; ++sl) s += lvl1[(int64_t)sl * nout + o];
   const int k = o / ncolr, c = o % ncolr;
-  for (int kp = 0; kp < nk; ++kp) s += Hee[k * nk + kp] * (double)X[(d.g.n_nodes + kp) * ldr + c];
+  for (int kp = 0; kp < nk; ++kp) s += Hee[k * nk + kp] * (double)to_wide(X[(d.g.n_nodes + kp) * ldx + c]);
   Y[(d.g.n_nodes + k) * ldr + c] = (IO)s;
 }
 
@@ -472,8 +476,8 @@ k_tridiag_coef(const double *__restrict__ alpha, const double *__restrict__ beta
 
 inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-template <typename GT, typename IO>
-void couple_apply_t(const DevData &d, const GT *G, const double *Hee, const IO *X, IO *Y, int ncolr,
+template <typename GT, typename XT, typename IO>
+void couple_apply_t(const DevData &d, const GT *G, const double *Hee, const XT *X, int64_t ldx, IO *Y, int ncolr,
                     int64_t ldr, double *scratch, hipStream_t s, const int *any) {
   if (d.nk == 0) return;
   const int nout = d.nk * ncolr;
@@ -491,23 +495,23 @@ void couple_apply_t(const DevData &d, const GT *G, const double *Hee, const IO *
       const int nranges = (int)((ntiles + tpr - 1) / tpr);
       const int nslice = (ncolr + kCcNT * 16 - 1) / (kCcNT * 16);
       const unsigned nb = (unsigned)(((nranges + 7) / 8) * 8 * nslice);
-      hipLaunchKernelGGL((k_couple_c48<GT, IO>), dim3(nb), dim3(kCcWaves * 64), 0, s, d, G, X, Y, ncolr, ldr, tpr,
+      hipLaunchKernelGGL((k_couple_c48<GT, XT, IO>), dim3(nb), dim3(kCcWaves * 64), 0, s, d, G, X, ldx, Y, ncolr, ldr, tpr,
                          nranges, nslice, any);
     } else {
       const int64_t tpc = (ntiles + kCoupleCWaves - 1) / kCoupleCWaves;
-      hipLaunchKernelGGL((k_couple_c<GT, IO>), dim3((unsigned)((ntiles + tpc - 1) / tpc), nyc), dim3(64), 0, s, d, G,
-                         X, Y, ncolr, ldr, tpc, any);
+      hipLaunchKernelGGL((k_couple_c<GT, XT, IO>), dim3((unsigned)((ntiles + tpc - 1) / tpc), nyc), dim3(64), 0, s, d, G,
+                         X, ldx, Y, ncolr, ldr, tpc, any);
     }
-    hipLaunchKernelGGL((k_couple_e<GT, IO>), dim3((unsigned)nblk, ny, nz), dim3(kCpWaves * 64), 0, s, d, G, X, ncolr,
-                       ldr, tpb, scratch, any);
+    hipLaunchKernelGGL((k_couple_e<GT, XT>), dim3((unsigned)nblk, ny, nz), dim3(kCpWaves * 64), 0, s, d, G, X, ncolr,
+                       ldx, tpb, scratch, any);
     nsl = kCpSlices;
     hipLaunchKernelGGL(k_couple_sum, dim3(nblocks((int64_t)nout, 64), kCpSlices), dim3(256), 0, s, scratch, nblk, nout,
                        lvl1, any);
   } else {
     k::zero(lvl1, (int64_t)nout, s);
   }
-  hipLaunchKernelGGL((k_couple_final<IO>), dim3(nblocks((int64_t)nout, 64)), dim3(64), 0, s, d, lvl1, nsl, Hee, X, Y,
-                     ncolr, ldr, any);
+  hipLaunchKernelGGL((k_couple_final<XT, IO>), dim3(nblocks((int64_t)nout, 64)), dim3(64), 0, s, d, lvl1, nsl, Hee, X, ldx,
+                     Y, ncolr, ldr, any);
 }
 
 }  // namespace
@@ -516,12 +520,13 @@ namespace k {
 
 void couple_apply(const DevData &d, const double *G, const double *Hee, const double *X, double *Y, int ncolr,
                   int64_t ldr, double *scratch, hipStream_t s, const int *any) {
-  couple_apply_t(d, G, Hee, X, Y, ncolr, ldr, scratch, s, any);
+  couple_apply_t(d, G, Hee, X, ldr, Y, ncolr, ldr, scratch, s, any);
 }
 
-void couple_apply_f(const DevData &d, const float *G, const double *Hee, const float *X, float *Y, int ncolr,
-                    int64_t ldf, double *scratch, hipStream_t s, const int *any) {
-  couple_apply_t(d, G, Hee, X, Y, ncolr, ldf, scratch, s, any);
+void couple_apply_f(const DevData &d, const float *G, const double *Hee, const float *X, const double *X64,
+                    float *Y, int ncolr, int64_t ldf, double *scratch, hipStream_t s, const int *any) {
+  if (X64) couple_apply_t(d, G, Hee, X64, (int64_t)ncolr, Y, ncolr, ldf, scratch, s, any);
+  else couple_apply_t(d, G, Hee, X, ldf, Y, ncolr, ldf, scratch, s, any);
 }
 
 void tridiag_coef(const double *alpha, const double *beta, const int *kused, int ncol, int kmax, const double *taus,

@@ -20,7 +20,7 @@
 // wld complex values) that the first update reads and writes, orthogonalised, into
 // the FP64 slot; the update also leaves an FP32 copy of the slot (the next
 // product's input).  The recurrence itself is FP64 throughout.
-#include "device.h"
+#include "common.h"
 
 namespace efe {
 namespace {
@@ -50,10 +50,19 @@ __device__ __forceinline__ double2 ldnt(const float2 *p) {
   const float x = __builtin_nontemporal_load(&p->x), y = __builtin_nontemporal_load(&p->y);
   return make_double2((double)x, (double)y);
 }
-__device__ __forceinline__ double2 ld2(const double2 *p) { return *p; }
-__device__ __forceinline__ double2 ld2(const float2 *p) {
-  const float2 v = *p;
-  return make_double2((double)v.x, (double)v.y);
+__device__ __forceinline__ void stnt(double2 *p, double2 v) {
+  __builtin_nontemporal_store(v.x, &p->x);
+  __builtin_nontemporal_store(v.y, &p->y);
+}
+// one complex value of the reduced-precision copy of a Lanczos vector (two floats, or
+// two BF16 values in one 32-bit word)
+__device__ __forceinline__ void stnt(float *p, double2 v) {
+  __builtin_nontemporal_store((float)v.x, p);
+  __builtin_nontemporal_store((float)v.y, p + 1);
+}
+__device__ __forceinline__ void stnt(Bf16 *p, double2 v) {
+  const uint32_t w = (uint32_t)bf16_bits((float)v.x) | ((uint32_t)bf16_bits((float)v.y) << 16);
+  __builtin_nontemporal_store(w, (uint32_t *)p);
 }
 
 // part[blk][l0 + v][c] (double2) for v < nl: sum_r conj(slot_{l0+v}[r][c]) w[r][c];
@@ -61,7 +70,7 @@ __device__ __forceinline__ double2 ld2(const float2 *p) {
 // contribute zeros.  Returns at once when *any == 0.  w: FP64 or FP32 complex, wld
 // complex values per row.
 template <int NL, typename W2>
-__global__ void __launch_bounds__(kLzThreads) __attribute__((amdgpu_waves_per_eu(6)))
+__global__ void __launch_bounds__(kLzThreads) __attribute__((amdgpu_waves_per_eu(NL <= 8 ? 6 : 4)))
 k_lz_dots(Basis B, int l0, int nl, const W2 *__restrict__ w, int64_t wld, int64_t nrows, int ncol,
           const int *__restrict__ mask, const int *__restrict__ any, int with_norm, int nvtot,
           double2 *__restrict__ part) {
@@ -109,16 +118,16 @@ k_lz_dots(Basis B, int l0, int nl, const W2 *__restrict__ w, int64_t wld, int64_
   }
 }
 
-// w <- gw[c] src - sum_{l < nl} coef[l0 + l][c] slot_{l0+l}  (mask[c] != 0), two rows per
-// step; src is w itself (in place) or another block (FP64 or FP32 complex, sld complex
-// values per row); sh, when given, receives an FP32 copy of the result (shld complex
-// values per row).  with_norm writes the partial ||w||^2 of the result to part[blk][c].
+// w <- gw[c] src - sum_{l < nl} coef[l0 + l][c] slot_{l0+l}  (mask[c] != 0); src is w
+// itself (in place) or another block (FP64 or FP32 complex, sld complex values per
+// row); sh, when given, receives an FP32 or BF16 copy of the result (shld complex values
+// per row).  with_norm writes the partial ||w||^2 of the result to part[blk][c].
 // gw == nullptr means 1.  zero_masked clears the columns with mask[c] == 0 instead
 // (stopped columns: their later slots stay zero).
-template <int NL, typename S2, bool INPLACE>
-__global__ void __launch_bounds__(kLzThreads)
+template <int NL, typename S2, bool INPLACE, typename SHT>
+__global__ void __launch_bounds__(kLzThreads) __attribute__((amdgpu_waves_per_eu(4)))
 k_lz_update(Basis B, int l0, int nl, const double2 *__restrict__ coef, const double *__restrict__ gw,
-            const S2 *__restrict__ src, int64_t sld, double2 *__restrict__ w, float2 *__restrict__ sh, int64_t shld,
+            const S2 *__restrict__ src, int64_t sld, double2 *__restrict__ w, SHT *__restrict__ sh, int64_t shld,
             int64_t nrows, int ncol, const int *__restrict__ mask, const int *__restrict__ any, int with_norm,
             int zero_masked, double2 *__restrict__ part) {
   if (any && *any == 0) return;
@@ -134,7 +143,7 @@ k_lz_update(Basis B, int l0, int nl, const double2 *__restrict__ coef, const dou
   if (r0 < R && !on && zero_masked) {
     for (int64_t r = (int64_t)blockIdx.x * R + r0; r < nrows; r += (int64_t)gridDim.x * R) {
       w[r * ncol + c] = make_double2(0.0, 0.0);
-      if (sh) sh[r * shld + c] = make_float2(0.f, 0.f);
+      if (sh) stnt(sh + 2 * (r * shld + c), make_double2(0.0, 0.0));
     }
   }
   if (on) {
@@ -142,53 +151,56 @@ k_lz_update(Basis B, int l0, int nl, const double2 *__restrict__ coef, const dou
     const double2 *q[NL];
 #pragma unroll
     for (int l = 0; l < NL; ++l) q[l] = slot_ptr(B, l0 + (l < nl ? l : 0));
+    // RU rows per step (two for the three-term step, one for the long passes, whose
+    // loads of NL slots fill the registers)
+    constexpr int RU = NL <= 4 ? 2 : 1;
     const int64_t step = (int64_t)gridDim.x * R;
     int64_t r = (int64_t)blockIdx.x * R + r0;
-    for (; r + step < nrows; r += 2 * step) {
-      const int64_t oa = r * ncol + c, ob = (r + step) * ncol + c;
-      double2 va, vb;
-      if constexpr (INPLACE) {
-        va = w[oa];
-        vb = w[ob];
-      } else {
-        va = ld2(src + r * sld + c);
-        vb = ld2(src + (r + step) * sld + c);
+    for (; r + (RU - 1) * step < nrows; r += RU * step) {
+      double2 v[RU];
+#pragma unroll
+      for (int u = 0; u < RU; ++u) {
+        const int64_t ru = r + u * step;
+        if constexpr (INPLACE) v[u] = ldnt(w + ru * ncol + c);
+        else v[u] = ldnt(src + ru * sld + c);
+        v[u].x *= g;
+        v[u].y *= g;
       }
-      va.x *= g; va.y *= g; vb.x *= g; vb.y *= g;
 #pragma unroll
       for (int l = 0; l < NL; ++l)
         if (l < nl) {
-          const double2 qa = q[l][oa], qb = q[l][ob];
           const double2 h = cs[l * ncol + c];
-          va.x -= h.x * qa.x - h.y * qa.y;
-          va.y -= h.x * qa.y + h.y * qa.x;
-          vb.x -= h.x * qb.x - h.y * qb.y;
-          vb.y -= h.x * qb.y + h.y * qb.x;
+#pragma unroll
+          for (int u = 0; u < RU; ++u) {
+            const double2 qv = ldnt(q[l] + (r + u * step) * ncol + c);
+            v[u].x -= h.x * qv.x - h.y * qv.y;
+            v[u].y -= h.x * qv.y + h.y * qv.x;
+          }
         }
-      w[oa] = va;
-      w[ob] = vb;
-      if (sh) {
-        sh[r * shld + c] = make_float2((float)va.x, (float)va.y);
-        sh[(r + step) * shld + c] = make_float2((float)vb.x, (float)vb.y);
+#pragma unroll
+      for (int u = 0; u < RU; ++u) {
+        const int64_t ru = r + u * step;
+        stnt(w + ru * ncol + c, v[u]);
+        if (sh) stnt(sh + 2 * (ru * shld + c), v[u]);
+        nrm += v[u].x * v[u].x + v[u].y * v[u].y;
       }
-      nrm += va.x * va.x + va.y * va.y + vb.x * vb.x + vb.y * vb.y;
     }
     for (; r < nrows; r += step) {
       const int64_t oa = r * ncol + c;
       double2 va;
-      if constexpr (INPLACE) va = w[oa];
-      else va = ld2(src + r * sld + c);
+      if constexpr (INPLACE) va = ldnt(w + oa);
+      else va = ldnt(src + r * sld + c);
       va.x *= g; va.y *= g;
 #pragma unroll
       for (int l = 0; l < NL; ++l)
         if (l < nl) {
-          const double2 qa = q[l][oa];
+          const double2 qa = ldnt(q[l] + oa);
           const double2 h = cs[l * ncol + c];
           va.x -= h.x * qa.x - h.y * qa.y;
           va.y -= h.x * qa.y + h.y * qa.x;
         }
-      w[oa] = va;
-      if (sh) sh[r * shld + c] = make_float2((float)va.x, (float)va.y);
+      stnt(w + oa, va);
+      if (sh) stnt(sh + 2 * (r * shld + c), va);
       nrm += va.x * va.x + va.y * va.y;
     }
   }
@@ -224,39 +236,31 @@ k_lz_combine(Basis B, int l0, int nl, const double2 *__restrict__ coef, double2 
   for (int l = 0; l < NL; ++l) q[l] = slot_ptr(B, l0 + (l < nl ? l : 0));
   const int64_t step = (int64_t)gridDim.x * R;
   int64_t r = (int64_t)blockIdx.x * R + r0;
-  for (; r + step < nrows; r += 2 * step) {
-    const int64_t oa = r * ncol + c, ob = (r + step) * ncol + c;
-    double2 va = acc_out ? out[oa] : make_double2(0.0, 0.0);
-    double2 vb = acc_out ? out[ob] : make_double2(0.0, 0.0);
+  // slots past a column's k hold unused data: they are not read (their coefficient is
+  // zero); the loads of a row's slots are all issued before its first product
+  bool use[NL];
 #pragma unroll
-    for (int l = 0; l < NL; ++l)
-      if (l < nl) {
-        const double2 h = cs[l * ncol + c];
-        if (h.x != 0.0 || h.y != 0.0) {   // slots past a column's k hold unused data
-          const double2 qa = q[l][oa], qb = q[l][ob];
-          va.x += h.x * qa.x - h.y * qa.y;
-          va.y += h.x * qa.y + h.y * qa.x;
-          vb.x += h.x * qb.x - h.y * qb.y;
-          vb.y += h.x * qb.y + h.y * qb.x;
-        }
-      }
-    out[oa] = va;
-    out[ob] = vb;
+  for (int l = 0; l < NL; ++l) {
+    const double2 h = l < nl ? cs[l * ncol + c] : make_double2(0.0, 0.0);
+    use[l] = h.x != 0.0 || h.y != 0.0;
   }
   for (; r < nrows; r += step) {
     const int64_t oa = r * ncol + c;
+    double2 qa[NL];
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      qa[l] = make_double2(0.0, 0.0);
+      if (use[l]) qa[l] = ldnt(q[l] + oa);
+    }
     double2 va = acc_out ? out[oa] : make_double2(0.0, 0.0);
 #pragma unroll
     for (int l = 0; l < NL; ++l)
-      if (l < nl) {
+      if (use[l]) {
         const double2 h = cs[l * ncol + c];
-        if (h.x != 0.0 || h.y != 0.0) {
-          const double2 qa = q[l][oa];
-          va.x += h.x * qa.x - h.y * qa.y;
-          va.y += h.x * qa.y + h.y * qa.x;
-        }
+        va.x += h.x * qa[l].x - h.y * qa[l].y;
+        va.y += h.x * qa[l].y + h.y * qa[l].x;
       }
-    out[oa] = va;
+    stnt(out + oa, va);
   }
 }
 
@@ -538,28 +542,28 @@ int lz_dots_t(const double *q0, const double *qb, int64_t bs, int nq, const W2 *
   return nb;
 }
 
-template <typename S2, bool INPLACE>
+template <typename S2, bool INPLACE, typename SHT>
 void lz_update_launch(int nl, int nb, size_t lds, hipStream_t s, const Basis &B, int l0, const double *coef,
-                      const double *g, const S2 *src, int64_t sld, double *w, float2 *shc, int64_t shld,
+                      const double *g, const S2 *src, int64_t sld, double *w, SHT *shc, int64_t shld,
                       int64_t nrows, int ncol, const int *mask, const int *any, int wn, int zm, double *part) {
   if (nl <= 4)
-    hipLaunchKernelGGL((k_lz_update<4, S2, INPLACE>), dim3(nb), dim3(kLzUpdThreads), lds, s, B, l0, nl,
+    hipLaunchKernelGGL((k_lz_update<4, S2, INPLACE, SHT>), dim3(nb), dim3(kLzUpdThreads), lds, s, B, l0, nl,
                        (const double2 *)coef, g, src, sld, (double2 *)w, shc, shld, nrows, ncol, mask, any, wn, zm,
                        (double2 *)part);
   else if (nl <= 8)
-    hipLaunchKernelGGL((k_lz_update<8, S2, INPLACE>), dim3(nb), dim3(kLzUpdThreads), lds, s, B, l0, nl,
+    hipLaunchKernelGGL((k_lz_update<8, S2, INPLACE, SHT>), dim3(nb), dim3(kLzUpdThreads), lds, s, B, l0, nl,
                        (const double2 *)coef, g, src, sld, (double2 *)w, shc, shld, nrows, ncol, mask, any, wn, zm,
                        (double2 *)part);
   else
-    hipLaunchKernelGGL((k_lz_update<kLzChunk, S2, INPLACE>), dim3(nb), dim3(kLzUpdThreads), lds, s, B, l0, nl,
+    hipLaunchKernelGGL((k_lz_update<kLzChunk, S2, INPLACE, SHT>), dim3(nb), dim3(kLzUpdThreads), lds, s, B, l0, nl,
                        (const double2 *)coef, g, src, sld, (double2 *)w, shc, shld, nrows, ncol, mask, any, wn, zm,
                        (double2 *)part);
 }
 
-// src == nullptr: in place on w
-template <typename S2>
+// src == nullptr: in place on w; sh: the reduced-precision copy (SHT float or Bf16) or nullptr
+template <typename S2, typename SHT>
 int lz_update_t(const double *q0, const double *qb, int64_t bs, int nq, const double *coef, const double *gw,
-                const S2 *src, int64_t sld, double *w, float *sh, int64_t shld, int64_t nrows, int ncol,
+                const S2 *src, int64_t sld, double *w, SHT *sh, int64_t shld, int64_t nrows, int ncol,
                 const int *mask, const int *any, double *part, hipStream_t s, int zero_masked) {
   const Basis B{(const double2 *)q0, (const double2 *)qb, bs / 2};
   const int nb = lz_grid(nrows, ncol, kLzUpdThreads);
@@ -569,16 +573,28 @@ int lz_update_t(const double *q0, const double *qb, int64_t bs, int nq, const do
     const bool last = l0 + nl == nq;
     const int wn = last ? 1 : 0;
     const double *g = l0 == 0 ? gw : nullptr;
-    float2 *shc = last ? (float2 *)sh : nullptr;
+    SHT *shc = last ? sh : nullptr;
     // the first chunk reads src; later chunks continue in place on w
     if (l0 == 0 && src)
-      lz_update_launch<S2, false>(nl, nb, lds, s, B, l0, coef, g, src, sld, w, shc, shld, nrows, ncol, mask, any, wn,
-                                  zero_masked, part);
+      lz_update_launch<S2, false, SHT>(nl, nb, lds, s, B, l0, coef, g, src, sld, w, shc, shld, nrows, ncol, mask, any,
+                                       wn, zero_masked, part);
     else
-      lz_update_launch<double2, true>(nl, nb, lds, s, B, l0, coef, g, nullptr, 0, w, shc, shld, nrows, ncol, mask,
-                                      any, wn, l0 == 0 ? zero_masked : 0, part);
+      lz_update_launch<double2, true, SHT>(nl, nb, lds, s, B, l0, coef, g, nullptr, 0, w, shc, shld, nrows, ncol,
+                                           mask, any, wn, l0 == 0 ? zero_masked : 0, part);
   }
   return nb;
+}
+
+// X (packed FP64, ncolr values per row) -> Xs (FP32 or BF16, ldf values per row; pad columns zero)
+template <typename SHT>
+__global__ void __launch_bounds__(256)
+k_to_shadow(const double *__restrict__ X, int64_t nrows, int ncolr, SHT *__restrict__ Xs, int64_t ldf) {
+  const int64_t n = nrows * ldf;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / ldf;
+    const int c = (int)(i - r * ldf);
+    Xs[i] = narrow<SHT>(c < ncolr ? X[r * ncolr + c] : 0.0);
+  }
 }
 
 }  // namespace
@@ -597,16 +613,29 @@ int lz_dots_f(const double *q0, const double *qb, int64_t bs, int nq, const floa
 
 int lz_update(const double *q0, const double *qb, int64_t bs, int nq, const double *coef, const double *gw, double *w,
               int64_t nrows, int ncol, const int *mask, const int *any, double *part, hipStream_t s, int zero_masked,
-              float *sh, int64_t shldf) {
-  return lz_update_t(q0, qb, bs, nq, coef, gw, (const double2 *)nullptr, 0, w, sh, shldf / 2, nrows, ncol, mask, any,
-                     part, s, zero_masked);
+              void *sh, int64_t shld, int sh_bf16) {
+  if (sh && sh_bf16)
+    return lz_update_t(q0, qb, bs, nq, coef, gw, (const double2 *)nullptr, 0, w, (Bf16 *)sh, shld / 2, nrows, ncol,
+                       mask, any, part, s, zero_masked);
+  return lz_update_t(q0, qb, bs, nq, coef, gw, (const double2 *)nullptr, 0, w, (float *)sh, shld / 2, nrows, ncol,
+                     mask, any, part, s, zero_masked);
 }
 
 int lz_update_from(const double *q0, const double *qb, int64_t bs, int nq, const double *coef, const double *gw,
-                   const float *src, int64_t ldf, double *w, float *sh, int64_t nrows, int ncol, const int *mask,
-                   const int *any, double *part, hipStream_t s, int zero_masked) {
-  return lz_update_t(q0, qb, bs, nq, coef, gw, (const float2 *)src, ldf / 2, w, sh, ldf / 2, nrows, ncol, mask, any,
-                     part, s, zero_masked);
+                   const float *src, int64_t ldf, double *w, void *sh, int sh_bf16, int64_t nrows, int ncol,
+                   const int *mask, const int *any, double *part, hipStream_t s, int zero_masked) {
+  if (sh_bf16)
+    return lz_update_t(q0, qb, bs, nq, coef, gw, (const float2 *)src, ldf / 2, w, (Bf16 *)sh, ldf / 2, nrows, ncol,
+                       mask, any, part, s, zero_masked);
+  return lz_update_t(q0, qb, bs, nq, coef, gw, (const float2 *)src, ldf / 2, w, (float *)sh, ldf / 2, nrows, ncol,
+                     mask, any, part, s, zero_masked);
+}
+
+void to_shadow(const double *X, int64_t nrows, int ncolr, void *Xs, int64_t ldf, int bf16, hipStream_t s) {
+  const int64_t n = nrows * ldf;
+  const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
+  if (bf16) hipLaunchKernelGGL(k_to_shadow<Bf16>, dim3(nb), dim3(256), 0, s, X, nrows, ncolr, (Bf16 *)Xs, ldf);
+  else hipLaunchKernelGGL(k_to_shadow<float>, dim3(nb), dim3(256), 0, s, X, nrows, ncolr, (float *)Xs, ldf);
 }
 
 void to_f32(const double *X, int64_t nrows, int ncolr, float *Xf, int64_t ldf, hipStream_t s) {
