@@ -122,6 +122,10 @@ def run_apply_mode(spec, dtype, n_apply):
 # arithmetic each stored-block type is multiplied in: the MFMA peak of that instruction
 MFMA_OF = {"f64": ("f64", 78.6), "f32": ("f32", 157.3), "bf16": ("bf16", 2500.0), "bf16x3": ("bf16", 2500.0 / 3)}
 BLOCK_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "bf16x3": 4}
+# bytes per real element of the orbital rows the cell products read (X: the FP64 Lanczos
+# vector, or its FP32 / BF16 copy) and write (Y: FP64, or the FP32 product block)
+X_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "bf16x3": 4}
+Y_BYTES = {"f64": 8, "f32": 4, "bf16": 4, "bf16x3": 4}
 
 
 def roofline(spec, res, dtype):
@@ -137,7 +141,10 @@ def roofline(spec, res, dtype):
     arithmetic intensity times the HBM bandwidth, whichever is lower; the achieved
     figure is flops or unique bytes over the time of all colour launches of one
     Hbar X (HIP events of the library on its stream).  The per-launch figures with
-    the gathered bytes are kept as secondary keys."""
+    the gathered bytes are kept as secondary keys, and so is the stricter fraction
+    on the kernel's own unique bytes (reduced-precision products read an FP32 or
+    BF16 copy of X and write an FP32 Y, fewer bytes than the FP64 rows counted
+    above)."""
     P = spec.degree + 1
     nloc = P ** 3
     ncells = spec.ncell[0] * spec.ncell[1] * spec.ncell[2]
@@ -165,7 +172,9 @@ def roofline(spec, res, dtype):
         incid *= nn[a] + spec.ncell[a] - 1
     yreads = (incid - n_nodes) / ncolour
     cells_l = ncells / ncolour
-    bytes_launch = cells_l * nloc * nloc * esz + 2 * cells_l * nloc * row + yreads * row
+    xrow, yrow = ncolr * X_BYTES[dtype], ncolr * Y_BYTES[dtype]
+    bytes_launch = cells_l * nloc * nloc * esz + cells_l * nloc * (xrow + yrow) + yreads * yrow
+    kernel_unique_hx = n_nodes * (xrow + yrow) + ncells * nloc * nloc * esz
     launch_s = hx_s / ncolour
     tr = traffic_summary(dtype)
     return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
@@ -175,7 +184,10 @@ def roofline(spec, res, dtype):
             "tflops": flop_hx / hx_s / 1e12, "unique_GBps": unique_hx / hx_s / 1e9,
             "launches_per_hx": ncolour, "launch_avg_us": launch_s * 1e6,
             "per_launch_bytes_with_gathers": bytes_launch, "per_launch_GBps_with_gathers": bytes_launch / launch_s / 1e9,
-            "hx_per_step": n_hx / max(1, len(res["k"])), "traffic_detail": tr}
+            "hx_per_step": n_hx / max(1, len(res["k"])), "traffic_detail": tr,
+            "kernel_unique_bytes_per_hx": kernel_unique_hx,
+            "kernel_unique_GBps": kernel_unique_hx / hx_s / 1e9,
+            "frac_of_hbm_on_kernel_unique_bytes": kernel_unique_hx / hx_s / 1e9 / HBM_GBS}
 
 
 def _cpu_model():
@@ -498,17 +510,18 @@ def main():
     if args.mode == "apply":
         run_apply_mode(spec, args.dtype, max(1, args.steps))
         return
-    res = run_gpu(spec, "f64", args.steps, args.warmup, args.kmax)
+    # the headline run is FP64; --dtype gives another product type for profiling runs
+    res = run_gpu(spec, args.dtype, args.steps, args.warmup, args.kmax)
     value = args.steps / res["wall"]
-    roof = roofline(spec, res, "f64")
+    roof = roofline(spec, res, args.dtype if args.dtype in MFMA_OF else "f64")
     out = {
         "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * res["wall"] / args.steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": args.dtype, "data": "synthetic",
         "config": {"workload": f"{spec.name}: {spec.natom} atoms, {spec.ncell[0]}^3 cells degree {spec.degree}, "
                                f"{(spec.ncell[0] * spec.degree + 1) ** 3} nodes, {spec.norb} orbitals, "
                                f"dt {spec.dt}, Krylov tol {spec.krylov_tol}, z kick {spec.kick}",
-                   "precision": "FP64 products, FP64 Lanczos",
+                   "precision": ("FP64" if args.dtype == "f64" else args.dtype.upper()) + " products, FP64 Lanczos",
                    "lanczos_reorthogonalisation": "partial (Simon's omega recurrence)"},
         "roofline": roof, "autotune": res["tune"],
         "stage_ms_per_step": {k: v / args.steps for k, v in res["stage"].items() if k != "n_hx"},
