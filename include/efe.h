@@ -203,8 +203,8 @@ efe_status efe_apply_H(efe_ctx *ctx, const void *X, void *Y, int32_t ncol, int64
  * serving loops, harnesses that forbid hipMalloc): the same Y = Hbar X as
  * efe_apply_H with no device or host allocation, no host synchronisation and no
  * use of the context's work blocks (FP64 products: bit for bit; with FP32 or BF16
- * blocks the rows stay FP64 between the colour passes and the coupling runs in
- * FP64, so the two agree to the precision of the products).  X and Y: device, n_rows x ncol, PACKED
+ * blocks the rows stay FP64 between the colour passes, so the two agree to the
+ * precision of the products).  X and Y: device, n_rows x ncol, PACKED
  * (leading dimension = ncol), distinct, Y fully overwritten; the call returns
  * once the kernels are enqueued on the context's stream (synchronise before
  * reading Y).  The enrichment coupling's partial sums live in a static device

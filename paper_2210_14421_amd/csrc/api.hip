@@ -65,15 +65,18 @@ struct efe_ctx {
   double *cg[7] = {nullptr};
   double *part = nullptr, *hee_part = nullptr, *G = nullptr, *Hee_raw = nullptr, *Hbar_ee = nullptr;
   // reduced-precision products (FP32 or BF16 blocks): the products read a reduced-precision
-  // copy of their input (xs: the current Lanczos vector, kept by the update kernels; BF16
-  // for BF16 blocks, FP32 otherwise) and leave their result in yf (FP32); G32 is the
-  // coupling G in FP32.  Rows of ldf elements (ncolr rounded up to 4: 16-byte aligned
-  // FP32 rows for the direct-to-LDS copies).
+  // copy of their input (BF16 for BF16 blocks, FP32 otherwise) and leave their result in
+  // FP32, in rows of ldf = ncolr rounded up to 4 elements (16-byte aligned FP32 rows for
+  // the direct-to-LDS copies).  Inside the Lanczos these live in memory the iteration does
+  // not use: the copy of slot j - 1 in the memory of slot j (written there by the update
+  // of iteration j - 1, before slot j is), the product in the block that receives the
+  // exponential at the end.  The standalone products (efe_apply_H, the adjoint's
+  // potential term, the autotuner) use ws_xs / ws_yf, allocated at their first use.  G
+  // (Hbar^ce on the union rows) is kept in FP32 only (G32).
   bool mixed = false;
   int xs_bf16 = 0;
-  int64_t ldf = 0;
-  void *xs = nullptr;
-  float *yf = nullptr, *G32 = nullptr;
+  void *ws_xs = nullptr;
+  float *ws_yf = nullptr, *G32 = nullptr;
   double *hee_blk = nullptr;   // block sums of the H^ee partials
   double *psiE = nullptr, *red = nullptr, *small = nullptr, *couple_scr = nullptr;
   efe::k::DenWork den, adj_den;   // density workspaces (forward columns; adjoint column pairs)
@@ -434,19 +437,10 @@ efe_status build_device(efe_ctx *ctx) {
   for (int i = 0; i < 7; ++i) EFE_TRY(dalloc(ctx, &ctx->cg[i], pl.n_nodes));
   EFE_TRY(dalloc(ctx, &ctx->part, tpart[d.nt]));
   EFE_TRY(dalloc(ctx, &ctx->hee_part, thee[d.nt]));
-  EFE_TRY(dalloc(ctx, &ctx->G, d.nr * std::max(1, d.nk)));
   ctx->mixed = ctx->dtype == 1 || ctx->dtype == 2 || ctx->dtype == 4;
-  if (ctx->mixed) {
-    ctx->ldf = (ctx->ncolr + 3) & ~3;
-    ctx->xs_bf16 = ctx->dtype == 2 ? 1 : 0;
-    float *xsf = nullptr;   // FP32 elements; a BF16 copy uses the first half
-    EFE_TRY(dalloc(ctx, &xsf, ctx->n_rows * ctx->ldf));
-    ctx->xs = xsf;
-    EFE_TRY(dalloc(ctx, &ctx->yf, ctx->n_rows * ctx->ldf));
-    EFE_TRY(dalloc(ctx, &ctx->G32, d.nr * std::max(1, d.nk)));
-    HIP_TRY(hipMemset(ctx->xs, 0, (size_t)ctx->n_rows * ctx->ldf * sizeof(float)));
-    HIP_TRY(hipMemset(ctx->yf, 0, (size_t)ctx->n_rows * ctx->ldf * sizeof(float)));
-  }
+  ctx->xs_bf16 = ctx->dtype == 2 ? 1 : 0;
+  if (ctx->mixed) EFE_TRY(dalloc(ctx, &ctx->G32, d.nr * std::max(1, d.nk)));
+  else EFE_TRY(dalloc(ctx, &ctx->G, d.nr * std::max(1, d.nk)));
   EFE_TRY(dalloc(ctx, &ctx->Hee_raw, (int64_t)d.ne * d.ne));
   EFE_TRY(dalloc(ctx, &ctx->hee_blk, std::max<int64_t>(1, efe::k::hee_scratch_size(d))));
   EFE_TRY(dalloc(ctx, &ctx->Hbar_ee, (int64_t)d.nk * d.nk));
@@ -519,26 +513,42 @@ void cell_products(efe_ctx *ctx, const double *X, double *Y, int ncolr, int64_t 
 }
 
 // The same with FP32 rows (reduced-precision products: FP32 or BF16 blocks)
+// row length (elements) of the reduced-precision blocks of ncolr real columns
+int64_t ldf_of(int ncolr) { return (ncolr + 3) & ~3; }
+
 void cell_products_f(efe_ctx *ctx, const void *X, float *Y, int ncolr, hipStream_t s, const int *any,
                      int variant = -1) {
   const int v = variant >= 0 ? variant : ctx->cell_variant;
-  efe::k::cell_apply_f(ctx->d, ctx->cells, ctx->dtype, X, Y, ncolr, ctx->ldf, s, any, v);
+  efe::k::cell_apply_f(ctx->d, ctx->cells, ctx->dtype, X, Y, ncolr, ldf_of(ncolr), s, any, v);
 }
 
-// yf = A xs: the reduced-precision products on the reduced-precision copy of their input;
-// the coupling reads the FP32 copy, or with BF16 blocks the FP64 rows X64 (the enrichment
-// rows carry the core states, whose coupling terms BF16 rounding would spoil)
-efe_status apply_op_f(efe_ctx *ctx, int ncolr, const int *any, const double *X64) {
+// yf = A xs: the reduced-precision products on the reduced-precision copy xs of their input
+// (rows of ldf_of(ncolr) elements); the coupling reads the FP32 copy, or with BF16 blocks
+// the FP64 rows X64 (the enrichment rows carry the core states, whose coupling terms BF16
+// rounding would spoil)
+efe_status apply_op_f(efe_ctx *ctx, int ncolr, const int *any, const void *xs, float *yf, const double *X64) {
   hipStream_t s = ctx->stream;
+  const int64_t ldf = ldf_of(ncolr);
   tstart(ctx, 0);
-  cell_products_f(ctx, ctx->xs, ctx->yf, ncolr, s, any);
+  cell_products_f(ctx, xs, yf, ncolr, s, any);
   tstop(ctx, 0);
   tstart(ctx, 1);
-  efe::k::couple_apply_f(ctx->d, ctx->G32, ctx->Hbar_ee, (const float *)ctx->xs, ctx->xs_bf16 ? X64 : nullptr,
-                         ctx->yf, ncolr, ctx->ldf, ctx->couple_scr, s, any);
+  efe::k::couple_apply_f(ctx->d, ctx->G32, ctx->Hbar_ee, (const float *)xs, ctx->xs_bf16 ? X64 : nullptr, yf, ncolr,
+                         ldf, ctx->couple_scr, s, any);
   tstop(ctx, 1);
   ctx->timer.n_hx++;
   return check_launch(ctx, "apply");
+}
+
+// work blocks of the standalone reduced-precision products (allocated at their first use)
+efe_status ensure_ws(efe_ctx *ctx) {
+  if (ctx->ws_yf) return EFE_OK;
+  const int64_t n = ctx->n_rows * ldf_of(ctx->ncolr);
+  float *xs = nullptr;
+  EFE_TRY(dalloc(ctx, &xs, n));
+  EFE_TRY(dalloc(ctx, &ctx->ws_yf, n));
+  ctx->ws_xs = xs;
+  return EFE_OK;
 }
 
 // Y = A X with the operator currently held in the cell blocks (packed rows); reduced-
@@ -551,10 +561,11 @@ efe_status apply_op(efe_ctx *ctx, const double *X, double *Y, int ncolr, int64_t
     ctx->err = "internal: apply_op expects packed blocks";
     return EFE_ERR_ARG;
   }
-  if (ctx->mixed && ctx->dtype != 3) {
-    efe::k::to_shadow(X, ctx->n_rows, ncolr, ctx->xs, ctx->ldf, ctx->xs_bf16, s);
-    EFE_TRY(apply_op_f(ctx, ncolr, any, X));
-    efe::k::from_f32(ctx->yf, ctx->ldf, ctx->n_rows, ncolr, Y, s);
+  if (ctx->mixed) {
+    EFE_TRY(ensure_ws(ctx));
+    efe::k::to_shadow(X, ctx->n_rows, ncolr, ctx->ws_xs, ldf_of(ncolr), ctx->xs_bf16, s);
+    EFE_TRY(apply_op_f(ctx, ncolr, any, ctx->ws_xs, ctx->ws_yf, X));
+    efe::k::from_f32(ctx->ws_yf, ldf_of(ncolr), ctx->n_rows, ncolr, Y, s);
     return check_launch(ctx, "apply");
   }
   tstart(ctx, 0);
@@ -656,8 +667,7 @@ efe_status rebuild(efe_ctx *ctx, int mode, const double *rho, double t, const ef
   efe::k::set_scalar(ctx->stepp + 2, efield, s);
   efe::k::rebuild_cells(d, mode, rho, ctx->phi, ctx->stepp + 2, fdir, ctx->plan.xc, ctx->cells, ctx->dtype, ctx->vq, s);
   efe::k::coupling_partials(d, ctx->vq, ctx->part, ctx->hee_part, s);
-  efe::k::coupling_gather(d, ctx->part, mode == 0 ? 1 : 0, ctx->G, s);
-  if (ctx->mixed) efe::k::to_f32(ctx->G, d.nr, d.nk, ctx->G32, d.nk, s);
+  efe::k::coupling_gather(d, ctx->part, mode == 0 ? 1 : 0, ctx->G, ctx->G32, s);
   efe::k::hee_reduce(d, ctx->hee_part, mode == 0 ? 1 : 0, ctx->Hee_raw, ctx->Hbar_ee, ctx->hee_blk, s);
   tstop(ctx, 6);
   ctx->cells_mode = mode;
@@ -686,7 +696,7 @@ efe_status dipole_of(efe_ctx *ctx, const double *rho, double mu[3]) {
 // exponential and stopping test.  With any != nullptr every kernel returns at
 // once when no column is active (device-driven loops), and *any is refreshed.
 efe_status lz_iteration(efe_ctx *ctx, double tau, const double *X, int ncol, int j, const int *kf, double tol,
-                        int *any) {
+                        int *any, double *out) {
   hipStream_t s = ctx->stream;
   const int64_t nrows = ctx->n_rows;
   const int ncolr = 2 * ncol;
@@ -694,10 +704,15 @@ efe_status lz_iteration(efe_ctx *ctx, double tau, const double *X, int ncol, int
   double *Qb = ctx->Q;
   const double *prev = j == 1 ? X : Qb + (int64_t)(j - 2) * bs;
   double *w = Qb + (int64_t)(j - 1) * bs;   // slot j
-  // reduced-precision products: xs holds slot j - 1 in FP32 and the product goes to yf,
-  // which the first update reads into slot j (writing the next xs)
+  // reduced-precision products: the copy of slot j - 1 sits in the memory of slot j, the
+  // product goes to the output block (free until the final combination); the first update
+  // reads it into slot j and writes the copy of slot j into the memory of slot j + 1 (none
+  // after the last iteration: no product follows)
   const bool mx = ctx->mixed;
-  if (mx) EFE_TRY(apply_op_f(ctx, ncolr, any, prev));
+  const int64_t ldf = ldf_of(ncolr);
+  float *yf = (float *)out;
+  void *xs_in = w, *xs_out = j < ctx->kmax ? (void *)(Qb + (int64_t)j * bs) : nullptr;
+  if (mx) EFE_TRY(apply_op_f(ctx, ncolr, any, xs_in, yf, prev));
   else EFE_TRY(apply_op(ctx, prev, w, ncolr, ncolr, any));
   tstart(ctx, 2);
   double *a_j = ctx->alpha + (int64_t)(j - 1) * ncol;
@@ -713,19 +728,19 @@ efe_status lz_iteration(efe_ctx *ctx, double tau, const double *X, int ncol, int
   int nb;
   if (partial) {
     const double *q0d = j == 1 ? X : Qb + (int64_t)(j - 2) * bs;   // slot j - 1
-    nb = mx ? efe::k::lz_dots_f(q0d, Qb + (int64_t)(j - 1) * bs, bs, 1, ctx->yf, ctx->ldf, nrows, ncol, ctx->active,
-                                any, 1, ctx->red, s)
+    nb = mx ? efe::k::lz_dots_f(q0d, Qb + (int64_t)(j - 1) * bs, bs, 1, yf, ldf, nrows, ncol, ctx->active, any, 1,
+                                ctx->red, s)
             : efe::k::lz_dots(q0d, Qb + (int64_t)(j - 1) * bs, bs, 1, w, nrows, ncol, ctx->active, any, 1, ctx->red, s);
     efe::k::reduce_partials(ctx->red, nb, 2 * ncolr, ctx->h1, s);
     efe::k::lz_coef3(ctx->h1, ctx->sig, ctx->beta, j, ncol, ctx->active, a_j, ctx->coef, ctx->gsc, ctx->msc, s);
   } else {
-    nb = mx ? efe::k::lz_dots_f(q0f, qbf, bs, nq, ctx->yf, ctx->ldf, nrows, ncol, ctx->active, any, 1, ctx->red, s)
+    nb = mx ? efe::k::lz_dots_f(q0f, qbf, bs, nq, yf, ldf, nrows, ncol, ctx->active, any, 1, ctx->red, s)
             : efe::k::lz_dots(q0f, qbf, bs, nq, w, nrows, ncol, ctx->active, any, 1, ctx->red, s);
     efe::k::reduce_partials(ctx->red, nb, (nq + 1) * ncolr, ctx->h1, s);
     efe::k::lz_coef1(ctx->h1, ctx->sig, j, first, ncol, ctx->active, a_j, ctx->coef, ctx->gsc, ctx->msc, s);
   }
-  nb = mx ? efe::k::lz_update_from(q0f, qbf, bs, nq, ctx->coef, ctx->gsc, ctx->yf, ctx->ldf, w, ctx->xs, ctx->xs_bf16,
-                                   nrows, ncol, ctx->active, any, ctx->red, s, 1)
+  nb = mx ? efe::k::lz_update_from(q0f, qbf, bs, nq, ctx->coef, ctx->gsc, yf, ldf, w, xs_out, ctx->xs_bf16, nrows,
+                                   ncol, ctx->active, any, ctx->red, s, 1)
           : efe::k::lz_update(q0f, qbf, bs, nq, ctx->coef, ctx->gsc, w, nrows, ncol, ctx->active, any, ctx->red, s, 1);
   efe::k::reduce_partials(ctx->red, nb, ncolr, ctx->nrm1, s);
   if (partial)
@@ -737,7 +752,7 @@ efe_status lz_iteration(efe_ctx *ctx, double tau, const double *X, int ncol, int
   efe::k::reduce_partials(ctx->red, nb, j * ncolr, ctx->h2n, s);
   efe::k::lz_coef2(ctx->h2n, ctx->nrm1, ctx->sig, j, ncol, ctx->need, ctx->coef, ctx->gsc, ctx->msc, s);
   nb = efe::k::lz_update(X, Qb, bs, j, ctx->coef, ctx->gsc, w, nrows, ncol, ctx->need, ctx->anyflag, ctx->red, s, 0,
-                         mx ? ctx->xs : nullptr, ctx->ldf, ctx->xs_bf16);
+                         mx ? xs_out : nullptr, ldf, ctx->xs_bf16);
   efe::k::reduce_partials(ctx->red, nb, ncolr, ctx->nrm2, s);
   efe::k::lz_beta(ctx->nrm1, ctx->nrm2, ctx->need, ctx->active, ctx->msc, j, ncol, b_j, ctx->sig, s);
   tstop(ctx, 2);
@@ -778,7 +793,8 @@ efe_status run_lanczos(efe_ctx *ctx, double tau, const double *X, double *out, i
   int nb = efe::k::lz_dots(X, Qb, bs, 0, X, nrows, ncol, ctx->one_mask, nullptr, 1, ctx->red, s);
   efe::k::reduce_partials(ctx->red, nb, ncolr, ctx->small, s);
   efe::k::lz_init(ctx->small, ncol, ctx->beta0, ctx->sig, ctx->active, ctx->kused, ctx->pro, s);
-  if (ctx->mixed) efe::k::to_shadow(X, nrows, ncolr, ctx->xs, ctx->ldf, ctx->xs_bf16, s);
+  // the reduced-precision copy of X (the first product's input) in the memory of slot 1
+  if (ctx->mixed) efe::k::to_shadow(X, nrows, ncolr, Qb, ldf_of(ncolr), ctx->xs_bf16, s);
   tstop(ctx, 2);
   efe::k::lz_any(ctx->active, ncol, ctx->lz_anyf, s);
   std::vector<double> b0h(ncol);
@@ -800,7 +816,7 @@ efe_status run_lanczos(efe_ctx *ctx, double tau, const double *X, double *out, i
   int enq = 0;
   auto enqueue = [&]() -> efe_status {
     ++enq;
-    EFE_TRY(lz_iteration(ctx, tau, X, ncol, enq, kf, tol, ctx->lz_anyf));
+    EFE_TRY(lz_iteration(ctx, tau, X, ncol, enq, kf, tol, ctx->lz_anyf, out));
     HIP_TRY(hipMemcpyAsync(ctx->lz_pin + (enq & 1), ctx->lz_anyf, sizeof(int), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipEventRecord(ctx->lz_ev[enq & 1], s));
     return EFE_OK;
@@ -876,9 +892,9 @@ efe_status run_lanczos_dev(efe_ctx *ctx, double tau, const double *X, double *ou
   int nb = efe::k::lz_dots(X, ctx->Q, bs, 0, X, nrows, ncol, ctx->one_mask, nullptr, 1, ctx->red, s);
   efe::k::reduce_partials(ctx->red, nb, ncolr, ctx->small, s);
   efe::k::lz_init(ctx->small, ncol, ctx->beta0, ctx->sig, ctx->active, ctx->kused, ctx->pro, s);
-  if (ctx->mixed) efe::k::to_shadow(X, nrows, ncolr, ctx->xs, ctx->ldf, ctx->xs_bf16, s);
+  if (ctx->mixed) efe::k::to_shadow(X, nrows, ncolr, ctx->Q, ldf_of(ncolr), ctx->xs_bf16, s);
   efe::k::lz_any(ctx->active, ncol, ctx->lz_anyf, s);
-  for (int j = 1; j <= ctx->kmax; ++j) EFE_TRY(lz_iteration(ctx, tau, X, ncol, j, nullptr, tol, ctx->lz_anyf));
+  for (int j = 1; j <= ctx->kmax; ++j) EFE_TRY(lz_iteration(ctx, tau, X, ncol, j, nullptr, tol, ctx->lz_anyf, out));
   efe::k::lz_comb_coef(ctx->ubuf, ctx->sig, ctx->beta0, ctx->kused, ctx->kmax, ctx->kmax, ncol, ctx->coef, s);
   efe::k::lz_kmax(ctx->kused, ncol, ctx->lz_kmaxu, s);
   efe::k::lz_combine(X, ctx->Q, bs, ctx->kmax, ctx->coef, out, nrows, ncol, s, ctx->lz_kmaxu);
@@ -934,8 +950,7 @@ efe_status rebuild_dev(efe_ctx *ctx, const double *rho, const double *efield, in
   EFE_TRY(hartree_dev(ctx, rho, ctx->phi, slot));
   efe::k::rebuild_cells(d, 0, rho, ctx->phi, efield, fdir, ctx->plan.xc, ctx->cells, ctx->dtype, ctx->vq, s);
   efe::k::coupling_partials(d, ctx->vq, ctx->part, ctx->hee_part, s);
-  efe::k::coupling_gather(d, ctx->part, 1, ctx->G, s);
-  if (ctx->mixed) efe::k::to_f32(ctx->G, d.nr, d.nk, ctx->G32, d.nk, s);
+  efe::k::coupling_gather(d, ctx->part, 1, ctx->G, ctx->G32, s);
   efe::k::hee_reduce(d, ctx->hee_part, 1, ctx->Hee_raw, ctx->Hbar_ee, ctx->hee_blk, s);
   return check_launch(ctx, "device rebuild");
 }
@@ -1584,8 +1599,12 @@ efe_status efe_apply_H_noalloc(efe_ctx *ctx, const void *X, void *Y, int32_t nco
   }
   const DevData &d = ctx->d;
   cell_products(ctx, (const double *)X, (double *)Y, ncolr, ncolr, ctx->stream, nullptr);
-  efe::k::couple_apply(d, ctx->G, ctx->Hbar_ee, (const double *)X, (double *)Y, ncolr, ncolr, g_scratch_ptr[dev],
-                       ctx->stream, nullptr);
+  if (ctx->mixed)   // H^ce in FP32 (the reduced-precision coupling) on the FP64 rows
+    efe::k::couple_apply_g32(d, ctx->G32, ctx->Hbar_ee, (const double *)X, (double *)Y, ncolr, ncolr,
+                             g_scratch_ptr[dev], ctx->stream, nullptr);
+  else
+    efe::k::couple_apply(d, ctx->G, ctx->Hbar_ee, (const double *)X, (double *)Y, ncolr, ncolr, g_scratch_ptr[dev],
+                         ctx->stream, nullptr);
   return check_launch(ctx, "apply_H_noalloc");
 }
 
@@ -2000,6 +2019,13 @@ efe_status efe_autotune(efe_ctx *ctx, const char *cache_path, int32_t flags, cha
       cand.push_back(v);
       names.push_back(nm);
     }
+    int nv2[2];
+    const int nn = efe::k::cell_narrow_variants(d.g.nloc, ctx->ncolr, nv2);
+    for (int i = 0; i < nn; ++i) {
+      efe::k::cell_variant_name(nv2[i], nm, sizeof(nm));
+      cand.push_back(nv2[i]);
+      names.push_back(nm);
+    }
     if (ctx->dtype == 0 && efe::k::sf_supported(d.g) && efe::k::sf_init(d.g) == 0) {
       cand.push_back(kSFVariant);
       names.push_back("sum_factorised");
@@ -2045,17 +2071,20 @@ efe_status efe_autotune(efe_ctx *ctx, const char *cache_path, int32_t flags, cha
     const int ncolr = ctx->ncolr;
     double *X = ctx->X0, *Y = ctx->X1, *Yref = ctx->Q;
     const int64_t n = ctx->plan.n_nodes * ncolr;   // the cell products write the classical rows only
-    if (ctx->mixed) efe::k::to_shadow(X, ctx->n_rows, ncolr, ctx->xs, ctx->ldf, ctx->xs_bf16, s);
+    if (ctx->mixed) {
+      EFE_TRY(ensure_ws(ctx));
+      efe::k::to_shadow(X, ctx->n_rows, ncolr, ctx->ws_xs, ldf_of(ncolr), ctx->xs_bf16, s);
+    }
     auto apply = [&](int v, double *out) {   // one application of shape v, result in out (FP64)
       if (ctx->mixed) {
-        cell_products_f(ctx, ctx->xs, ctx->yf, ncolr, s, nullptr, v);
-        efe::k::from_f32(ctx->yf, ctx->ldf, ctx->plan.n_nodes, ncolr, out, s);
+        cell_products_f(ctx, ctx->ws_xs, ctx->ws_yf, ncolr, s, nullptr, v);
+        efe::k::from_f32(ctx->ws_yf, ldf_of(ncolr), ctx->plan.n_nodes, ncolr, out, s);
       } else {
         cell_products(ctx, X, out, ncolr, ncolr, s, nullptr, v);
       }
     };
     auto timed = [&](int v) {
-      if (ctx->mixed) cell_products_f(ctx, ctx->xs, ctx->yf, ncolr, s, nullptr, v);
+      if (ctx->mixed) cell_products_f(ctx, ctx->ws_xs, ctx->ws_yf, ncolr, s, nullptr, v);
       else cell_products(ctx, X, Y, ncolr, ncolr, s, nullptr, v);
     };
     // squared 2-norm of a block on the device (fixed-order partial sums)

@@ -99,7 +99,8 @@ void axpby(const double *x, const double *y, double a, double b, double *out, in
 void rebuild_cells(const DevData &d, int mode, const double *rho, const double *phi, const double *efield, int fdir,
                    int xc, void *cells, int dtype, double *vq, hipStream_t s);
 void coupling_partials(const DevData &d, const double *vq, double *part, double *hee_part, hipStream_t s);
-void coupling_gather(const DevData &d, const double *part, int kinetic, double *G, hipStream_t s);
+// G = Hbar^ce on the union rows, in FP64 (G), or in FP32 (G32, when G is null)
+void coupling_gather(const DevData &d, const double *part, int kinetic, double *G, float *G32, hipStream_t s);
 // scratch: hee_scratch_size(d) doubles
 int64_t hee_scratch_size(const DevData &d);
 void hee_reduce(const DevData &d, const double *hee_part, int kinetic, double *Hee_raw, double *Hbar_ee,
@@ -128,6 +129,9 @@ int cell_bf16_variant_count(int nloc);
 // blocks of esz bytes (all give the same bits; variant 0 is the default), and their names
 int cell_variant_count(int nloc, size_t esz);
 void cell_variant_name(int v, char *out, int len);
+// narrow-tile variants (64 or 32 columns per workgroup) worth trying for ncolr real columns
+// (FP64 and FP32 blocks, degree <= 5): their ids in out[], their number returned
+int cell_narrow_variants(int nloc, int ncolr, int *out);
 // sum-factorised cell products (FP64, no stored blocks): Y = sum_c P_c^T Hbar_c P_c X from the
 // potential at the quadrature points (vq) and, with kinetic, the kinetic term
 bool sf_supported(const Geom &g);
@@ -136,6 +140,9 @@ void sf_apply(const DevData &d, const double *vq, int kinetic, const double *X, 
               hipStream_t s, const int *any = nullptr);
 void couple_apply(const DevData &d, const double *G, const double *Hee, const double *X, double *Y,
                   int ncolr, int64_t ldr, double *scratch, hipStream_t s, const int *any = nullptr);
+// the FP32 coupling (G in FP32, FP32 MFMA) on FP64 rows X and Y
+void couple_apply_g32(const DevData &d, const float *G, const double *Hee, const double *X, double *Y, int ncolr,
+                      int64_t ldr, double *scratch, hipStream_t s, const int *any = nullptr);
 // FP32 coupling products (FP32 MFMA; G and Y in FP32, Y with ldf floats per row); X: the
 // FP32 copy (ldf floats per row), or, when X64 is given, the packed FP64 rows
 void couple_apply_f(const DevData &d, const float *G, const double *Hee, const float *X, const double *X64,

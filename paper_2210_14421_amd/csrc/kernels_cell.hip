@@ -58,8 +58,7 @@ template <> struct Mfma<float> {
 // Wave w takes the M tiles (w >> 1) + 4 i and the three 16-column N tiles of
 // half (w & 1): every SIMD then carries the same number of tiles.
 constexpr int kCellWaves = 8;
-constexpr int kCellNT = 3;                  // N tiles per wave
-constexpr int kCellCols = 2 * kCellNT * 16; // columns per workgroup
+constexpr int kCellNT = 3;                  // N tiles per wave (default: 96 columns per workgroup)
 // LDS row stride of X in elements: the 4 rows of a B read hit disjoint banks
 // (FP64 rows: 112 doubles; FP32 rows: 144 floats, 16 banks apart)
 template <typename IO> constexpr int x_ldx() { return sizeof(IO) == 8 ? 112 : 144; }
@@ -94,7 +93,9 @@ inline size_t cell_lds_bytes(int nloc, size_t esz, int ns, int kc, size_t xsz = 
 }
 
 // IO: element type of X and Y (double, or float for FP32 blocks); ldr counts IO elements.
-template <typename T, typename IO, int CMT, int NS, int KC, int WPE>
+// NT: 16-column N tiles per wave, 32 NT columns per workgroup (narrow tiles for blocks of
+// few orbitals, whose columns would otherwise be mostly padding).
+template <typename T, typename IO, int CMT, int NS, int KC, int WPE, int NT = kCellNT>
 __global__ void __launch_bounds__(kCellWaves * 64) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, const T *__restrict__ cells,
              const IO *__restrict__ X, IO *__restrict__ Y, int ncolr, int64_t ldr, const int *__restrict__ any) {
@@ -118,8 +119,9 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
   unsigned char *Xs = cell_sm + NS * aseg * 1024;                // NS * kXStage
   unsigned char *junk = Xs + NS * kXStage;                       // 1 KB target of padding copies
   const int ci = blockIdx.x;
-  const int col0 = blockIdx.y * kCellCols;
-  const int wcol = ncolr - col0 < kCellCols ? ncolr - col0 : kCellCols;   // columns of this chunk (even)
+  constexpr int kCols = 2 * NT * 16;
+  const int col0 = blockIdx.y * kCols;
+  const int wcol = ncolr - col0 < kCols ? ncolr - col0 : kCols;   // columns of this chunk (even)
   const int64_t cell = cell_list[ci];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -169,11 +171,11 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
     }
   };
   const int nmt = (nloc + 15) / 16;
-  Acc acc[CMT][kCellNT];
+  Acc acc[CMT][NT];
 #pragma unroll
   for (int i = 0; i < CMT; ++i)
 #pragma unroll
-    for (int j = 0; j < kCellNT; ++j) acc[i][j] = Acc{0, 0, 0, 0};
+    for (int j = 0; j < NT; ++j) acc[i][j] = Acc{0, 0, 0, 0};
 #pragma unroll
   for (int c = 0; c < NS - 1; ++c)
     if (c < nchunk) issue(c);
@@ -193,9 +195,9 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
     for (int s4 = 0; s4 < KC / 4; ++s4) {
       const int kl = s4 * 4 + kr;
       const bool kok = kc * KC + kl < nloc;
-      C b[kCellNT], a[CMT];
+      C b[NT], a[CMT];
 #pragma unroll
-      for (int j = 0; j < kCellNT; ++j) b[j] = (C)Xl[kl * kLDX + (nh * kCellNT + j) * 16 + cl];
+      for (int j = 0; j < NT; ++j) b[j] = (C)Xl[kl * kLDX + (nh * NT + j) * 16 + cl];
 #pragma unroll
       for (int i = 0; i < CMT; ++i) {
         const int t = min(mg + 4 * i, nmt - 1);
@@ -206,7 +208,7 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
       for (int i = 0; i < CMT; ++i)
         if (mg + 4 * i < nmt) {
 #pragma unroll
-          for (int j = 0; j < kCellNT; ++j) acc[i][j] = Mfma<T>::mma(a[i], b[j], acc[i][j]);
+          for (int j = 0; j < NT; ++j) acc[i][j] = Mfma<T>::mma(a[i], b[j], acc[i][j]);
         }
     }
   }
@@ -220,15 +222,15 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
     if (mg + 4 * i >= nmt) continue;
 #pragma unroll
     for (int r0 = 0; r0 < 4; r0 += kRB) {
-      IO old[kRB][kCellNT];
+      IO old[kRB][NT];
 #pragma unroll
       for (int r = 0; r < kRB; ++r) {
         const int row = (mg + 4 * i) * 16 + Mfma<T>::row(kr, r0 + r);
         const bool add = row < nloc && !first[row];
         const IO *yr = Y + (row < nloc ? rowoff[row] : 0);
 #pragma unroll
-        for (int j = 0; j < kCellNT; ++j) {
-          const int col = col0 + (nh * kCellNT + j) * 16 + cl;
+        for (int j = 0; j < NT; ++j) {
+          const int col = col0 + (nh * NT + j) * 16 + cl;
           old[r][j] = (add && col < ncolr) ? yr[col] : (IO)0;
         }
       }
@@ -238,8 +240,8 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
         if (row >= nloc) continue;
         IO *yr = Y + rowoff[row];
 #pragma unroll
-        for (int j = 0; j < kCellNT; ++j) {
-          const int col = col0 + (nh * kCellNT + j) * 16 + cl;
+        for (int j = 0; j < NT; ++j) {
+          const int col = col0 + (nh * NT + j) * 16 + cl;
           if (col < ncolr) yr[col] = old[r][j] + (IO)acc[i][j][r0 + r];
         }
       }
@@ -247,16 +249,17 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
   }
 }
 
-template <typename T, int CMT, int NS, int KC, int WPE = (CMT <= 4 ? 4 : 2), typename IO>
+template <typename T, int CMT, int NS, int KC, int WPE = (CMT <= 4 ? 4 : 2), int NT = kCellNT, typename IO>
 void launch_apply_m(const DevData &d, const T *cells, const IO *X, IO *Y, int ncolr, int64_t ldr,
                     hipStream_t s, const int *any) {
-  const unsigned ny = (unsigned)((ncolr + kCellCols - 1) / kCellCols);
+  const unsigned ny = (unsigned)((ncolr + 32 * NT - 1) / (32 * NT));
   const size_t lds = cell_lds_bytes(d.g.nloc, sizeof(T), NS, KC, sizeof(IO));
   for (int c = 0; c < 8; ++c) {
     const int cnt = d.colour_off[c + 1] - d.colour_off[c];
     if (cnt == 0) continue;
     const int *list = d.colour_cells + d.colour_off[c];
-    hipLaunchKernelGGL((k_cell_apply<T, IO, CMT, NS, KC, WPE>), dim3((unsigned)cnt, ny), dim3(kCellWaves * 64), lds, s, d,
+    hipLaunchKernelGGL((k_cell_apply<T, IO, CMT, NS, KC, WPE, NT>), dim3((unsigned)cnt, ny), dim3(kCellWaves * 64), lds,
+                       s, d,
                        list, d.colour_off[c], cells, X, Y, ncolr, ldr, any);
   }
 }
@@ -270,6 +273,9 @@ constexpr int kCellVariantsF64 = 6;
 constexpr int kVarNS[kCellVariants] = {3, 2, 4, 2, 6, 4, 3, 2, 2};
 constexpr int kVarKC[kCellVariants] = {8, 8, 4, 16, 4, 8, 8, 8, 16};
 constexpr int kVarWPE[kCellVariants] = {4, 4, 4, 4, 4, 4, 6, 6, 6};
+// narrow-tile variants (the default pipeline with 64 or 32 columns per workgroup), for
+// blocks of at most that many real columns
+constexpr int kNarrow64 = 9, kNarrow32 = 10;
 
 template <typename T, int CMT, int V, typename IO>
 void launch_v(const DevData &d, const T *cells, const IO *X, IO *Y, int ncolr, int64_t ldr, hipStream_t s,
@@ -281,6 +287,8 @@ template <typename T, int CMT, typename IO>
 void launch_variant(int v, const DevData &d, const T *cells, const IO *X, IO *Y, int ncolr, int64_t ldr,
                     hipStream_t s, const int *any) {
   switch (v) {
+    case kNarrow64: launch_apply_m<T, CMT, kVarNS[0], kVarKC[0], kVarWPE[0], 2>(d, cells, X, Y, ncolr, ldr, s, any); break;
+    case kNarrow32: launch_apply_m<T, CMT, kVarNS[0], kVarKC[0], kVarWPE[0], 1>(d, cells, X, Y, ncolr, ldr, s, any); break;
     case 1: launch_v<T, CMT, 1>(d, cells, X, Y, ncolr, ldr, s, any); break;
     case 2: launch_v<T, CMT, 2>(d, cells, X, Y, ncolr, ldr, s, any); break;
     case 3: launch_v<T, CMT, 3>(d, cells, X, Y, ncolr, ldr, s, any); break;
@@ -309,6 +317,13 @@ int set_lds_v(size_t esz, int nloc) {
                                   (int)cell_lds_bytes(nloc, esz, kVarNS[V], kVarKC[V], sizeof(IO)));
 }
 
+template <typename T, typename IO, int CMT, int NT>
+int set_lds_nt(size_t esz, int nloc) {
+  return (int)hipFuncSetAttribute((const void *)k_cell_apply<T, IO, CMT, kVarNS[0], kVarKC[0], kVarWPE[0], NT>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)cell_lds_bytes(nloc, esz, kVarNS[0], kVarKC[0], sizeof(IO)));
+}
+
 template <typename T, typename IO, int CMT>
 int set_lds_io(int nloc) {
   const size_t e = sizeof(T);
@@ -316,7 +331,7 @@ int set_lds_io(int nloc) {
            set_lds_v<T, IO, CMT, 3>(e, nloc) | set_lds_v<T, IO, CMT, 4>(e, nloc) | set_lds_v<T, IO, CMT, 5>(e, nloc);
   if (sizeof(T) == 4)
     st |= set_lds_v<T, IO, CMT, 6>(e, nloc) | set_lds_v<T, IO, CMT, 7>(e, nloc) | set_lds_v<T, IO, CMT, 8>(e, nloc);
-  return st;
+  return st | set_lds_nt<T, IO, CMT, 2>(e, nloc) | set_lds_nt<T, IO, CMT, 1>(e, nloc);
 }
 
 template <typename T, int CMT>
@@ -337,7 +352,19 @@ int cell_variant_count(int nloc, size_t esz) {
   return n;
 }
 
+int cell_narrow_variants(int nloc, int ncolr, int *out) {
+  if ((nloc + 15) / 16 > 16) return 0;
+  int n = 0;
+  if (ncolr <= 64) out[n++] = kNarrow64;
+  if (ncolr <= 32) out[n++] = kNarrow32;
+  return n;
+}
+
 void cell_variant_name(int v, char *out, int len) {
+  if (v == kNarrow64 || v == kNarrow32) {
+    snprintf(out, len, "dense_ns%d_kc%d_cols%d", kVarNS[0], kVarKC[0], v == kNarrow64 ? 64 : 32);
+    return;
+  }
   if (v < 0 || v >= kCellVariants) v = 0;
   if (kVarWPE[v] == 4) snprintf(out, len, "dense_ns%d_kc%d", kVarNS[v], kVarKC[v]);
   else snprintf(out, len, "dense_ns%d_kc%d_w%d", kVarNS[v], kVarKC[v], kVarWPE[v]);

@@ -382,8 +382,9 @@ k_coupling_mfma(const DevData d, const double *__restrict__ vq, double *__restri
 // of the A tile a[r0 + i][4 s + k] from the row's cell pairs (at most 8).
 constexpr int kGatherWaves = 4096;
 
+template <typename GT>
 __global__ void __launch_bounds__(64)
-k_coupling_gather(const DevData d, const double *__restrict__ part, int kinetic, double *__restrict__ G,
+k_coupling_gather(const DevData d, const double *__restrict__ part, int kinetic, GT *__restrict__ G,
                   int64_t tiles_per_wave) {
   typedef double v4d __attribute__((ext_vector_type(4)));
   const int ne = d.ne, nk = d.nk;
@@ -445,7 +446,7 @@ k_coupling_gather(const DevData d, const double *__restrict__ part, int kinetic,
 #pragma unroll
       for (int nt = 0; nt < 3; ++nt) {
         const int kp = n0 + nt * 16 + cl;
-        if (kp < nk) G[row * nk + kp] = dm * acc[nt][r];
+        if (kp < nk) G[row * nk + kp] = (GT)(dm * acc[nt][r]);
       }
     }
   }
@@ -1432,14 +1433,18 @@ void coupling_partials(const DevData &d, const double *vq, double *part, double 
   hipLaunchKernelGGL(k_coupling_partials<true>, dim3(d.nt), dim3(kThreads), lds, s, d, vq, part, hee_part);
 }
 
-void coupling_gather(const DevData &d, const double *part, int kinetic, double *G, hipStream_t s) {
+void coupling_gather(const DevData &d, const double *part, int kinetic, double *G, float *G32, hipStream_t s) {
   if (d.nr == 0 || d.nk == 0) return;
   const int64_t ntiles = (d.nr + 15) / 16;
   const int64_t nw = ntiles < kGatherWaves ? ntiles : kGatherWaves;
   const int64_t tpw = (ntiles + nw - 1) / nw;
   const unsigned ny = (unsigned)((d.nk + 47) / 48);
-  hipLaunchKernelGGL(k_coupling_gather, dim3((unsigned)((ntiles + tpw - 1) / tpw), ny), dim3(64), 0, s, d, part,
-                     kinetic, G, tpw);
+  if (G)
+    hipLaunchKernelGGL(k_coupling_gather<double>, dim3((unsigned)((ntiles + tpw - 1) / tpw), ny), dim3(64), 0, s, d,
+                       part, kinetic, G, tpw);
+  else
+    hipLaunchKernelGGL(k_coupling_gather<float>, dim3((unsigned)((ntiles + tpw - 1) / tpw), ny), dim3(64), 0, s, d,
+                       part, kinetic, G32, tpw);
 }
 
 int64_t hee_scratch_size(const DevData &d) { return (int64_t)kHeeBlocks * d.ne * d.ne; }

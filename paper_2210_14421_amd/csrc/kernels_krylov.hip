@@ -523,6 +523,11 @@ void couple_apply(const DevData &d, const double *G, const double *Hee, const do
   couple_apply_t(d, G, Hee, X, ldr, Y, ncolr, ldr, scratch, s, any);
 }
 
+void couple_apply_g32(const DevData &d, const float *G, const double *Hee, const double *X, double *Y, int ncolr,
+                      int64_t ldr, double *scratch, hipStream_t s, const int *any) {
+  couple_apply_t(d, G, Hee, X, ldr, Y, ncolr, ldr, scratch, s, any);
+}
+
 void couple_apply_f(const DevData &d, const float *G, const double *Hee, const float *X, const double *X64,
                     float *Y, int ncolr, int64_t ldf, double *scratch, hipStream_t s, const int *any) {
   if (X64) couple_apply_t(d, G, Hee, X64, (int64_t)ncolr, Y, ncolr, ldf, scratch, s, any);
