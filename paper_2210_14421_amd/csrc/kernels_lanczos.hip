@@ -586,15 +586,13 @@ int lz_update_t(const double *q0, const double *qb, int64_t bs, int nq, const do
 }
 
 // X (packed FP64, ncolr values per row) -> Xs (FP32 or BF16, ldf values per row; pad columns zero)
+// (one row per 64-lane group of a 256-thread block; rows of up to 64 lanes x 4 elements)
 template <typename SHT>
 __global__ void __launch_bounds__(256)
 k_to_shadow(const double *__restrict__ X, int64_t nrows, int ncolr, SHT *__restrict__ Xs, int64_t ldf) {
-  const int64_t n = nrows * ldf;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = i / ldf;
-    const int c = (int)(i - r * ldf);
-    Xs[i] = narrow<SHT>(c < ncolr ? X[r * ncolr + c] : 0.0);
-  }
+  const int lane = threadIdx.x & 63;
+  for (int64_t r = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); r < nrows; r += (int64_t)gridDim.x * 4)
+    for (int c = lane; c < ldf; c += 64) Xs[r * ldf + c] = narrow<SHT>(c < ncolr ? X[r * ncolr + c] : 0.0);
 }
 
 }  // namespace
@@ -632,8 +630,7 @@ int lz_update_from(const double *q0, const double *qb, int64_t bs, int nq, const
 }
 
 void to_shadow(const double *X, int64_t nrows, int ncolr, void *Xs, int64_t ldf, int bf16, hipStream_t s) {
-  const int64_t n = nrows * ldf;
-  const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 8192);
+  const unsigned nb = (unsigned)std::min<int64_t>((nrows + 3) / 4, 8192);
   if (bf16) hipLaunchKernelGGL(k_to_shadow<Bf16>, dim3(nb), dim3(256), 0, s, X, nrows, ncolr, (Bf16 *)Xs, ldf);
   else hipLaunchKernelGGL(k_to_shadow<float>, dim3(nb), dim3(256), 0, s, X, nrows, ncolr, (float *)Xs, ldf);
 }
