@@ -297,12 +297,15 @@ def run_batch(steps, warmup, kmax, dtype="f32"):
     specs = {}
     ctxs, Psis = [], []
     members = batch_members()
+    tuned = {}
     for natom, seed, d, kick in members:
         spec = specs.setdefault((natom, seed), na_cluster(natom, seed=seed))
         c = Context(spec, dtype=dtype, kmax=kmax)
         P = c.initial_state()
         c.lanczos_expm(P, -kick, op=d)
         c.set_hamiltonian(P, 0.0)
+        # cell-product shape per cluster (the cache key is the problem shape: one tuning per cluster)
+        tuned[natom] = c.autotune(cache=TUNE_CACHE)["choice"]
         ctxs.append(c)
         Psis.append(P)
     torch.cuda.synchronize()
@@ -342,7 +345,7 @@ def run_batch(steps, warmup, kmax, dtype="f32"):
             "vs_baseline": None, "dtype": "f32 products, f64 Krylov", "data": "synthetic",
             "device_memory_used_GB": (total_b - free_b) / 1e9, "device_memory_total_GB": total_b / 1e9,
             "config": {"workload": "{Na2, Na4, Na6, Na8} x {x,y,z} x {1e-4,1e-3}, dt 0.02, tol 1e-10",
-                       "members": n, "kmax": kmax},
+                       "members": n, "kmax": kmax, "cell_product_shapes": {f"Na{k}": v for k, v in tuned.items()}},
             "sequential_ms_per_step": seq_ms, "speedup_vs_sequential": seq_ms / (1e3 * wall / steps),
             "krylov_k_mean_last": ks[-1] if ks else None}
 

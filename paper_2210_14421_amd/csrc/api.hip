@@ -2071,20 +2071,31 @@ efe_status efe_autotune(efe_ctx *ctx, const char *cache_path, int32_t flags, cha
     const int ncolr = ctx->ncolr;
     double *X = ctx->X0, *Y = ctx->X1, *Yref = ctx->Q;
     const int64_t n = ctx->plan.n_nodes * ncolr;   // the cell products write the classical rows only
+    // reduced-precision rows: in the Krylov slots 2 and 3 (free outside a Lanczos run), or in
+    // the standalone work blocks when the basis is shorter
+    void *xs = nullptr;
+    float *yf = nullptr;
     if (ctx->mixed) {
-      EFE_TRY(ensure_ws(ctx));
-      efe::k::to_shadow(X, ctx->n_rows, ncolr, ctx->ws_xs, ldf_of(ncolr), ctx->xs_bf16, s);
+      if (ctx->kmax >= 3) {
+        xs = ctx->Q + ctx->blk;
+        yf = (float *)(ctx->Q + 2 * ctx->blk);
+      } else {
+        EFE_TRY(ensure_ws(ctx));
+        xs = ctx->ws_xs;
+        yf = ctx->ws_yf;
+      }
+      efe::k::to_shadow(X, ctx->n_rows, ncolr, xs, ldf_of(ncolr), ctx->xs_bf16, s);
     }
     auto apply = [&](int v, double *out) {   // one application of shape v, result in out (FP64)
       if (ctx->mixed) {
-        cell_products_f(ctx, ctx->ws_xs, ctx->ws_yf, ncolr, s, nullptr, v);
-        efe::k::from_f32(ctx->ws_yf, ldf_of(ncolr), ctx->plan.n_nodes, ncolr, out, s);
+        cell_products_f(ctx, xs, yf, ncolr, s, nullptr, v);
+        efe::k::from_f32(yf, ldf_of(ncolr), ctx->plan.n_nodes, ncolr, out, s);
       } else {
         cell_products(ctx, X, out, ncolr, ncolr, s, nullptr, v);
       }
     };
     auto timed = [&](int v) {
-      if (ctx->mixed) cell_products_f(ctx, ctx->ws_xs, ctx->ws_yf, ncolr, s, nullptr, v);
+      if (ctx->mixed) cell_products_f(ctx, xs, yf, ncolr, s, nullptr, v);
       else cell_products(ctx, X, Y, ncolr, ncolr, s, nullptr, v);
     };
     // squared 2-norm of a block on the device (fixed-order partial sums)
