@@ -255,8 +255,10 @@ def cpu_baseline(spec, hx_per_step):
         Y[nodes] += m.cell_block(c, v) @ X[nodes]
     dt = time.perf_counter() - t0
     cores = int(max([i.get("num_threads", 1) for i in threadpool_info()] + [1]))
+    flop_hx = 2.0 * mesh.n_cells * float(spec.degree + 1) ** 6 * 2 * spec.norb
     out = {"value": 1.0 / (dt * hx_per_step), "unit": "steps/s", "cores": cores, "kind": "oracle",
            "estimate": True, "cpu_model": _cpu_model(),
+           "hx_cell_gflops": flop_hx / dt / 1e9,
            "sample": f"Na8 estimate (upper bound): oracle cell part of one Hbar X ({mesh.n_cells} cells, {dt:.1f} s "
                      f"at {cores} threads; set-up {t_setup:.0f} s untimed) scaled to {hx_per_step:.0f} Hbar X per "
                      f"step; coupling, vector work, densities, Poisson and rebuilds excluded"}
