@@ -331,16 +331,29 @@ def run_batch(steps, warmup, kmax, dtype="f32"):
     wall = time.perf_counter() - t1
     free_b, total_b = torch.cuda.mem_get_info()      # every member alive
     batch.close()
-    # the same members stepped one after another by the host-driven magnus_step
+    # the same members stepped one after another by the host-driven magnus_step, each timed
+    # alone: its cell-product work per second is what the GPU gives that member by itself
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    for c, P in zip(ctxs, Psis):
-        c.magnus_step(P, t, dt)
-    torch.cuda.synchronize()
+    alone = {}
+    for (natom, _, _, _), c, P in zip(members, ctxs, Psis):
+        ta = time.perf_counter()
+        st = c.magnus_step(P, t, dt)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - ta)
+        nhx = float(np.mean(st["k_pred"]) + np.mean(st["k_corr"]))
+        flop = 2.0 * (c.spec.degree + 1) ** 6 * int(np.prod(c.spec.ncell)) * 2 * c.norb * nhx
+        alone.setdefault(f"Na{natom}", []).append((ms, flop))
     seq_ms = 1e3 * (time.perf_counter() - t2)
     for c in ctxs:
         c.close()
     n = len(ctxs)
+    # the members' cell-product work at the best rate any member reaches alone: the time a
+    # launch shared by all members could at best approach if it ran every member at that rate
+    rates = {k: sum(f for _, f in v) / sum(m for m, _ in v) for k, v in alone.items()}
+    best = max(rates, key=rates.get)
+    total_flop = sum(f for v in alone.values() for _, f in v)
+    bound_ms = total_flop / rates[best]
     return {"metric": f"batched Magnus steps/s ({n} independent Na2/Na4/Na6/Na8 propagations, one hipGraph per step)",
             "value": n * steps / wall, "unit": "propagation-steps/s", "n_gpus": 1, "steps": steps,
             "warmup": warmup, "ms_per_step": 1e3 * wall / steps, "higher_is_better": True, "scaling": "weak",
@@ -349,6 +362,10 @@ def run_batch(steps, warmup, kmax, dtype="f32"):
             "config": {"workload": "{Na2, Na4, Na6, Na8} x {x,y,z} x {1e-4,1e-3}, dt 0.02, tol 1e-10",
                        "members": n, "kmax": kmax, "cell_product_shapes": {f"Na{k}": v for k, v in tuned.items()}},
             "sequential_ms_per_step": seq_ms, "speedup_vs_sequential": seq_ms / (1e3 * wall / steps),
+            "alone_ms_per_step": {k: [round(m, 2) for m, _ in v] for k, v in alone.items()},
+            "alone_cell_gflop_per_s": {k: r / 1e6 for k, r in rates.items()},
+            "ms_per_step_at_best_alone_rate": bound_ms, "best_alone_rate_member": best,
+            "batch_over_best_alone_rate": (1e3 * wall / steps) / bound_ms,
             "krylov_k_mean_last": ks[-1] if ks else None}
 
 
