@@ -47,98 +47,19 @@ template <> struct CMfma<float> {
 //   Y_E     = G^T X[R] + Hbar^ee X_E
 // on the 16x16x4 MFMA: FP64, or FP32 for the reduced-precision products (G, X and
 // Y in FP32, FP32 accumulation; the workgroup partials of Y_E and Hbar^ee X_E in FP64).
-//   k_couple_c: one wave per block walks a contiguous range of 16-row tiles of
-//               R; a block covers KNT 16-column tiles (blockIdx.y).
-//   k_couple_e: a workgroup of kCpWaves waves takes a contiguous range of
-//               tiles, 48 columns (blockIdx.y) and 48 functions (blockIdx.z);
-//               wave w walks every kCpWaves-th tile of the range and keeps its
-//               Y_E sums in registers; the waves' sums are added in LDS in wave
-//               order and written as the workgroup's partial, and two
-//               reduction kernels sum the partials in a fixed order.
-// The two products run as separate launches: the Y_E sums hold 72 registers,
-// which in one fused kernel would cut the occupancy of the Y_C stream.
+//   k_couple_fused (n_k <= 48): both products in one pass over the rows of R.
+//   k_couple_c / k_couple_e (any n_k): Y_C by one wave per block over a contiguous
+//               range of 16-row tiles (a block covers KNT 16-column tiles); Y_E by
+//               workgroups of kCpWaves waves over a contiguous range of tiles, 48
+//               columns (blockIdx.y) and 48 functions (blockIdx.z), each wave keeping
+//               its Y_E sums in registers.
+// Workgroup partials of Y_E are added in LDS in wave order and written per
+// workgroup; two reduction kernels sum them in a fixed order.
 // ---------------------------------------------------------------------------
 constexpr int kCoupleCWaves = 4096;   // four per SIMD
 constexpr int KNT = 6;    // 16-column tiles per block (88 columns = 5.5 tiles)
 
-// Y_C += G X_E for n_k <= 48: a workgroup of kCcWaves waves per (range of
-// 16-row tiles, 48-column slice), X_E of the slice in LDS.  Per tile a wave
-// issues the loads of its A operands (G rows) and of the Y rows it updates
-// before the products, so one wait covers the tile.  Flat block b runs on XCD
-// b mod 8; the slices of one tile range are consecutive blocks of one XCD, so
-// the second slice reads the G tile from L2.
-constexpr int kCcWaves = 4;
-constexpr int kCcBlocks = 1024;   // tile ranges
-constexpr int kCcNT = 3;          // 16-column tiles per slice
-constexpr int kCcMaxK = 48;
-
-template <typename GT, typename XT, typename IO>
-__global__ void __launch_bounds__(kCcWaves * 64) __attribute__((amdgpu_waves_per_eu(3)))
-k_couple_c48(const DevData d, const GT *__restrict__ G, const XT *__restrict__ X, int64_t ldx, IO *__restrict__ Y,
-             int ncolr, int64_t ldr, int64_t tiles_per_block, int nranges, int nslice, const int *__restrict__ any) {
-  if (any && *any == 0) return;
-  __shared__ GT xe[kCcMaxK * kCcNT * 16];
-  const int nk = d.nk;
-  const int64_t nr = d.nr;
-  const int b = blockIdx.x, xcd = b & 7, q = b >> 3;
-  const int slice = q % nslice, range = (q / nslice) * 8 + xcd;
-  if (range >= nranges) return;
-  const int tid = threadIdx.x, lane = tid & 63, kr = lane >> 4, cl = lane & 15, wave = tid >> 6;
-  const int n0 = slice * kCcNT * 16;
-  const XT *XE = X + (int64_t)d.g.n_nodes * ldx;
-  for (int t = tid; t < kCcMaxK * kCcNT * 16; t += kCcWaves * 64) {
-    const int k = t / (kCcNT * 16), c = n0 + t % (kCcNT * 16);
-    xe[t] = (k < nk && c < ncolr) ? (GT)to_wide(XE[(int64_t)k * ldx + c]) : (GT)0;
-  }
-  __syncthreads();
-  int col[kCcNT];
-  bool cok[kCcNT];
-#pragma unroll
-  for (int nt = 0; nt < kCcNT; ++nt) {
-    col[nt] = n0 + nt * 16 + cl;
-    cok[nt] = col[nt] < ncolr;
-  }
-  const int64_t ntiles = (nr + 15) / 16;
-  const int64_t t_begin = (int64_t)range * tiles_per_block;
-  const int64_t t_end = t_begin + tiles_per_block < ntiles ? t_begin + tiles_per_block : ntiles;
-  for (int64_t t = t_begin + wave; t < t_end; t += kCcWaves) {
-    const int64_t r0 = t * 16, ra = r0 + cl;
-    const bool rok = ra < nr;
-    GT a[kCcMaxK / 4];
-#pragma unroll
-    for (int ks = 0; ks < kCcMaxK / 4; ++ks) {
-      const int k = ks * 4 + kr;
-      a[ks] = (rok && k < nk) ? G[ra * nk + k] : (GT)0;
-    }
-    int64_t yoff[4];
-    IO yv[4][kCcNT];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t row = r0 + CMfma<GT>::row(kr, r);
-      yoff[r] = row < nr ? d.urow_node[row] * ldr : -1;
-#pragma unroll
-      for (int nt = 0; nt < kCcNT; ++nt) yv[r][nt] = (yoff[r] >= 0 && cok[nt]) ? Y[yoff[r] + col[nt]] : (IO)0;
-    }
-    typename CMfma<GT>::Acc acc[kCcNT];
-#pragma unroll
-    for (int nt = 0; nt < kCcNT; ++nt) acc[nt] = typename CMfma<GT>::Acc{0, 0, 0, 0};
-#pragma unroll
-    for (int ks = 0; ks < kCcMaxK / 4; ++ks) {
-#pragma unroll
-      for (int nt = 0; nt < kCcNT; ++nt) {
-        const GT bv = xe[(ks * 4 + kr) * (kCcNT * 16) + nt * 16 + cl];
-        acc[nt] = CMfma<GT>::mma(a[ks], bv, acc[nt]);
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      if (yoff[r] < 0) continue;
-#pragma unroll
-      for (int nt = 0; nt < kCcNT; ++nt)
-        if (cok[nt]) Y[yoff[r] + col[nt]] = yv[r][nt] + (IO)acc[nt][r];
-    }
-  }
-}
+constexpr int kCcMaxK = 48;   // most enrichment directions of the one-pass kernel
 
 // general n_k: one wave per block, X_E from global memory
 template <typename GT, typename XT, typename IO>
@@ -266,6 +187,146 @@ k_couple_e(const DevData d, const GT *__restrict__ G, const XT *__restrict__ X, 
   for (int idx = tid; idx < kCpMT * 16 * kCpNT * 16; idx += kCpWaves * 64) {
     const int m = m0 + idx / (kCpNT * 16), c = n0 + idx % (kCpNT * 16);
     if (m < nk && c < ncolr) pb[(int64_t)m * ncolr + c] = red[idx];
+  }
+}
+
+// Both products in one pass over the union rows (n_k <= 48): per 16-row tile a wave
+// loads the tile's G rows, and the X and Y rows of its column slice, once; it adds G X_E
+// into the Y rows and accumulates G^T X[R] in registers.  The four rows a lane holds are
+// the rows of its output registers for Y_C, and the same rows serve as its k rows for
+// Y_E (step s takes row(kr, s)), so one gather of node offsets covers both products.
+// The node offsets of the wave's next tile are loaded while the current tile's
+// products run.  Workgroup (range, slice) partials of Y_E are summed in LDS in wave
+// order and reduced by k_couple_sum as those of k_couple_e.
+constexpr int kCfWaves = 4;
+constexpr int kCfRanges = kCpBlocks;   // tile ranges: one partial block each
+
+template <typename GT, typename XT, typename IO, int NT>
+__global__ void __launch_bounds__(kCfWaves * 64) __attribute__((amdgpu_waves_per_eu(2)))
+k_couple_fused(const DevData d, const GT *__restrict__ G, const XT *__restrict__ X, int64_t ldx,
+               IO *__restrict__ Y, int ncolr, int64_t ldr, int64_t tiles_per_range, int nranges, int nslice,
+               double *__restrict__ part, const int *__restrict__ any) {
+  if (any && *any == 0) return;
+  constexpr int kMT = kCcMaxK / 16;
+  constexpr int kNC = NT * 16;
+  __shared__ GT xe[kCcMaxK * kNC];
+  __shared__ double red[kMT * 16 * kNC];
+  const int nk = d.nk;
+  const int64_t nr = d.nr;
+  const int b = blockIdx.x, xcd = b & 7, q = b >> 3;
+  const int slice = q % nslice, range = (q / nslice) * 8 + xcd;
+  if (range >= nranges) return;   // the whole workgroup: no barrier is left waiting
+  const int tid = threadIdx.x, lane = tid & 63, kr = lane >> 4, cl = lane & 15, wave = tid >> 6;
+  const int n0 = slice * kNC;
+  const XT *XE = X + (int64_t)d.g.n_nodes * ldx;
+  for (int i = tid; i < kCcMaxK * kNC; i += kCfWaves * 64) {
+    const int k = i / kNC, c = n0 + i % kNC;
+    xe[i] = (k < nk && c < ncolr) ? (GT)to_wide(XE[(int64_t)k * ldx + c]) : (GT)0;
+  }
+  __syncthreads();
+  int col[NT];
+  bool cok[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    col[nt] = n0 + nt * 16 + cl;
+    cok[nt] = col[nt] < ncolr;
+  }
+  const int64_t ntiles = (nr + 15) / 16;
+  const int64_t t_begin = (int64_t)range * tiles_per_range;
+  const int64_t t_end = t_begin + tiles_per_range < ntiles ? t_begin + tiles_per_range : ntiles;
+  typename CMfma<GT>::Acc acc_e[kMT][NT];
+#pragma unroll
+  for (int mt = 0; mt < kMT; ++mt)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc_e[mt][nt] = typename CMfma<GT>::Acc{0, 0, 0, 0};
+  int64_t nd[4];   // nodes of the lane's rows of the tile (-1 past n_R)
+  int64_t t = t_begin + wave;
+  if (t < t_end) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = t * 16 + CMfma<GT>::row(kr, r);
+      nd[r] = row < nr ? d.urow_node[row] : -1;
+    }
+  }
+  for (; t < t_end; t += kCfWaves) {
+    const int64_t r0 = t * 16;
+    const int64_t ra = r0 + cl;
+    const bool rok = ra < nr;
+    GT a[kCcMaxK / 4];   // Y_C: A(i, k) = G[r0 + i][k]
+#pragma unroll
+    for (int ks = 0; ks < kCcMaxK / 4; ++ks) {
+      const int k = ks * 4 + kr;
+      a[ks] = (rok && k < nk) ? G[ra * nk + k] : (GT)0;
+    }
+    GT ae[4][kMT];       // Y_E: A(i, k) = G[row(k, s)][16 mt + i]
+    GT xv[4][NT];        //      B(k, j) = X[node(row(k, s))][j]
+    IO yv[4][NT];
+    int64_t nc[4];
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int64_t row = r0 + CMfma<GT>::row(kr, s4);
+      const bool ok = row < nr;
+#pragma unroll
+      for (int mt = 0; mt < kMT; ++mt) {
+        const int m = mt * 16 + cl;
+        ae[s4][mt] = (ok && m < nk) ? G[row * nk + m] : (GT)0;
+      }
+      nc[s4] = nd[s4];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const bool v = nc[s4] >= 0 && cok[nt];
+        xv[s4][nt] = v ? (GT)to_wide(X[nc[s4] * ldx + col[nt]]) : (GT)0;
+        yv[s4][nt] = v ? Y[nc[s4] * ldr + col[nt]] : (IO)0;
+      }
+    }
+    if (t + kCfWaves < t_end) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = (t + kCfWaves) * 16 + CMfma<GT>::row(kr, r);
+        nd[r] = row < nr ? d.urow_node[row] : -1;
+      }
+    }
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+      for (int mt = 0; mt < kMT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc_e[mt][nt] = CMfma<GT>::mma(ae[s4][mt], xv[s4][nt], acc_e[mt][nt]);
+    typename CMfma<GT>::Acc acc[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) acc[nt] = typename CMfma<GT>::Acc{0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < kCcMaxK / 4; ++ks)
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+        acc[nt] = CMfma<GT>::mma(a[ks], xe[(ks * 4 + kr) * kNC + nt * 16 + cl], acc[nt]);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      if (nc[r] < 0) continue;
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+        if (cok[nt]) Y[nc[r] * ldr + col[nt]] = yv[r][nt] + (IO)acc[nt][r];
+    }
+  }
+  // workgroup partial of Y_E: red[m][c] = sum over waves in wave order
+  for (int w = 0; w < kCfWaves; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int mt = 0; mt < kMT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt) {
+            const int idx = (mt * 16 + CMfma<GT>::row(kr, r)) * kNC + nt * 16 + cl;
+            red[idx] = (w == 0 ? 0.0 : red[idx]) + (double)acc_e[mt][nt][r];
+          }
+    }
+    __syncthreads();
+  }
+  double *pb = part + (int64_t)range * nk * ncolr;
+  for (int i = tid; i < kMT * 16 * kNC; i += kCfWaves * 64) {
+    const int m = i / kNC, c = n0 + i % kNC;
+    if (m < nk && c < ncolr) pb[(int64_t)m * ncolr + c] = red[i];
   }
 }
 
@@ -483,25 +544,30 @@ void couple_apply_t(const DevData &d, const GT *G, const double *Hee, const XT *
   const int nout = d.nk * ncolr;
   double *lvl1 = scratch + (int64_t)kCpBlocks * nout;
   int nsl = 1;
-  if (d.nr > 0) {
+  if (d.nr > 0 && d.nk <= kCcMaxK) {
+    // one pass: 48-column slices for FP32 rows and blocks, 32-column slices where the
+    // G or X values are FP64 (the Y_E sums of a 48-column slice would spill)
+    constexpr int NT = (sizeof(GT) == 4 && sizeof(XT) == 4) ? 3 : 2;
+    const int64_t ntiles = (d.nr + 15) / 16;
+    const int64_t tpr = (ntiles + kCfRanges - 1) / kCfRanges;
+    const int nranges = (int)((ntiles + tpr - 1) / tpr);
+    const int nslice = (ncolr + NT * 16 - 1) / (NT * 16);
+    const unsigned nb = (unsigned)(((nranges + 7) / 8) * 8 * nslice);
+    hipLaunchKernelGGL((k_couple_fused<GT, XT, IO, NT>), dim3(nb), dim3(kCfWaves * 64), 0, s, d, G, X, ldx, Y, ncolr, ldr,
+                       tpr, nranges, nslice, scratch, any);
+    nsl = kCpSlices;
+    hipLaunchKernelGGL(k_couple_sum, dim3(nblocks((int64_t)nout, 64), kCpSlices), dim3(256), 0, s, scratch, nranges, nout,
+                       lvl1, any);
+  } else if (d.nr > 0) {
     const int64_t ntiles = (d.nr + 15) / 16;
     const int64_t tpb = (ntiles + kCpBlocks - 1) / kCpBlocks;
     const int nblk = (int)((ntiles + tpb - 1) / tpb);
     const unsigned ny = (unsigned)((ncolr + kCpNT * 16 - 1) / (kCpNT * 16));
     const unsigned nz = (unsigned)((d.nk + kCpMT * 16 - 1) / (kCpMT * 16));
     const unsigned nyc = (unsigned)((ncolr + KNT * 16 - 1) / (KNT * 16));
-    if (d.nk <= kCcMaxK) {
-      const int64_t tpr = (ntiles + kCcBlocks - 1) / kCcBlocks;
-      const int nranges = (int)((ntiles + tpr - 1) / tpr);
-      const int nslice = (ncolr + kCcNT * 16 - 1) / (kCcNT * 16);
-      const unsigned nb = (unsigned)(((nranges + 7) / 8) * 8 * nslice);
-      hipLaunchKernelGGL((k_couple_c48<GT, XT, IO>), dim3(nb), dim3(kCcWaves * 64), 0, s, d, G, X, ldx, Y, ncolr, ldr, tpr,
-                         nranges, nslice, any);
-    } else {
-      const int64_t tpc = (ntiles + kCoupleCWaves - 1) / kCoupleCWaves;
-      hipLaunchKernelGGL((k_couple_c<GT, XT, IO>), dim3((unsigned)((ntiles + tpc - 1) / tpc), nyc), dim3(64), 0, s, d, G,
-                         X, ldx, Y, ncolr, ldr, tpc, any);
-    }
+    const int64_t tpc = (ntiles + kCoupleCWaves - 1) / kCoupleCWaves;
+    hipLaunchKernelGGL((k_couple_c<GT, XT, IO>), dim3((unsigned)((ntiles + tpc - 1) / tpc), nyc), dim3(64), 0, s, d, G, X,
+                       ldx, Y, ncolr, ldr, tpc, any);
     hipLaunchKernelGGL((k_couple_e<GT, XT>), dim3((unsigned)nblk, ny, nz), dim3(kCpWaves * 64), 0, s, d, G, X, ncolr,
                        ldx, tpb, scratch, any);
     nsl = kCpSlices;

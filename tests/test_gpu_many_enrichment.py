@@ -3,7 +3,7 @@ tiny box, 52 functions, all kept, up to 52 nonzero on one T-cell).
 
 Past 48 functions on a T-cell the coupling partials leave the MFMA kernel for
 the general one, and past 48 kept directions the enrichment-coupling product
-leaves k_couple_c48 for the general row-tile kernel; the density's folded rows
+leaves the one-pass k_couple_fused for the row-tile kernels; the density's folded rows
 and enrichment cells, the H^ee assembly and the Lowdin step run with 52.
 Against the oracle at the same seeded orthonormal two-orbital block:
 * density (1e-12), Hartree (1e-11), dipole (1e-12);
