@@ -69,8 +69,9 @@ def run_gpu(spec, dtype, steps, warmup, kmax, scheme="pc", reorth="partial", aut
     wall = time.perf_counter() - t_start
     G = Psi.conj().T @ Psi
     orth = float((G - torch.eye(spec.norb, dtype=G.dtype, device=G.device)).abs().max())
+    dims = dict(n_union_rows=ctx.n_union_rows, n_kept=ctx.n_kept)
     ctx.close()
-    return dict(wall=wall, stage=stage, k=ks, mu=mus, orth=orth, setup_s=setup_s, tune=tune)
+    return dict(wall=wall, stage=stage, k=ks, mu=mus, orth=orth, setup_s=setup_s, tune=tune, dims=dims)
 
 
 def traffic_summary(dtype):
@@ -177,6 +178,24 @@ def roofline(spec, res, dtype):
     kernel_unique_hx = n_nodes * (xrow + yrow) + ncells * nloc * nloc * esz
     launch_s = hx_s / ncolour
     tr = traffic_summary(dtype)
+    # enrichment coupling of the same Hbar X: Y_C[R] += G X_E and Y_E = G^T X[R] (+ the
+    # small H^ee X_E), G the n_R x n_k block; unique bytes: G, the X rows of R and the Y
+    # rows of R read and written, in the element types the kernels use (FP64 X rows with
+    # BF16 blocks)
+    nr, nk = res["dims"]["n_union_rows"], res["dims"]["n_kept"]
+    cp_s = res["stage"]["coupling"] * 1e-3 / n_hx
+    gsz = 8 if dtype == "f64" else 4
+    cxsz = 8 if dtype in ("f64", "bf16") else 4
+    cp_flop = 4.0 * nr * nk * ncolr
+    cp_bytes = nr * nk * gsz + nr * ncolr * (cxsz + 2 * Y_BYTES[dtype])
+    whole_s = hx_s + cp_s
+    if bound == "mfma":
+        whole_frac = (flop_hx + cp_flop) / whole_s / 1e12 / peak
+    else:
+        whole_frac = (unique_hx + cp_bytes) / whole_s / 1e9 / peak
+    coupling = {"us_per_hx": cp_s * 1e6, "flop_per_hx": cp_flop, "unique_bytes_per_hx": cp_bytes,
+                "GBps": cp_bytes / cp_s / 1e9, "frac_of_hbm": cp_bytes / cp_s / 1e9 / HBM_GBS,
+                "n_union_rows": nr, "n_k": nk}
     return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit, "frac": achieved / peak,
             "traffic": None if tr is None else tr["total"] * ncolour,
             "kernel": "k_cell_bf16" if dtype in ("bf16", "bf16x3") else "k_cell_apply", "mfma_instruction": inst, "flop_per_hx": flop_hx,
@@ -187,7 +206,8 @@ def roofline(spec, res, dtype):
             "hx_per_step": n_hx / max(1, len(res["k"])), "traffic_detail": tr,
             "kernel_unique_bytes_per_hx": kernel_unique_hx,
             "kernel_unique_GBps": kernel_unique_hx / hx_s / 1e9,
-            "frac_of_hbm_on_kernel_unique_bytes": kernel_unique_hx / hx_s / 1e9 / HBM_GBS}
+            "frac_of_hbm_on_kernel_unique_bytes": kernel_unique_hx / hx_s / 1e9 / HBM_GBS,
+            "coupling": coupling, "whole_hx_us": whole_s * 1e6, "whole_hx_frac": whole_frac}
 
 
 def _cpu_model():

@@ -176,8 +176,10 @@ const char *efe_plan_error(const efe_plan *plan);
  * Errors: EFE_ERR_ARG, EFE_ERR_SINGULAR, EFE_ERR_ALLOC, EFE_ERR_HIP. */
 efe_status efe_setup(const efe_system *sys, const efe_options *opt, efe_ctx **out);
 efe_status efe_free(efe_ctx *ctx);
-/* n_rows (= n_nodes + n_enr_kept), n_nodes, n_enr_kept, n_quad. */
-efe_status efe_dims(const efe_ctx *ctx, int64_t dims[4]);
+/* n_rows (= n_nodes + n_enr_kept), n_nodes, n_enr_kept, n_quad, n_union_rows (the FE
+ * rows of the enrichment coupling H^ce: the nodes of the cells where an enrichment
+ * function is nonzero, Sec. 2.2). */
+efe_status efe_dims(const efe_ctx *ctx, int64_t dims[5]);
 /* Changes stream / Krylov settings of a live context (kmax only downwards). */
 efe_status efe_set_options(efe_ctx *ctx, const efe_options *opt);
 

@@ -1503,12 +1503,13 @@ efe_status efe_free(efe_ctx *ctx) {
   return EFE_OK;
 }
 
-efe_status efe_dims(const efe_ctx *ctx, int64_t dims[4]) {
+efe_status efe_dims(const efe_ctx *ctx, int64_t dims[5]) {
   if (!ctx || !dims) return EFE_ERR_ARG;
   dims[0] = ctx->n_rows;
   dims[1] = ctx->plan.n_nodes;
   dims[2] = ctx->plan.nk;
   dims[3] = ctx->plan.n_quad;
+  dims[4] = ctx->d.nr;
   return EFE_OK;
 }
 

@@ -312,9 +312,9 @@ class Context:
             _free(self._c)
             self._c = None
             raise EfeError(st, msg)
-        d = (C.c_int64 * 4)()
+        d = (C.c_int64 * 5)()
         _dims(self._c, d)
-        self.n_rows, self.n_nodes, self.n_kept, self.n_quad = [int(x) for x in d]
+        self.n_rows, self.n_nodes, self.n_kept, self.n_quad, self.n_union_rows = [int(x) for x in d]
         self.norb = spec.norb
         self.kmax = o.kmax
 

@@ -40,10 +40,12 @@ def _dev(X):
 
 
 def test_dims(env):
+    from paper_2210_14421_amd.efe import Plan
     spec, model, X0, ctx = env
     assert ctx.n_rows == model.n_rows
     assert ctx.n_nodes == model.mesh.n_nodes
     assert ctx.n_quad == model.mesh.n_quad
+    assert ctx.n_union_rows == Plan(spec).n_union_rows > 0
 
 
 def test_density_parity(env):

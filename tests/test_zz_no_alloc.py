@@ -2,7 +2,8 @@
 
 Two calls in a row on each system, the second with fewer columns than the
 first (the workspace keeps the first call's partial sums: the second must not
-see them); each output must equal efe_apply_H's on the same input.  Systems:
+see them); each output must equal efe_apply_H's on the same input (with FP32 and
+BF16 blocks: to the FP32 accumulation of the products).  Systems:
 tiny (5 enrichment directions, 2 orbitals), lattice13 (52 directions: the
 general coupling path), Na2 (12 directions, 11 orbitals); then the error paths
 (no Hamiltonian, more columns than orbitals, a workspace beyond the limit).
@@ -33,10 +34,10 @@ def _block(ctx, spec, ncol, seed):
     return torch.from_numpy(X).to("cuda")
 
 
-def _check(spec, name, ncols):
+def _check(spec, name, ncols, dtype="f64", tol=1e-14):
     from paper_2210_14421_amd.efe import Context
-    print(f"no-alloc apply: {name}, columns per call {ncols}", flush=True)
-    ctx = Context(spec, kmax=8)
+    print(f"no-alloc apply: {name} ({dtype} blocks), columns per call {ncols}", flush=True)
+    ctx = Context(spec, dtype=dtype, kmax=8)
     try:
         ctx.set_hamiltonian(_block(ctx, spec, spec.norb, 1), 0.0)
         for call, ncol in enumerate(ncols):
@@ -48,7 +49,7 @@ def _check(spec, name, ncols):
             err = float((Y - Yref).abs().max() / Yref.abs().max())
             print(f"  call {call}: {ncol} columns, max |Y - Y_ref| / max |Y_ref| = {err:.2e}", flush=True)
             assert bool(torch.isfinite(Y).all())
-            assert err <= 1e-14
+            assert err <= tol
     finally:
         ctx.close()
 
@@ -67,6 +68,16 @@ def test_noalloc_many_enrichment():
 def test_noalloc_na2():
     from workloads import na_cluster
     _check(na_cluster(2, seed=2), "Na2", [11, 4])
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_noalloc_reduced_precision(dtype):
+    """FP32 / BF16 blocks: the entry point keeps the rows in FP64 between the colour
+    passes where efe_apply_H accumulates FP32 rows (both round X to the blocks' type the
+    same way), so the two agree to the FP32 accumulation, not bit for bit."""
+    from workloads import tiny, na_cluster
+    _check(tiny(), "tiny", [2, 1], dtype, 1e-6)
+    _check(na_cluster(2, seed=2), "Na2", [11, 4], dtype, 1e-6)
 
 
 def test_noalloc_error_paths():
