@@ -22,7 +22,6 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 // register r of a lane in row group kr = lane / 16 (the column is lane % 16).
 __device__ __forceinline__ double to_wide(double v) { return v; }
 __device__ __forceinline__ float to_wide(float v) { return v; }
-__device__ __forceinline__ float to_wide(Bf16 v) { return to_float(v); }
 
 template <typename T> struct CMfma;
 template <> struct CMfma<double> {
