@@ -2020,9 +2020,15 @@ efe_status efe_autotune(efe_ctx *ctx, const char *cache_path, int32_t flags, cha
       cand.push_back(v);
       names.push_back(nm);
     }
-    int nv2[2];
+    int nv2[3];
     const int nn = efe::k::cell_narrow_variants(d.g.nloc, ctx->ncolr, nv2);
     for (int i = 0; i < nn; ++i) {
+      efe::k::cell_variant_name(nv2[i], nm, sizeof(nm));
+      cand.push_back(nv2[i]);
+      names.push_back(nm);
+    }
+    const int nw = efe::k::cell_wide_variants(d.g.nloc, esz, nv2);
+    for (int i = 0; i < nw; ++i) {
       efe::k::cell_variant_name(nv2[i], nm, sizeof(nm));
       cand.push_back(nv2[i]);
       names.push_back(nm);

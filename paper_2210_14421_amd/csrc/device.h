@@ -128,6 +128,9 @@ int cell_bf16_variant_count(int nloc);
 // pipeline variants of the cell products that fit the LDS for cells of nloc nodes and
 // blocks of esz bytes (all give the same bits; variant 0 is the default), and their names
 int cell_variant_count(int nloc, size_t esz);
+// sixteen-wave variants of the FP32 block products (ids written to out[<= 3]; none for
+// FP64 blocks or cells of more than 256 nodes)
+int cell_wide_variants(int nloc, size_t esz, int *out);
 void cell_variant_name(int v, char *out, int len);
 // narrow-tile variants (64 or 32 columns per workgroup) worth trying for ncolr real columns
 // (FP64 and FP32 blocks, degree <= 5): their ids in out[], their number returned

@@ -78,12 +78,12 @@ __device__ __forceinline__ void copy16_to_lds(const void *src, void *lds_base) {
   __builtin_amdgcn_global_load_lds((gptr_t)src, (lptr_t)lds_base, 16, 0, 0);
 }
 
-template <typename T, int KC>
+template <typename T, int KC, int NW>
 struct CellChunk {
   // A-chunk copies per wave per chunk, sized for the largest cell (nloc <= 384)
-  static constexpr int kAIns = (KC * kApplyMaxLoc * (int)sizeof(T) + 1024 * kCellWaves - 1) / (1024 * kCellWaves);
-  static constexpr int kXIns = (KC + kCellWaves - 1) / kCellWaves;   // X-row copies per wave per chunk
-  static constexpr int kPer = kAIns + kXIns;                         // copies per wave per chunk
+  static constexpr int kAIns = (KC * kApplyMaxLoc * (int)sizeof(T) + 1024 * NW - 1) / (1024 * NW);
+  static constexpr int kXIns = (KC + NW - 1) / NW;   // X-row copies per wave per chunk
+  static constexpr int kPer = kAIns + kXIns;         // copies per wave per chunk
 };
 
 inline size_t cell_lds_bytes(int nloc, size_t esz, int ns, int kc, size_t xsz = 8) {
@@ -95,8 +95,8 @@ inline size_t cell_lds_bytes(int nloc, size_t esz, int ns, int kc, size_t xsz = 
 // IO: element type of X and Y (double, or float for FP32 blocks); ldr counts IO elements.
 // NT: 16-column N tiles per wave, 32 NT columns per workgroup (narrow tiles for blocks of
 // few orbitals, whose columns would otherwise be mostly padding).
-template <typename T, typename IO, int CMT, int NS, int KC, int WPE, int NT = kCellNT>
-__global__ void __launch_bounds__(kCellWaves * 64) __attribute__((amdgpu_waves_per_eu(WPE)))
+template <typename T, typename IO, int CMT, int NS, int KC, int WPE, int NT = kCellNT, int NW = kCellWaves>
+__global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, const T *__restrict__ cells,
              const IO *__restrict__ X, IO *__restrict__ Y, int ncolr, int64_t ldr, const int *__restrict__ any) {
   static_assert(KC % 4 == 0 && NS >= 2, "chunks of whole k-steps, at least one in flight");
@@ -104,7 +104,9 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
   if (any && *any == 0) return;
   typedef typename Mfma<T>::C C;
   typedef typename Mfma<T>::Acc Acc;
-  constexpr int kAIns = CellChunk<T, KC>::kAIns, kXIns = CellChunk<T, KC>::kXIns, kPer = CellChunk<T, KC>::kPer;
+  constexpr int kAIns = CellChunk<T, KC, NW>::kAIns, kXIns = CellChunk<T, KC, NW>::kXIns;
+  constexpr int kPer = CellChunk<T, KC, NW>::kPer;
+  constexpr int kMG = NW / 2;   // M-tile groups: wave w takes the tiles w / 2 + kMG i
   constexpr int kXStage = x_stage<KC, IO>();
   constexpr int kLDX = x_ldx<IO>();
   constexpr int kEPL = 16 / (int)sizeof(IO);   // elements of an X row per 16-byte copy
@@ -129,7 +131,7 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
   const int mg = wave >> 1, nh = wave & 1;
   int e[3];
   cell_ijk(g, cell, e);
-  for (int l = tid; l < nloc; l += kCellWaves * 64) {
+  for (int l = tid; l < nloc; l += NW * 64) {
     rowoff[l] = local_node(g, e, l) * ldr;
     // colours run in the order (e_x & 1) + 2 (e_y & 1) + 4 (e_z & 1); a node on a
     // face shared along some axis is reached first by the even cell of that axis
@@ -143,7 +145,7 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
     first[l] = later ? 0 : 1;
   }
   // X stages start zeroed: pad columns are never copied into
-  for (int i = tid; i < NS * kXStage / 8; i += kCellWaves * 64) ((double *)Xs)[i] = 0.0;
+  for (int i = tid; i < NS * kXStage / 8; i += NW * 64) ((double *)Xs)[i] = 0.0;
   __syncthreads();
   const unsigned char *Ag = (const unsigned char *)(cells + (int64_t)(slot0 + ci) * g.cstride);   // 16-byte aligned
   const int64_t ablock = g.cstride * (int64_t)sizeof(T);   // padded block: copies never cross into the next one
@@ -153,14 +155,14 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
     const int64_t abase = (int64_t)kc * abytes;
 #pragma unroll
     for (int i = 0; i < kAIns; ++i) {
-      const int seg = wave + kCellWaves * i;
+      const int seg = wave + NW * i;
       const int64_t off = abase + (int64_t)seg * 1024 + lane * 16;
       const bool ok = seg < aseg && off + 16 <= ablock;
       copy16_to_lds(Ag + (ok ? off : 0), seg < aseg ? As + (st * aseg + seg) * 1024 : junk);
     }
 #pragma unroll
     for (int i = 0; i < kXIns; ++i) {
-      const int r = wave + kCellWaves * i;
+      const int r = wave + NW * i;
       const int k = kc * KC + r;
       if (r < KC && k < nloc) {
         if (kEPL * lane < wcol)
@@ -200,13 +202,13 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
       for (int j = 0; j < NT; ++j) b[j] = (C)Xl[kl * kLDX + (nh * NT + j) * 16 + cl];
 #pragma unroll
       for (int i = 0; i < CMT; ++i) {
-        const int t = min(mg + 4 * i, nmt - 1);
+        const int t = min(mg + kMG * i, nmt - 1);
         const C v = widen<T, C>(Al[kl * nloc + t * 16 + cl]);
         a[i] = kok ? v : (C)0;
       }
 #pragma unroll
       for (int i = 0; i < CMT; ++i)
-        if (mg + 4 * i < nmt) {
+        if (mg + kMG * i < nmt) {
 #pragma unroll
           for (int j = 0; j < NT; ++j) acc[i][j] = Mfma<T>::mma(a[i], b[j], acc[i][j]);
         }
@@ -219,13 +221,13 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
   constexpr int kRB = sizeof(C) == 8 ? 2 : 4;
 #pragma unroll
   for (int i = 0; i < CMT; ++i) {
-    if (mg + 4 * i >= nmt) continue;
+    if (mg + kMG * i >= nmt) continue;
 #pragma unroll
     for (int r0 = 0; r0 < 4; r0 += kRB) {
       IO old[kRB][NT];
 #pragma unroll
       for (int r = 0; r < kRB; ++r) {
-        const int row = (mg + 4 * i) * 16 + Mfma<T>::row(kr, r0 + r);
+        const int row = (mg + kMG * i) * 16 + Mfma<T>::row(kr, r0 + r);
         const bool add = row < nloc && !first[row];
         const IO *yr = Y + (row < nloc ? rowoff[row] : 0);
 #pragma unroll
@@ -236,7 +238,7 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
       }
 #pragma unroll
       for (int r = 0; r < kRB; ++r) {
-        const int row = (mg + 4 * i) * 16 + Mfma<T>::row(kr, r0 + r);
+        const int row = (mg + kMG * i) * 16 + Mfma<T>::row(kr, r0 + r);
         if (row >= nloc) continue;
         IO *yr = Y + rowoff[row];
 #pragma unroll
@@ -249,7 +251,8 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
   }
 }
 
-template <typename T, int CMT, int NS, int KC, int WPE = (CMT <= 4 ? 4 : 2), int NT = kCellNT, typename IO>
+template <typename T, int CMT, int NS, int KC, int WPE = (CMT <= 4 ? 4 : 2), int NT = kCellNT, int NW = kCellWaves,
+          typename IO>
 void launch_apply_m(const DevData &d, const T *cells, const IO *X, IO *Y, int ncolr, int64_t ldr,
                     hipStream_t s, const int *any) {
   const unsigned ny = (unsigned)((ncolr + 32 * NT - 1) / (32 * NT));
@@ -258,7 +261,7 @@ void launch_apply_m(const DevData &d, const T *cells, const IO *X, IO *Y, int nc
     const int cnt = d.colour_off[c + 1] - d.colour_off[c];
     if (cnt == 0) continue;
     const int *list = d.colour_cells + d.colour_off[c];
-    hipLaunchKernelGGL((k_cell_apply<T, IO, CMT, NS, KC, WPE, NT>), dim3((unsigned)cnt, ny), dim3(kCellWaves * 64), lds,
+    hipLaunchKernelGGL((k_cell_apply<T, IO, CMT, NS, KC, WPE, NT, NW>), dim3((unsigned)cnt, ny), dim3(NW * 64), lds,
                        s, d,
                        list, d.colour_off[c], cells, X, Y, ncolr, ldr, any);
   }
@@ -276,11 +279,22 @@ constexpr int kVarWPE[kCellVariants] = {4, 4, 4, 4, 4, 4, 6, 6, 6};
 // narrow-tile variants (the default pipeline with 64 or 32 columns per workgroup), for
 // blocks of at most that many real columns
 constexpr int kNarrow64 = 9, kNarrow32 = 10;
+// sixteen-wave variants (FP32 blocks): half the M tiles per wave, registers budgeted for
+// eight waves per SIMD (two workgroups per CU)
+constexpr int kWide0 = 11, kWideN = 3;
+constexpr int kWideNS[kWideN] = {3, 4, 2};
+constexpr int kWideKC[kWideN] = {8, 8, 16};
 
 template <typename T, int CMT, int V, typename IO>
 void launch_v(const DevData &d, const T *cells, const IO *X, IO *Y, int ncolr, int64_t ldr, hipStream_t s,
               const int *any) {
   launch_apply_m<T, CMT, kVarNS[V], kVarKC[V], (CMT <= 4 ? kVarWPE[V] : 2)>(d, cells, X, Y, ncolr, ldr, s, any);
+}
+
+template <typename T, int CMT, int W, typename IO>
+void launch_w(const DevData &d, const T *cells, const IO *X, IO *Y, int ncolr, int64_t ldr, hipStream_t s,
+              const int *any) {
+  launch_apply_m<T, (CMT + 1) / 2, kWideNS[W], kWideKC[W], 8, kCellNT, 16>(d, cells, X, Y, ncolr, ldr, s, any);
 }
 
 template <typename T, int CMT, typename IO>
@@ -297,6 +311,12 @@ void launch_variant(int v, const DevData &d, const T *cells, const IO *X, IO *Y,
     case 6: if (sizeof(T) == 4) { launch_v<T, CMT, 6>(d, cells, X, Y, ncolr, ldr, s, any); break; } [[fallthrough]];
     case 7: if (sizeof(T) == 4) { launch_v<T, CMT, 7>(d, cells, X, Y, ncolr, ldr, s, any); break; } [[fallthrough]];
     case 8: if (sizeof(T) == 4) { launch_v<T, CMT, 8>(d, cells, X, Y, ncolr, ldr, s, any); break; } [[fallthrough]];
+    case kWide0:
+      if (sizeof(T) == 4) { launch_w<T, CMT, 0>(d, cells, X, Y, ncolr, ldr, s, any); break; } [[fallthrough]];
+    case kWide0 + 1:
+      if (sizeof(T) == 4) { launch_w<T, CMT, 1>(d, cells, X, Y, ncolr, ldr, s, any); break; } [[fallthrough]];
+    case kWide0 + 2:
+      if (sizeof(T) == 4) { launch_w<T, CMT, 2>(d, cells, X, Y, ncolr, ldr, s, any); break; } [[fallthrough]];
     default: launch_v<T, CMT, 0>(d, cells, X, Y, ncolr, ldr, s, any); break;
   }
 }
@@ -324,13 +344,21 @@ int set_lds_nt(size_t esz, int nloc) {
                                   (int)cell_lds_bytes(nloc, esz, kVarNS[0], kVarKC[0], sizeof(IO)));
 }
 
+template <typename T, typename IO, int CMT, int W>
+int set_lds_w(size_t esz, int nloc) {
+  return (int)hipFuncSetAttribute(
+      (const void *)k_cell_apply<T, IO, (CMT + 1) / 2, kWideNS[W], kWideKC[W], 8, kCellNT, 16>,
+      hipFuncAttributeMaxDynamicSharedMemorySize, (int)cell_lds_bytes(nloc, esz, kWideNS[W], kWideKC[W], sizeof(IO)));
+}
+
 template <typename T, typename IO, int CMT>
 int set_lds_io(int nloc) {
   const size_t e = sizeof(T);
   int st = set_lds_v<T, IO, CMT, 0>(e, nloc) | set_lds_v<T, IO, CMT, 1>(e, nloc) | set_lds_v<T, IO, CMT, 2>(e, nloc) |
            set_lds_v<T, IO, CMT, 3>(e, nloc) | set_lds_v<T, IO, CMT, 4>(e, nloc) | set_lds_v<T, IO, CMT, 5>(e, nloc);
-  if (sizeof(T) == 4)
-    st |= set_lds_v<T, IO, CMT, 6>(e, nloc) | set_lds_v<T, IO, CMT, 7>(e, nloc) | set_lds_v<T, IO, CMT, 8>(e, nloc);
+  if constexpr (sizeof(T) == 4)
+    st |= set_lds_v<T, IO, CMT, 6>(e, nloc) | set_lds_v<T, IO, CMT, 7>(e, nloc) | set_lds_v<T, IO, CMT, 8>(e, nloc) |
+          set_lds_w<T, IO, CMT, 0>(e, nloc) | set_lds_w<T, IO, CMT, 1>(e, nloc) | set_lds_w<T, IO, CMT, 2>(e, nloc);
   return st | set_lds_nt<T, IO, CMT, 2>(e, nloc) | set_lds_nt<T, IO, CMT, 1>(e, nloc);
 }
 
@@ -360,7 +388,19 @@ int cell_narrow_variants(int nloc, int ncolr, int *out) {
   return n;
 }
 
+int cell_wide_variants(int nloc, size_t esz, int *out) {
+  if (esz != 4 || (nloc + 15) / 16 > 16) return 0;
+  int n = 0;
+  for (int w = 0; w < kWideN; ++w)
+    if (cell_lds_bytes(nloc, esz, kWideNS[w], kWideKC[w]) <= 156 * 1024) out[n++] = kWide0 + w;
+  return n;
+}
+
 void cell_variant_name(int v, char *out, int len) {
+  if (v >= kWide0 && v < kWide0 + kWideN) {
+    snprintf(out, len, "dense_ns%d_kc%d_16w", kWideNS[v - kWide0], kWideKC[v - kWide0]);
+    return;
+  }
   if (v == kNarrow64 || v == kNarrow32) {
     snprintf(out, len, "dense_ns%d_kc%d_cols%d", kVarNS[0], kVarKC[0], v == kNarrow64 ? 64 : 32);
     return;
