@@ -219,33 +219,43 @@ k_cell_bf16(const DevData d, const int *__restrict__ cell_list, int slot0, const
     __syncthreads();
   }
   // output register r of a lane holds row 4 (lane / 16) + r, column lane % 16 of its tile.
-  // Per tile, every earlier value of Y is loaded before any store, so that the loads of
-  // the rows a previous colour reached are in flight together.
+  // Every earlier value of Y the wave adds to (the rows a previous colour reached) is
+  // loaded before any store: with FP32 rows all tiles at once (one memory round trip for
+  // the read-modify-write), with FP64 rows tile by tile (the registers of all tiles'
+  // values would spill).
+  constexpr int TB = sizeof(IO) == 4 ? CMT : 1;   // tiles whose loads are issued together
 #pragma unroll
-  for (int i = 0; i < CMT; ++i) {
-    const int t = mg + 4 * i;
-    if (t >= nmt) continue;
-    IO old[4][NPW];
+  for (int i0 = 0; i0 < CMT; i0 += TB) {
+    IO old[TB][4][NPW];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = 16 * t + 4 * kg + r;
-      const bool add = row < nloc && !first[row];
-      const IO *yr = Y + (row < nloc ? rowoff[row] : 0);
+    for (int i = 0; i < TB; ++i) {
+      const int t = mg + 4 * (i0 + i);
 #pragma unroll
-      for (int j = 0; j < NPW; ++j) {
-        const int col = col0 + 16 * (NPW * ng + j) + cl;
-        old[r][j] = (add && col < ncolr) ? yr[col] : (IO)0;
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * t + 4 * kg + r;
+        const bool add = t < nmt && row < nloc && !first[row];
+        const IO *yr = Y + (add ? rowoff[row] : 0);
+#pragma unroll
+        for (int j = 0; j < NPW; ++j) {
+          const int col = col0 + 16 * (NPW * ng + j) + cl;
+          old[i][r][j] = (add && col < ncolr) ? yr[col] : (IO)0;
+        }
       }
     }
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = 16 * t + 4 * kg + r;
-      if (row >= nloc) continue;
-      IO *yr = Y + rowoff[row];
+    for (int i = 0; i < TB; ++i) {
+      const int t = mg + 4 * (i0 + i);
+      if (t >= nmt) continue;
 #pragma unroll
-      for (int j = 0; j < NPW; ++j) {
-        const int col = col0 + 16 * (NPW * ng + j) + cl;
-        if (col < ncolr) yr[col] = old[r][j] + (IO)acc[i][j][r];
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * t + 4 * kg + r;
+        if (row >= nloc) continue;
+        IO *yr = Y + rowoff[row];
+#pragma unroll
+        for (int j = 0; j < NPW; ++j) {
+          const int col = col0 + 16 * (NPW * ng + j) + cl;
+          if (col < ncolr) yr[col] = old[i][r][j] + (IO)acc[i0 + i][j][r];
+        }
       }
     }
   }
