@@ -2007,10 +2007,11 @@ efe_status efe_autotune(efe_ctx *ctx, const char *cache_path, int32_t flags, cha
     cand.push_back(0);
     names.push_back("sum_factorised");
   } else if (ctx->dtype == 2 || ctx->dtype == 4) {
-    const int nv = efe::k::cell_bf16_variant_count(d.g.nloc);
+    const int nv = efe::k::cell_bf16_variant_count(d.g.nloc, ctx->dtype == 4 ? 2 : 1);
     for (int v = 0; v < nv; ++v) {
       cand.push_back(v);
-      names.push_back(std::string(ctx->dtype == 2 ? "bf16_mfma" : "bf16x3_mfma") + (v ? "_w6" : ""));
+      names.push_back(std::string(ctx->dtype == 2 ? "bf16_mfma" : "bf16x3_mfma") + ((v & 1) ? "_w6" : "") +
+                      (v >= 2 ? "_a3" : ""));
     }
   } else {
     const size_t esz = ctx->dtype == 0 ? 8 : 4;

@@ -123,8 +123,9 @@ void cell_apply_bf16(const DevData &d, const uint16_t *cells, int planes, const 
                      int64_t ldr, hipStream_t s, const int *any = nullptr, int variant = 0);
 void cell_apply_bf16_f(const DevData &d, const uint16_t *cells, int planes, const void *X, int x_bf16, float *Y,
                        int ncolr, int64_t ldf, hipStream_t s, const int *any = nullptr, int variant = 0);
-// register-budget variants of the BF16 products (0: two workgroups per CU, 1: three)
-int cell_bf16_variant_count(int nloc);
+// variants of the BF16 products: 0 eight waves, 1 twelve waves per workgroup; 2 and 3 the
+// same with three stages of the block rows in LDS (one BF16 plane only)
+int cell_bf16_variant_count(int nloc, int planes);
 // pipeline variants of the cell products that fit the LDS for cells of nloc nodes and
 // blocks of esz bytes (all give the same bits; variant 0 is the default), and their names
 int cell_variant_count(int nloc, size_t esz);

@@ -53,18 +53,20 @@ __device__ __forceinline__ void copy16(const void *src, void *lds_base) {
   __builtin_amdgcn_global_load_lds((gptr_t)src, (lptr_t)lds_base, 16, 0, 0);
 }
 
-inline size_t bf16_lds_bytes(int mmax, int planes) {
-  return (size_t)2 * planes * ((size_t)mmax * kBRow + kBXPlane) + 1024;
+inline size_t bf16_lds_bytes(int mmax, int planes, int astages = 2) {
+  return (size_t)planes * ((size_t)astages * mmax * kBRow + 2 * kBXPlane) + 1024;
 }
 
 // One workgroup per (cell, 96 columns) of 4 * 6 / NPW waves; wave w takes the M tiles
 // w / G + 4 i (G = 6 / NPW) and the NPW N tiles NPW (w % G) .. + NPW - 1.  K advances in
-// steps of 32 k-rows, two stages in LDS: the A operand rows [m][32 k] (copied global ->
-// LDS directly, one 16-byte chunk per lane) and the B operand [n][32 k] (X rows loaded
-// into registers, rounded to BF16, written transposed).  MMAX: rows of A staged (nloc
-// rounded up to whole M tiles); PL: 1 (BF16) or 2 (split); NPW 3 (8 waves) or 2 (12
-// waves, fewer registers per wave: three waves per SIMD for each of two workgroups).
-template <int MMAX, int CMT, int PL, int NPW, int WPE, typename XT, typename IO>
+// steps of 32 k-rows through LDS: the A operand rows [m][32 k] (copied global -> LDS
+// directly, one 16-byte chunk per lane; AS stages, so that with three the copies of step
+// s + 2 are in flight during step s) and the B operand [n][32 k] (X rows loaded into
+// registers one step ahead, rounded to BF16, written transposed; two stages).  MMAX: rows
+// of A staged (nloc rounded up to whole M tiles); PL: 1 (BF16) or 2 (split); NPW 3 (8
+// waves) or 2 (12 waves, fewer registers per wave: three waves per SIMD for each of two
+// workgroups).
+template <int MMAX, int CMT, int PL, int NPW, int WPE, typename XT, typename IO, int AS = 2>
 __global__ void __launch_bounds__(4 * (6 / NPW) * 64) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_cell_bf16(const DevData d, const int *__restrict__ cell_list, int slot0, const uint16_t *__restrict__ cells,
             const XT *__restrict__ X, IO *__restrict__ Y, int ncolr, int64_t ldr, const int *__restrict__ any) {
@@ -78,11 +80,13 @@ k_cell_bf16(const DevData d, const int *__restrict__ cell_list, int slot0, const
   if (any && *any == 0) return;
   constexpr int kAIns = (MMAX / 16 + W - 1) / W;   // A copies per wave per plane and step
   constexpr int kAPlane = MMAX * kBRow;
-  constexpr int kStage = PL * (kAPlane + kBXPlane);
+  constexpr int kAStage = PL * kAPlane, kBStage = PL * kBXPlane;
+  static_assert(AS == 2 || AS == 3, "A stages");
   __shared__ int64_t rowoff[MMAX];
   __shared__ unsigned char first[MMAX];
   extern __shared__ __attribute__((aligned(16))) unsigned char bsm[];
-  unsigned char *junk = bsm + 2 * kStage;
+  unsigned char *const bsmB = bsm + AS * kAStage;   // B stages after the A stages
+  unsigned char *junk = bsmB + 2 * kBStage;
   const Geom &g = d.g;
   const int nloc = g.nloc;
   const int lda = (nloc + 7) & ~7;
@@ -129,7 +133,7 @@ k_cell_bf16(const DevData d, const int *__restrict__ cell_list, int slot0, const
           const int k0 = 32 * s + 8 * q;
           const bool ok = r < nloc && k0 < nloc;
           copy16(Ag + pl * plane + (ok ? (int64_t)r * lda + k0 : 0),
-                 bsm + st * kStage + pl * kAPlane + ins * 1024);
+                 bsm + st * kAStage + pl * kAPlane + ins * 1024);
         } else {
           copy16(Ag, junk);
         }
@@ -161,7 +165,7 @@ k_cell_bf16(const DevData d, const int *__restrict__ cell_list, int slot0, const
         lo[j] = (uint32_t)l0 | ((uint32_t)l1 << 16);
       }
     }
-    unsigned char *xb = bsm + st * kStage + PL * kAPlane + xn * kBRow + slot_of(xn, xq) * 16 + xp * 2 * XV;
+    unsigned char *xb = bsmB + st * kBStage + xn * kBRow + slot_of(xn, xq) * 16 + xp * 2 * XV;
     if (XV == 8) {
       *(u32x4 *)xb = u32x4{hi[0], hi[1], hi[2], hi[3]};
       if (PL == 2) *(u32x4 *)(xb + kBXPlane) = u32x4{lo[0], lo[1], lo[2], lo[3]};
@@ -177,18 +181,26 @@ k_cell_bf16(const DevData d, const int *__restrict__ cell_list, int slot0, const
     for (int j = 0; j < NPW; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
   const int cl = lane & 15, kg = lane >> 4;
   issueA(0, 0);
+  if (AS == 3 && nks > 1) issueA(1, 1);
   loadX(0);
   writeX(0);
   wait_vm<0>();
   __syncthreads();
   for (int s = 0; s < nks; ++s) {
-    const int st = s & 1;
-    if (s + 1 < nks) {
-      issueA(s + 1, st ^ 1);
-      loadX(s + 1);
+    const int st = s & 1, sa = AS == 2 ? st : s % 3;
+    if constexpr (AS == 2) {
+      if (s + 1 < nks) {
+        issueA(s + 1, st ^ 1);
+        loadX(s + 1);
+      }
+    } else {
+      // the X loads first: the wait the compiler puts before writeX then leaves the A
+      // copies of step s + 2, issued after them, in flight
+      if (s + 1 < nks) loadX(s + 1);
+      if (s + 2 < nks) issueA(s + 2, (s + 2) % 3);
     }
-    const unsigned char *Ast = bsm + st * kStage;
-    const unsigned char *Bst = Ast + PL * kAPlane;
+    const unsigned char *Ast = bsm + sa * kAStage;
+    const unsigned char *Bst = bsmB + st * kBStage;
     bf16x8 b[NPW], bl[NPW];
 #pragma unroll
     for (int j = 0; j < NPW; ++j) {
@@ -215,7 +227,10 @@ k_cell_bf16(const DevData d, const int *__restrict__ cell_list, int slot0, const
       }
     }
     if (s + 1 < nks) writeX(st ^ 1);
-    wait_vm<0>();
+    // this wave's copies of step s + 1 have landed once at most the copies of step s + 2
+    // (the last ones issued, PL * kAIns per wave, padding copies included) remain
+    if (AS == 3 && s + 2 < nks) wait_vm<PL * kAIns>();
+    else wait_vm<0>();
     __syncthreads();
   }
   // output register r of a lane holds row 4 (lane / 16) + r, column lane % 16 of its tile.
@@ -261,46 +276,49 @@ k_cell_bf16(const DevData d, const int *__restrict__ cell_list, int slot0, const
   }
 }
 
-template <int MMAX, int CMT, int PL, int NPW, int WPE, typename XT, typename IO>
+template <int MMAX, int CMT, int PL, int NPW, int WPE, typename XT, typename IO, int AS = 2>
 void launch_bf16(const DevData &d, const uint16_t *cells, const XT *X, IO *Y, int ncolr, int64_t ldr,
                  hipStream_t s, const int *any) {
   const unsigned ny = (unsigned)((ncolr + kBCols - 1) / kBCols);
-  const size_t lds = bf16_lds_bytes(MMAX, PL);
+  const size_t lds = bf16_lds_bytes(MMAX, PL, AS);
   for (int c = 0; c < 8; ++c) {
     const int cnt = d.colour_off[c + 1] - d.colour_off[c];
     if (cnt == 0) continue;
     const int *list = d.colour_cells + d.colour_off[c];
-    hipLaunchKernelGGL((k_cell_bf16<MMAX, CMT, PL, NPW, WPE, XT, IO>), dim3((unsigned)cnt, ny), dim3(4 * (6 / NPW) * 64),
-                       lds,
-                       s, d, list,
-                       d.colour_off[c], cells, X, Y, ncolr, ldr, any);
+    hipLaunchKernelGGL((k_cell_bf16<MMAX, CMT, PL, NPW, WPE, XT, IO, AS>), dim3((unsigned)cnt, ny),
+                       dim3(4 * (6 / NPW) * 64), lds, s, d, list, d.colour_off[c], cells, X, Y, ncolr, ldr, any);
   }
 }
 
-template <int MMAX, int CMT, int PL, int NPW, int WPE>
+template <int MMAX, int CMT, int PL, int NPW, int WPE, int AS = 2>
 int set_lds_bf16() {
-  const int lds = (int)bf16_lds_bytes(MMAX, PL);
-  return (int)hipFuncSetAttribute((const void *)k_cell_bf16<MMAX, CMT, PL, NPW, WPE, double, double>,
+  const int lds = (int)bf16_lds_bytes(MMAX, PL, AS);
+  return (int)hipFuncSetAttribute((const void *)k_cell_bf16<MMAX, CMT, PL, NPW, WPE, double, double, AS>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds) |
-         (int)hipFuncSetAttribute((const void *)k_cell_bf16<MMAX, CMT, PL, NPW, WPE, float, float>,
+         (int)hipFuncSetAttribute((const void *)k_cell_bf16<MMAX, CMT, PL, NPW, WPE, float, float, AS>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds) |
-         (int)hipFuncSetAttribute((const void *)k_cell_bf16<MMAX, CMT, PL, NPW, WPE, Bf16, float>,
+         (int)hipFuncSetAttribute((const void *)k_cell_bf16<MMAX, CMT, PL, NPW, WPE, Bf16, float, AS>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
 // variant 0: eight waves of three N tiles, four waves per SIMD (two workgroups per CU);
-// variant 1: twelve waves of two N tiles, six waves per SIMD
+// variant 1: twelve waves of two N tiles, six waves per SIMD; variants 2 and 3: the same
+// with three A stages (BF16 blocks, one plane; the split form runs 0 or 1 instead)
 template <int MMAX, int CMT, int PL, typename XT, typename IO>
 void launch_bf16_v(int v, const DevData &d, const uint16_t *cells, const XT *X, IO *Y, int ncolr,
                    int64_t ldr, hipStream_t s, const int *any) {
-  if (v == 1) launch_bf16<MMAX, CMT, PL, 2, 6>(d, cells, X, Y, ncolr, ldr, s, any);
+  if constexpr (PL == 1) {
+    if (v == 3) return launch_bf16<MMAX, CMT, PL, 2, 6, XT, IO, 3>(d, cells, X, Y, ncolr, ldr, s, any);
+    if (v == 2) return launch_bf16<MMAX, CMT, PL, 3, 4, XT, IO, 3>(d, cells, X, Y, ncolr, ldr, s, any);
+  }
+  if (v & 1) launch_bf16<MMAX, CMT, PL, 2, 6>(d, cells, X, Y, ncolr, ldr, s, any);
   else launch_bf16<MMAX, CMT, PL, 3, 4>(d, cells, X, Y, ncolr, ldr, s, any);
 }
 
 template <int MMAX, int CMT>
 int set_lds_bf16_all() {
   return set_lds_bf16<MMAX, CMT, 1, 3, 4>() | set_lds_bf16<MMAX, CMT, 2, 3, 4>() | set_lds_bf16<MMAX, CMT, 1, 2, 6>() |
-         set_lds_bf16<MMAX, CMT, 2, 2, 6>();
+         set_lds_bf16<MMAX, CMT, 2, 2, 6>() | set_lds_bf16<MMAX, CMT, 1, 3, 4, 3>() | set_lds_bf16<MMAX, CMT, 1, 2, 6, 3>();
 }
 
 }  // namespace
@@ -311,7 +329,7 @@ int64_t bf16_block_elems(const Geom &g, int planes) {
   return (int64_t)planes * g.nloc * ((g.nloc + 7) & ~7);
 }
 
-int cell_bf16_variant_count(int nloc) { return nloc <= 224 ? 2 : 1; }
+int cell_bf16_variant_count(int nloc, int planes) { return nloc <= 224 ? (planes == 1 ? 4 : 2) : 1; }
 
 int cell_bf16_init(int nloc) {
   if (nloc > 352) return 1;

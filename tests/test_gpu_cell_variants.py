@@ -2,12 +2,13 @@
 
 The autotuner picks one shape per problem; all shapes (chunks in flight, k-rows per
 chunk, register budget, 64- and 32-column workgroups, sixteen-wave workgroups for FP32
-blocks) add the k terms of each output in the same order, so each must reproduce the
-default shape's Hbar X bit for bit.  Each shape is selected through the autotuner's
+blocks; for BF16 blocks eight or twelve waves, two or three stages of block rows) add
+the k terms of each output in the same order, so each must reproduce the default
+shape's Hbar X bit for bit.  Each shape is selected through the autotuner's
 cache (a forced run writes the problem's entry; the test rewrites its choice and a fresh
 context reads it back).  Systems: tiny (125-node cells) with 3 orbitals and Na2 (216-node
-cells) with its 11; FP64 and FP32 blocks (FP32 blocks on the FP32 rows of the
-propagation).
+cells) with its 11; FP64, FP32, BF16 and split BF16 blocks (the reduced-precision ones on
+the FP32 / BF16 rows of the propagation).
 """
 import dataclasses
 import json
@@ -41,7 +42,7 @@ def _systems():
     return [("tiny", dataclasses.replace(tiny(), occ=np.array([2.0, 1.0, 1.0]))), ("Na2", na_cluster(2, seed=2))]
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16", "bf16x3"])
 @pytest.mark.parametrize("which", [0, 1])
 def test_every_dense_shape_same_bits(dtype, which, tmp_path):
     from paper_2210_14421_amd.efe import Context
@@ -57,6 +58,8 @@ def test_every_dense_shape_same_bits(dtype, which, tmp_path):
         print(f"{name} {dtype}: {r['times_us']}", flush=True)
         if dtype == "f32":
             assert any(n.endswith("_16w") for n in shapes)
+        if dtype == "bf16":
+            assert sum(n.endswith("_a3") for n in shapes) == 2
         text = cache.read_text()
         assert len(json.loads(text)) == 1
         for shape in shapes:
