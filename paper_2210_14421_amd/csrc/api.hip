@@ -2011,7 +2011,7 @@ efe_status efe_autotune(efe_ctx *ctx, const char *cache_path, int32_t flags, cha
     for (int v = 0; v < nv; ++v) {
       cand.push_back(v);
       names.push_back(std::string(ctx->dtype == 2 ? "bf16_mfma" : "bf16x3_mfma") + ((v & 1) ? "_w6" : "") +
-                      (v >= 2 ? "_a3" : ""));
+                      (v >= 4 ? "_a3" : v >= 2 ? "_ra" : ""));
     }
   } else {
     const size_t esz = ctx->dtype == 0 ? 8 : 4;

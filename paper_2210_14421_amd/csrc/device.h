@@ -124,7 +124,8 @@ void cell_apply_bf16(const DevData &d, const uint16_t *cells, int planes, const 
 void cell_apply_bf16_f(const DevData &d, const uint16_t *cells, int planes, const void *X, int x_bf16, float *Y,
                        int ncolr, int64_t ldf, hipStream_t s, const int *any = nullptr, int variant = 0);
 // variants of the BF16 products: 0 eight waves, 1 twelve waves per workgroup; 2 and 3 the
-// same with three stages of the block rows in LDS (one BF16 plane only)
+// same with the block rows loaded through registers; 4 and 5 with three stages of the
+// block rows in LDS (2 to 5: one BF16 plane only)
 int cell_bf16_variant_count(int nloc, int planes);
 // pipeline variants of the cell products that fit the LDS for cells of nloc nodes and
 // blocks of esz bytes (all give the same bits; variant 0 is the default), and their names

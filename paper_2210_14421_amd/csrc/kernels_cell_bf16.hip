@@ -66,7 +66,7 @@ inline size_t bf16_lds_bytes(int mmax, int planes, int astages = 2) {
 // of A staged (nloc rounded up to whole M tiles); PL: 1 (BF16) or 2 (split); NPW 3 (8
 // waves) or 2 (12 waves, fewer registers per wave: three waves per SIMD for each of two
 // workgroups).
-template <int MMAX, int CMT, int PL, int NPW, int WPE, typename XT, typename IO, int AS = 2>
+template <int MMAX, int CMT, int PL, int NPW, int WPE, typename XT, typename IO, int AS = 2, bool RA = false>
 __global__ void __launch_bounds__(4 * (6 / NPW) * 64) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_cell_bf16(const DevData d, const int *__restrict__ cell_list, int slot0, const uint16_t *__restrict__ cells,
             const XT *__restrict__ X, IO *__restrict__ Y, int ncolr, int64_t ldr, const int *__restrict__ any) {
@@ -82,6 +82,7 @@ k_cell_bf16(const DevData d, const int *__restrict__ cell_list, int slot0, const
   constexpr int kAPlane = MMAX * kBRow;
   constexpr int kAStage = PL * kAPlane, kBStage = PL * kBXPlane;
   static_assert(AS == 2 || AS == 3, "A stages");
+  static_assert(!RA || AS == 2, "block rows through registers: two stages");
   __shared__ int64_t rowoff[MMAX];
   __shared__ unsigned char first[MMAX];
   extern __shared__ __attribute__((aligned(16))) unsigned char bsm[];
@@ -139,6 +140,33 @@ k_cell_bf16(const DevData d, const int *__restrict__ cell_list, int slot0, const
         }
       }
   };
+  // RA: the same rows through registers (16-byte loads, written to LDS after the step's
+  // MFMAs, beside the B operand) instead of direct copies into LDS
+  u32x4 ra[PL][kAIns];
+  auto loadA = [&](int s) {
+#pragma unroll
+    for (int pl = 0; pl < PL; ++pl)
+#pragma unroll
+      for (int i = 0; i < kAIns; ++i) {
+        const int ins = wave + W * i;
+        if (ins < MMAX / 16) {
+          const int r = 16 * ins + (lane >> 2), sl = lane & 3;
+          const int q = sl ^ ((r >> 1) & 3);
+          const int k0 = 32 * s + 8 * q;
+          const bool ok = r < nloc && k0 < nloc;
+          ra[pl][i] = *(const u32x4 *)(Ag + pl * plane + (ok ? (int64_t)r * lda + k0 : 0));
+        }
+      }
+  };
+  auto storeA = [&](int st) {
+#pragma unroll
+    for (int pl = 0; pl < PL; ++pl)
+#pragma unroll
+      for (int i = 0; i < kAIns; ++i) {
+        const int ins = wave + W * i;
+        if (ins < MMAX / 16) *(u32x4 *)(bsm + st * kAStage + pl * kAPlane + ins * 1024 + lane * 16) = ra[pl][i];
+      }
+  };
   // B operand of k-step s: thread t < 384 H takes column n = t % 96, chunk q = (t / 96) % 4
   // (k = 32 s + 8 q .. + 7) and part t / 384 of it (XV of the 8 k-values), rounded (and
   // split) to BF16
@@ -180,8 +208,13 @@ k_cell_bf16(const DevData d, const int *__restrict__ cell_list, int slot0, const
 #pragma unroll
     for (int j = 0; j < NPW; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
   const int cl = lane & 15, kg = lane >> 4;
-  issueA(0, 0);
-  if (AS == 3 && nks > 1) issueA(1, 1);
+  if constexpr (RA) {
+    loadA(0);
+    storeA(0);
+  } else {
+    issueA(0, 0);
+    if (AS == 3 && nks > 1) issueA(1, 1);
+  }
   loadX(0);
   writeX(0);
   wait_vm<0>();
@@ -190,7 +223,8 @@ k_cell_bf16(const DevData d, const int *__restrict__ cell_list, int slot0, const
     const int st = s & 1, sa = AS == 2 ? st : s % 3;
     if constexpr (AS == 2) {
       if (s + 1 < nks) {
-        issueA(s + 1, st ^ 1);
+        if constexpr (RA) loadA(s + 1);
+        else issueA(s + 1, st ^ 1);
         loadX(s + 1);
       }
     } else {
@@ -226,7 +260,10 @@ k_cell_bf16(const DevData d, const int *__restrict__ cell_list, int slot0, const
         }
       }
     }
-    if (s + 1 < nks) writeX(st ^ 1);
+    if (s + 1 < nks) {
+      if constexpr (RA) storeA(st ^ 1);
+      writeX(st ^ 1);
+    }
     // this wave's copies of step s + 1 have landed once at most the copies of step s + 2
     // (the last ones issued, PL * kAIns per wave, padding copies included) remain
     if (AS == 3 && s + 2 < nks) wait_vm<PL * kAIns>();
@@ -276,7 +313,7 @@ k_cell_bf16(const DevData d, const int *__restrict__ cell_list, int slot0, const
   }
 }
 
-template <int MMAX, int CMT, int PL, int NPW, int WPE, typename XT, typename IO, int AS = 2>
+template <int MMAX, int CMT, int PL, int NPW, int WPE, typename XT, typename IO, int AS = 2, bool RA = false>
 void launch_bf16(const DevData &d, const uint16_t *cells, const XT *X, IO *Y, int ncolr, int64_t ldr,
                  hipStream_t s, const int *any) {
   const unsigned ny = (unsigned)((ncolr + kBCols - 1) / kBCols);
@@ -285,31 +322,34 @@ void launch_bf16(const DevData &d, const uint16_t *cells, const XT *X, IO *Y, in
     const int cnt = d.colour_off[c + 1] - d.colour_off[c];
     if (cnt == 0) continue;
     const int *list = d.colour_cells + d.colour_off[c];
-    hipLaunchKernelGGL((k_cell_bf16<MMAX, CMT, PL, NPW, WPE, XT, IO, AS>), dim3((unsigned)cnt, ny),
+    hipLaunchKernelGGL((k_cell_bf16<MMAX, CMT, PL, NPW, WPE, XT, IO, AS, RA>), dim3((unsigned)cnt, ny),
                        dim3(4 * (6 / NPW) * 64), lds, s, d, list, d.colour_off[c], cells, X, Y, ncolr, ldr, any);
   }
 }
 
-template <int MMAX, int CMT, int PL, int NPW, int WPE, int AS = 2>
+template <int MMAX, int CMT, int PL, int NPW, int WPE, int AS = 2, bool RA = false>
 int set_lds_bf16() {
   const int lds = (int)bf16_lds_bytes(MMAX, PL, AS);
-  return (int)hipFuncSetAttribute((const void *)k_cell_bf16<MMAX, CMT, PL, NPW, WPE, double, double, AS>,
+  return (int)hipFuncSetAttribute((const void *)k_cell_bf16<MMAX, CMT, PL, NPW, WPE, double, double, AS, RA>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds) |
-         (int)hipFuncSetAttribute((const void *)k_cell_bf16<MMAX, CMT, PL, NPW, WPE, float, float, AS>,
+         (int)hipFuncSetAttribute((const void *)k_cell_bf16<MMAX, CMT, PL, NPW, WPE, float, float, AS, RA>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds) |
-         (int)hipFuncSetAttribute((const void *)k_cell_bf16<MMAX, CMT, PL, NPW, WPE, Bf16, float, AS>,
+         (int)hipFuncSetAttribute((const void *)k_cell_bf16<MMAX, CMT, PL, NPW, WPE, Bf16, float, AS, RA>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
 // variant 0: eight waves of three N tiles, four waves per SIMD (two workgroups per CU);
 // variant 1: twelve waves of two N tiles, six waves per SIMD; variants 2 and 3: the same
-// with three A stages (BF16 blocks, one plane; the split form runs 0 or 1 instead)
+// with the block rows through registers; 4 and 5: with three stages of block rows (2 to 5
+// for BF16 blocks, one plane; the split form runs 0 or 1 instead)
 template <int MMAX, int CMT, int PL, typename XT, typename IO>
 void launch_bf16_v(int v, const DevData &d, const uint16_t *cells, const XT *X, IO *Y, int ncolr,
                    int64_t ldr, hipStream_t s, const int *any) {
   if constexpr (PL == 1) {
-    if (v == 3) return launch_bf16<MMAX, CMT, PL, 2, 6, XT, IO, 3>(d, cells, X, Y, ncolr, ldr, s, any);
-    if (v == 2) return launch_bf16<MMAX, CMT, PL, 3, 4, XT, IO, 3>(d, cells, X, Y, ncolr, ldr, s, any);
+    if (v == 5) return launch_bf16<MMAX, CMT, PL, 2, 6, XT, IO, 3>(d, cells, X, Y, ncolr, ldr, s, any);
+    if (v == 4) return launch_bf16<MMAX, CMT, PL, 3, 4, XT, IO, 3>(d, cells, X, Y, ncolr, ldr, s, any);
+    if (v == 3) return launch_bf16<MMAX, CMT, PL, 2, 6, XT, IO, 2, true>(d, cells, X, Y, ncolr, ldr, s, any);
+    if (v == 2) return launch_bf16<MMAX, CMT, PL, 3, 4, XT, IO, 2, true>(d, cells, X, Y, ncolr, ldr, s, any);
   }
   if (v & 1) launch_bf16<MMAX, CMT, PL, 2, 6>(d, cells, X, Y, ncolr, ldr, s, any);
   else launch_bf16<MMAX, CMT, PL, 3, 4>(d, cells, X, Y, ncolr, ldr, s, any);
@@ -318,7 +358,8 @@ void launch_bf16_v(int v, const DevData &d, const uint16_t *cells, const XT *X, 
 template <int MMAX, int CMT>
 int set_lds_bf16_all() {
   return set_lds_bf16<MMAX, CMT, 1, 3, 4>() | set_lds_bf16<MMAX, CMT, 2, 3, 4>() | set_lds_bf16<MMAX, CMT, 1, 2, 6>() |
-         set_lds_bf16<MMAX, CMT, 2, 2, 6>() | set_lds_bf16<MMAX, CMT, 1, 3, 4, 3>() | set_lds_bf16<MMAX, CMT, 1, 2, 6, 3>();
+         set_lds_bf16<MMAX, CMT, 2, 2, 6>() | set_lds_bf16<MMAX, CMT, 1, 3, 4, 3>() | set_lds_bf16<MMAX, CMT, 1, 2, 6, 3>() |
+         set_lds_bf16<MMAX, CMT, 1, 3, 4, 2, true>() | set_lds_bf16<MMAX, CMT, 1, 2, 6, 2, true>();
 }
 
 }  // namespace
@@ -329,7 +370,7 @@ int64_t bf16_block_elems(const Geom &g, int planes) {
   return (int64_t)planes * g.nloc * ((g.nloc + 7) & ~7);
 }
 
-int cell_bf16_variant_count(int nloc, int planes) { return nloc <= 224 ? (planes == 1 ? 4 : 2) : 1; }
+int cell_bf16_variant_count(int nloc, int planes) { return nloc <= 224 ? (planes == 1 ? 6 : 2) : 1; }
 
 int cell_bf16_init(int nloc) {
   if (nloc > 352) return 1;

@@ -2,7 +2,8 @@
 
 The autotuner picks one shape per problem; all shapes (chunks in flight, k-rows per
 chunk, register budget, 64- and 32-column workgroups, sixteen-wave workgroups for FP32
-blocks; for BF16 blocks eight or twelve waves, two or three stages of block rows) add
+blocks; for BF16 blocks eight or twelve waves, two or three stages of block rows, block
+rows through LDS copies or through registers) add
 the k terms of each output in the same order, so each must reproduce the default
 shape's Hbar X bit for bit.  Each shape is selected through the autotuner's
 cache (a forced run writes the problem's entry; the test rewrites its choice and a fresh
@@ -59,7 +60,7 @@ def test_every_dense_shape_same_bits(dtype, which, tmp_path):
         if dtype == "f32":
             assert any(n.endswith("_16w") for n in shapes)
         if dtype == "bf16":
-            assert sum(n.endswith("_a3") for n in shapes) == 2
+            assert sum(n.endswith("_a3") for n in shapes) == 2 and sum(n.endswith("_ra") for n in shapes) == 2
         text = cache.read_text()
         assert len(json.loads(text)) == 1
         for shape in shapes:
