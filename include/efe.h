@@ -62,7 +62,7 @@ enum { EFE_F64 = 0, EFE_F32 = 1, EFE_BF16 = 2, EFE_F64_SF = 3, EFE_BF16X3 = 4 };
 /* adiabatic LDA (Sec. 2.1): none, Slater exchange, Slater + PW92 correlation */
 enum { EFE_XC_NONE = 0, EFE_XC_SLATER = 1, EFE_XC_SLATER_PW92 = 2 };
 /* Lanczos reorthogonalisation (efe_options.reorth) */
-enum { EFE_REORTH_PARTIAL = 0, EFE_REORTH_FULL = 1 };
+enum { EFE_REORTH_PARTIAL = 0, EFE_REORTH_FULL = 1, EFE_REORTH_PARTIAL_DOT = 2 };
 /* operator exponentiated by lanczos_expm: Hbar, or the Loewdin position operator */
 enum { EFE_OP_H = 0, EFE_OP_X = 1, EFE_OP_Y = 2, EFE_OP_Z = 3 };
 
@@ -124,7 +124,13 @@ typedef struct {
                               previous ones when Simon's omega recurrence (1984) estimates
                               a loss above sqrt(eps), for that vector and the next;
                               EFE_REORTH_FULL (1): a pass against all previous vectors at
-                              every step, repeated where it cancelled most of the vector */
+                              every step, repeated where it cancelled most of the vector;
+                              EFE_REORTH_PARTIAL_DOT (2): the partial scheme with alpha_j
+                              always from a dot pass over the new vector.  With EFE_F64
+                              blocks the partial scheme (0) takes alpha_j = q^H Hbar q from
+                              the products instead (each cell's and the coupling's share,
+                              summed in a fixed order), which saves that pass; the two
+                              agree to rounding */
 } efe_options;
 
 /* External field E(t) = dir * sum_k A_k sin(w_k t + phi_k) exp(-(t-t0)^2/s^2),

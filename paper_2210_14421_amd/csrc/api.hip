@@ -84,6 +84,9 @@ struct efe_ctx {
   double *alpha = nullptr, *beta = nullptr, *beta0 = nullptr, *errv = nullptr, *ubuf = nullptr;
   int *active = nullptr, *kused = nullptr, *kforce = nullptr, *need = nullptr, *anyflag = nullptr;
   double *h1 = nullptr, *h2n = nullptr, *nrm1 = nullptr, *nrm2 = nullptr;
+  // FP64 blocks: the products' shares of x^H Hbar x, per column: n_cells cell sums, then nk
+  // enrichment terms (the three-term Lanczos step takes alpha from them, with no dot pass)
+  double *apart = nullptr;
   double *sig = nullptr, *coef = nullptr, *gsc = nullptr, *msc = nullptr;
   efe::ProState pro;            // partial reorthogonalisation state of the Lanczos columns
   // device-driven step (no host round trip; capturable in a hipGraph)
@@ -468,6 +471,7 @@ efe_status build_device(efe_ctx *ctx) {
   EFE_TRY(dalloc(ctx, &ctx->pro.anorm, std::max(1, pl.norb)));
   EFE_TRY(dalloc(ctx, &ctx->pro.force, std::max(1, pl.norb)));
   EFE_TRY(dalloc(ctx, &ctx->h1, (int64_t)(ctx->kmax + 1) * ctx->ncolr));
+  if (ctx->dtype == 0) EFE_TRY(dalloc(ctx, &ctx->apart, ((int64_t)d.colour_off[8] + d.nk) * ctx->ncolr));
   EFE_TRY(dalloc(ctx, &ctx->h2n, (int64_t)(ctx->kmax + 1) * ctx->ncolr));
   EFE_TRY(dalloc(ctx, &ctx->nrm1, ctx->ncolr));
   EFE_TRY(dalloc(ctx, &ctx->nrm2, ctx->ncolr));
@@ -504,12 +508,20 @@ efe_status build_device(efe_ctx *ctx) {
 constexpr int kSFVariant = 100;   // cell_variant of an FP64 context that applies the blocks by sum factorisation
 
 // Cell part of Y = A X with the kernel shape of the context (efe_autotune) or the given variant.
+// apart: see efe::k::cell_apply (FP64 blocks on the dense kernel only).
 void cell_products(efe_ctx *ctx, const double *X, double *Y, int ncolr, int64_t ldr, hipStream_t s, const int *any,
-                   int variant = -1) {
+                   int variant = -1, double *apart = nullptr) {
   const DevData &d = ctx->d;
   const int v = variant >= 0 ? variant : ctx->cell_variant;
   if (ctx->dtype == 3 || v == kSFVariant) efe::k::sf_apply(d, ctx->vq, ctx->cells_mode == 0 ? 1 : 0, X, Y, ncolr, ldr, s, any);
-  else efe::k::cell_apply(d, ctx->cells, ctx->dtype, X, Y, ncolr, ldr, s, any, v);
+  else efe::k::cell_apply(d, ctx->cells, ctx->dtype, X, Y, ncolr, ldr, s, any, v, apart);
+}
+
+// Whether the three-term Lanczos step takes alpha_j from the products (x^H Hbar x summed by
+// the FP64 dense cell kernel and the coupling) instead of a dot pass over the new vector.
+bool alpha_from_products(const efe_ctx *ctx) {
+  return ctx->apart && ctx->opt.reorth == EFE_REORTH_PARTIAL && !ctx->mixed && ctx->dtype == 0 &&
+         ctx->cell_variant != kSFVariant;
 }
 
 // The same with FP32 rows (reduced-precision products: FP32 or BF16 blocks)
@@ -554,7 +566,9 @@ efe_status ensure_ws(efe_ctx *ctx) {
 // Y = A X with the operator currently held in the cell blocks (packed rows); reduced-
 // precision products go through the FP32 copies, so that this is the operator the
 // propagation applies
-efe_status apply_op(efe_ctx *ctx, const double *X, double *Y, int ncolr, int64_t ldr, const int *any = nullptr) {
+// With apart (alpha_from_products), also the products' shares of x^H A x.
+efe_status apply_op(efe_ctx *ctx, const double *X, double *Y, int ncolr, int64_t ldr, const int *any = nullptr,
+                    double *apart = nullptr) {
   const DevData &d = ctx->d;
   hipStream_t s = ctx->stream;
   if (ldr != ncolr) {
@@ -569,10 +583,11 @@ efe_status apply_op(efe_ctx *ctx, const double *X, double *Y, int ncolr, int64_t
     return check_launch(ctx, "apply");
   }
   tstart(ctx, 0);
-  cell_products(ctx, X, Y, ncolr, ldr, s, any);
+  cell_products(ctx, X, Y, ncolr, ldr, s, any, -1, apart);
   tstop(ctx, 0);
   tstart(ctx, 1);
-  efe::k::couple_apply(d, ctx->G, ctx->Hbar_ee, X, Y, ncolr, ldr, ctx->couple_scr, s, any);
+  efe::k::couple_apply(d, ctx->G, ctx->Hbar_ee, X, Y, ncolr, ldr, ctx->couple_scr, s, any,
+                       apart ? apart + (int64_t)d.colour_off[8] * ncolr : nullptr);
   tstop(ctx, 1);
   ctx->timer.n_hx++;
   return check_launch(ctx, "apply");
@@ -712,8 +727,9 @@ efe_status lz_iteration(efe_ctx *ctx, double tau, const double *X, int ncol, int
   const int64_t ldf = ldf_of(ncolr);
   float *yf = (float *)out;
   void *xs_in = w, *xs_out = j < ctx->kmax ? (void *)(Qb + (int64_t)j * bs) : nullptr;
+  const bool fused = alpha_from_products(ctx);
   if (mx) EFE_TRY(apply_op_f(ctx, ncolr, any, xs_in, yf, prev));
-  else EFE_TRY(apply_op(ctx, prev, w, ncolr, ncolr, any));
+  else EFE_TRY(apply_op(ctx, prev, w, ncolr, ncolr, any, fused ? ctx->apart : nullptr));
   tstart(ctx, 2);
   double *a_j = ctx->alpha + (int64_t)(j - 1) * ncol;
   double *b_j = ctx->beta + (int64_t)(j - 1) * ncol;
@@ -721,12 +737,16 @@ efe_status lz_iteration(efe_ctx *ctx, double tau, const double *X, int ncol, int
   // second pass against all slots runs for the columns that need it
   // first pass: all previous slots (full), or the three-term step (partial: the q_j coefficient
   // from the dot with slot j - 1, the q_{j-1} one from the known beta_{j-1})
-  const bool partial = ctx->opt.reorth == EFE_REORTH_PARTIAL;
+  const bool partial = ctx->opt.reorth != EFE_REORTH_FULL;
   const int first = partial ? std::max(0, j - 2) : 0, nq = j - first;
   const double *q0f = first == 0 ? X : Qb + (int64_t)(first - 1) * bs;
   const double *qbf = Qb + (int64_t)first * bs;
   int nb;
-  if (partial) {
+  if (fused) {
+    efe::k::lz_alpha_sum(ctx->apart, ctx->d.colour_off[8], ctx->apart + (int64_t)ctx->d.colour_off[8] * ncolr,
+                         ctx->d.nk, ncolr, any, ctx->h1, s);
+    efe::k::lz_coef3x(ctx->h1, ctx->sig, ctx->beta, j, ncol, ctx->active, a_j, ctx->coef, ctx->gsc, ctx->msc, s);
+  } else if (partial) {
     const double *q0d = j == 1 ? X : Qb + (int64_t)(j - 2) * bs;   // slot j - 1
     nb = mx ? efe::k::lz_dots_f(q0d, Qb + (int64_t)(j - 1) * bs, bs, 1, yf, ldf, nrows, ncol, ctx->active, any, 1,
                                 ctx->red, s)
@@ -745,7 +765,7 @@ efe_status lz_iteration(efe_ctx *ctx, double tau, const double *X, int ncol, int
   efe::k::reduce_partials(ctx->red, nb, ncolr, ctx->nrm1, s);
   if (partial)
     efe::k::lz_pro(ctx->nrm1, ctx->msc, ctx->alpha, ctx->beta, j, ncol, ctx->active, ctx->pro, ctx->need,
-                   ctx->anyflag, s);
+                   ctx->anyflag, s, fused ? 1 : 0);
   else
     efe::k::lz_decide(ctx->nrm1, ncol, ctx->active, ctx->gsc, ctx->need, ctx->anyflag, s);
   nb = efe::k::lz_dots(X, Qb, bs, j, w, nrows, ncol, ctx->need, ctx->anyflag, 0, ctx->red, s);
@@ -1452,7 +1472,7 @@ efe_status efe_setup(const efe_system *sys, const efe_options *opt, efe_ctx **ou
   if (!sys || !opt || !out) return EFE_ERR_ARG;
   *out = nullptr;
   if (opt->prod_dtype < 0 || opt->prod_dtype > 4 || opt->kmax < 1 || opt->kmax > 64 || opt->reorth < 0 ||
-      opt->reorth > 1)
+      opt->reorth > 2)
     return EFE_ERR_ARG;
   efe_ctx *ctx = new (std::nothrow) efe_ctx();
   if (!ctx) return EFE_ERR_ALLOC;
@@ -1516,8 +1536,8 @@ efe_status efe_dims(const efe_ctx *ctx, int64_t dims[5]) {
 efe_status efe_set_options(efe_ctx *ctx, const efe_options *opt) {
   if (!ctx || !opt) return EFE_ERR_ARG;
   if (opt->kmax < 1 || opt->kmax > ctx->kmax || opt->prod_dtype != ctx->dtype || opt->reorth < 0 ||
-      opt->reorth > 1) {
-    ctx->err = "kmax may only decrease, the product dtype is fixed at setup, reorth is 0 or 1";
+      opt->reorth > 2) {
+    ctx->err = "kmax may only decrease, the product dtype is fixed at setup, reorth is 0, 1 or 2";
     return EFE_ERR_ARG;
   }
   // a captured step holds the Krylov settings it was recorded with: record again
@@ -2022,7 +2042,7 @@ efe_status efe_autotune(efe_ctx *ctx, const char *cache_path, int32_t flags, cha
       names.push_back(nm);
     }
     int nv2[3];
-    const int nn = efe::k::cell_narrow_variants(d.g.nloc, ctx->ncolr, nv2);
+    const int nn = efe::k::cell_narrow_variants(d.g.nloc, ctx->ncolr, esz, nv2);
     for (int i = 0; i < nn; ++i) {
       efe::k::cell_variant_name(nv2[i], nm, sizeof(nm));
       cand.push_back(nv2[i]);

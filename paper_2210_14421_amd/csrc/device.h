@@ -109,8 +109,10 @@ void hee_reduce(const DevData &d, const double *hee_part, int kinetic, double *H
 // Hbar X
 // raises the dynamic LDS limit of the cell-product kernels for cells of nloc nodes; 0 on success
 int cell_apply_init(int nloc);
+// apart (FP64 blocks only, else ignored): per column and cell, the sum over the cell's rows
+// of X (Hbar_c X_c), at apart[col * n_cells + cell slot] (cell slots in colour order)
 void cell_apply(const DevData &d, const void *cells, int dtype, const double *X, double *Y, int ncolr, int64_t ldr,
-                hipStream_t s, const int *any = nullptr, int variant = 0);
+                hipStream_t s, const int *any = nullptr, int variant = 0, double *apart = nullptr);
 // the same with FP32 Y (ldf floats per row, a multiple of 4) and X in the reduced-precision
 // copy: FP32 for FP32 and split BF16 blocks, BF16 for BF16 blocks
 void cell_apply_f(const DevData &d, const void *cells, int dtype, const void *X, float *Y, int ncolr, int64_t ldf,
@@ -134,17 +136,19 @@ int cell_variant_count(int nloc, size_t esz);
 // FP64 blocks or cells of more than 256 nodes)
 int cell_wide_variants(int nloc, size_t esz, int *out);
 void cell_variant_name(int v, char *out, int len);
-// narrow-tile variants (64 or 32 columns per workgroup) worth trying for ncolr real columns
-// (FP64 and FP32 blocks, degree <= 5): their ids in out[], their number returned
-int cell_narrow_variants(int nloc, int ncolr, int *out);
+// narrow-tile variants (64 columns per workgroup for FP64 and FP32 blocks, 32 for FP32 blocks)
+// worth trying for ncolr real columns (degree <= 5): their ids in out[], their number returned
+int cell_narrow_variants(int nloc, int ncolr, size_t esz, int *out);
 // sum-factorised cell products (FP64, no stored blocks): Y = sum_c P_c^T Hbar_c P_c X from the
 // potential at the quadrature points (vq) and, with kinetic, the kinetic term
 bool sf_supported(const Geom &g);
 int sf_init(const Geom &g);
 void sf_apply(const DevData &d, const double *vq, int kinetic, const double *X, double *Y, int ncolr, int64_t ldr,
               hipStream_t s, const int *any = nullptr);
+// aE (optional): the enrichment terms of x^H Hbar x per (function, column), nk x ncolr
 void couple_apply(const DevData &d, const double *G, const double *Hee, const double *X, double *Y,
-                  int ncolr, int64_t ldr, double *scratch, hipStream_t s, const int *any = nullptr);
+                  int ncolr, int64_t ldr, double *scratch, hipStream_t s, const int *any = nullptr,
+                  double *aE = nullptr);
 // the FP32 coupling (G in FP32, FP32 MFMA) on FP64 rows X and Y
 void couple_apply_g32(const DevData &d, const float *G, const double *Hee, const double *X, double *Y, int ncolr,
                       int64_t ldr, double *scratch, hipStream_t s, const int *any = nullptr);
@@ -232,9 +236,18 @@ void lz_coef1(const double *h, const double *sig, int j, int first, int ncol, co
 // three-term step of iteration j from the dot with slot j - 1 and the known beta_{j-1}
 void lz_coef3(const double *h, const double *sig, const double *beta, int j, int ncol, const int *active,
               double *alpha_j, double *coef, double *gsc, double *msc, hipStream_t s);
-// partial reorthogonalisation decision after the local pass of iteration j (sets need, any)
+// x^H Hbar x per real column (ncolr values, h) from the products' shares: apart[col][cell]
+// of ncell cells and aE[k][col] of nk enrichment functions, each summed in a fixed order
+void lz_alpha_sum(const double *apart, int ncell, const double *aE, int nk, int ncolr, const int *any, double *h,
+                  hipStream_t s);
+// the three-term step from those sums (hx[c] = x^H Hbar x of slot j - 1, real columns 2c, 2c + 1)
+void lz_coef3x(const double *hx, const double *sig, const double *beta, int j, int ncol, const int *active,
+               double *alpha_j, double *coef, double *gsc, double *msc, hipStream_t s);
+// partial reorthogonalisation decision after the local pass of iteration j (sets need, any);
+// rel: the update pass was not scaled to a unit input, so the cancellation test divides by
+// the input's norm (the second entry of nrm1)
 void lz_pro(const double *nrm1, const double *msc, const double *alpha, const double *beta, int j, int ncol,
-            const int *active, const ProState &pro, int *need, int *any, hipStream_t s);
+            const int *active, const ProState &pro, int *need, int *any, hipStream_t s, int rel = 0);
 void lz_decide(const double *nrm1, int ncol, const int *active, const double *gsc, int *need, int *any,
                hipStream_t s);
 void lz_coef2(const double *h2, const double *nrm1, const double *sig, int j, int ncol, const int *need, double *coef,

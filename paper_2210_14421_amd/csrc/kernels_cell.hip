@@ -77,6 +77,11 @@ typedef void __attribute__((address_space(3))) *lptr_t;
 __device__ __forceinline__ void copy16_to_lds(const void *src, void *lds_base) {
   __builtin_amdgcn_global_load_lds((gptr_t)src, (lptr_t)lds_base, 16, 0, 0);
 }
+// the same, non-temporal (the cell blocks, read once per product: they leave the caches
+// to the gathered X rows, which the epilogue reads again)
+__device__ __forceinline__ void copy16_to_lds_nt(const void *src, void *lds_base) {
+  __builtin_amdgcn_global_load_lds((gptr_t)src, (lptr_t)lds_base, 16, 0, 2);
+}
 
 template <typename T, int KC, int NW>
 struct CellChunk {
@@ -86,10 +91,15 @@ struct CellChunk {
   static constexpr int kPer = kAIns + kXIns;         // copies per wave per chunk
 };
 
+// FP64 blocks: at least the epilogue's staging of X values (1 KB per 16-column tile of a
+// wave, eight waves of three tiles)
+constexpr size_t kAlphaStage = 8 * 3 * 1024;
+
 inline size_t cell_lds_bytes(int nloc, size_t esz, int ns, int kc, size_t xsz = 8) {
   const size_t aseg = ((size_t)kc * nloc * esz + 1023) / 1024;
   const size_t xrow = xsz == 8 ? (size_t)x_ldx<double>() * 8 : (size_t)x_ldx<float>() * 4;
-  return (size_t)ns * (aseg * 1024 + (size_t)kc * xrow) + 1024;
+  const size_t b = (size_t)ns * (aseg * 1024 + (size_t)kc * xrow) + 1024;
+  return esz == 8 && b < kAlphaStage ? kAlphaStage : b;
 }
 
 // IO: element type of X and Y (double, or float for FP32 blocks); ldr counts IO elements.
@@ -98,7 +108,8 @@ inline size_t cell_lds_bytes(int nloc, size_t esz, int ns, int kc, size_t xsz = 
 template <typename T, typename IO, int CMT, int NS, int KC, int WPE, int NT = kCellNT, int NW = kCellWaves>
 __global__ void __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(WPE)))
 k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, const T *__restrict__ cells,
-             const IO *__restrict__ X, IO *__restrict__ Y, int ncolr, int64_t ldr, const int *__restrict__ any) {
+             const IO *__restrict__ X, IO *__restrict__ Y, int ncolr, int64_t ldr, const int *__restrict__ any,
+             double *__restrict__ apart, int64_t apld) {
   static_assert(KC % 4 == 0 && NS >= 2, "chunks of whole k-steps, at least one in flight");
   static_assert(sizeof(IO) >= sizeof(T), "X and Y at least as wide as the blocks");
   if (any && *any == 0) return;
@@ -158,7 +169,7 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
       const int seg = wave + NW * i;
       const int64_t off = abase + (int64_t)seg * 1024 + lane * 16;
       const bool ok = seg < aseg && off + 16 <= ablock;
-      copy16_to_lds(Ag + (ok ? off : 0), seg < aseg ? As + (st * aseg + seg) * 1024 : junk);
+      copy16_to_lds_nt(Ag + (ok ? off : 0), seg < aseg ? As + (st * aseg + seg) * 1024 : junk);
     }
 #pragma unroll
     for (int i = 0; i < kXIns; ++i) {
@@ -218,12 +229,43 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
   // earlier value of Y is loaded before any store, so that the loads of the rows a
   // previous colour reached are in flight together.
   // (FP64 accumulators leave room for half a tile's values at a time.)
+  // With apart (FP64 blocks and rows only) the workgroup also leaves, per column, the
+  // sum over the cell's rows of X (Hbar_c X_c): the cell's share of the Lanczos
+  // coefficient x^H Hbar x (Sec. 2.6), at apart[col * apld + cell slot].  The X values of
+  // a half tile (8 rows of the wave's NT * 16 columns) are copied global -> LDS into the
+  // wave's staging area right before the half's earlier Y values are loaded, so that the
+  // one wait for those loads covers them too and no registers hold them in flight; the
+  // products of the half are kept in its first accumulator register.
+  constexpr bool kAlpha = sizeof(T) == 8 && sizeof(IO) == 8;
+  const bool wa = kAlpha && apart != nullptr;
   constexpr int kRB = sizeof(C) == 8 ? 2 : 4;
+  constexpr int kHalfCols = NT * 16;
+  IO *xstage = (IO *)(cell_sm + wave * NT * 1024);   // [8][kHalfCols]
+  if constexpr (kAlpha) {
+    static_assert(NW * NT * 1024 <= kAlphaStage, "staging fits the minimum dynamic LDS");
+    if (wa) __syncthreads();   // every wave has left the k loop: the chunk stages are free
+  }
 #pragma unroll
   for (int i = 0; i < CMT; ++i) {
     if (mg + kMG * i >= nmt) continue;
 #pragma unroll
     for (int r0 = 0; r0 < 4; r0 += kRB) {
+      if constexpr (kAlpha) {
+        if (wa) {
+          // rows 4 r0 .. 4 r0 + 7 of the tile: lane l of copy q takes bytes 16 (64 q + l);
+          // issued after the previous half's reads of the staging area
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int q = 0; q < NT; ++q) {
+            const int off = (64 * q + lane) * 16;
+            const int rq = off / (kHalfCols * 8), cq = (off % (kHalfCols * 8)) / 8;
+            const int row = (mg + kMG * i) * 16 + 4 * r0 + rq;
+            const int col = col0 + nh * kHalfCols + cq;
+            if (row < nloc && col < ncolr) copy16_to_lds(X + rowoff[row] + col, xstage + q * 128);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
       IO old[kRB][NT];
 #pragma unroll
       for (int r = 0; r < kRB; ++r) {
@@ -236,6 +278,9 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
           old[r][j] = (add && col < ncolr) ? yr[col] : (IO)0;
         }
       }
+      if constexpr (kAlpha) {
+        if (wa) wait_vmcnt<0>();   // the loads above, and with them the copies issued before them
+      }
 #pragma unroll
       for (int r = 0; r < kRB; ++r) {
         const int row = (mg + kMG * i) * 16 + Mfma<T>::row(kr, r0 + r);
@@ -247,6 +292,58 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
           if (col < ncolr) yr[col] = old[r][j] + (IO)acc[i][j][r0 + r];
         }
       }
+      if constexpr (kAlpha) {
+        if (wa) {
+#pragma unroll
+          for (int j = 0; j < NT; ++j) {
+            C t = (C)0;
+#pragma unroll
+            for (int r = 0; r < kRB; ++r) {
+              // rows past nloc hold products of unused LDS words: left out, not multiplied
+              const int row = (mg + kMG * i) * 16 + Mfma<T>::row(kr, r0 + r);
+              const int rq = kr + 4 * r;   // row within the staged half
+              if (row < nloc) t += (C)xstage[rq * kHalfCols + j * 16 + cl] * acc[i][j][r0 + r];
+            }
+            acc[i][j][r0] = t;
+          }
+        }
+      }
+    }
+  }
+  if constexpr (kAlpha) {
+    if (wa) {
+      // per column: the half tiles of this lane in order, the four row groups (lanes
+      // cl + 16 kr), then the kMG waves of a column half, in a fixed order
+      C pa[NT];
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        pa[j] = (C)0;
+#pragma unroll
+        for (int i = 0; i < CMT; ++i)
+          if (mg + kMG * i < nmt) {
+#pragma unroll
+            for (int r0 = 0; r0 < 4; r0 += kRB) pa[j] += acc[i][j][r0];
+          }
+      }
+#pragma unroll
+      for (int j = 0; j < NT; ++j) {
+        pa[j] += __shfl_xor(pa[j], 16);
+        pa[j] += __shfl_xor(pa[j], 32);
+      }
+      constexpr int kWc = 2 * NT * 16;   // columns of the workgroup
+      double *ared = (double *)cell_sm;  // [kMG][kWc], free once every wave has left the k loop
+      __syncthreads();
+      if (kr == 0) {
+#pragma unroll
+        for (int j = 0; j < NT; ++j) ared[mg * kWc + (nh * NT + j) * 16 + cl] = pa[j];
+      }
+      __syncthreads();
+      for (int t = tid; t < kWc; t += NW * 64) {
+        if (col0 + t >= ncolr) continue;
+        double sum = 0.0;
+        for (int m = 0; m < kMG; ++m) sum += ared[m * kWc + t];
+        apart[(int64_t)(col0 + t) * apld + slot0 + ci] = sum;
+      }
     }
   }
 }
@@ -254,7 +351,7 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
 template <typename T, int CMT, int NS, int KC, int WPE = (CMT <= 4 ? 4 : 2), int NT = kCellNT, int NW = kCellWaves,
           typename IO>
 void launch_apply_m(const DevData &d, const T *cells, const IO *X, IO *Y, int ncolr, int64_t ldr,
-                    hipStream_t s, const int *any) {
+                    hipStream_t s, const int *any, double *apart = nullptr) {
   const unsigned ny = (unsigned)((ncolr + 32 * NT - 1) / (32 * NT));
   const size_t lds = cell_lds_bytes(d.g.nloc, sizeof(T), NS, KC, sizeof(IO));
   for (int c = 0; c < 8; ++c) {
@@ -263,7 +360,7 @@ void launch_apply_m(const DevData &d, const T *cells, const IO *X, IO *Y, int nc
     const int *list = d.colour_cells + d.colour_off[c];
     hipLaunchKernelGGL((k_cell_apply<T, IO, CMT, NS, KC, WPE, NT, NW>), dim3((unsigned)cnt, ny), dim3(NW * 64), lds,
                        s, d,
-                       list, d.colour_off[c], cells, X, Y, ncolr, ldr, any);
+                       list, d.colour_off[c], cells, X, Y, ncolr, ldr, any, apart, (int64_t)d.colour_off[8]);
   }
 }
 
@@ -287,47 +384,53 @@ constexpr int kWideKC[kWideN] = {8, 8, 16};
 
 template <typename T, int CMT, int V, typename IO>
 void launch_v(const DevData &d, const T *cells, const IO *X, IO *Y, int ncolr, int64_t ldr, hipStream_t s,
-              const int *any) {
-  launch_apply_m<T, CMT, kVarNS[V], kVarKC[V], (CMT <= 4 ? kVarWPE[V] : 2)>(d, cells, X, Y, ncolr, ldr, s, any);
+              const int *any, double *apart) {
+  launch_apply_m<T, CMT, kVarNS[V], kVarKC[V], (CMT <= 4 ? kVarWPE[V] : 2)>(d, cells, X, Y, ncolr, ldr, s, any,
+                                                                             apart);
 }
 
 template <typename T, int CMT, int W, typename IO>
 void launch_w(const DevData &d, const T *cells, const IO *X, IO *Y, int ncolr, int64_t ldr, hipStream_t s,
-              const int *any) {
-  launch_apply_m<T, (CMT + 1) / 2, kWideNS[W], kWideKC[W], 8, kCellNT, 16>(d, cells, X, Y, ncolr, ldr, s, any);
+              const int *any, double *apart) {
+  launch_apply_m<T, (CMT + 1) / 2, kWideNS[W], kWideKC[W], 8, kCellNT, 16>(d, cells, X, Y, ncolr, ldr, s, any, apart);
 }
 
 template <typename T, int CMT, typename IO>
 void launch_variant(int v, const DevData &d, const T *cells, const IO *X, IO *Y, int ncolr, int64_t ldr,
-                    hipStream_t s, const int *any) {
+                    hipStream_t s, const int *any, double *apart) {
   switch (v) {
-    case kNarrow64: launch_apply_m<T, CMT, kVarNS[0], kVarKC[0], kVarWPE[0], 2>(d, cells, X, Y, ncolr, ldr, s, any); break;
-    case kNarrow32: launch_apply_m<T, CMT, kVarNS[0], kVarKC[0], kVarWPE[0], 1>(d, cells, X, Y, ncolr, ldr, s, any); break;
-    case 1: launch_v<T, CMT, 1>(d, cells, X, Y, ncolr, ldr, s, any); break;
-    case 2: launch_v<T, CMT, 2>(d, cells, X, Y, ncolr, ldr, s, any); break;
-    case 3: launch_v<T, CMT, 3>(d, cells, X, Y, ncolr, ldr, s, any); break;
-    case 4: launch_v<T, CMT, 4>(d, cells, X, Y, ncolr, ldr, s, any); break;
-    case 5: launch_v<T, CMT, 5>(d, cells, X, Y, ncolr, ldr, s, any); break;
-    case 6: if (sizeof(T) == 4) { launch_v<T, CMT, 6>(d, cells, X, Y, ncolr, ldr, s, any); break; } [[fallthrough]];
-    case 7: if (sizeof(T) == 4) { launch_v<T, CMT, 7>(d, cells, X, Y, ncolr, ldr, s, any); break; } [[fallthrough]];
-    case 8: if (sizeof(T) == 4) { launch_v<T, CMT, 8>(d, cells, X, Y, ncolr, ldr, s, any); break; } [[fallthrough]];
+    case kNarrow64: launch_apply_m<T, CMT, kVarNS[0], kVarKC[0], kVarWPE[0], 2>(d, cells, X, Y, ncolr, ldr, s, any, apart); break;
+    case 1: launch_v<T, CMT, 1>(d, cells, X, Y, ncolr, ldr, s, any, apart); break;
+    case 2: launch_v<T, CMT, 2>(d, cells, X, Y, ncolr, ldr, s, any, apart); break;
+    case 3: launch_v<T, CMT, 3>(d, cells, X, Y, ncolr, ldr, s, any, apart); break;
+    case 4: launch_v<T, CMT, 4>(d, cells, X, Y, ncolr, ldr, s, any, apart); break;
+    case 5: launch_v<T, CMT, 5>(d, cells, X, Y, ncolr, ldr, s, any, apart); break;
+    case 6: if constexpr (sizeof(T) == 4) { launch_v<T, CMT, 6>(d, cells, X, Y, ncolr, ldr, s, any, apart); break; } [[fallthrough]];
+    case 7: if constexpr (sizeof(T) == 4) { launch_v<T, CMT, 7>(d, cells, X, Y, ncolr, ldr, s, any, apart); break; } [[fallthrough]];
+    case 8: if constexpr (sizeof(T) == 4) { launch_v<T, CMT, 8>(d, cells, X, Y, ncolr, ldr, s, any, apart); break; } [[fallthrough]];
     case kWide0:
-      if (sizeof(T) == 4) { launch_w<T, CMT, 0>(d, cells, X, Y, ncolr, ldr, s, any); break; } [[fallthrough]];
+      if constexpr (sizeof(T) == 4) { launch_w<T, CMT, 0>(d, cells, X, Y, ncolr, ldr, s, any, apart); break; } [[fallthrough]];
     case kWide0 + 1:
-      if (sizeof(T) == 4) { launch_w<T, CMT, 1>(d, cells, X, Y, ncolr, ldr, s, any); break; } [[fallthrough]];
+      if constexpr (sizeof(T) == 4) { launch_w<T, CMT, 1>(d, cells, X, Y, ncolr, ldr, s, any, apart); break; } [[fallthrough]];
     case kWide0 + 2:
-      if (sizeof(T) == 4) { launch_w<T, CMT, 2>(d, cells, X, Y, ncolr, ldr, s, any); break; } [[fallthrough]];
-    default: launch_v<T, CMT, 0>(d, cells, X, Y, ncolr, ldr, s, any); break;
+      if constexpr (sizeof(T) == 4) { launch_w<T, CMT, 2>(d, cells, X, Y, ncolr, ldr, s, any, apart); break; } [[fallthrough]];
+    case kNarrow32:   // FP32 blocks (the FP64 form of one N tile per wave spills its registers)
+      if constexpr (sizeof(T) == 4) {
+        launch_apply_m<T, CMT, kVarNS[0], kVarKC[0], kVarWPE[0], 1>(d, cells, X, Y, ncolr, ldr, s, any, apart);
+        break;
+      }
+      [[fallthrough]];
+    default: launch_v<T, CMT, 0>(d, cells, X, Y, ncolr, ldr, s, any, apart); break;
   }
 }
 
 template <typename T, typename IO>
 void launch_apply(const DevData &d, const T *cells, const IO *X, IO *Y, int ncolr, int64_t ldr, hipStream_t s,
-                  const int *any, int v) {
+                  const int *any, int v, double *apart = nullptr) {
   const int nmt = (d.g.nloc + 15) / 16;     // M tiles per cell; wave group w >> 1 takes ceil(nmt / 4)
-  if (nmt <= 8) launch_variant<T, 2>(v, d, cells, X, Y, ncolr, ldr, s, any);
-  else if (nmt <= 16) launch_variant<T, 4>(v, d, cells, X, Y, ncolr, ldr, s, any);
-  else launch_apply_m<T, 6, 3, 8>(d, cells, X, Y, ncolr, ldr, s, any);
+  if (nmt <= 8) launch_variant<T, 2>(v, d, cells, X, Y, ncolr, ldr, s, any, apart);
+  else if (nmt <= 16) launch_variant<T, 4>(v, d, cells, X, Y, ncolr, ldr, s, any, apart);
+  else launch_apply_m<T, 6, 3, 8>(d, cells, X, Y, ncolr, ldr, s, any, apart);
 }
 
 template <typename T, typename IO, int CMT, int V>
@@ -359,7 +462,8 @@ int set_lds_io(int nloc) {
   if constexpr (sizeof(T) == 4)
     st |= set_lds_v<T, IO, CMT, 6>(e, nloc) | set_lds_v<T, IO, CMT, 7>(e, nloc) | set_lds_v<T, IO, CMT, 8>(e, nloc) |
           set_lds_w<T, IO, CMT, 0>(e, nloc) | set_lds_w<T, IO, CMT, 1>(e, nloc) | set_lds_w<T, IO, CMT, 2>(e, nloc);
-  return st | set_lds_nt<T, IO, CMT, 2>(e, nloc) | set_lds_nt<T, IO, CMT, 1>(e, nloc);
+  if constexpr (sizeof(T) == 4) st |= set_lds_nt<T, IO, CMT, 1>(e, nloc);
+  return st | set_lds_nt<T, IO, CMT, 2>(e, nloc);
 }
 
 template <typename T, int CMT>
@@ -380,11 +484,11 @@ int cell_variant_count(int nloc, size_t esz) {
   return n;
 }
 
-int cell_narrow_variants(int nloc, int ncolr, int *out) {
+int cell_narrow_variants(int nloc, int ncolr, size_t esz, int *out) {
   if ((nloc + 15) / 16 > 16) return 0;
   int n = 0;
   if (ncolr <= 64) out[n++] = kNarrow64;
-  if (ncolr <= 32) out[n++] = kNarrow32;
+  if (ncolr <= 32 && esz == 4) out[n++] = kNarrow32;
   return n;
 }
 
@@ -429,8 +533,8 @@ int cell_apply_init(int nloc) {
 }
 
 void cell_apply(const DevData &d, const void *cells, int dtype, const double *X, double *Y, int ncolr, int64_t ldr,
-                hipStream_t s, const int *any, int variant) {
-  if (dtype == 0) launch_apply<double, double>(d, (const double *)cells, X, Y, ncolr, ldr, s, any, variant);
+                hipStream_t s, const int *any, int variant, double *apart) {
+  if (dtype == 0) launch_apply<double, double>(d, (const double *)cells, X, Y, ncolr, ldr, s, any, variant, apart);
   else if (dtype == 1) launch_apply<float, double>(d, (const float *)cells, X, Y, ncolr, ldr, s, any, variant);
   else cell_apply_bf16(d, (const uint16_t *)cells, dtype == 4 ? 2 : 1, X, Y, ncolr, ldr, s, any, variant);
 }

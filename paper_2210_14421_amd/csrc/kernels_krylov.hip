@@ -350,21 +350,25 @@ k_couple_sum(const double *__restrict__ part, int nblk, int nout, double *__rest
   lvl1[(int64_t)sl * nout + o] = red[0][lo] + red[1][lo] + red[2][lo] + red[3][lo];
 }
 
-// Y_E[k][c] = sum_s lvl1[s][k][c] + sum_k' Hbar^ee[k][k'] X_E[k'][c]
+// Y_E[k][c] = sum_s lvl1[s][k][c] + sum_k' Hbar^ee[k][k'] X_E[k'][c].  With aE, also the
+// enrichment terms of x^H Hbar x: aE[k][c] = X_E[k][c] (p + Y_E[k][c]) with p = (G^T X[R])[k][c],
+// since the rows R add sum_k X_E[k][c] p to it through Y_C[R] += G X_E (G real).
 template <typename XT, typename IO>
 __global__ void __launch_bounds__(64)
 k_couple_final(const DevData d, const double *__restrict__ lvl1, int nsl, const double *__restrict__ Hee,
                const XT *__restrict__ X, int64_t ldx, IO *__restrict__ Y, int ncolr, int64_t ldr,
-               const int *__restrict__ any) {
+               const int *__restrict__ any, double *__restrict__ aE) {
   if (any && *any == 0) return;
   const int nk = d.nk, nout = nk * ncolr;
   const int o = blockIdx.x * 64 + threadIdx.x;
   if (o >= nout) return;
   double s = 0.0;
   for (int sl = 0; sl < nsl; ++sl) s += lvl1[(int64_t)sl * nout + o];
+  const double p = s;
   const int k = o / ncolr, c = o % ncolr;
   for (int kp = 0; kp < nk; ++kp) s += Hee[k * nk + kp] * (double)to_wide(X[(d.g.n_nodes + kp) * ldx + c]);
   Y[(d.g.n_nodes + k) * ldr + c] = (IO)s;
+  if (aE) aE[o] = (double)to_wide(X[(d.g.n_nodes + k) * ldx + c]) * (p + s);
 }
 
 // ---------------------------------------------------------------------------
@@ -538,7 +542,7 @@ inline unsigned nblocks(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs
 
 template <typename GT, typename XT, typename IO>
 void couple_apply_t(const DevData &d, const GT *G, const double *Hee, const XT *X, int64_t ldx, IO *Y, int ncolr,
-                    int64_t ldr, double *scratch, hipStream_t s, const int *any) {
+                    int64_t ldr, double *scratch, hipStream_t s, const int *any, double *aE = nullptr) {
   if (d.nk == 0) return;
   const int nout = d.nk * ncolr;
   double *lvl1 = scratch + (int64_t)kCpBlocks * nout;
@@ -576,7 +580,7 @@ void couple_apply_t(const DevData &d, const GT *G, const double *Hee, const XT *
     k::zero(lvl1, (int64_t)nout, s);
   }
   hipLaunchKernelGGL((k_couple_final<XT, IO>), dim3(nblocks((int64_t)nout, 64)), dim3(64), 0, s, d, lvl1, nsl, Hee, X, ldx,
-                     Y, ncolr, ldr, any);
+                     Y, ncolr, ldr, any, aE);
 }
 
 }  // namespace
@@ -584,8 +588,8 @@ void couple_apply_t(const DevData &d, const GT *G, const double *Hee, const XT *
 namespace k {
 
 void couple_apply(const DevData &d, const double *G, const double *Hee, const double *X, double *Y, int ncolr,
-                  int64_t ldr, double *scratch, hipStream_t s, const int *any) {
-  couple_apply_t(d, G, Hee, X, ldr, Y, ncolr, ldr, scratch, s, any);
+                  int64_t ldr, double *scratch, hipStream_t s, const int *any, double *aE) {
+  couple_apply_t(d, G, Hee, X, ldr, Y, ncolr, ldr, scratch, s, any, aE);
 }
 
 void couple_apply_g32(const DevData &d, const float *G, const double *Hee, const double *X, double *Y, int ncolr,

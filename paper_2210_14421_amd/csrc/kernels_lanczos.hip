@@ -121,7 +121,8 @@ k_lz_dots(Basis B, int l0, int nl, const W2 *__restrict__ w, int64_t wld, int64_
 // w <- gw[c] src - sum_{l < nl} coef[l0 + l][c] slot_{l0+l}  (mask[c] != 0); src is w
 // itself (in place) or another block (FP64 or FP32 complex, sld complex values per
 // row); sh, when given, receives an FP32 or BF16 copy of the result (shld complex values
-// per row).  with_norm writes the partial ||w||^2 of the result to part[blk][c].
+// per row).  with_norm writes the partial ||w||^2 of the result to part[blk][c].x and
+// that of the pass's input (gw[c] src for a pass of one chunk) to part[blk][c].y.
 // gw == nullptr means 1.  zero_masked clears the columns with mask[c] == 0 instead
 // (stopped columns: their later slots stay zero).
 template <int NL, typename S2, bool INPLACE, typename SHT>
@@ -139,7 +140,7 @@ k_lz_update(Basis B, int l0, int nl, const double2 *__restrict__ coef, const dou
   const int R = blockDim.x / ncol;
   const int c = threadIdx.x % ncol, r0 = threadIdx.x / ncol;
   const bool on = r0 < R && mask[c] != 0;
-  double nrm = 0.0;
+  double nrm = 0.0, nin = 0.0;
   if (r0 < R && !on && zero_masked) {
     for (int64_t r = (int64_t)blockIdx.x * R + r0; r < nrows; r += (int64_t)gridDim.x * R) {
       w[r * ncol + c] = make_double2(0.0, 0.0);
@@ -165,6 +166,7 @@ k_lz_update(Basis B, int l0, int nl, const double2 *__restrict__ coef, const dou
         else v[u] = ldnt(src + ru * sld + c);
         v[u].x *= g;
         v[u].y *= g;
+        nin += v[u].x * v[u].x + v[u].y * v[u].y;
       }
 #pragma unroll
       for (int l = 0; l < NL; ++l)
@@ -191,6 +193,7 @@ k_lz_update(Basis B, int l0, int nl, const double2 *__restrict__ coef, const dou
       if constexpr (INPLACE) va = ldnt(w + oa);
       else va = ldnt(src + r * sld + c);
       va.x *= g; va.y *= g;
+      nin += va.x * va.x + va.y * va.y;
 #pragma unroll
       for (int l = 0; l < NL; ++l)
         if (l < nl) {
@@ -205,12 +208,15 @@ k_lz_update(Basis B, int l0, int nl, const double2 *__restrict__ coef, const dou
     }
   }
   if (!with_norm) return;
-  red[threadIdx.x] = make_double2(on ? nrm : 0.0, 0.0);
+  red[threadIdx.x] = on ? make_double2(nrm, nin) : make_double2(0.0, 0.0);
   __syncthreads();
   if (threadIdx.x < ncol) {
-    double s = 0.0;
-    for (int rr = 0; rr < R; ++rr) s += red[rr * ncol + threadIdx.x].x;
-    part[(int64_t)blockIdx.x * ncol + threadIdx.x] = make_double2(s, 0.0);
+    double s = 0.0, si = 0.0;
+    for (int rr = 0; rr < R; ++rr) {
+      s += red[rr * ncol + threadIdx.x].x;
+      si += red[rr * ncol + threadIdx.x].y;
+    }
+    part[(int64_t)blockIdx.x * ncol + threadIdx.x] = make_double2(s, si);
   }
 }
 
@@ -341,6 +347,54 @@ __global__ void k_lz_coef3(const double2 *__restrict__ h, const double *__restri
   msc[c] = g > 0.0 ? sj / g : 0.0;
 }
 
+// x^H Hbar x of the product's input per real column: h[c] = sum over the cells (in slot
+// order) of apart[c][cell] + sum_k aE[k][c].  One block per column.
+__global__ void __launch_bounds__(256)
+k_lz_alpha_sum(const double *__restrict__ apart, int ncell, const double *__restrict__ aE, int nk, int ncolr,
+               const int *__restrict__ any, double *__restrict__ h) {
+  if (any && *any == 0) return;
+  __shared__ double red[256];
+  const int c = blockIdx.x;
+  const double *pc = apart + (int64_t)c * ncell;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < ncell; i += 256) acc += pc[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double t = red[0];
+    for (int k = 0; k < nk; ++k) t += aE[(int64_t)k * ncolr + c];
+    h[c] = t;
+  }
+}
+
+// The three-term step from hx = x^H Hbar x of slot j - 1 (no dot pass): alpha_j = sig_{j-1}^2
+// (hx[2c] + hx[2c + 1]); the update scales by g = sig_{j-1}, so that slot j becomes the Lanczos
+// residual itself (msc = 1):
+// slot_j <- sig_{j-1} slot_j - beta_{j-1} sig_{j-2} slot_{j-2} - sig_{j-1}^3 hx slot_{j-1}.
+__global__ void k_lz_coef3x(const double *__restrict__ hx, const double *__restrict__ sig,
+                            const double *__restrict__ beta, int j, int ncol, const int *__restrict__ active,
+                            double *__restrict__ alpha_j, double2 *__restrict__ coef, double *__restrict__ gsc,
+                            double *__restrict__ msc) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncol || !active[c]) return;
+  const double sj = sig[(int64_t)(j - 1) * ncol + c];
+  const double v = hx[2 * c] + hx[2 * c + 1];
+  alpha_j[c] = sj * sj * v;
+  const double f = sj * sj * sj * v;
+  if (j >= 2) {
+    coef[c] = make_double2(beta[(int64_t)(j - 2) * ncol + c] * sig[(int64_t)(j - 2) * ncol + c], 0.0);
+    coef[(int64_t)ncol + c] = make_double2(f, 0.0);
+  } else {
+    coef[c] = make_double2(f, 0.0);
+  }
+  gsc[c] = sj;
+  msc[c] = 1.0;
+}
+
 // Partial reorthogonalisation (Simon 1984): after the local pass of iteration j,
 // beta_j ~ msc ||slot_j|| and the omega recurrence estimates omega_{j+1,k} ~
 // q_{j+1}^H q_k from alpha_1..j, beta_1..j-1 and the rows omega_j, omega_{j-1}:
@@ -354,7 +408,8 @@ __global__ void k_lz_coef3(const double2 *__restrict__ h, const double *__restri
 // estimates of a column that gets the pass restart at eps.  One thread per column.
 __global__ void k_lz_pro(const double2 *__restrict__ nrm1, const double *__restrict__ msc,
                          const double *__restrict__ alpha, const double *__restrict__ beta, int j, int ncol,
-                         const int *__restrict__ active, ProState pro, int *__restrict__ need, int *__restrict__ any) {
+                         const int *__restrict__ active, ProState pro, int *__restrict__ need, int *__restrict__ any,
+                         int rel) {
   __shared__ int flag;
   if (threadIdx.x == 0) flag = 0;
   __syncthreads();
@@ -392,7 +447,9 @@ __global__ void k_lz_pro(const double2 *__restrict__ nrm1, const double *__restr
       }
       nw[(int64_t)j * ncol] = 1.0;
       const int exceed = (j > 1 && mx > sqrt_eps) ? 1 : 0;
-      nd = (bj > 0.0 && (exceed || pro.force[c] || n1 < kReorthEta * kReorthEta)) ? 1 : 0;
+      // cancellation: ||w'|| < eta ||w|| (the update's input had unit norm unless rel)
+      const double lim = kReorthEta * kReorthEta * (rel ? nrm1[c].y : 1.0);
+      nd = (bj > 0.0 && (exceed || pro.force[c] || n1 < lim)) ? 1 : 0;
       if (nd)
         for (int k = 1; k <= j; ++k) nw[(int64_t)(k - 1) * ncol] = eps;
       pro.force[c] = exceed;
@@ -690,9 +747,20 @@ void lz_coef3(const double *h, const double *sig, const double *beta, int j, int
 }
 
 void lz_pro(const double *nrm1, const double *msc, const double *alpha, const double *beta, int j, int ncol,
-            const int *active, const ProState &pro, int *need, int *any, hipStream_t s) {
+            const int *active, const ProState &pro, int *need, int *any, hipStream_t s, int rel) {
   hipLaunchKernelGGL(k_lz_pro, dim3(1), dim3(128), 0, s, (const double2 *)nrm1, msc, alpha, beta, j, ncol, active, pro,
-                     need, any);
+                     need, any, rel);
+}
+
+void lz_alpha_sum(const double *apart, int ncell, const double *aE, int nk, int ncolr, const int *any, double *h,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(k_lz_alpha_sum, dim3(ncolr), dim3(256), 0, s, apart, ncell, aE, nk, ncolr, any, h);
+}
+
+void lz_coef3x(const double *hx, const double *sig, const double *beta, int j, int ncol, const int *active,
+               double *alpha_j, double *coef, double *gsc, double *msc, hipStream_t s) {
+  hipLaunchKernelGGL(k_lz_coef3x, dim3((ncol + 63) / 64), dim3(64), 0, s, hx, sig, beta, j, ncol, active, alpha_j,
+                     (double2 *)coef, gsc, msc);
 }
 
 void lz_decide(const double *nrm1, int ncol, const int *active, const double *gsc, int *need, int *any,

@@ -46,7 +46,7 @@ class EfeOptions(C.Structure):
                 ("reorth", C.c_int32)]
 
 
-REORTH = {"partial": 0, "full": 1}
+REORTH = {"partial": 0, "full": 1, "partial_dot": 2}
 
 
 class EfeField(C.Structure):

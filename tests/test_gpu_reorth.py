@@ -1,5 +1,6 @@
 """Lanczos reorthogonalisation on the GPU: partial (Simon's omega recurrence, the
-default) and full, each against the oracle running the same scheme.
+default; alpha_j from the products, or from a dot pass with "partial_dot") and full,
+each against the oracle running the same scheme.
 
 * tiny Hbar, random complex block, tau = 0.2 (k = 14: long enough for the
   estimates to call for passes against all previous vectors): identical k per
@@ -37,7 +38,7 @@ def tiny_env(golden_dir):
     return spec, model, X0
 
 
-@pytest.mark.parametrize("reorth", ["partial", "full"])
+@pytest.mark.parametrize("reorth", ["partial", "partial_dot", "full"])
 def test_reorth_parity_tiny(tiny_env, reorth):
     from oracle.propagate import lanczos_expm
     from paper_2210_14421_amd.efe import Context
@@ -49,7 +50,8 @@ def test_reorth_parity_tiny(tiny_env, reorth):
     X[act] = rng.standard_normal((len(act), spec.norb)) + 1j * rng.standard_normal((len(act), spec.norb))
     X /= np.linalg.norm(X, axis=0)
     st = {}
-    ref, kref, _ = lanczos_expm(H, 0.2, X, tol=1e-10, kmax=64, reorth=reorth, stats=st)
+    scheme = "full" if reorth == "full" else "partial"   # alpha from the products or a dot pass
+    ref, kref, _ = lanczos_expm(H, 0.2, X, tol=1e-10, kmax=64, reorth=scheme, stats=st)
     ctx = Context(spec, dtype="f64", kmax=64, reorth=reorth)
     try:
         ctx.set_hamiltonian(_dev(X0), 0.0)
