@@ -122,7 +122,8 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
   constexpr int kLDX = x_ldx<IO>();
   constexpr int kEPL = 16 / (int)sizeof(IO);   // elements of an X row per 16-byte copy
   __shared__ int64_t rowoff[kApplyMaxLoc];
-  __shared__ unsigned char first[kApplyMaxLoc];   // this cell's colour is the first to reach the node
+  // bit 0: this cell's colour is the first to reach the node; bit 1: the last
+  __shared__ unsigned char reach[kApplyMaxLoc];
   extern __shared__ __attribute__((aligned(16))) unsigned char cell_sm[];
   const Geom &g = d.g;
   const int nloc = g.nloc;
@@ -145,15 +146,17 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
   for (int l = tid; l < nloc; l += NW * 64) {
     rowoff[l] = local_node(g, e, l) * ldr;
     // colours run in the order (e_x & 1) + 2 (e_y & 1) + 4 (e_z & 1); a node on a
-    // face shared along some axis is reached first by the even cell of that axis
+    // face shared along some axis is reached first by the even cell of that axis and
+    // last by the odd one
     const int li[3] = {l % g.P, (l / g.P) % g.P, l / (g.P * g.P)};
-    bool later = false;
+    bool later = false, earlier = false;
 #pragma unroll
     for (int ax = 0; ax < 3; ++ax) {
       const bool shared = (li[ax] == 0 && e[ax] > 0) || (li[ax] == g.p && e[ax] < g.nc[ax] - 1);
       later |= shared && (e[ax] & 1);
+      earlier |= shared && !(e[ax] & 1);
     }
-    first[l] = later ? 0 : 1;
+    reach[l] = (later ? 0 : 1) | (earlier ? 0 : 2);
   }
   // X stages start zeroed: pad columns are never copied into
   for (int i = tid; i < NS * kXStage / 8; i += NW * 64) ((double *)Xs)[i] = 0.0;
@@ -230,12 +233,14 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
   // previous colour reached are in flight together.
   // (FP64 accumulators leave room for half a tile's values at a time.)
   // With apart (FP64 blocks and rows only) the workgroup also leaves, per column, the
-  // sum over the cell's rows of X (Hbar_c X_c): the cell's share of the Lanczos
-  // coefficient x^H Hbar x (Sec. 2.6), at apart[col * apld + cell slot].  The X values of
-  // a half tile (8 rows of the wave's NT * 16 columns) are copied global -> LDS into the
-  // wave's staging area right before the half's earlier Y values are loaded, so that the
-  // one wait for those loads covers them too and no registers hold them in flight; the
-  // products of the half are kept in its first accumulator register.
+  // sum of X Y over the nodes this cell's colour reaches last, with Y the sum of all
+  // cell products there (the value stored): the cell's share of the cell part of the
+  // Lanczos coefficient x^H Hbar x (Sec. 2.6), at apart[col * apld + cell slot]; each
+  // node's X is read once per Hbar X.  The X values of a half tile (8 rows of the wave's
+  // NT * 16 columns) are copied global -> LDS into the wave's staging area right before
+  // the half's earlier Y values are loaded, so that the one wait for those loads covers
+  // them too and no registers hold them in flight; the stored values, then the
+  // products of the half, are kept in its accumulator registers.
   constexpr bool kAlpha = sizeof(T) == 8 && sizeof(IO) == 8;
   const bool wa = kAlpha && apart != nullptr;
   constexpr int kRB = sizeof(C) == 8 ? 2 : 4;
@@ -261,7 +266,7 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
             const int rq = off / (kHalfCols * 8), cq = (off % (kHalfCols * 8)) / 8;
             const int row = (mg + kMG * i) * 16 + 4 * r0 + rq;
             const int col = col0 + nh * kHalfCols + cq;
-            if (row < nloc && col < ncolr) copy16_to_lds(X + rowoff[row] + col, xstage + q * 128);
+            if (row < nloc && (reach[row] & 2) && col < ncolr) copy16_to_lds(X + rowoff[row] + col, xstage + q * 128);
           }
           __builtin_amdgcn_sched_barrier(0);
         }
@@ -270,7 +275,7 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
 #pragma unroll
       for (int r = 0; r < kRB; ++r) {
         const int row = (mg + kMG * i) * 16 + Mfma<T>::row(kr, r0 + r);
-        const bool add = row < nloc && !first[row];
+        const bool add = row < nloc && !(reach[row] & 1);
         const IO *yr = Y + (row < nloc ? rowoff[row] : 0);
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
@@ -289,7 +294,9 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
           const int col = col0 + (nh * NT + j) * 16 + cl;
-          if (col < ncolr) yr[col] = old[r][j] + (IO)acc[i][j][r0 + r];
+          const IO yv = old[r][j] + (IO)acc[i][j][r0 + r];
+          if (col < ncolr) yr[col] = yv;
+          if constexpr (kAlpha) acc[i][j][r0 + r] = (C)yv;
         }
       }
       if constexpr (kAlpha) {
@@ -299,10 +306,10 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
             C t = (C)0;
 #pragma unroll
             for (int r = 0; r < kRB; ++r) {
-              // rows past nloc hold products of unused LDS words: left out, not multiplied
+              // only the rows staged (this colour reaches them last); the others hold stale words
               const int row = (mg + kMG * i) * 16 + Mfma<T>::row(kr, r0 + r);
               const int rq = kr + 4 * r;   // row within the staged half
-              if (row < nloc) t += (C)xstage[rq * kHalfCols + j * 16 + cl] * acc[i][j][r0 + r];
+              if (row < nloc && (reach[row] & 2)) t += (C)xstage[rq * kHalfCols + j * 16 + cl] * acc[i][j][r0 + r];
             }
             acc[i][j][r0] = t;
           }
