@@ -84,8 +84,9 @@ struct efe_ctx {
   double *alpha = nullptr, *beta = nullptr, *beta0 = nullptr, *errv = nullptr, *ubuf = nullptr;
   int *active = nullptr, *kused = nullptr, *kforce = nullptr, *need = nullptr, *anyflag = nullptr;
   double *h1 = nullptr, *h2n = nullptr, *nrm1 = nullptr, *nrm2 = nullptr;
-  // FP64 blocks: the products' shares of x^H Hbar x, per column: n_cells cell sums, then nk
-  // enrichment terms (the three-term Lanczos step takes alpha from them, with no dot pass)
+  // FP64 blocks: the products' shares of x^H Hbar x, per column: kAlphaParts partials per cell,
+  // then nk enrichment terms, then kAlphaLvl first-level sums (the three-term Lanczos step takes
+  // alpha from them, no dot pass)
   double *apart = nullptr;
   double *sig = nullptr, *coef = nullptr, *gsc = nullptr, *msc = nullptr;
   efe::ProState pro;            // partial reorthogonalisation state of the Lanczos columns
@@ -471,7 +472,9 @@ efe_status build_device(efe_ctx *ctx) {
   EFE_TRY(dalloc(ctx, &ctx->pro.anorm, std::max(1, pl.norb)));
   EFE_TRY(dalloc(ctx, &ctx->pro.force, std::max(1, pl.norb)));
   EFE_TRY(dalloc(ctx, &ctx->h1, (int64_t)(ctx->kmax + 1) * ctx->ncolr));
-  if (ctx->dtype == 0) EFE_TRY(dalloc(ctx, &ctx->apart, ((int64_t)d.colour_off[8] + d.nk) * ctx->ncolr));
+  if (ctx->dtype == 0)
+    EFE_TRY(dalloc(ctx, &ctx->apart,
+                   ((int64_t)d.colour_off[8] * efe::k::kAlphaParts + d.nk + efe::k::kAlphaLvl) * ctx->ncolr));
   EFE_TRY(dalloc(ctx, &ctx->h2n, (int64_t)(ctx->kmax + 1) * ctx->ncolr));
   EFE_TRY(dalloc(ctx, &ctx->nrm1, ctx->ncolr));
   EFE_TRY(dalloc(ctx, &ctx->nrm2, ctx->ncolr));
@@ -587,7 +590,7 @@ efe_status apply_op(efe_ctx *ctx, const double *X, double *Y, int ncolr, int64_t
   tstop(ctx, 0);
   tstart(ctx, 1);
   efe::k::couple_apply(d, ctx->G, ctx->Hbar_ee, X, Y, ncolr, ldr, ctx->couple_scr, s, any,
-                       apart ? apart + (int64_t)d.colour_off[8] * ncolr : nullptr);
+                       apart ? apart + (int64_t)d.colour_off[8] * efe::k::kAlphaParts * ncolr : nullptr);
   tstop(ctx, 1);
   ctx->timer.n_hx++;
   return check_launch(ctx, "apply");
@@ -743,9 +746,10 @@ efe_status lz_iteration(efe_ctx *ctx, double tau, const double *X, int ncol, int
   const double *qbf = Qb + (int64_t)first * bs;
   int nb;
   if (fused) {
-    efe::k::lz_alpha_sum(ctx->apart, ctx->d.colour_off[8], ctx->apart + (int64_t)ctx->d.colour_off[8] * ncolr,
-                         ctx->d.nk, ncolr, any, ctx->h1, s);
-    efe::k::lz_coef3x(ctx->h1, ctx->sig, ctx->beta, j, ncol, ctx->active, a_j, ctx->coef, ctx->gsc, ctx->msc, s);
+    const int nparts = ctx->d.colour_off[8] * efe::k::kAlphaParts;
+    const double *aE = ctx->apart + (int64_t)nparts * ncolr;
+    efe::k::lz_alpha_coef3(ctx->apart, nparts, aE, ctx->d.nk, ctx->apart + (int64_t)(nparts + ctx->d.nk) * ncolr,
+                           ctx->sig, ctx->beta, j, ncol, ctx->active, any, a_j, ctx->coef, ctx->gsc, ctx->msc, s);
   } else if (partial) {
     const double *q0d = j == 1 ? X : Qb + (int64_t)(j - 2) * bs;   // slot j - 1
     nb = mx ? efe::k::lz_dots_f(q0d, Qb + (int64_t)(j - 1) * bs, bs, 1, yf, ldf, nrows, ncol, ctx->active, any, 1,

@@ -90,6 +90,7 @@ namespace k {
 
 constexpr int kDotBlocksMax = 1024;   // partial blocks of the column reductions
 constexpr int kCoupleScratch = 520;  // n_k x ncolr blocks: workgroup partials and first-level sums of Y_E
+constexpr int kAlphaParts = 4;       // partials of x^H Hbar x per (column, cell): one per wave of a column half
 
 void zero(double *p, int64_t n, hipStream_t s);
 void copy_rows(const double *src, int64_t lds, double *dst, int64_t ldd, int64_t nrows, int ncolr, hipStream_t s);
@@ -109,8 +110,9 @@ void hee_reduce(const DevData &d, const double *hee_part, int kinetic, double *H
 // Hbar X
 // raises the dynamic LDS limit of the cell-product kernels for cells of nloc nodes; 0 on success
 int cell_apply_init(int nloc);
-// apart (FP64 blocks only, else ignored): per column and cell, the sum over the cell's rows
-// of X (Hbar_c X_c), at apart[col * n_cells + cell slot] (cell slots in colour order)
+// apart (FP64 blocks only, else ignored): per column and cell, the sum of X Y over the nodes
+// the cell's colour reaches last (Y the stored sum of all cell products), in kAlphaParts
+// partials at apart[(col * n_cells + cell slot) * kAlphaParts + part] (cell slots in colour order)
 void cell_apply(const DevData &d, const void *cells, int dtype, const double *X, double *Y, int ncolr, int64_t ldr,
                 hipStream_t s, const int *any = nullptr, int variant = 0, double *apart = nullptr);
 // the same with FP32 Y (ldf floats per row, a multiple of 4) and X in the reduced-precision
@@ -236,13 +238,13 @@ void lz_coef1(const double *h, const double *sig, int j, int first, int ncol, co
 // three-term step of iteration j from the dot with slot j - 1 and the known beta_{j-1}
 void lz_coef3(const double *h, const double *sig, const double *beta, int j, int ncol, const int *active,
               double *alpha_j, double *coef, double *gsc, double *msc, hipStream_t s);
-// x^H Hbar x per real column (ncolr values, h) from the products' shares: apart[col][cell]
-// of ncell cells and aE[k][col] of nk enrichment functions, each summed in a fixed order
-void lz_alpha_sum(const double *apart, int ncell, const double *aE, int nk, int ncolr, const int *any, double *h,
-                  hipStream_t s);
-// the three-term step from those sums (hx[c] = x^H Hbar x of slot j - 1, real columns 2c, 2c + 1)
-void lz_coef3x(const double *hx, const double *sig, const double *beta, int j, int ncol, const int *active,
-               double *alpha_j, double *coef, double *gsc, double *msc, hipStream_t s);
+constexpr int kAlphaLvl = 16;   // first-level sums of x^H Hbar x per real column (lz_alpha_coef3 workspace)
+// the three-term step of iteration j with x^H Hbar x of slot j - 1 from the products' shares:
+// apart[col][part] (nparts cell partials per real column) and aE[k][col] (nk enrichment terms),
+// each summed in a fixed order (lvl: kAlphaLvl x 2 ncol doubles of workspace)
+void lz_alpha_coef3(const double *apart, int nparts, const double *aE, int nk, double *lvl, const double *sig,
+                    const double *beta, int j, int ncol, const int *active, const int *any, double *alpha_j,
+                    double *coef, double *gsc, double *msc, hipStream_t s);
 // partial reorthogonalisation decision after the local pass of iteration j (sets need, any);
 // rel: the update pass was not scaled to a unit input, so the cancellation test divides by
 // the input's norm (the second entry of nrm1)

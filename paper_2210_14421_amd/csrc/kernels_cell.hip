@@ -91,15 +91,10 @@ struct CellChunk {
   static constexpr int kPer = kAIns + kXIns;         // copies per wave per chunk
 };
 
-// FP64 blocks: at least the epilogue's staging of X values (1 KB per 16-column tile of a
-// wave, eight waves of three tiles)
-constexpr size_t kAlphaStage = 8 * 3 * 1024;
-
 inline size_t cell_lds_bytes(int nloc, size_t esz, int ns, int kc, size_t xsz = 8) {
   const size_t aseg = ((size_t)kc * nloc * esz + 1023) / 1024;
   const size_t xrow = xsz == 8 ? (size_t)x_ldx<double>() * 8 : (size_t)x_ldx<float>() * 4;
-  const size_t b = (size_t)ns * (aseg * 1024 + (size_t)kc * xrow) + 1024;
-  return esz == 8 && b < kAlphaStage ? kAlphaStage : b;
+  return (size_t)ns * (aseg * 1024 + (size_t)kc * xrow) + 1024;
 }
 
 // IO: element type of X and Y (double, or float for FP32 blocks); ldr counts IO elements.
@@ -235,43 +230,41 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
   // With apart (FP64 blocks and rows only) the workgroup also leaves, per column, the
   // sum of X Y over the nodes this cell's colour reaches last, with Y the sum of all
   // cell products there (the value stored): the cell's share of the cell part of the
-  // Lanczos coefficient x^H Hbar x (Sec. 2.6), at apart[col * apld + cell slot]; each
-  // node's X is read once per Hbar X.  The X values of a half tile (8 rows of the wave's
-  // NT * 16 columns) are copied global -> LDS into the wave's staging area right before
-  // the half's earlier Y values are loaded, so that the one wait for those loads covers
-  // them too and no registers hold them in flight; the stored values, then the
-  // products of the half, are kept in its accumulator registers.
+  // Lanczos coefficient x^H Hbar x (Sec. 2.6), at apart[(col * apld + cell slot) * 4 + wave
+  // group] (one partial per wave of a column half); each node's X is read once per Hbar X.
+  // The X values of the first tile are loaded after its stores, into the registers of the
+  // earlier Y values; those of the later tiles, whose accumulators the first tile's
+  // products have freed, together with the earlier Y values, in the same round trip.
   constexpr bool kAlpha = sizeof(T) == 8 && sizeof(IO) == 8;
   const bool wa = kAlpha && apart != nullptr;
   constexpr int kRB = sizeof(C) == 8 ? 2 : 4;
-  constexpr int kHalfCols = NT * 16;
-  IO *xstage = (IO *)(cell_sm + wave * NT * 1024);   // [8][kHalfCols]
-  if constexpr (kAlpha) {
-    static_assert(NW * NT * 1024 <= kAlphaStage, "staging fits the minimum dynamic LDS");
-    if (wa) __syncthreads();   // every wave has left the k loop: the chunk stages are free
-  }
+  C pa[NT];   // this lane's running sums per column, over its half tiles in order
+#pragma unroll
+  for (int j = 0; j < NT; ++j) pa[j] = (C)0;
+  if constexpr (kAlpha) static_assert(kMG == k::kAlphaParts, "one partial per wave of a column half");
 #pragma unroll
   for (int i = 0; i < CMT; ++i) {
     if (mg + kMG * i >= nmt) continue;
 #pragma unroll
     for (int r0 = 0; r0 < 4; r0 += kRB) {
-      if constexpr (kAlpha) {
-        if (wa) {
-          // rows 4 r0 .. 4 r0 + 7 of the tile: lane l of copy q takes bytes 16 (64 q + l);
-          // issued after the previous half's reads of the staging area
-          __builtin_amdgcn_sched_barrier(0);
+      IO old[kRB][NT], xo[kRB][NT];
+      // X at the rows this colour reaches last (zero elsewhere)
+      auto load_x = [&]() {
 #pragma unroll
-          for (int q = 0; q < NT; ++q) {
-            const int off = (64 * q + lane) * 16;
-            const int rq = off / (kHalfCols * 8), cq = (off % (kHalfCols * 8)) / 8;
-            const int row = (mg + kMG * i) * 16 + 4 * r0 + rq;
-            const int col = col0 + nh * kHalfCols + cq;
-            if (row < nloc && (reach[row] & 2) && col < ncolr) copy16_to_lds(X + rowoff[row] + col, xstage + q * 128);
+        for (int r = 0; r < kRB; ++r) {
+          const int row = (mg + kMG * i) * 16 + Mfma<T>::row(kr, r0 + r);
+          const bool use = row < nloc && (reach[row] & 2);
+          const IO *xr = X + (row < nloc ? rowoff[row] : 0);
+#pragma unroll
+          for (int j = 0; j < NT; ++j) {
+            const int col = col0 + (nh * NT + j) * 16 + cl;
+            xo[r][j] = (use && col < ncolr) ? xr[col] : (IO)0;
           }
-          __builtin_amdgcn_sched_barrier(0);
         }
+      };
+      if constexpr (kAlpha) {
+        if (i > 0 && wa) load_x();
       }
-      IO old[kRB][NT];
 #pragma unroll
       for (int r = 0; r < kRB; ++r) {
         const int row = (mg + kMG * i) * 16 + Mfma<T>::row(kr, r0 + r);
@@ -283,9 +276,6 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
           old[r][j] = (add && col < ncolr) ? yr[col] : (IO)0;
         }
       }
-      if constexpr (kAlpha) {
-        if (wa) wait_vmcnt<0>();   // the loads above, and with them the copies issued before them
-      }
 #pragma unroll
       for (int r = 0; r < kRB; ++r) {
         const int row = (mg + kMG * i) * 16 + Mfma<T>::row(kr, r0 + r);
@@ -296,22 +286,22 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
           const int col = col0 + (nh * NT + j) * 16 + cl;
           const IO yv = old[r][j] + (IO)acc[i][j][r0 + r];
           if (col < ncolr) yr[col] = yv;
-          if constexpr (kAlpha) acc[i][j][r0 + r] = (C)yv;
+          if constexpr (kAlpha) acc[i][j][r0 + r] = (C)yv;   // the stored value, for the products below
         }
       }
       if constexpr (kAlpha) {
         if (wa) {
+          if (i == 0) load_x();
 #pragma unroll
           for (int j = 0; j < NT; ++j) {
             C t = (C)0;
 #pragma unroll
             for (int r = 0; r < kRB; ++r) {
-              // only the rows staged (this colour reaches them last); the others hold stale words
+              // rows past nloc hold products of unused LDS words: left out, not multiplied
               const int row = (mg + kMG * i) * 16 + Mfma<T>::row(kr, r0 + r);
-              const int rq = kr + 4 * r;   // row within the staged half
-              if (row < nloc && (reach[row] & 2)) t += (C)xstage[rq * kHalfCols + j * 16 + cl] * acc[i][j][r0 + r];
+              if (row < nloc) t += (C)xo[r][j] * acc[i][j][r0 + r];
             }
-            acc[i][j][r0] = t;
+            pa[j] += t;
           }
         }
       }
@@ -319,37 +309,19 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
   }
   if constexpr (kAlpha) {
     if (wa) {
-      // per column: the half tiles of this lane in order, the four row groups (lanes
-      // cl + 16 kr), then the kMG waves of a column half, in a fixed order
-      C pa[NT];
-#pragma unroll
-      for (int j = 0; j < NT; ++j) {
-        pa[j] = (C)0;
-#pragma unroll
-        for (int i = 0; i < CMT; ++i)
-          if (mg + kMG * i < nmt) {
-#pragma unroll
-            for (int r0 = 0; r0 < 4; r0 += kRB) pa[j] += acc[i][j][r0];
-          }
-      }
+      // per column: the four row groups (lanes cl + 16 kr) in a fixed order; each wave of
+      // a column half leaves its own partial, apart[col][cell slot][mg]
 #pragma unroll
       for (int j = 0; j < NT; ++j) {
         pa[j] += __shfl_xor(pa[j], 16);
         pa[j] += __shfl_xor(pa[j], 32);
       }
-      constexpr int kWc = 2 * NT * 16;   // columns of the workgroup
-      double *ared = (double *)cell_sm;  // [kMG][kWc], free once every wave has left the k loop
-      __syncthreads();
       if (kr == 0) {
 #pragma unroll
-        for (int j = 0; j < NT; ++j) ared[mg * kWc + (nh * NT + j) * 16 + cl] = pa[j];
-      }
-      __syncthreads();
-      for (int t = tid; t < kWc; t += NW * 64) {
-        if (col0 + t >= ncolr) continue;
-        double sum = 0.0;
-        for (int m = 0; m < kMG; ++m) sum += ared[m * kWc + t];
-        apart[(int64_t)(col0 + t) * apld + slot0 + ci] = sum;
+        for (int j = 0; j < NT; ++j) {
+          const int col = col0 + (nh * NT + j) * 16 + cl;
+          if (col < ncolr) apart[((int64_t)col * apld + slot0 + ci) * k::kAlphaParts + mg] = pa[j];
+        }
       }
     }
   }

@@ -347,42 +347,55 @@ __global__ void k_lz_coef3(const double2 *__restrict__ h, const double *__restri
   msc[c] = g > 0.0 ? sj / g : 0.0;
 }
 
-// x^H Hbar x of the product's input per real column: h[c] = sum over the cells (in slot
-// order) of apart[c][cell] + sum_k aE[k][c].  One block per column.
+// x^H Hbar x of the product's input, first level: lvl[c][sl] = sum of the cell partials
+// apart[c][part] of slice sl (a contiguous range of parts), the last slice with the
+// enrichment terms aE[k][c] (k < nk) as well, each summed in a fixed order.  Grid
+// (ncolr, kAlphaSlices).
+constexpr int kAlphaSlices = k::kAlphaLvl;
 __global__ void __launch_bounds__(256)
-k_lz_alpha_sum(const double *__restrict__ apart, int ncell, const double *__restrict__ aE, int nk, int ncolr,
-               const int *__restrict__ any, double *__restrict__ h) {
+k_lz_alpha_sum(const double *__restrict__ apart, int nparts, const double *__restrict__ aE, int nk, int ncolr,
+               const int *__restrict__ any, double *__restrict__ lvl) {
   if (any && *any == 0) return;
   __shared__ double red[256];
-  const int c = blockIdx.x;
-  const double *pc = apart + (int64_t)c * ncell;
+  const int c = blockIdx.x, sl = blockIdx.y;
+  const int per = (nparts + kAlphaSlices - 1) / kAlphaSlices;
+  const int b0 = sl * per, b1 = b0 + per < nparts ? b0 + per : nparts;
+  const double *pc = apart + (int64_t)c * nparts;
   double acc = 0.0;
-  for (int i = threadIdx.x; i < ncell; i += 256) acc += pc[i];
+  for (int i = b0 + threadIdx.x; i < b1; i += 256) acc += pc[i];
+  if (sl == kAlphaSlices - 1)
+    for (int k = threadIdx.x; k < nk; k += 256) acc += aE[(int64_t)k * ncolr + c];
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    double t = red[0];
-    for (int k = 0; k < nk; ++k) t += aE[(int64_t)k * ncolr + c];
-    h[c] = t;
-  }
+  if (threadIdx.x == 0) lvl[c * kAlphaSlices + sl] = red[0];
 }
 
-// The three-term step from hx = x^H Hbar x of slot j - 1 (no dot pass): alpha_j = sig_{j-1}^2
-// (hx[2c] + hx[2c + 1]); the update scales by g = sig_{j-1}, so that slot j becomes the Lanczos
-// residual itself (msc = 1):
+// The three-term step from hx = x^H Hbar x of slot j - 1 (no dot pass): per real column, the
+// slice sums lvl[col][0..kAlphaSlices) in order; alpha_j = sig_{j-1}^2 (hx[2c] + hx[2c + 1]);
+// the update scales by g = sig_{j-1}, so that slot j becomes the Lanczos residual itself
+// (msc = 1):
 // slot_j <- sig_{j-1} slot_j - beta_{j-1} sig_{j-2} slot_{j-2} - sig_{j-1}^3 hx slot_{j-1}.
-__global__ void k_lz_coef3x(const double *__restrict__ hx, const double *__restrict__ sig,
+__global__ void k_lz_coef3x(const double *__restrict__ lvl, const double *__restrict__ sig,
                             const double *__restrict__ beta, int j, int ncol, const int *__restrict__ active,
                             double *__restrict__ alpha_j, double2 *__restrict__ coef, double *__restrict__ gsc,
                             double *__restrict__ msc) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncol || !active[c]) return;
   const double sj = sig[(int64_t)(j - 1) * ncol + c];
-  const double v = hx[2 * c] + hx[2 * c + 1];
+  double hx[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const double *lv = lvl + (2 * c + h) * kAlphaSlices;
+    double t = 0.0;
+#pragma unroll
+    for (int sl = 0; sl < kAlphaSlices; ++sl) t += lv[sl];
+    hx[h] = t;
+  }
+  const double v = hx[0] + hx[1];
   alpha_j[c] = sj * sj * v;
   const double f = sj * sj * sj * v;
   if (j >= 2) {
@@ -752,14 +765,12 @@ void lz_pro(const double *nrm1, const double *msc, const double *alpha, const do
                      need, any, rel);
 }
 
-void lz_alpha_sum(const double *apart, int ncell, const double *aE, int nk, int ncolr, const int *any, double *h,
-                  hipStream_t s) {
-  hipLaunchKernelGGL(k_lz_alpha_sum, dim3(ncolr), dim3(256), 0, s, apart, ncell, aE, nk, ncolr, any, h);
-}
-
-void lz_coef3x(const double *hx, const double *sig, const double *beta, int j, int ncol, const int *active,
-               double *alpha_j, double *coef, double *gsc, double *msc, hipStream_t s) {
-  hipLaunchKernelGGL(k_lz_coef3x, dim3((ncol + 63) / 64), dim3(64), 0, s, hx, sig, beta, j, ncol, active, alpha_j,
+void lz_alpha_coef3(const double *apart, int nparts, const double *aE, int nk, double *lvl, const double *sig,
+                    const double *beta, int j, int ncol, const int *active, const int *any, double *alpha_j,
+                    double *coef, double *gsc, double *msc, hipStream_t s) {
+  hipLaunchKernelGGL(k_lz_alpha_sum, dim3(2 * ncol, kAlphaSlices), dim3(256), 0, s, apart, nparts, aE, nk, 2 * ncol,
+                     any, lvl);
+  hipLaunchKernelGGL(k_lz_coef3x, dim3((ncol + 63) / 64), dim3(64), 0, s, lvl, sig, beta, j, ncol, active, alpha_j,
                      (double2 *)coef, gsc, msc);
 }
 
