@@ -287,7 +287,11 @@ def _stats_dict(st, n):
 
 
 class Context:
-    """A GPU context: static data uploaded, workspace allocated."""
+    """A GPU context: static data uploaded, workspace allocated.
+
+    reorth (efe_options.reorth): "partial" (default; with FP64 blocks the Lanczos
+    coefficient alpha_j comes from the products), "partial_dot" (the same scheme with
+    alpha_j from a dot pass) or "full"."""
 
     def __init__(self, spec, dtype="f64", kmax=None, tol=None, cg_tol=1e-12, cg_maxit=50, stream=None,
                  reorth="partial"):
