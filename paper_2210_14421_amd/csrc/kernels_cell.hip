@@ -232,9 +232,10 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
   // cell products there (the value stored): the cell's share of the cell part of the
   // Lanczos coefficient x^H Hbar x (Sec. 2.6), at apart[(col * apld + cell slot) * 4 + wave
   // group] (one partial per wave of a column half); each node's X is read once per Hbar X.
-  // The X values of the first tile are loaded after its stores, into the registers of the
-  // earlier Y values; those of the later tiles, whose accumulators the first tile's
-  // products have freed, together with the earlier Y values, in the same round trip.
+  // The X values of a wave's first half tile are loaded after its stores, into the
+  // registers of the earlier Y values; those of the later halves, whose accumulators the
+  // first half's products have freed, together with the earlier Y values, in the same
+  // round trip.
   constexpr bool kAlpha = sizeof(T) == 8 && sizeof(IO) == 8;
   const bool wa = kAlpha && apart != nullptr;
   constexpr int kRB = sizeof(C) == 8 ? 2 : 4;
@@ -263,7 +264,7 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
         }
       };
       if constexpr (kAlpha) {
-        if (i > 0 && wa) load_x();
+        if ((i > 0 || r0 > 0) && wa) load_x();
       }
 #pragma unroll
       for (int r = 0; r < kRB; ++r) {
@@ -291,7 +292,7 @@ k_cell_apply(const DevData d, const int *__restrict__ cell_list, int slot0, cons
       }
       if constexpr (kAlpha) {
         if (wa) {
-          if (i == 0) load_x();
+          if (i == 0 && r0 == 0) load_x();
 #pragma unroll
           for (int j = 0; j < NT; ++j) {
             C t = (C)0;
